@@ -1,0 +1,7 @@
+"""MI355X-native iPEPS real-time evolution of the disorder-dilated 2D XXZ model.
+
+The compute path is the gfx950 library ``libipeps.so`` (HIP kernels behind the
+C ABI in include/ipeps.h); this package only marshals arguments to it.
+"""
+from .native import (Config, IpepsError, Obs, Server, State, footprint_bytes, load,  # noqa: F401
+                     make_config)

@@ -1,0 +1,803 @@
+// C ABI of the iPEPS library: state lifetime, the simple-update Trotter step,
+// the CTMRG driver with half-system projectors, and the readout.  Every step
+// of the method runs in device kernels; this file only plans and enqueues.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "ctm.h"
+#include "gemm.h"
+#include "linalg.h"
+#include "state.h"
+#include "su.h"
+
+using namespace ipeps;
+
+// ---------------------------------------------------------------- memory
+void* ipeps::DevMem::get(size_t bytes) {
+    bytes = (bytes + 255) & ~(size_t)255;
+    if (bytes == 0) bytes = 256;
+    total += bytes;
+    if (dry) return nullptr;
+    void* p = nullptr;
+    if (alloc) {
+        p = alloc(bytes, (void*)stream, ctx);
+        if (!p) throw status_error(IPEPS_ENOMEM, "allocation hook failed");
+    } else {
+        if (hipMalloc(&p, bytes) != hipSuccess) throw status_error(IPEPS_ENOMEM, "hipMalloc failed");
+    }
+    ptrs.push_back(p);
+    return p;
+}
+
+void ipeps::DevMem::release() {
+    for (void* p : ptrs) {
+        if (free_fn)
+            free_fn(p, (void*)stream, ctx);
+        else
+            (void)hipFree(p);
+    }
+    ptrs.clear();
+}
+
+namespace {
+
+constexpr int kDirectMax = 96;  // projector SVD by direct Jacobi when n <= this
+constexpr int kColdIters = 8;   // subspace iterations for a fresh random block
+constexpr int kWarmIters = 3;   // ... when warm-started from the last iteration
+constexpr double kCholDrop = 1e-12;
+
+int idx(int x, int y) { return ((x % 2 + 2) % 2) + 2 * ((y % 2 + 2) % 2); }
+int hl(int x, int y) { return idx(x, y); }
+int vl(int x, int y) { return 4 + idx(x, y); }
+
+// physical site of frame coordinates (X, Y) in frame f: frames 0 and 2 keep
+// the 2x2 cell, frames 1 and 3 transpose it (coordinates mod 2).
+int frame_site(int f, int X, int Y) { return (f % 2 == 0) ? idx(X, Y) : idx(Y, X); }
+
+// move order of one iteration: left, right, up, down = frames 0, 2, 1, 3
+const int kMoveFrames[4] = {0, 2, 1, 3};
+
+int choose_k(int n, int chi) {
+    int p = std::max(16, chi / 3);
+    return std::min(n, chi + p);
+}
+
+void validate(const ipeps_config* c) {
+    IPEPS_REQUIRE(c != nullptr, IPEPS_EINVAL, "config is NULL");
+    IPEPS_REQUIRE(c->D >= 1 && c->D <= 8, IPEPS_EINVAL, "D must be in 1..8");
+    IPEPS_REQUIRE(c->d_A == 2, IPEPS_EINVAL, "d_A must be 2");
+    IPEPS_REQUIRE(c->chi >= c->D * c->D && c->chi <= 160, IPEPS_EINVAL, "chi must be in D^2..160");
+    IPEPS_REQUIRE(c->dt > 0 && std::isfinite(c->dt), IPEPS_EINVAL, "dt must be > 0");
+    IPEPS_REQUIRE(c->trotter_order == 2, IPEPS_EINVAL, "trotter_order must be 2");
+    IPEPS_REQUIRE(c->dtype == IPEPS_DTYPE_FP64 || c->dtype == IPEPS_DTYPE_FP32, IPEPS_EINVAL,
+                  "dtype must be FP64 or FP32");
+    IPEPS_REQUIRE(std::isfinite(c->J) && std::isfinite(c->V) && std::isfinite(c->W), IPEPS_EINVAL,
+                  "non-finite model parameter");
+}
+
+GemmGroup add_group(ipeps_state* st, std::vector<GemmProb> probs, int dtype) {
+    GemmGroup g;
+    g.first = (int)st->probs.size();
+    g.count = (int)probs.size();
+    g.dtype = dtype;
+    g.tiles = gemm_plan_tiles(probs.data(), g.count, dtype, &g.tile);
+    for (auto& p : probs) st->probs.push_back(p);
+    return g;
+}
+
+void run(ipeps_state* st, const GemmGroup& g) {
+    if (g.count == 0) return;
+    gemm_launch(st->stream, g.dtype, g.tile, st->d_probs + g.first, g.count, g.tiles);
+}
+
+char* off(void* base, long elems, size_t esz) { return (char*)base + elems * (long)esz; }
+
+// ---------------------------------------------------------------- allocation
+void allocate(ipeps_state* st) {
+    DevMem& M = st->mem;
+    const int D = st->D, d = st->d, q = st->q, chi = st->chi, n = st->n, k = st->k;
+    const size_t e = st->esz;
+    const long D4 = (long)D * D * D * D, q4 = (long)q * q * q * q, n2 = (long)n * n;
+    const long cqc = (long)chi * q * chi;
+    st->gam = (cplx*)M.get(4 * d * D4 * sizeof(cplx));
+    st->lam = (double*)M.get(8 * D * sizeof(double));
+    st->eps = (double*)M.get(4 * sizeof(double));
+    st->gates = (cplx*)M.get(8 * (long)d * d * d * d * sizeof(cplx));
+    st->su_scratch = M.get(su_scratch_bytes(D, d));
+    st->A = (cplx*)M.get(4 * d * D4 * sizeof(cplx));
+    st->a_base = (double*)M.get(4 * q4 * sizeof(double));
+    for (int i = 0; i < 16; ++i) {
+        st->a_lu[i] = M.get(q4 * e);
+        st->a_dl[i] = M.get(q4 * e);
+    }
+    st->d_a_lu = (void**)M.get(16 * sizeof(void*));
+    st->d_a_dl = (void**)M.get(16 * sizeof(void*));
+    st->Cenv = M.get(16L * chi * chi * e);
+    st->Tenv = M.get(16L * cqc * e);
+    st->X1 = M.get(8 * cqc * e);
+    st->X2 = M.get(8 * n2 * e);
+    st->X2p = M.get(8 * n2 * e);
+    st->E = M.get(8 * n2 * e);
+    st->Fh = M.get(2 * n2 * e);
+    st->Gh = M.get(2 * n2 * e);
+    st->N64 = (double*)M.get(2 * n2 * sizeof(double));
+    st->Nd = (st->dtype == IPEPS_DTYPE_FP64) ? (void*)st->N64 : M.get(2 * n2 * e);
+    st->Z = M.get(2 * cqc * e);
+    st->Us = M.get(2L * n * chi * e);
+    st->Vs = M.get(2L * n * chi * e);
+    st->Plow = M.get(2L * n * chi * e);
+    st->Pup = M.get(2L * n * chi * e);
+    st->PlowP = M.get(2L * n * chi * e);
+    st->PupP = M.get(2L * n * chi * e);
+    st->W1 = M.get(2 * n2 * e);
+    st->W1p = M.get(2 * n2 * e);
+    st->W2 = M.get(2 * n2 * e);
+    st->g_dev = (int*)M.get(2 * sizeof(int));
+    const long nk = (long)n * k;
+    st->warm = (double*)M.get(16 * nk * sizeof(double));
+    st->Yw = (double*)M.get(2 * nk * sizeof(double));
+    st->Zw = (double*)M.get(2 * nk * sizeof(double));
+    st->Qw = (double*)M.get(2 * nk * sizeof(double));
+    st->Qz = (double*)M.get(2 * nk * sizeof(double));
+    st->Gm = (double*)M.get(2L * k * k * sizeof(double));
+    st->Ri = (double*)M.get(2L * k * k * sizeof(double));
+    st->Cs = (double*)M.get(2L * k * k * sizeof(double));
+    st->Uc = (double*)M.get(2L * k * k * sizeof(double));
+    st->Vc = (double*)M.get(2L * k * k * sizeof(double));
+    st->sig = (double*)M.get(2L * std::max(k, n) * sizeof(double));
+    st->Uo = (double*)M.get(2 * std::max(nk, n2 <= 96L * 96 ? n2 : 0L) * sizeof(double));
+    st->Vo = (double*)M.get(2 * std::max(nk, n2 <= 96L * 96 ? n2 : 0L) * sizeof(double));
+    size_t jw = std::max({jacobi_svd_real_work(2, k, k), jacobi_svd_real_work(16, chi, chi),
+                          n <= kDirectMax ? jacobi_svd_real_work(2, n, n) : (size_t)0});
+    st->jwork = (double*)M.get(std::max(jw, (size_t)1) * sizeof(double));
+    st->C64 = (double*)M.get(16L * chi * chi * sizeof(double));
+    st->csig = (double*)M.get(16L * chi * sizeof(double));
+    st->spectra = (double*)M.get(16L * chi * sizeof(double));
+    st->spec_prev = (double*)M.get(16L * chi * sizeof(double));
+    st->dev_scalars = (double*)M.get(8 * sizeof(double));
+    st->Eout = M.get(4 * q4 * e);
+    st->E64 = (double*)M.get(4 * q4 * sizeof(double));
+    st->rho = (cplx*)M.get(4 * (long)d * d * sizeof(cplx));
+    st->obs_dev = (double*)M.get(16 * sizeof(double));
+}
+
+// ---------------------------------------------------------------- plan
+void build_plan(ipeps_state* st) {
+    const int q = st->q, chi = st->chi, n = st->n, k = st->k, dt = st->dtype;
+    const size_t e = st->esz;
+    const long n2 = (long)n * n, cqc = (long)chi * q * chi, cc = (long)chi * chi;
+    auto Cp = [&](int site, int kk) { return off(st->Cenv, (site * 4 + kk) * cc, e); };
+    auto Tp = [&](int site, int kk) { return off(st->Tenv, (site * 4 + kk) * cqc, e); };
+
+    for (int mi = 0; mi < 4; ++mi) {
+        const int f = kMoveFrames[mi];
+        for (int X = 0; X < 2; ++X) {
+            ColumnStep& cs = st->steps[mi * 2 + X];
+            cs.slot = mi * 2 + X;
+            std::vector<GemmProb> s1, s2, s3, half, np, pr, w1, w2, fin;
+            for (int Y = 0; Y < 2; ++Y) {
+                const int fx[4] = {X, X + 1, X + 1, X}, fy[4] = {Y, Y, Y + 1, Y + 1};
+                for (int j = 0; j < 4; ++j) {
+                    const int s = frame_site(f, fx[j], fy[j]);
+                    const int g = (f + j) % 4;
+                    const int blk = Y * 4 + j;
+                    char* x1 = off(st->X1, blk * cqc, e);
+                    char* x2 = off(st->X2, blk * n2, e);
+                    char* x2p = off(st->X2p, blk * n2, e);
+                    char* E = off(st->E, blk * n2, e);
+                    // S1: C (chi x chi) . Tnext (chi x q chi)
+                    s1.push_back(gemm_nn(Cp(s, g), chi, Tp(s, g), (long)q * chi, x1, (long)q * chi,
+                                         chi, q * chi, chi));
+                    // S2: Tprev (chi q x chi) . X1 (chi x q chi)
+                    s2.push_back(gemm_nn(Tp(s, (g + 3) % 4), chi, x1, (long)q * chi, x2,
+                                         (long)q * chi, chi * q, q * chi, chi));
+                    // S3: X2p (chi^2 x q^2) . a[L U][D R]; result as the n x n
+                    // matrix [prev = (t, D)][next = (c, R)]
+                    GemmProb p3 = gemm_nn(x2p, (long)q * q, st->a_lu[s * 4 + g], (long)q * q, E, n,
+                                          chi * chi, q * q, q * q);
+                    p3.c_rows0 = chi;
+                    p3.c_rs1 = (long)q * n;
+                    p3.c_rs0 = q;
+                    p3.c_cols0 = q;
+                    p3.c_cs1 = n;
+                    p3.c_cs0 = 1;
+                    s3.push_back(p3);
+                }
+                char* E0 = off(st->E, (Y * 4 + 0) * n2, e);
+                char* E1 = off(st->E, (Y * 4 + 1) * n2, e);
+                char* E2 = off(st->E, (Y * 4 + 2) * n2, e);
+                char* E3 = off(st->E, (Y * 4 + 3) * n2, e);
+                char* F = off(st->Fh, Y * n2, e);
+                char* G = off(st->Gh, Y * n2, e);
+                half.push_back(gemm_nn(E0, n, E1, n, F, n, n, n, n));
+                half.push_back(gemm_nn(E2, n, E3, n, G, n, n, n, n));
+                np.push_back(gemm_nn(G, n, F, n, off(st->Nd, Y * n2, e), n, n, n, n));
+                // projectors: P_low = F Vs (n x chi), P_up = Us^T G (chi x n)
+                char* us = off(st->Us, Y * (long)n * chi, e);
+                char* vs = off(st->Vs, Y * (long)n * chi, e);
+                pr.push_back(gemm_nn(F, n, vs, chi, off(st->Plow, Y * (long)n * chi, e), chi, n, chi, n));
+                pr.push_back(gemm_general(us, true, chi, G, false, n, off(st->Pup, Y * (long)n * chi, e),
+                                          n, chi, n, n));
+                // renormalisation inputs of column X
+                const int sxy = frame_site(f, X, Y);
+                cs.site_x[Y] = sxy;
+                cs.site_x1[Y] = frame_site(f, X + 1, Y);
+                // Z = T3(X,Y) (chi q x chi) . C4(X,Y)  -> [t3p][q3][c4n]
+                s1.push_back(gemm_nn(Tp(sxy, (2 + f) % 4), chi, Cp(sxy, (3 + f) % 4), chi,
+                                     off(st->Z, Y * cqc, e), chi, chi * q, chi, chi));
+                // W1 = PupP (chi q x chi) . T4(X,Y) (chi x q chi)
+                w1.push_back(gemm_nn(off(st->PupP, Y * (long)n * chi, e), chi, Tp(sxy, (3 + f) % 4),
+                                     (long)q * chi, off(st->W1, Y * n2, e), (long)q * chi, chi * q,
+                                     q * chi, chi));
+                // W2 = W1p (chi^2 x q^2) . a[D L][U R] in frame f
+                w2.push_back(gemm_nn(off(st->W1p, Y * n2, e), (long)q * q, st->a_dl[sxy * 4 + f],
+                                     (long)q * q, off(st->W2, Y * n2, e), (long)q * q, chi * chi,
+                                     q * q, q * q));
+            }
+            for (int Y = 0; Y < 2; ++Y) {
+                const int Yn = (Y + 1) % 2, Yp = (Y + 1) % 2;  // Y+1 and Y-1 coincide mod 2
+                // C1(X+1, Y+1) = P_up(Y) (chi x n) . X1 of UL at (X, Y+1) (n x chi)
+                fin.push_back(gemm_nn(off(st->Pup, Y * (long)n * chi, e), n,
+                                      off(st->X1, (Yn * 4 + 0) * cqc, e), chi,
+                                      Cp(frame_site(f, X + 1, Y + 1), f % 4), chi, chi, chi, n));
+                // C4(X+1, Y) = Z(Y) (chi x q chi, k = (q3, c4n)) . PlowP(Y)
+                fin.push_back(gemm_nn(off(st->Z, Y * cqc, e), (long)q * chi,
+                                      off(st->PlowP, Y * (long)n * chi, e), chi,
+                                      Cp(frame_site(f, X + 1, Y), (3 + f) % 4), chi, chi, chi, n));
+                // T4(X+1, Y) = W2(Y) [rows (c', R), k = (t4n, U)] . P_low(Y-1)
+                GemmProb pt = gemm_nn(off(st->W2, Y * n2, e), 0, off(st->Plow, Yp * (long)n * chi, e),
+                                      chi, Tp(frame_site(f, X + 1, Y), (3 + f) % 4), chi, chi * q,
+                                      chi, n);
+                pt.a_rows0 = q;
+                pt.a_rs1 = (long)n * q;
+                pt.a_rs0 = 1;
+                pt.a_ks = q;
+                fin.push_back(pt);
+            }
+            cs.s1 = add_group(st, s1, dt);
+            cs.s2 = add_group(st, s2, dt);
+            cs.s3 = add_group(st, s3, dt);
+            cs.half = add_group(st, half, dt);
+            cs.nprod = add_group(st, np, dt);
+            cs.proj = add_group(st, pr, dt);
+            cs.w1 = add_group(st, w1, dt);
+            cs.w2 = add_group(st, w2, dt);
+            cs.fin = add_group(st, fin, dt);
+            cs.norm_first = (long)st->norms.size();
+            for (int Y = 0; Y < 2; ++Y) {
+                st->norms.push_back({Cp(frame_site(f, X + 1, Y + 1), f % 4), cc});
+                st->norms.push_back({Cp(frame_site(f, X + 1, Y), (3 + f) % 4), cc});
+                st->norms.push_back({Tp(frame_site(f, X + 1, Y), (3 + f) % 4), cqc});
+            }
+        }
+    }
+
+    // projector SVD, FP64, batch of the two cuts
+    if (n > kDirectMax) {
+        const long nk = (long)n * k, kk = (long)k * k;
+        std::vector<GemmProb> v;
+        auto batch2 = [&](auto make) {
+            std::vector<GemmProb> out;
+            for (int b = 0; b < 2; ++b) out.push_back(make(b));
+            return add_group(st, out, IPEPS_DTYPE_FP64);
+        };
+        SvdPlan& P = st->svd;
+        P.NV = batch2([&](int b) {
+            return gemm_nn(st->N64 + b * n2, n, st->Qz + b * nk, k, st->Yw + b * nk, k, n, k, n);
+        });
+        P.NtQ = batch2([&](int b) {
+            return gemm_general(st->N64 + b * n2, true, n, st->Yw + b * nk, false, k, st->Zw + b * nk,
+                                k, n, k, n);
+        });
+        auto gram = [&](double* X) {
+            return batch2([&](int b) {
+                return gemm_general(X + b * nk, true, k, X + b * nk, false, k, st->Gm + b * kk, k, k,
+                                    k, n);
+            });
+        };
+        auto mulR = [&](double* X, double* out) {
+            return batch2([&](int b) {
+                return gemm_nn(X + b * nk, k, st->Ri + b * kk, k, out + b * nk, k, n, k, k);
+            });
+        };
+        P.gramY = gram(st->Yw);
+        P.QfromY = mulR(st->Yw, st->Qw);
+        P.gramQ = gram(st->Qw);
+        P.YfromQ = mulR(st->Qw, st->Yw);
+        P.gramZ = gram(st->Zw);
+        P.QfromZ = mulR(st->Zw, st->Qz);
+        P.gramQz = gram(st->Qz);
+        P.ZfromQz = mulR(st->Qz, st->Zw);
+        // final: Qw = N V (V in Qz), Cs = Yw^T Qw, Uo = Yw Uc, Vo = Qz Vc
+        P.NVfinal = batch2([&](int b) {
+            return gemm_nn(st->N64 + b * n2, n, st->Qz + b * nk, k, st->Qw + b * nk, k, n, k, n);
+        });
+        P.Cs = batch2([&](int b) {
+            return gemm_general(st->Yw + b * nk, true, k, st->Qw + b * nk, false, k, st->Cs + b * kk,
+                                k, k, k, n);
+        });
+        P.Uo = batch2([&](int b) {
+            return gemm_nn(st->Yw + b * nk, k, st->Uc + b * kk, k, st->Uo + b * nk, k, n, k, k);
+        });
+        P.Vo = batch2([&](int b) {
+            return gemm_nn(st->Qz + b * nk, k, st->Vc + b * kk, k, st->Vo + b * nk, k, n, k, k);
+        });
+    }
+
+    // readout: per site, L' = (T4 (C1 T1)) C2 and R' = (T2 (C3 T3)) C4
+    {
+        std::vector<GemmProb> r1, r2, r3, r4;
+        const long q4 = (long)q * q * q * q;
+        for (int s = 0; s < 4; ++s) {
+            for (int side = 0; side < 2; ++side) {
+                const int g = side ? 2 : 0;
+                const int blk = side * 4 + s;
+                char* x1 = off(st->X1, blk * cqc, e);
+                char* x2 = off(st->X2, blk * n2, e);
+                r1.push_back(gemm_nn(Cp(s, g), chi, Tp(s, g), (long)q * chi, x1, (long)q * chi, chi,
+                                     q * chi, chi));
+                r2.push_back(gemm_nn(Tp(s, (g + 3) % 4), chi, x1, (long)q * chi, x2, (long)q * chi,
+                                     chi * q, q * chi, chi));
+                // contract the open chi leg with the next corner (C2 resp. C4)
+                r3.push_back(gemm_nn(x2, chi, Cp(s, g + 1), chi, off(st->X2p, blk * n2, e), chi,
+                                     chi * q * q, chi, chi));
+            }
+            // E[s] = Lp (q^2 x chi^2) . Rp (chi^2 x q^2)
+            r4.push_back(gemm_nn(off(st->E, s * n2, e), (long)chi * chi, off(st->E, (4 + s) * n2, e),
+                                 (long)q * q, off(st->Eout, s * q4, e), (long)q * q, q * q, q * q,
+                                 chi * chi));
+        }
+        st->read1 = add_group(st, r1, dt);
+        st->read2 = add_group(st, r2, dt);
+        st->read3 = add_group(st, r3, dt);
+        st->read4 = add_group(st, r4, dt);
+    }
+
+    // upload
+    HIP_CHECK(hipMalloc(&st->d_probs, st->probs.size() * sizeof(GemmProb)));
+    HIP_CHECK(hipMemcpy(st->d_probs, st->probs.data(), st->probs.size() * sizeof(GemmProb),
+                        hipMemcpyHostToDevice));
+    HIP_CHECK(hipMalloc(&st->d_norms, st->norms.size() * sizeof(NormItem)));
+    HIP_CHECK(hipMemcpy(st->d_norms, st->norms.data(), st->norms.size() * sizeof(NormItem),
+                        hipMemcpyHostToDevice));
+    HIP_CHECK(hipMemcpy(st->d_a_lu, st->a_lu, 16 * sizeof(void*), hipMemcpyHostToDevice));
+    HIP_CHECK(hipMemcpy(st->d_a_dl, st->a_dl, 16 * sizeof(void*), hipMemcpyHostToDevice));
+}
+
+void build_layers(ipeps_state* st) {
+    // H_A, H_B, V_A, V_B: bonds named by their left / upper site
+    const int bonds[4][2][2] = {{{0, 0}, {1, 1}}, {{1, 0}, {0, 1}}, {{0, 0}, {1, 1}}, {{1, 0}, {0, 1}}};
+    const int seq_layer[7] = {0, 1, 2, 3, 2, 1, 0};
+    const int seq_full[7] = {0, 0, 0, 1, 0, 0, 0};
+    for (int i = 0; i < 7; ++i) {
+        const int L = seq_layer[i];
+        LayerDesc& ld = st->layers[i];
+        ld.gate = L * 2 + seq_full[i];
+        for (int b = 0; b < 2; ++b) {
+            const int x = bonds[L][b][0], y = bonds[L][b][1];
+            BondDesc& bd = ld.bond[b];
+            if (L < 2) {  // horizontal (x,y).right -- (x+1,y).left
+                bd.site_i = idx(x, y);
+                bd.site_j = idx(x + 1, y);
+                bd.leg_i = 4;
+                bd.leg_j = 2;
+                bd.lam_b = hl(x, y);
+                bd.outer_i[0] = vl(x, y - 1);
+                bd.outer_i[1] = hl(x - 1, y);
+                bd.outer_i[2] = vl(x, y);
+                bd.outer_j[0] = vl(x + 1, y - 1);
+                bd.outer_j[1] = vl(x + 1, y);
+                bd.outer_j[2] = hl(x + 1, y);
+            } else {  // vertical (x,y).down -- (x,y+1).up
+                bd.site_i = idx(x, y);
+                bd.site_j = idx(x, y + 1);
+                bd.leg_i = 3;
+                bd.leg_j = 1;
+                bd.lam_b = vl(x, y);
+                bd.outer_i[0] = vl(x, y - 1);
+                bd.outer_i[1] = hl(x - 1, y);
+                bd.outer_i[2] = hl(x, y);
+                bd.outer_j[0] = hl(x - 1, y + 1);
+                bd.outer_j[1] = vl(x, y + 1);
+                bd.outer_j[2] = hl(x, y + 1);
+            }
+        }
+    }
+}
+
+void set_neel(ipeps_state* st) {
+    const int D = st->D, d = st->d, dA = st->cfg.d_A;
+    const long D4 = (long)D * D * D * D;
+    std::vector<cplx> g(4 * d * D4, cmake(0, 0));
+    for (int s = 0; s < 4; ++s) {
+        const int x = s % 2, y = s / 2;
+        const int p = ((x + y) % 2 == 0) ? 0 : 1;
+        for (int a = 0; a < dA; ++a) g[s * d * D4 + (p * dA + a) * D4] = cmake(1.0 / std::sqrt((double)dA), 0);
+    }
+    std::vector<double> lam(8 * D, 0.0);
+    for (int b = 0; b < 8; ++b) lam[b * D] = 1.0;
+    HIP_CHECK(hipMemcpyAsync(st->gam, g.data(), g.size() * sizeof(cplx), hipMemcpyHostToDevice, st->stream));
+    HIP_CHECK(hipMemcpyAsync(st->lam, lam.data(), lam.size() * sizeof(double), hipMemcpyHostToDevice, st->stream));
+    HIP_CHECK(hipMemsetAsync(st->eps, 0, 4 * sizeof(double), st->stream));
+    HIP_CHECK(hipStreamSynchronize(st->stream));
+}
+
+// ---------------------------------------------------------------- CTMRG pieces
+void prepare_double_layers(ipeps_state* st) {
+    absorb_sqrt_lambda(st->stream, st->D, st->d, st->gam, st->lam, st->A);
+    double_layer_real(st->stream, st->D, st->d, st->A, st->a_base);
+    frame_layouts(st->stream, st->q, st->dtype, st->a_base, st->d_a_lu, st->d_a_dl);
+}
+
+void orth(ipeps_state* st, double* X, const GemmGroup& gram1, const GemmGroup& mul1,
+          const GemmGroup& gram2, const GemmGroup& mul2) {
+    normalize_columns(st->stream, 2, st->n, st->k, X);
+    run(st, gram1);
+    chol_inverse(st->stream, 2, st->k, st->Gm, st->Ri, kCholDrop);
+    run(st, mul1);
+    run(st, gram2);
+    chol_inverse(st->stream, 2, st->k, st->Gm, st->Ri, kCholDrop);
+    run(st, mul2);
+}
+
+// Truncated SVD of the two cut matrices N64[0..1]; fills Us, Vs and g_dev.
+void projector_svd(ipeps_state* st, int slot) {
+    const int n = st->n, k = st->k, chi = st->chi;
+    hipStream_t s = st->stream;
+    if (n <= kDirectMax) {
+        jacobi_svd_real(s, 2, n, n, st->N64, n, (long)n * n, st->sig, st->Uo, st->Vo, st->jwork);
+        projector_factors(s, st->dtype, 2, n, n, chi, st->Uo, st->Vo, st->sig, (long)n * n, st->Us,
+                          st->Vs, (long)n * chi, st->g_dev);
+        return;
+    }
+    const long nk = (long)n * k;
+    SvdPlan& P = st->svd;
+    const bool warm = st->warm_valid[2 * slot];
+    // the current right block V lives in Qz (orthonormal after orth)
+    if (warm) {
+        HIP_CHECK(hipMemcpyAsync(st->Qz, st->warm + 2 * slot * nk, 2 * nk * sizeof(double),
+                                 hipMemcpyDeviceToDevice, s));
+    } else {
+        random_block(s, 2, n, k, st->cfg.seed * 1315423911ull + (uint64_t)slot + 1, st->Zw);
+        orth(st, st->Zw, P.gramZ, P.QfromZ, P.gramQz, P.ZfromQz);
+        HIP_CHECK(hipMemcpyAsync(st->Qz, st->Zw, 2 * nk * sizeof(double), hipMemcpyDeviceToDevice, s));
+    }
+    const int iters = warm ? kWarmIters : kColdIters;
+    for (int it = 0; it < iters; ++it) {
+        run(st, P.NV);  // Yw = N V
+        orth(st, st->Yw, P.gramY, P.QfromY, P.gramQ, P.YfromQ);
+        run(st, P.NtQ);  // Zw = N^T Q
+        orth(st, st->Zw, P.gramZ, P.QfromZ, P.gramQz, P.ZfromQz);
+        HIP_CHECK(hipMemcpyAsync(st->Qz, st->Zw, 2 * nk * sizeof(double), hipMemcpyDeviceToDevice, s));
+    }
+    // Rayleigh-Ritz on span(N V) x span(V)
+    run(st, P.NV);
+    orth(st, st->Yw, P.gramY, P.QfromY, P.gramQ, P.YfromQ);
+    run(st, P.NVfinal);  // Qw = N V
+    run(st, P.Cs);       // Cs = Q^T N V
+    jacobi_svd_real(s, 2, k, k, st->Cs, k, (long)k * k, st->sig, st->Uc, st->Vc, st->jwork);
+    run(st, P.Uo);
+    run(st, P.Vo);
+    HIP_CHECK(hipMemcpyAsync(st->warm + 2 * slot * nk, st->Vo, 2 * nk * sizeof(double),
+                             hipMemcpyDeviceToDevice, s));
+    st->warm_valid[2 * slot] = st->warm_valid[2 * slot + 1] = true;
+    projector_factors(s, st->dtype, 2, n, k, chi, st->Uo, st->Vo, st->sig, nk, st->Us, st->Vs,
+                      (long)n * chi, st->g_dev);
+}
+
+void column_step(ipeps_state* st, int si) {
+    const ColumnStep& cs = st->steps[si];
+    const int q = st->q, chi = st->chi, n = st->n;
+    const long n2 = (long)n * n;
+    hipStream_t s = st->stream;
+    run(st, cs.s1);
+    run(st, cs.s2);
+    batched_transpose(s, st->dtype, 8 * chi, q * q, chi, st->X2, st->X2p);
+    run(st, cs.s3);
+    run(st, cs.half);
+    run(st, cs.nprod);
+    if (st->dtype != IPEPS_DTYPE_FP64) to_fp64(s, st->dtype, st->Nd, st->N64, 2 * n2);
+    projector_svd(st, si);
+    run(st, cs.proj);
+    for (int Y = 0; Y < 2; ++Y) {
+        const size_t e = st->esz;
+        // PupP[c'][D][t4p] <- Pup[c'][t4p][D];  PlowP[q3][c4n][c'] <- Plow[c4n][q3][c']
+        permute3(s, st->dtype, 1, chi, chi, q, off(st->Pup, Y * (long)n * chi, e),
+                 off(st->PupP, Y * (long)n * chi, e));
+        permute3(s, st->dtype, 0, chi, q, chi, off(st->Plow, Y * (long)n * chi, e),
+                 off(st->PlowP, Y * (long)n * chi, e));
+    }
+    run(st, cs.w1);
+    batched_transpose(s, st->dtype, 2 * chi, q * q, chi, st->W1, st->W1p);
+    run(st, cs.w2);
+    run(st, cs.fin);
+    normalize_tensors(s, st->dtype, st->d_norms + cs.norm_first, 6);
+}
+
+void corner_spectra_update(ipeps_state* st, bool first) {
+    const int chi = st->chi;
+    hipStream_t s = st->stream;
+    to_fp64(s, st->dtype, st->Cenv, st->C64, 16L * chi * chi);
+    jacobi_svd_real(s, 16, chi, chi, st->C64, chi, (long)chi * chi, st->csig, nullptr, nullptr,
+                    st->jwork);
+    spectra_delta(s, 16, chi, st->csig, st->spectra, st->spec_prev, st->dev_scalars, first ? 1 : 0);
+    st->spectra_valid = true;
+}
+
+void check_poison(ipeps_state* st) {
+    IPEPS_REQUIRE(!st->poisoned, IPEPS_ENUMERIC, "state poisoned by an earlier NaN/Inf");
+}
+
+int guard(ipeps_state* st, int code) {
+    if (code == IPEPS_ENUMERIC && st) st->poisoned = true;
+    return code;
+}
+
+template <typename F>
+int wrap(ipeps_state* st, F&& fn) {
+    try {
+        fn();
+        return IPEPS_OK;
+    } catch (const status_error& e) {
+        return guard(st, e.code);
+    } catch (const hip_error& e) {
+        fprintf(stderr, "ipeps: %s\n", e.what());
+        return IPEPS_EDEVICE;
+    } catch (const std::bad_alloc&) {
+        return IPEPS_ENOMEM;
+    }
+}
+
+}  // namespace
+
+// ==================================================================== C ABI
+extern "C" {
+
+void ipeps_config_default(ipeps_config* c) {
+    if (!c) return;
+    std::memset(c, 0, sizeof(*c));
+    c->D = 2;
+    c->chi = 8;
+    c->d_A = 2;
+    c->J = 1.0;
+    c->V = 1.0;
+    c->W = 5.0;
+    c->dt = 0.05;
+    c->trotter_order = 2;
+    c->dtype = IPEPS_DTYPE_FP64;
+    for (int l = 0; l < 4; ++l) {
+        c->layer_J[l] = 1.0;
+        c->layer_V[l] = 1.0;
+        c->layer_w[l] = 0.25;
+    }
+    c->seed = 1;
+}
+
+static void fill_dims(ipeps_state* st, const ipeps_config* cfg) {
+    st->cfg = *cfg;
+    st->D = cfg->D;
+    st->d = 2 * cfg->d_A;
+    st->q = cfg->D * cfg->D;
+    st->chi = cfg->chi;
+    st->n = cfg->chi * st->q;
+    st->k = choose_k(st->n, cfg->chi);
+    st->dtype = cfg->dtype;
+    st->esz = cfg->dtype == IPEPS_DTYPE_FP64 ? sizeof(double) : sizeof(float);
+}
+
+size_t ipeps_footprint_bytes(const ipeps_config* cfg) {
+    try {
+        validate(cfg);
+        ipeps_state* st = new ipeps_state();
+        fill_dims(st, cfg);
+        st->mem.dry = true;
+        allocate(st);
+        size_t tot = st->mem.total;
+        delete st;
+        return tot + (1 << 20);  // plan tables
+    } catch (...) {
+        return 0;
+    }
+}
+
+int ipeps_init(const ipeps_config* cfg, void* hip_stream, ipeps_alloc_fn alloc, ipeps_free_fn free_fn,
+               void* alloc_ctx, ipeps_state** out) {
+    if (!out) return IPEPS_EINVAL;
+    *out = nullptr;
+    ipeps_state* st = nullptr;
+    int rc = wrap(nullptr, [&] {
+        validate(cfg);
+        int ndev = 0;
+        if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1)
+            throw status_error(IPEPS_EDEVICE, "no HIP device");
+        st = new ipeps_state();
+        fill_dims(st, cfg);
+        st->stream = (hipStream_t)hip_stream;
+        st->mem.alloc = alloc;
+        st->mem.free_fn = free_fn;
+        st->mem.ctx = alloc_ctx;
+        st->mem.stream = st->stream;
+        allocate(st);
+        HIP_CHECK(hipHostMalloc((void**)&st->host_buf, 65536 * sizeof(double), hipHostMallocDefault));
+        build_layers(st);
+        build_plan(st);
+        build_gates(st->stream, st->cfg, st->gates);
+        set_neel(st);
+    });
+    if (rc != IPEPS_OK) {
+        if (st) ipeps_destroy(st);
+        return rc;
+    }
+    *out = st;
+    return IPEPS_OK;
+}
+
+void ipeps_destroy(ipeps_state* st) {
+    if (!st) return;
+    (void)hipStreamSynchronize(st->stream);
+    st->mem.release();
+    if (st->d_probs) (void)hipFree(st->d_probs);
+    if (st->d_norms) (void)hipFree(st->d_norms);
+    if (st->host_buf) (void)hipHostFree(st->host_buf);
+    delete st;
+}
+
+int ipeps_set_state(ipeps_state* st, const double* gamma, const double* lambda) {
+    if (!st || !gamma || !lambda) return IPEPS_EINVAL;
+    return wrap(st, [&] {
+        const long D4 = (long)st->D * st->D * st->D * st->D;
+        for (long i = 0; i < 8L * st->D; ++i)
+            IPEPS_REQUIRE(std::isfinite(lambda[i]) && lambda[i] >= 0, IPEPS_EINVAL, "bad lambda");
+        HIP_CHECK(hipMemcpyAsync(st->gam, gamma, 4 * st->d * D4 * sizeof(cplx), hipMemcpyHostToDevice, st->stream));
+        HIP_CHECK(hipMemcpyAsync(st->lam, lambda, 8 * st->D * sizeof(double), hipMemcpyHostToDevice, st->stream));
+        HIP_CHECK(hipMemsetAsync(st->eps, 0, 4 * sizeof(double), st->stream));
+        HIP_CHECK(hipStreamSynchronize(st->stream));
+        st->have_env = false;
+        st->poisoned = false;
+        st->spectra_valid = false;
+        for (bool& w : st->warm_valid) w = false;
+    });
+}
+
+int ipeps_get_state(ipeps_state* st, double* gamma, double* lambda) {
+    if (!st) return IPEPS_EINVAL;
+    return wrap(st, [&] {
+        const long D4 = (long)st->D * st->D * st->D * st->D;
+        if (gamma) HIP_CHECK(hipMemcpyAsync(gamma, st->gam, 4 * st->d * D4 * sizeof(cplx), hipMemcpyDeviceToHost, st->stream));
+        if (lambda) HIP_CHECK(hipMemcpyAsync(lambda, st->lam, 8 * st->D * sizeof(double), hipMemcpyDeviceToHost, st->stream));
+        HIP_CHECK(hipStreamSynchronize(st->stream));
+    });
+}
+
+int ipeps_trotter_step(ipeps_state* st, int n_steps, double* trunc_err_out) {
+    if (!st || n_steps < 0) return IPEPS_EINVAL;
+    return wrap(st, [&] {
+        check_poison(st);
+        for (int t = 0; t < n_steps; ++t) {
+            for (int l = 0; l < 7; ++l)
+                su_layer(st->stream, st->D, st->d, st->layers[l], st->gam, st->lam, st->eps, st->gates,
+                         st->su_scratch);
+            st->step_count++;
+        }
+        if (trunc_err_out) {
+            HIP_CHECK(hipMemcpyAsync(st->host_buf, st->eps, 4 * sizeof(double), hipMemcpyDeviceToHost, st->stream));
+            HIP_CHECK(hipMemcpyAsync(st->host_buf + 4, st->lam, 8 * st->D * sizeof(double), hipMemcpyDeviceToHost, st->stream));
+            HIP_CHECK(hipStreamSynchronize(st->stream));
+            for (int i = 0; i < 4; ++i) trunc_err_out[i] = st->host_buf[i];
+            for (int i = 0; i < 8 * st->D; ++i)
+                IPEPS_REQUIRE(std::isfinite(st->host_buf[4 + i]), IPEPS_ENUMERIC, "NaN in bond weights");
+        }
+    });
+}
+
+int ctmrg_converge(ipeps_state* st, double tol, int max_iter, int cold_start, int* iters, double* delta) {
+    if (!st || max_iter < 1) return IPEPS_EINVAL;
+    int it_done = 0;
+    double dl = INFINITY;
+    int rc = wrap(st, [&] {
+        check_poison(st);
+        prepare_double_layers(st);
+        bool first = false;
+        if (cold_start || !st->have_env) {
+            init_environment(st->stream, st->D, st->chi, st->dtype, st->a_base, st->Cenv, st->Tenv);
+            for (bool& w : st->warm_valid) w = false;
+            st->have_env = true;
+            corner_spectra_update(st, true);
+            first = true;
+        } else if (!st->spectra_valid) {
+            corner_spectra_update(st, true);
+        }
+        (void)first;
+        for (int it = 0; it < max_iter; ++it) {
+            for (int si = 0; si < 8; ++si) column_step(st, si);
+            corner_spectra_update(st, false);
+            it_done = it + 1;
+            if (tol > 0 || it + 1 == max_iter) {
+                HIP_CHECK(hipMemcpyAsync(st->host_buf, st->dev_scalars, sizeof(double), hipMemcpyDeviceToHost, st->stream));
+                HIP_CHECK(hipStreamSynchronize(st->stream));
+                dl = st->host_buf[0];
+                IPEPS_REQUIRE(!std::isnan(dl), IPEPS_ENUMERIC, "NaN in the environment");
+                if (tol > 0 && dl < tol) break;
+            }
+        }
+        st->last_iters = it_done;
+        st->last_delta = dl;
+        if (tol > 0 && !(dl < tol)) throw status_error(IPEPS_ENOTCONV, "CTMRG not converged");
+    });
+    if (iters) *iters = it_done;
+    if (delta) *delta = dl;
+    return rc;
+}
+
+int ipeps_observe(ipeps_state* st, ipeps_obs* out) {
+    if (!st || !out) return IPEPS_EINVAL;
+    return wrap(st, [&] {
+        check_poison(st);
+        IPEPS_REQUIRE(st->have_env, IPEPS_EINVAL, "no environment: call ctmrg_converge first");
+        const int q = st->q, chi = st->chi, n = st->n;
+        const long n2 = (long)n * n, q4 = (long)q * q * q * q;
+        const size_t e = st->esz;
+        hipStream_t s = st->stream;
+        run(st, st->read1);
+        run(st, st->read2);
+        run(st, st->read3);
+        for (int site = 0; site < 4; ++site) {
+            // Lp[q^2][t4p][t2p] <- L'[t4p][q^2][t2p];  Rp[t4p][t2p][q^2] <- R'[t2p][q^2][t4p]
+            permute3(s, st->dtype, 0, chi, q * q, chi, off(st->X2p, site * n2, e), off(st->E, site * n2, e));
+            permute3(s, st->dtype, 2, chi, q * q, chi, off(st->X2p, (4 + site) * n2, e),
+                     off(st->E, (4 + site) * n2, e));
+        }
+        run(st, st->read4);
+        to_fp64(s, st->dtype, st->Eout, st->E64, 4 * q4);
+        readout(s, st->D, st->d, st->cfg.d_A, st->E64, st->A, st->rho, st->obs_dev);
+        HIP_CHECK(hipMemcpyAsync(st->host_buf, st->obs_dev, 8 * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIP_CHECK(hipMemcpyAsync(st->host_buf + 8, st->eps, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIP_CHECK(hipStreamSynchronize(s));
+        const double* h = st->host_buf;
+        for (int i = 0; i < 7; ++i) IPEPS_REQUIRE(std::isfinite(h[i]), IPEPS_ENUMERIC, "NaN in readout");
+        out->t = st->step_count * st->cfg.dt;
+        for (int i = 0; i < 4; ++i) out->n[i] = h[i];
+        out->imbalance = h[4];
+        out->sum_n = h[5];
+        out->max_offdiag = h[6];
+        for (int i = 0; i < 4; ++i) out->trunc_err[i] = h[8 + i];
+        out->ctm_iters = st->last_iters;
+        out->ctm_delta = st->last_delta;
+    });
+}
+
+int ipeps_corner_spectra(ipeps_state* st, double* out) {
+    if (!st || !out) return IPEPS_EINVAL;
+    return wrap(st, [&] {
+        IPEPS_REQUIRE(st->have_env, IPEPS_EINVAL, "no environment");
+        if (!st->spectra_valid) corner_spectra_update(st, true);
+        HIP_CHECK(hipMemcpyAsync(out, st->spectra, 16L * st->chi * sizeof(double), hipMemcpyDeviceToHost, st->stream));
+        HIP_CHECK(hipStreamSynchronize(st->stream));
+    });
+}
+
+int ipeps_bond_spectra(ipeps_state* st, double* out) {
+    if (!st || !out) return IPEPS_EINVAL;
+    return wrap(st, [&] {
+        HIP_CHECK(hipMemcpyAsync(out, st->lam, 8L * st->D * sizeof(double), hipMemcpyDeviceToHost, st->stream));
+        HIP_CHECK(hipStreamSynchronize(st->stream));
+    });
+}
+
+const char* ipeps_strerror(int code) {
+    switch (code) {
+        case IPEPS_OK: return "ok";
+        case IPEPS_EINVAL: return "invalid argument";
+        case IPEPS_ENOMEM: return "out of device memory";
+        case IPEPS_EDEVICE: return "HIP device error";
+        case IPEPS_ENUMERIC: return "NaN/Inf in the state";
+        case IPEPS_ENOTCONV: return "CTMRG did not converge";
+        case IPEPS_EAGAIN: return "not finished";
+        case IPEPS_ENOTFOUND: return "unknown job";
+        default: return "unknown error";
+    }
+}
+
+}  // extern "C"

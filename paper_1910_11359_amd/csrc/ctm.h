@@ -1,0 +1,73 @@
+// CTMRG support kernels: double layer in the Hermitian (real) basis, frame
+// layouts, cold environment, permutations, norms, spectra and readout.
+#pragma once
+
+#include "common.h"
+
+namespace ipeps {
+
+// A = Gamma with sqrt(lambda) on its four legs, for the 4 sites.
+void absorb_sqrt_lambda(hipStream_t s, int D, int d, const cplx* gam, const double* lam,
+                        cplx* A);
+
+// Double layer of each site in the real basis: a[m_u][m_l][m_d][m_r] (FP64),
+// up/left legs in the basis {H_m}, down/right legs in {H_m^T}, where for the
+// pair (k, k') of a leg, m = k*D + k' and H_m = E_kk (k = k'),
+// (E_kk' + E_k'k)/sqrt2 (k < k'), i(E_kk' - E_k'k)/sqrt2 (k > k').
+void double_layer_real(hipStream_t s, int D, int d, const cplx* A, double* a_base);
+
+// Frame copies: for site s and rotation g, out_lu[s][g] = rot^g(a) stored as
+// [L][U][D][R] and out_dl[s][g] stored as [D][L][U][R] (frame legs), in the
+// CTMRG dtype.  rot^g maps frame leg F to physical leg (F - g) mod 4.
+void frame_layouts(hipStream_t s, int q, int dtype, const double* a_base, void* const* out_lu,
+                   void* const* out_dl);
+
+// Cold environment: every C/T of every site is its neighbour's double layer
+// with the outward legs closed by the identity (diagonal basis elements),
+// embedded in chi.  C[(site*4 + k) * chi^2], T[(site*4 + k) * chi*q*chi].
+void init_environment(hipStream_t s, int D, int chi, int dtype, const double* a_base, void* C,
+                      void* T);
+
+// out[b][c][r] = in[b][r][c] for b < batch (rows R, cols Cc), dtype elements.
+void batched_transpose(hipStream_t s, int dtype, int batch, int R, int Cc, const void* in,
+                       void* out);
+
+// Rank-3 permutations of small tensors (dtype elements):
+//   mode 0: out[b][a][c] = in[a][b][c];  mode 1: out[a][c][b] = in[a][b][c];
+//   mode 2: out[c][a][b] = in[a][b][c]
+void permute3(hipStream_t s, int dtype, int mode, int A, int B, int C, const void* in, void* out);
+
+// Divide each tensor by its Frobenius norm (accumulated in FP64).
+struct NormItem {
+    void* ptr;
+    long count;
+};
+void normalize_tensors(hipStream_t s, int dtype, const NormItem* d_items, int n);
+
+// Convert between dtype and FP64.
+void to_fp64(hipStream_t s, int dtype, const void* in, double* out, long count);
+void from_fp64(hipStream_t s, int dtype, const double* in, void* out, long count);
+
+// Projector factors from an SVD of the cut matrix: the truncation rule on
+// sigma (k values, descending) picks g <= chi; Us[i][c] = U[i][c]/sqrt(s_c),
+// Vs[i][c] = V[i][c]/sqrt(s_c) for c < g, zero for g <= c < chi (n x chi,
+// dtype).  U and V are n x k row-major (ld k).  g_out[b] receives g.
+void projector_factors(hipStream_t s, int dtype, int batch, int n, int k, int chi,
+                       const double* U, const double* V, const double* sigma, long strideUV,
+                       void* Us, void* Vs, long strideP, int* g_out);
+
+// Normalised corner spectra (16 x chi) from raw singular values; delta_out =
+// max over corners of |s - s_prev|_2; prev <- current.
+void spectra_delta(hipStream_t s, int nspec, int chi, const double* sig, double* spectra,
+                   double* prev, double* delta_out, int first);
+
+// Random n x k starting block (seeded counter-based uniforms in [-1, 1)).
+void random_block(hipStream_t s, int batch, int n, int k, uint64_t seed, double* X);
+
+// One-site reduced density matrices from the site environments E (real
+// basis, [L][U][R][D] each q^4, FP64) and A; writes rho (4 x d x d complex,
+// trace-normalised) and obs[0..9] = n[4], imbalance, sum_n, max_offdiag.
+void readout(hipStream_t s, int D, int d, int d_A, const double* E, const cplx* A, cplx* rho,
+             double* obs);
+
+}  // namespace ipeps

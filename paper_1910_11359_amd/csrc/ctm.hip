@@ -1,0 +1,538 @@
+// CTMRG support kernels (double layer, layouts, environment init, permutes,
+// norms, projector factors, spectra, readout).
+#include "ctm.h"
+
+#include <cmath>
+
+namespace ipeps {
+
+__device__ inline int site_idx(int x, int y) { return ((x % 2 + 2) % 2) + 2 * ((y % 2 + 2) % 2); }
+
+// ------------------------------------------------------------ A = Gamma sqrt(lambda)
+__global__ void k_absorb(int D, int d, const cplx* __restrict__ gam, const double* __restrict__ lam,
+                         cplx* __restrict__ A) {
+    const int site = blockIdx.y;
+    const int x = site % 2, y = site / 2;
+    const long D4 = (long)D * D * D * D, sz = d * D4;
+    const double* lu = lam + (4 + site_idx(x, y - 1)) * D;
+    const double* ll = lam + site_idx(x - 1, y) * D;
+    const double* ld = lam + (4 + site_idx(x, y)) * D;
+    const double* lr = lam + site_idx(x, y) * D;
+    for (long e = blockIdx.x * blockDim.x + threadIdx.x; e < sz; e += (long)gridDim.x * blockDim.x) {
+        const int r = e % D, dd = (e / D) % D, l = (e / (D * D)) % D, u = (e / (D * D * D)) % D;
+        const double w = sqrt(lu[u] * ll[l] * ld[dd] * lr[r]);
+        A[site * sz + e] = cscale(gam[site * sz + e], w);
+    }
+}
+
+void absorb_sqrt_lambda(hipStream_t s, int D, int d, const cplx* gam, const double* lam, cplx* A) {
+    const long sz = (long)d * D * D * D * D;
+    hipLaunchKernelGGL(k_absorb, dim3(ceil_div(sz, 256), 4), dim3(256), 0, s, D, d, gam, lam, A);
+    HIP_CHECK(hipGetLastError());
+}
+
+// ------------------------------------------------------------ Hermitian basis
+// Forward terms of one leg: a_H[m] = sum_t c_t a[(x_t, y_t)] for the basis of
+// pair m = (k, k'); H^T legs read a at (y_t, x_t).
+struct LegTerms {
+    int n;
+    int x[2], y[2];
+    cplx c[2];
+};
+__device__ inline LegTerms fwd_terms(int m, int D, bool transposed) {
+    const int k = m / D, kp = m % D;
+    const double h = 0.70710678118654752440;
+    LegTerms t;
+    if (k == kp) {
+        t.n = 1;
+        t.x[0] = k;
+        t.y[0] = k;
+        t.c[0] = cmake(1, 0);
+    } else {
+        t.n = 2;
+        t.x[0] = k;
+        t.y[0] = kp;
+        t.x[1] = kp;
+        t.y[1] = k;
+        if (k < kp) {
+            t.c[0] = cmake(h, 0);
+            t.c[1] = cmake(h, 0);
+        } else {
+            t.c[0] = cmake(0, h);
+            t.c[1] = cmake(0, -h);
+        }
+    }
+    if (transposed)
+        for (int i = 0; i < t.n; ++i) {
+            int tmp = t.x[i];
+            t.x[i] = t.y[i];
+            t.y[i] = tmp;
+        }
+    return t;
+}
+
+// Inverse terms: E_c[(k, k')] = sum_t c_t E_H[m_t] (H legs); H^T legs use the
+// pair (k', k).
+struct InvTerms {
+    int n;
+    int m[2];
+    cplx c[2];
+};
+__device__ inline InvTerms inv_terms(int k, int kp, int D, bool transposed) {
+    if (transposed) {
+        int t = k;
+        k = kp;
+        kp = t;
+    }
+    const double h = 0.70710678118654752440;
+    InvTerms t;
+    if (k == kp) {
+        t.n = 1;
+        t.m[0] = k * D + k;
+        t.c[0] = cmake(1, 0);
+    } else if (k < kp) {
+        t.n = 2;
+        t.m[0] = k * D + kp;  // symmetric element
+        t.c[0] = cmake(h, 0);
+        t.m[1] = kp * D + k;  // antisymmetric element, H[k][k'] = -i/sqrt2
+        t.c[1] = cmake(0, -h);
+    } else {
+        t.n = 2;
+        t.m[0] = kp * D + k;
+        t.c[0] = cmake(h, 0);
+        t.m[1] = k * D + kp;  // H[k][k'] = +i/sqrt2
+        t.c[1] = cmake(0, h);
+    }
+    return t;
+}
+
+__global__ void k_double_layer(int D, int d, const cplx* __restrict__ A, double* __restrict__ a) {
+    const int site = blockIdx.y;
+    const int q = D * D;
+    const long q4 = (long)q * q * q * q;
+    const long D4 = (long)D * D * D * D;
+    const cplx* As = A + site * d * D4;
+    for (long e = blockIdx.x * blockDim.x + threadIdx.x; e < q4; e += (long)gridDim.x * blockDim.x) {
+        const int mr = e % q, md = (e / q) % q, ml = (e / (q * q)) % q, mu = e / ((long)q * q * q);
+        const LegTerms tu = fwd_terms(mu, D, false), tl = fwd_terms(ml, D, false);
+        const LegTerms td = fwd_terms(md, D, true), tr = fwd_terms(mr, D, true);
+        double acc = 0.0;
+        for (int iu = 0; iu < tu.n; ++iu)
+            for (int il = 0; il < tl.n; ++il)
+                for (int id = 0; id < td.n; ++id)
+                    for (int ir = 0; ir < tr.n; ++ir) {
+                        const cplx c = cmul(cmul(tu.c[iu], tl.c[il]), cmul(td.c[id], tr.c[ir]));
+                        const long kx = (((long)tu.x[iu] * D + tl.x[il]) * D + td.x[id]) * D + tr.x[ir];
+                        const long ky = (((long)tu.y[iu] * D + tl.y[il]) * D + td.y[id]) * D + tr.y[ir];
+                        cplx s = cmake(0, 0);
+                        for (int p = 0; p < d; ++p) s = cadd(s, cmul(As[p * D4 + kx], cconj(As[p * D4 + ky])));
+                        acc += cmul(c, s).re;
+                    }
+        a[site * q4 + e] = acc;
+    }
+}
+
+void double_layer_real(hipStream_t s, int D, int d, const cplx* A, double* a_base) {
+    const long q = (long)D * D, q4 = q * q * q * q;
+    hipLaunchKernelGGL(k_double_layer, dim3(ceil_div(q4, 256), 4), dim3(256), 0, s, D, d, A, a_base);
+    HIP_CHECK(hipGetLastError());
+}
+
+// ------------------------------------------------------------ frame layouts
+template <typename T>
+__global__ void k_frame_layouts(int q, const double* __restrict__ a_base, T* const* out_lu,
+                                T* const* out_dl) {
+    const int which = blockIdx.y;  // site*8 + g*2 + kind
+    const int site = which / 8, g = (which / 2) % 4, kind = which % 2;
+    T* out = kind == 0 ? out_lu[site * 4 + g] : out_dl[site * 4 + g];
+    const long q4 = (long)q * q * q * q;
+    const double* a = a_base + site * q4;
+    for (long e = blockIdx.x * blockDim.x + threadIdx.x; e < q4; e += (long)gridDim.x * blockDim.x) {
+        const int i3 = e % q, i2 = (e / q) % q, i1 = (e / ((long)q * q)) % q, i0 = e / ((long)q * q * q);
+        int f[4];  // frame legs U, L, D, R
+        if (kind == 0) {  // [L][U][D][R]
+            f[1] = i0; f[0] = i1; f[2] = i2; f[3] = i3;
+        } else {          // [D][L][U][R]
+            f[2] = i0; f[1] = i1; f[0] = i2; f[3] = i3;
+        }
+        int p[4];
+        for (int F = 0; F < 4; ++F) p[(F - g + 4) % 4] = f[F];
+        const long src = (((long)p[0] * q + p[1]) * q + p[2]) * q + p[3];
+        out[e] = (T)a[src];
+    }
+}
+
+void frame_layouts(hipStream_t s, int q, int dtype, const double* a_base, void* const* out_lu,
+                   void* const* out_dl) {
+    const long q4 = (long)q * q * q * q;
+    dim3 grid(ceil_div(q4, 256) < 4096 ? ceil_div(q4, 256) : 4096, 32);
+    if (dtype == IPEPS_DTYPE_FP64)
+        hipLaunchKernelGGL(k_frame_layouts<double>, grid, dim3(256), 0, s, q, a_base,
+                           (double* const*)out_lu, (double* const*)out_dl);
+    else
+        hipLaunchKernelGGL(k_frame_layouts<float>, grid, dim3(256), 0, s, q, a_base,
+                           (float* const*)out_lu, (float* const*)out_dl);
+    HIP_CHECK(hipGetLastError());
+}
+
+// ------------------------------------------------------------ cold environment
+template <typename T>
+__global__ void k_init_env(int D, int chi, const double* __restrict__ a_base, T* C, T* T_) {
+    const int site = blockIdx.y / 8, which = blockIdx.y % 8;  // 0..3 corners, 4..7 edges
+    const int x = site % 2, y = site / 2;
+    const int q = D * D;
+    const long q2 = (long)q * q, q3 = q2 * q, q4 = q3 * q;
+    auto A = [&](int xx, int yy) { return a_base + site_idx(xx, yy) * q4; };
+    if (which < 4) {
+        const int k = which;
+        T* out = C + (long)(site * 4 + k) * chi * chi;
+        for (long e = blockIdx.x * blockDim.x + threadIdx.x; e < (long)chi * chi;
+             e += (long)gridDim.x * blockDim.x) {
+            const int i = e / chi, j = e % chi;
+            double v = 0.0;
+            if (i < q && j < q) {
+                for (int t1 = 0; t1 < D; ++t1)
+                    for (int t2 = 0; t2 < D; ++t2) {
+                        const int m1 = t1 * (D + 1), m2 = t2 * (D + 1);
+                        if (k == 0) v += A(x - 1, y - 1)[m1 * q3 + m2 * q2 + i * q + j];       // tr u,l -> [d][r]
+                        else if (k == 1) v += A(x + 1, y - 1)[m1 * q3 + i * q2 + j * q + m2];  // tr u,r -> [l][d]
+                        else if (k == 2) v += A(x + 1, y + 1)[i * q3 + j * q2 + m1 * q + m2];  // tr d,r -> [u][l]
+                        else v += A(x - 1, y + 1)[j * q3 + m1 * q2 + m2 * q + i];              // tr l,d -> [r][u]
+                    }
+            }
+            out[e] = (T)v;
+        }
+    } else {
+        const int k = which - 4;
+        T* out = T_ + (long)(site * 4 + k) * chi * q * chi;
+        for (long e = blockIdx.x * blockDim.x + threadIdx.x; e < (long)chi * q * chi;
+             e += (long)gridDim.x * blockDim.x) {
+            const int i = e / ((long)q * chi), mq = (e / chi) % q, j = e % chi;
+            double v = 0.0;
+            if (i < q && j < q) {
+                for (int t1 = 0; t1 < D; ++t1) {
+                    const int m1 = t1 * (D + 1);
+                    if (k == 0) v += A(x, y - 1)[m1 * q3 + i * q2 + mq * q + j];       // tr u -> [l][d][r]
+                    else if (k == 1) v += A(x + 1, y)[i * q3 + mq * q2 + j * q + m1];  // tr r -> [u][l][d]
+                    else if (k == 2) v += A(x, y + 1)[mq * q3 + j * q2 + m1 * q + i];  // tr d -> [r][u][l]
+                    else v += A(x - 1, y)[j * q3 + m1 * q2 + i * q + mq];              // tr l -> [d][r][u]
+                }
+            }
+            out[e] = (T)v;
+        }
+    }
+}
+
+void init_environment(hipStream_t s, int D, int chi, int dtype, const double* a_base, void* C,
+                      void* T) {
+    const long big = (long)chi * D * D * chi;
+    dim3 grid(ceil_div(big, 256) < 2048 ? ceil_div(big, 256) : 2048, 32);
+    if (dtype == IPEPS_DTYPE_FP64)
+        hipLaunchKernelGGL(k_init_env<double>, grid, dim3(256), 0, s, D, chi, a_base, (double*)C,
+                           (double*)T);
+    else
+        hipLaunchKernelGGL(k_init_env<float>, grid, dim3(256), 0, s, D, chi, a_base, (float*)C,
+                           (float*)T);
+    HIP_CHECK(hipGetLastError());
+}
+
+// ------------------------------------------------------------ permutations
+template <typename T>
+__global__ __launch_bounds__(256) void k_transpose(int R, int Cc, const T* __restrict__ in,
+                                                   T* __restrict__ out) {
+    __shared__ T tile[32][33];
+    const long b = blockIdx.z;
+    const T* ib = in + b * (long)R * Cc;
+    T* ob = out + b * (long)R * Cc;
+    const int r0 = blockIdx.y * 32, c0 = blockIdx.x * 32;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+    for (int k = ty; k < 32; k += 8) {
+        const int r = r0 + k, c = c0 + tx;
+        if (r < R && c < Cc) tile[k][tx] = ib[(long)r * Cc + c];
+    }
+    __syncthreads();
+    for (int k = ty; k < 32; k += 8) {
+        const int c = c0 + k, r = r0 + tx;
+        if (r < R && c < Cc) ob[(long)c * R + r] = tile[tx][k];
+    }
+}
+
+void batched_transpose(hipStream_t s, int dtype, int batch, int R, int Cc, const void* in,
+                       void* out) {
+    dim3 grid(ceil_div(Cc, 32), ceil_div(R, 32), batch);
+    if (dtype == IPEPS_DTYPE_FP64)
+        hipLaunchKernelGGL(k_transpose<double>, grid, dim3(256), 0, s, R, Cc, (const double*)in,
+                           (double*)out);
+    else
+        hipLaunchKernelGGL(k_transpose<float>, grid, dim3(256), 0, s, R, Cc, (const float*)in,
+                           (float*)out);
+    HIP_CHECK(hipGetLastError());
+}
+
+template <typename T>
+__global__ void k_permute3(int mode, int A, int B, int C, const T* __restrict__ in, T* __restrict__ out) {
+    const long tot = (long)A * B * C;
+    for (long e = blockIdx.x * blockDim.x + threadIdx.x; e < tot; e += (long)gridDim.x * blockDim.x) {
+        const int c = e % C, b = (e / C) % B, a = e / ((long)B * C);
+        long o;
+        if (mode == 0) o = ((long)b * A + a) * C + c;
+        else if (mode == 1) o = ((long)a * C + c) * B + b;
+        else o = ((long)c * A + a) * B + b;
+        out[o] = in[e];
+    }
+}
+
+void permute3(hipStream_t s, int dtype, int mode, int A, int B, int C, const void* in, void* out) {
+    const long tot = (long)A * B * C;
+    const int grid = ceil_div(tot, 256) < 4096 ? ceil_div(tot, 256) : 4096;
+    if (dtype == IPEPS_DTYPE_FP64)
+        hipLaunchKernelGGL(k_permute3<double>, dim3(grid), dim3(256), 0, s, mode, A, B, C,
+                           (const double*)in, (double*)out);
+    else
+        hipLaunchKernelGGL(k_permute3<float>, dim3(grid), dim3(256), 0, s, mode, A, B, C,
+                           (const float*)in, (float*)out);
+    HIP_CHECK(hipGetLastError());
+}
+
+// ------------------------------------------------------------ norms / conversion
+template <typename T>
+__global__ __launch_bounds__(1024) void k_normalize(const NormItem* items) {
+    __shared__ double red[16];
+    const NormItem it = items[blockIdx.x];
+    T* p = (T*)it.ptr;
+    double s = 0.0;
+    for (long e = threadIdx.x; e < it.count; e += blockDim.x) {
+        const double v = (double)p[e];
+        s += v * v;
+    }
+    s = block_sum(s, red);
+    const double inv = s > 0 ? 1.0 / sqrt(s) : 0.0;
+    for (long e = threadIdx.x; e < it.count; e += blockDim.x) p[e] = (T)((double)p[e] * inv);
+}
+
+void normalize_tensors(hipStream_t s, int dtype, const NormItem* d_items, int n) {
+    if (n <= 0) return;
+    if (dtype == IPEPS_DTYPE_FP64)
+        hipLaunchKernelGGL(k_normalize<double>, dim3(n), dim3(1024), 0, s, d_items);
+    else
+        hipLaunchKernelGGL(k_normalize<float>, dim3(n), dim3(1024), 0, s, d_items);
+    HIP_CHECK(hipGetLastError());
+}
+
+template <typename T>
+__global__ void k_to64(const T* in, double* out, long n) {
+    for (long e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x)
+        out[e] = (double)in[e];
+}
+template <typename T>
+__global__ void k_from64(const double* in, T* out, long n) {
+    for (long e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x)
+        out[e] = (T)in[e];
+}
+
+void to_fp64(hipStream_t s, int dtype, const void* in, double* out, long count) {
+    const int grid = ceil_div(count, 256) < 8192 ? ceil_div(count, 256) : 8192;
+    if (count <= 0) return;
+    if (dtype == IPEPS_DTYPE_FP64)
+        hipLaunchKernelGGL(k_to64<double>, dim3(grid), dim3(256), 0, s, (const double*)in, out, count);
+    else
+        hipLaunchKernelGGL(k_to64<float>, dim3(grid), dim3(256), 0, s, (const float*)in, out, count);
+    HIP_CHECK(hipGetLastError());
+}
+
+void from_fp64(hipStream_t s, int dtype, const double* in, void* out, long count) {
+    const int grid = ceil_div(count, 256) < 8192 ? ceil_div(count, 256) : 8192;
+    if (count <= 0) return;
+    if (dtype == IPEPS_DTYPE_FP64)
+        hipLaunchKernelGGL(k_from64<double>, dim3(grid), dim3(256), 0, s, in, (double*)out, count);
+    else
+        hipLaunchKernelGGL(k_from64<float>, dim3(grid), dim3(256), 0, s, in, (float*)out, count);
+    HIP_CHECK(hipGetLastError());
+}
+
+// ------------------------------------------------------------ projector factors
+__device__ inline int trunc_rule_dev(const double* s, int n, int K) {
+    if (n <= 0 || !(s[0] > 0.0)) return 0;
+    int r = 0;
+    for (int i = 0; i < n; ++i) r += s[i] > 1e-12 * s[0];
+    int g = r < K ? r : K;
+    if (g < r)
+        while (g > 1 && s[g - 1] - s[g] <= 1e-10 * s[g - 1]) --g;
+    return g;
+}
+
+template <typename T>
+__global__ __launch_bounds__(1024) void k_proj_factors(int n, int k, int chi, const double* U,
+                                                       const double* V, const double* sigma,
+                                                       long strideUV, T* Us, T* Vs, long strideP,
+                                                       int* g_out) {
+    __shared__ int g_s;
+    __shared__ double w[256];
+    const int b = blockIdx.x;
+    const double* sg = sigma + (long)b * k;
+    if (threadIdx.x == 0) {
+        g_s = trunc_rule_dev(sg, k, chi);
+        g_out[b] = g_s;
+    }
+    __syncthreads();
+    const int g = g_s;
+    for (int c = threadIdx.x; c < chi; c += blockDim.x) w[c] = (c < g) ? 1.0 / sqrt(sg[c]) : 0.0;
+    __syncthreads();
+    const double* Ub = U + b * strideUV;
+    const double* Vb = V + b * strideUV;
+    T* us = Us + b * strideP;
+    T* vs = Vs + b * strideP;
+    for (long e = threadIdx.x; e < (long)n * chi; e += blockDim.x) {
+        const int i = e / chi, c = e % chi;
+        const double wc = w[c];
+        us[e] = (T)(wc != 0.0 ? Ub[(long)i * k + c] * wc : 0.0);
+        vs[e] = (T)(wc != 0.0 ? Vb[(long)i * k + c] * wc : 0.0);
+    }
+}
+
+void projector_factors(hipStream_t s, int dtype, int batch, int n, int k, int chi,
+                       const double* U, const double* V, const double* sigma, long strideUV,
+                       void* Us, void* Vs, long strideP, int* g_out) {
+    IPEPS_REQUIRE(chi <= 256, IPEPS_EINVAL, "chi > 256");
+    if (dtype == IPEPS_DTYPE_FP64)
+        hipLaunchKernelGGL(k_proj_factors<double>, dim3(batch), dim3(1024), 0, s, n, k, chi, U, V,
+                           sigma, strideUV, (double*)Us, (double*)Vs, strideP, g_out);
+    else
+        hipLaunchKernelGGL(k_proj_factors<float>, dim3(batch), dim3(1024), 0, s, n, k, chi, U, V,
+                           sigma, strideUV, (float*)Us, (float*)Vs, strideP, g_out);
+    HIP_CHECK(hipGetLastError());
+}
+
+// ------------------------------------------------------------ spectra
+__global__ void k_spectra_delta(int nspec, int chi, const double* sig, double* spectra, double* prev,
+                                double* delta_out, int first) {
+    __shared__ double dmax[64];
+    const int c = threadIdx.x;
+    double dl = 0.0;
+    if (c < nspec) {
+        const double* sc = sig + (long)c * chi;
+        double n2 = 0;
+        for (int i = 0; i < chi; ++i) n2 += sc[i] * sc[i];
+        const double inv = n2 > 0 ? 1.0 / sqrt(n2) : 0.0;
+        double d2 = 0;
+        for (int i = 0; i < chi; ++i) {
+            const double v = sc[i] * inv;
+            spectra[(long)c * chi + i] = v;
+            const double dv = v - prev[(long)c * chi + i];
+            d2 += dv * dv;
+            prev[(long)c * chi + i] = v;
+        }
+        dl = sqrt(d2);
+    }
+    dmax[c] = dl;
+    __syncthreads();
+    if (c == 0) {
+        double m = 0;
+        for (int i = 0; i < nspec; ++i) m = fmax(m, dmax[i]);
+        *delta_out = first ? INFINITY : m;
+    }
+}
+
+void spectra_delta(hipStream_t s, int nspec, int chi, const double* sig, double* spectra,
+                   double* prev, double* delta_out, int first) {
+    hipLaunchKernelGGL(k_spectra_delta, dim3(1), dim3(64), 0, s, nspec, chi, sig, spectra, prev,
+                       delta_out, first);
+    HIP_CHECK(hipGetLastError());
+}
+
+__global__ void k_random_block(int n, int k, uint64_t seed, double* X) {
+    const long tot = (long)n * k;
+    const int b = blockIdx.y;
+    for (long e = blockIdx.x * blockDim.x + threadIdx.x; e < tot; e += (long)gridDim.x * blockDim.x)
+        X[b * tot + e] = 2.0 * hash_uniform(seed, (uint64_t)(b * tot + e)) - 1.0;
+}
+
+void random_block(hipStream_t s, int batch, int n, int k, uint64_t seed, double* X) {
+    const long tot = (long)n * k;
+    hipLaunchKernelGGL(k_random_block, dim3(ceil_div(tot, 256) < 1024 ? ceil_div(tot, 256) : 1024, batch),
+                       dim3(256), 0, s, n, k, seed, X);
+    HIP_CHECK(hipGetLastError());
+}
+
+// ------------------------------------------------------------ readout
+__global__ __launch_bounds__(1024) void k_readout(int D, int d, int dA, const double* __restrict__ E,
+                                                  const cplx* __restrict__ A, cplx* rho, double* obs) {
+    __shared__ double red[16];
+    __shared__ double nsite[4], offd[4];
+    const int q = D * D;
+    const long q4 = (long)q * q * q * q, D4 = (long)D * D * D * D;
+    for (int site = 0; site < 4; ++site) {
+        const double* Es = E + site * q4;
+        const cplx* As = A + site * d * D4;
+        // rho[s][s'] = sum_x A[s][x] sum_x' E_c(x, x') conj(A[s'][x'])
+        cplx racc[64];
+        for (int i = 0; i < d * d; ++i) racc[i] = cmake(0, 0);
+        for (long x = threadIdx.x; x < D4; x += blockDim.x) {
+            const int r = x % D, dd = (x / D) % D, l = (x / (D * D)) % D, u = x / (D * D * D);
+            cplx t[8];
+            for (int sp = 0; sp < d; ++sp) t[sp] = cmake(0, 0);
+            for (long xp = 0; xp < D4; ++xp) {
+                const int rp = xp % D, dp = (xp / D) % D, lp = (xp / (D * D)) % D, up = xp / (D * D * D);
+                const InvTerms tl = inv_terms(l, lp, D, false), tu = inv_terms(u, up, D, false);
+                const InvTerms tr = inv_terms(r, rp, D, true), td = inv_terms(dd, dp, D, true);
+                cplx ec = cmake(0, 0);
+                for (int a = 0; a < tl.n; ++a)
+                    for (int b = 0; b < tu.n; ++b)
+                        for (int c = 0; c < tr.n; ++c)
+                            for (int e = 0; e < td.n; ++e) {
+                                const double ev =
+                                    Es[(((long)tl.m[a] * q + tu.m[b]) * q + tr.m[c]) * q + td.m[e]];
+                                ec = cadd(ec, cscale(cmul(cmul(tl.c[a], tu.c[b]), cmul(tr.c[c], td.c[e])), ev));
+                            }
+                for (int sp = 0; sp < d; ++sp) t[sp] = cadd(t[sp], cmul(ec, cconj(As[sp * D4 + xp])));
+            }
+            for (int s = 0; s < d; ++s) {
+                const cplx av = As[s * D4 + x];
+                for (int sp = 0; sp < d; ++sp) racc[s * d + sp] = cadd(racc[s * d + sp], cmul(av, t[sp]));
+            }
+        }
+        __shared__ cplx rs[64];
+        for (int i = 0; i < d * d; ++i) {
+            const double re = block_sum(racc[i].re, red);
+            const double im = block_sum(racc[i].im, red);
+            if (threadIdx.x == 0) rs[i] = cmake(re, im);
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            cplx tr = cmake(0, 0);
+            for (int i = 0; i < d; ++i) tr = cadd(tr, rs[i * d + i]);
+            const double tn = cabs2(tr);
+            const cplx inv = cmake(tr.re / tn, -tr.im / tn);
+            for (int i = 0; i < d * d; ++i) rho[site * d * d + i] = cmul(rs[i], inv);
+            // physical 2x2 block after tracing the auxiliary level
+            cplx p00 = cmake(0, 0), p01 = cmake(0, 0);
+            for (int a = 0; a < dA; ++a) {
+                p00 = cadd(p00, cmul(rs[(0 * dA + a) * d + (0 * dA + a)], inv));
+                p01 = cadd(p01, cmul(rs[(0 * dA + a) * d + (1 * dA + a)], inv));
+            }
+            nsite[site] = p00.re;
+            offd[site] = sqrt(cabs2(p01));
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        double sum = 0, mo = 0;
+        for (int i = 0; i < 4; ++i) {
+            obs[i] = nsite[i];
+            sum += nsite[i];
+            mo = fmax(mo, offd[i]);
+        }
+        obs[4] = 0.5 * (nsite[0] + nsite[3] - nsite[1] - nsite[2]);
+        obs[5] = sum;
+        obs[6] = mo;
+    }
+}
+
+void readout(hipStream_t s, int D, int d, int d_A, const double* E, const cplx* A, cplx* rho,
+             double* obs) {
+    IPEPS_REQUIRE(d <= 8, IPEPS_EINVAL, "readout supports d <= 8");
+    hipLaunchKernelGGL(k_readout, dim3(1), dim3(1024), 0, s, D, d, d_A, E, A, rho, obs);
+    HIP_CHECK(hipGetLastError());
+}
+
+}  // namespace ipeps

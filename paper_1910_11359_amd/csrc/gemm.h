@@ -1,0 +1,47 @@
+// Grouped MFMA GEMM: C = alpha * A B + beta * C for a list of problems of
+// one dtype, all tiles of all problems in one launch.
+#pragma once
+
+#include "common.h"
+
+namespace ipeps {
+
+// Element (i, k) of A lives at A[(i / a_rows0) * a_rs1 + (i % a_rows0) * a_rs0 + k * a_ks]
+// (a two-level row index lets a tensor with two free legs on either side of
+// the contracted ones be read in place); B(k, j) at B[k * b_ks + j * b_cs];
+// C(i, j) at C[(i / c_rows0) * c_rs1 + (i % c_rows0) * c_rs0
+//            + (j / c_cols0) * c_cs1 + (j % c_cols0) * c_cs0].
+// beta == 0 never reads C.
+struct GemmProb {
+    const void* A;
+    const void* B;
+    void* C;
+    int M, N, K;
+    int a_rows0;
+    long a_rs1, a_rs0, a_ks;
+    long b_ks, b_cs;
+    int c_rows0, c_cols0;
+    long c_rs1, c_rs0, c_cs1, c_cs0;
+    double alpha, beta;
+    int tiles_n;     // filled by gemm_plan_tiles
+    int tile_begin;  // first tile of this problem within its launch
+};
+
+// Plain row-major helpers: op(X) = X (lda = row stride) or X^T.
+GemmProb gemm_nn(const void* A, long lda, const void* B, long ldb, void* C, long ldc, int M,
+                 int N, int K, double alpha = 1.0, double beta = 0.0);
+GemmProb gemm_general(const void* A, bool transA, long lda, const void* B, bool transB,
+                      long ldb, void* C, long ldc, int M, int N, int K, double alpha = 1.0,
+                      double beta = 0.0);
+
+enum GemmTile { TILE_LARGE = 0, TILE_SMALL = 1 };
+
+// Chooses the tile shape for a group and fills tiles_n / tile_begin;
+// returns the total number of tiles (the grid size).
+int gemm_plan_tiles(GemmProb* probs, int n, int dtype, GemmTile* tile);
+
+// Launch on `stream`; d_probs is a device copy of the planned descriptors.
+void gemm_launch(hipStream_t stream, int dtype, GemmTile tile, const GemmProb* d_probs,
+                 int nprob, int total_tiles);
+
+}  // namespace ipeps

@@ -1,0 +1,264 @@
+// Grouped MFMA GEMM for gfx950 (CDNA4), FP64 and FP32.
+//
+// One workgroup computes a BM x BN tile of one problem; 4 waves in a 2x2
+// arrangement each own a (BM/2) x (BN/2) block made of 16x16 MFMA blocks
+// (v_mfma_f64_16x16x4f64 / v_mfma_f32_16x16x4f32).  Operand tiles go
+// global -> registers -> LDS (k-major, one element of padding per row so the
+// MFMA operand reads of 16 consecutive rows/columns hit distinct banks); the
+// next tile's global loads are issued before the current tile's MFMAs.
+//
+// MFMA lane layouts (checked on the device): operand A element (i, k) is held
+// by lane i + 16 k, operand B element (k, j) by lane j + 16 k; the FP32
+// result register r of lane l is row 4 (l / 16) + r, column l % 16; the FP64
+// result register r of lane l is row l / 16 + 4 r, column l % 16.
+#include "gemm.h"
+
+namespace ipeps {
+
+typedef double d4_t __attribute__((ext_vector_type(4)));
+typedef float f4_t __attribute__((ext_vector_type(4)));
+
+template <typename T>
+struct Mfma;
+template <>
+struct Mfma<double> {
+    typedef d4_t acc_t;
+    static __device__ inline acc_t step(double a, double b, acc_t c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    static __device__ inline int row(int lane, int r) { return (lane >> 4) + 4 * r; }
+};
+template <>
+struct Mfma<float> {
+    typedef f4_t acc_t;
+    static __device__ inline acc_t step(float a, float b, acc_t c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    static __device__ inline int row(int lane, int r) { return 4 * (lane >> 4) + r; }
+};
+
+template <typename T, int BM, int BN, int BK>
+__global__ __launch_bounds__(256) void k_gemm_grouped(const GemmProb* __restrict__ probs,
+                                                      int nprob) {
+    constexpr int NT = 256;
+    constexpr int WM = BM / 2, WN = BN / 2;
+    constexpr int FM = WM / 16, FN = WN / 16;
+    constexpr int LA = BM * BK / NT;  // A elements per thread per tile
+    constexpr int LB = BN * BK / NT;
+    constexpr int PA = BM + 1, PB = BN + 1;
+    __shared__ T As[BK * PA];
+    __shared__ T Bs[BK * PB];
+
+    // ---- which problem / tile
+    int bid = blockIdx.x;
+    int p = 0;
+    while (p + 1 < nprob && probs[p + 1].tile_begin <= bid) ++p;
+    const GemmProb& P = probs[p];
+    const int t = bid - P.tile_begin;
+    const int tm = t / P.tiles_n, tn = t - (t / P.tiles_n) * P.tiles_n;
+    const int M = P.M, N = P.N, K = P.K;
+    const int m0 = tm * BM, n0 = tn * BN;
+    const T* __restrict__ A = (const T*)P.A;
+    const T* __restrict__ B = (const T*)P.B;
+
+    const int tid = threadIdx.x;
+    const bool a_kcontig = (P.a_ks == 1);
+    const bool b_ncontig = (P.b_cs == 1);
+
+    // per-thread element coordinates inside the tile (fixed across k tiles)
+    int a_mi[LA], a_ki[LA];
+    long a_row[LA];
+#pragma unroll
+    for (int r = 0; r < LA; ++r) {
+        int e = tid + r * NT;
+        if (a_kcontig) {
+            a_ki[r] = e % BK;
+            a_mi[r] = e / BK;
+        } else {
+            a_mi[r] = e % BM;
+            a_ki[r] = e / BM;
+        }
+        int i = m0 + a_mi[r];
+        a_row[r] = (i < M) ? (long)(i / P.a_rows0) * P.a_rs1 + (long)(i % P.a_rows0) * P.a_rs0
+                           : -1;
+    }
+    int b_ni[LB], b_ki[LB];
+#pragma unroll
+    for (int r = 0; r < LB; ++r) {
+        int e = tid + r * NT;
+        if (b_ncontig) {
+            b_ni[r] = e % BN;
+            b_ki[r] = e / BN;
+        } else {
+            b_ki[r] = e % BK;
+            b_ni[r] = e / BK;
+        }
+    }
+
+    T ra[LA], rb[LB];
+    auto load = [&](int k0) {
+#pragma unroll
+        for (int r = 0; r < LA; ++r) {
+            int k = k0 + a_ki[r];
+            ra[r] = (a_row[r] >= 0 && k < K) ? A[a_row[r] + (long)k * P.a_ks] : T(0);
+        }
+#pragma unroll
+        for (int r = 0; r < LB; ++r) {
+            int k = k0 + b_ki[r], j = n0 + b_ni[r];
+            rb[r] = (j < N && k < K) ? B[(long)k * P.b_ks + (long)j * P.b_cs] : T(0);
+        }
+    };
+    auto store = [&]() {
+#pragma unroll
+        for (int r = 0; r < LA; ++r) As[a_ki[r] * PA + a_mi[r]] = ra[r];
+#pragma unroll
+        for (int r = 0; r < LB; ++r) Bs[b_ki[r] * PB + b_ni[r]] = rb[r];
+    };
+
+    const int lane = tid & 63, wave = tid >> 6;
+    const int wm0 = (wave >> 1) * WM, wn0 = (wave & 1) * WN;
+    typedef typename Mfma<T>::acc_t acc_t;
+    acc_t acc[FM][FN];
+#pragma unroll
+    for (int a = 0; a < FM; ++a)
+#pragma unroll
+        for (int b = 0; b < FN; ++b) acc[a][b] = acc_t{0, 0, 0, 0};
+
+    const int nk = (K + BK - 1) / BK;
+    load(0);
+    store();
+    __syncthreads();
+    for (int kt = 0; kt < nk; ++kt) {
+        if (kt + 1 < nk) load((kt + 1) * BK);
+#pragma unroll
+        for (int kk = 0; kk < BK; kk += 4) {
+            T fa[FM], fb[FN];
+            const int kr = kk + (lane >> 4);
+#pragma unroll
+            for (int a = 0; a < FM; ++a) fa[a] = As[kr * PA + wm0 + a * 16 + (lane & 15)];
+#pragma unroll
+            for (int b = 0; b < FN; ++b) fb[b] = Bs[kr * PB + wn0 + b * 16 + (lane & 15)];
+#pragma unroll
+            for (int a = 0; a < FM; ++a)
+#pragma unroll
+                for (int b = 0; b < FN; ++b) acc[a][b] = Mfma<T>::step(fa[a], fb[b], acc[a][b]);
+        }
+        __syncthreads();
+        if (kt + 1 < nk) {
+            store();
+            __syncthreads();
+        }
+    }
+
+    // ---- epilogue
+    T* __restrict__ C = (T*)P.C;
+    const T alpha = (T)P.alpha, beta = (T)P.beta;
+#pragma unroll
+    for (int b = 0; b < FN; ++b) {
+        const int j = n0 + wn0 + b * 16 + (lane & 15);
+        if (j >= N) continue;
+        const long cj = (long)(j / P.c_cols0) * P.c_cs1 + (long)(j % P.c_cols0) * P.c_cs0;
+#pragma unroll
+        for (int a = 0; a < FM; ++a) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = m0 + wm0 + a * 16 + Mfma<T>::row(lane, r);
+                if (i >= M) continue;
+                const long off =
+                    (long)(i / P.c_rows0) * P.c_rs1 + (long)(i % P.c_rows0) * P.c_rs0 + cj;
+                T v = alpha * acc[a][b][r];
+                if (beta != T(0)) v += beta * C[off];
+                C[off] = v;
+            }
+        }
+    }
+}
+
+GemmProb gemm_general(const void* A, bool transA, long lda, const void* B, bool transB,
+                      long ldb, void* C, long ldc, int M, int N, int K, double alpha,
+                      double beta) {
+    GemmProb p{};
+    p.A = A;
+    p.B = B;
+    p.C = C;
+    p.M = M;
+    p.N = N;
+    p.K = K;
+    p.a_rows0 = M > 0 ? M : 1;
+    p.a_rs1 = 0;
+    p.a_rs0 = transA ? 1 : lda;
+    p.a_ks = transA ? lda : 1;
+    p.b_ks = transB ? 1 : ldb;
+    p.b_cs = transB ? ldb : 1;
+    p.c_rows0 = M > 0 ? M : 1;
+    p.c_cols0 = N > 0 ? N : 1;
+    p.c_rs1 = 0;
+    p.c_rs0 = ldc;
+    p.c_cs1 = 0;
+    p.c_cs0 = 1;
+    p.alpha = alpha;
+    p.beta = beta;
+    return p;
+}
+
+GemmProb gemm_nn(const void* A, long lda, const void* B, long ldb, void* C, long ldc, int M,
+                 int N, int K, double alpha, double beta) {
+    return gemm_general(A, false, lda, B, false, ldb, C, ldc, M, N, K, alpha, beta);
+}
+
+static void tile_dims(int dtype, GemmTile tile, int* bm, int* bn) {
+    (void)dtype;
+    if (tile == TILE_LARGE) {
+        *bm = 128;
+        *bn = 128;
+    } else {
+        *bm = 64;
+        *bn = 64;
+    }
+}
+
+int gemm_plan_tiles(GemmProb* probs, int n, int dtype, GemmTile* tile) {
+    // large tiles when every problem fills at least ~half of one
+    long small_work = 0, all_work = 0;
+    for (int i = 0; i < n; ++i) {
+        long w = (long)probs[i].M * probs[i].N;
+        all_work += w;
+        if (probs[i].M < 96 || probs[i].N < 96) small_work += w;
+    }
+    *tile = (small_work * 4 > all_work) ? TILE_SMALL : TILE_LARGE;
+    int bm, bn;
+    tile_dims(dtype, *tile, &bm, &bn);
+    int total = 0;
+    for (int i = 0; i < n; ++i) {
+        int tm = ceil_div(probs[i].M, bm), tnn = ceil_div(probs[i].N, bn);
+        if (probs[i].M <= 0 || probs[i].N <= 0) tm = tnn = 0;
+        probs[i].tiles_n = tnn > 0 ? tnn : 1;
+        probs[i].tile_begin = total;
+        total += tm * tnn;
+    }
+    return total;
+}
+
+void gemm_launch(hipStream_t stream, int dtype, GemmTile tile, const GemmProb* d_probs,
+                 int nprob, int total_tiles) {
+    if (total_tiles <= 0) return;
+    dim3 grid(total_tiles), block(256);
+    if (dtype == IPEPS_DTYPE_FP64) {
+        if (tile == TILE_LARGE)
+            hipLaunchKernelGGL((k_gemm_grouped<double, 128, 128, 16>), grid, block, 0, stream,
+                               d_probs, nprob);
+        else
+            hipLaunchKernelGGL((k_gemm_grouped<double, 64, 64, 16>), grid, block, 0, stream,
+                               d_probs, nprob);
+    } else {
+        if (tile == TILE_LARGE)
+            hipLaunchKernelGGL((k_gemm_grouped<float, 128, 128, 32>), grid, block, 0, stream,
+                               d_probs, nprob);
+        else
+            hipLaunchKernelGGL((k_gemm_grouped<float, 64, 64, 32>), grid, block, 0, stream,
+                               d_probs, nprob);
+    }
+    HIP_CHECK(hipGetLastError());
+}
+
+}  // namespace ipeps

@@ -1,0 +1,29 @@
+// Small dense FP64 linear algebra on the device: one workgroup per matrix.
+#pragma once
+
+#include "common.h"
+
+namespace ipeps {
+
+// Batched one-sided (Hestenes) Jacobi SVD of real m x n matrices, m >= n.
+// Matrix b is read from A + b*strideA with element (i, j) at [i*lda + j]
+// (row-major).  Outputs, sorted by descending singular value:
+//   sigma[b*n + j], U (m x n, row-major ld n, b*m*n) with unit columns (zero
+//   for zero singular values), V (n x n row-major, b*n*n) with A = U S V^T.
+// U and V may be NULL.  Works in LDS when 2*m*n... fits, else in `work`
+// (device scratch of at least batch * (m*n + n*n) doubles).
+void jacobi_svd_real(hipStream_t s, int batch, int m, int n, const double* A, long lda,
+                     long strideA, double* sigma, double* U, double* V, double* work);
+size_t jacobi_svd_real_work(int batch, int m, int n);
+
+// Batched Cholesky of k x k SPD Gram matrices G (row-major, stride k*k) with
+// dependency dropping, followed by the inverse of the factor: on exit
+// Rinv[b] holds R^{-1} (upper triangular, G = R^T R) with the rows/columns of
+// dropped pivots (pivot <= tol * G_ii) set to zero.
+void chol_inverse(hipStream_t s, int batch, int k, const double* G, double* Rinv, double tol);
+
+// Scale the columns of batched n x k row-major matrices (stride n*k) to unit
+// 2-norm; zero columns stay zero.
+void normalize_columns(hipStream_t s, int batch, int n, int k, double* X);
+
+}  // namespace ipeps

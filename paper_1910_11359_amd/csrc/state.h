@@ -1,0 +1,131 @@
+// Internal state of one iPEPS job and its device-side execution plan.
+#pragma once
+
+#include <vector>
+
+#include "common.h"
+#include "gemm.h"
+#include "su.h"
+#include "ctm.h"
+
+namespace ipeps {
+
+// Device allocations of one state, through the caller's hooks or hipMalloc.
+// In dry mode nothing is allocated and only the byte count is summed (the
+// footprint used for admission is exactly what a real state allocates).
+struct DevMem {
+    ipeps_alloc_fn alloc = nullptr;
+    ipeps_free_fn free_fn = nullptr;
+    void* ctx = nullptr;
+    hipStream_t stream = nullptr;
+    bool dry = false;
+    size_t total = 0;
+    std::vector<void*> ptrs;
+    void* get(size_t bytes);
+    void release();
+};
+
+// A group of GEMM problems launched together (a slice of the plan table).
+struct GemmGroup {
+    int first = 0, count = 0, dtype = 0, tiles = 0;
+    GemmTile tile = TILE_LARGE;
+};
+
+struct ColumnStep {
+    GemmGroup s1, s2, s3, half, nprod, proj, w1, w2, fin;
+    // buffers the step touches
+    int site_x[2], site_x1[2];  // physical site of frame (X, Y) and (X+1, Y)
+    int slot;                    // warm-subspace slot (frame * 2 + X)
+    long norm_first;             // index of the 6 NormItems in the table
+};
+
+struct SvdPlan {
+    // orth passes on Y and Z and the Rayleigh-Ritz products, batch 2 (FP64)
+    GemmGroup NV, NtQ, gramY, gramZ, gramQ, gramQz, QfromY, QfromZ, YfromQ, ZfromQz, Cs, Uo,
+        Vo, NVfinal;
+};
+
+}  // namespace ipeps
+
+struct ipeps_state {
+    ipeps_config cfg;
+    int D, d, q, chi, n, k, dtype;
+    size_t esz;
+    hipStream_t stream;
+    ipeps::DevMem mem;
+
+    // simple update
+    ipeps::cplx* gam;
+    double* lam;
+    double* eps;
+    ipeps::cplx* gates;
+    void* su_scratch;
+    ipeps::LayerDesc layers[7];
+
+    // double layers
+    ipeps::cplx* A;
+    double* a_base;
+    void* a_lu[16];
+    void* a_dl[16];
+    void** d_a_lu;
+    void** d_a_dl;
+
+    // environment: C[(site*4 + k)], T[(site*4 + k)] contiguous
+    void* Cenv;
+    void* Tenv;
+
+    // column-step workspace
+    void* X1;   // 8 blocks of chi * q * chi
+    void* X2;   // 8 blocks of n^2
+    void* X2p;  // 8 blocks of n^2
+    void* E;    // 8 blocks of n^2
+    void* Fh;   // 2 blocks of n^2
+    void* Gh;   // 2 blocks of n^2
+    void* Nd;   // 2 blocks of n^2 (dtype; aliases N64 in FP64 mode)
+    double* N64;
+    void* Z;    // 2 blocks of chi*q*chi
+    void* Us;   // 2 blocks of n*chi
+    void* Vs;
+    void* Plow;
+    void* Pup;
+    void* PlowP;
+    void* PupP;
+    void* W1;   // 2 blocks of n^2
+    void* W1p;
+    void* W2;
+    int* g_dev;
+
+    // projector SVD (FP64)
+    double* warm;  // 16 slots of n*k
+    bool warm_valid[16];
+    double *Yw, *Zw, *Qw, *Qz, *Gm, *Ri, *Cs, *Uc, *Vc, *sig, *Uo, *Vo, *jwork;
+    double *Nfull_U, *Nfull_V;  // direct path (n <= 96)
+
+    // spectra / readout
+    double* C64;
+    double* csig;
+    double* spectra;
+    double* spec_prev;
+    double* dev_scalars;  // [0] delta
+    void* Eout;           // 4 blocks of q^4 (dtype)
+    double* E64;
+    ipeps::cplx* rho;
+    double* obs_dev;
+    double* host_buf;  // pinned
+
+    // plan
+    std::vector<ipeps::GemmProb> probs;
+    ipeps::GemmProb* d_probs;
+    std::vector<ipeps::NormItem> norms;
+    ipeps::NormItem* d_norms;
+    ipeps::ColumnStep steps[8];  // frame f (in move order) * 2 + X
+    ipeps::SvdPlan svd;
+    ipeps::GemmGroup read1, read2, read3, read4;
+
+    long step_count;
+    bool have_env;
+    bool spectra_valid;
+    bool poisoned;
+    int last_iters;
+    double last_delta;
+};

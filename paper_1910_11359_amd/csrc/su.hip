@@ -1,0 +1,524 @@
+// Simple update on the device (FP64, complex): Trotter gates and bond updates.
+//
+// A bond update of sites i -- j (bond weights lambda_b):
+//   M_X[(outer legs), (s, bond)] = Gamma_X * outer lambdas          (D^3 x dD)
+//   M_X = Q_X R_X                         Householder QR, R_X is r x dD
+//   Theta'[(k_i, s_i'), (s_j', k_j)] = sum_b lambda_b sum_{s_i s_j}
+//        G[(s_i' s_j'), (s_i s_j)] R_i[k_i, (s_i, b)] R_j[k_j, (s_j, b)]
+//   Theta' = U S V^H                      one-sided (Hestenes) Jacobi, FP64
+//   keep g <= D values (zeros <= 1e-12 s_1 dropped, multiplets kept whole)
+//   Gamma_i' = Q_i U_g / outer lambdas,  Gamma_j' = Q_j conj(V_g) / outer lambdas
+//   lambda_b' = s_g / |s_g|,  eps += sum_{k >= g} s_k^2 / sum_k s_k^2 on i and j
+//   Gamma' /= max |Gamma'|
+// The reduced matrix has the same singular values and truncated state (up to
+// gauge) as the full (d D^3) x (d D^3) two-site matrix.  One workgroup per
+// bond; the two bonds of a layer touch disjoint sites and run together.
+#include "su.h"
+
+#include <cmath>
+
+namespace ipeps {
+
+// ------------------------------------------------------------------ gates
+struct GateParams {
+    int d_A;
+    double J[4], V[4], w[4];
+    double W, dt;
+};
+
+__global__ void k_build_gates(GateParams gp, cplx* gates) {
+    extern __shared__ double sm[];
+    const int layer = blockIdx.x >> 1, which = blockIdx.x & 1;
+    const int dA = gp.d_A, d = 2 * dA, dd = d * d;
+    double* h = sm;
+    double* V = sm + dd * dd;
+    if (threadIdx.x != 0) return;
+    const double Jl = gp.J[layer], Vl = gp.V[layer], wW = gp.w[layer] * gp.W;
+    for (int r = 0; r < dd; ++r) {
+        const int si = r / d, sj = r % d;
+        const int pi = si / dA, ai = si % dA, pj = sj / dA, aj = sj % dA;
+        for (int c = 0; c < dd; ++c) {
+            const int ti = c / d, tj = c % d;
+            const int qi = ti / dA, bi = ti % dA, qj = tj / dA, bj = tj % dA;
+            double v = 0.0;
+            if (ai == bi && aj == bj) {
+                if (pi == qi && pj == qj) {
+                    const double szi = pi == 0 ? 0.5 : -0.5, szj = pj == 0 ? 0.5 : -0.5;
+                    const double zi = dA > 1 ? 1.0 - 2.0 * ai / (dA - 1) : 0.0;
+                    const double zj = dA > 1 ? 1.0 - 2.0 * aj / (dA - 1) : 0.0;
+                    v = Vl * szi * szj + wW * (szi * zi + szj * zj);
+                } else if (pi == qj && pj == qi && pi != pj) {
+                    v = 0.5 * Jl;
+                }
+            }
+            h[r * dd + c] = v;
+            V[r * dd + c] = (r == c) ? 1.0 : 0.0;
+        }
+    }
+    // cyclic Jacobi eigen-decomposition h = V diag(h_kk) V^T
+    for (int sweep = 0; sweep < 60; ++sweep) {
+        double off = 0.0, tot = 0.0;
+        for (int p = 0; p < dd; ++p)
+            for (int q = 0; q < dd; ++q) {
+                tot += h[p * dd + q] * h[p * dd + q];
+                if (p != q) off += h[p * dd + q] * h[p * dd + q];
+            }
+        if (off <= 1e-32 * tot || off == 0.0) break;
+        for (int p = 0; p < dd - 1; ++p)
+            for (int q = p + 1; q < dd; ++q) {
+                const double hpq = h[p * dd + q];
+                if (fabs(hpq) < 1e-300) continue;
+                const double th = (h[q * dd + q] - h[p * dd + p]) / (2.0 * hpq);
+                const double t = (th >= 0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+                const double c = 1.0 / sqrt(t * t + 1.0), s = t * c;
+                for (int k = 0; k < dd; ++k) {
+                    const double a = h[k * dd + p], b = h[k * dd + q];
+                    h[k * dd + p] = c * a - s * b;
+                    h[k * dd + q] = s * a + c * b;
+                }
+                for (int k = 0; k < dd; ++k) {
+                    const double a = h[p * dd + k], b = h[q * dd + k];
+                    h[p * dd + k] = c * a - s * b;
+                    h[q * dd + k] = s * a + c * b;
+                }
+                for (int k = 0; k < dd; ++k) {
+                    const double a = V[k * dd + p], b = V[k * dd + q];
+                    V[k * dd + p] = c * a - s * b;
+                    V[k * dd + q] = s * a + c * b;
+                }
+            }
+    }
+    const double tau = which ? gp.dt : 0.5 * gp.dt;
+    cplx* G = gates + (long)blockIdx.x * dd * dd;
+    for (int r = 0; r < dd; ++r)
+        for (int c = 0; c < dd; ++c) {
+            double re = 0, im = 0;
+            for (int k = 0; k < dd; ++k) {
+                const double vv = V[r * dd + k] * V[c * dd + k], ph = tau * h[k * dd + k];
+                re += vv * cos(ph);
+                im -= vv * sin(ph);
+            }
+            G[r * dd + c] = cmake(re, im);
+        }
+}
+
+void build_gates(hipStream_t s, const ipeps_config& cfg, cplx* gates) {
+    GateParams gp;
+    gp.d_A = cfg.d_A;
+    for (int l = 0; l < 4; ++l) {
+        gp.J[l] = cfg.J * cfg.layer_J[l];
+        gp.V[l] = cfg.V * cfg.layer_V[l];
+        gp.w[l] = cfg.layer_w[l];
+    }
+    gp.W = cfg.W;
+    gp.dt = cfg.dt;
+    const int dd = 4 * cfg.d_A * cfg.d_A;
+    IPEPS_REQUIRE(dd <= 64, IPEPS_EINVAL, "gate builder supports d <= 8");
+    hipLaunchKernelGGL(k_build_gates, dim3(8), dim3(64), 2 * dd * dd * sizeof(double), s, gp,
+                       gates);
+    HIP_CHECK(hipGetLastError());
+}
+
+// ------------------------------------------------------------------ bond update
+struct SuDims {
+    int D, d, Dc, nb, r, m;  // Dc = D^3, nb = d D, r = min(Dc, nb), m = d r
+};
+
+__host__ __device__ inline SuDims su_dims(int D, int d) {
+    SuDims s;
+    s.D = D;
+    s.d = d;
+    s.Dc = D * D * D;
+    s.nb = d * D;
+    s.r = s.Dc < s.nb ? s.Dc : s.nb;
+    s.m = d * s.r;
+    return s;
+}
+
+struct SuScratch {
+    cplx *Mi, *Mj, *taui, *tauj, *Th, *Ac, *U, *B, *Xi, *Xj;
+    double* sig;
+};
+
+__host__ __device__ inline size_t su_layout(const SuDims& s, char* base, SuScratch* out) {
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        char* p = base ? base + off : nullptr;
+        off += (bytes + 255) & ~(size_t)255;
+        return p;
+    };
+    const size_t cm = (size_t)s.Dc * s.nb * sizeof(cplx);
+    SuScratch t;
+    t.Mi = (cplx*)take(cm);
+    t.Mj = (cplx*)take(cm);
+    t.taui = (cplx*)take(s.nb * sizeof(cplx));
+    t.tauj = (cplx*)take(s.nb * sizeof(cplx));
+    t.Th = (cplx*)take((size_t)s.m * s.m * sizeof(cplx));
+    t.Ac = (cplx*)take((size_t)s.m * s.m * sizeof(cplx));
+    t.U = (cplx*)take((size_t)s.m * s.D * sizeof(cplx));
+    t.B = (cplx*)take((size_t)s.m * s.D * sizeof(cplx));
+    t.Xi = (cplx*)take(cm);
+    t.Xj = (cplx*)take(cm);
+    t.sig = (double*)take((size_t)s.m * sizeof(double));
+    if (out) *out = t;
+    return off;
+}
+
+size_t su_scratch_bytes(int D, int d) { return 2 * su_layout(su_dims(D, d), nullptr, nullptr); }
+
+// Leg values (u, l, d, r) of a site tensor from the outer-leg row index and
+// the bond index.
+__device__ inline long gam_offset(int D, int bond_leg, int row, int s, int b) {
+    int o[3] = {row / (D * D), (row / D) % D, row % D};
+    int leg[5];
+    int k = 0;
+    for (int p = 1; p <= 4; ++p) leg[p] = (p == bond_leg) ? b : o[k++];
+    const long D2 = (long)D * D;
+    return (long)s * D2 * D2 + (long)leg[1] * D2 * D + (long)leg[2] * D2 + (long)leg[3] * D +
+           leg[4];
+}
+
+// Householder QR of the column-major Dc x nb matrix M in place (LAPACK
+// zgeqr2 conventions: R in the upper triangle, v_j below the diagonal with
+// v_j[j] = 1 implicit, H_j = I - tau_j v_j v_j^H).
+__device__ void householder_qr(int Dc, int nb, int r, cplx* M, cplx* tau, double* red,
+                               cplx* bcast) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    for (int j = 0; j < r; ++j) {
+        cplx* col = M + (long)j * Dc;
+        double s = 0;
+        for (int i = j + 1 + threadIdx.x; i < Dc; i += blockDim.x) s += cabs2(col[i]);
+        s = block_sum(s, red);
+        if (threadIdx.x == 0) {
+            const cplx alpha = col[j];
+            cplx t = cmake(0, 0), scale = cmake(0, 0);
+            if (!(s == 0.0 && alpha.im == 0.0)) {
+                const double nrm = sqrt(cabs2(alpha) + s);
+                const double beta = alpha.re >= 0 ? -nrm : nrm;
+                t = cmake((beta - alpha.re) / beta, -alpha.im / beta);
+                const cplx den = cmake(alpha.re - beta, alpha.im);  // 1 / (alpha - beta)
+                const double dn = cabs2(den);
+                scale = cmake(den.re / dn, -den.im / dn);
+                col[j] = cmake(beta, 0.0);
+            }
+            tau[j] = t;
+            bcast[0] = scale;
+        }
+        __syncthreads();
+        const cplx sc = bcast[0];
+        const cplx tj = tau[j];
+        if (tj.re != 0.0 || tj.im != 0.0)
+            for (int i = j + 1 + threadIdx.x; i < Dc; i += blockDim.x) col[i] = cmul(col[i], sc);
+        __syncthreads();
+        if (tj.re != 0.0 || tj.im != 0.0) {
+            // a_c -= conj(tau) v (v^H a_c) for the trailing columns
+            for (int c = j + 1 + wave; c < nb; c += nw) {
+                cplx* ac = M + (long)c * Dc;
+                cplx w = cmake(0, 0);
+                for (int i = j + lane; i < Dc; i += 64) {
+                    const cplx v = (i == j) ? cmake(1, 0) : col[i];
+                    w = cadd(w, cdotc(v, ac[i]));
+                }
+                w.re = wave_sum(w.re);
+                w.im = wave_sum(w.im);
+                const cplx f = cmul(cconj(tj), w);
+                for (int i = j + lane; i < Dc; i += 64) {
+                    const cplx v = (i == j) ? cmake(1, 0) : col[i];
+                    ac[i] = csub(ac[i], cmul(f, v));
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// X (Dc x ncols, column-major) <- Q X with Q = H_0 H_1 ... H_{r-1}.
+__device__ void householder_apply_q(int Dc, int r, int ncols, const cplx* M, const cplx* tau,
+                                    cplx* X) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    for (int j = r - 1; j >= 0; --j) {
+        const cplx tj = tau[j];
+        if (tj.re == 0.0 && tj.im == 0.0) continue;
+        const cplx* v = M + (long)j * Dc;
+        for (int c = wave; c < ncols; c += nw) {
+            cplx* xc = X + (long)c * Dc;
+            cplx w = cmake(0, 0);
+            for (int i = j + lane; i < Dc; i += 64) {
+                const cplx vi = (i == j) ? cmake(1, 0) : v[i];
+                w = cadd(w, cdotc(vi, xc[i]));
+            }
+            w.re = wave_sum(w.re);
+            w.im = wave_sum(w.im);
+            const cplx f = cmul(tj, w);
+            for (int i = j + lane; i < Dc; i += 64) {
+                const cplx vi = (i == j) ? cmake(1, 0) : v[i];
+                xc[i] = csub(xc[i], cmul(f, vi));
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// One-sided complex Jacobi on the columns of the m x n column-major A.
+__device__ void complex_jacobi(int m, int n, cplx* A, int* flag) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int ne = n + (n & 1), npair = ne / 2;
+    const double tol = fmax(1e-15, sqrt((double)m) * 2.3e-16);
+    for (int sweep = 0; sweep < 40; ++sweep) {
+        if (threadIdx.x == 0) *flag = 0;
+        __syncthreads();
+        for (int rr = 0; rr < ne - 1; ++rr) {
+            for (int k = wave; k < npair; k += nw) {
+                int p, q;
+                if (k == 0) {
+                    p = rr;
+                    q = ne - 1;
+                } else {
+                    p = (rr + k) % (ne - 1);
+                    q = (rr - k + ne - 1) % (ne - 1);
+                }
+                if (p > q) {
+                    int t = p;
+                    p = q;
+                    q = t;
+                }
+                if (q >= n) continue;
+                cplx* ap = A + (long)p * m;
+                cplx* aq = A + (long)q * m;
+                double al = 0, be = 0, gr = 0, gi = 0;
+                for (int i = lane; i < m; i += 64) {
+                    const cplx x = ap[i], y = aq[i];
+                    al += cabs2(x);
+                    be += cabs2(y);
+                    const cplx g = cdotc(x, y);
+                    gr += g.re;
+                    gi += g.im;
+                }
+                al = wave_sum(al);
+                be = wave_sum(be);
+                gr = wave_sum(gr);
+                gi = wave_sum(gi);
+                const double ga = sqrt(gr * gr + gi * gi);
+                if (al == 0.0 || be == 0.0) continue;
+                if (ga <= tol * sqrt(al) * sqrt(be)) continue;
+                // phase e^{-i phi} on column q makes a_p^H a_q real positive
+                const cplx ph = cmake(gr / ga, -gi / ga);
+                const double zeta = (be - al) / (2.0 * ga);
+                const double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+                const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
+                for (int i = lane; i < m; i += 64) {
+                    const cplx x = ap[i];
+                    const cplx y = cmul(ph, aq[i]);
+                    ap[i] = csub(cscale(x, c), cscale(y, s));
+                    aq[i] = cadd(cscale(x, s), cscale(y, c));
+                }
+                if (lane == 0) *flag = 1;
+            }
+            __syncthreads();
+        }
+        const int any = *flag;
+        __syncthreads();
+        if (!any) break;
+    }
+}
+
+template <bool THETA_LDS>
+__global__ __launch_bounds__(1024) void k_su_bond(SuDims dm, LayerDesc L, cplx* gam,
+                                                  double* lam, double* eps, const cplx* gates,
+                                                  char* scratch, size_t scratch_per_bond) {
+    extern __shared__ char smem_raw[];
+    __shared__ double red[16];
+    __shared__ cplx bcast[2];
+    __shared__ int flag;
+    __shared__ int g_s;
+    __shared__ double lam_inv_i[3][8], lam_inv_j[3][8], lam_i[3][8], lam_j[3][8];
+    __shared__ double sig_sorted[256];
+    __shared__ int col_of_rank[256];
+
+    const BondDesc bd = L.bond[blockIdx.x];
+    const int D = dm.D, d = dm.d, Dc = dm.Dc, nb = dm.nb, r = dm.r, m = dm.m;
+    SuScratch S;
+    su_layout(dm, scratch + blockIdx.x * scratch_per_bond, &S);
+    cplx* Ac = THETA_LDS ? (cplx*)smem_raw : S.Ac;
+    const cplx* G = gates + (long)L.gate * d * d * d * d;
+    const long site_sz = (long)d * D * D * D * D;
+    cplx* gi = gam + bd.site_i * site_sz;
+    cplx* gj = gam + bd.site_j * site_sz;
+
+    // ---- outer lambdas and their pseudo-inverses (cutoff 1e-14 relative)
+    if (threadIdx.x < 6) {
+        const int side = threadIdx.x / 3, k = threadIdx.x % 3;
+        const double* lv = lam + (long)(side ? bd.outer_j[k] : bd.outer_i[k]) * D;
+        double mx = 0;
+        for (int a = 0; a < D; ++a) mx = fmax(mx, lv[a]);
+        for (int a = 0; a < D; ++a) {
+            const double v = lv[a];
+            (side ? lam_j : lam_i)[k][a] = v;
+            (side ? lam_inv_j : lam_inv_i)[k][a] = (v > 1e-14 * mx) ? 1.0 / v : 0.0;
+        }
+    }
+    __syncthreads();
+
+    // ---- M_X = Gamma_X * outer lambdas, column-major (Dc x nb), col = s*D + b
+    for (long e = threadIdx.x; e < (long)Dc * nb; e += blockDim.x) {
+        const int col = (int)(e / Dc), row = (int)(e % Dc);
+        const int s = col / D, b = col % D;
+        const int o0 = row / (D * D), o1 = (row / D) % D, o2 = row % D;
+        const double wi = lam_i[0][o0] * lam_i[1][o1] * lam_i[2][o2];
+        const double wj = lam_j[0][o0] * lam_j[1][o1] * lam_j[2][o2];
+        S.Mi[e] = cscale(gi[gam_offset(D, bd.leg_i, row, s, b)], wi);
+        S.Mj[e] = cscale(gj[gam_offset(D, bd.leg_j, row, s, b)], wj);
+    }
+    __syncthreads();
+    householder_qr(Dc, nb, r, S.Mi, S.taui, red, bcast);
+    householder_qr(Dc, nb, r, S.Mj, S.tauj, red, bcast);
+
+    // ---- Theta' (m x m, column-major), rows (k_i, s_i'), cols (s_j', k_j)
+    const double* lb = lam + (long)bd.lam_b * D;
+    for (long e = threadIdx.x; e < (long)m * m; e += blockDim.x) {
+        const int col = (int)(e / m), row = (int)(e % m);
+        const int ki = row / d, sip = row % d, sjp = col / r, kj = col % r;
+        cplx acc = cmake(0, 0);
+        for (int b = 0; b < D; ++b) {
+            const double lv = lb[b];
+            if (lv == 0.0) continue;
+            for (int si = 0; si < d; ++si) {
+                const int ci = si * D + b;
+                if (ci < ki) continue;  // R_i is upper triangular
+                const cplx ri = S.Mi[(long)ci * Dc + ki];
+                for (int sj = 0; sj < d; ++sj) {
+                    const int cj = sj * D + b;
+                    if (cj < kj) continue;
+                    const cplx rj = S.Mj[(long)cj * Dc + kj];
+                    const cplx g = G[(sip * d + sjp) * d * d + si * d + sj];
+                    acc = cadd(acc, cscale(cmul(g, cmul(ri, rj)), lv));
+                }
+            }
+        }
+        Ac[e] = acc;
+        S.Th[e] = acc;
+    }
+    __syncthreads();
+    complex_jacobi(m, m, Ac, &flag);
+    __syncthreads();
+
+    // ---- singular values, ranks, truncation
+    for (int c = threadIdx.x; c < m; c += blockDim.x) {
+        double s = 0;
+        for (int i = 0; i < m; ++i) s += cabs2(Ac[(long)c * m + i]);
+        S.sig[c] = sqrt(s);
+    }
+    __syncthreads();
+    for (int c = threadIdx.x; c < m; c += blockDim.x) {
+        const double sc = S.sig[c];
+        int rank = 0;
+        for (int l = 0; l < m; ++l) {
+            const double sl = S.sig[l];
+            rank += (sl > sc) || (sl == sc && l < c);
+        }
+        sig_sorted[rank] = sc;
+        col_of_rank[rank] = c;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double tot = 0;
+        for (int k = 0; k < m; ++k) tot += sig_sorted[k] * sig_sorted[k];
+        int g = 0;
+        if (sig_sorted[0] > 0) {
+            int rk = 0;
+            for (int k = 0; k < m; ++k) rk += sig_sorted[k] > 1e-12 * sig_sorted[0];
+            g = rk < D ? rk : D;
+            if (g < rk)
+                while (g > 1 && sig_sorted[g - 1] - sig_sorted[g] <= 1e-10 * sig_sorted[g - 1]) --g;
+        }
+        double kept = 0;
+        for (int k = 0; k < g; ++k) kept += sig_sorted[k] * sig_sorted[k];
+        const double nk = sqrt(kept);
+        for (int k = 0; k < D; ++k) lam[(long)bd.lam_b * D + k] = (k < g) ? sig_sorted[k] / nk : 0.0;
+        const double e = tot > 0 ? (tot - kept) / tot : 0.0;
+        eps[bd.site_i] += e;
+        eps[bd.site_j] += e;
+        g_s = g;
+    }
+    __syncthreads();
+    const int g = g_s;
+
+    // ---- U_k = column / s_k ; B_k = U_k^H Theta' / s_k  (k < g)
+    for (long e = threadIdx.x; e < (long)m * g; e += blockDim.x) {
+        const int k = (int)(e / m), x = (int)(e % m);
+        S.U[(long)k * m + x] = cscale(Ac[(long)col_of_rank[k] * m + x], 1.0 / sig_sorted[k]);
+    }
+    __syncthreads();
+    for (long e = threadIdx.x; e < (long)m * g; e += blockDim.x) {
+        const int k = (int)(e / m), y = (int)(e % m);
+        cplx acc = cmake(0, 0);
+        for (int x = 0; x < m; ++x) acc = cadd(acc, cdotc(S.U[(long)k * m + x], S.Th[(long)y * m + x]));
+        S.B[(long)k * m + y] = cscale(acc, 1.0 / sig_sorted[k]);
+    }
+    __syncthreads();
+
+    // ---- X_i = [U_g] (r rows used), X_j = [B_g], both Dc x nb, col = s*D + k
+    for (long e = threadIdx.x; e < (long)Dc * nb; e += blockDim.x) {
+        const int col = (int)(e / Dc), row = (int)(e % Dc);
+        const int s = col / D, k = col % D;
+        cplx xi = cmake(0, 0), xj = cmake(0, 0);
+        if (row < r && k < g) {
+            xi = S.U[(long)k * m + row * d + s];
+            xj = S.B[(long)k * m + s * r + row];
+        }
+        S.Xi[e] = xi;
+        S.Xj[e] = xj;
+    }
+    __syncthreads();
+    householder_apply_q(Dc, r, nb, S.Mi, S.taui, S.Xi);
+    householder_apply_q(Dc, r, nb, S.Mj, S.tauj, S.Xj);
+
+    // ---- divide the outer lambdas back out, normalise to max |.| = 1, store
+    for (int side = 0; side < 2; ++side) {
+        cplx* X = side ? S.Xj : S.Xi;
+        double mx = 0;
+        for (long e = threadIdx.x; e < (long)Dc * nb; e += blockDim.x) {
+            const int row = (int)(e % Dc);
+            const int o0 = row / (D * D), o1 = (row / D) % D, o2 = row % D;
+            const double w = side ? lam_inv_j[0][o0] * lam_inv_j[1][o1] * lam_inv_j[2][o2]
+                                  : lam_inv_i[0][o0] * lam_inv_i[1][o1] * lam_inv_i[2][o2];
+            const cplx v = cscale(X[e], w);
+            X[e] = v;
+            mx = fmax(mx, sqrt(cabs2(v)));
+        }
+        mx = block_max(mx, red);
+        const double inv = mx > 0 ? 1.0 / mx : 0.0;
+        cplx* gout = side ? gj : gi;
+        const int leg = side ? bd.leg_j : bd.leg_i;
+        for (long e = threadIdx.x; e < (long)Dc * nb; e += blockDim.x) {
+            const int col = (int)(e / Dc), row = (int)(e % Dc);
+            gout[gam_offset(D, leg, row, col / D, col % D)] = cscale(X[e], inv);
+        }
+        __syncthreads();
+    }
+}
+
+void su_layer(hipStream_t s, int D, int d, const LayerDesc& L, cplx* gam, double* lam,
+              double* eps, const cplx* gates, void* scratch) {
+    const SuDims dm = su_dims(D, d);
+    IPEPS_REQUIRE(dm.m <= 256 && D <= 8, IPEPS_EINVAL, "simple update: d*min(D^3,dD) > 256");
+    const size_t per_bond = su_layout(dm, nullptr, nullptr);
+    const size_t lds = (size_t)dm.m * dm.m * sizeof(cplx);
+    static const size_t kMax = 160 * 1024 - 12 * 1024;
+    if (lds <= kMax) {
+        static bool attr = false;
+        if (!attr) {
+            HIP_CHECK(hipFuncSetAttribute((const void*)k_su_bond<true>,
+                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMax));
+            attr = true;
+        }
+        hipLaunchKernelGGL(k_su_bond<true>, dim3(2), dim3(1024), lds, s, dm, L, gam, lam, eps,
+                           gates, (char*)scratch, per_bond);
+    } else {
+        hipLaunchKernelGGL(k_su_bond<false>, dim3(2), dim3(1024), 0, s, dm, L, gam, lam, eps,
+                           gates, (char*)scratch, per_bond);
+    }
+    HIP_CHECK(hipGetLastError());
+}
+
+}  // namespace ipeps

@@ -1,0 +1,254 @@
+"""ctypes binding of libipeps.so (argument marshalling only).
+
+Every call below forwards to the C ABI declared in include/ipeps.h; no step
+of the method runs in Python.  Loading fails loudly when the gfx950 library
+has not been built (``python -m paper_1910_11359_amd.build``).
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libipeps.so")
+
+IPEPS_OK = 0
+IPEPS_EINVAL = -1
+IPEPS_ENOMEM = -2
+IPEPS_EDEVICE = -3
+IPEPS_ENUMERIC = -4
+IPEPS_ENOTCONV = -5
+IPEPS_EAGAIN = -6
+IPEPS_ENOTFOUND = -7
+DTYPES = {"fp64": 0, "fp32": 1, "bf16": 2}
+JOB_QUEUED, JOB_RUNNING, JOB_DONE = 0, 1, 2
+
+
+class Config(C.Structure):
+    _fields_ = [("D", C.c_int), ("chi", C.c_int), ("d_A", C.c_int),
+                ("J", C.c_double), ("V", C.c_double), ("W", C.c_double), ("dt", C.c_double),
+                ("trotter_order", C.c_int), ("dtype", C.c_int),
+                ("layer_J", C.c_double * 4), ("layer_V", C.c_double * 4),
+                ("layer_w", C.c_double * 4), ("flags", C.c_uint32), ("seed", C.c_uint64)]
+
+
+class Obs(C.Structure):
+    _fields_ = [("t", C.c_double), ("n", C.c_double * 4), ("imbalance", C.c_double),
+                ("sum_n", C.c_double), ("max_offdiag", C.c_double),
+                ("trunc_err", C.c_double * 4), ("ctm_iters", C.c_int), ("ctm_delta", C.c_double)]
+
+    def as_dict(self):
+        return {"t": self.t, "n": np.array(self.n[:]), "imbalance": self.imbalance,
+                "sum_n": self.sum_n, "max_offdiag": self.max_offdiag,
+                "eps": np.array(self.trunc_err[:]), "ctm_iters": self.ctm_iters,
+                "ctm_delta": self.ctm_delta}
+
+
+class Job(C.Structure):
+    _fields_ = [("cfg", Config), ("n_steps", C.c_int), ("observe_every", C.c_int),
+                ("ctm_iters", C.c_int), ("tag", C.c_uint64)]
+
+
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p)
+
+EXPORTS = [
+    "ipeps_config_default", "ipeps_footprint_bytes", "ipeps_init", "ipeps_set_state",
+    "ipeps_get_state", "ipeps_trotter_step", "ctmrg_converge", "ipeps_observe",
+    "ipeps_corner_spectra", "ipeps_bond_spectra", "ipeps_destroy", "solve_server_create",
+    "solve_submit", "solve_poll", "solve_job_times", "solve_server_destroy", "ipeps_strerror",
+]
+
+_lib = None
+
+
+def load():
+    """Load libipeps.so once; raises if it is missing or incomplete."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built: run python -m paper_1910_11359_amd.build")
+    lib = C.CDLL(LIB_PATH)
+    for name in EXPORTS:
+        if not hasattr(lib, name):
+            raise ImportError(f"libipeps.so lacks {name}")
+    P = C.POINTER
+    lib.ipeps_config_default.argtypes = [P(Config)]
+    lib.ipeps_config_default.restype = None
+    lib.ipeps_footprint_bytes.argtypes = [P(Config)]
+    lib.ipeps_footprint_bytes.restype = C.c_size_t
+    lib.ipeps_init.argtypes = [P(Config), C.c_void_p, ALLOC_FN, FREE_FN, C.c_void_p, P(C.c_void_p)]
+    lib.ipeps_set_state.argtypes = [C.c_void_p, P(C.c_double), P(C.c_double)]
+    lib.ipeps_get_state.argtypes = [C.c_void_p, P(C.c_double), P(C.c_double)]
+    lib.ipeps_trotter_step.argtypes = [C.c_void_p, C.c_int, P(C.c_double)]
+    lib.ctmrg_converge.argtypes = [C.c_void_p, C.c_double, C.c_int, C.c_int, P(C.c_int),
+                                   P(C.c_double)]
+    lib.ipeps_observe.argtypes = [C.c_void_p, P(Obs)]
+    lib.ipeps_corner_spectra.argtypes = [C.c_void_p, P(C.c_double)]
+    lib.ipeps_bond_spectra.argtypes = [C.c_void_p, P(C.c_double)]
+    lib.ipeps_destroy.argtypes = [C.c_void_p]
+    lib.ipeps_destroy.restype = None
+    lib.solve_server_create.argtypes = [C.c_size_t, C.c_int, P(C.c_void_p)]
+    lib.solve_submit.argtypes = [C.c_void_p, P(Job), P(C.c_uint64)]
+    lib.solve_poll.argtypes = [C.c_void_p, C.c_uint64, P(C.c_int), P(Obs), C.c_int, P(C.c_int)]
+    lib.solve_job_times.argtypes = [C.c_void_p, C.c_uint64, P(C.c_double), P(C.c_double),
+                                    P(C.c_double)]
+    lib.solve_server_destroy.argtypes = [C.c_void_p]
+    lib.solve_server_destroy.restype = None
+    lib.ipeps_strerror.argtypes = [C.c_int]
+    lib.ipeps_strerror.restype = C.c_char_p
+    _lib = lib
+    return lib
+
+
+class IpepsError(RuntimeError):
+    def __init__(self, code, where):
+        self.code = code
+        msg = load().ipeps_strerror(code).decode()
+        super().__init__(f"{where}: {msg} ({code})")
+
+
+def _check(code, where):
+    if code != IPEPS_OK:
+        raise IpepsError(code, where)
+
+
+def make_config(D, chi, J=1.0, V=1.0, W=5.0, dt=0.05, d_A=2, dtype="fp64", layer_J=None,
+                layer_V=None, layer_w=None, seed=1):
+    lib = load()
+    c = Config()
+    lib.ipeps_config_default(C.byref(c))
+    c.D, c.chi, c.d_A = int(D), int(chi), int(d_A)
+    c.J, c.V, c.W, c.dt = float(J), float(V), float(W), float(dt)
+    c.dtype = DTYPES[dtype] if isinstance(dtype, str) else int(dtype)
+    for name, val in (("layer_J", layer_J), ("layer_V", layer_V), ("layer_w", layer_w)):
+        if val is not None:
+            arr = getattr(c, name)
+            for i in range(4):
+                arr[i] = float(val[i])
+    c.seed = int(seed)
+    return c
+
+
+def footprint_bytes(cfg):
+    return int(load().ipeps_footprint_bytes(C.byref(cfg)))
+
+
+def _dptr(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+class State:
+    """One iPEPS job on the device (wraps ipeps_state*)."""
+
+    def __init__(self, cfg, stream=None):
+        lib = load()
+        self.cfg = cfg
+        self._lib = lib
+        handle = C.c_void_p()
+        sptr = None
+        if stream is not None:  # a torch.cuda.Stream or a raw hipStream_t
+            sptr = getattr(stream, "cuda_stream", stream)
+        _check(lib.ipeps_init(C.byref(cfg), C.c_void_p(sptr), ALLOC_FN(), FREE_FN(), None,
+                              C.byref(handle)), "ipeps_init")
+        self.h = handle
+
+    def close(self):
+        if getattr(self, "h", None):
+            self._lib.ipeps_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_state(self, gamma, lam):
+        g = np.ascontiguousarray(gamma, dtype=np.complex128).view(np.float64)
+        l = np.ascontiguousarray(lam, dtype=np.float64)
+        _check(self._lib.ipeps_set_state(self.h, _dptr(g), _dptr(l)), "ipeps_set_state")
+
+    def get_state(self):
+        D, d = self.cfg.D, 2 * self.cfg.d_A
+        g = np.zeros((4, d, D, D, D, D), dtype=np.complex128)
+        l = np.zeros((8, D))
+        gv = g.view(np.float64)
+        _check(self._lib.ipeps_get_state(self.h, _dptr(gv), _dptr(l)), "ipeps_get_state")
+        return g, l
+
+    def trotter_step(self, n_steps=1, want_eps=False):
+        eps = np.zeros(4)
+        _check(self._lib.ipeps_trotter_step(self.h, int(n_steps), _dptr(eps) if want_eps else None),
+               "ipeps_trotter_step")
+        return eps if want_eps else None
+
+    def ctmrg(self, tol=0.0, max_iter=10, cold=True, allow_notconv=False):
+        it = C.c_int()
+        dl = C.c_double()
+        rc = self._lib.ctmrg_converge(self.h, float(tol), int(max_iter), int(bool(cold)),
+                                      C.byref(it), C.byref(dl))
+        if not (allow_notconv and rc == IPEPS_ENOTCONV):
+            _check(rc, "ctmrg_converge")
+        return it.value, dl.value
+
+    def observe(self):
+        o = Obs()
+        _check(self._lib.ipeps_observe(self.h, C.byref(o)), "ipeps_observe")
+        return o.as_dict()
+
+    def corner_spectra(self):
+        out = np.zeros((16, self.cfg.chi))
+        _check(self._lib.ipeps_corner_spectra(self.h, _dptr(out)), "ipeps_corner_spectra")
+        return out
+
+    def bond_spectra(self):
+        out = np.zeros((8, self.cfg.D))
+        _check(self._lib.ipeps_bond_spectra(self.h, _dptr(out)), "ipeps_bond_spectra")
+        return out
+
+
+class Server:
+    """The request loop (wraps ipeps_server*)."""
+
+    def __init__(self, hbm_budget=0, max_slots=4):
+        self._lib = load()
+        h = C.c_void_p()
+        _check(self._lib.solve_server_create(C.c_size_t(int(hbm_budget)), int(max_slots),
+                                             C.byref(h)), "solve_server_create")
+        self.h = h
+
+    def submit(self, cfg, n_steps, observe_every=10, ctm_iters=10, tag=0):
+        j = Job()
+        j.cfg = cfg
+        j.n_steps, j.observe_every, j.ctm_iters, j.tag = int(n_steps), int(observe_every), int(ctm_iters), int(tag)
+        jid = C.c_uint64()
+        _check(self._lib.solve_submit(self.h, C.byref(j), C.byref(jid)), "solve_submit")
+        return jid.value
+
+    def poll(self, job_id, cap=4096):
+        status = C.c_int()
+        n = C.c_int()
+        buf = (Obs * cap)()
+        rc = self._lib.solve_poll(self.h, C.c_uint64(job_id), C.byref(status), buf, cap, C.byref(n))
+        if rc == IPEPS_EAGAIN:
+            return status.value, None
+        _check(rc, "solve_poll")
+        return status.value, [buf[i].as_dict() for i in range(min(cap, n.value))]
+
+    def times(self, job_id):
+        a, b, c = C.c_double(), C.c_double(), C.c_double()
+        rc = self._lib.solve_job_times(self.h, C.c_uint64(job_id), C.byref(a), C.byref(b), C.byref(c))
+        return rc, (a.value, b.value, c.value)
+
+    def close(self):
+        if getattr(self, "h", None):
+            self._lib.solve_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
