@@ -1,0 +1,159 @@
+"""Throughput of the iPEPS hot path on one MI355X.
+
+One step = one second-order Trotter step (14 simple-update bond updates) +
+one CTMRG iteration (left, right, up and down moves: 64 enlarged corners, 16
+half-system projector pairs, 16 T and 32 C renormalisations, 16 corner
+spectra) continuing from the previous environment + one readout of the four
+site occupations and the imbalance.  Workload: D=6, chi=72, d=4 (binary
+disorder), J=1, V=1, W=8, dt=0.05, synthetic Néel ⊗ |+> start; the state is
+first evolved (untimed) to t = 1 so that every bond carries D singular values.
+
+Prints one JSON line.  The roofline entry is for the dominant kernel (the
+grouped GEMM of the four n^3 half-system products of a column step, n =
+chi D^2): algorithmic flops per launch / mean launch time from HIP events on
+the library's stream during the timed steps.  cpu_baseline is the oracle
+(complex128 NumPy) timed on a bounded sample of the same step and scaled to
+steps/s.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}
+DTYPE_NAME = {"fp64": "f64", "fp32": "f32", "bf16": "bf16"}
+METRIC = "Trotter+CTMRG steps/s at D=6,χ=72 (MFMA % peak); batched jobs/s, p50/p99 latency"
+
+
+def step_flops(D, chi):
+    """Algorithmic real flops of one CTMRG iteration in the real basis."""
+    q = D * D
+    n = chi * q
+    return 2.0 * (64 * (chi ** 3 * q + chi ** 3 * q ** 2 + chi ** 2 * q ** 4)
+                  + 16 * (3 * n ** 3 + 2 * n ** 2 * chi)
+                  + 16 * (chi ** 2 * q ** 4 + 2 * chi ** 3 * q ** 2)
+                  + 32 * 2 * chi ** 3 * q)
+
+
+def cpu_baseline(D, chi, W, V):
+    """Oracle on a bounded sample: 1 bond update, 1 enlarged corner, 1 cut
+    (3 n^3 products + full SVD), scaled to one step (14 bond updates, 64
+    enlarged corners + 16 T renormalisations of the same cost, 16 cuts)."""
+    import numpy as np
+
+    import synthetic
+    from oracle import ctmrg as ct
+    from oracle import peps
+    from oracle.model import Params
+
+    par = Params(D=D, chi=chi, J=1.0, V=V, W=W, dt=0.05)
+    gam, lam = synthetic.random_state(7, D)
+    st = peps.new_state(par)
+    for i, s in enumerate(peps.SITES):
+        st["gam"][s], st["lam_h"][s], st["lam_v"][s] = gam[i], lam[i], lam[4 + i]
+    G = par.layer_gate(0, 0.5 * par.dt)
+    t0 = time.perf_counter()
+    peps.update_horizontal(st, (0, 0), G, D)
+    t_bond = time.perf_counter() - t0
+    a = ct.double_layers(st)
+    rng = np.random.default_rng(0)
+    q = D * D
+    C = rng.normal(size=(chi, chi)).astype(complex)
+    T = rng.normal(size=(chi, q, chi)).astype(complex)
+    t0 = time.perf_counter()
+    E = ct.enlarged_corner(C, T, T, a[(0, 0)])
+    t_corner = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    ct.projectors(E, E, E, E, chi)
+    t_cut = time.perf_counter() - t0
+    t_step = 14 * t_bond + 80 * t_corner + 16 * t_cut
+    cores = os.cpu_count()
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max(int(i.get("num_threads", 0)) for i in threadpool_info()) or cores
+    except Exception:
+        pass
+    return {"value": 1.0 / t_step, "unit": "steps/s", "cores": cores, "kind": "oracle",
+            "sample": (f"D={D} chi={chi}: 1 bond update {t_bond:.2f}s, 1 enlarged corner "
+                       f"{t_corner:.2f}s, 1 cut (3 n^3 products + full SVD) {t_cut:.2f}s; "
+                       f"step = 14 bonds + 80 corner-size contractions + 16 cuts "
+                       f"= {t_step:.1f}s")}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--dtype", default="fp64", choices=["fp64", "fp32"])
+    ap.add_argument("--prelude", type=int, default=20, help="untimed Trotter steps first")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs one GPU only (the path has no multi-GPU mode); got --gpus {args.gpus}",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_1910_11359_amd as P
+    import synthetic
+
+    wl = synthetic.headline_config()
+    D, chi = wl["D"], wl["chi"]
+    torch.cuda.init()
+    stream = torch.cuda.Stream()
+    cfg = P.make_config(D, chi, J=wl["J"], V=wl["V"], W=wl["W"], dt=wl["dt"], dtype=args.dtype)
+    st = P.State(cfg, stream=stream)
+    st.trotter_step(args.prelude)
+    st.ctmrg(0.0, 10, True)
+
+    def one_step():
+        st.trotter_step(1)
+        st.ctmrg(0.0, 1, False)
+        return st.observe()
+
+    for _ in range(args.warmup):
+        one_step()
+    stream.synchronize()
+    torch.cuda.synchronize()
+    st.profile(True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        obs = one_step()
+    stream.synchronize()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms_tot, launches, fl = st.profile_read()
+    st.profile(False)
+    ms_per_step = 1e3 * dt / args.steps
+    value = args.steps / dt
+    achieved = fl / (ms_tot / launches * 1e-3) / 1e12 if launches else 0.0
+    peak = PEAK_TFLOPS[args.dtype]
+    out = {
+        "metric": METRIC, "value": value, "unit": "steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": DTYPE_NAME[args.dtype],
+        "data": "synthetic",
+        "config": {"workload": f"headline iPEPS step: D={D}, chi={chi}, d=4, J=1, V={wl['V']}, "
+                               f"W={wl['W']}, dt={wl['dt']}, after {args.prelude} prelude steps",
+                   "D": D, "chi": chi, "d": 4, "t_end": obs["t"]},
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                     "frac": achieved / peak, "traffic": None,
+                     "kernel": "k_gemm_grouped<...,TAG=1> (4 half-system n^3 products)",
+                     "launch_ms": ms_tot / max(1, launches), "flops_per_launch": fl},
+        "step_mfma_frac": step_flops(D, chi) / (ms_per_step * 1e-3) / (peak * 1e12),
+        "imbalance": obs["imbalance"],
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(D, chi, wl["W"], wl["V"])
+    print(json.dumps(out), flush=True)
+    st.close()
+
+
+if __name__ == "__main__":
+    main()

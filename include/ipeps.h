@@ -216,6 +216,17 @@ int solve_job_times(ipeps_server* srv, uint64_t job_id, double* t_submit, double
 /* Wait for all jobs, stop the loop and release everything. */
 void solve_server_destroy(ipeps_server* srv);
 
+/* ------------------------------------------------------------ instrumentation
+ * Time the launches of the n^3 half-system products (the largest MFMA GEMM
+ * launch of a CTMRG column step, four (chi D^2)^3 products) with HIP events on
+ * the state's stream.  ipeps_profile(st, 1) starts (and clears) recording of
+ * up to 4096 launches; ipeps_profile_read synchronises the stream and returns
+ * the summed launch time in ms, the number of launches and the algorithmic
+ * flops of one launch (2 M N K summed over its products), then clears. */
+int ipeps_profile(ipeps_state* st, int enable);
+int ipeps_profile_read(ipeps_state* st, double* total_ms, int* launches,
+                       double* flops_per_launch);
+
 const char* ipeps_strerror(int code);
 
 #ifdef __cplusplus

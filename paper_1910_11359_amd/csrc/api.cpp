@@ -83,13 +83,23 @@ GemmGroup add_group(ipeps_state* st, std::vector<GemmProb> probs, int dtype) {
     g.count = (int)probs.size();
     g.dtype = dtype;
     g.tiles = gemm_plan_tiles(probs.data(), g.count, dtype, &g.tile);
-    for (auto& p : probs) st->probs.push_back(p);
+    for (auto& p : probs) {
+        g.flops += 2.0 * p.M * (double)p.N * p.K;
+        st->probs.push_back(p);
+    }
     return g;
 }
 
 void run(ipeps_state* st, const GemmGroup& g) {
     if (g.count == 0) return;
-    gemm_launch(st->stream, g.dtype, g.tile, st->d_probs + g.first, g.count, g.tiles);
+    const bool timed = st->prof_on && g.tag == 1 && st->prof_used + 2 <= (int)st->prof_ev.size();
+    if (timed) HIP_CHECK(hipEventRecord(st->prof_ev[st->prof_used], st->stream));
+    gemm_launch(st->stream, g.dtype, g.tile, st->d_probs + g.first, g.count, g.tiles, g.tag);
+    if (timed) {
+        HIP_CHECK(hipEventRecord(st->prof_ev[st->prof_used + 1], st->stream));
+        st->prof_used += 2;
+        st->prof_flops = g.flops;
+    }
 }
 
 char* off(void* base, long elems, size_t esz) { return (char*)base + elems * (long)esz; }
@@ -260,6 +270,7 @@ void build_plan(ipeps_state* st) {
             cs.s2 = add_group(st, s2, dt);
             cs.s3 = add_group(st, s3, dt);
             cs.half = add_group(st, half, dt);
+            cs.half.tag = 1;
             cs.nprod = add_group(st, np, dt);
             cs.proj = add_group(st, pr, dt);
             cs.w1 = add_group(st, w1, dt);
@@ -641,6 +652,7 @@ void ipeps_destroy(ipeps_state* st) {
     if (st->d_probs) (void)hipFree(st->d_probs);
     if (st->d_norms) (void)hipFree(st->d_norms);
     if (st->host_buf) (void)hipHostFree(st->host_buf);
+    for (auto& e : st->prof_ev) (void)hipEventDestroy(e);
     delete st;
 }
 
@@ -783,6 +795,35 @@ int ipeps_bond_spectra(ipeps_state* st, double* out) {
     return wrap(st, [&] {
         HIP_CHECK(hipMemcpyAsync(out, st->lam, 8L * st->D * sizeof(double), hipMemcpyDeviceToHost, st->stream));
         HIP_CHECK(hipStreamSynchronize(st->stream));
+    });
+}
+
+int ipeps_profile(ipeps_state* st, int enable) {
+    if (!st) return IPEPS_EINVAL;
+    return wrap(st, [&] {
+        if (enable && st->prof_ev.empty()) {
+            st->prof_ev.resize(2 * 4096);
+            for (auto& e : st->prof_ev) HIP_CHECK(hipEventCreate(&e));
+        }
+        st->prof_on = enable != 0;
+        st->prof_used = 0;
+    });
+}
+
+int ipeps_profile_read(ipeps_state* st, double* total_ms, int* launches, double* flops_per_launch) {
+    if (!st) return IPEPS_EINVAL;
+    return wrap(st, [&] {
+        HIP_CHECK(hipStreamSynchronize(st->stream));
+        double tot = 0;
+        for (int i = 0; i + 1 < st->prof_used; i += 2) {
+            float ms = 0;
+            HIP_CHECK(hipEventElapsedTime(&ms, st->prof_ev[i], st->prof_ev[i + 1]));
+            tot += ms;
+        }
+        if (total_ms) *total_ms = tot;
+        if (launches) *launches = st->prof_used / 2;
+        if (flops_per_launch) *flops_per_launch = st->prof_flops;
+        st->prof_used = 0;
     });
 }
 

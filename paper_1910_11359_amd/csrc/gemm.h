@@ -41,7 +41,8 @@ enum GemmTile { TILE_LARGE = 0, TILE_SMALL = 1 };
 int gemm_plan_tiles(GemmProb* probs, int n, int dtype, GemmTile* tile);
 
 // Launch on `stream`; d_probs is a device copy of the planned descriptors.
+// tag 1 selects a separate kernel symbol for the cut products (profiling).
 void gemm_launch(hipStream_t stream, int dtype, GemmTile tile, const GemmProb* d_probs,
-                 int nprob, int total_tiles);
+                 int nprob, int total_tiles, int tag = 0);
 
 }  // namespace ipeps

@@ -29,6 +29,8 @@ struct DevMem {
 struct GemmGroup {
     int first = 0, count = 0, dtype = 0, tiles = 0;
     GemmTile tile = TILE_LARGE;
+    int tag = 0;       // 1: the n^3 half-system products (own kernel symbol)
+    double flops = 0;  // algorithmic flops of the whole launch
 };
 
 struct ColumnStep {
@@ -121,6 +123,12 @@ struct ipeps_state {
     ipeps::ColumnStep steps[8];  // frame f (in move order) * 2 + X
     ipeps::SvdPlan svd;
     ipeps::GemmGroup read1, read2, read3, read4;
+
+    // timing of the half-system product launches (HIP events on the stream)
+    bool prof_on;
+    std::vector<hipEvent_t> prof_ev;
+    int prof_used;
+    double prof_flops;
 
     long step_count;
     bool have_env;

@@ -423,6 +423,13 @@ __global__ __launch_bounds__(1024) void k_su_bond(SuDims dm, LayerDesc L, cplx* 
     if (threadIdx.x == 0) {
         double tot = 0;
         for (int k = 0; k < m; ++k) tot += sig_sorted[k] * sig_sorted[k];
+        if (!isfinite(tot)) {
+            // non-finite input: poison the bond weights so the host notices
+            for (int k = 0; k < D; ++k) lam[(long)bd.lam_b * D + k] = NAN;
+            eps[bd.site_i] = NAN;
+            eps[bd.site_j] = NAN;
+            tot = 0.0;
+        }
         int g = 0;
         if (sig_sorted[0] > 0) {
             int rk = 0;
@@ -434,10 +441,12 @@ __global__ __launch_bounds__(1024) void k_su_bond(SuDims dm, LayerDesc L, cplx* 
         double kept = 0;
         for (int k = 0; k < g; ++k) kept += sig_sorted[k] * sig_sorted[k];
         const double nk = sqrt(kept);
-        for (int k = 0; k < D; ++k) lam[(long)bd.lam_b * D + k] = (k < g) ? sig_sorted[k] / nk : 0.0;
-        const double e = tot > 0 ? (tot - kept) / tot : 0.0;
-        eps[bd.site_i] += e;
-        eps[bd.site_j] += e;
+        if (tot > 0) {
+            for (int k = 0; k < D; ++k) lam[(long)bd.lam_b * D + k] = (k < g) ? sig_sorted[k] / nk : 0.0;
+            const double e = (tot - kept) / tot;
+            eps[bd.site_i] += e;
+            eps[bd.site_j] += e;
+        }
         g_s = g;
     }
     __syncthreads();

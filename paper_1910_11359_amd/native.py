@@ -57,6 +57,7 @@ EXPORTS = [
     "ipeps_get_state", "ipeps_trotter_step", "ctmrg_converge", "ipeps_observe",
     "ipeps_corner_spectra", "ipeps_bond_spectra", "ipeps_destroy", "solve_server_create",
     "solve_submit", "solve_poll", "solve_job_times", "solve_server_destroy", "ipeps_strerror",
+    "ipeps_profile", "ipeps_profile_read",
 ]
 
 _lib = None
@@ -96,6 +97,8 @@ def load():
                                     P(C.c_double)]
     lib.solve_server_destroy.argtypes = [C.c_void_p]
     lib.solve_server_destroy.restype = None
+    lib.ipeps_profile.argtypes = [C.c_void_p, C.c_int]
+    lib.ipeps_profile_read.argtypes = [C.c_void_p, P(C.c_double), P(C.c_int), P(C.c_double)]
     lib.ipeps_strerror.argtypes = [C.c_int]
     lib.ipeps_strerror.restype = C.c_char_p
     _lib = lib
@@ -202,6 +205,15 @@ class State:
         out = np.zeros((16, self.cfg.chi))
         _check(self._lib.ipeps_corner_spectra(self.h, _dptr(out)), "ipeps_corner_spectra")
         return out
+
+    def profile(self, enable=True):
+        _check(self._lib.ipeps_profile(self.h, int(bool(enable))), "ipeps_profile")
+
+    def profile_read(self):
+        ms, n, fl = C.c_double(), C.c_int(), C.c_double()
+        _check(self._lib.ipeps_profile_read(self.h, C.byref(ms), C.byref(n), C.byref(fl)),
+               "ipeps_profile_read")
+        return ms.value, n.value, fl.value
 
     def bond_spectra(self):
         out = np.zeros((8, self.cfg.D))

@@ -1,0 +1,75 @@
+"""Host-side checks of the C ABI (no GPU needed, no device compute).
+
+* the gfx950 library loads and exports every function include/ipeps.h
+  declares;
+* the footprint query (pure host arithmetic) is consistent and rejects
+  invalid configurations;
+* error strings, defaults, and argument validation without a device.
+"""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_1910_11359_amd as P
+from paper_1910_11359_amd import native
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if not fn.endswith(".h"):
+            continue
+        text = open(os.path.join(ROOT, "include", fn)).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        text = re.sub(r"typedef[^;]*;", "", text)
+        for m in re.finditer(r"\b([A-Za-z_]\w*)\s*\(", text):
+            name = m.group(1)
+            if name.startswith(("ipeps_", "solve_", "ctmrg_")) and name not in ("ipeps_alloc_fn", "ipeps_free_fn"):
+                names.add(name)
+    return names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = native.load()
+    declared = _declared_functions()
+    assert len(declared) >= 15
+    for name in sorted(declared):
+        assert hasattr(lib, name), name
+    assert set(native.EXPORTS) <= declared
+
+
+def test_config_defaults_and_layout():
+    c = P.make_config(4, 32)
+    assert (c.D, c.chi, c.d_A, c.trotter_order, c.dtype) == (4, 32, 2, 2, 0)
+    assert list(c.layer_w) == [0.25] * 4 and list(c.layer_J) == [1.0] * 4
+    assert ctypes.sizeof(native.Obs) == 8 * 13 + 8  # 13 doubles + an int padded to 8
+
+
+def test_footprint_monotone_and_validation():
+    fp = lambda **kw: P.footprint_bytes(P.make_config(**kw))
+    a = fp(D=4, chi=32)
+    b = fp(D=4, chi=48)
+    c = fp(D=6, chi=72)
+    assert 0 < a < b < c
+    assert fp(D=6, chi=72, dtype="fp32") < c
+    assert fp(D=4, chi=8) == 0          # chi < D^2
+    assert fp(D=9, chi=81) == 0         # D > 8
+    assert fp(D=2, chi=8, dt=-0.1) == 0
+    assert fp(D=2, chi=8, d_A=3) == 0   # only binary disorder in this version
+
+
+def test_strerror():
+    lib = native.load()
+    assert lib.ipeps_strerror(0) == b"ok"
+    assert b"converge" in lib.ipeps_strerror(-5)
+    assert lib.ipeps_strerror(-99) == b"unknown error"
+
+
+def test_init_rejects_bad_config_before_touching_the_device():
+    with pytest.raises(P.IpepsError) as e:
+        P.State(P.make_config(D=3, chi=4))
+    assert e.value.code == native.IPEPS_EINVAL

@@ -1,0 +1,154 @@
+"""Device path vs the oracle, through the C ABI (needs an MI355X).
+
+Tolerances: imbalance and occupations 1e-6 absolute (the target stated for
+the FP64 path), bond spectra and truncation errors 1e-10, corner spectra:
+2-norms of near-degenerate clusters to max(1e-8, 10 x the oracle's own
+rounding floor) and single entries to 1e-6 (tests/_parity.py explains why).
+"""
+import numpy as np
+import pytest
+
+import synthetic
+from oracle import peps as opeps
+from oracle import run as orun
+from tests import _parity as par
+
+P = pytest.importorskip("paper_1910_11359_amd")
+
+pytestmark = pytest.mark.gpu
+
+
+def _gpu_state(D, chi, **kw):
+    return P.State(P.make_config(D, chi, **kw))
+
+
+def test_small_workload_vs_oracle():
+    """D=2, chi=8, W=5, V=1, dt=0.05: 20 steps, 10 cold CTMRG iterations
+    after every step."""
+    cfg = synthetic.small_config()
+    kw = dict(J=cfg["J"], V=cfg["V"], W=cfg["W"], dt=cfg["dt"])
+    st = _gpu_state(cfg["D"], cfg["chi"], **kw)
+    p = par.oracle_params(cfg["D"], cfg["chi"], **kw)
+    ost = opeps.new_state(p)
+    for step in range(1, cfg["n_steps"] + 1):
+        st.trotter_step(1)
+        opeps.trotter_step(ost, p)
+        st.ctmrg(0.0, cfg["ctm_iters"], True)
+        g = st.observe()
+        o, _ = orun.observe_state(ost, p, ctm_iters=cfg["ctm_iters"])
+        assert abs(g["t"] - step * cfg["dt"]) < 1e-12
+        assert abs(g["imbalance"] - o["imbalance"]) < 1e-6, step
+        assert np.max(np.abs(g["n"] - o["n"])) < 1e-6, step
+        assert np.max(np.abs(g["eps"] - o["eps"])) < 1e-10, step
+        assert np.max(np.abs(st.bond_spectra() - o["bond_spectra"])) < 1e-10, step
+        spread = par.oracle_spread(ost, p, cfg["ctm_iters"], o["corner_spectra"])
+        par.assert_spectra(st.corner_spectra(), o["corner_spectra"], spread, step)
+        assert abs(g["sum_n"] - 2.0) < 1e-10 and g["max_offdiag"] < 1e-10
+
+
+@pytest.mark.parametrize("D,chi,seed", [(2, 8, 3), (3, 9, 4), (3, 12, 5), (4, 16, 6)])
+def test_random_state_vs_oracle(D, chi, seed):
+    """Seeded random site tensors and bond weights (full rank at every
+    bond): CTMRG from the state, one Trotter step, CTMRG again.  Covers the
+    direct projector SVD (n <= 96) and the subspace-iteration one."""
+    gam, lam = synthetic.random_state(seed, D)
+    kw = dict(J=1.0, V=1.0, W=3.0, dt=0.05)
+    st = _gpu_state(D, chi, **kw)
+    st.set_state(gam, lam)
+    p = par.oracle_params(D, chi, **kw)
+    ost = par.oracle_state_from(gam, lam, p)
+    for phase in range(2):
+        st.ctmrg(0.0, 4, True)
+        g = st.observe()
+        o, _ = orun.observe_state(ost, p, ctm_iters=4)
+        assert abs(g["imbalance"] - o["imbalance"]) < 1e-6
+        assert np.max(np.abs(g["n"] - o["n"])) < 1e-6
+        spread = par.oracle_spread(ost, p, 4, o["corner_spectra"])
+        par.assert_spectra(st.corner_spectra(), o["corner_spectra"], spread, phase)
+        if phase == 0:
+            eps = st.trotter_step(1, want_eps=True)
+            opeps.trotter_step(ost, p)
+            assert np.max(np.abs(st.bond_spectra() - opeps.bond_spectra(ost))) < 1e-10
+            assert np.max(np.abs(eps - np.array([ost["eps"][s] for s in opeps.SITES]))) < 1e-10
+
+
+def _dimer_exact(t, J, W):
+    w = np.sqrt(J ** 2 + 4 * W ** 2)
+    return 1 - np.sin(J * t / 2) ** 2 - J ** 2 / w ** 2 * np.sin(w * t / 2) ** 2
+
+
+def test_dimer_limit_closed_form():
+    st = _gpu_state(4, 16, J=1.0, V=1.0, W=5.0, dt=0.5, layer_J=(1, 0, 0, 0),
+                    layer_V=(1, 0, 0, 0), layer_w=(1, 0, 0, 0))
+    for steps in (1, 1, 2):
+        st.trotter_step(steps)
+        st.ctmrg(0.0, 2, True)
+        g = st.observe()
+        assert abs(g["imbalance"] - _dimer_exact(g["t"], 1.0, 5.0)) < 1e-10
+
+
+def test_zero_hopping_keeps_neel():
+    st = _gpu_state(3, 9, J=0.0, V=1.0, W=5.0, dt=0.1)
+    st.trotter_step(4)
+    st.ctmrg(0.0, 3, True)
+    g = st.observe()
+    assert abs(g["imbalance"] - 1.0) < 1e-13
+    assert np.max(np.abs(g["n"] - np.array([1.0, 0.0, 0.0, 1.0]))) < 1e-13
+
+
+def test_checkerboard_bitwise():
+    st = _gpu_state(3, 9, J=1.0, V=1.0, W=2.0, dt=0.05)
+    st.trotter_step(5)
+    gam, lam = st.get_state()
+    assert np.array_equal(gam[0], gam[3]) and np.array_equal(gam[1], gam[2])
+    assert np.array_equal(lam[0], lam[3]) and np.array_equal(lam[1], lam[2])
+    assert np.array_equal(lam[4], lam[7]) and np.array_equal(lam[5], lam[6])
+
+
+def test_symmetries_on_device():
+    base = dict(J=1.0, V=1.0, W=3.0, dt=0.05)
+
+    def imb(**kw):
+        st = _gpu_state(2, 8, **kw)
+        st.trotter_step(5)
+        st.ctmrg(0.0, 6, True)
+        return st.observe()["imbalance"]
+
+    ref = imb(**base)
+    for key in ("J", "V", "W"):
+        kw = dict(base)
+        kw[key] = -kw[key]
+        assert abs(imb(**kw) - ref) < 1e-10, key
+
+
+def test_warm_start_continues():
+    st = _gpu_state(2, 8, J=1.0, V=1.0, W=5.0, dt=0.05)
+    st.trotter_step(6)
+    st.ctmrg(0.0, 20, True)
+    a = st.observe()
+    it, dl = st.ctmrg(0.0, 2, False)
+    b = st.observe()
+    assert abs(a["imbalance"] - b["imbalance"]) < 1e-8
+    assert dl < 1e-6
+
+
+def test_nan_state_is_reported_and_poisons():
+    gam, lam = synthetic.random_state(9, 2)
+    gam[0, 0, 0, 0, 0, 0] = np.nan
+    st = _gpu_state(2, 8)
+    st.set_state(gam, lam)
+    with pytest.raises(P.IpepsError) as e:
+        st.trotter_step(1, want_eps=True)
+    assert e.value.code == -4
+    with pytest.raises(P.IpepsError) as e:
+        st.ctmrg(0.0, 1, True)
+    assert e.value.code == -4
+
+
+def test_not_converged_is_flagged():
+    st = _gpu_state(2, 8, J=1.0, V=1.0, W=5.0, dt=0.05)
+    st.trotter_step(3)
+    with pytest.raises(P.IpepsError) as e:
+        st.ctmrg(1e-30, 2, True)
+    assert e.value.code == -5
+    st.observe()  # environment still usable
