@@ -45,7 +45,7 @@ namespace {
 
 constexpr int kDirectMax = 96;  // projector SVD by direct Jacobi when n <= this
 constexpr int kColdIters = 8;   // subspace iterations for a fresh random block
-constexpr int kWarmIters = 3;   // ... when warm-started from the last iteration
+constexpr int kWarmIters = 2;   // ... when warm-started from the last iteration
 constexpr double kCholDrop = 1e-12;
 
 int idx(int x, int y) { return ((x % 2 + 2) % 2) + 2 * ((y % 2 + 2) % 2); }
@@ -85,6 +85,7 @@ GemmGroup add_group(ipeps_state* st, std::vector<GemmProb> probs, int dtype) {
     g.tiles = gemm_plan_tiles(probs.data(), g.count, dtype, &g.tile);
     for (auto& p : probs) {
         g.flops += 2.0 * p.M * (double)p.N * p.K;
+        if (p.ksplit > 1) g.reduce_elems = std::max(g.reduce_elems, (long)p.M * p.N);
         st->probs.push_back(p);
     }
     return g;
@@ -94,7 +95,8 @@ void run(ipeps_state* st, const GemmGroup& g) {
     if (g.count == 0) return;
     const bool timed = st->prof_on && g.tag == 1 && st->prof_used + 2 <= (int)st->prof_ev.size();
     if (timed) HIP_CHECK(hipEventRecord(st->prof_ev[st->prof_used], st->stream));
-    gemm_launch(st->stream, g.dtype, g.tile, st->d_probs + g.first, g.count, g.tiles, g.tag);
+    gemm_launch(st->stream, g.dtype, g.tile, st->d_probs + g.first, g.count, g.tiles, g.tag,
+                g.reduce_elems);
     if (timed) {
         HIP_CHECK(hipEventRecord(st->prof_ev[st->prof_used + 1], st->stream));
         st->prof_used += 2;
@@ -103,6 +105,16 @@ void run(ipeps_state* st, const GemmGroup& g) {
 }
 
 char* off(void* base, long elems, size_t esz) { return (char*)base + elems * (long)esz; }
+
+GemmProb split(GemmProb p, int ks, void* ws) {
+    if (ks > 1) {
+        p.ksplit = ks;
+        p.ws = ws;
+    }
+    return p;
+}
+
+int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
 // ---------------------------------------------------------------- allocation
 void allocate(ipeps_state* st) {
@@ -146,6 +158,12 @@ void allocate(ipeps_state* st) {
     st->W2 = M.get(2 * n2 * e);
     st->g_dev = (int*)M.get(2 * sizeof(int));
     const long nk = (long)n * k;
+    st->ks_gram = clampi(n / 64, 1, 48);
+    st->ks_nv = clampi(n / 512, 1, 8);
+    st->ks_c = clampi(n / 256, 1, 32);
+    st->ws_gram = (double*)M.get(2L * st->ks_gram * k * k * sizeof(double));
+    st->ws_nv = (double*)M.get(2L * st->ks_nv * nk * sizeof(double));
+    st->ws_c = M.get(4L * st->ks_c * chi * chi * e);
     st->warm = (double*)M.get(16 * nk * sizeof(double));
     st->Yw = (double*)M.get(2 * nk * sizeof(double));
     st->Zw = (double*)M.get(2 * nk * sizeof(double));
@@ -170,6 +188,7 @@ void allocate(ipeps_state* st) {
     st->Eout = M.get(4 * q4 * e);
     st->E64 = (double*)M.get(4 * q4 * sizeof(double));
     st->rho = (cplx*)M.get(4 * (long)d * d * sizeof(cplx));
+    st->rho_T = (cplx*)M.get(4 * D4 * d * sizeof(cplx));
     st->obs_dev = (double*)M.get(16 * sizeof(double));
 }
 
@@ -249,13 +268,16 @@ void build_plan(ipeps_state* st) {
             for (int Y = 0; Y < 2; ++Y) {
                 const int Yn = (Y + 1) % 2, Yp = (Y + 1) % 2;  // Y+1 and Y-1 coincide mod 2
                 // C1(X+1, Y+1) = P_up(Y) (chi x n) . X1 of UL at (X, Y+1) (n x chi)
-                fin.push_back(gemm_nn(off(st->Pup, Y * (long)n * chi, e), n,
-                                      off(st->X1, (Yn * 4 + 0) * cqc, e), chi,
-                                      Cp(frame_site(f, X + 1, Y + 1), f % 4), chi, chi, chi, n));
+                const int ksc = st->ks_c;
+                fin.push_back(split(gemm_nn(off(st->Pup, Y * (long)n * chi, e), n,
+                                            off(st->X1, (Yn * 4 + 0) * cqc, e), chi,
+                                            Cp(frame_site(f, X + 1, Y + 1), f % 4), chi, chi, chi, n),
+                                    ksc, off(st->ws_c, (2 * Y + 0) * (long)ksc * chi * chi, e)));
                 // C4(X+1, Y) = Z(Y) (chi x q chi, k = (q3, c4n)) . PlowP(Y)
-                fin.push_back(gemm_nn(off(st->Z, Y * cqc, e), (long)q * chi,
-                                      off(st->PlowP, Y * (long)n * chi, e), chi,
-                                      Cp(frame_site(f, X + 1, Y), (3 + f) % 4), chi, chi, chi, n));
+                fin.push_back(split(gemm_nn(off(st->Z, Y * cqc, e), (long)q * chi,
+                                            off(st->PlowP, Y * (long)n * chi, e), chi,
+                                            Cp(frame_site(f, X + 1, Y), (3 + f) % 4), chi, chi, chi, n),
+                                    ksc, off(st->ws_c, (2 * Y + 1) * (long)ksc * chi * chi, e)));
                 // T4(X+1, Y) = W2(Y) [rows (c', R), k = (t4n, U)] . P_low(Y-1)
                 GemmProb pt = gemm_nn(off(st->W2, Y * n2, e), 0, off(st->Plow, Yp * (long)n * chi, e),
                                       chi, Tp(frame_site(f, X + 1, Y), (3 + f) % 4), chi, chi * q,
@@ -295,17 +317,23 @@ void build_plan(ipeps_state* st) {
             return add_group(st, out, IPEPS_DTYPE_FP64);
         };
         SvdPlan& P = st->svd;
+        const int kg = st->ks_gram, kv = st->ks_nv;
+        double* wg = st->ws_gram;
+        double* wv = st->ws_nv;
         P.NV = batch2([&](int b) {
-            return gemm_nn(st->N64 + b * n2, n, st->Qz + b * nk, k, st->Yw + b * nk, k, n, k, n);
+            return split(gemm_nn(st->N64 + b * n2, n, st->Qz + b * nk, k, st->Yw + b * nk, k, n, k, n),
+                         kv, wv + b * kv * nk);
         });
         P.NtQ = batch2([&](int b) {
-            return gemm_general(st->N64 + b * n2, true, n, st->Yw + b * nk, false, k, st->Zw + b * nk,
-                                k, n, k, n);
+            return split(gemm_general(st->N64 + b * n2, true, n, st->Qw + b * nk, false, k,
+                                      st->Zw + b * nk, k, n, k, n),
+                         kv, wv + b * kv * nk);
         });
         auto gram = [&](double* X) {
             return batch2([&](int b) {
-                return gemm_general(X + b * nk, true, k, X + b * nk, false, k, st->Gm + b * kk, k, k,
-                                    k, n);
+                return split(gemm_general(X + b * nk, true, k, X + b * nk, false, k, st->Gm + b * kk,
+                                          k, k, k, n),
+                             kg, wg + b * kg * kk);
             });
         };
         auto mulR = [&](double* X, double* out) {
@@ -323,11 +351,13 @@ void build_plan(ipeps_state* st) {
         P.ZfromQz = mulR(st->Qz, st->Zw);
         // final: Qw = N V (V in Qz), Cs = Yw^T Qw, Uo = Yw Uc, Vo = Qz Vc
         P.NVfinal = batch2([&](int b) {
-            return gemm_nn(st->N64 + b * n2, n, st->Qz + b * nk, k, st->Qw + b * nk, k, n, k, n);
+            return split(gemm_nn(st->N64 + b * n2, n, st->Qz + b * nk, k, st->Qw + b * nk, k, n, k, n),
+                         kv, wv + b * kv * nk);
         });
         P.Cs = batch2([&](int b) {
-            return gemm_general(st->Yw + b * nk, true, k, st->Qw + b * nk, false, k, st->Cs + b * kk,
-                                k, k, k, n);
+            return split(gemm_general(st->Yw + b * nk, true, k, st->Qw + b * nk, false, k,
+                                      st->Cs + b * kk, k, k, k, n),
+                         kg, wg + b * kg * kk);
         });
         P.Uo = batch2([&](int b) {
             return gemm_nn(st->Yw + b * nk, k, st->Uc + b * kk, k, st->Uo + b * nk, k, n, k, k);
@@ -442,12 +472,15 @@ void prepare_double_layers(ipeps_state* st) {
     frame_layouts(st->stream, st->q, st->dtype, st->a_base, st->d_a_lu, st->d_a_dl);
 }
 
+// Column-normalised Cholesky QR of X (n x k, batch 2): one pass leaves the
+// result in the temporary (via mul1), two passes (CholQR2) back in X.
 void orth(ipeps_state* st, double* X, const GemmGroup& gram1, const GemmGroup& mul1,
-          const GemmGroup& gram2, const GemmGroup& mul2) {
+          const GemmGroup& gram2, const GemmGroup& mul2, bool two_pass = true) {
     normalize_columns(st->stream, 2, st->n, st->k, X);
     run(st, gram1);
     chol_inverse(st->stream, 2, st->k, st->Gm, st->Ri, kCholDrop);
     run(st, mul1);
+    if (!two_pass) return;
     run(st, gram2);
     chol_inverse(st->stream, 2, st->k, st->Gm, st->Ri, kCholDrop);
     run(st, mul2);
@@ -477,11 +510,11 @@ void projector_svd(ipeps_state* st, int slot) {
     }
     const int iters = warm ? kWarmIters : kColdIters;
     for (int it = 0; it < iters; ++it) {
+        // power step with one Cholesky-QR pass per side: only the span matters
         run(st, P.NV);  // Yw = N V
-        orth(st, st->Yw, P.gramY, P.QfromY, P.gramQ, P.YfromQ);
-        run(st, P.NtQ);  // Zw = N^T Q
-        orth(st, st->Zw, P.gramZ, P.QfromZ, P.gramQz, P.ZfromQz);
-        HIP_CHECK(hipMemcpyAsync(st->Qz, st->Zw, 2 * nk * sizeof(double), hipMemcpyDeviceToDevice, s));
+        orth(st, st->Yw, P.gramY, P.QfromY, P.gramQ, P.YfromQ, false);  // -> Qw
+        run(st, P.NtQ);  // Zw = N^T Qw
+        orth(st, st->Zw, P.gramZ, P.QfromZ, P.gramQz, P.ZfromQz, false);  // -> Qz
     }
     // Rayleigh-Ritz on span(N V) x span(V)
     run(st, P.NV);
@@ -763,7 +796,7 @@ int ipeps_observe(ipeps_state* st, ipeps_obs* out) {
         }
         run(st, st->read4);
         to_fp64(s, st->dtype, st->Eout, st->E64, 4 * q4);
-        readout(s, st->D, st->d, st->cfg.d_A, st->E64, st->A, st->rho, st->obs_dev);
+        readout(s, st->D, st->d, st->cfg.d_A, st->E64, st->A, st->rho_T, st->rho, st->obs_dev);
         HIP_CHECK(hipMemcpyAsync(st->host_buf, st->obs_dev, 8 * sizeof(double), hipMemcpyDeviceToHost, s));
         HIP_CHECK(hipMemcpyAsync(st->host_buf + 8, st->eps, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
         HIP_CHECK(hipStreamSynchronize(s));

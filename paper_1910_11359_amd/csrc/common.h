@@ -67,6 +67,38 @@ __device__ inline double wave_max(double v) {
     return v;
 }
 
+// Sum over each aligned group of 16 lanes with DPP moves (quad swaps, half-row
+// and row mirrors); every lane of the group gets the same bits.
+__device__ inline double dpp_move(double v, int ctrl_sel) {
+    int lo = __double2loint(v), hi = __double2hiint(v);
+    switch (ctrl_sel) {
+        case 0:
+            lo = __builtin_amdgcn_mov_dpp(lo, 0xB1, 0xF, 0xF, true);  // quad_perm [1,0,3,2]
+            hi = __builtin_amdgcn_mov_dpp(hi, 0xB1, 0xF, 0xF, true);
+            break;
+        case 1:
+            lo = __builtin_amdgcn_mov_dpp(lo, 0x4E, 0xF, 0xF, true);  // quad_perm [2,3,0,1]
+            hi = __builtin_amdgcn_mov_dpp(hi, 0x4E, 0xF, 0xF, true);
+            break;
+        case 2:
+            lo = __builtin_amdgcn_mov_dpp(lo, 0x141, 0xF, 0xF, true);  // row_half_mirror
+            hi = __builtin_amdgcn_mov_dpp(hi, 0x141, 0xF, 0xF, true);
+            break;
+        default:
+            lo = __builtin_amdgcn_mov_dpp(lo, 0x140, 0xF, 0xF, true);  // row_mirror
+            hi = __builtin_amdgcn_mov_dpp(hi, 0x140, 0xF, 0xF, true);
+            break;
+    }
+    return __hiloint2double(hi, lo);
+}
+__device__ inline double group16_sum(double v) {
+    v += dpp_move(v, 0);
+    v += dpp_move(v, 1);
+    v += dpp_move(v, 2);
+    v += dpp_move(v, 3);
+    return v;
+}
+
 // Block-wide sum of one double per thread; `red` must hold blockDim.x/64
 // doubles of LDS.  All threads receive the result.
 __device__ inline double block_sum(double v, double* red) {

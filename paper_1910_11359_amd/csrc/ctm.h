@@ -67,7 +67,8 @@ void random_block(hipStream_t s, int batch, int n, int k, uint64_t seed, double*
 // One-site reduced density matrices from the site environments E (real
 // basis, [L][U][R][D] each q^4, FP64) and A; writes rho (4 x d x d complex,
 // trace-normalised) and obs[0..9] = n[4], imbalance, sum_n, max_offdiag.
-void readout(hipStream_t s, int D, int d, int d_A, const double* E, const cplx* A, cplx* rho,
-             double* obs);
+// Twork: 4 * D^4 * d complex scratch.
+void readout(hipStream_t s, int D, int d, int d_A, const double* E, const cplx* A, cplx* Twork,
+             cplx* rho, double* obs);
 
 }  // namespace ipeps

@@ -455,46 +455,69 @@ void random_block(hipStream_t s, int batch, int n, int k, uint64_t seed, double*
 }
 
 // ------------------------------------------------------------ readout
-__global__ __launch_bounds__(1024) void k_readout(int D, int d, int dA, const double* __restrict__ E,
-                                                  const cplx* __restrict__ A, cplx* rho, double* obs) {
-    __shared__ double red[16];
-    __shared__ double nsite[4], offd[4];
+// Rows of T = E_c A^H: one wave per (site, x), lanes over x'; E_c(x, x') is
+// rebuilt on the fly from the real-basis E (at most 16 terms).
+__global__ __launch_bounds__(256) void k_readout_rows(int D, int d, const double* __restrict__ E,
+                                                      const cplx* __restrict__ A, cplx* __restrict__ T) {
     const int q = D * D;
     const long q4 = (long)q * q * q * q, D4 = (long)D * D * D * D;
-    for (int site = 0; site < 4; ++site) {
-        const double* Es = E + site * q4;
-        const cplx* As = A + site * d * D4;
-        // rho[s][s'] = sum_x A[s][x] sum_x' E_c(x, x') conj(A[s'][x'])
-        cplx racc[64];
-        for (int i = 0; i < d * d; ++i) racc[i] = cmake(0, 0);
-        for (long x = threadIdx.x; x < D4; x += blockDim.x) {
-            const int r = x % D, dd = (x / D) % D, l = (x / (D * D)) % D, u = x / (D * D * D);
-            cplx t[8];
-            for (int sp = 0; sp < d; ++sp) t[sp] = cmake(0, 0);
-            for (long xp = 0; xp < D4; ++xp) {
-                const int rp = xp % D, dp = (xp / D) % D, lp = (xp / (D * D)) % D, up = xp / (D * D * D);
-                const InvTerms tl = inv_terms(l, lp, D, false), tu = inv_terms(u, up, D, false);
-                const InvTerms tr = inv_terms(r, rp, D, true), td = inv_terms(dd, dp, D, true);
-                cplx ec = cmake(0, 0);
-                for (int a = 0; a < tl.n; ++a)
-                    for (int b = 0; b < tu.n; ++b)
-                        for (int c = 0; c < tr.n; ++c)
-                            for (int e = 0; e < td.n; ++e) {
-                                const double ev =
-                                    Es[(((long)tl.m[a] * q + tu.m[b]) * q + tr.m[c]) * q + td.m[e]];
-                                ec = cadd(ec, cscale(cmul(cmul(tl.c[a], tu.c[b]), cmul(tr.c[c], td.c[e])), ev));
-                            }
-                for (int sp = 0; sp < d; ++sp) t[sp] = cadd(t[sp], cmul(ec, cconj(As[sp * D4 + xp])));
-            }
-            for (int s = 0; s < d; ++s) {
-                const cplx av = As[s * D4 + x];
-                for (int sp = 0; sp < d; ++sp) racc[s * d + sp] = cadd(racc[s * d + sp], cmul(av, t[sp]));
-            }
+    const long row = (long)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (row >= 4 * D4) return;
+    const int site = (int)(row / D4);
+    const long x = row % D4;
+    const double* Es = E + site * q4;
+    const cplx* As = A + site * d * D4;
+    const int r = x % D, dd = (x / D) % D, l = (x / (D * D)) % D, u = x / (D * D * D);
+    double tr[8], ti[8];
+    for (int sp = 0; sp < d; ++sp) tr[sp] = ti[sp] = 0.0;
+    for (long xp = lane; xp < D4; xp += 64) {
+        const int rp = xp % D, dp = (xp / D) % D, lp = (xp / (D * D)) % D, up = xp / (D * D * D);
+        const InvTerms tl = inv_terms(l, lp, D, false), tu = inv_terms(u, up, D, false);
+        const InvTerms tR = inv_terms(r, rp, D, true), tD = inv_terms(dd, dp, D, true);
+        cplx ec = cmake(0, 0);
+        for (int a = 0; a < tl.n; ++a)
+            for (int b = 0; b < tu.n; ++b)
+                for (int c = 0; c < tR.n; ++c)
+                    for (int e = 0; e < tD.n; ++e) {
+                        const double ev = Es[(((long)tl.m[a] * q + tu.m[b]) * q + tR.m[c]) * q + tD.m[e]];
+                        ec = cadd(ec, cscale(cmul(cmul(tl.c[a], tu.c[b]), cmul(tR.c[c], tD.c[e])), ev));
+                    }
+        for (int sp = 0; sp < d; ++sp) {
+            const cplx t = cmul(ec, cconj(As[sp * D4 + xp]));
+            tr[sp] += t.re;
+            ti[sp] += t.im;
         }
-        __shared__ cplx rs[64];
+    }
+    for (int sp = 0; sp < d; ++sp) {
+        tr[sp] = wave_sum(tr[sp]);
+        ti[sp] = wave_sum(ti[sp]);
+    }
+    if (lane == 0)
+        for (int sp = 0; sp < d; ++sp) T[row * d + sp] = cmake(tr[sp], ti[sp]);
+}
+
+// rho[s][s'] = sum_x A[s][x] T[x][s'], trace-normalised; occupations with the
+// auxiliary level traced out, imbalance, their sum, largest |rho_p[up,dn]|.
+__global__ __launch_bounds__(1024) void k_readout_finish(int D, int d, int dA, const cplx* __restrict__ A,
+                                                         const cplx* __restrict__ T, cplx* rho, double* obs) {
+    __shared__ double red[16];
+    __shared__ cplx rs[64];
+    __shared__ double nsite[4], offd[4];
+    const long D4 = (long)D * D * D * D;
+    for (int site = 0; site < 4; ++site) {
+        const cplx* As = A + site * d * D4;
+        const cplx* Ts = T + site * D4 * d;
         for (int i = 0; i < d * d; ++i) {
-            const double re = block_sum(racc[i].re, red);
-            const double im = block_sum(racc[i].im, red);
+            const int s = i / d, sp = i % d;
+            double re = 0, im = 0;
+            for (long x = threadIdx.x; x < D4; x += blockDim.x) {
+                const cplx v = cmul(As[s * D4 + x], Ts[x * d + sp]);
+                re += v.re;
+                im += v.im;
+            }
+            re = block_sum(re, red);
+            im = block_sum(im, red);
             if (threadIdx.x == 0) rs[i] = cmake(re, im);
         }
         __syncthreads();
@@ -504,7 +527,6 @@ __global__ __launch_bounds__(1024) void k_readout(int D, int d, int dA, const do
             const double tn = cabs2(tr);
             const cplx inv = cmake(tr.re / tn, -tr.im / tn);
             for (int i = 0; i < d * d; ++i) rho[site * d * d + i] = cmul(rs[i], inv);
-            // physical 2x2 block after tracing the auxiliary level
             cplx p00 = cmake(0, 0), p01 = cmake(0, 0);
             for (int a = 0; a < dA; ++a) {
                 p00 = cadd(p00, cmul(rs[(0 * dA + a) * d + (0 * dA + a)], inv));
@@ -528,10 +550,12 @@ __global__ __launch_bounds__(1024) void k_readout(int D, int d, int dA, const do
     }
 }
 
-void readout(hipStream_t s, int D, int d, int d_A, const double* E, const cplx* A, cplx* rho,
-             double* obs) {
+void readout(hipStream_t s, int D, int d, int d_A, const double* E, const cplx* A, cplx* Twork,
+             cplx* rho, double* obs) {
     IPEPS_REQUIRE(d <= 8, IPEPS_EINVAL, "readout supports d <= 8");
-    hipLaunchKernelGGL(k_readout, dim3(1), dim3(1024), 0, s, D, d, d_A, E, A, rho, obs);
+    const long rows = 4L * D * D * D * D;
+    hipLaunchKernelGGL(k_readout_rows, dim3(ceil_div(rows, 4)), dim3(256), 0, s, D, d, E, A, Twork);
+    hipLaunchKernelGGL(k_readout_finish, dim3(1), dim3(1024), 0, s, D, d, d_A, A, Twork, rho, obs);
     HIP_CHECK(hipGetLastError());
 }
 

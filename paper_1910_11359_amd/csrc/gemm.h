@@ -23,6 +23,9 @@ struct GemmProb {
     int c_rows0, c_cols0;
     long c_rs1, c_rs0, c_cs1, c_cs0;
     double alpha, beta;
+    int ksplit;      // > 1: K is split over this many workgroups per tile, whose
+    void* ws;        //   partial products go to ws[split][M][N] (row-major, dtype)
+                     //   and are summed in a fixed order by a second kernel
     int tiles_n;     // filled by gemm_plan_tiles
     int tile_begin;  // first tile of this problem within its launch
 };
@@ -42,7 +45,8 @@ int gemm_plan_tiles(GemmProb* probs, int n, int dtype, GemmTile* tile);
 
 // Launch on `stream`; d_probs is a device copy of the planned descriptors.
 // tag 1 selects a separate kernel symbol for the cut products (profiling).
+// reduce_elems > 0 (largest M*N of a split problem) adds the split-K sum.
 void gemm_launch(hipStream_t stream, int dtype, GemmTile tile, const GemmProb* d_probs,
-                 int nprob, int total_tiles, int tag = 0);
+                 int nprob, int total_tiles, int tag = 0, long reduce_elems = 0);
 
 }  // namespace ipeps

@@ -56,9 +56,15 @@ __global__ __launch_bounds__(256) void k_gemm_grouped(const GemmProb* __restrict
     int p = 0;
     while (p + 1 < nprob && probs[p + 1].tile_begin <= bid) ++p;
     const GemmProb& P = probs[p];
-    const int t = bid - P.tile_begin;
+    const int ks = P.ksplit > 1 ? P.ksplit : 1;
+    const int tt = bid - P.tile_begin;
+    const int split = tt % ks, t = tt / ks;
     const int tm = t / P.tiles_n, tn = t - (t / P.tiles_n) * P.tiles_n;
-    const int M = P.M, N = P.N, K = P.K;
+    const int M = P.M, N = P.N;
+    // K range of this split, in whole BK tiles
+    const int kchunk = ((P.K + ks - 1) / ks + BK - 1) / BK * BK;
+    const int kbeg = split * kchunk;
+    const int K = (kbeg + kchunk < P.K) ? kbeg + kchunk : P.K;
     const int m0 = tm * BM, n0 = tn * BN;
     const T* __restrict__ A = (const T*)P.A;
     const T* __restrict__ B = (const T*)P.B;
@@ -126,12 +132,14 @@ __global__ __launch_bounds__(256) void k_gemm_grouped(const GemmProb* __restrict
 #pragma unroll
         for (int b = 0; b < FN; ++b) acc[a][b] = acc_t{0, 0, 0, 0};
 
-    const int nk = (K + BK - 1) / BK;
-    load(0);
-    store();
+    const int nk = K > kbeg ? (K - kbeg + BK - 1) / BK : 0;
+    if (nk > 0) {
+        load(kbeg);
+        store();
+    }
     __syncthreads();
     for (int kt = 0; kt < nk; ++kt) {
-        if (kt + 1 < nk) load((kt + 1) * BK);
+        if (kt + 1 < nk) load(kbeg + (kt + 1) * BK);
 #pragma unroll
         for (int kk = 0; kk < BK; kk += 4) {
             T fa[FM], fb[FN];
@@ -153,8 +161,24 @@ __global__ __launch_bounds__(256) void k_gemm_grouped(const GemmProb* __restrict
     }
 
     // ---- epilogue
-    T* __restrict__ C = (T*)P.C;
     const T alpha = (T)P.alpha, beta = (T)P.beta;
+    if (ks > 1) {
+        T* __restrict__ W = (T*)P.ws + (long)split * M * N;
+#pragma unroll
+        for (int b = 0; b < FN; ++b) {
+            const int j = n0 + wn0 + b * 16 + (lane & 15);
+            if (j >= N) continue;
+#pragma unroll
+            for (int a = 0; a < FM; ++a)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int i = m0 + wm0 + a * 16 + Mfma<T>::row(lane, r);
+                    if (i < M) W[(long)i * N + j] = alpha * acc[a][b][r];
+                }
+        }
+        return;
+    }
+    T* __restrict__ C = (T*)P.C;
 #pragma unroll
     for (int b = 0; b < FN; ++b) {
         const int j = n0 + wn0 + b * 16 + (lane & 15);
@@ -200,6 +224,8 @@ GemmProb gemm_general(const void* A, bool transA, long lda, const void* B, bool 
     p.c_cs0 = 1;
     p.alpha = alpha;
     p.beta = beta;
+    p.ksplit = 1;
+    p.ws = nullptr;
     return p;
 }
 
@@ -220,25 +246,49 @@ static void tile_dims(int dtype, GemmTile tile, int* bm, int* bn) {
 }
 
 int gemm_plan_tiles(GemmProb* probs, int n, int dtype, GemmTile* tile) {
-    // large tiles when every problem fills at least ~half of one
-    long small_work = 0, all_work = 0;
+    // large tiles when the launch still has >= 2 workgroups per CU with them
+    // and few problems are thinner than a large tile
+    long small_work = 0, all_work = 0, large_tiles = 0;
     for (int i = 0; i < n; ++i) {
         long w = (long)probs[i].M * probs[i].N;
         all_work += w;
         if (probs[i].M < 96 || probs[i].N < 96) small_work += w;
+        const int ks = probs[i].ksplit > 1 ? probs[i].ksplit : 1;
+        large_tiles += (long)ceil_div(probs[i].M, 128) * ceil_div(probs[i].N, 128) * ks;
     }
-    *tile = (small_work * 4 > all_work) ? TILE_SMALL : TILE_LARGE;
+    *tile = (small_work * 4 > all_work || large_tiles < 512) ? TILE_SMALL : TILE_LARGE;
     int bm, bn;
     tile_dims(dtype, *tile, &bm, &bn);
     int total = 0;
     for (int i = 0; i < n; ++i) {
         int tm = ceil_div(probs[i].M, bm), tnn = ceil_div(probs[i].N, bn);
         if (probs[i].M <= 0 || probs[i].N <= 0) tm = tnn = 0;
+        if (probs[i].ksplit < 1) probs[i].ksplit = 1;
         probs[i].tiles_n = tnn > 0 ? tnn : 1;
         probs[i].tile_begin = total;
-        total += tm * tnn;
+        total += tm * tnn * probs[i].ksplit;
     }
     return total;
+}
+
+// C = sum over splits (fixed order) + beta C, with C's two-level indexing.
+template <typename T>
+__global__ __launch_bounds__(256) void k_splitk_reduce(const GemmProb* __restrict__ probs) {
+    const GemmProb& P = probs[blockIdx.y];
+    if (P.ksplit <= 1) return;
+    const long MN = (long)P.M * P.N;
+    const T* W = (const T*)P.ws;
+    T* C = (T*)P.C;
+    const T beta = (T)P.beta;
+    for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < MN; e += (long)gridDim.x * blockDim.x) {
+        T v = W[e];
+        for (int sp = 1; sp < P.ksplit; ++sp) v += W[sp * MN + e];
+        const int i = (int)(e / P.N), j = (int)(e % P.N);
+        const long off = (long)(i / P.c_rows0) * P.c_rs1 + (long)(i % P.c_rows0) * P.c_rs0 +
+                         (long)(j / P.c_cols0) * P.c_cs1 + (long)(j % P.c_cols0) * P.c_cs0;
+        if (beta != T(0)) v += beta * C[off];
+        C[off] = v;
+    }
 }
 
 template <int TAG>
@@ -263,13 +313,20 @@ static void launch_tagged(hipStream_t stream, int dtype, GemmTile tile, const Ge
 }
 
 void gemm_launch(hipStream_t stream, int dtype, GemmTile tile, const GemmProb* d_probs,
-                 int nprob, int total_tiles, int tag) {
+                 int nprob, int total_tiles, int tag, long reduce_elems) {
     if (total_tiles <= 0) return;
     dim3 grid(total_tiles);
     if (tag == 1)
         launch_tagged<1>(stream, dtype, tile, d_probs, nprob, grid);
     else
         launch_tagged<0>(stream, dtype, tile, d_probs, nprob, grid);
+    if (reduce_elems > 0) {
+        const int gx = ceil_div(reduce_elems, 256) < 1024 ? ceil_div(reduce_elems, 256) : 1024;
+        if (dtype == IPEPS_DTYPE_FP64)
+            hipLaunchKernelGGL(k_splitk_reduce<double>, dim3(gx, nprob), dim3(256), 0, stream, d_probs);
+        else
+            hipLaunchKernelGGL(k_splitk_reduce<float>, dim3(gx, nprob), dim3(256), 0, stream, d_probs);
+    }
     HIP_CHECK(hipGetLastError());
 }
 

@@ -26,37 +26,45 @@ __device__ inline void circle_pair(int r, int k, int ne, int* p, int* q) {
 }
 
 // Ac: m x n column-major working copy of A, Vc: n x n column-major (or NULL).
-__device__ void jacobi_sweeps(int m, int n, double* Ac, double* Vc, int* flag) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+// Each pair of a round is handled by a group of 16 lanes (4 groups per wave);
+// the three inner products are summed with DPP moves inside the group.
+__device__ void jacobi_sweeps(int m, int n, double* Ac, double* Vc, int* flag, double* red) {
+    const int g16 = threadIdx.x & 15, group = threadIdx.x >> 4, ngroups = blockDim.x >> 4;
     const int ne = n + (n & 1);
     const int npair = ne / 2;
-    const double tol = fmax(1e-15, sqrt((double)m) * 2.3e-16);
+    const double tol = 4.0 * m * 1.11e-16;
+    // columns below 1e-14 |A|_F are rounding noise: a rotation against a large
+    // column re-pollutes them at their own size, so they are left alone
+    double fro = 0.0;
+    for (long e = threadIdx.x; e < (long)m * n; e += blockDim.x) fro += Ac[e] * Ac[e];
+    fro = block_sum(fro, red);
+    const double small2 = 1e-28 * fro;
     for (int sweep = 0; sweep < 40; ++sweep) {
         if (threadIdx.x == 0) *flag = 0;
         __syncthreads();
         for (int r = 0; r < ne - 1; ++r) {
-            for (int k = wave; k < npair; k += nw) {
+            for (int k = group; k < npair; k += ngroups) {
                 int p, q;
                 circle_pair(r, k, ne, &p, &q);
                 if (q >= n) continue;
                 double* ap = Ac + (long)p * m;
                 double* aq = Ac + (long)q * m;
                 double al = 0, be = 0, ga = 0;
-                for (int i = lane; i < m; i += 64) {
+                for (int i = g16; i < m; i += 16) {
                     const double x = ap[i], y = aq[i];
                     al += x * x;
                     be += y * y;
                     ga += x * y;
                 }
-                al = wave_sum(al);
-                be = wave_sum(be);
-                ga = wave_sum(ga);
-                if (al == 0.0 || be == 0.0) continue;
+                al = group16_sum(al);
+                be = group16_sum(be);
+                ga = group16_sum(ga);
+                if (al <= small2 || be <= small2) continue;
                 if (fabs(ga) <= tol * sqrt(al) * sqrt(be)) continue;
                 const double zeta = (be - al) / (2.0 * ga);
                 const double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
                 const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
-                for (int i = lane; i < m; i += 64) {
+                for (int i = g16; i < m; i += 16) {
                     const double x = ap[i], y = aq[i];
                     ap[i] = c * x - s * y;
                     aq[i] = s * x + c * y;
@@ -64,13 +72,13 @@ __device__ void jacobi_sweeps(int m, int n, double* Ac, double* Vc, int* flag) {
                 if (Vc) {
                     double* vp = Vc + (long)p * n;
                     double* vq = Vc + (long)q * n;
-                    for (int i = lane; i < n; i += 64) {
+                    for (int i = g16; i < n; i += 16) {
                         const double x = vp[i], y = vq[i];
                         vp[i] = c * x - s * y;
                         vq[i] = s * x + c * y;
                     }
                 }
-                if (lane == 0) *flag = 1;
+                if (g16 == 0) *flag = 1;
             }
             __syncthreads();
         }
@@ -112,6 +120,7 @@ __global__ __launch_bounds__(1024) void k_jacobi_svd(int m, int n, const double*
                                                      double* U, double* V, double* work) {
     extern __shared__ double smem[];
     __shared__ int flag;
+    __shared__ double red[16];
     const int b = blockIdx.x;
     const bool wantV = (V != nullptr);
     const long nv = wantV ? (long)n * n : 0;
@@ -130,7 +139,7 @@ __global__ __launch_bounds__(1024) void k_jacobi_svd(int m, int n, const double*
     }
     for (long e = threadIdx.x; e < nv; e += blockDim.x) Vc[e] = ((e / n) == (e % n)) ? 1.0 : 0.0;
     __syncthreads();
-    jacobi_sweeps(m, n, Ac, wantV ? Vc : nullptr, &flag);
+    jacobi_sweeps(m, n, Ac, wantV ? Vc : nullptr, &flag, red);
     __syncthreads();
     jacobi_finish(m, n, Ac, Vc, sig_s, sigma + (long)b * n, U ? U + (long)b * m * n : nullptr,
                   V ? V + (long)b * n * n : nullptr);
@@ -169,55 +178,75 @@ void jacobi_svd_real(hipStream_t s, int batch, int m, int n, const double* A, lo
 }
 
 // ----------------------------------------------------------------- Cholesky
-// G = R^T R (R upper) with dropping, then Rinv = R^{-1}.  G and Rinv are
-// row-major k x k.  One workgroup of 256 threads per matrix; R lives in LDS
-// (k <= 128), the inverse is written straight to global memory.
-__global__ __launch_bounds__(256) void k_chol_inverse(int k, const double* __restrict__ G,
-                                                      double* __restrict__ Rinv, double tol) {
-    extern __shared__ double R[];  // k*k, row-major, upper part used
-    __shared__ double piv;
-    __shared__ int dead_s[256];
+// G = R^T R (R upper) with dropping, then R^{-1} in place (column-oriented
+// triangular inversion); both in LDS (k <= 128), one wave per matrix so the
+// k sequential steps need no workgroup barriers.  A dropped pivot zeroes its
+// row of R and its row and column of R^{-1}, so the matching column of
+// X R^{-1} is zero.
+__global__ __launch_bounds__(64) void k_chol_inverse(int k, const double* __restrict__ G,
+                                                     double* __restrict__ Rinv, double tol) {
+    extern __shared__ double R[];  // k*k, row-major
+    __shared__ double colj[128];
+    __shared__ int dead_s[128];
+    const int lane = threadIdx.x;
     const int b = blockIdx.x;
     const double* Gb = G + (long)b * k * k;
     double* Xb = Rinv + (long)b * k * k;
-    for (int e = threadIdx.x; e < k * k; e += blockDim.x) R[e] = Gb[e];
+    for (int e = lane; e < k * k; e += 64) R[e] = Gb[e];
     __syncthreads();
     for (int j = 0; j < k; ++j) {
-        if (threadIdx.x == 0) {
-            // diagonal of a column-normalised Gram matrix is ~1; the original
-            // diagonal is not kept, so the threshold is taken relative to 1
-            // when the caller normalised the columns (tol * max(G_jj_orig,...))
-            const double d = R[j * k + j];
-            const int dead = !(d > tol);
+        const double dj = R[j * k + j];
+        const bool dead = !(dj > tol);  // every lane decides alike
+        const double piv = dead ? 0.0 : sqrt(dj);
+        const double ipiv = dead ? 0.0 : 1.0 / piv;
+        __syncthreads();
+        for (int c = j + 1 + lane; c < k; c += 64) R[j * k + c] *= ipiv;
+        if (lane == 0) {
+            R[j * k + j] = piv;
             dead_s[j] = dead;
-            piv = dead ? 0.0 : sqrt(d);
         }
         __syncthreads();
-        const double pj = piv;
-        for (int c = j + threadIdx.x; c < k; c += blockDim.x)
-            R[j * k + c] = (pj > 0.0) ? R[j * k + c] / pj : 0.0;
-        __syncthreads();
-        // trailing update of the upper triangle: R[a][c] -= R[j][a] R[j][c]
-        const int rem = k - j - 1;
-        for (int e = threadIdx.x; e < rem * rem; e += blockDim.x) {
-            const int a = j + 1 + e / rem, c = j + 1 + e % rem;
-            if (c >= a) R[a * k + c] -= R[j * k + a] * R[j * k + c];
+        // trailing update of the upper triangle, one row per lane
+        for (int a = j + 1 + lane; a < k; a += 64) {
+            const double rja = R[j * k + a];
+            double* __restrict__ ra = R + a * k;
+            const double* __restrict__ rj = R + j * k;
+            if (rja != 0.0) {
+#pragma unroll 8
+                for (int c = a; c < k; ++c) ra[c] -= rja * rj[c];
+            }
         }
         __syncthreads();
     }
-    // back substitution, one column of the inverse per thread
-    for (int c = threadIdx.x; c < k; c += blockDim.x) {
-        for (int i = k - 1; i >= 0; --i) {
-            double v;
-            if (i > c || dead_s[i]) {
-                v = 0.0;
-            } else {
-                double s = (i == c) ? 1.0 : 0.0;
-                for (int l = i + 1; l <= c; ++l) s -= R[i * k + l] * Xb[(long)l * k + c];
-                v = s / R[i * k + i];
+    // in-place inverse of the upper-triangular R
+    for (int j = 0; j < k; ++j) {
+        const bool dead = dead_s[j];
+        for (int i = lane; i < j; i += 64) colj[i] = R[i * k + j];
+        __syncthreads();
+        if (dead) {
+            for (int i = lane; i <= j; i += 64) R[i * k + j] = 0.0;
+        } else {
+            const double inv = 1.0 / R[j * k + j];
+            for (int i = lane; i < j; i += 64) {
+                double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+                const double* __restrict__ ri = R + i * k;
+                int l = i;
+                for (; l + 3 < j; l += 4) {
+                    s0 += ri[l] * colj[l];
+                    s1 += ri[l + 1] * colj[l + 1];
+                    s2 += ri[l + 2] * colj[l + 2];
+                    s3 += ri[l + 3] * colj[l + 3];
+                }
+                for (; l < j; ++l) s0 += ri[l] * colj[l];
+                R[i * k + j] = -inv * ((s0 + s1) + (s2 + s3));
             }
-            Xb[(long)i * k + c] = v;
+            if (lane == 0) R[j * k + j] = inv;
         }
+        __syncthreads();
+    }
+    for (int e = lane; e < k * k; e += 64) {
+        const int i = e / k, c = e % k;
+        Xb[e] = (c >= i && !dead_s[i]) ? R[e] : 0.0;
     }
 }
 
@@ -232,7 +261,7 @@ void chol_inverse(hipStream_t s, int batch, int k, const double* G, double* Rinv
                                       128 * 128 * (int)sizeof(double)));
         attr_set = true;
     }
-    hipLaunchKernelGGL(k_chol_inverse, dim3(batch), dim3(256), lds, s, k, G, Rinv, tol);
+    hipLaunchKernelGGL(k_chol_inverse, dim3(batch), dim3(64), lds, s, k, G, Rinv, tol);
     HIP_CHECK(hipGetLastError());
 }
 

@@ -30,6 +30,7 @@ struct GemmGroup {
     int first = 0, count = 0, dtype = 0, tiles = 0;
     GemmTile tile = TILE_LARGE;
     int tag = 0;       // 1: the n^3 half-system products (own kernel symbol)
+    long reduce_elems = 0;  // largest M*N of a split-K problem (0: none)
     double flops = 0;  // algorithmic flops of the whole launch
 };
 
@@ -102,6 +103,9 @@ struct ipeps_state {
     bool warm_valid[16];
     double *Yw, *Zw, *Qw, *Qz, *Gm, *Ri, *Cs, *Uc, *Vc, *sig, *Uo, *Vo, *jwork;
     double *Nfull_U, *Nfull_V;  // direct path (n <= 96)
+    int ks_gram, ks_nv, ks_c;   // split-K factors
+    double *ws_gram, *ws_nv;    // split-K partials (FP64)
+    void* ws_c;                 // split-K partials of the corner renormalisations (dtype)
 
     // spectra / readout
     double* C64;
@@ -112,6 +116,7 @@ struct ipeps_state {
     void* Eout;           // 4 blocks of q^4 (dtype)
     double* E64;
     ipeps::cplx* rho;
+    ipeps::cplx* rho_T;
     double* obs_dev;
     double* host_buf;  // pinned
 

@@ -259,16 +259,22 @@ __device__ void householder_apply_q(int Dc, int r, int ncols, const cplx* M, con
     }
 }
 
-// One-sided complex Jacobi on the columns of the m x n column-major A.
-__device__ void complex_jacobi(int m, int n, cplx* A, int* flag) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+// One-sided complex Jacobi on the columns of the m x n column-major A; one
+// group of 16 lanes per column pair (DPP sums inside the group).
+__device__ void complex_jacobi(int m, int n, cplx* A, int* flag, double* red) {
+    const int g16 = threadIdx.x & 15, group = threadIdx.x >> 4, ngroups = blockDim.x >> 4;
     const int ne = n + (n & 1), npair = ne / 2;
-    const double tol = fmax(1e-15, sqrt((double)m) * 2.3e-16);
+    const double tol = 4.0 * m * 1.11e-16;
+    // columns below 1e-14 |A|_F are rounding noise and are left alone
+    double fro = 0.0;
+    for (long e = threadIdx.x; e < (long)m * n; e += blockDim.x) fro += cabs2(A[e]);
+    fro = block_sum(fro, red);
+    const double small2 = 1e-28 * fro;
     for (int sweep = 0; sweep < 40; ++sweep) {
         if (threadIdx.x == 0) *flag = 0;
         __syncthreads();
         for (int rr = 0; rr < ne - 1; ++rr) {
-            for (int k = wave; k < npair; k += nw) {
+            for (int k = group; k < npair; k += ngroups) {
                 int p, q;
                 if (k == 0) {
                     p = rr;
@@ -286,7 +292,7 @@ __device__ void complex_jacobi(int m, int n, cplx* A, int* flag) {
                 cplx* ap = A + (long)p * m;
                 cplx* aq = A + (long)q * m;
                 double al = 0, be = 0, gr = 0, gi = 0;
-                for (int i = lane; i < m; i += 64) {
+                for (int i = g16; i < m; i += 16) {
                     const cplx x = ap[i], y = aq[i];
                     al += cabs2(x);
                     be += cabs2(y);
@@ -294,25 +300,25 @@ __device__ void complex_jacobi(int m, int n, cplx* A, int* flag) {
                     gr += g.re;
                     gi += g.im;
                 }
-                al = wave_sum(al);
-                be = wave_sum(be);
-                gr = wave_sum(gr);
-                gi = wave_sum(gi);
+                al = group16_sum(al);
+                be = group16_sum(be);
+                gr = group16_sum(gr);
+                gi = group16_sum(gi);
                 const double ga = sqrt(gr * gr + gi * gi);
-                if (al == 0.0 || be == 0.0) continue;
+                if (al <= small2 || be <= small2) continue;
                 if (ga <= tol * sqrt(al) * sqrt(be)) continue;
                 // phase e^{-i phi} on column q makes a_p^H a_q real positive
                 const cplx ph = cmake(gr / ga, -gi / ga);
                 const double zeta = (be - al) / (2.0 * ga);
                 const double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
                 const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
-                for (int i = lane; i < m; i += 64) {
+                for (int i = g16; i < m; i += 16) {
                     const cplx x = ap[i];
                     const cplx y = cmul(ph, aq[i]);
                     ap[i] = csub(cscale(x, c), cscale(y, s));
                     aq[i] = cadd(cscale(x, s), cscale(y, c));
                 }
-                if (lane == 0) *flag = 1;
+                if (g16 == 0) *flag = 1;
             }
             __syncthreads();
         }
@@ -399,7 +405,7 @@ __global__ __launch_bounds__(1024) void k_su_bond(SuDims dm, LayerDesc L, cplx* 
         S.Th[e] = acc;
     }
     __syncthreads();
-    complex_jacobi(m, m, Ac, &flag);
+    complex_jacobi(m, m, Ac, &flag, red);
     __syncthreads();
 
     // ---- singular values, ranks, truncation
