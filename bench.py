@@ -113,8 +113,10 @@ def main():
     st.ctmrg(0.0, 10, True)
 
     def one_step():
+        # CTMRG of the current state and the next Trotter step are enqueued
+        # back to back: the simple update (its own stream) overlaps the CTMRG
+        st.ctmrg(0.0, 1, False, want_delta=False)
         st.trotter_step(1)
-        st.ctmrg(0.0, 1, False)
         return st.observe()
 
     for _ in range(args.warmup):

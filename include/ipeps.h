@@ -124,14 +124,16 @@ int ipeps_set_state(ipeps_state* st, const double* gamma, const double* lambda);
 int ipeps_get_state(ipeps_state* st, double* gamma, double* lambda);
 
 /* Advance n_steps symmetric second-order Trotter steps (Quench: simple
- * update), each the layers H_A/2 H_B/2 V_A/2 V_B V_A/2 H_B/2 H_A/2, two
- * disjoint bonds per layer.  Each bond update: absorb the outer bond weights,
+ * update) on an internal stream of the state, ordered after the last
+ * double-layer build (so it overlaps the rest of a pending CTMRG) and before
+ * the next one.  Each step is the layers H_A/2 H_B/2 V_A/2 V_B V_A/2 H_B/2
+ * H_A/2, two disjoint bonds per layer.  Each bond update: absorb the outer bond weights,
  * reduce both tensors by QR, apply the gate, SVD in FP64, keep at most D
  * values without splitting multiplets (relative gap <= 1e-10) or keeping
  * values <= 1e-12 s_1, normalise the new weights to unit 2-norm, divide the
  * outer weights back out (pseudo-inverse, cutoff 1e-14 relative), scale the
  * site tensors to max |.| = 1.  trunc_err_out (4 doubles, nullable) receives
- * the accumulated truncation error of each site (synchronises the stream;
+ * the accumulated truncation error of each site (waits for the steps;
  * otherwise the call only enqueues work).  Errors: EINVAL, ENUMERIC. */
 int ipeps_trotter_step(ipeps_state* st, int n_steps, double* trunc_err_out);
 
@@ -146,7 +148,9 @@ int ipeps_trotter_step(ipeps_state* st, int n_steps, double* trunc_err_out);
  * change of a normalised corner spectrum is < tol, or after max_iter
  * iterations; tol <= 0 runs exactly max_iter.  *iters and *delta (nullable)
  * receive the count and last change.  Synchronises the stream once per
- * iteration when tol > 0.  Errors: EINVAL, ENUMERIC, ENOTCONV (tol > 0 not
+ * iteration when tol > 0, and once at the end when delta is not NULL;
+ * with tol <= 0 and delta NULL the call only enqueues work (the change is
+ * reported by the next ipeps_observe).  Errors: EINVAL, ENUMERIC, ENOTCONV (tol > 0 not
  * reached; the environment is still usable). */
 int ctmrg_converge(ipeps_state* st, double tol, int max_iter, int cold_start, int* iters,
                    double* delta);

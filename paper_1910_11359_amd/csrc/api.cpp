@@ -126,6 +126,7 @@ void allocate(ipeps_state* st) {
     st->gam = (cplx*)M.get(4 * d * D4 * sizeof(cplx));
     st->lam = (double*)M.get(8 * D * sizeof(double));
     st->eps = (double*)M.get(4 * sizeof(double));
+    st->eps_snap = (double*)M.get(4 * sizeof(double));
     st->gates = (cplx*)M.get(8 * (long)d * d * d * d * sizeof(cplx));
     st->su_scratch = M.get(su_scratch_bytes(D, d));
     st->A = (cplx*)M.get(4 * d * D4 * sizeof(cplx));
@@ -462,15 +463,24 @@ void set_neel(ipeps_state* st) {
     HIP_CHECK(hipMemcpyAsync(st->gam, g.data(), g.size() * sizeof(cplx), hipMemcpyHostToDevice, st->stream));
     HIP_CHECK(hipMemcpyAsync(st->lam, lam.data(), lam.size() * sizeof(double), hipMemcpyHostToDevice, st->stream));
     HIP_CHECK(hipMemsetAsync(st->eps, 0, 4 * sizeof(double), st->stream));
+    HIP_CHECK(hipEventRecord(st->ev_gamma_free, st->stream));
     HIP_CHECK(hipStreamSynchronize(st->stream));
 }
 
 // ---------------------------------------------------------------- CTMRG pieces
 void prepare_double_layers(ipeps_state* st) {
+    HIP_CHECK(hipStreamWaitEvent(st->stream, st->ev_su_done, 0));
     absorb_sqrt_lambda(st->stream, st->D, st->d, st->gam, st->lam, st->A);
+    HIP_CHECK(hipMemcpyAsync(st->eps_snap, st->eps, 4 * sizeof(double), hipMemcpyDeviceToDevice,
+                             st->stream));
+    HIP_CHECK(hipEventRecord(st->ev_gamma_free, st->stream));
     double_layer_real(st->stream, st->D, st->d, st->A, st->a_base);
     frame_layouts(st->stream, st->q, st->dtype, st->a_base, st->d_a_lu, st->d_a_dl);
+    st->ctm_step = st->step_count;
 }
+
+// Order the main stream after all enqueued simple-update work.
+void join_su(ipeps_state* st) { HIP_CHECK(hipStreamWaitEvent(st->stream, st->ev_su_done, 0)); }
 
 // Column-normalised Cholesky QR of X (n x k, batch 2): one pass leaves the
 // result in the temporary (via mul1), two passes (CholQR2) back in X.
@@ -664,6 +674,9 @@ int ipeps_init(const ipeps_config* cfg, void* hip_stream, ipeps_alloc_fn alloc, 
         st->mem.ctx = alloc_ctx;
         st->mem.stream = st->stream;
         allocate(st);
+        HIP_CHECK(hipStreamCreateWithFlags(&st->su_stream, hipStreamNonBlocking));
+        HIP_CHECK(hipEventCreateWithFlags(&st->ev_gamma_free, hipEventDisableTiming));
+        HIP_CHECK(hipEventCreateWithFlags(&st->ev_su_done, hipEventDisableTiming));
         HIP_CHECK(hipHostMalloc((void**)&st->host_buf, 65536 * sizeof(double), hipHostMallocDefault));
         build_layers(st);
         build_plan(st);
@@ -681,7 +694,11 @@ int ipeps_init(const ipeps_config* cfg, void* hip_stream, ipeps_alloc_fn alloc, 
 void ipeps_destroy(ipeps_state* st) {
     if (!st) return;
     (void)hipStreamSynchronize(st->stream);
+    if (st->su_stream) (void)hipStreamSynchronize(st->su_stream);
     st->mem.release();
+    if (st->su_stream) (void)hipStreamDestroy(st->su_stream);
+    if (st->ev_gamma_free) (void)hipEventDestroy(st->ev_gamma_free);
+    if (st->ev_su_done) (void)hipEventDestroy(st->ev_su_done);
     if (st->d_probs) (void)hipFree(st->d_probs);
     if (st->d_norms) (void)hipFree(st->d_norms);
     if (st->host_buf) (void)hipHostFree(st->host_buf);
@@ -695,9 +712,11 @@ int ipeps_set_state(ipeps_state* st, const double* gamma, const double* lambda) 
         const long D4 = (long)st->D * st->D * st->D * st->D;
         for (long i = 0; i < 8L * st->D; ++i)
             IPEPS_REQUIRE(std::isfinite(lambda[i]) && lambda[i] >= 0, IPEPS_EINVAL, "bad lambda");
+        join_su(st);
         HIP_CHECK(hipMemcpyAsync(st->gam, gamma, 4 * st->d * D4 * sizeof(cplx), hipMemcpyHostToDevice, st->stream));
         HIP_CHECK(hipMemcpyAsync(st->lam, lambda, 8 * st->D * sizeof(double), hipMemcpyHostToDevice, st->stream));
         HIP_CHECK(hipMemsetAsync(st->eps, 0, 4 * sizeof(double), st->stream));
+        HIP_CHECK(hipEventRecord(st->ev_gamma_free, st->stream));
         HIP_CHECK(hipStreamSynchronize(st->stream));
         st->have_env = false;
         st->poisoned = false;
@@ -710,6 +729,7 @@ int ipeps_get_state(ipeps_state* st, double* gamma, double* lambda) {
     if (!st) return IPEPS_EINVAL;
     return wrap(st, [&] {
         const long D4 = (long)st->D * st->D * st->D * st->D;
+        join_su(st);
         if (gamma) HIP_CHECK(hipMemcpyAsync(gamma, st->gam, 4 * st->d * D4 * sizeof(cplx), hipMemcpyDeviceToHost, st->stream));
         if (lambda) HIP_CHECK(hipMemcpyAsync(lambda, st->lam, 8 * st->D * sizeof(double), hipMemcpyDeviceToHost, st->stream));
         HIP_CHECK(hipStreamSynchronize(st->stream));
@@ -720,16 +740,19 @@ int ipeps_trotter_step(ipeps_state* st, int n_steps, double* trunc_err_out) {
     if (!st || n_steps < 0) return IPEPS_EINVAL;
     return wrap(st, [&] {
         check_poison(st);
+        hipStream_t ss = st->su_stream;
+        HIP_CHECK(hipStreamWaitEvent(ss, st->ev_gamma_free, 0));
         for (int t = 0; t < n_steps; ++t) {
             for (int l = 0; l < 7; ++l)
-                su_layer(st->stream, st->D, st->d, st->layers[l], st->gam, st->lam, st->eps, st->gates,
+                su_layer(ss, st->D, st->d, st->layers[l], st->gam, st->lam, st->eps, st->gates,
                          st->su_scratch);
             st->step_count++;
         }
+        HIP_CHECK(hipEventRecord(st->ev_su_done, ss));
         if (trunc_err_out) {
-            HIP_CHECK(hipMemcpyAsync(st->host_buf, st->eps, 4 * sizeof(double), hipMemcpyDeviceToHost, st->stream));
-            HIP_CHECK(hipMemcpyAsync(st->host_buf + 4, st->lam, 8 * st->D * sizeof(double), hipMemcpyDeviceToHost, st->stream));
-            HIP_CHECK(hipStreamSynchronize(st->stream));
+            HIP_CHECK(hipMemcpyAsync(st->host_buf, st->eps, 4 * sizeof(double), hipMemcpyDeviceToHost, ss));
+            HIP_CHECK(hipMemcpyAsync(st->host_buf + 4, st->lam, 8 * st->D * sizeof(double), hipMemcpyDeviceToHost, ss));
+            HIP_CHECK(hipStreamSynchronize(ss));
             for (int i = 0; i < 4; ++i) trunc_err_out[i] = st->host_buf[i];
             for (int i = 0; i < 8 * st->D; ++i)
                 IPEPS_REQUIRE(std::isfinite(st->host_buf[4 + i]), IPEPS_ENUMERIC, "NaN in bond weights");
@@ -759,7 +782,7 @@ int ctmrg_converge(ipeps_state* st, double tol, int max_iter, int cold_start, in
             for (int si = 0; si < 8; ++si) column_step(st, si);
             corner_spectra_update(st, false);
             it_done = it + 1;
-            if (tol > 0 || it + 1 == max_iter) {
+            if (tol > 0 || (delta && it + 1 == max_iter)) {
                 HIP_CHECK(hipMemcpyAsync(st->host_buf, st->dev_scalars, sizeof(double), hipMemcpyDeviceToHost, st->stream));
                 HIP_CHECK(hipStreamSynchronize(st->stream));
                 dl = st->host_buf[0];
@@ -798,18 +821,19 @@ int ipeps_observe(ipeps_state* st, ipeps_obs* out) {
         to_fp64(s, st->dtype, st->Eout, st->E64, 4 * q4);
         readout(s, st->D, st->d, st->cfg.d_A, st->E64, st->A, st->rho_T, st->rho, st->obs_dev);
         HIP_CHECK(hipMemcpyAsync(st->host_buf, st->obs_dev, 8 * sizeof(double), hipMemcpyDeviceToHost, s));
-        HIP_CHECK(hipMemcpyAsync(st->host_buf + 8, st->eps, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIP_CHECK(hipMemcpyAsync(st->host_buf + 8, st->eps_snap, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIP_CHECK(hipMemcpyAsync(st->host_buf + 12, st->dev_scalars, sizeof(double), hipMemcpyDeviceToHost, s));
         HIP_CHECK(hipStreamSynchronize(s));
         const double* h = st->host_buf;
         for (int i = 0; i < 7; ++i) IPEPS_REQUIRE(std::isfinite(h[i]), IPEPS_ENUMERIC, "NaN in readout");
-        out->t = st->step_count * st->cfg.dt;
+        out->t = st->ctm_step * st->cfg.dt;
         for (int i = 0; i < 4; ++i) out->n[i] = h[i];
         out->imbalance = h[4];
         out->sum_n = h[5];
         out->max_offdiag = h[6];
         for (int i = 0; i < 4; ++i) out->trunc_err[i] = h[8 + i];
         out->ctm_iters = st->last_iters;
-        out->ctm_delta = st->last_delta;
+        out->ctm_delta = h[12];
     });
 }
 
@@ -826,6 +850,7 @@ int ipeps_corner_spectra(ipeps_state* st, double* out) {
 int ipeps_bond_spectra(ipeps_state* st, double* out) {
     if (!st || !out) return IPEPS_EINVAL;
     return wrap(st, [&] {
+        join_su(st);
         HIP_CHECK(hipMemcpyAsync(out, st->lam, 8L * st->D * sizeof(double), hipMemcpyDeviceToHost, st->stream));
         HIP_CHECK(hipStreamSynchronize(st->stream));
     });

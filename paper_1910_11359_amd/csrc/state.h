@@ -55,6 +55,14 @@ struct ipeps_state {
     int D, d, q, chi, n, k, dtype;
     size_t esz;
     hipStream_t stream;
+    // The simple update runs on its own stream so that the Trotter step t+1
+    // overlaps the CTMRG of step t: su_stream waits for ev_gamma_free (the
+    // double layer of the last CTMRG has read Gamma), the main stream waits
+    // for ev_su_done before it reads Gamma again.
+    hipStream_t su_stream;
+    hipEvent_t ev_gamma_free, ev_su_done;
+    double* eps_snap;  // truncation errors as of the last double-layer build
+    long ctm_step;     // Trotter steps contained in the current environment
     ipeps::DevMem mem;
 
     // simple update

@@ -187,14 +187,14 @@ class State:
                "ipeps_trotter_step")
         return eps if want_eps else None
 
-    def ctmrg(self, tol=0.0, max_iter=10, cold=True, allow_notconv=False):
+    def ctmrg(self, tol=0.0, max_iter=10, cold=True, allow_notconv=False, want_delta=True):
         it = C.c_int()
         dl = C.c_double()
         rc = self._lib.ctmrg_converge(self.h, float(tol), int(max_iter), int(bool(cold)),
-                                      C.byref(it), C.byref(dl))
+                                      C.byref(it), C.byref(dl) if want_delta else None)
         if not (allow_notconv and rc == IPEPS_ENOTCONV):
             _check(rc, "ctmrg_converge")
-        return it.value, dl.value
+        return it.value, (dl.value if want_delta else None)
 
     def observe(self):
         o = Obs()

@@ -1,0 +1,55 @@
+"""Write oracle reference values for the plain FP64 workload (D=4, chi=32).
+
+    python tests/golden/make_plain_golden.py W V [--max-iter N]
+
+Calls only oracle/ (and synthetic/ for the parameters): evolves Néel ⊗ |+>
+with dt=0.05 for 100 steps and, every 10 steps, runs CTMRG from a cold start
+until the corner spectra change by less than 1e-10 in one iteration (capped at
+--max-iter), then records the imbalance, occupations, truncation errors,
+corner spectra and bond spectra to tests/golden/plain_W{W}_V{V}.json.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+
+from oracle import peps, run  # noqa: E402
+from oracle.model import Params  # noqa: E402
+import synthetic  # noqa: E402
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("W", type=float)
+    ap.add_argument("V", type=float)
+    ap.add_argument("--max-iter", type=int, default=200)
+    args = ap.parse_args()
+    cfg = [c for c in synthetic.plain_configs() if c["W"] == args.W and c["V"] == args.V][0]
+    p = Params(D=cfg["D"], chi=cfg["chi"], J=cfg["J"], V=cfg["V"], W=cfg["W"], dt=cfg["dt"])
+    out = {"config": cfg, "max_iter": args.max_iter, "tol": cfg["ctm_tol"], "obs": []}
+    path = os.path.join(ROOT, "tests", "golden", f"plain_W{args.W:g}_V{args.V:g}.json")
+    st = peps.new_state(p)
+    for step in range(0, cfg["n_steps"] + 1):
+        if step > 0:
+            peps.trotter_step(st, p)
+        if step % cfg["observe_every"]:
+            continue
+        t0 = time.time()
+        o, _ = run.observe_state(st, p, tol=cfg["ctm_tol"], max_iter=args.max_iter)
+        out["obs"].append({"step": step, "imbalance": o["imbalance"], "n": o["n"].tolist(),
+                           "eps": o["eps"].tolist(), "ctm_iters": o["ctm_iters"],
+                           "ctm_delta": o["ctm_delta"],
+                           "corner_spectra": o["corner_spectra"].tolist(),
+                           "bond_spectra": o["bond_spectra"].tolist()})
+        print(f"step {step} I={o['imbalance']:.12f} iters={o['ctm_iters']} "
+              f"delta={o['ctm_delta']:.2e} ({time.time() - t0:.0f}s)", flush=True)
+        with open(path, "w") as f:
+            json.dump(out, f)
+
+
+if __name__ == "__main__":
+    main()
