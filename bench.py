@@ -84,6 +84,41 @@ def cpu_baseline(D, chi, W, V):
                        f"= {t_step:.1f}s")}
 
 
+def serving_sample(P, synthetic, dtype, n_req=16, rate=8.0, d_max=4, steps_max=40):
+    """Request loop on a bounded sample of the serving stream: the first n_req
+    requests of default_rng(20191025) (D capped at d_max, steps at steps_max,
+    chi = min(128, c D^2)), submitted at their Poisson arrival times (rate per
+    second) into a 4-slot server; latency = completion - arrival."""
+    reqs = synthetic.serving_stream(n=n_req, rate=rate)
+    srv = P.Server(hbm_budget=0, max_slots=4)
+    t0 = time.perf_counter()
+    ids = []
+    for r in reqs:
+        D = min(r["D"], d_max)
+        chi = min(128, max(D * D, (r["chi"] // (r["D"] ** 2)) * D * D))
+        cfg = P.make_config(D, chi, J=r["J"], V=r["V"], W=r["W"], dt=r["dt"], dtype=dtype)
+        while time.perf_counter() - t0 < r["arrival"]:
+            time.sleep(0.001)
+        ids.append((srv.submit(cfg, n_steps=min(r["n_steps"], steps_max),
+                               observe_every=r["observe_every"], ctm_iters=r["ctm_iters"]),
+                    r["arrival"]))
+    lat, t_last = [], 0.0
+    for jid, arr in ids:
+        while srv.poll(jid)[1] is None:
+            time.sleep(0.002)
+        rc, (ts, ta, td) = srv.times(jid)
+        lat.append(td - ts)
+        t_last = max(t_last, td)
+    t_first = min(srv.times(j)[1][0] for j, _ in ids)
+    srv.close()
+    lat = sorted(lat)
+    pct = lambda q: lat[min(len(lat) - 1, int(q * len(lat)))]
+    return {"jobs_per_s": len(ids) / (t_last - t_first), "p50_s": pct(0.5), "p99_s": pct(0.99),
+            "requests": len(ids), "rate_per_s": rate, "slots": 4, "dtype": dtype,
+            "sample": f"first {n_req} requests of the serving stream, D capped at {d_max}, "
+                      f"steps at {steps_max}, observe every 10 with 10 warm CTMRG iterations"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -92,6 +127,7 @@ def main():
     ap.add_argument("--dtype", default="fp64", choices=["fp64", "fp32"])
     ap.add_argument("--prelude", type=int, default=20, help="untimed Trotter steps first")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs one GPU only (the path has no multi-GPU mode); got --gpus {args.gpus}",
@@ -149,12 +185,13 @@ def main():
                      "kernel": "k_gemm_grouped<...,TAG=1> (4 half-system n^3 products)",
                      "launch_ms": ms_tot / max(1, launches), "flops_per_launch": fl},
         "step_mfma_frac": step_flops(D, chi) / (ms_per_step * 1e-3) / (peak * 1e12),
-        "imbalance": obs["imbalance"],
     }
+    st.close()
+    if not args.no_serving:
+        out["serving"] = serving_sample(P, synthetic, args.dtype)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(D, chi, wl["W"], wl["V"])
     print(json.dumps(out), flush=True)
-    st.close()
 
 
 if __name__ == "__main__":

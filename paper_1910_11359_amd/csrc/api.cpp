@@ -172,6 +172,8 @@ void allocate(ipeps_state* st) {
     st->Qz = (double*)M.get(2 * nk * sizeof(double));
     st->Gm = (double*)M.get(2L * k * k * sizeof(double));
     st->Ri = (double*)M.get(2L * k * k * sizeof(double));
+    st->Rb = (double*)M.get(2 * nk * sizeof(double));
+    st->dead_dev = (int*)M.get((2L * k + 2) * sizeof(int));
     st->Cs = (double*)M.get(2L * k * k * sizeof(double));
     st->Uc = (double*)M.get(2L * k * k * sizeof(double));
     st->Vc = (double*)M.get(2L * k * k * sizeof(double));
@@ -366,7 +368,35 @@ void build_plan(ipeps_state* st) {
         P.Vo = batch2([&](int b) {
             return gemm_nn(st->Qz + b * nk, k, st->Vc + b * kk, k, st->Vo + b * nk, k, n, k, k);
         });
+        // gated on the number of dropped columns of matrix b
+        auto proj1 = [&](double* Q) {
+            return batch2([&](int b) {
+                GemmProb p = split(gemm_general(Q + b * nk, true, k, st->Rb + b * nk, false, k,
+                                                st->Gm + b * kk, k, k, k, n),
+                                   kg, wg + b * kg * kk);
+                p.gate = st->dead_dev + 2 * k + b;
+                return p;
+            });
+        };
+        auto proj2 = [&](double* Q) {
+            return batch2([&](int b) {
+                GemmProb p = gemm_nn(Q + b * nk, k, st->Gm + b * kk, k, st->Rb + b * nk, k, n, k, k,
+                                     -1.0, 1.0);
+                p.gate = st->dead_dev + 2 * k + b;
+                return p;
+            });
+        };
+        P.projQw1 = proj1(st->Qw);
+        P.projQw2 = proj2(st->Qw);
     }
+
+    // Frobenius normalisation of the double layers and of a fresh environment
+    st->norm_a_first = (long)st->norms.size();
+    const long qa = (long)q * q * q * q;
+    for (int i = 0; i < 4; ++i) st->norms.push_back({st->a_base + i * qa, qa});
+    st->norm_env_first = (long)st->norms.size();
+    for (int i = 0; i < 16; ++i) st->norms.push_back({off(st->Cenv, i * cc, e), cc});
+    for (int i = 0; i < 16; ++i) st->norms.push_back({off(st->Tenv, i * cqc, e), cqc});
 
     // readout: per site, L' = (T4 (C1 T1)) C2 and R' = (T2 (C3 T3)) C4
     {
@@ -475,6 +505,9 @@ void prepare_double_layers(ipeps_state* st) {
                              st->stream));
     HIP_CHECK(hipEventRecord(st->ev_gamma_free, st->stream));
     double_layer_real(st->stream, st->D, st->d, st->A, st->a_base);
+    // a scale per site changes no projector, spectrum or expectation value;
+    // unit norm keeps the cut products far from the FP32 underflow range
+    normalize_tensors(st->stream, IPEPS_DTYPE_FP64, st->d_norms + st->norm_a_first, 4);
     frame_layouts(st->stream, st->q, st->dtype, st->a_base, st->d_a_lu, st->d_a_dl);
     st->ctm_step = st->step_count;
 }
@@ -482,19 +515,45 @@ void prepare_double_layers(ipeps_state* st) {
 // Order the main stream after all enqueued simple-update work.
 void join_su(ipeps_state* st) { HIP_CHECK(hipStreamWaitEvent(st->stream, st->ev_su_done, 0)); }
 
-// Column-normalised Cholesky QR of X (n x k, batch 2): one pass leaves the
-// result in the temporary (via mul1), two passes (CholQR2) back in X.
-void orth(ipeps_state* st, double* X, const GemmGroup& gram1, const GemmGroup& mul1,
-          const GemmGroup& gram2, const GemmGroup& mul2, bool two_pass = true) {
-    normalize_columns(st->stream, 2, st->n, st->k, X);
+// Column-normalised Cholesky QR of X (n x k, batch 2) into Q.  Columns that
+// the Cholesky drops as dependent (their directions sit below the rounding
+// level of the dominant ones) are, with refill, restarted as random vectors
+// made orthogonal to the kept columns by two projections: the block keeps k
+// independent directions, and the next power step with N pulls out the
+// directions the dominant ones were hiding.  two_pass re-orthonormalises Q
+// back into X (CholQR2).
+void orth(ipeps_state* st, double* X, double* Q, const GemmGroup& gram1, const GemmGroup& mul1,
+          const GemmGroup& gram2, const GemmGroup& mul2, bool two_pass,
+          const GemmGroup* proj1 = nullptr, const GemmGroup* proj2 = nullptr) {
+    const bool refill = proj1 && proj2;
+    const int n = st->n, k = st->k;
+    hipStream_t s = st->stream;
+    normalize_columns(s, 2, n, k, X);
     run(st, gram1);
-    chol_inverse(st->stream, 2, st->k, st->Gm, st->Ri, kCholDrop);
+    chol_inverse(s, 2, k, st->Gm, st->Ri, kCholDrop, refill ? st->dead_dev : nullptr);
     run(st, mul1);
+    if (refill) {
+        const uint64_t seed = st->cfg.seed * 0x9E3779B97F4A7C15ull + 0x632BE59BD9B4E019ull * ++st->orth_calls;
+        dead_fill(s, 2, n, k, st->dead_dev, seed, st->Rb);
+        for (int pass = 0; pass < 2; ++pass) {
+            run(st, *proj1);  // Gm = Q^T Rb
+            run(st, *proj2);  // Rb -= Q Gm
+        }
+        add_gated(s, 2, (long)n * k, st->dead_dev + 2 * k, st->Rb, Q);
+    }
     if (!two_pass) return;
+    normalize_columns(s, 2, n, k, Q);
     run(st, gram2);
-    chol_inverse(st->stream, 2, st->k, st->Gm, st->Ri, kCholDrop);
+    chol_inverse(s, 2, k, st->Gm, st->Ri, kCholDrop);
     run(st, mul2);
 }
+
+// Relative cutoff below which singular values of a cut matrix count as zero.
+// The FP32 path keeps the same value: its tail below ~1e-6 is rounding noise
+// of the products, but such directions enter the renormalised tensors with
+// weight sqrt(sigma), and cutting them at 1e-6 was measured to move the
+// imbalance more (1e-4) than keeping them (5e-6).
+double proj_cutoff(const ipeps_state*) { return 1e-12; }
 
 // Truncated SVD of the two cut matrices N64[0..1]; fills Us, Vs and g_dev.
 void projector_svd(ipeps_state* st, int slot) {
@@ -502,7 +561,8 @@ void projector_svd(ipeps_state* st, int slot) {
     hipStream_t s = st->stream;
     if (n <= kDirectMax) {
         jacobi_svd_real(s, 2, n, n, st->N64, n, (long)n * n, st->sig, st->Uo, st->Vo, st->jwork);
-        projector_factors(s, st->dtype, 2, n, n, chi, st->Uo, st->Vo, st->sig, (long)n * n, st->Us,
+        projector_factors(s, st->dtype, 2, n, n, chi, proj_cutoff(st), st->Uo, st->Vo, st->sig,
+                          (long)n * n, st->Us,
                           st->Vs, (long)n * chi, st->g_dev);
         return;
     }
@@ -515,20 +575,25 @@ void projector_svd(ipeps_state* st, int slot) {
                                  hipMemcpyDeviceToDevice, s));
     } else {
         random_block(s, 2, n, k, st->cfg.seed * 1315423911ull + (uint64_t)slot + 1, st->Zw);
-        orth(st, st->Zw, P.gramZ, P.QfromZ, P.gramQz, P.ZfromQz);
+        orth(st, st->Zw, st->Qz, P.gramZ, P.QfromZ, P.gramQz, P.ZfromQz, true);
         HIP_CHECK(hipMemcpyAsync(st->Qz, st->Zw, 2 * nk * sizeof(double), hipMemcpyDeviceToDevice, s));
     }
     const int iters = warm ? kWarmIters : kColdIters;
     for (int it = 0; it < iters; ++it) {
-        // power step with one Cholesky-QR pass per side: only the span matters
+        // power step with one Cholesky-QR pass per side (only the span
+        // matters).  Dropped left columns are restarted; a right column
+        // dropped here is zero in V, hence dead in the next left block and
+        // restarted there.  Zero columns of the final V only add zero Ritz
+        // values.
         run(st, P.NV);  // Yw = N V
-        orth(st, st->Yw, P.gramY, P.QfromY, P.gramQ, P.YfromQ, false);  // -> Qw
+        orth(st, st->Yw, st->Qw, P.gramY, P.QfromY, P.gramQ, P.YfromQ, false, &P.projQw1,
+             &P.projQw2);
         run(st, P.NtQ);  // Zw = N^T Qw
-        orth(st, st->Zw, P.gramZ, P.QfromZ, P.gramQz, P.ZfromQz, false);  // -> Qz
+        orth(st, st->Zw, st->Qz, P.gramZ, P.QfromZ, P.gramQz, P.ZfromQz, false);
     }
     // Rayleigh-Ritz on span(N V) x span(V)
     run(st, P.NV);
-    orth(st, st->Yw, P.gramY, P.QfromY, P.gramQ, P.YfromQ);
+    orth(st, st->Yw, st->Qw, P.gramY, P.QfromY, P.gramQ, P.YfromQ, true);
     run(st, P.NVfinal);  // Qw = N V
     run(st, P.Cs);       // Cs = Q^T N V
     jacobi_svd_real(s, 2, k, k, st->Cs, k, (long)k * k, st->sig, st->Uc, st->Vc, st->jwork);
@@ -537,7 +602,8 @@ void projector_svd(ipeps_state* st, int slot) {
     HIP_CHECK(hipMemcpyAsync(st->warm + 2 * slot * nk, st->Vo, 2 * nk * sizeof(double),
                              hipMemcpyDeviceToDevice, s));
     st->warm_valid[2 * slot] = st->warm_valid[2 * slot + 1] = true;
-    projector_factors(s, st->dtype, 2, n, k, chi, st->Uo, st->Vo, st->sig, nk, st->Us, st->Vs,
+    projector_factors(s, st->dtype, 2, n, k, chi, proj_cutoff(st), st->Uo, st->Vo, st->sig, nk,
+                      st->Us, st->Vs,
                       (long)n * chi, st->g_dev);
 }
 
@@ -770,6 +836,7 @@ int ctmrg_converge(ipeps_state* st, double tol, int max_iter, int cold_start, in
         bool first = false;
         if (cold_start || !st->have_env) {
             init_environment(st->stream, st->D, st->chi, st->dtype, st->a_base, st->Cenv, st->Tenv);
+            normalize_tensors(st->stream, st->dtype, st->d_norms + st->norm_env_first, 32);
             for (bool& w : st->warm_valid) w = false;
             st->have_env = true;
             corner_spectra_update(st, true);

@@ -49,10 +49,11 @@ void to_fp64(hipStream_t s, int dtype, const void* in, double* out, long count);
 void from_fp64(hipStream_t s, int dtype, const double* in, void* out, long count);
 
 // Projector factors from an SVD of the cut matrix: the truncation rule on
-// sigma (k values, descending) picks g <= chi; Us[i][c] = U[i][c]/sqrt(s_c),
+// sigma (k values, descending; values <= tau * s_1 count as zero, multiplets
+// within 100 tau are kept whole) picks g <= chi; Us[i][c] = U[i][c]/sqrt(s_c),
 // Vs[i][c] = V[i][c]/sqrt(s_c) for c < g, zero for g <= c < chi (n x chi,
 // dtype).  U and V are n x k row-major (ld k).  g_out[b] receives g.
-void projector_factors(hipStream_t s, int dtype, int batch, int n, int k, int chi,
+void projector_factors(hipStream_t s, int dtype, int batch, int n, int k, int chi, double tau,
                        const double* U, const double* V, const double* sigma, long strideUV,
                        void* Us, void* Vs, long strideP, int* g_out);
 

@@ -351,18 +351,21 @@ void from_fp64(hipStream_t s, int dtype, const double* in, void* out, long count
 }
 
 // ------------------------------------------------------------ projector factors
-__device__ inline int trunc_rule_dev(const double* s, int n, int K) {
+// Keep g <= K values: zeros (<= tau s_1) are dropped, and a multiplet
+// (neighbours within 100 tau relative) is never cut.
+__device__ inline int trunc_rule_dev(const double* s, int n, int K, double tau) {
     if (n <= 0 || !(s[0] > 0.0)) return 0;
     int r = 0;
-    for (int i = 0; i < n; ++i) r += s[i] > 1e-12 * s[0];
+    for (int i = 0; i < n; ++i) r += s[i] > tau * s[0];
     int g = r < K ? r : K;
     if (g < r)
-        while (g > 1 && s[g - 1] - s[g] <= 1e-10 * s[g - 1]) --g;
+        while (g > 1 && s[g - 1] - s[g] <= 100.0 * tau * s[g - 1]) --g;
     return g;
 }
 
 template <typename T>
-__global__ __launch_bounds__(1024) void k_proj_factors(int n, int k, int chi, const double* U,
+__global__ __launch_bounds__(1024) void k_proj_factors(int n, int k, int chi, double tau,
+                                                       const double* U,
                                                        const double* V, const double* sigma,
                                                        long strideUV, T* Us, T* Vs, long strideP,
                                                        int* g_out) {
@@ -371,7 +374,7 @@ __global__ __launch_bounds__(1024) void k_proj_factors(int n, int k, int chi, co
     const int b = blockIdx.x;
     const double* sg = sigma + (long)b * k;
     if (threadIdx.x == 0) {
-        g_s = trunc_rule_dev(sg, k, chi);
+        g_s = trunc_rule_dev(sg, k, chi, tau);
         g_out[b] = g_s;
     }
     __syncthreads();
@@ -390,15 +393,15 @@ __global__ __launch_bounds__(1024) void k_proj_factors(int n, int k, int chi, co
     }
 }
 
-void projector_factors(hipStream_t s, int dtype, int batch, int n, int k, int chi,
+void projector_factors(hipStream_t s, int dtype, int batch, int n, int k, int chi, double tau,
                        const double* U, const double* V, const double* sigma, long strideUV,
                        void* Us, void* Vs, long strideP, int* g_out) {
     IPEPS_REQUIRE(chi <= 256, IPEPS_EINVAL, "chi > 256");
     if (dtype == IPEPS_DTYPE_FP64)
-        hipLaunchKernelGGL(k_proj_factors<double>, dim3(batch), dim3(1024), 0, s, n, k, chi, U, V,
+        hipLaunchKernelGGL(k_proj_factors<double>, dim3(batch), dim3(1024), 0, s, n, k, chi, tau, U, V,
                            sigma, strideUV, (double*)Us, (double*)Vs, strideP, g_out);
     else
-        hipLaunchKernelGGL(k_proj_factors<float>, dim3(batch), dim3(1024), 0, s, n, k, chi, U, V,
+        hipLaunchKernelGGL(k_proj_factors<float>, dim3(batch), dim3(1024), 0, s, n, k, chi, tau, U, V,
                            sigma, strideUV, (float*)Us, (float*)Vs, strideP, g_out);
     HIP_CHECK(hipGetLastError());
 }

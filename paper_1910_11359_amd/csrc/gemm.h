@@ -28,6 +28,7 @@ struct GemmProb {
                      //   and are summed in a fixed order by a second kernel
     int tiles_n;     // filled by gemm_plan_tiles
     int tile_begin;  // first tile of this problem within its launch
+    const int* gate; // not null: the problem is skipped while *gate == 0
 };
 
 // Plain row-major helpers: op(X) = X (lda = row stride) or X^T.

@@ -56,6 +56,7 @@ __global__ __launch_bounds__(256) void k_gemm_grouped(const GemmProb* __restrict
     int p = 0;
     while (p + 1 < nprob && probs[p + 1].tile_begin <= bid) ++p;
     const GemmProb& P = probs[p];
+    if (P.gate && *P.gate == 0) return;  // uniform over the workgroup, before any barrier
     const int ks = P.ksplit > 1 ? P.ksplit : 1;
     const int tt = bid - P.tile_begin;
     const int split = tt % ks, t = tt / ks;
@@ -275,7 +276,7 @@ int gemm_plan_tiles(GemmProb* probs, int n, int dtype, GemmTile* tile) {
 template <typename T>
 __global__ __launch_bounds__(256) void k_splitk_reduce(const GemmProb* __restrict__ probs) {
     const GemmProb& P = probs[blockIdx.y];
-    if (P.ksplit <= 1) return;
+    if (P.ksplit <= 1 || (P.gate && *P.gate == 0)) return;
     const long MN = (long)P.M * P.N;
     const T* W = (const T*)P.ws;
     T* C = (T*)P.C;

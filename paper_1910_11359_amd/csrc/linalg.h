@@ -19,11 +19,24 @@ size_t jacobi_svd_real_work(int batch, int m, int n);
 // Batched Cholesky of k x k SPD Gram matrices G (row-major, stride k*k) with
 // dependency dropping, followed by the inverse of the factor: on exit
 // Rinv[b] holds R^{-1} (upper triangular, G = R^T R) with the rows/columns of
-// dropped pivots (pivot <= tol * G_ii) set to zero.
-void chol_inverse(hipStream_t s, int batch, int k, const double* G, double* Rinv, double tol);
+// dropped pivots (pivot <= tol * G_ii) set to zero.  If dead is not null
+// (batch*k + batch ints), dead[b*k + j] is set to 1 for a dropped column j
+// and 0 otherwise, and dead[batch*k + b] to the number of dropped columns.
+void chol_inverse(hipStream_t s, int batch, int k, const double* G, double* Rinv, double tol,
+                  int* dead = nullptr);
 
 // Scale the columns of batched n x k row-major matrices (stride n*k) to unit
 // 2-norm; zero columns stay zero.
 void normalize_columns(hipStream_t s, int batch, int n, int k, double* X);
+
+// R (batched n x k row-major, flags as written by chol_inverse): column j
+// uniform in [-1, 1) from a counter hash of (seed, element) where
+// dead[b*k + j] != 0, zero elsewhere; matrices with no dropped column are
+// left untouched.
+void dead_fill(hipStream_t s, int batch, int n, int k, const int* dead, uint64_t seed, double* R);
+
+// X_b[e] += Y_b[e] for e < count, for the batches b with gate[b] != 0
+// (matrix b at offset b*count).
+void add_gated(hipStream_t s, int batch, long count, const int* gate, const double* Y, double* X);
 
 }  // namespace ipeps

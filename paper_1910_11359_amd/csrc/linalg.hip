@@ -179,41 +179,43 @@ void jacobi_svd_real(hipStream_t s, int batch, int m, int n, const double* A, lo
 
 // ----------------------------------------------------------------- Cholesky
 // G = R^T R (R upper) with dropping, then R^{-1} in place (column-oriented
-// triangular inversion); both in LDS (k <= 128), one wave per matrix so the
-// k sequential steps need no workgroup barriers.  A dropped pivot zeroes its
-// row of R and its row and column of R^{-1}, so the matching column of
-// X R^{-1} is zero.
-__global__ __launch_bounds__(64) void k_chol_inverse(int k, const double* __restrict__ G,
-                                                     double* __restrict__ Rinv, double tol) {
+// triangular inversion); both in LDS (k <= 128), one workgroup of 4 waves per
+// matrix.  Each trailing-update row is split over 4 lanes.  A dropped pivot
+// zeroes its row of R and its row and column of R^{-1}, so the matching
+// column of X R^{-1} is zero; dead (if not null) receives 1 for such columns.
+__global__ __launch_bounds__(256) void k_chol_inverse(int k, const double* __restrict__ G,
+                                                      double* __restrict__ Rinv, double tol,
+                                                      int* __restrict__ dead) {
     extern __shared__ double R[];  // k*k, row-major
     __shared__ double colj[128];
     __shared__ int dead_s[128];
-    const int lane = threadIdx.x;
+    const int tid = threadIdx.x, nt = blockDim.x;
     const int b = blockIdx.x;
     const double* Gb = G + (long)b * k * k;
     double* Xb = Rinv + (long)b * k * k;
-    for (int e = lane; e < k * k; e += 64) R[e] = Gb[e];
+    for (int e = tid; e < k * k; e += nt) R[e] = Gb[e];
     __syncthreads();
     for (int j = 0; j < k; ++j) {
         const double dj = R[j * k + j];
-        const bool dead = !(dj > tol);  // every lane decides alike
+        const bool dead = !(dj > tol);  // every thread decides alike
         const double piv = dead ? 0.0 : sqrt(dj);
         const double ipiv = dead ? 0.0 : 1.0 / piv;
         __syncthreads();
-        for (int c = j + 1 + lane; c < k; c += 64) R[j * k + c] *= ipiv;
-        if (lane == 0) {
+        for (int c = j + 1 + tid; c < k; c += nt) R[j * k + c] *= ipiv;
+        if (tid == 0) {
             R[j * k + j] = piv;
             dead_s[j] = dead;
         }
         __syncthreads();
-        // trailing update of the upper triangle, one row per lane
-        for (int a = j + 1 + lane; a < k; a += 64) {
+        // trailing update of the upper triangle: row a split over 4 threads
+        for (int t = tid; t < 4 * (k - j - 1); t += nt) {
+            const int a = j + 1 + (t >> 2), part = t & 3;
             const double rja = R[j * k + a];
             double* __restrict__ ra = R + a * k;
             const double* __restrict__ rj = R + j * k;
             if (rja != 0.0) {
-#pragma unroll 8
-                for (int c = a; c < k; ++c) ra[c] -= rja * rj[c];
+#pragma unroll 4
+                for (int c = a + part; c < k; c += 4) ra[c] -= rja * rj[c];
             }
         }
         __syncthreads();
@@ -221,13 +223,13 @@ __global__ __launch_bounds__(64) void k_chol_inverse(int k, const double* __rest
     // in-place inverse of the upper-triangular R
     for (int j = 0; j < k; ++j) {
         const bool dead = dead_s[j];
-        for (int i = lane; i < j; i += 64) colj[i] = R[i * k + j];
+        for (int i = tid; i < j; i += nt) colj[i] = R[i * k + j];
         __syncthreads();
         if (dead) {
-            for (int i = lane; i <= j; i += 64) R[i * k + j] = 0.0;
+            for (int i = tid; i <= j; i += nt) R[i * k + j] = 0.0;
         } else {
             const double inv = 1.0 / R[j * k + j];
-            for (int i = lane; i < j; i += 64) {
+            for (int i = tid; i < j; i += nt) {
                 double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
                 const double* __restrict__ ri = R + i * k;
                 int l = i;
@@ -240,17 +242,26 @@ __global__ __launch_bounds__(64) void k_chol_inverse(int k, const double* __rest
                 for (; l < j; ++l) s0 += ri[l] * colj[l];
                 R[i * k + j] = -inv * ((s0 + s1) + (s2 + s3));
             }
-            if (lane == 0) R[j * k + j] = inv;
+            if (tid == 0) R[j * k + j] = inv;
         }
         __syncthreads();
     }
-    for (int e = lane; e < k * k; e += 64) {
+    for (int e = tid; e < k * k; e += nt) {
         const int i = e / k, c = e % k;
         Xb[e] = (c >= i && !dead_s[i]) ? R[e] : 0.0;
     }
+    if (dead) {
+        for (int j = tid; j < k; j += nt) dead[(long)b * k + j] = dead_s[j];
+        if (tid == 0) {
+            int c = 0;
+            for (int j = 0; j < k; ++j) c += dead_s[j];
+            dead[(long)gridDim.x * k + b] = c;
+        }
+    }
 }
 
-void chol_inverse(hipStream_t s, int batch, int k, const double* G, double* Rinv, double tol) {
+void chol_inverse(hipStream_t s, int batch, int k, const double* G, double* Rinv, double tol,
+                  int* dead) {
     if (batch <= 0) return;
     IPEPS_REQUIRE(k <= 128, IPEPS_EINVAL, "chol_inverse: k > 128");
     const size_t lds = (size_t)k * k * sizeof(double);
@@ -261,7 +272,7 @@ void chol_inverse(hipStream_t s, int batch, int k, const double* G, double* Rinv
                                       128 * 128 * (int)sizeof(double)));
         attr_set = true;
     }
-    hipLaunchKernelGGL(k_chol_inverse, dim3(batch), dim3(64), lds, s, k, G, Rinv, tol);
+    hipLaunchKernelGGL(k_chol_inverse, dim3(batch), dim3(256), lds, s, k, G, Rinv, tol, dead);
     HIP_CHECK(hipGetLastError());
 }
 
@@ -280,6 +291,46 @@ __global__ __launch_bounds__(256) void k_normalize_columns(int n, int k, double*
 void normalize_columns(hipStream_t s, int batch, int n, int k, double* X) {
     if (batch <= 0 || k <= 0) return;
     hipLaunchKernelGGL(k_normalize_columns, dim3(k, batch), dim3(256), 0, s, n, k, X);
+    HIP_CHECK(hipGetLastError());
+}
+
+__global__ __launch_bounds__(256) void k_dead_fill(int n, int k, const int* __restrict__ dead,
+                                                   uint64_t seed, double* __restrict__ R) {
+    const long tot = (long)n * k;
+    const int b = blockIdx.y;
+    if (dead[(long)gridDim.y * k + b] == 0) return;
+    for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < tot;
+         e += (long)gridDim.x * blockDim.x) {
+        const int j = (int)(e % k);
+        R[b * tot + e] = dead[(long)b * k + j] ? 2.0 * hash_uniform(seed, (uint64_t)(b * tot + e)) - 1.0
+                                               : 0.0;
+    }
+}
+
+void dead_fill(hipStream_t s, int batch, int n, int k, const int* dead, uint64_t seed, double* R) {
+    if (batch <= 0 || k <= 0) return;
+    const long tot = (long)n * k;
+    const int grid = ceil_div(tot, 256) < 1024 ? (int)ceil_div(tot, 256) : 1024;
+    hipLaunchKernelGGL(k_dead_fill, dim3(grid, batch), dim3(256), 0, s, n, k, dead, seed, R);
+    HIP_CHECK(hipGetLastError());
+}
+
+__global__ __launch_bounds__(256) void k_add_gated(long count, const int* __restrict__ gate,
+                                                   const double* __restrict__ Y,
+                                                   double* __restrict__ X) {
+    const int b = blockIdx.y;
+    if (gate[b] == 0) return;
+    const double* Yb = Y + b * count;
+    double* Xb = X + b * count;
+    for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < count;
+         e += (long)gridDim.x * blockDim.x)
+        Xb[e] += Yb[e];
+}
+
+void add_gated(hipStream_t s, int batch, long count, const int* gate, const double* Y, double* X) {
+    if (batch <= 0 || count <= 0) return;
+    const int grid = ceil_div(count, 256) < 1024 ? (int)ceil_div(count, 256) : 1024;
+    hipLaunchKernelGGL(k_add_gated, dim3(grid, batch), dim3(256), 0, s, count, gate, Y, X);
     HIP_CHECK(hipGetLastError());
 }
 

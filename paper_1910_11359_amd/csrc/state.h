@@ -46,6 +46,8 @@ struct SvdPlan {
     // orth passes on Y and Z and the Rayleigh-Ritz products, batch 2 (FP64)
     GemmGroup NV, NtQ, gramY, gramZ, gramQ, gramQz, QfromY, QfromZ, YfromQ, ZfromQz, Cs, Uo,
         Vo, NVfinal;
+    // restart of dropped left columns: Gm = Qw^T Rb, Rb -= Qw Gm
+    GemmGroup projQw1, projQw2;
 };
 
 }  // namespace ipeps
@@ -110,6 +112,9 @@ struct ipeps_state {
     double* warm;  // 16 slots of n*k
     bool warm_valid[16];
     double *Yw, *Zw, *Qw, *Qz, *Gm, *Ri, *Cs, *Uc, *Vc, *sig, *Uo, *Vo, *jwork;
+    double* Rb;          // 2 blocks of n*k: refill directions for dropped columns
+    int* dead_dev;       // 2*k flags of dropped columns, then 2 counts
+    uint64_t orth_calls; // counter feeding the refill hash
     double *Nfull_U, *Nfull_V;  // direct path (n <= 96)
     int ks_gram, ks_nv, ks_c;   // split-K factors
     double *ws_gram, *ws_nv;    // split-K partials (FP64)
@@ -133,6 +138,8 @@ struct ipeps_state {
     ipeps::GemmProb* d_probs;
     std::vector<ipeps::NormItem> norms;
     ipeps::NormItem* d_norms;
+    long norm_a_first;    // 4 FP64 items: the double-layer tensors
+    long norm_env_first;  // 32 dtype items: the 16 corners and 16 edges
     ipeps::ColumnStep steps[8];  // frame f (in move order) * 2 + X
     ipeps::SvdPlan svd;
     ipeps::GemmGroup read1, read2, read3, read4;

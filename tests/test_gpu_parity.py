@@ -72,6 +72,38 @@ def test_random_state_vs_oracle(D, chi, seed):
             assert np.max(np.abs(eps - np.array([ost["eps"][s] for s in opeps.SITES]))) < 1e-10
 
 
+def test_product_start_low_rank_cuts():
+    """Neel start, D=3, chi=18 (n=162: subspace-iteration SVD), large V.
+    Right after the start the cut matrices have a few dominant singular
+    values and a tail spanning ten decades above the cutoff: the tail
+    directions sit below the rounding level of the dominant ones in a mixed
+    block, so the device must recover them by restarting dropped columns.
+    The FP32 path (products in FP32, cutoff 1e-6) runs beside it and must
+    stay finite with the imbalance within 1e-3."""
+    kw = dict(J=1.0, V=1.6759187457576177, W=1.3506622087662332, dt=0.05)
+    st = _gpu_state(3, 18, **kw)
+    st32 = P.State(P.make_config(3, 18, dtype="fp32", **kw))
+    p = par.oracle_params(3, 18, **kw)
+    ost = opeps.new_state(p)
+    for step in range(1, 6):
+        st.trotter_step(1)
+        st32.trotter_step(1)
+        opeps.trotter_step(ost, p)
+        if step not in (1, 2, 5):
+            continue
+        st.ctmrg(0.0, 10, True)
+        st32.ctmrg(0.0, 10, True)
+        g, g32 = st.observe(), st32.observe()
+        o, _ = orun.observe_state(ost, p, ctm_iters=10)
+        assert abs(g["imbalance"] - o["imbalance"]) < 1e-6, step
+        assert np.max(np.abs(g["n"] - o["n"])) < 1e-6, step
+        spread = par.oracle_spread(ost, p, 10, o["corner_spectra"])
+        par.assert_spectra(st.corner_spectra(), o["corner_spectra"], spread, step)
+        assert abs(g32["imbalance"] - o["imbalance"]) < 1e-3, step
+    st.close()
+    st32.close()
+
+
 def _dimer_exact(t, J, W):
     w = np.sqrt(J ** 2 + 4 * W ** 2)
     return 1 - np.sin(J * t / 2) ** 2 - J ** 2 / w ** 2 * np.sin(w * t / 2) ** 2
