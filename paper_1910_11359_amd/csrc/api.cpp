@@ -640,8 +640,9 @@ void corner_spectra_update(ipeps_state* st, bool first) {
     const int chi = st->chi;
     hipStream_t s = st->stream;
     to_fp64(s, st->dtype, st->Cenv, st->C64, 16L * chi * chi);
+    // spectra are reported to 1e-8 sigma_1: columns below 1e-10 |C|_F need no rotation
     jacobi_svd_real(s, 16, chi, chi, st->C64, chi, (long)chi * chi, st->csig, nullptr, nullptr,
-                    st->jwork);
+                    st->jwork, 1e-10);
     spectra_delta(s, 16, chi, st->csig, st->spectra, st->spec_prev, st->dev_scalars, first ? 1 : 0);
     st->spectra_valid = true;
 }

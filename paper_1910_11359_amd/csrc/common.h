@@ -125,6 +125,21 @@ __device__ inline double block_max(double v, double* red) {
 }
 
 // Stateless counter-based uniform in [0,1) (SplitMix64 finaliser).
+// 1/x and 1/sqrt(x) for finite x > 0 (FP64): the hardware estimates refined by
+// two Newton steps (each squares the relative error), accurate to rounding.
+__device__ inline double fast_rcp(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(r, fma(-x, r, 1.0), r);
+    r = fma(r, fma(-x, r, 1.0), r);
+    return r;
+}
+__device__ inline double fast_rsq(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+    y = y * fma(-0.5 * x * y, y, 1.5);
+    y = y * fma(-0.5 * x * y, y, 1.5);
+    return y;
+}
+
 __device__ inline double hash_uniform(uint64_t seed, uint64_t counter) {
     uint64_t z = seed + 0x9E3779B97F4A7C15ull * (counter + 1);
     z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;

@@ -5,18 +5,21 @@
 
 namespace ipeps {
 
-// Batched one-sided (Hestenes) Jacobi SVD of real m x n matrices, m >= n.
+// Batched one-sided (Hestenes) Jacobi SVD of real m x n matrices, n <= m <= 256.
 // Matrix b is read from A + b*strideA with element (i, j) at [i*lda + j]
 // (row-major).  Outputs, sorted by descending singular value:
 //   sigma[b*n + j], U (m x n, row-major ld n, b*m*n) with unit columns (zero
 //   for zero singular values), V (n x n row-major, b*n*n) with A = U S V^T.
-// U and V may be NULL.  Works in LDS when 2*m*n... fits, else in `work`
-// (device scratch of at least batch * (m*n + n*n) doubles).
+// U and V may be NULL.  Columns whose norm falls below skip_rel * |A|_F are
+// not rotated (their singular values are then known to that absolute
+// level).  Works in LDS when m*n + n*n + 2n doubles fit, else in `work`
+// (device scratch of jacobi_svd_real_work doubles).
 void jacobi_svd_real(hipStream_t s, int batch, int m, int n, const double* A, long lda,
-                     long strideA, double* sigma, double* U, double* V, double* work);
+                     long strideA, double* sigma, double* U, double* V, double* work,
+                     double skip_rel = 1e-14);
 size_t jacobi_svd_real_work(int batch, int m, int n);
 
-// Batched Cholesky of k x k SPD Gram matrices G (row-major, stride k*k) with
+// Batched Cholesky of k x k SPD Gram matrices G (row-major, stride k*k, k <= 256) with
 // dependency dropping, followed by the inverse of the factor: on exit
 // Rinv[b] holds R^{-1} (upper triangular, G = R^T R) with the rows/columns of
 // dropped pivots (pivot <= tol * G_ii) set to zero.  If dead is not null

@@ -25,60 +25,91 @@ __device__ inline void circle_pair(int r, int k, int ne, int* p, int* q) {
     }
 }
 
-// Ac: m x n column-major working copy of A, Vc: n x n column-major (or NULL).
-// Each pair of a round is handled by a group of 16 lanes (4 groups per wave);
-// the three inner products are summed with DPP moves inside the group.
-__device__ void jacobi_sweeps(int m, int n, double* Ac, double* Vc, int* flag, double* red) {
+// Ac: m x n column-major working copy of A, Vc: n x n column-major (or NULL),
+// nrm: n squared column norms (recomputed exactly at the start of each sweep,
+// updated in closed form after each rotation, so a pair needs only one inner
+// product).  Each pair of a round is handled by a group of 16 lanes (4 groups
+// per wave) holding its two columns in registers (EPL elements per lane);
+// the inner product is summed with DPP moves inside the group.
+template <int EPL>
+__device__ void jacobi_sweeps(int m, int n, double* Ac, double* Vc, double* nrm, int* flag,
+                              double* red, double skip_rel) {
     const int g16 = threadIdx.x & 15, group = threadIdx.x >> 4, ngroups = blockDim.x >> 4;
     const int ne = n + (n & 1);
     const int npair = ne / 2;
-    const double tol = 4.0 * m * 1.11e-16;
-    // columns below 1e-14 |A|_F are rounding noise: a rotation against a large
-    // column re-pollutes them at their own size, so they are left alone
+    const double tol = 4.0 * m * 1.11e-16, tol2 = tol * tol;
+    // columns below skip_rel |A|_F are left alone: a rotation against a large
+    // column re-pollutes them at their own size
     double fro = 0.0;
     for (long e = threadIdx.x; e < (long)m * n; e += blockDim.x) fro += Ac[e] * Ac[e];
     fro = block_sum(fro, red);
-    const double small2 = 1e-28 * fro;
+    const double small2 = skip_rel * skip_rel * fro;
     for (int sweep = 0; sweep < 40; ++sweep) {
+        for (int j = group; j < n; j += ngroups) {
+            const double* aj = Ac + (long)j * m;
+            double sq = 0.0;
+#pragma unroll
+            for (int e = 0; e < EPL; ++e) {
+                const int i = g16 + 16 * e;
+                const double v = (i < m) ? aj[i] : 0.0;
+                sq += v * v;
+            }
+            sq = group16_sum(sq);
+            if (g16 == 0) nrm[j] = sq;
+        }
         if (threadIdx.x == 0) *flag = 0;
         __syncthreads();
         for (int r = 0; r < ne - 1; ++r) {
-            for (int k = group; k < npair; k += ngroups) {
+            for (int kk = group; kk < npair; kk += ngroups) {
                 int p, q;
-                circle_pair(r, k, ne, &p, &q);
+                circle_pair(r, kk, ne, &p, &q);
                 if (q >= n) continue;
                 double* ap = Ac + (long)p * m;
                 double* aq = Ac + (long)q * m;
-                double al = 0, be = 0, ga = 0;
-                for (int i = g16; i < m; i += 16) {
-                    const double x = ap[i], y = aq[i];
-                    al += x * x;
-                    be += y * y;
-                    ga += x * y;
+                double x[EPL], y[EPL];
+                double ga = 0.0;
+#pragma unroll
+                for (int e = 0; e < EPL; ++e) {
+                    const int i = g16 + 16 * e;
+                    x[e] = (i < m) ? ap[i] : 0.0;
+                    y[e] = (i < m) ? aq[i] : 0.0;
+                    ga += x[e] * y[e];
                 }
-                al = group16_sum(al);
-                be = group16_sum(be);
                 ga = group16_sum(ga);
+                const double al = nrm[p], be = nrm[q];
                 if (al <= small2 || be <= small2) continue;
-                if (fabs(ga) <= tol * sqrt(al) * sqrt(be)) continue;
-                const double zeta = (be - al) / (2.0 * ga);
-                const double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-                const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
-                for (int i = g16; i < m; i += 16) {
-                    const double x = ap[i], y = aq[i];
-                    ap[i] = c * x - s * y;
-                    aq[i] = s * x + c * y;
+                if (ga * ga <= tol2 * al * be) continue;
+                const double zeta = 0.5 * (be - al) * fast_rcp(ga);
+                const double az = fabs(zeta);
+                const double den = (az > 1e150) ? 2.0 * az : az + (1.0 + az * az) * fast_rsq(1.0 + az * az);
+                const double t = copysign(fast_rcp(den), zeta);
+                const double c = fast_rsq(1.0 + t * t), s = c * t;
+#pragma unroll
+                for (int e = 0; e < EPL; ++e) {
+                    const int i = g16 + 16 * e;
+                    if (i < m) {
+                        ap[i] = c * x[e] - s * y[e];
+                        aq[i] = s * x[e] + c * y[e];
+                    }
                 }
                 if (Vc) {
                     double* vp = Vc + (long)p * n;
                     double* vq = Vc + (long)q * n;
-                    for (int i = g16; i < n; i += 16) {
-                        const double x = vp[i], y = vq[i];
-                        vp[i] = c * x - s * y;
-                        vq[i] = s * x + c * y;
+#pragma unroll
+                    for (int e = 0; e < EPL; ++e) {
+                        const int i = g16 + 16 * e;
+                        if (i < n) {
+                            const double xv = vp[i], yv = vq[i];
+                            vp[i] = c * xv - s * yv;
+                            vq[i] = s * xv + c * yv;
+                        }
                     }
                 }
-                if (g16 == 0) *flag = 1;
+                if (g16 == 0) {
+                    nrm[p] = al - t * ga;
+                    nrm[q] = be + t * ga;
+                    *flag = 1;
+                }
             }
             __syncthreads();
         }
@@ -114,24 +145,31 @@ __device__ void jacobi_finish(int m, int n, const double* Ac, const double* Vc, 
     }
 }
 
-template <bool IN_LDS>
-__global__ __launch_bounds__(1024) void k_jacobi_svd(int m, int n, const double* __restrict__ A,
+// Threads per workgroup: 1024 while the two register columns fit the
+// 128-VGPR budget of a 16-wave group, 512 for longer columns.
+template <int EPL>
+constexpr int jacobi_threads() { return EPL <= 6 ? 1024 : 512; }
+
+template <bool IN_LDS, int EPL>
+__global__ __launch_bounds__(jacobi_threads<EPL>()) void k_jacobi_svd(int m, int n, const double* __restrict__ A,
                                                      long lda, long strideA, double* sigma,
-                                                     double* U, double* V, double* work) {
+                                                     double* U, double* V, double* work,
+                                                     double skip_rel) {
     extern __shared__ double smem[];
     __shared__ int flag;
     __shared__ double red[16];
     const int b = blockIdx.x;
     const bool wantV = (V != nullptr);
     const long nv = wantV ? (long)n * n : 0;
-    double *Ac, *Vc, *sig_s;
+    double *Ac, *Vc, *sig_s, *nrm;
     if (IN_LDS) {
         Ac = smem;
     } else {
-        Ac = work + (long)b * ((long)m * n + nv + n);
+        Ac = work + (long)b * ((long)m * n + nv + 2 * n);
     }
     Vc = Ac + (long)m * n;
     sig_s = Vc + nv;
+    nrm = sig_s + n;
     const double* Ab = A + (long)b * strideA;
     for (long e = threadIdx.x; e < (long)m * n; e += blockDim.x) {
         const int j = (int)(e / m), i = (int)(e % m);
@@ -139,140 +177,269 @@ __global__ __launch_bounds__(1024) void k_jacobi_svd(int m, int n, const double*
     }
     for (long e = threadIdx.x; e < nv; e += blockDim.x) Vc[e] = ((e / n) == (e % n)) ? 1.0 : 0.0;
     __syncthreads();
-    jacobi_sweeps(m, n, Ac, wantV ? Vc : nullptr, &flag, red);
+    jacobi_sweeps<EPL>(m, n, Ac, wantV ? Vc : nullptr, nrm, &flag, red, skip_rel);
     __syncthreads();
     jacobi_finish(m, n, Ac, Vc, sig_s, sigma + (long)b * n, U ? U + (long)b * m * n : nullptr,
                   V ? V + (long)b * n * n : nullptr);
 }
 
 static size_t jacobi_lds_bytes(int m, int n, bool wantV) {
-    return ((size_t)m * n + (wantV ? (size_t)n * n : 0) + n) * sizeof(double);
+    return ((size_t)m * n + (wantV ? (size_t)n * n : 0) + 2 * (size_t)n) * sizeof(double);
 }
 static const size_t kMaxLds = 160 * 1024 - 1024;
 
 size_t jacobi_svd_real_work(int batch, int m, int n) {
     if (jacobi_lds_bytes(m, n, true) <= kMaxLds) return 0;
-    return (size_t)batch * ((size_t)m * n + (size_t)n * n + n);
+    return (size_t)batch * ((size_t)m * n + (size_t)n * n + 2 * (size_t)n);
 }
 
-void jacobi_svd_real(hipStream_t s, int batch, int m, int n, const double* A, long lda,
-                     long strideA, double* sigma, double* U, double* V, double* work) {
-    if (batch <= 0 || n <= 0) return;
+template <int EPL>
+static void launch_jacobi(hipStream_t s, int batch, int m, int n, const double* A, long lda,
+                          long strideA, double* sigma, double* U, double* V, double* work,
+                          double skip_rel) {
     const size_t lds = jacobi_lds_bytes(m, n, V != nullptr);
     if (lds <= kMaxLds) {
         static bool attr_set = false;
         if (!attr_set) {
-            HIP_CHECK(hipFuncSetAttribute((const void*)k_jacobi_svd<true>,
+            HIP_CHECK(hipFuncSetAttribute((const void*)k_jacobi_svd<true, EPL>,
                                           hipFuncAttributeMaxDynamicSharedMemorySize,
                                           (int)kMaxLds));
             attr_set = true;
         }
-        hipLaunchKernelGGL(k_jacobi_svd<true>, dim3(batch), dim3(1024), lds, s, m, n, A, lda,
-                           strideA, sigma, U, V, work);
+        hipLaunchKernelGGL((k_jacobi_svd<true, EPL>), dim3(batch), dim3(jacobi_threads<EPL>()), lds, s, m, n, A, lda,
+                           strideA, sigma, U, V, work, skip_rel);
     } else {
         IPEPS_REQUIRE(work != nullptr, IPEPS_EINVAL, "jacobi_svd_real: work buffer needed");
-        hipLaunchKernelGGL(k_jacobi_svd<false>, dim3(batch), dim3(1024), 0, s, m, n, A, lda,
-                           strideA, sigma, U, V, work);
+        hipLaunchKernelGGL((k_jacobi_svd<false, EPL>), dim3(batch), dim3(jacobi_threads<EPL>()), 0, s, m, n, A, lda,
+                           strideA, sigma, U, V, work, skip_rel);
     }
     HIP_CHECK(hipGetLastError());
 }
 
+void jacobi_svd_real(hipStream_t s, int batch, int m, int n, const double* A, long lda,
+                     long strideA, double* sigma, double* U, double* V, double* work,
+                     double skip_rel) {
+    if (batch <= 0 || n <= 0) return;
+    IPEPS_REQUIRE(m >= n && m <= 256, IPEPS_EINVAL, "jacobi_svd_real: need n <= m <= 256");
+    if (m <= 64)
+        launch_jacobi<4>(s, batch, m, n, A, lda, strideA, sigma, U, V, work, skip_rel);
+    else if (m <= 96)
+        launch_jacobi<6>(s, batch, m, n, A, lda, strideA, sigma, U, V, work, skip_rel);
+    else if (m <= 128)
+        launch_jacobi<8>(s, batch, m, n, A, lda, strideA, sigma, U, V, work, skip_rel);
+    else if (m <= 176)
+        launch_jacobi<11>(s, batch, m, n, A, lda, strideA, sigma, U, V, work, skip_rel);
+    else
+        launch_jacobi<16>(s, batch, m, n, A, lda, strideA, sigma, U, V, work, skip_rel);
+}
+
 // ----------------------------------------------------------------- Cholesky
-// G = R^T R (R upper) with dropping, then R^{-1} in place (column-oriented
-// triangular inversion); both in LDS (k <= 128), one workgroup of 4 waves per
-// matrix.  Each trailing-update row is split over 4 lanes.  A dropped pivot
-// zeroes its row of R and its row and column of R^{-1}, so the matching
-// column of X R^{-1} is zero; dead (if not null) receives 1 for such columns.
+// G = R^T R (R upper) with dropping, and X = R^{-1} built alongside, in
+// place; one workgroup of 4 waves per matrix, blocked by NB = 16 columns.
+// Per block J (three barriers):
+//  (a) wave 0 factors the 16 x 16 diagonal block in registers (lane c holds
+//      column c; rows are broadcast with readlane) and inverts it the same way
+//      (lane i builds row i of X_JJ), writing X_JJ over R_JJ;
+//  (b) the panel R[J, rest] = X_JJ^T G[J, rest] (independent dot products) and
+//      T = X[:J, :J] R[:J, J] (4 x 4 register tiles);
+//  (c) the trailing update G[rest, rest] -= R[J, rest]^T R[J, rest] (4 x 4
+//      tiles) and X[:J, J] = -T X_JJ.
+// A dropped pivot (Schur diagonal <= tol) zeroes its row of R and its row and
+// column of X, so the matching column of Y X is zero.  R lives in LDS for
+// k <= 128, else in the output buffer (L2-resident).
+constexpr int kNb = 16;
+
+__device__ inline double readlane_d(double v, int lane) {
+    const long long x = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)x, lane);
+    const int hi = __builtin_amdgcn_readlane((int)(x >> 32), lane);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+template <bool IN_LDS>
 __global__ __launch_bounds__(256) void k_chol_inverse(int k, const double* __restrict__ G,
                                                       double* __restrict__ Rinv, double tol,
                                                       int* __restrict__ dead) {
-    extern __shared__ double R[];  // k*k, row-major
-    __shared__ double colj[128];
-    __shared__ int dead_s[128];
-    const int tid = threadIdx.x, nt = blockDim.x;
+    extern __shared__ double smem[];
+    __shared__ int dead_s[256];
+    const int tid = threadIdx.x, lane = tid & 63;
     const int b = blockIdx.x;
     const double* Gb = G + (long)b * k * k;
-    double* Xb = Rinv + (long)b * k * k;
-    for (int e = tid; e < k * k; e += nt) R[e] = Gb[e];
+    double* out = Rinv + (long)b * k * k;
+    double* R = IN_LDS ? smem : out;
+    double* Tb = IN_LDS ? smem + (long)k * k : smem;  // k x NB
+    for (int e = tid; e < k * k; e += 256) R[e] = Gb[e];
     __syncthreads();
-    for (int j = 0; j < k; ++j) {
-        const double dj = R[j * k + j];
-        const bool dead = !(dj > tol);  // every thread decides alike
-        const double piv = dead ? 0.0 : sqrt(dj);
-        const double ipiv = dead ? 0.0 : 1.0 / piv;
-        __syncthreads();
-        for (int c = j + 1 + tid; c < k; c += nt) R[j * k + c] *= ipiv;
-        if (tid == 0) {
-            R[j * k + j] = piv;
-            dead_s[j] = dead;
-        }
-        __syncthreads();
-        // trailing update of the upper triangle: row a split over 4 threads
-        for (int t = tid; t < 4 * (k - j - 1); t += nt) {
-            const int a = j + 1 + (t >> 2), part = t & 3;
-            const double rja = R[j * k + a];
-            double* __restrict__ ra = R + a * k;
-            const double* __restrict__ rj = R + j * k;
-            if (rja != 0.0) {
-#pragma unroll 4
-                for (int c = a + part; c < k; c += 4) ra[c] -= rja * rj[c];
-            }
-        }
-        __syncthreads();
-    }
-    // in-place inverse of the upper-triangular R
-    for (int j = 0; j < k; ++j) {
-        const bool dead = dead_s[j];
-        for (int i = tid; i < j; i += nt) colj[i] = R[i * k + j];
-        __syncthreads();
-        if (dead) {
-            for (int i = tid; i <= j; i += nt) R[i * k + j] = 0.0;
-        } else {
-            const double inv = 1.0 / R[j * k + j];
-            for (int i = tid; i < j; i += nt) {
-                double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-                const double* __restrict__ ri = R + i * k;
-                int l = i;
-                for (; l + 3 < j; l += 4) {
-                    s0 += ri[l] * colj[l];
-                    s1 += ri[l + 1] * colj[l + 1];
-                    s2 += ri[l + 2] * colj[l + 2];
-                    s3 += ri[l + 3] * colj[l + 3];
+
+    for (int J0 = 0; J0 < k; J0 += kNb) {
+        const int jb = min(kNb, k - J0), J1 = J0 + jb;
+        // (a) diagonal block: factor, then invert, in the registers of wave 0
+        if (tid < 64) {
+            const int c = lane;
+            double col[kNb];
+#pragma unroll
+            for (int r = 0; r < kNb; ++r)
+                col[r] = (c < jb && r <= c) ? R[(long)(J0 + r) * k + J0 + c] : 0.0;
+            unsigned int deadmask = 0;
+            double ipc[kNb];  // 1 / R[j][j] (0 when dropped), the same in every lane
+#pragma unroll
+            for (int j = 0; j < kNb; ++j) {
+                ipc[j] = 0.0;
+                if (j < jb) {
+                    const double d = readlane_d(col[j], j);
+                    const bool dj = !(d > tol);
+                    const double piv = dj ? 0.0 : sqrt(d);
+                    const double ip = dj ? 0.0 : 1.0 / piv;
+                    ipc[j] = ip;
+                    if (c == j) col[j] = piv;
+                    else if (c > j) col[j] *= ip;
+                    deadmask |= dj ? (1u << j) : 0u;
+#pragma unroll
+                    for (int a = j + 1; a < kNb; ++a) {
+                        const double rja = readlane_d(col[j], a);
+                        if (c >= a) col[a] -= rja * col[j];
+                    }
                 }
-                for (; l < j; ++l) s0 += ri[l] * colj[l];
-                R[i * k + j] = -inv * ((s0 + s1) + (s2 + s3));
             }
-            if (tid == 0) R[j * k + j] = inv;
+            // row i = lane of X_JJ: X[i][c] = (delta_ic - sum_{l<c} X[i][l] R[l][c]) / R[c][c]
+            double x[kNb];
+#pragma unroll
+            for (int cc = 0; cc < kNb; ++cc) {
+                double s0 = (lane == cc) ? 1.0 : 0.0, s1 = 0.0;
+#pragma unroll
+                for (int l = 0; l < cc; ++l) {
+                    const double rlc = readlane_d(col[l], cc);
+                    if (l & 1) s1 -= x[l] * rlc;
+                    else s0 -= x[l] * rlc;
+                }
+                x[cc] = (cc >= jb || lane > cc) ? 0.0 : (s0 + s1) * ipc[cc];
+            }
+            if (lane < jb) {
+                dead_s[J0 + lane] = (deadmask >> lane) & 1u;
+#pragma unroll
+                for (int cc = 0; cc < kNb; ++cc)
+                    if (cc >= lane && cc < jb) R[(long)(J0 + lane) * k + J0 + cc] = x[cc];
+            }
+        }
+        __syncthreads();
+        // (b) panel rows of R and T = X[:J0, :J0] R[:J0, J]
+        const int npanel = k - J1;
+        const int ntile = ((J0 + 3) / 4) * (kNb / 4);
+        for (int t = tid; t < npanel + ntile; t += 256) {
+            if (t < npanel) {
+                const int c = J1 + t;
+                double g[kNb];
+#pragma unroll
+                for (int i = 0; i < kNb; ++i) g[i] = (i < jb) ? R[(long)(J0 + i) * k + c] : 0.0;
+#pragma unroll
+                for (int j = 0; j < kNb; ++j) {
+                    if (j < jb) {
+                        double sacc = 0.0;
+#pragma unroll
+                        for (int i = 0; i <= j; ++i) sacc += R[(long)(J0 + i) * k + J0 + j] * g[i];
+                        R[(long)(J0 + j) * k + c] = sacc;
+                    }
+                }
+            } else {
+                const int u = t - npanel;
+                const int i0 = 4 * (u / (kNb / 4)), c0 = 4 * (u % (kNb / 4));
+                double acc[4][4] = {};
+                for (int L = i0; L < J0; ++L) {
+                    double xv[4], rv[4];
+#pragma unroll
+                    for (int p = 0; p < 4; ++p)
+                        xv[p] = (i0 + p <= L) ? R[(long)(i0 + p) * k + L] : 0.0;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        rv[q] = (c0 + q < jb) ? R[(long)L * k + J0 + c0 + q] : 0.0;
+#pragma unroll
+                    for (int p = 0; p < 4; ++p)
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) acc[p][q] += xv[p] * rv[q];
+                }
+#pragma unroll
+                for (int p = 0; p < 4; ++p)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        if (i0 + p < J0) Tb[(i0 + p) * kNb + c0 + q] = acc[p][q];
+            }
+        }
+        __syncthreads();
+        // (c) trailing update (4 x 4 register tiles) and X[:J0, J] = -T X_JJ
+        const int m = k - J1, T4 = (m + 3) / 4;
+        const int nupd = T4 * T4, nx = J0 * jb;
+        for (int t = tid; t < nupd + nx; t += 256) {
+            if (t < nupd) {
+                const int ta = t / T4, tc = t - (t / T4) * T4;
+                if (ta > tc) continue;
+                const int a0 = J1 + 4 * ta, c0 = J1 + 4 * tc;
+                double acc[4][4] = {};
+                for (int j = 0; j < jb; ++j) {
+                    const double* rj = R + (long)(J0 + j) * k;
+                    double ra[4], rc[4];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        ra[q] = (a0 + q < k) ? rj[a0 + q] : 0.0;
+                        rc[q] = (c0 + q < k) ? rj[c0 + q] : 0.0;
+                    }
+#pragma unroll
+                    for (int p = 0; p < 4; ++p)
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) acc[p][q] += ra[p] * rc[q];
+                }
+#pragma unroll
+                for (int p = 0; p < 4; ++p)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        if (a0 + p < k && c0 + q < k) R[(long)(a0 + p) * k + c0 + q] -= acc[p][q];
+            } else {
+                const int u = t - nupd;
+                const int i = u / jb, jj = u - (u / jb) * jb;
+                double sacc = 0.0;
+                for (int l = 0; l <= jj; ++l) sacc += Tb[i * kNb + l] * R[(long)(J0 + l) * k + J0 + jj];
+                R[(long)i * k + J0 + jj] = -sacc;
+            }
         }
         __syncthreads();
     }
-    for (int e = tid; e < k * k; e += nt) {
-        const int i = e / k, c = e % k;
-        Xb[e] = (c >= i && !dead_s[i]) ? R[e] : 0.0;
+    for (int e = tid; e < k * k; e += 256) {
+        const int i = e / k, c = e - (e / k) * k;
+        out[e] = (c >= i && !dead_s[i]) ? R[e] : 0.0;
     }
     if (dead) {
-        for (int j = tid; j < k; j += nt) dead[(long)b * k + j] = dead_s[j];
+        for (int j = tid; j < k; j += 256) dead[(long)b * k + j] = dead_s[j];
         if (tid == 0) {
-            int c = 0;
-            for (int j = 0; j < k; ++j) c += dead_s[j];
-            dead[(long)gridDim.x * k + b] = c;
+            int cnt = 0;
+            for (int j = 0; j < k; ++j) cnt += dead_s[j];
+            dead[(long)gridDim.x * k + b] = cnt;
         }
     }
+}
+
+static size_t chol_lds_bytes(int k, bool in_lds) {
+    return ((in_lds ? (size_t)k * k : 0) + (size_t)k * kNb) * sizeof(double);
 }
 
 void chol_inverse(hipStream_t s, int batch, int k, const double* G, double* Rinv, double tol,
                   int* dead) {
     if (batch <= 0) return;
-    IPEPS_REQUIRE(k <= 128, IPEPS_EINVAL, "chol_inverse: k > 128");
-    const size_t lds = (size_t)k * k * sizeof(double);
+    IPEPS_REQUIRE(k >= 1 && k <= 256, IPEPS_EINVAL, "chol_inverse: k must be in 1..256");
+    const bool in_lds = k <= 128;
+    const size_t lds = chol_lds_bytes(k, in_lds);
     static bool attr_set = false;
     if (!attr_set) {
-        HIP_CHECK(hipFuncSetAttribute((const void*)k_chol_inverse,
+        HIP_CHECK(hipFuncSetAttribute((const void*)k_chol_inverse<true>,
                                       hipFuncAttributeMaxDynamicSharedMemorySize,
-                                      128 * 128 * (int)sizeof(double)));
+                                      (int)chol_lds_bytes(128, true)));
+        HIP_CHECK(hipFuncSetAttribute((const void*)k_chol_inverse<false>,
+                                      hipFuncAttributeMaxDynamicSharedMemorySize,
+                                      (int)chol_lds_bytes(256, false)));
         attr_set = true;
     }
-    hipLaunchKernelGGL(k_chol_inverse, dim3(batch), dim3(256), lds, s, k, G, Rinv, tol, dead);
+    if (in_lds)
+        hipLaunchKernelGGL(k_chol_inverse<true>, dim3(batch), dim3(256), lds, s, k, G, Rinv, tol, dead);
+    else
+        hipLaunchKernelGGL(k_chol_inverse<false>, dim3(batch), dim3(256), lds, s, k, G, Rinv, tol, dead);
     HIP_CHECK(hipGetLastError());
 }
 
