@@ -182,7 +182,7 @@ def main():
                    "D": D, "chi": chi, "d": 4, "t_end": obs["t"]},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak, "traffic": None,
-                     "kernel": "k_gemm_grouped<...,TAG=1> (4 half-system n^3 products)",
+                     "kernel": "k_gemm_direct<...,TAG=1> (4 half-system n^3 products)",
                      "launch_ms": ms_tot / max(1, launches), "flops_per_launch": fl},
         "step_mfma_frac": step_flops(D, chi) / (ms_per_step * 1e-3) / (peak * 1e12),
     }

@@ -13,6 +13,8 @@
 // result register r of lane l is row l / 16 + 4 r, column l % 16.
 #include "gemm.h"
 
+#include <cstdint>
+
 namespace ipeps {
 
 typedef double d4_t __attribute__((ext_vector_type(4)));
@@ -237,7 +239,7 @@ GemmProb gemm_nn(const void* A, long lda, const void* B, long ldb, void* C, long
 
 static void tile_dims(int dtype, GemmTile tile, int* bm, int* bn) {
     (void)dtype;
-    if (tile == TILE_LARGE) {
+    if (tile == TILE_LARGE || tile == TILE_DIRECT) {
         *bm = 128;
         *bn = 128;
     } else {
@@ -258,6 +260,17 @@ int gemm_plan_tiles(GemmProb* probs, int n, int dtype, GemmTile* tile) {
         large_tiles += (long)ceil_div(probs[i].M, 128) * ceil_div(probs[i].N, 128) * ks;
     }
     *tile = (small_work * 4 > all_work || large_tiles < 512) ? TILE_SMALL : TILE_LARGE;
+    if (*tile == TILE_LARGE) {
+        const long vw = dtype == IPEPS_DTYPE_FP64 ? 2 : 4;
+        bool direct = true;
+        for (int i = 0; i < n && direct; ++i) {
+            const GemmProb& p = probs[i];
+            direct = p.a_ks == 1 && p.a_rs0 % vw == 0 && p.a_rs1 % vw == 0 && p.K % vw == 0 &&
+                     p.K >= vw && ((uintptr_t)p.A & 15) == 0 && p.b_cs == 1 && p.b_ks % vw == 0 &&
+                     p.N % vw == 0 && p.N >= vw && ((uintptr_t)p.B & 15) == 0;
+        }
+        if (direct) *tile = TILE_DIRECT;
+    }
     int bm, bn;
     tile_dims(dtype, *tile, &bm, &bn);
     int total = 0;
@@ -271,6 +284,221 @@ int gemm_plan_tiles(GemmProb* probs, int n, int dtype, GemmTile* tile) {
     }
     return total;
 }
+
+// ---------------------------------------------------------------------------
+template <typename T>
+struct Vec16;
+template <>
+struct Vec16<float> { typedef float v_t __attribute__((ext_vector_type(4))); };
+template <>
+struct Vec16<double> { typedef double v_t __attribute__((ext_vector_type(2))); };
+
+// Direct kernel: operand tiles copied global -> LDS by 16-byte LDS-DMA loads
+// (no register staging) through an NS-stage ring, one barrier per k tile, and
+// an XCD-aware tile order (workgroup b runs on XCD b % 8; each XCD gets a
+// contiguous range of tiles so neighbouring tiles share its L2).
+// A (k contiguous) is stored [m][k] with the 16-byte chunk index XOR-swizzled
+// by the row, read as 16-byte vectors (k order inside a tile permuted alike
+// for A and B); B (n contiguous) is stored [k][n] with chunks swizzled by the
+// lane group that reads the row, read as scalars.
+__device__ inline void wait_vm(int n) {
+    // s_waitcnt vmcnt(n) (gfx9 encoding: vmcnt[3:0] and [15:14]; expcnt and
+    // lgkmcnt left at their maxima so they impose no wait)
+    switch (n) {
+        case 0: __builtin_amdgcn_s_waitcnt(0 | (7 << 4) | (15 << 8)); break;
+        case 8: __builtin_amdgcn_s_waitcnt(8 | (7 << 4) | (15 << 8)); break;
+        case 16: __builtin_amdgcn_s_waitcnt(0 | (1 << 14) | (7 << 4) | (15 << 8)); break;
+        default: __builtin_amdgcn_s_waitcnt(8 | (1 << 14) | (7 << 4) | (15 << 8)); break;
+    }
+}
+
+template <typename T, int BM, int BN, int BK, int NS, int TAG>
+__global__ __launch_bounds__(256) void k_gemm_direct(const GemmProb* __restrict__ probs, int nprob) {
+    constexpr int VW = 16 / (int)sizeof(T);
+    constexpr int WM = BM / 2, WN = BN / 2;
+    constexpr int FM = WM / 16, FN = WN / 16;
+    constexpr int KPL = BK / 4;
+    constexpr int NCH = KPL / VW;
+    constexpr int ACH = BK / VW;              // 16-byte chunks per A row (8)
+    constexpr int BCH = BN / VW;              // 16-byte chunks per B row
+    constexpr int BSW = (BCH / 4) < 8 ? (BCH / 4) : 8;  // B swizzle step per lane group
+    constexpr int ASZ = BM * BK, BSZ = BK * BN;
+    constexpr int NLD = (BM * ACH) / 256;     // A loads per lane per tile (= B loads)
+    static_assert(BM * ACH == BK * BCH, "A and B tiles must need the same number of loads");
+    typedef typename Vec16<T>::v_t v_t;
+    __shared__ __attribute__((aligned(16))) T Sm[NS * (ASZ + BSZ)];
+
+    const int G = gridDim.x;
+    const int xcd = blockIdx.x & 7, idx = blockIdx.x >> 3;
+    const int per = G >> 3, rem = G & 7;
+    const int bid = xcd * per + (xcd < rem ? xcd : rem) + idx;
+    int p = 0;
+    while (p + 1 < nprob && probs[p + 1].tile_begin <= bid) ++p;
+    const GemmProb& P = probs[p];
+    if (P.gate && *P.gate == 0) return;
+    const int ks = P.ksplit > 1 ? P.ksplit : 1;
+    const int tt = bid - P.tile_begin;
+    const int split = tt % ks, t = tt / ks;
+    const int tm = t / P.tiles_n, tn = t - (t / P.tiles_n) * P.tiles_n;
+    const int M = P.M, N = P.N;
+    const int kchunk = ((P.K + ks - 1) / ks + BK - 1) / BK * BK;
+    const int kbeg = split * kchunk;
+    const int K = (kbeg + kchunk < P.K) ? kbeg + kchunk : P.K;
+    const int m0 = tm * BM, n0 = tn * BN;
+    const T* __restrict__ A = (const T*)P.A;
+    const T* __restrict__ B = (const T*)P.B;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+
+    // per-lane source offsets (fixed across k tiles)
+    long a_src[NLD];
+    int a_lk[NLD];
+#pragma unroll
+    for (int r = 0; r < NLD; ++r) {
+        const int row = (r * 4 + wave) * (64 / ACH) + lane / ACH;
+        const int lchunk = (lane % ACH) ^ (row & 7);
+        int i = m0 + row;
+        i = i < M ? i : M - 1;
+        a_src[r] = (long)(i / P.a_rows0) * P.a_rs1 + (long)(i % P.a_rows0) * P.a_rs0;
+        a_lk[r] = lchunk * VW;
+    }
+    int b_k[NLD], b_n[NLD];
+#pragma unroll
+    for (int r = 0; r < NLD; ++r) {
+        const int c = (r * 4 + wave) * 64 + lane;
+        const int k = c / BCH, pch = c % BCH;
+        const int lchunk = pch ^ (((k / KPL) & 3) * BSW);
+        int n = n0 + lchunk * VW;
+        n = n < N ? n : N - VW;
+        b_k[r] = k;
+        b_n[r] = n;
+    }
+    auto issue = [&](int kt, int stg) {
+        const int k0 = kbeg + kt * BK;
+        T* as = Sm + stg * (ASZ + BSZ);
+        T* bs = as + ASZ;
+#pragma unroll
+        for (int r = 0; r < NLD; ++r) {
+            int k = k0 + a_lk[r];
+            k = k < K ? k : K - VW;
+            __builtin_amdgcn_global_load_lds((const void*)(A + a_src[r] + k),
+                                             (__attribute__((address_space(3))) void*)(as + (r * 4 + wave) * 64 * VW),
+                                             16, 0, 0);
+        }
+#pragma unroll
+        for (int r = 0; r < NLD; ++r) {
+            int k = k0 + b_k[r];
+            k = k < K ? k : K - 1;
+            __builtin_amdgcn_global_load_lds((const void*)(B + (long)k * P.b_ks + b_n[r]),
+                                             (__attribute__((address_space(3))) void*)(bs + (r * 4 + wave) * 64 * VW),
+                                             16, 0, 0);
+        }
+    };
+
+    const int wm0 = (wave >> 1) * WM, wn0 = (wave & 1) * WN;
+    const int lg = lane >> 4, l16 = lane & 15;
+    typedef typename Mfma<T>::acc_t acc_t;
+    acc_t acc[FM][FN];
+#pragma unroll
+    for (int a = 0; a < FM; ++a)
+#pragma unroll
+        for (int b = 0; b < FN; ++b) acc[a][b] = acc_t{0, 0, 0, 0};
+
+    const int nk = K > kbeg ? (K - kbeg + BK - 1) / BK : 0;
+#pragma unroll
+    for (int s = 0; s < NS - 1; ++s)
+        if (s < nk) issue(s, s);
+    for (int kt = 0; kt < nk; ++kt) {
+        const int ahead = nk - 1 - kt;  // tiles issued after this one
+        wait_vm(NLD * 2 * (ahead < NS - 2 ? ahead : NS - 2));
+        const int stg = kt % NS;
+        T* as = Sm + stg * (ASZ + BSZ);
+        const T* bs = as + ASZ;
+        const int k0 = kbeg + kt * BK;
+        if (k0 + BK > K) {
+            // tail tile: zero the A chunks of this lane that lie beyond K
+#pragma unroll
+            for (int r = 0; r < NLD; ++r)
+                if (k0 + a_lk[r] >= K) {
+                    v_t z = {};
+                    *(v_t*)(as + (r * 4 + wave) * 64 * VW + lane * VW) = z;
+                }
+        }
+        // plain s_barrier: the LDS-DMA loads this lane waited for above are in
+        // LDS; a full __syncthreads fence would also drain the loads of the
+        // stages still in flight
+        __builtin_amdgcn_s_waitcnt((15 & 15) | (3 << 14) | (7 << 4) | (0 << 8));  // lgkmcnt(0)
+        __builtin_amdgcn_s_barrier();
+        if (kt + NS - 1 < nk) issue(kt + NS - 1, (kt + NS - 1) % NS);
+#pragma unroll
+        for (int ch = 0; ch < NCH; ++ch) {
+            v_t fa[FM];
+            T fb[FN][VW];
+#pragma unroll
+            for (int a = 0; a < FM; ++a) {
+                const int row = wm0 + a * 16 + l16;
+                const int pc = (lg * NCH + ch) ^ (row & 7);
+                fa[a] = *(const v_t*)(as + row * BK + pc * VW);
+            }
+#pragma unroll
+            for (int tq = 0; tq < VW; ++tq) {
+                const int k = lg * KPL + ch * VW + tq;
+                const int sw = ((k / KPL) & 3) * BSW;
+#pragma unroll
+                for (int b = 0; b < FN; ++b) {
+                    const int n = wn0 + b * 16 + l16;
+                    fb[b][tq] = bs[k * BN + (((n / VW) ^ sw) * VW) + (n % VW)];
+                }
+            }
+#pragma unroll
+            for (int tq = 0; tq < VW; ++tq)
+#pragma unroll
+                for (int a = 0; a < FM; ++a)
+#pragma unroll
+                    for (int b = 0; b < FN; ++b)
+                        acc[a][b] = Mfma<T>::step(fa[a][tq], fb[b][tq], acc[a][b]);
+        }
+    }
+
+    // ---- epilogue
+    const T alpha = (T)P.alpha, beta = (T)P.beta;
+    if (ks > 1) {
+        T* __restrict__ W = (T*)P.ws + (long)split * M * N;
+#pragma unroll
+        for (int b = 0; b < FN; ++b) {
+            const int j = n0 + wn0 + b * 16 + l16;
+            if (j >= N) continue;
+#pragma unroll
+            for (int a = 0; a < FM; ++a)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int i = m0 + wm0 + a * 16 + Mfma<T>::row(lane, r);
+                    if (i < M) W[(long)i * N + j] = alpha * acc[a][b][r];
+                }
+        }
+        return;
+    }
+    T* __restrict__ C = (T*)P.C;
+#pragma unroll
+    for (int b = 0; b < FN; ++b) {
+        const int j = n0 + wn0 + b * 16 + l16;
+        if (j >= N) continue;
+        const long cj = (long)(j / P.c_cols0) * P.c_cs1 + (long)(j % P.c_cols0) * P.c_cs0;
+#pragma unroll
+        for (int a = 0; a < FM; ++a) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = m0 + wm0 + a * 16 + Mfma<T>::row(lane, r);
+                if (i >= M) continue;
+                const long off =
+                    (long)(i / P.c_rows0) * P.c_rs1 + (long)(i % P.c_rows0) * P.c_rs0 + cj;
+                T v = alpha * acc[a][b][r];
+                if (beta != T(0)) v += beta * C[off];
+                C[off] = v;
+            }
+        }
+    }
+}
+
 
 // C = sum over splits (fixed order) + beta C, with C's two-level indexing.
 template <typename T>
@@ -296,6 +524,15 @@ template <int TAG>
 static void launch_tagged(hipStream_t stream, int dtype, GemmTile tile, const GemmProb* d_probs,
                           int nprob, dim3 grid) {
     dim3 block(256);
+    if (tile == TILE_DIRECT) {
+        if (dtype == IPEPS_DTYPE_FP64)
+            hipLaunchKernelGGL((k_gemm_direct<double, 128, 128, 16, 2, TAG>), grid, block, 0, stream,
+                               d_probs, nprob);
+        else
+            hipLaunchKernelGGL((k_gemm_direct<float, 128, 128, 32, 2, TAG>), grid, block, 0, stream,
+                               d_probs, nprob);
+        return;
+    }
     if (dtype == IPEPS_DTYPE_FP64) {
         if (tile == TILE_LARGE)
             hipLaunchKernelGGL((k_gemm_grouped<double, 128, 128, 16, TAG>), grid, block, 0, stream,
