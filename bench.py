@@ -8,12 +8,18 @@ site occupations and the imbalance.  Workload: D=6, chi=72, d=4 (binary
 disorder), J=1, V=1, W=8, dt=0.05, synthetic Néel ⊗ |+> start; the state is
 first evolved (untimed) to t = 1 so that every bond carries D singular values.
 
+Default precision: CTMRG contractions in FP32 on MFMA, the simple update,
+projector SVDs and normalisations in FP64 (--dtype fp64 runs everything in
+FP64; with FP32 the FP64 path is also timed and reported as fp64_path).
+
 Prints one JSON line.  The roofline entry is for the dominant kernel (the
-grouped GEMM of the four n^3 half-system products of a column step, n =
-chi D^2): algorithmic flops per launch / mean launch time from HIP events on
-the library's stream during the timed steps.  cpu_baseline is the oracle
-(complex128 NumPy) timed on a bounded sample of the same step and scaled to
-steps/s.
+GEMM of the four n^3 half-system products of a column step, n = chi D^2):
+algorithmic flops per launch / mean launch time from HIP events on the
+library's stream during the timed steps.  serving runs a bounded sample of
+the request stream in the chosen precision and in FP64 and reports jobs/s,
+p50/p99 latency and the largest imbalance difference between the two.
+cpu_baseline is the oracle (complex128 NumPy) timed on a bounded sample of
+the same step and scaled to steps/s.
 """
 import argparse
 import json
@@ -25,6 +31,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}
+# HBM bytes per launch of the cut-product GEMM (FETCH_SIZE + WRITE_SIZE, scaled
+# by a 256 MiB copy), profiles/traffic_cut_products_D6_chi72_fp32.md; valid
+# only for the GEMM source they were measured on.
+TRAFFIC = {"fp32": {"gemm_sha256_16": "fa839cc0fd43cb71", "bytes_per_launch": 1.784e9}}
 DTYPE_NAME = {"fp64": "f64", "fp32": "f32", "bf16": "bf16"}
 METRIC = "Trotter+CTMRG steps/s at D=6,χ=72 (MFMA % peak); batched jobs/s, p50/p99 latency"
 
@@ -102,10 +112,14 @@ def serving_sample(P, synthetic, dtype, n_req=16, rate=8.0, d_max=4, steps_max=4
         ids.append((srv.submit(cfg, n_steps=min(r["n_steps"], steps_max),
                                observe_every=r["observe_every"], ctm_iters=r["ctm_iters"]),
                     r["arrival"]))
-    lat, t_last = [], 0.0
+    lat, t_last, series = [], 0.0, []
     for jid, arr in ids:
-        while srv.poll(jid)[1] is None:
+        while True:
+            res = srv.poll(jid)[1]
+            if res is not None:
+                break
             time.sleep(0.002)
+        series.append([o["imbalance"] for o in res])
         rc, (ts, ta, td) = srv.times(jid)
         lat.append(td - ts)
         t_last = max(t_last, td)
@@ -116,7 +130,43 @@ def serving_sample(P, synthetic, dtype, n_req=16, rate=8.0, d_max=4, steps_max=4
     return {"jobs_per_s": len(ids) / (t_last - t_first), "p50_s": pct(0.5), "p99_s": pct(0.99),
             "requests": len(ids), "rate_per_s": rate, "slots": 4, "dtype": dtype,
             "sample": f"first {n_req} requests of the serving stream, D capped at {d_max}, "
-                      f"steps at {steps_max}, observe every 10 with 10 warm CTMRG iterations"}
+                      f"steps at {steps_max}, observe every 10 with 10 warm CTMRG iterations"}, series
+
+
+def headline(P, torch, wl, dtype, steps, warmup, prelude):
+    """Time `steps` steps (after `warmup`) of the headline workload; the state
+    is first evolved for `prelude` Trotter steps and 10 cold CTMRG iterations."""
+    stream = torch.cuda.Stream()
+    cfg = P.make_config(wl["D"], wl["chi"], J=wl["J"], V=wl["V"], W=wl["W"], dt=wl["dt"], dtype=dtype)
+    st = P.State(cfg, stream=stream)
+    st.trotter_step(prelude)
+    st.ctmrg(0.0, 10, True)
+
+    def one_step():
+        # CTMRG of the current state and the next Trotter step are enqueued
+        # back to back: the simple update (its own stream) overlaps the CTMRG
+        st.ctmrg(0.0, 1, False, want_delta=False)
+        st.trotter_step(1)
+        return st.observe()
+
+    for _ in range(warmup):
+        one_step()
+    stream.synchronize()
+    torch.cuda.synchronize()
+    st.profile(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        obs = one_step()
+    stream.synchronize()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms_tot, launches, fl = st.profile_read()
+    st.profile(False)
+    st.close()
+    launch_ms = ms_tot / max(1, launches)
+    return {"value": steps / dt, "ms_per_step": 1e3 * dt / steps, "t_end": obs["t"],
+            "achieved": fl / (launch_ms * 1e-3) / 1e12 if launches else 0.0,
+            "launch_ms": launch_ms, "flops": fl}
 
 
 def main():
@@ -124,10 +174,15 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--dtype", default="fp64", choices=["fp64", "fp32"])
+    ap.add_argument("--dtype", default="fp32", choices=["fp64", "fp32"],
+                    help="CTMRG contraction precision (SVDs, simple update and norms stay FP64)")
+    ap.add_argument("--no-fp64-ref", action="store_true",
+                    help="skip the FP64 comparison run (headline and serving)")
     ap.add_argument("--prelude", type=int, default=20, help="untimed Trotter steps first")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="also copy MIB MiB device to device once (reference kernel for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs one GPU only (the path has no multi-GPU mode); got --gpus {args.gpus}",
@@ -142,53 +197,49 @@ def main():
     wl = synthetic.headline_config()
     D, chi = wl["D"], wl["chi"]
     torch.cuda.init()
-    stream = torch.cuda.Stream()
-    cfg = P.make_config(D, chi, J=wl["J"], V=wl["V"], W=wl["W"], dt=wl["dt"], dtype=args.dtype)
-    st = P.State(cfg, stream=stream)
-    st.trotter_step(args.prelude)
-    st.ctmrg(0.0, 10, True)
-
-    def one_step():
-        # CTMRG of the current state and the next Trotter step are enqueued
-        # back to back: the simple update (its own stream) overlaps the CTMRG
-        st.ctmrg(0.0, 1, False, want_delta=False)
-        st.trotter_step(1)
-        return st.observe()
-
-    for _ in range(args.warmup):
-        one_step()
-    stream.synchronize()
-    torch.cuda.synchronize()
-    st.profile(True)
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        obs = one_step()
-    stream.synchronize()
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    ms_tot, launches, fl = st.profile_read()
-    st.profile(False)
-    ms_per_step = 1e3 * dt / args.steps
-    value = args.steps / dt
-    achieved = fl / (ms_tot / launches * 1e-3) / 1e12 if launches else 0.0
+    rec = headline(P, torch, wl, args.dtype, args.steps, args.warmup, args.prelude)
     peak = PEAK_TFLOPS[args.dtype]
+    traffic = None
+    tr = TRAFFIC.get(args.dtype)
+    if tr:
+        import hashlib
+        src = os.path.join(ROOT, "paper_1910_11359_amd", "csrc", "gemm.hip")
+        with open(src, "rb") as f:
+            if hashlib.sha256(f.read()).hexdigest()[:16] == tr["gemm_sha256_16"]:
+                traffic = tr["bytes_per_launch"]
     out = {
-        "metric": METRIC, "value": value, "unit": "steps/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
+        "metric": METRIC, "value": rec["value"], "unit": "steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": rec["ms_per_step"], "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": DTYPE_NAME[args.dtype],
         "data": "synthetic",
         "config": {"workload": f"headline iPEPS step: D={D}, chi={chi}, d=4, J=1, V={wl['V']}, "
                                f"W={wl['W']}, dt={wl['dt']}, after {args.prelude} prelude steps",
-                   "D": D, "chi": chi, "d": 4, "t_end": obs["t"]},
-        "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": None,
+                   "D": D, "chi": chi, "d": 4, "t_end": rec["t_end"],
+                   "contractions": args.dtype, "svd_su_norms": "fp64"},
+        "roofline": {"bound": "mfma", "achieved": rec["achieved"], "peak": peak, "unit": "TFLOP/s",
+                     "frac": rec["achieved"] / peak, "traffic": traffic,
                      "kernel": "k_gemm_direct<...,TAG=1> (4 half-system n^3 products)",
-                     "launch_ms": ms_tot / max(1, launches), "flops_per_launch": fl},
-        "step_mfma_frac": step_flops(D, chi) / (ms_per_step * 1e-3) / (peak * 1e12),
+                     "launch_ms": rec["launch_ms"], "flops_per_launch": rec["flops"]},
+        "step_mfma_frac": step_flops(D, chi) / (rec["ms_per_step"] * 1e-3) / (peak * 1e12),
     }
-    st.close()
+    if args.dtype != "fp64" and not args.no_fp64_ref:
+        r64 = headline(P, torch, wl, "fp64", args.steps, args.warmup, args.prelude)
+        out["fp64_path"] = {"value": r64["value"], "ms_per_step": r64["ms_per_step"],
+                            "roofline_frac": r64["achieved"] / PEAK_TFLOPS["fp64"]}
+    if args.copy_probe > 0:
+        src = torch.empty(args.copy_probe << 18, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_probe_bytes"] = 2 * src.numel() * 4
     if not args.no_serving:
-        out["serving"] = serving_sample(P, synthetic, args.dtype)
+        srv, ser = serving_sample(P, synthetic, args.dtype)
+        out["serving"] = srv
+        if args.dtype != "fp64":
+            srv64, ser64 = serving_sample(P, synthetic, "fp64")
+            err = max(abs(a - b) for x, y in zip(ser, ser64) for a, b in zip(x, y))
+            out["serving"]["fp64_jobs_per_s"] = srv64["jobs_per_s"]
+            out["serving"]["max_imbalance_err_vs_fp64"] = err
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(D, chi, wl["W"], wl["V"])
     print(json.dumps(out), flush=True)
