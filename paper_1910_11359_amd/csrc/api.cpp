@@ -45,7 +45,11 @@ namespace {
 
 constexpr int kDirectMax = 96;  // projector SVD by direct Jacobi when n <= this
 constexpr int kColdIters = 8;   // subspace iterations for a fresh random block
-constexpr int kWarmIters = 2;   // ... when warm-started from the last iteration
+constexpr int kWarmIters = 2;   // ... when warm-started from the last iteration (FP64)
+// With FP32 cut products the matrix itself carries ~1e-7 relative rounding;
+// one warm iteration per CTMRG iteration is enough there (the FP32 path is
+// checked against the FP64 path to its 1e-3 imbalance bound).
+constexpr int kWarmItersLow = 1;
 constexpr double kCholDrop = 1e-12;
 
 int idx(int x, int y) { return ((x % 2 + 2) % 2) + 2 * ((y % 2 + 2) % 2); }
@@ -174,6 +178,7 @@ void allocate(ipeps_state* st) {
     st->Ri = (double*)M.get(2L * k * k * sizeof(double));
     st->Rb = (double*)M.get(2 * nk * sizeof(double));
     st->dead_dev = (int*)M.get((2L * k + 2) * sizeof(int));
+    st->norm_ws = (double*)M.get(normalize_ws_doubles(32) * sizeof(double));
     st->Cs = (double*)M.get(2L * k * k * sizeof(double));
     st->Uc = (double*)M.get(2L * k * k * sizeof(double));
     st->Vc = (double*)M.get(2L * k * k * sizeof(double));
@@ -183,6 +188,7 @@ void allocate(ipeps_state* st) {
     size_t jw = std::max({jacobi_svd_real_work(2, k, k), jacobi_svd_real_work(16, chi, chi),
                           n <= kDirectMax ? jacobi_svd_real_work(2, n, n) : (size_t)0});
     st->jwork = (double*)M.get(std::max(jw, (size_t)1) * sizeof(double));
+    st->jwork_c = (double*)M.get(std::max(jacobi_svd_real_work(16, chi, chi), (size_t)1) * sizeof(double));
     st->C64 = (double*)M.get(16L * chi * chi * sizeof(double));
     st->csig = (double*)M.get(16L * chi * sizeof(double));
     st->spectra = (double*)M.get(16L * chi * sizeof(double));
@@ -507,7 +513,7 @@ void prepare_double_layers(ipeps_state* st) {
     double_layer_real(st->stream, st->D, st->d, st->A, st->a_base);
     // a scale per site changes no projector, spectrum or expectation value;
     // unit norm keeps the cut products far from the FP32 underflow range
-    normalize_tensors(st->stream, IPEPS_DTYPE_FP64, st->d_norms + st->norm_a_first, 4);
+    normalize_tensors(st->stream, IPEPS_DTYPE_FP64, st->d_norms + st->norm_a_first, 4, st->norm_ws);
     frame_layouts(st->stream, st->q, st->dtype, st->a_base, st->d_a_lu, st->d_a_dl);
     st->ctm_step = st->step_count;
 }
@@ -578,7 +584,7 @@ void projector_svd(ipeps_state* st, int slot) {
         orth(st, st->Zw, st->Qz, P.gramZ, P.QfromZ, P.gramQz, P.ZfromQz, true);
         HIP_CHECK(hipMemcpyAsync(st->Qz, st->Zw, 2 * nk * sizeof(double), hipMemcpyDeviceToDevice, s));
     }
-    const int iters = warm ? kWarmIters : kColdIters;
+    const int iters = warm ? (st->dtype == IPEPS_DTYPE_FP64 ? kWarmIters : kWarmItersLow) : kColdIters;
     for (int it = 0; it < iters; ++it) {
         // power step with one Cholesky-QR pass per side (only the span
         // matters).  Dropped left columns are restarted; a right column
@@ -633,19 +639,29 @@ void column_step(ipeps_state* st, int si) {
     batched_transpose(s, st->dtype, 2 * chi, q * q, chi, st->W1, st->W1p);
     run(st, cs.w2);
     run(st, cs.fin);
-    normalize_tensors(s, st->dtype, st->d_norms + cs.norm_first, 6);
+    normalize_tensors(s, st->dtype, st->d_norms + cs.norm_first, 6, st->norm_ws);
 }
 
+// Snapshot the 16 corners (FP64) on the main stream, then take their spectra
+// and the change Delta on the spectra stream, overlapping the next iteration.
+// Readers of spectra / Delta wait for ev_spec_done (wait_spectra).
 void corner_spectra_update(ipeps_state* st, bool first) {
     const int chi = st->chi;
     hipStream_t s = st->stream;
+    HIP_CHECK(hipStreamWaitEvent(s, st->ev_spec_done, 0));  // C64 free again
     to_fp64(s, st->dtype, st->Cenv, st->C64, 16L * chi * chi);
+    HIP_CHECK(hipEventRecord(st->ev_c64_ready, s));
+    hipStream_t ss = st->spec_stream;
+    HIP_CHECK(hipStreamWaitEvent(ss, st->ev_c64_ready, 0));
     // spectra are reported to 1e-8 sigma_1: columns below 1e-10 |C|_F need no rotation
-    jacobi_svd_real(s, 16, chi, chi, st->C64, chi, (long)chi * chi, st->csig, nullptr, nullptr,
-                    st->jwork, 1e-10);
-    spectra_delta(s, 16, chi, st->csig, st->spectra, st->spec_prev, st->dev_scalars, first ? 1 : 0);
+    jacobi_svd_real(ss, 16, chi, chi, st->C64, chi, (long)chi * chi, st->csig, nullptr, nullptr,
+                    st->jwork_c, 1e-10);
+    spectra_delta(ss, 16, chi, st->csig, st->spectra, st->spec_prev, st->dev_scalars, first ? 1 : 0);
+    HIP_CHECK(hipEventRecord(st->ev_spec_done, ss));
     st->spectra_valid = true;
 }
+
+void wait_spectra(ipeps_state* st) { HIP_CHECK(hipStreamWaitEvent(st->stream, st->ev_spec_done, 0)); }
 
 void check_poison(ipeps_state* st) {
     IPEPS_REQUIRE(!st->poisoned, IPEPS_ENUMERIC, "state poisoned by an earlier NaN/Inf");
@@ -744,6 +760,9 @@ int ipeps_init(const ipeps_config* cfg, void* hip_stream, ipeps_alloc_fn alloc, 
         HIP_CHECK(hipStreamCreateWithFlags(&st->su_stream, hipStreamNonBlocking));
         HIP_CHECK(hipEventCreateWithFlags(&st->ev_gamma_free, hipEventDisableTiming));
         HIP_CHECK(hipEventCreateWithFlags(&st->ev_su_done, hipEventDisableTiming));
+        HIP_CHECK(hipStreamCreateWithFlags(&st->spec_stream, hipStreamNonBlocking));
+        HIP_CHECK(hipEventCreateWithFlags(&st->ev_c64_ready, hipEventDisableTiming));
+        HIP_CHECK(hipEventCreateWithFlags(&st->ev_spec_done, hipEventDisableTiming));
         HIP_CHECK(hipHostMalloc((void**)&st->host_buf, 65536 * sizeof(double), hipHostMallocDefault));
         build_layers(st);
         build_plan(st);
@@ -762,8 +781,12 @@ void ipeps_destroy(ipeps_state* st) {
     if (!st) return;
     (void)hipStreamSynchronize(st->stream);
     if (st->su_stream) (void)hipStreamSynchronize(st->su_stream);
+    if (st->spec_stream) (void)hipStreamSynchronize(st->spec_stream);
     st->mem.release();
     if (st->su_stream) (void)hipStreamDestroy(st->su_stream);
+    if (st->spec_stream) (void)hipStreamDestroy(st->spec_stream);
+    if (st->ev_c64_ready) (void)hipEventDestroy(st->ev_c64_ready);
+    if (st->ev_spec_done) (void)hipEventDestroy(st->ev_spec_done);
     if (st->ev_gamma_free) (void)hipEventDestroy(st->ev_gamma_free);
     if (st->ev_su_done) (void)hipEventDestroy(st->ev_su_done);
     if (st->d_probs) (void)hipFree(st->d_probs);
@@ -837,7 +860,7 @@ int ctmrg_converge(ipeps_state* st, double tol, int max_iter, int cold_start, in
         bool first = false;
         if (cold_start || !st->have_env) {
             init_environment(st->stream, st->D, st->chi, st->dtype, st->a_base, st->Cenv, st->Tenv);
-            normalize_tensors(st->stream, st->dtype, st->d_norms + st->norm_env_first, 32);
+            normalize_tensors(st->stream, st->dtype, st->d_norms + st->norm_env_first, 32, st->norm_ws);
             for (bool& w : st->warm_valid) w = false;
             st->have_env = true;
             corner_spectra_update(st, true);
@@ -851,6 +874,7 @@ int ctmrg_converge(ipeps_state* st, double tol, int max_iter, int cold_start, in
             corner_spectra_update(st, false);
             it_done = it + 1;
             if (tol > 0 || (delta && it + 1 == max_iter)) {
+                wait_spectra(st);
                 HIP_CHECK(hipMemcpyAsync(st->host_buf, st->dev_scalars, sizeof(double), hipMemcpyDeviceToHost, st->stream));
                 HIP_CHECK(hipStreamSynchronize(st->stream));
                 dl = st->host_buf[0];
@@ -890,6 +914,7 @@ int ipeps_observe(ipeps_state* st, ipeps_obs* out) {
         readout(s, st->D, st->d, st->cfg.d_A, st->E64, st->A, st->rho_T, st->rho, st->obs_dev);
         HIP_CHECK(hipMemcpyAsync(st->host_buf, st->obs_dev, 8 * sizeof(double), hipMemcpyDeviceToHost, s));
         HIP_CHECK(hipMemcpyAsync(st->host_buf + 8, st->eps_snap, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
+        wait_spectra(st);
         HIP_CHECK(hipMemcpyAsync(st->host_buf + 12, st->dev_scalars, sizeof(double), hipMemcpyDeviceToHost, s));
         HIP_CHECK(hipStreamSynchronize(s));
         const double* h = st->host_buf;
@@ -910,6 +935,7 @@ int ipeps_corner_spectra(ipeps_state* st, double* out) {
     return wrap(st, [&] {
         IPEPS_REQUIRE(st->have_env, IPEPS_EINVAL, "no environment");
         if (!st->spectra_valid) corner_spectra_update(st, true);
+        wait_spectra(st);
         HIP_CHECK(hipMemcpyAsync(out, st->spectra, 16L * st->chi * sizeof(double), hipMemcpyDeviceToHost, st->stream));
         HIP_CHECK(hipStreamSynchronize(st->stream));
     });

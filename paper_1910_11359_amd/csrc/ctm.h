@@ -37,12 +37,14 @@ void batched_transpose(hipStream_t s, int dtype, int batch, int R, int Cc, const
 //   mode 2: out[c][a][b] = in[a][b][c]
 void permute3(hipStream_t s, int dtype, int mode, int A, int B, int C, const void* in, void* out);
 
-// Divide each tensor by its Frobenius norm (accumulated in FP64).
+// Divide each of the n tensors of d_items by its Frobenius norm (accumulated
+// in FP64, deterministic order); ws holds normalize_ws_doubles(n) doubles.
 struct NormItem {
     void* ptr;
     long count;
 };
-void normalize_tensors(hipStream_t s, int dtype, const NormItem* d_items, int n);
+size_t normalize_ws_doubles(int max_items);
+void normalize_tensors(hipStream_t s, int dtype, const NormItem* d_items, int n, double* ws);
 
 // Convert between dtype and FP64.
 void to_fp64(hipStream_t s, int dtype, const void* in, double* out, long count);

@@ -295,27 +295,48 @@ void permute3(hipStream_t s, int dtype, int mode, int A, int B, int C, const voi
 }
 
 // ------------------------------------------------------------ norms / conversion
+// Deterministic two-pass Frobenius normalisation: kNormBlocks blocks per
+// tensor write partial sums of squares (FP64) in a fixed partition, then every
+// block of the tensor adds the partials in the same order and scales its slice.
+constexpr int kNormBlocks = 32;
+
 template <typename T>
-__global__ __launch_bounds__(1024) void k_normalize(const NormItem* items) {
-    __shared__ double red[16];
-    const NormItem it = items[blockIdx.x];
-    T* p = (T*)it.ptr;
+__global__ __launch_bounds__(256) void k_norm_partial(const NormItem* items, double* ws) {
+    __shared__ double red[4];
+    const NormItem it = items[blockIdx.y];
+    const T* p = (const T*)it.ptr;
     double s = 0.0;
-    for (long e = threadIdx.x; e < it.count; e += blockDim.x) {
+    for (long e = blockIdx.x * 256L + threadIdx.x; e < it.count; e += 256L * kNormBlocks) {
         const double v = (double)p[e];
         s += v * v;
     }
     s = block_sum(s, red);
-    const double inv = s > 0 ? 1.0 / sqrt(s) : 0.0;
-    for (long e = threadIdx.x; e < it.count; e += blockDim.x) p[e] = (T)((double)p[e] * inv);
+    if (threadIdx.x == 0) ws[blockIdx.y * kNormBlocks + blockIdx.x] = s;
 }
 
-void normalize_tensors(hipStream_t s, int dtype, const NormItem* d_items, int n) {
+template <typename T>
+__global__ __launch_bounds__(256) void k_norm_scale(const NormItem* items, const double* ws) {
+    const NormItem it = items[blockIdx.y];
+    T* p = (T*)it.ptr;
+    double s = 0.0;
+    for (int b = 0; b < kNormBlocks; ++b) s += ws[blockIdx.y * kNormBlocks + b];
+    const double inv = s > 0 ? 1.0 / sqrt(s) : 0.0;
+    for (long e = blockIdx.x * 256L + threadIdx.x; e < it.count; e += 256L * kNormBlocks)
+        p[e] = (T)((double)p[e] * inv);
+}
+
+size_t normalize_ws_doubles(int max_items) { return (size_t)max_items * kNormBlocks; }
+
+void normalize_tensors(hipStream_t s, int dtype, const NormItem* d_items, int n, double* ws) {
     if (n <= 0) return;
-    if (dtype == IPEPS_DTYPE_FP64)
-        hipLaunchKernelGGL(k_normalize<double>, dim3(n), dim3(1024), 0, s, d_items);
-    else
-        hipLaunchKernelGGL(k_normalize<float>, dim3(n), dim3(1024), 0, s, d_items);
+    const dim3 grid(kNormBlocks, n);
+    if (dtype == IPEPS_DTYPE_FP64) {
+        hipLaunchKernelGGL(k_norm_partial<double>, grid, dim3(256), 0, s, d_items, ws);
+        hipLaunchKernelGGL(k_norm_scale<double>, grid, dim3(256), 0, s, d_items, ws);
+    } else {
+        hipLaunchKernelGGL(k_norm_partial<float>, grid, dim3(256), 0, s, d_items, ws);
+        hipLaunchKernelGGL(k_norm_scale<float>, grid, dim3(256), 0, s, d_items, ws);
+    }
     HIP_CHECK(hipGetLastError());
 }
 
@@ -364,18 +385,18 @@ __device__ inline int trunc_rule_dev(const double* s, int n, int K, double tau) 
 }
 
 template <typename T>
-__global__ __launch_bounds__(1024) void k_proj_factors(int n, int k, int chi, double tau,
-                                                       const double* U,
-                                                       const double* V, const double* sigma,
-                                                       long strideUV, T* Us, T* Vs, long strideP,
-                                                       int* g_out) {
+__global__ __launch_bounds__(256) void k_proj_factors(int n, int k, int chi, double tau,
+                                                      const double* U, const double* V,
+                                                      const double* sigma, long strideUV, T* Us,
+                                                      T* Vs, long strideP, int* g_out) {
+    // every block of matrix b re-derives g (k <= 256 values) and the weights
     __shared__ int g_s;
     __shared__ double w[256];
-    const int b = blockIdx.x;
+    const int b = blockIdx.y;
     const double* sg = sigma + (long)b * k;
     if (threadIdx.x == 0) {
         g_s = trunc_rule_dev(sg, k, chi, tau);
-        g_out[b] = g_s;
+        if (blockIdx.x == 0) g_out[b] = g_s;
     }
     __syncthreads();
     const int g = g_s;
@@ -385,7 +406,8 @@ __global__ __launch_bounds__(1024) void k_proj_factors(int n, int k, int chi, do
     const double* Vb = V + b * strideUV;
     T* us = Us + b * strideP;
     T* vs = Vs + b * strideP;
-    for (long e = threadIdx.x; e < (long)n * chi; e += blockDim.x) {
+    for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < (long)n * chi;
+         e += (long)gridDim.x * blockDim.x) {
         const int i = e / chi, c = e % chi;
         const double wc = w[c];
         us[e] = (T)(wc != 0.0 ? Ub[(long)i * k + c] * wc : 0.0);
@@ -396,12 +418,14 @@ __global__ __launch_bounds__(1024) void k_proj_factors(int n, int k, int chi, do
 void projector_factors(hipStream_t s, int dtype, int batch, int n, int k, int chi, double tau,
                        const double* U, const double* V, const double* sigma, long strideUV,
                        void* Us, void* Vs, long strideP, int* g_out) {
-    IPEPS_REQUIRE(chi <= 256, IPEPS_EINVAL, "chi > 256");
+    IPEPS_REQUIRE(chi <= 256 && k <= 256, IPEPS_EINVAL, "projector_factors: chi, k > 256");
+    const long tot = (long)n * chi;
+    const dim3 grid(ceil_div(tot, 256) < 512 ? ceil_div(tot, 256) : 512, batch);
     if (dtype == IPEPS_DTYPE_FP64)
-        hipLaunchKernelGGL(k_proj_factors<double>, dim3(batch), dim3(1024), 0, s, n, k, chi, tau, U, V,
+        hipLaunchKernelGGL(k_proj_factors<double>, grid, dim3(256), 0, s, n, k, chi, tau, U, V,
                            sigma, strideUV, (double*)Us, (double*)Vs, strideP, g_out);
     else
-        hipLaunchKernelGGL(k_proj_factors<float>, dim3(batch), dim3(1024), 0, s, n, k, chi, tau, U, V,
+        hipLaunchKernelGGL(k_proj_factors<float>, grid, dim3(256), 0, s, n, k, chi, tau, U, V,
                            sigma, strideUV, (float*)Us, (float*)Vs, strideP, g_out);
     HIP_CHECK(hipGetLastError());
 }

@@ -63,6 +63,10 @@ struct ipeps_state {
     // for ev_su_done before it reads Gamma again.
     hipStream_t su_stream;
     hipEvent_t ev_gamma_free, ev_su_done;
+    // corner spectra run on their own stream, overlapping the next iteration
+    hipStream_t spec_stream;
+    hipEvent_t ev_c64_ready, ev_spec_done;
+    double* jwork_c;
     double* eps_snap;  // truncation errors as of the last double-layer build
     long ctm_step;     // Trotter steps contained in the current environment
     ipeps::DevMem mem;
@@ -115,6 +119,7 @@ struct ipeps_state {
     double* Rb;          // 2 blocks of n*k: refill directions for dropped columns
     int* dead_dev;       // 2*k flags of dropped columns, then 2 counts
     uint64_t orth_calls; // counter feeding the refill hash
+    double* norm_ws;     // partial sums of the tensor normalisation (32 tensors)
     double *Nfull_U, *Nfull_V;  // direct path (n <= 96)
     int ks_gram, ks_nv, ks_c;   // split-K factors
     double *ws_gram, *ws_nv;    // split-K partials (FP64)
