@@ -602,7 +602,10 @@ void projector_svd(ipeps_state* st, int slot) {
     orth(st, st->Yw, st->Qw, P.gramY, P.QfromY, P.gramQ, P.YfromQ, true);
     run(st, P.NVfinal);  // Qw = N V
     run(st, P.Cs);       // Cs = Q^T N V
-    jacobi_svd_real(s, 2, k, k, st->Cs, k, (long)k * k, st->sig, st->Uc, st->Vc, st->jwork);
+    // Rayleigh-Ritz SVD.  Columns are left unrotated only below 1e-14 |Cs|_F,
+    // far under the 1e-12 sigma_1 projector cutoff: a kept direction that was
+    // never rotated against the dominant ones would break P_up P_low = 1.
+    jacobi_svd_real(s, 2, k, k, st->Cs, k, (long)k * k, st->sig, st->Uc, st->Vc, st->jwork, 1e-14);
     run(st, P.Uo);
     run(st, P.Vo);
     HIP_CHECK(hipMemcpyAsync(st->warm + 2 * slot * nk, st->Vo, 2 * nk * sizeof(double),
@@ -653,9 +656,11 @@ void corner_spectra_update(ipeps_state* st, bool first) {
     HIP_CHECK(hipEventRecord(st->ev_c64_ready, s));
     hipStream_t ss = st->spec_stream;
     HIP_CHECK(hipStreamWaitEvent(ss, st->ev_c64_ready, 0));
-    // spectra are reported to 1e-8 sigma_1: columns below 1e-10 |C|_F need no rotation
+    // spectra are reported to 1e-8 sigma_1 (FP64 corners) and carry the
+    // ~1e-7 rounding of FP32 corners: columns below 1e-10 (FP64) or 1e-8
+    // (FP32) of |C|_F need no rotation
     jacobi_svd_real(ss, 16, chi, chi, st->C64, chi, (long)chi * chi, st->csig, nullptr, nullptr,
-                    st->jwork_c, 1e-10);
+                    st->jwork_c, st->dtype == IPEPS_DTYPE_FP64 ? 1e-10 : 1e-8);
     spectra_delta(ss, 16, chi, st->csig, st->spectra, st->spec_prev, st->dev_scalars, first ? 1 : 0);
     HIP_CHECK(hipEventRecord(st->ev_spec_done, ss));
     st->spectra_valid = true;

@@ -39,7 +39,8 @@ __device__ void jacobi_sweeps(int m, int n, double* Ac, double* Vc, double* nrm,
     const int npair = ne / 2;
     const double tol = 4.0 * m * 1.11e-16, tol2 = tol * tol;
     // columns below skip_rel |A|_F are left alone: a rotation against a large
-    // column re-pollutes them at their own size
+    // column re-pollutes them at their own size; pairs whose inner product is
+    // below skip_rel^2 |A|_F^2 count as converged
     double fro = 0.0;
     for (long e = threadIdx.x; e < (long)m * n; e += blockDim.x) fro += Ac[e] * Ac[e];
     fro = block_sum(fro, red);
@@ -78,7 +79,10 @@ __device__ void jacobi_sweeps(int m, int n, double* Ac, double* Vc, double* nrm,
                 ga = group16_sum(ga);
                 const double al = nrm[p], be = nrm[q];
                 if (al <= small2 || be <= small2) continue;
-                if (ga * ga <= tol2 * al * be) continue;
+                // converged pair: relative test, or an inner product below
+                // skip_rel^2 |A|_F^2, which moves no singular value by more
+                // than ~skip_rel |A|_F
+                if (ga * ga <= tol2 * al * be || fabs(ga) <= small2) continue;
                 const double zeta = 0.5 * (be - al) * fast_rcp(ga);
                 const double az = fabs(zeta);
                 const double den = (az > 1e150) ? 2.0 * az : az + (1.0 + az * az) * fast_rsq(1.0 + az * az);
