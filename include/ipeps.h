@@ -80,7 +80,11 @@ typedef struct {
  * filling), the largest |rho_p[up,down]| (0 by particle-number
  * conservation), the accumulated local truncation error of each site (sum
  * over its bond updates of discarded squared weights / total squared
- * weights), and the CTMRG iterations / last corner-spectrum change. */
+ * weights), the CTMRG iterations / last corner-spectrum change, and the
+ * Renyi entropies S_1 = -Tr r ln r and S_1/2 = 2 ln Tr sqrt(r) of each
+ * site's physical one-site matrix r (auxiliary spin traced; maximum ln 2),
+ * the paper's monitor of how far the state is from saturation (section
+ * Results). */
 typedef struct {
     double t;
     double n[4];
@@ -90,6 +94,8 @@ typedef struct {
     double trunc_err[4];
     int ctm_iters;
     double ctm_delta;
+    double renyi1[4];
+    double renyi_half[4];
 } ipeps_obs;
 
 typedef struct ipeps_state ipeps_state;

@@ -277,9 +277,19 @@ def reduced_density_matrix(E, A):
     return rho / np.trace(rho)
 
 
+def renyi(rp):
+    """Renyi entropies S_1 = -Tr r ln r and S_1/2 = 2 ln Tr sqrt(r) of a
+    Hermitian unit-trace matrix r (section Results: entropies of the one-site
+    reduced density matrix, orders 1 and 1/2; natural log, maximum ln d_p)."""
+    lam = np.clip(np.linalg.eigvalsh(0.5 * (rp + rp.conj().T)), 0.0, None)
+    nz = lam[lam > 0]
+    return float(-(nz * np.log(nz)).sum()), float(2.0 * np.log(np.sqrt(lam).sum()))
+
+
 def observe(st, env, d_A):
-    """Occupations n(x,y) (aux traced), imbalance, sum of n, max |rho_p[up,dn]|."""
-    n = {}
+    """Occupations n(x,y) (aux traced), imbalance, sum of n, max |rho_p[up,dn]|,
+    Renyi S_1 and S_1/2 of each physical one-site matrix rho_p."""
+    n, s1, sh = {}, {}, {}
     offd = 0.0
     for site in SITES:
         A = absorb_sqrt_lambda(st, site)
@@ -287,9 +297,12 @@ def observe(st, env, d_A):
         rp = np.einsum("paqa->pq", rho.reshape(2, d_A, 2, d_A))
         n[site] = float(rp[0, 0].real)
         offd = max(offd, abs(rp[0, 1]))
+        s1[site], sh[site] = renyi(rp)
     imb = 0.5 * (n[(0, 0)] + n[(1, 1)] - n[(1, 0)] - n[(0, 1)])
     return {"n": np.array([n[s] for s in SITES]), "imbalance": imb,
-            "sum_n": float(sum(n.values())), "max_offdiag": float(offd)}
+            "sum_n": float(sum(n.values())), "max_offdiag": float(offd),
+            "renyi1": np.array([s1[s] for s in SITES]),
+            "renyi_half": np.array([sh[s] for s in SITES])}
 
 
 def double_layers(st):

@@ -70,7 +70,9 @@ def trunc_rule(s, K):
 
     Values <= 1e-12 s_1 count as zeros and are never kept; when values are
     dropped, the cut is moved down so that it never separates two values
-    whose relative gap is <= 1e-10 (a multiplet is kept or dropped whole).
+    whose gap is <= 1e-10 of the larger one plus 1e-12 s_1 (a multiplet is
+    kept or dropped whole; the absolute part makes the decision independent
+    of rounding-level splittings of small degenerate values).
     """
     s = np.asarray(s, dtype=float)
     if s.size == 0 or s[0] <= 0.0:
@@ -78,7 +80,7 @@ def trunc_rule(s, K):
     r = int(np.sum(s > SV_ZERO_REL * s[0]))
     g = min(K, r)
     if g < r:
-        while g > 1 and s[g - 1] - s[g] <= MULTIPLET_REL * s[g - 1]:
+        while g > 1 and s[g - 1] - s[g] <= MULTIPLET_REL * s[g - 1] + SV_ZERO_REL * s[0]:
             g -= 1
     return g
 

@@ -917,21 +917,25 @@ int ipeps_observe(ipeps_state* st, ipeps_obs* out) {
         run(st, st->read4);
         to_fp64(s, st->dtype, st->Eout, st->E64, 4 * q4);
         readout(s, st->D, st->d, st->cfg.d_A, st->E64, st->A, st->rho_T, st->rho, st->obs_dev);
-        HIP_CHECK(hipMemcpyAsync(st->host_buf, st->obs_dev, 8 * sizeof(double), hipMemcpyDeviceToHost, s));
-        HIP_CHECK(hipMemcpyAsync(st->host_buf + 8, st->eps_snap, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIP_CHECK(hipMemcpyAsync(st->host_buf, st->obs_dev, 16 * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIP_CHECK(hipMemcpyAsync(st->host_buf + 16, st->eps_snap, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
         wait_spectra(st);
-        HIP_CHECK(hipMemcpyAsync(st->host_buf + 12, st->dev_scalars, sizeof(double), hipMemcpyDeviceToHost, s));
+        HIP_CHECK(hipMemcpyAsync(st->host_buf + 20, st->dev_scalars, sizeof(double), hipMemcpyDeviceToHost, s));
         HIP_CHECK(hipStreamSynchronize(s));
         const double* h = st->host_buf;
-        for (int i = 0; i < 7; ++i) IPEPS_REQUIRE(std::isfinite(h[i]), IPEPS_ENUMERIC, "NaN in readout");
+        for (int i = 0; i < 16; ++i) IPEPS_REQUIRE(std::isfinite(h[i]), IPEPS_ENUMERIC, "NaN in readout");
         out->t = st->ctm_step * st->cfg.dt;
         for (int i = 0; i < 4; ++i) out->n[i] = h[i];
         out->imbalance = h[4];
         out->sum_n = h[5];
         out->max_offdiag = h[6];
-        for (int i = 0; i < 4; ++i) out->trunc_err[i] = h[8 + i];
+        for (int i = 0; i < 4; ++i) out->trunc_err[i] = h[16 + i];
         out->ctm_iters = st->last_iters;
-        out->ctm_delta = h[12];
+        out->ctm_delta = h[20];
+        for (int i = 0; i < 4; ++i) {
+            out->renyi1[i] = h[8 + i];
+            out->renyi_half[i] = h[12 + i];
+        }
     });
 }
 

@@ -69,7 +69,8 @@ void random_block(hipStream_t s, int batch, int n, int k, uint64_t seed, double*
 
 // One-site reduced density matrices from the site environments E (real
 // basis, [L][U][R][D] each q^4, FP64) and A; writes rho (4 x d x d complex,
-// trace-normalised) and obs[0..9] = n[4], imbalance, sum_n, max_offdiag.
+// trace-normalised) and obs[0..15] = n[4], imbalance, sum_n, max_offdiag, 0,
+// Renyi S_1[4], S_1/2[4] of the physical one-site matrix (natural log).
 // Twork: 4 * D^4 * d complex scratch.
 void readout(hipStream_t s, int D, int d, int d_A, const double* E, const cplx* A, cplx* Twork,
              cplx* rho, double* obs);

@@ -373,14 +373,14 @@ void from_fp64(hipStream_t s, int dtype, const double* in, void* out, long count
 
 // ------------------------------------------------------------ projector factors
 // Keep g <= K values: zeros (<= tau s_1) are dropped, and a multiplet
-// (neighbours within 100 tau relative) is never cut.
+// (neighbours whose gap is <= 1e-10 of the larger plus tau s_1) is never cut.
 __device__ inline int trunc_rule_dev(const double* s, int n, int K, double tau) {
     if (n <= 0 || !(s[0] > 0.0)) return 0;
     int r = 0;
     for (int i = 0; i < n; ++i) r += s[i] > tau * s[0];
     int g = r < K ? r : K;
     if (g < r)
-        while (g > 1 && s[g - 1] - s[g] <= 100.0 * tau * s[g - 1]) --g;
+        while (g > 1 && s[g - 1] - s[g] <= 1e-10 * s[g - 1] + tau * s[0]) --g;
     return g;
 }
 
@@ -530,7 +530,7 @@ __global__ __launch_bounds__(1024) void k_readout_finish(int D, int d, int dA, c
                                                          const cplx* __restrict__ T, cplx* rho, double* obs) {
     __shared__ double red[16];
     __shared__ cplx rs[64];
-    __shared__ double nsite[4], offd[4];
+    __shared__ double nsite[4], offd[4], s1[4], shalf[4];
     const long D4 = (long)D * D * D * D;
     for (int site = 0; site < 4; ++site) {
         const cplx* As = A + site * d * D4;
@@ -554,13 +554,27 @@ __global__ __launch_bounds__(1024) void k_readout_finish(int D, int d, int dA, c
             const double tn = cabs2(tr);
             const cplx inv = cmake(tr.re / tn, -tr.im / tn);
             for (int i = 0; i < d * d; ++i) rho[site * d * d + i] = cmul(rs[i], inv);
-            cplx p00 = cmake(0, 0), p01 = cmake(0, 0);
+            cplx p00 = cmake(0, 0), p01 = cmake(0, 0), p11 = cmake(0, 0);
             for (int a = 0; a < dA; ++a) {
                 p00 = cadd(p00, cmul(rs[(0 * dA + a) * d + (0 * dA + a)], inv));
                 p01 = cadd(p01, cmul(rs[(0 * dA + a) * d + (1 * dA + a)], inv));
+                p11 = cadd(p11, cmul(rs[(1 * dA + a) * d + (1 * dA + a)], inv));
             }
             nsite[site] = p00.re;
             offd[site] = sqrt(cabs2(p01));
+            // Renyi entropies of the physical one-site matrix rho_p (2 x 2,
+            // Hermitian, unit trace): eigenvalues (t +- r) / 2
+            const double tt = p00.re + p11.re, df = p00.re - p11.re;
+            const double r = sqrt(df * df + 4.0 * cabs2(p01));
+            double lam[2] = {0.5 * (tt + r), 0.5 * (tt - r)};
+            double e1 = 0.0, sq = 0.0;
+            for (int i = 0; i < 2; ++i) {
+                const double l = lam[i] > 0.0 ? lam[i] : 0.0;
+                if (l > 0.0) e1 -= l * log(l);
+                sq += sqrt(l);
+            }
+            s1[site] = e1;
+            shalf[site] = 2.0 * log(sq);
         }
         __syncthreads();
     }
@@ -574,6 +588,11 @@ __global__ __launch_bounds__(1024) void k_readout_finish(int D, int d, int dA, c
         obs[4] = 0.5 * (nsite[0] + nsite[3] - nsite[1] - nsite[2]);
         obs[5] = sum;
         obs[6] = mo;
+        obs[7] = 0.0;
+        for (int i = 0; i < 4; ++i) {
+            obs[8 + i] = s1[i];
+            obs[12 + i] = shalf[i];
+        }
     }
 }
 

@@ -6,7 +6,8 @@
 //   Theta'[(k_i, s_i'), (s_j', k_j)] = sum_b lambda_b sum_{s_i s_j}
 //        G[(s_i' s_j'), (s_i s_j)] R_i[k_i, (s_i, b)] R_j[k_j, (s_j, b)]
 //   Theta' = U S V^H                      one-sided (Hestenes) Jacobi, FP64
-//   keep g <= D values (zeros <= 1e-12 s_1 dropped, multiplets kept whole)
+//   keep g <= D values (zeros <= 1e-12 s_1 dropped, multiplets -- gaps <=
+//   1e-10 s_g + 1e-12 s_1 -- kept whole)
 //   Gamma_i' = Q_i U_g / outer lambdas,  Gamma_j' = Q_j conj(V_g) / outer lambdas
 //   lambda_b' = s_g / |s_g|,  eps += sum_{k >= g} s_k^2 / sum_k s_k^2 on i and j
 //   Gamma' /= max |Gamma'|
@@ -442,7 +443,9 @@ __global__ __launch_bounds__(1024) void k_su_bond(SuDims dm, LayerDesc L, cplx* 
             for (int k = 0; k < m; ++k) rk += sig_sorted[k] > 1e-12 * sig_sorted[0];
             g = rk < D ? rk : D;
             if (g < rk)
-                while (g > 1 && sig_sorted[g - 1] - sig_sorted[g] <= 1e-10 * sig_sorted[g - 1]) --g;
+                while (g > 1 && sig_sorted[g - 1] - sig_sorted[g] <=
+                                    1e-10 * sig_sorted[g - 1] + 1e-12 * sig_sorted[0])
+                    --g;
         }
         double kept = 0;
         for (int k = 0; k < g; ++k) kept += sig_sorted[k] * sig_sorted[k];

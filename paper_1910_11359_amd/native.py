@@ -35,13 +35,15 @@ class Config(C.Structure):
 class Obs(C.Structure):
     _fields_ = [("t", C.c_double), ("n", C.c_double * 4), ("imbalance", C.c_double),
                 ("sum_n", C.c_double), ("max_offdiag", C.c_double),
-                ("trunc_err", C.c_double * 4), ("ctm_iters", C.c_int), ("ctm_delta", C.c_double)]
+                ("trunc_err", C.c_double * 4), ("ctm_iters", C.c_int), ("ctm_delta", C.c_double),
+                ("renyi1", C.c_double * 4), ("renyi_half", C.c_double * 4)]
 
     def as_dict(self):
         return {"t": self.t, "n": np.array(self.n[:]), "imbalance": self.imbalance,
                 "sum_n": self.sum_n, "max_offdiag": self.max_offdiag,
                 "eps": np.array(self.trunc_err[:]), "ctm_iters": self.ctm_iters,
-                "ctm_delta": self.ctm_delta}
+                "ctm_delta": self.ctm_delta, "renyi1": np.array(self.renyi1[:]),
+                "renyi_half": np.array(self.renyi_half[:])}
 
 
 class Job(C.Structure):

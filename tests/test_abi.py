@@ -46,7 +46,7 @@ def test_config_defaults_and_layout():
     c = P.make_config(4, 32)
     assert (c.D, c.chi, c.d_A, c.trotter_order, c.dtype) == (4, 32, 2, 2, 0)
     assert list(c.layer_w) == [0.25] * 4 and list(c.layer_J) == [1.0] * 4
-    assert ctypes.sizeof(native.Obs) == 8 * 13 + 8  # 13 doubles + an int padded to 8
+    assert ctypes.sizeof(native.Obs) == 8 * 21 + 8  # 21 doubles + an int padded to 8
 
 
 def test_footprint_monotone_and_validation():

@@ -44,6 +44,8 @@ def test_small_workload_vs_oracle():
         spread = par.oracle_spread(ost, p, cfg["ctm_iters"], o["corner_spectra"])
         par.assert_spectra(st.corner_spectra(), o["corner_spectra"], spread, step)
         assert abs(g["sum_n"] - 2.0) < 1e-10 and g["max_offdiag"] < 1e-10
+        assert np.max(np.abs(g["renyi1"] - o["renyi1"])) < 1e-6, step
+        assert np.max(np.abs(g["renyi_half"] - o["renyi_half"])) < 1e-6, step
 
 
 @pytest.mark.parametrize("D,chi,seed", [(2, 8, 3), (3, 9, 4), (3, 12, 5), (4, 16, 6)])

@@ -96,3 +96,25 @@ def test_rejections():
     with pytest.raises(P.IpepsError):
         srv.poll(987654)
     srv.close()
+
+
+def test_bond_dimension_stopping_rule():
+    """D=2 and D=3 evolved together through the request loop: each series
+    equals its job run alone, t_stop is the first time their imbalances
+    differ by more than tol, and the entropies stay in [0, ln 2]."""
+    from paper_1910_11359_amd import validity
+
+    kw = dict(J=1.0, V=1.0, W=3.0, dt=0.05)
+    out = validity.compare_bond_dimensions(2, lambda D: 2 * D * D, n_steps=20, observe_every=5,
+                                           ctm_iters=6, tol=1e-3, **kw)
+    s2, s3 = out["series"][2], out["series"][3]
+    assert len(s2) == len(s3) == 4
+    ref = _alone(P.make_config(3, 18, **kw), 20, 5, 6)
+    assert all(a["imbalance"] == b["imbalance"] for a, b in zip(s3, ref))
+    diffs = [abs(a["imbalance"] - b["imbalance"]) for a, b in zip(s2, s3)]
+    expect = next((a["t"] for a, d in zip(s2, diffs) if d > 1e-3), None)
+    assert out["t_stop"] == expect
+    for s in (s2, s3):
+        for o in s:
+            assert np.all(o["renyi1"] >= -1e-12) and np.all(o["renyi1"] <= np.log(2) + 1e-12)
+            assert np.all(o["renyi_half"] >= o["renyi1"] - 1e-12)

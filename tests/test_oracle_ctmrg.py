@@ -123,3 +123,27 @@ def test_real_basis_invariance():
     # the two runs differ only by rounding: the spread measured here (~1e-10)
     # is the floor any two FP64 implementations of this CTMRG can reach
     assert np.max(np.abs(sc - sr)) < 1e-9
+
+
+def test_renyi_helper_against_matrix_functions():
+    """S_1 = -Tr r log r and S_1/2 = 2 log Tr sqrt(r) through scipy's matrix
+    logarithm and square root (a different route than the eigenvalues the
+    oracle uses), for random density matrices; pure states give 0, the
+    maximally mixed state log d for both orders, and S_1/2 >= S_1."""
+    from scipy.linalg import logm, sqrtm
+
+    rng = np.random.default_rng(11)
+    for d in (2, 3, 4):
+        for _ in range(5):
+            X = rng.normal(size=(d, d)) + 1j * rng.normal(size=(d, d))
+            r = X @ X.conj().T
+            r /= np.trace(r).real
+            s1, sh = ct.renyi(r)
+            assert abs(s1 - float(-np.trace(r @ logm(r)).real)) < 1e-10
+            assert abs(sh - float(2 * np.log(np.trace(sqrtm(r)).real))) < 1e-10
+            assert sh >= s1 - 1e-12
+        v = rng.normal(size=d) + 1j * rng.normal(size=d)
+        v /= np.linalg.norm(v)
+        assert max(abs(x) for x in ct.renyi(np.outer(v, v.conj()))) < 1e-7
+        s1, sh = ct.renyi(np.eye(d) / d)
+        assert abs(s1 - np.log(d)) < 1e-12 and abs(sh - np.log(d)) < 1e-12

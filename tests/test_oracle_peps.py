@@ -68,7 +68,16 @@ def test_dimer_limit(W, steps):
                layer_J=(1, 0, 0, 0), layer_V=(1, 0, 0, 0), layer_w=(1, 0, 0, 0))
     obs, _ = run.run_job(p, max(steps), steps, ctm_iters=2)
     for o in obs:
-        assert abs(o["imbalance"] - _dimer_exact(o["t"], 1.0, W)) < 1e-12
+        imb = _dimer_exact(o["t"], 1.0, W)
+        assert abs(o["imbalance"] - imb) < 1e-12
+        # every site is one end of an isolated dimer: rho_p = diag(n, 1 - n)
+        # with n = (1 + I)/2 on A sites, so both entropies are binary-entropy
+        # closed forms of the exact imbalance
+        nA = 0.5 * (1.0 + imb)
+        h1 = -sum(x * np.log(x) for x in (nA, 1.0 - nA) if x > 0)
+        hh = 2.0 * np.log(np.sqrt(nA) + np.sqrt(1.0 - nA))
+        assert np.max(np.abs(o["renyi1"] - h1)) < 1e-10
+        assert np.max(np.abs(o["renyi_half"] - hh)) < 1e-10
     if W == 0.0:
         assert abs(obs[0]["imbalance"] - np.cos(obs[0]["t"])) < 1e-12
 
