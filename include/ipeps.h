@@ -59,7 +59,8 @@ enum { IPEPS_DTYPE_FP64 = 0, IPEPS_DTYPE_FP32 = 1, IPEPS_DTYPE_BF16 = 2 };
  *   h_bond = J (Sx Sx + Sy Sy) + V Sz Sz + w W (Sz Za (x) 1 + 1 (x) Sz Za)
  * on every nearest-neighbour bond, w = 1/4 (four bonds per site).
  * D: PEPS bond dimension (1..8); chi: environment dimension (D^2..160);
- * d_A: auxiliary levels (2 in this version); dt: Trotter step (> 0);
+ * d_A: auxiliary levels, 1..5 (d = 2 d_A <= 10; d_A = 1 is the clean model;
+ *      the simple update needs d min(D^3, d D) <= 512); dt: Trotter step (> 0);
  * trotter_order: must be 2.  layer_J / layer_V multiply J and V on the bonds
  * of the layers H_A, H_B, V_A, V_B, and layer_w sets their field weight w:
  * hooks for exactly solvable limits (a dimer lattice, decoupled chains);

@@ -71,7 +71,12 @@ int choose_k(int n, int chi) {
 void validate(const ipeps_config* c) {
     IPEPS_REQUIRE(c != nullptr, IPEPS_EINVAL, "config is NULL");
     IPEPS_REQUIRE(c->D >= 1 && c->D <= 8, IPEPS_EINVAL, "D must be in 1..8");
-    IPEPS_REQUIRE(c->d_A == 2, IPEPS_EINVAL, "d_A must be 2");
+    IPEPS_REQUIRE(c->d_A >= 1 && c->d_A <= 5, IPEPS_EINVAL, "d_A must be in 1..5");
+    {
+        const int d = 2 * c->d_A, Dc = c->D * c->D * c->D, nb = d * c->D;
+        IPEPS_REQUIRE(d * (Dc < nb ? Dc : nb) <= 512, IPEPS_EINVAL,
+                      "simple update: d * min(D^3, d D) must be <= 512");
+    }
     IPEPS_REQUIRE(c->chi >= c->D * c->D && c->chi <= 160, IPEPS_EINVAL, "chi must be in D^2..160");
     IPEPS_REQUIRE(c->dt > 0 && std::isfinite(c->dt), IPEPS_EINVAL, "dt must be > 0");
     IPEPS_REQUIRE(c->trotter_order == 2, IPEPS_EINVAL, "trotter_order must be 2");

@@ -496,7 +496,7 @@ __global__ __launch_bounds__(256) void k_readout_rows(int D, int d, const double
     const double* Es = E + site * q4;
     const cplx* As = A + site * d * D4;
     const int r = x % D, dd = (x / D) % D, l = (x / (D * D)) % D, u = x / (D * D * D);
-    double tr[8], ti[8];
+    double tr[10], ti[10];
     for (int sp = 0; sp < d; ++sp) tr[sp] = ti[sp] = 0.0;
     for (long xp = lane; xp < D4; xp += 64) {
         const int rp = xp % D, dp = (xp / D) % D, lp = (xp / (D * D)) % D, up = xp / (D * D * D);
@@ -529,7 +529,7 @@ __global__ __launch_bounds__(256) void k_readout_rows(int D, int d, const double
 __global__ __launch_bounds__(1024) void k_readout_finish(int D, int d, int dA, const cplx* __restrict__ A,
                                                          const cplx* __restrict__ T, cplx* rho, double* obs) {
     __shared__ double red[16];
-    __shared__ cplx rs[64];
+    __shared__ cplx rs[100];
     __shared__ double nsite[4], offd[4], s1[4], shalf[4];
     const long D4 = (long)D * D * D * D;
     for (int site = 0; site < 4; ++site) {
@@ -598,7 +598,7 @@ __global__ __launch_bounds__(1024) void k_readout_finish(int D, int d, int dA, c
 
 void readout(hipStream_t s, int D, int d, int d_A, const double* E, const cplx* A, cplx* Twork,
              cplx* rho, double* obs) {
-    IPEPS_REQUIRE(d <= 8, IPEPS_EINVAL, "readout supports d <= 8");
+    IPEPS_REQUIRE(d <= 10, IPEPS_EINVAL, "readout supports d <= 10");
     const long rows = 4L * D * D * D * D;
     hipLaunchKernelGGL(k_readout_rows, dim3(ceil_div(rows, 4)), dim3(256), 0, s, D, d, E, A, Twork);
     hipLaunchKernelGGL(k_readout_finish, dim3(1), dim3(1024), 0, s, D, d, d_A, A, Twork, rho, obs);

@@ -27,80 +27,41 @@ struct GateParams {
     double W, dt;
 };
 
+// h_b conserves both auxiliary labels and the number of up spins, so
+// exp(-i tau h_b) splits into blocks per (a_i, a_j): phases on |up up> and
+// |dn dn>, and a 2 x 2 unitary on {|up dn>, |dn up>} with the closed form
+// exp(-i tau (m0 + m.sigma)) = e^{-i tau m0} (cos(tau|m|) - i sin(tau|m|) m.sigma/|m|).
 __global__ void k_build_gates(GateParams gp, cplx* gates) {
-    extern __shared__ double sm[];
     const int layer = blockIdx.x >> 1, which = blockIdx.x & 1;
     const int dA = gp.d_A, d = 2 * dA, dd = d * d;
-    double* h = sm;
-    double* V = sm + dd * dd;
-    if (threadIdx.x != 0) return;
     const double Jl = gp.J[layer], Vl = gp.V[layer], wW = gp.w[layer] * gp.W;
-    for (int r = 0; r < dd; ++r) {
-        const int si = r / d, sj = r % d;
-        const int pi = si / dA, ai = si % dA, pj = sj / dA, aj = sj % dA;
-        for (int c = 0; c < dd; ++c) {
-            const int ti = c / d, tj = c % d;
-            const int qi = ti / dA, bi = ti % dA, qj = tj / dA, bj = tj % dA;
-            double v = 0.0;
-            if (ai == bi && aj == bj) {
-                if (pi == qi && pj == qj) {
-                    const double szi = pi == 0 ? 0.5 : -0.5, szj = pj == 0 ? 0.5 : -0.5;
-                    const double zi = dA > 1 ? 1.0 - 2.0 * ai / (dA - 1) : 0.0;
-                    const double zj = dA > 1 ? 1.0 - 2.0 * aj / (dA - 1) : 0.0;
-                    v = Vl * szi * szj + wW * (szi * zi + szj * zj);
-                } else if (pi == qj && pj == qi && pi != pj) {
-                    v = 0.5 * Jl;
-                }
-            }
-            h[r * dd + c] = v;
-            V[r * dd + c] = (r == c) ? 1.0 : 0.0;
-        }
-    }
-    // cyclic Jacobi eigen-decomposition h = V diag(h_kk) V^T
-    for (int sweep = 0; sweep < 60; ++sweep) {
-        double off = 0.0, tot = 0.0;
-        for (int p = 0; p < dd; ++p)
-            for (int q = 0; q < dd; ++q) {
-                tot += h[p * dd + q] * h[p * dd + q];
-                if (p != q) off += h[p * dd + q] * h[p * dd + q];
-            }
-        if (off <= 1e-32 * tot || off == 0.0) break;
-        for (int p = 0; p < dd - 1; ++p)
-            for (int q = p + 1; q < dd; ++q) {
-                const double hpq = h[p * dd + q];
-                if (fabs(hpq) < 1e-300) continue;
-                const double th = (h[q * dd + q] - h[p * dd + p]) / (2.0 * hpq);
-                const double t = (th >= 0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
-                const double c = 1.0 / sqrt(t * t + 1.0), s = t * c;
-                for (int k = 0; k < dd; ++k) {
-                    const double a = h[k * dd + p], b = h[k * dd + q];
-                    h[k * dd + p] = c * a - s * b;
-                    h[k * dd + q] = s * a + c * b;
-                }
-                for (int k = 0; k < dd; ++k) {
-                    const double a = h[p * dd + k], b = h[q * dd + k];
-                    h[p * dd + k] = c * a - s * b;
-                    h[q * dd + k] = s * a + c * b;
-                }
-                for (int k = 0; k < dd; ++k) {
-                    const double a = V[k * dd + p], b = V[k * dd + q];
-                    V[k * dd + p] = c * a - s * b;
-                    V[k * dd + q] = s * a + c * b;
-                }
-            }
-    }
     const double tau = which ? gp.dt : 0.5 * gp.dt;
     cplx* G = gates + (long)blockIdx.x * dd * dd;
-    for (int r = 0; r < dd; ++r)
-        for (int c = 0; c < dd; ++c) {
-            double re = 0, im = 0;
-            for (int k = 0; k < dd; ++k) {
-                const double vv = V[r * dd + k] * V[c * dd + k], ph = tau * h[k * dd + k];
-                re += vv * cos(ph);
-                im -= vv * sin(ph);
-            }
-            G[r * dd + c] = cmake(re, im);
-        }
+    for (long e = threadIdx.x; e < (long)dd * dd; e += blockDim.x) G[e] = cmake(0, 0);
+    __syncthreads();
+    for (int blk = threadIdx.x; blk < dA * dA; blk += blockDim.x) {
+        const int ai = blk / dA, aj = blk % dA;
+        const double zi = dA > 1 ? 1.0 - 2.0 * ai / (dA - 1) : 0.0;
+        const double zj = dA > 1 ? 1.0 - 2.0 * aj / (dA - 1) : 0.0;
+        auto idx = [&](int pi, int pj) { return (pi * dA + ai) * d + (pj * dA + aj); };
+        auto phase = [&](double E) { return cmake(cos(tau * E), -sin(tau * E)); };
+        // S^z = +1/2 for p = 0 (up), -1/2 for p = 1
+        const double e00 = 0.25 * Vl + 0.5 * wW * (zi + zj);
+        const double e11 = 0.25 * Vl - 0.5 * wW * (zi + zj);
+        const double e01 = -0.25 * Vl + 0.5 * wW * (zi - zj);
+        const double e10 = -0.25 * Vl - 0.5 * wW * (zi - zj);
+        G[(long)idx(0, 0) * dd + idx(0, 0)] = phase(e00);
+        G[(long)idx(1, 1) * dd + idx(1, 1)] = phase(e11);
+        const double m0 = 0.5 * (e01 + e10), mz = 0.5 * (e01 - e10), mx = 0.5 * Jl;
+        const double mm = sqrt(mz * mz + mx * mx);
+        const double c = cos(tau * mm), sn = mm > 0 ? sin(tau * mm) / mm : tau;
+        const cplx ph = phase(m0);
+        const int u = idx(0, 1), v = idx(1, 0);
+        G[(long)u * dd + u] = cmul(ph, cmake(c, -sn * mz));
+        G[(long)v * dd + v] = cmul(ph, cmake(c, sn * mz));
+        G[(long)u * dd + v] = cmul(ph, cmake(0, -sn * mx));
+        G[(long)v * dd + u] = cmul(ph, cmake(0, -sn * mx));
+    }
 }
 
 void build_gates(hipStream_t s, const ipeps_config& cfg, cplx* gates) {
@@ -113,10 +74,7 @@ void build_gates(hipStream_t s, const ipeps_config& cfg, cplx* gates) {
     }
     gp.W = cfg.W;
     gp.dt = cfg.dt;
-    const int dd = 4 * cfg.d_A * cfg.d_A;
-    IPEPS_REQUIRE(dd <= 64, IPEPS_EINVAL, "gate builder supports d <= 8");
-    hipLaunchKernelGGL(k_build_gates, dim3(8), dim3(64), 2 * dd * dd * sizeof(double), s, gp,
-                       gates);
+    hipLaunchKernelGGL(k_build_gates, dim3(8), dim3(256), 0, s, gp, gates);
     HIP_CHECK(hipGetLastError());
 }
 
@@ -339,8 +297,8 @@ __global__ __launch_bounds__(1024) void k_su_bond(SuDims dm, LayerDesc L, cplx* 
     __shared__ int flag;
     __shared__ int g_s;
     __shared__ double lam_inv_i[3][8], lam_inv_j[3][8], lam_i[3][8], lam_j[3][8];
-    __shared__ double sig_sorted[256];
-    __shared__ int col_of_rank[256];
+    __shared__ double sig_sorted[512];
+    __shared__ int col_of_rank[512];
 
     const BondDesc bd = L.bond[blockIdx.x];
     const int D = dm.D, d = dm.d, Dc = dm.Dc, nb = dm.nb, r = dm.r, m = dm.m;
@@ -519,7 +477,7 @@ __global__ __launch_bounds__(1024) void k_su_bond(SuDims dm, LayerDesc L, cplx* 
 void su_layer(hipStream_t s, int D, int d, const LayerDesc& L, cplx* gam, double* lam,
               double* eps, const cplx* gates, void* scratch) {
     const SuDims dm = su_dims(D, d);
-    IPEPS_REQUIRE(dm.m <= 256 && D <= 8, IPEPS_EINVAL, "simple update: d*min(D^3,dD) > 256");
+    IPEPS_REQUIRE(dm.m <= 512 && D <= 8, IPEPS_EINVAL, "simple update: d*min(D^3,dD) > 512");
     const size_t per_bond = su_layout(dm, nullptr, nullptr);
     const size_t lds = (size_t)dm.m * dm.m * sizeof(cplx);
     static const size_t kMax = 160 * 1024 - 12 * 1024;

@@ -106,6 +106,33 @@ def test_product_start_low_rank_cuts():
     st32.close()
 
 
+@pytest.mark.parametrize("d_A,D,chi", [(1, 2, 8), (3, 2, 8), (4, 2, 8), (5, 2, 4), (3, 3, 9)])
+def test_aux_levels_vs_oracle(d_A, D, chi):
+    """More disorder levels (d = 2 d_A up to 10, fields on d_A equally spaced
+    levels; d_A = 1 is the clean model): 6 steps, CTMRG from a cold start
+    after steps 3 and 6."""
+    kw = dict(J=1.0, V=1.0, W=3.0, dt=0.05, d_A=d_A)
+    st = _gpu_state(D, chi, **kw)
+    p = par.oracle_params(D, chi, **kw)
+    ost = opeps.new_state(p)
+    for step in range(1, 7):
+        st.trotter_step(1)
+        opeps.trotter_step(ost, p)
+        if step % 3:
+            continue
+        st.ctmrg(0.0, 8, True)
+        g = st.observe()
+        o, _ = orun.observe_state(ost, p, ctm_iters=8)
+        assert abs(g["imbalance"] - o["imbalance"]) < 1e-6, step
+        assert np.max(np.abs(g["n"] - o["n"])) < 1e-6, step
+        assert np.max(np.abs(g["eps"] - o["eps"])) < 1e-10, step
+        assert np.max(np.abs(st.bond_spectra() - o["bond_spectra"])) < 1e-10, step
+        assert np.max(np.abs(g["renyi1"] - o["renyi1"])) < 1e-6, step
+        spread = par.oracle_spread(ost, p, 8, o["corner_spectra"])
+        par.assert_spectra(st.corner_spectra(), o["corner_spectra"], spread, step)
+    st.close()
+
+
 def _dimer_exact(t, J, W):
     w = np.sqrt(J ** 2 + 4 * W ** 2)
     return 1 - np.sin(J * t / 2) ** 2 - J ** 2 / w ** 2 * np.sin(w * t / 2) ** 2

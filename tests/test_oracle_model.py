@@ -111,9 +111,11 @@ def _evolve(H, psi0, times):
     return out
 
 
-@pytest.mark.parametrize("Lx,Ly", [(2, 2), (4, 2)])
-def test_dilation_identity(Lx, Ly):
-    J, V, W, d_A = 1.0, 1.0, 2.0, 2
+@pytest.mark.parametrize("Lx,Ly,d_A", [(2, 2, 2), (4, 2, 2), (2, 2, 3)])
+def test_dilation_identity(Lx, Ly, d_A):
+    """Dilated dynamics = average over all d_A^N explicit field
+    configurations (fields W z, z on d_A equally spaced levels in [-1, 1])."""
+    J, V, W = 1.0, 1.0, 2.0
     times = [0.3, 1.1]
     bonds, idx = _torus_bonds(Lx, Ly)
     N = Lx * Ly
@@ -151,12 +153,13 @@ def test_dilation_identity(Lx, Ly):
     for s in range(N):
         phi0 = np.kron(phi0, np.eye(2)[neel[s]])
     avg = np.zeros((len(times), N))
-    for zs in itertools.product([1.0, -1.0], repeat=N):
+    levels = [1.0 - 2.0 * a / (d_A - 1) for a in range(d_A)]
+    for zs in itertools.product(levels, repeat=N):
         Hz = (Hb + sum(W * z * Z for z, Z in zip(zs, Zs))).toarray()
         lam, U = np.linalg.eigh(Hz)
         c0 = U.conj().T @ phi0
         for k, t in enumerate(times):
             phi = U @ (np.exp(-1j * t * lam) * c0)
             avg[k] += [np.vdot(phi, nloc[s] @ phi).real for s in range(N)]
-    avg /= 2 ** N
+    avg /= d_A ** N
     assert np.max(np.abs(dil - avg)) < 1e-12
