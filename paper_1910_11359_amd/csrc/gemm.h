@@ -38,11 +38,12 @@ GemmProb gemm_general(const void* A, bool transA, long lda, const void* B, bool 
                       long ldb, void* C, long ldc, int M, int N, int K, double alpha = 1.0,
                       double beta = 0.0);
 
-// TILE_DIRECT: 128 x 128 tiles loaded straight into LDS (16-byte LDS-DMA);
-// chosen instead of TILE_LARGE when every problem of the group has A with k
-// contiguous and B with n contiguous, 16-byte aligned, with K and N (and the
-// A row strides, B k stride) multiples of the 16-byte vector.
-enum GemmTile { TILE_LARGE = 0, TILE_SMALL = 1, TILE_DIRECT = 2 };
+// TILE_DIRECT / TILE_DIRECT_SMALL: 128 x 128 / 64 x 64 tiles loaded straight
+// into LDS (16-byte LDS-DMA); chosen instead of TILE_LARGE / TILE_SMALL when
+// every problem of the group has A with k contiguous and B with n contiguous,
+// 16-byte aligned, with K and N (and the A row strides, B k stride) multiples
+// of the 16-byte vector.
+enum GemmTile { TILE_LARGE = 0, TILE_SMALL = 1, TILE_DIRECT = 2, TILE_DIRECT_SMALL = 3 };
 
 // Chooses the tile shape for a group and fills tiles_n / tile_begin;
 // returns the total number of tiles (the grid size).

@@ -260,7 +260,7 @@ int gemm_plan_tiles(GemmProb* probs, int n, int dtype, GemmTile* tile) {
         large_tiles += (long)ceil_div(probs[i].M, 128) * ceil_div(probs[i].N, 128) * ks;
     }
     *tile = (small_work * 4 > all_work || large_tiles < 512) ? TILE_SMALL : TILE_LARGE;
-    if (*tile == TILE_LARGE) {
+    {
         const long vw = dtype == IPEPS_DTYPE_FP64 ? 2 : 4;
         bool direct = true;
         for (int i = 0; i < n && direct; ++i) {
@@ -269,7 +269,7 @@ int gemm_plan_tiles(GemmProb* probs, int n, int dtype, GemmTile* tile) {
                      p.K >= vw && ((uintptr_t)p.A & 15) == 0 && p.b_cs == 1 && p.b_ks % vw == 0 &&
                      p.N % vw == 0 && p.N >= vw && ((uintptr_t)p.B & 15) == 0;
         }
-        if (direct) *tile = TILE_DIRECT;
+        if (direct) *tile = (*tile == TILE_LARGE) ? TILE_DIRECT : TILE_DIRECT_SMALL;
     }
     int bm, bn;
     tile_dims(dtype, *tile, &bm, &bn);
@@ -530,6 +530,15 @@ static void launch_tagged(hipStream_t stream, int dtype, GemmTile tile, const Ge
                                d_probs, nprob);
         else
             hipLaunchKernelGGL((k_gemm_direct<float, 128, 128, 32, 2, TAG>), grid, block, 0, stream,
+                               d_probs, nprob);
+        return;
+    }
+    if (tile == TILE_DIRECT_SMALL) {
+        if (dtype == IPEPS_DTYPE_FP64)
+            hipLaunchKernelGGL((k_gemm_direct<double, 64, 64, 16, 2, TAG>), grid, block, 0, stream,
+                               d_probs, nprob);
+        else
+            hipLaunchKernelGGL((k_gemm_direct<float, 64, 64, 32, 2, TAG>), grid, block, 0, stream,
                                d_probs, nprob);
         return;
     }
