@@ -379,6 +379,10 @@ void build_plan(ipeps_state* st) {
         P.Vo = batch2([&](int b) {
             return gemm_nn(st->Qz + b * nk, k, st->Vc + b * kk, k, st->Vo + b * nk, k, n, k, k);
         });
+        P.VfromU = batch2([&](int b) {
+            return gemm_general(st->Cs + b * kk, true, k, st->Uc + b * kk, false, k,
+                                st->Vc + b * kk, k, k, k, k);
+        });
         // gated on the number of dropped columns of matrix b
         auto proj1 = [&](double* Q) {
             return batch2([&](int b) {
@@ -559,12 +563,12 @@ void orth(ipeps_state* st, double* X, double* Q, const GemmGroup& gram1, const G
     run(st, mul2);
 }
 
-// Relative cutoff below which singular values of a cut matrix count as zero.
-// The FP32 path keeps the same value: its tail below ~1e-6 is rounding noise
-// of the products, but such directions enter the renormalised tensors with
-// weight sqrt(sigma), and cutting them at 1e-6 was measured to move the
-// imbalance more (1e-4) than keeping them (5e-6).
-double proj_cutoff(const ipeps_state*) { return 1e-12; }
+// Relative cutoff below which singular values of a cut matrix count as zero:
+// 1e-12 with FP64 products.  With FP32 products the tail below ~1e-6 is
+// rounding noise, but such directions enter the renormalised tensors with
+// weight sqrt(sigma): cutting at 1e-6 moved the D=6, chi=72 imbalance by 1e-4,
+// at 1e-9 or 1e-12 by 5e-6.  1e-9 keeps V = Cs^T U S^{-1} accurate.
+double proj_cutoff(const ipeps_state* st) { return st->dtype == IPEPS_DTYPE_FP64 ? 1e-12 : 1e-9; }
 
 // Truncated SVD of the two cut matrices N64[0..1]; fills Us, Vs and g_dev.
 void projector_svd(ipeps_state* st, int slot) {
@@ -608,9 +612,20 @@ void projector_svd(ipeps_state* st, int slot) {
     run(st, P.NVfinal);  // Qw = N V
     run(st, P.Cs);       // Cs = Q^T N V
     // Rayleigh-Ritz SVD.  Columns are left unrotated only below 1e-14 |Cs|_F,
-    // far under the 1e-12 sigma_1 projector cutoff: a kept direction that was
-    // never rotated against the dominant ones would break P_up P_low = 1.
-    jacobi_svd_real(s, 2, k, k, st->Cs, k, (long)k * k, st->sig, st->Uc, st->Vc, st->jwork, 1e-14);
+    // far under the projector cutoff: a kept direction that was never rotated
+    // against the dominant ones would break P_up P_low = 1.
+    if (st->dtype == IPEPS_DTYPE_FP64) {
+        jacobi_svd_real(s, 2, k, k, st->Cs, k, (long)k * k, st->sig, st->Uc, st->Vc, st->jwork,
+                        1e-14);
+    } else {
+        // FP32 products: rotate the left vectors only (half the Jacobi
+        // traffic) and take V = Cs^T U S^{-1}; its error eps_64 s_1 / s_i
+        // stays below 1e-7 above the 1e-9 s_1 cutoff of this precision
+        jacobi_svd_real(s, 2, k, k, st->Cs, k, (long)k * k, st->sig, st->Uc, nullptr, st->jwork,
+                        1e-14);
+        run(st, P.VfromU);
+        scale_columns_inv(s, 2, k, k, st->Vc, st->sig, proj_cutoff(st));
+    }
     run(st, P.Uo);
     run(st, P.Vo);
     HIP_CHECK(hipMemcpyAsync(st->warm + 2 * slot * nk, st->Vo, 2 * nk * sizeof(double),

@@ -48,6 +48,8 @@ struct SvdPlan {
         Vo, NVfinal;
     // restart of dropped left columns: Gm = Qw^T Rb, Rb -= Qw Gm
     GemmGroup projQw1, projQw2;
+    // right Ritz vectors from the left ones (FP32 products): Vc = Cs^T Uc
+    GemmGroup VfromU;
 };
 
 }  // namespace ipeps
