@@ -133,6 +133,31 @@ def serving_sample(P, synthetic, dtype, n_req=16, rate=8.0, d_max=4, steps_max=4
                       f"steps at {steps_max}, observe every 10 with 10 warm CTMRG iterations"}, series
 
 
+def sweep(P, synthetic, dtype, slots=8):
+    """The batched parameter sweep: 64 jobs (D in 3..6 with chi = 2 D^2, V in
+    {0, 1}, 8 seeded W in [1, 20]), 50 Trotter steps each, 10 CTMRG
+    iterations every 10 steps, all submitted at once to a request loop with
+    `slots` concurrent jobs.  Returns jobs/s and the whole duration."""
+    jobs = synthetic.sweep_jobs()
+    srv = P.Server(hbm_budget=0, max_slots=slots)
+    t0 = time.perf_counter()
+    ids = [srv.submit(P.make_config(j["D"], j["chi"], J=j["J"], V=j["V"], W=j["W"], dt=j["dt"],
+                                    dtype=dtype),
+                      n_steps=j["n_steps"], observe_every=j["observe_every"],
+                      ctm_iters=j["ctm_iters"]) for j in jobs]
+    done = 0
+    for jid in ids:
+        while srv.poll(jid)[1] is None:
+            time.sleep(0.005)
+        done += 1
+    dt = time.perf_counter() - t0
+    srv.close()
+    return {"jobs": len(ids), "seconds": dt, "jobs_per_s": len(ids) / dt, "slots": slots,
+            "dtype": dtype,
+            "workload": "64 jobs: D in {3,4,5,6}, chi = 2D^2, V in {0,1}, W = 8 seeded values "
+                        "in [1,20]; 50 steps, 10 CTMRG iterations every 10 steps"}
+
+
 def headline(P, torch, wl, dtype, steps, warmup, prelude):
     """Time `steps` steps (after `warmup`) of the headline workload; the state
     is first evolved for `prelude` Trotter steps and 10 cold CTMRG iterations."""
@@ -181,6 +206,8 @@ def main():
     ap.add_argument("--prelude", type=int, default=20, help="untimed Trotter steps first")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--sweep", action="store_true",
+                    help="also run the 64-job batched sweep through the request loop")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="also copy MIB MiB device to device once (reference kernel for HBM counters)")
     args = ap.parse_args()
@@ -240,6 +267,10 @@ def main():
             err = max(abs(a - b) for x, y in zip(ser, ser64) for a, b in zip(x, y))
             out["serving"]["fp64_jobs_per_s"] = srv64["jobs_per_s"]
             out["serving"]["max_imbalance_err_vs_fp64"] = err
+    if args.sweep:
+        out["sweep"] = sweep(P, synthetic, args.dtype)
+        if args.dtype != "fp64" and not args.no_fp64_ref:
+            out["sweep"]["fp64_jobs_per_s"] = sweep(P, synthetic, "fp64")["jobs_per_s"]
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(D, chi, wl["W"], wl["V"])
     print(json.dumps(out), flush=True)

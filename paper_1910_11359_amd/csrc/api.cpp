@@ -379,10 +379,7 @@ void build_plan(ipeps_state* st) {
         P.Vo = batch2([&](int b) {
             return gemm_nn(st->Qz + b * nk, k, st->Vc + b * kk, k, st->Vo + b * nk, k, n, k, k);
         });
-        P.VfromU = batch2([&](int b) {
-            return gemm_general(st->Cs + b * kk, true, k, st->Uc + b * kk, false, k,
-                                st->Vc + b * kk, k, k, k, k);
-        });
+
         // gated on the number of dropped columns of matrix b
         auto proj1 = [&](double* Q) {
             return batch2([&](int b) {
@@ -567,7 +564,7 @@ void orth(ipeps_state* st, double* X, double* Q, const GemmGroup& gram1, const G
 // 1e-12 with FP64 products.  With FP32 products the tail below ~1e-6 is
 // rounding noise, but such directions enter the renormalised tensors with
 // weight sqrt(sigma): cutting at 1e-6 moved the D=6, chi=72 imbalance by 1e-4,
-// at 1e-9 or 1e-12 by 5e-6.  1e-9 keeps V = Cs^T U S^{-1} accurate.
+// at 1e-9 or 1e-12 by ~5e-6; 1e-9 is used.
 double proj_cutoff(const ipeps_state* st) { return st->dtype == IPEPS_DTYPE_FP64 ? 1e-12 : 1e-9; }
 
 // Truncated SVD of the two cut matrices N64[0..1]; fills Us, Vs and g_dev.
@@ -593,7 +590,8 @@ void projector_svd(ipeps_state* st, int slot) {
         orth(st, st->Zw, st->Qz, P.gramZ, P.QfromZ, P.gramQz, P.ZfromQz, true);
         HIP_CHECK(hipMemcpyAsync(st->Qz, st->Zw, 2 * nk * sizeof(double), hipMemcpyDeviceToDevice, s));
     }
-    const int iters = warm ? (st->dtype == IPEPS_DTYPE_FP64 ? kWarmIters : kWarmItersLow) : kColdIters;
+    int iters = warm ? (st->dtype == IPEPS_DTYPE_FP64 ? kWarmIters : kWarmItersLow) : kColdIters;
+    if (warm) iters += st->extra_warm_iters;
     for (int it = 0; it < iters; ++it) {
         // power step with one Cholesky-QR pass per side (only the span
         // matters).  Dropped left columns are restarted; a right column
@@ -613,19 +611,10 @@ void projector_svd(ipeps_state* st, int slot) {
     run(st, P.Cs);       // Cs = Q^T N V
     // Rayleigh-Ritz SVD.  Columns are left unrotated only below 1e-14 |Cs|_F,
     // far under the projector cutoff: a kept direction that was never rotated
-    // against the dominant ones would break P_up P_low = 1.
-    if (st->dtype == IPEPS_DTYPE_FP64) {
-        jacobi_svd_real(s, 2, k, k, st->Cs, k, (long)k * k, st->sig, st->Uc, st->Vc, st->jwork,
-                        1e-14);
-    } else {
-        // FP32 products: rotate the left vectors only (half the Jacobi
-        // traffic) and take V = Cs^T U S^{-1}; its error eps_64 s_1 / s_i
-        // stays below 1e-7 above the 1e-9 s_1 cutoff of this precision
-        jacobi_svd_real(s, 2, k, k, st->Cs, k, (long)k * k, st->sig, st->Uc, nullptr, st->jwork,
-                        1e-14);
-        run(st, P.VfromU);
-        scale_columns_inv(s, 2, k, k, st->Vc, st->sig, proj_cutoff(st));
-    }
+    // against the dominant ones would break P_up P_low = 1.  (Taking the right
+    // vectors as Cs^T U S^-1 instead of accumulating them halves the Jacobi
+    // traffic but moved the FP32 imbalance by 2e-4 at D=6, chi=72; not used.)
+    jacobi_svd_real(s, 2, k, k, st->Cs, k, (long)k * k, st->sig, st->Uc, st->Vc, st->jwork, 1e-14);
     run(st, P.Uo);
     run(st, P.Vo);
     HIP_CHECK(hipMemcpyAsync(st->warm + 2 * slot * nk, st->Vo, 2 * nk * sizeof(double),
@@ -894,6 +883,12 @@ int ctmrg_converge(ipeps_state* st, double tol, int max_iter, int cold_start, in
             corner_spectra_update(st, true);
         }
         (void)first;
+        // Converging to tol: once the spectra move by less than 1e-5 (1e-7) per
+        // iteration, the warm-started projector subspaces get two (four) more
+        // power iterations, so that their error (which decays like
+        // (s_{k+1}/s_chi)^(2q) per iteration) stays below the change being
+        // resolved; a fixed iteration count (tol <= 0) keeps the plain schedule.
+        st->extra_warm_iters = 0;
         for (int it = 0; it < max_iter; ++it) {
             for (int si = 0; si < 8; ++si) column_step(st, si);
             corner_spectra_update(st, false);
@@ -905,8 +900,10 @@ int ctmrg_converge(ipeps_state* st, double tol, int max_iter, int cold_start, in
                 dl = st->host_buf[0];
                 IPEPS_REQUIRE(!std::isnan(dl), IPEPS_ENUMERIC, "NaN in the environment");
                 if (tol > 0 && dl < tol) break;
+                if (tol > 0) st->extra_warm_iters = dl < 1e-7 ? 4 : (dl < 1e-5 ? 2 : 0);
             }
         }
+        st->extra_warm_iters = 0;
         st->last_iters = it_done;
         st->last_delta = dl;
         if (tol > 0 && !(dl < tol)) throw status_error(IPEPS_ENOTCONV, "CTMRG not converged");

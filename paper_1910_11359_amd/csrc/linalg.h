@@ -38,11 +38,6 @@ void normalize_columns(hipStream_t s, int batch, int n, int k, double* X);
 // left untouched.
 void dead_fill(hipStream_t s, int batch, int n, int k, const int* dead, uint64_t seed, double* R);
 
-// Column j of each batched m x k row-major X (stride m*k) divided by sig[b*k+j]
-// (descending per batch), or zeroed where sig <= tau * sig[b*k].
-void scale_columns_inv(hipStream_t s, int batch, int m, int k, double* X, const double* sig,
-                       double tau);
-
 // X_b[e] += Y_b[e] for e < count, for the batches b with gate[b] != 0
 // (matrix b at offset b*count).
 void add_gated(hipStream_t s, int batch, long count, const int* gate, const double* Y, double* X);

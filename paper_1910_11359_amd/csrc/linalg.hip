@@ -478,28 +478,6 @@ __global__ __launch_bounds__(256) void k_dead_fill(int n, int k, const int* __re
     }
 }
 
-__global__ __launch_bounds__(256) void k_scale_cols_inv(int m, int k, double* __restrict__ X,
-                                                        const double* __restrict__ sig,
-                                                        double tau) {
-    const int b = blockIdx.y;
-    double* Xb = X + (long)b * m * k;
-    const double* sb = sig + (long)b * k;
-    for (long e = blockIdx.x * 256L + threadIdx.x; e < (long)m * k; e += 256L * gridDim.x) {
-        const int j = (int)(e % k);
-        const double sj = sb[j];
-        Xb[e] = (sj > tau * sb[0]) ? Xb[e] / sj : 0.0;
-    }
-}
-
-void scale_columns_inv(hipStream_t s, int batch, int m, int k, double* X, const double* sig,
-                       double tau) {
-    if (batch <= 0 || m <= 0 || k <= 0) return;
-    const long tot = (long)m * k;
-    const int grid = ceil_div(tot, 256) < 256 ? ceil_div(tot, 256) : 256;
-    hipLaunchKernelGGL(k_scale_cols_inv, dim3(grid, batch), dim3(256), 0, s, m, k, X, sig, tau);
-    HIP_CHECK(hipGetLastError());
-}
-
 void dead_fill(hipStream_t s, int batch, int n, int k, const int* dead, uint64_t seed, double* R) {
     if (batch <= 0 || k <= 0) return;
     const long tot = (long)n * k;

@@ -48,8 +48,7 @@ struct SvdPlan {
         Vo, NVfinal;
     // restart of dropped left columns: Gm = Qw^T Rb, Rb -= Qw Gm
     GemmGroup projQw1, projQw2;
-    // right Ritz vectors from the left ones (FP32 products): Vc = Cs^T Uc
-    GemmGroup VfromU;
+
 };
 
 }  // namespace ipeps
@@ -121,6 +120,7 @@ struct ipeps_state {
     double* Rb;          // 2 blocks of n*k: refill directions for dropped columns
     int* dead_dev;       // 2*k flags of dropped columns, then 2 counts
     uint64_t orth_calls; // counter feeding the refill hash
+    int extra_warm_iters; // added warm subspace iterations (converging to a tolerance)
     double* norm_ws;     // partial sums of the tensor normalisation (32 tensors)
     double *Nfull_U, *Nfull_V;  // direct path (n <= 96)
     int ks_gram, ks_nv, ks_c;   // split-K factors

@@ -7,6 +7,14 @@ with dt=0.05 for 100 steps and, every 10 steps, runs CTMRG from a cold start
 until the corner spectra change by less than 1e-10 in one iteration (capped at
 --max-iter), then records the imbalance, occupations, truncation errors,
 corner spectra and bond spectra to tests/golden/plain_W{W}_V{V}.json.
+
+    python tests/golden/make_plain_golden.py W V --spread
+
+adds to an existing file the oracle's own rounding sensitivity along the
+trajectory: the simple update is run a second time from the same start with
+every element of Gamma scaled by (1 + 1e-15 r), r standard normal (seeded),
+and the largest bond-spectrum difference at each observation step is stored
+as "su_spread" (the simple update's amplification of one rounding).
 """
 import argparse
 import json
@@ -27,11 +35,15 @@ def main():
     ap.add_argument("W", type=float)
     ap.add_argument("V", type=float)
     ap.add_argument("--max-iter", type=int, default=200)
+    ap.add_argument("--spread", action="store_true")
     args = ap.parse_args()
     cfg = [c for c in synthetic.plain_configs() if c["W"] == args.W and c["V"] == args.V][0]
     p = Params(D=cfg["D"], chi=cfg["chi"], J=cfg["J"], V=cfg["V"], W=cfg["W"], dt=cfg["dt"])
     out = {"config": cfg, "max_iter": args.max_iter, "tol": cfg["ctm_tol"], "obs": []}
     path = os.path.join(ROOT, "tests", "golden", f"plain_W{args.W:g}_V{args.V:g}.json")
+    if args.spread:
+        add_spread(path, p, cfg)
+        return
     st = peps.new_state(p)
     for step in range(0, cfg["n_steps"] + 1):
         if step > 0:
@@ -49,6 +61,30 @@ def main():
               f"delta={o['ctm_delta']:.2e} ({time.time() - t0:.0f}s)", flush=True)
         with open(path, "w") as f:
             json.dump(out, f)
+
+
+def add_spread(path, p, cfg):
+    import numpy as np
+
+    with open(path) as f:
+        out = json.load(f)
+    a, b = peps.new_state(p), peps.new_state(p)
+    rng = np.random.default_rng(2019)
+    for s in peps.SITES:
+        g = b["gam"][s]
+        b["gam"][s] = g * (1 + 1e-15 * rng.normal(size=g.shape))
+    spread = {}
+    for step in range(0, cfg["n_steps"] + 1):
+        if step > 0:
+            peps.trotter_step(a, p)
+            peps.trotter_step(b, p)
+        if step % cfg["observe_every"] == 0:
+            spread[step] = float(np.max(np.abs(peps.bond_spectra(a) - peps.bond_spectra(b))))
+            print(f"step {step} su_spread {spread[step]:.2e}", flush=True)
+    for o in out["obs"]:
+        o["su_spread"] = spread[o["step"]]
+    with open(path, "w") as f:
+        json.dump(out, f)
 
 
 if __name__ == "__main__":
