@@ -150,6 +150,8 @@ def sweep(P, synthetic, dtype, slots=8):
         while srv.poll(jid)[1] is None:
             time.sleep(0.005)
         done += 1
+        print(f"sweep {dtype}: {done}/{len(ids)} jobs done after {time.perf_counter() - t0:.1f} s",
+              file=sys.stderr, flush=True)
     dt = time.perf_counter() - t0
     srv.close()
     return {"jobs": len(ids), "seconds": dt, "jobs_per_s": len(ids) / dt, "slots": slots,

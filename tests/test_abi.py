@@ -59,7 +59,10 @@ def test_footprint_monotone_and_validation():
     assert fp(D=4, chi=8) == 0          # chi < D^2
     assert fp(D=9, chi=81) == 0         # D > 8
     assert fp(D=2, chi=8, dt=-0.1) == 0
-    assert fp(D=2, chi=8, d_A=3) == 0   # only binary disorder in this version
+    assert fp(D=2, chi=8, d_A=3) > 0    # d_A = 1..5 are accepted
+    assert fp(D=2, chi=8, d_A=6) == 0   # d = 2 d_A <= 10
+    assert fp(D=5, chi=25, d_A=5) > 0   # simple update d min(D^3, dD) = 500 <= 512
+    assert fp(D=6, chi=36, d_A=5) == 0  # 600 > 512
 
 
 def test_strerror():
