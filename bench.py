@@ -34,7 +34,7 @@ PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}
 # HBM bytes per launch of the cut-product GEMM (FETCH_SIZE + WRITE_SIZE, scaled
 # by a 256 MiB copy), profiles/traffic_cut_products_D6_chi72_fp32.md; valid
 # only for the GEMM source they were measured on.
-TRAFFIC = {"fp32": {"gemm_sha256_16": "fa839cc0fd43cb71", "bytes_per_launch": 1.784e9}}
+TRAFFIC = {"fp32": {"gemm_sha256_16": "2a226e59e930a5d3", "bytes_per_launch": 1.782e9}}
 DTYPE_NAME = {"fp64": "f64", "fp32": "f32", "bf16": "bf16"}
 METRIC = "Trotter+CTMRG steps/s at D=6,χ=72 (MFMA % peak); batched jobs/s, p50/p99 latency"
 
