@@ -160,11 +160,12 @@ def sweep(P, synthetic, dtype, slots=8):
                         "in [1,20]; 50 steps, 10 CTMRG iterations every 10 steps"}
 
 
-def headline(P, torch, wl, dtype, steps, warmup, prelude):
+def headline(P, torch, wl, dtype, steps, warmup, prelude, flags=0):
     """Time `steps` steps (after `warmup`) of the headline workload; the state
     is first evolved for `prelude` Trotter steps and 10 cold CTMRG iterations."""
     stream = torch.cuda.Stream()
-    cfg = P.make_config(wl["D"], wl["chi"], J=wl["J"], V=wl["V"], W=wl["W"], dt=wl["dt"], dtype=dtype)
+    cfg = P.make_config(wl["D"], wl["chi"], J=wl["J"], V=wl["V"], W=wl["W"], dt=wl["dt"], dtype=dtype,
+                        flags=flags)
     st = P.State(cfg, stream=stream)
     st.trotter_step(prelude)
     st.ctmrg(0.0, 10, True)
@@ -205,6 +206,8 @@ def main():
                     help="CTMRG contraction precision (SVDs, simple update and norms stay FP64)")
     ap.add_argument("--no-fp64-ref", action="store_true",
                     help="skip the FP64 comparison run (headline and serving)")
+    ap.add_argument("--autotune", action="store_true",
+                    help="time every GEMM group's candidate tile kinds at init and keep the fastest")
     ap.add_argument("--prelude", type=int, default=20, help="untimed Trotter steps first")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
@@ -226,7 +229,8 @@ def main():
     wl = synthetic.headline_config()
     D, chi = wl["D"], wl["chi"]
     torch.cuda.init()
-    rec = headline(P, torch, wl, args.dtype, args.steps, args.warmup, args.prelude)
+    flags = P.FLAG_AUTOTUNE if args.autotune else 0
+    rec = headline(P, torch, wl, args.dtype, args.steps, args.warmup, args.prelude, flags)
     peak = PEAK_TFLOPS[args.dtype]
     traffic = None
     tr = TRAFFIC.get(args.dtype)
@@ -244,7 +248,8 @@ def main():
         "config": {"workload": f"headline iPEPS step: D={D}, chi={chi}, d=4, J=1, V={wl['V']}, "
                                f"W={wl['W']}, dt={wl['dt']}, after {args.prelude} prelude steps",
                    "D": D, "chi": chi, "d": 4, "t_end": rec["t_end"],
-                   "contractions": args.dtype, "svd_su_norms": "fp64"},
+                   "contractions": args.dtype, "svd_su_norms": "fp64",
+                   "gemm_tiles": "autotuned" if args.autotune else "heuristic"},
         "roofline": {"bound": "mfma", "achieved": rec["achieved"], "peak": peak, "unit": "TFLOP/s",
                      "frac": rec["achieved"] / peak, "traffic": traffic,
                      "kernel": "k_gemm_direct<...,TAG=1> (4 half-system n^3 products)",
@@ -252,7 +257,7 @@ def main():
         "step_mfma_frac": step_flops(D, chi) / (rec["ms_per_step"] * 1e-3) / (peak * 1e12),
     }
     if args.dtype != "fp64" and not args.no_fp64_ref:
-        r64 = headline(P, torch, wl, "fp64", args.steps, args.warmup, args.prelude)
+        r64 = headline(P, torch, wl, "fp64", args.steps, args.warmup, args.prelude, flags)
         out["fp64_path"] = {"value": r64["value"], "ms_per_step": r64["ms_per_step"],
                             "roofline_frac": r64["achieved"] / PEAK_TFLOPS["fp64"]}
     if args.copy_probe > 0:

@@ -64,7 +64,12 @@ enum { IPEPS_DTYPE_FP64 = 0, IPEPS_DTYPE_FP32 = 1, IPEPS_DTYPE_BF16 = 2 };
  * trotter_order: must be 2.  layer_J / layer_V multiply J and V on the bonds
  * of the layers H_A, H_B, V_A, V_B, and layer_w sets their field weight w:
  * hooks for exactly solvable limits (a dimer lattice, decoupled chains);
- * ipeps_config_default() sets 1, 1, 1/4.  flags: reserved, 0. */
+ * ipeps_config_default() sets 1, 1, 1/4.  flags: IPEPS_FLAG_AUTOTUNE picks
+ * every GEMM group's tile kind by timing the candidates once at ipeps_init
+ * (cached per process by shape; results may then differ from the default
+ * heuristic choice at rounding level); default 0. */
+#define IPEPS_FLAG_AUTOTUNE 1u
+
 typedef struct {
     int D, chi, d_A;
     double J, V, W, dt;

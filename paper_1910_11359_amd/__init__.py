@@ -3,5 +3,5 @@
 The compute path is the gfx950 library ``libipeps.so`` (HIP kernels behind the
 C ABI in include/ipeps.h); this package only marshals arguments to it.
 """
-from .native import (Config, IpepsError, Obs, Server, State, footprint_bytes, load,  # noqa: F401
+from .native import (FLAG_AUTOTUNE, Config, IpepsError, Obs, Server, State, footprint_bytes, load,  # noqa: F401
                      make_config)

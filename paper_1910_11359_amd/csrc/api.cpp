@@ -4,7 +4,10 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
+#include <string>
 
 #include "ctm.h"
 #include "gemm.h"
@@ -86,15 +89,84 @@ void validate(const ipeps_config* c) {
                   "non-finite model parameter");
 }
 
+// Opt-in autotuner (IPEPS_FLAG_AUTOTUNE): every candidate tile kind of a group
+// is timed on the state's own buffers (one warm-up and two timed launches)
+// and the fastest kept; choices are cached per process by problem shape.
+// Different tile kinds sum in different orders, so results can differ from
+// the default (heuristic) choice at rounding level.
+std::mutex g_tune_mu;
+std::map<std::string, GemmTile> g_tune_cache;
+
+std::string group_signature(const std::vector<GemmProb>& probs, int dtype) {
+    std::string k = std::to_string(dtype);
+    for (const auto& p : probs) {
+        k += "|" + std::to_string(p.M) + "," + std::to_string(p.N) + "," + std::to_string(p.K) + "," +
+             std::to_string(p.ksplit) + "," + std::to_string(p.a_ks == 1) +
+             std::to_string(p.b_cs == 1) + std::to_string(p.a_rows0 == p.M) +
+             std::to_string(p.c_rows0 == p.M) + std::to_string(p.beta != 0.0);
+    }
+    return k;
+}
+
+GemmTile autotune_tile(ipeps_state* st, std::vector<GemmProb> probs, int dtype, long reduce_elems,
+                       GemmTile fallback) {
+    for (const auto& p : probs)
+        if (p.gate) return fallback;  // a gated group may skip its work while timed
+    const std::string key = group_signature(probs, dtype);
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune_cache.find(key);
+        if (it != g_tune_cache.end()) return it->second;
+    }
+    const int n = (int)probs.size();
+    if ((int)st->tune_cap < n) {
+        if (st->tune_dev) HIP_CHECK(hipFree(st->tune_dev));
+        HIP_CHECK(hipMalloc(&st->tune_dev, n * sizeof(GemmProb)));
+        st->tune_cap = n;
+    }
+    GemmTile cand[4];
+    const int nc = gemm_tile_candidates(probs.data(), n, dtype, cand);
+    GemmTile best = fallback;
+    float best_ms = 1e30f;
+    for (int c = 0; c < nc; ++c) {
+        std::vector<GemmProb> q = probs;
+        const int tiles = gemm_plan_with(q.data(), n, dtype, cand[c]);
+        HIP_CHECK(hipMemcpy(st->tune_dev, q.data(), n * sizeof(GemmProb), hipMemcpyHostToDevice));
+        gemm_launch(st->stream, dtype, cand[c], (const GemmProb*)st->tune_dev, n, tiles, 0, reduce_elems);
+        HIP_CHECK(hipEventRecord(st->tune_ev[0], st->stream));
+        for (int r = 0; r < 2; ++r)
+            gemm_launch(st->stream, dtype, cand[c], (const GemmProb*)st->tune_dev, n, tiles, 0, reduce_elems);
+        HIP_CHECK(hipEventRecord(st->tune_ev[1], st->stream));
+        HIP_CHECK(hipEventSynchronize(st->tune_ev[1]));
+        float ms = 0.0f;
+        HIP_CHECK(hipEventElapsedTime(&ms, st->tune_ev[0], st->tune_ev[1]));
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = cand[c];
+        }
+    }
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_cache[key] = best;
+    return best;
+}
+
 GemmGroup add_group(ipeps_state* st, std::vector<GemmProb> probs, int dtype) {
     GemmGroup g;
     g.first = (int)st->probs.size();
     g.count = (int)probs.size();
     g.dtype = dtype;
     g.tiles = gemm_plan_tiles(probs.data(), g.count, dtype, &g.tile);
+    for (const auto& p : probs)
+        if (p.ksplit > 1) g.reduce_elems = std::max(g.reduce_elems, (long)p.M * p.N);
+    if (st->autotune && g.count > 0) {
+        const GemmTile t = autotune_tile(st, probs, dtype, g.reduce_elems, g.tile);
+        if (t != g.tile) {
+            g.tile = t;
+            g.tiles = gemm_plan_with(probs.data(), g.count, dtype, t);
+        }
+    }
     for (auto& p : probs) {
         g.flops += 2.0 * p.M * (double)p.N * p.K;
-        if (p.ksplit > 1) g.reduce_elems = std::max(g.reduce_elems, (long)p.M * p.N);
         st->probs.push_back(p);
     }
     return g;
@@ -778,6 +850,11 @@ int ipeps_init(const ipeps_config* cfg, void* hip_stream, ipeps_alloc_fn alloc, 
         HIP_CHECK(hipEventCreateWithFlags(&st->ev_c64_ready, hipEventDisableTiming));
         HIP_CHECK(hipEventCreateWithFlags(&st->ev_spec_done, hipEventDisableTiming));
         HIP_CHECK(hipHostMalloc((void**)&st->host_buf, 65536 * sizeof(double), hipHostMallocDefault));
+        st->autotune = (cfg->flags & IPEPS_FLAG_AUTOTUNE) != 0;
+        if (st->autotune) {
+            HIP_CHECK(hipEventCreate(&st->tune_ev[0]));
+            HIP_CHECK(hipEventCreate(&st->tune_ev[1]));
+        }
         build_layers(st);
         build_plan(st);
         build_gates(st->stream, st->cfg, st->gates);
@@ -805,6 +882,9 @@ void ipeps_destroy(ipeps_state* st) {
     if (st->ev_su_done) (void)hipEventDestroy(st->ev_su_done);
     if (st->d_probs) (void)hipFree(st->d_probs);
     if (st->d_norms) (void)hipFree(st->d_norms);
+    if (st->tune_dev) (void)hipFree(st->tune_dev);
+    for (auto& e : st->tune_ev)
+        if (e) (void)hipEventDestroy(e);
     if (st->host_buf) (void)hipHostFree(st->host_buf);
     for (auto& e : st->prof_ev) (void)hipEventDestroy(e);
     delete st;

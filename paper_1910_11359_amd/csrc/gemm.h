@@ -45,9 +45,16 @@ GemmProb gemm_general(const void* A, bool transA, long lda, const void* B, bool 
 // of the 16-byte vector.
 enum GemmTile { TILE_LARGE = 0, TILE_SMALL = 1, TILE_DIRECT = 2, TILE_DIRECT_SMALL = 3 };
 
-// Chooses the tile shape for a group and fills tiles_n / tile_begin;
-// returns the total number of tiles (the grid size).
+// Chooses the tile shape for a group by a size heuristic and fills tiles_n /
+// tile_begin; returns the total number of tiles (the grid size).
 int gemm_plan_tiles(GemmProb* probs, int n, int dtype, GemmTile* tile);
+
+// Tile kinds that can run the group (at most 4; the direct ones only where
+// the operand layout allows them); returns their number.
+int gemm_tile_candidates(const GemmProb* probs, int n, int dtype, GemmTile* out);
+
+// Fills tiles_n / tile_begin for a given tile kind; returns the total tiles.
+int gemm_plan_with(GemmProb* probs, int n, int dtype, GemmTile tile);
 
 // Launch on `stream`; d_probs is a device copy of the planned descriptors.
 // tag 1 selects a separate kernel symbol for the cut products (profiling).

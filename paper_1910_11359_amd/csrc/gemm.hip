@@ -248,6 +248,33 @@ static void tile_dims(int dtype, GemmTile tile, int* bm, int* bn) {
     }
 }
 
+static bool direct_ok(const GemmProb* probs, int n, int dtype) {
+    const long vw = dtype == IPEPS_DTYPE_FP64 ? 2 : 4;
+    for (int i = 0; i < n; ++i) {
+        const GemmProb& p = probs[i];
+        if (!(p.a_ks == 1 && p.a_rs0 % vw == 0 && p.a_rs1 % vw == 0 && p.K % vw == 0 &&
+              p.K >= vw && ((uintptr_t)p.A & 15) == 0 && p.b_cs == 1 && p.b_ks % vw == 0 &&
+              p.N % vw == 0 && p.N >= vw && ((uintptr_t)p.B & 15) == 0))
+            return false;
+    }
+    return true;
+}
+
+int gemm_plan_with(GemmProb* probs, int n, int dtype, GemmTile tile) {
+    int bm, bn;
+    tile_dims(dtype, tile, &bm, &bn);
+    int total = 0;
+    for (int i = 0; i < n; ++i) {
+        int tm = ceil_div(probs[i].M, bm), tnn = ceil_div(probs[i].N, bn);
+        if (probs[i].M <= 0 || probs[i].N <= 0) tm = tnn = 0;
+        if (probs[i].ksplit < 1) probs[i].ksplit = 1;
+        probs[i].tiles_n = tnn > 0 ? tnn : 1;
+        probs[i].tile_begin = total;
+        total += tm * tnn * probs[i].ksplit;
+    }
+    return total;
+}
+
 int gemm_plan_tiles(GemmProb* probs, int n, int dtype, GemmTile* tile) {
     // large tiles when the launch still has >= 2 workgroups per CU with them
     // and few problems are thinner than a large tile
@@ -260,29 +287,19 @@ int gemm_plan_tiles(GemmProb* probs, int n, int dtype, GemmTile* tile) {
         large_tiles += (long)ceil_div(probs[i].M, 128) * ceil_div(probs[i].N, 128) * ks;
     }
     *tile = (small_work * 4 > all_work || large_tiles < 512) ? TILE_SMALL : TILE_LARGE;
-    {
-        const long vw = dtype == IPEPS_DTYPE_FP64 ? 2 : 4;
-        bool direct = true;
-        for (int i = 0; i < n && direct; ++i) {
-            const GemmProb& p = probs[i];
-            direct = p.a_ks == 1 && p.a_rs0 % vw == 0 && p.a_rs1 % vw == 0 && p.K % vw == 0 &&
-                     p.K >= vw && ((uintptr_t)p.A & 15) == 0 && p.b_cs == 1 && p.b_ks % vw == 0 &&
-                     p.N % vw == 0 && p.N >= vw && ((uintptr_t)p.B & 15) == 0;
-        }
-        if (direct) *tile = (*tile == TILE_LARGE) ? TILE_DIRECT : TILE_DIRECT_SMALL;
+    if (direct_ok(probs, n, dtype)) *tile = (*tile == TILE_LARGE) ? TILE_DIRECT : TILE_DIRECT_SMALL;
+    return gemm_plan_with(probs, n, dtype, *tile);
+}
+
+int gemm_tile_candidates(const GemmProb* probs, int n, int dtype, GemmTile* out) {
+    int c = 0;
+    if (direct_ok(probs, n, dtype)) {
+        out[c++] = TILE_DIRECT;
+        out[c++] = TILE_DIRECT_SMALL;
     }
-    int bm, bn;
-    tile_dims(dtype, *tile, &bm, &bn);
-    int total = 0;
-    for (int i = 0; i < n; ++i) {
-        int tm = ceil_div(probs[i].M, bm), tnn = ceil_div(probs[i].N, bn);
-        if (probs[i].M <= 0 || probs[i].N <= 0) tm = tnn = 0;
-        if (probs[i].ksplit < 1) probs[i].ksplit = 1;
-        probs[i].tiles_n = tnn > 0 ? tnn : 1;
-        probs[i].tile_begin = total;
-        total += tm * tnn * probs[i].ksplit;
-    }
-    return total;
+    out[c++] = TILE_LARGE;
+    out[c++] = TILE_SMALL;
+    return c;
 }
 
 // ---------------------------------------------------------------------------

@@ -145,6 +145,10 @@ struct ipeps_state {
     ipeps::GemmProb* d_probs;
     std::vector<ipeps::NormItem> norms;
     ipeps::NormItem* d_norms;
+    bool autotune;              // IPEPS_FLAG_AUTOTUNE
+    void* tune_dev;             // device copy of a group being timed
+    int tune_cap;
+    hipEvent_t tune_ev[2];
     long norm_a_first;    // 4 FP64 items: the double-layer tensors
     long norm_env_first;  // 32 dtype items: the 16 corners and 16 edges
     ipeps::ColumnStep steps[8];  // frame f (in move order) * 2 + X

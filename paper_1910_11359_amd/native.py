@@ -21,6 +21,7 @@ IPEPS_ENOTCONV = -5
 IPEPS_EAGAIN = -6
 IPEPS_ENOTFOUND = -7
 DTYPES = {"fp64": 0, "fp32": 1, "bf16": 2}
+FLAG_AUTOTUNE = 1
 JOB_QUEUED, JOB_RUNNING, JOB_DONE = 0, 1, 2
 
 
@@ -120,7 +121,7 @@ def _check(code, where):
 
 
 def make_config(D, chi, J=1.0, V=1.0, W=5.0, dt=0.05, d_A=2, dtype="fp64", layer_J=None,
-                layer_V=None, layer_w=None, seed=1):
+                layer_V=None, layer_w=None, seed=1, flags=0):
     lib = load()
     c = Config()
     lib.ipeps_config_default(C.byref(c))
@@ -133,6 +134,7 @@ def make_config(D, chi, J=1.0, V=1.0, W=5.0, dt=0.05, d_A=2, dtype="fp64", layer
             for i in range(4):
                 arr[i] = float(val[i])
     c.seed = int(seed)
+    c.flags = int(flags)
     return c
 
 

@@ -48,14 +48,16 @@ def test_small_workload_vs_oracle():
         assert np.max(np.abs(g["renyi_half"] - o["renyi_half"])) < 1e-6, step
 
 
-@pytest.mark.parametrize("D,chi,seed", [(2, 8, 3), (3, 9, 4), (3, 12, 5), (4, 16, 6)])
-def test_random_state_vs_oracle(D, chi, seed):
+@pytest.mark.parametrize("D,chi,seed,flags", [(2, 8, 3, 0), (3, 9, 4, 0), (3, 12, 5, 0), (4, 16, 6, 0),
+                                              (4, 16, 7, 1)])
+def test_random_state_vs_oracle(D, chi, seed, flags):
     """Seeded random site tensors and bond weights (full rank at every
     bond): CTMRG from the state, one Trotter step, CTMRG again.  Covers the
-    direct projector SVD (n <= 96) and the subspace-iteration one."""
+    direct projector SVD (n <= 96) and the subspace-iteration one; flags=1
+    runs with autotuned GEMM tiles."""
     gam, lam = synthetic.random_state(seed, D)
     kw = dict(J=1.0, V=1.0, W=3.0, dt=0.05)
-    st = _gpu_state(D, chi, **kw)
+    st = _gpu_state(D, chi, flags=flags, **kw)
     st.set_state(gam, lam)
     p = par.oracle_params(D, chi, **kw)
     ost = par.oracle_state_from(gam, lam, p)
@@ -146,6 +148,24 @@ def test_dimer_limit_closed_form():
         st.ctmrg(0.0, 2, True)
         g = st.observe()
         assert abs(g["imbalance"] - _dimer_exact(g["t"], 1.0, 5.0)) < 1e-10
+
+
+@pytest.mark.parametrize("dtype,tol", [("fp64", 1e-9), ("fp32", 1e-4)])
+def test_autotuned_tiles_match_heuristic(dtype, tol):
+    """D=4, chi=32: the autotuned tile kinds change only the summation order
+    of the GEMMs, so observables agree with the default plan to rounding."""
+    kw = dict(J=1.0, V=1.0, W=5.0, dt=0.05, dtype=dtype)
+    out = []
+    for flags in (0, P.FLAG_AUTOTUNE):
+        st = _gpu_state(4, 32, flags=flags, **kw)
+        st.trotter_step(4)
+        st.ctmrg(0.0, 8, True)
+        st.trotter_step(2)
+        st.ctmrg(0.0, 3, False)
+        out.append(st.observe())
+        st.close()
+    assert np.max(np.abs(out[0]["n"] - out[1]["n"])) < tol
+    assert abs(out[0]["imbalance"] - out[1]["imbalance"]) < tol
 
 
 def test_zero_hopping_keeps_neel():
