@@ -435,13 +435,10 @@ void build_plan(ipeps_state* st) {
         P.QfromZ = mulR(st->Zw, st->Qz);
         P.gramQz = gram(st->Qz);
         P.ZfromQz = mulR(st->Qz, st->Zw);
-        // final: Qw = N V (V in Qz), Cs = Yw^T Qw, Uo = Yw Uc, Vo = Qz Vc
-        P.NVfinal = batch2([&](int b) {
-            return split(gemm_nn(st->N64 + b * n2, n, st->Qz + b * nk, k, st->Qw + b * nk, k, n, k, n),
-                         kv, wv + b * kv * nk);
-        });
+        // final: Zw = N V (a copy of Yw before its orthonormalisation, V in
+        // Qz), Cs = Yw^T Zw, Uo = Yw Uc, Vo = Qz Vc
         P.Cs = batch2([&](int b) {
-            return split(gemm_general(st->Yw + b * nk, true, k, st->Qw + b * nk, false, k,
+            return split(gemm_general(st->Yw + b * nk, true, k, st->Zw + b * nk, false, k,
                                       st->Cs + b * kk, k, k, k, n),
                          kg, wg + b * kg * kk);
         });
@@ -678,9 +675,9 @@ void projector_svd(ipeps_state* st, int slot) {
     }
     // Rayleigh-Ritz on span(N V) x span(V)
     run(st, P.NV);
+    HIP_CHECK(hipMemcpyAsync(st->Zw, st->Yw, 2 * nk * sizeof(double), hipMemcpyDeviceToDevice, s));
     orth(st, st->Yw, st->Qw, P.gramY, P.QfromY, P.gramQ, P.YfromQ, true);
-    run(st, P.NVfinal);  // Qw = N V
-    run(st, P.Cs);       // Cs = Q^T N V
+    run(st, P.Cs);  // Cs = Q^T N V
     // Rayleigh-Ritz SVD.  Columns are left unrotated only below 1e-14 |Cs|_F,
     // far under the projector cutoff: a kept direction that was never rotated
     // against the dominant ones would break P_up P_low = 1.  (Taking the right

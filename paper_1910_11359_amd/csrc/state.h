@@ -45,7 +45,7 @@ struct ColumnStep {
 struct SvdPlan {
     // orth passes on Y and Z and the Rayleigh-Ritz products, batch 2 (FP64)
     GemmGroup NV, NtQ, gramY, gramZ, gramQ, gramQz, QfromY, QfromZ, YfromQ, ZfromQz, Cs, Uo,
-        Vo, NVfinal;
+        Vo;
     // restart of dropped left columns: Gm = Qw^T Rb, Rb -= Qw Gm
     GemmGroup projQw1, projQw2;
 
