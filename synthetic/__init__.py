@@ -16,6 +16,14 @@ dataset, its workloads are parameter points):
     sweep       64 jobs: D in {3,4,5,6} x V in {0,1} x 8 W values drawn from
                 default_rng(1911359).uniform(1, 20, 8); chi = 2 D^2; 50 steps
     serving     256 requests from default_rng(20191025)
+
+Free-fermion workload (the paper's non-interacting comparison: L x L
+lattices, 100 disorder realizations, Néel start, t up to 5):
+    ff          L in {10, 20, 40} x h in {4, 10, 100} x {continuous, 3-level}
+    ff headline L = 40, h = 10, continuous, 100 realizations, 50 observations
+                every 0.1 (tau = 1/2, the hopping of J (SxSx + SySy) at J = 1)
+Fields: continuous eps ~ h U[-1, 1]; s-level eps = h z with z uniform over s
+equally spaced values in [-1, 1] (s = 3: spin-1 levels -h, 0, h).
 """
 import numpy as np
 
@@ -78,3 +86,22 @@ def random_state(seed, D, d_A=2, lam_min=0.05):
     lam = np.sort(rng.uniform(lam_min, 1.0, (8, D)), axis=1)[:, ::-1]
     lam = lam / np.linalg.norm(lam, axis=1, keepdims=True)
     return gamma, np.ascontiguousarray(lam)
+
+
+def ff_configs():
+    return [dict(L=L, h=h, kind=kind, n_real=100, tau=0.5, pbc=False, dt=0.1, n_times=50)
+            for L in (10, 20, 40) for h in (4.0, 10.0, 100.0) for kind in ("continuous", "discrete3")]
+
+
+def ff_headline():
+    return dict(L=40, h=10.0, kind="continuous", n_real=100, tau=0.5, pbc=False, dt=0.1, n_times=50)
+
+
+def ff_fields(L, n_real, h, kind, seed):
+    """Seeded on-site fields, shape (n_real, L*L), FP64."""
+    rng = np.random.default_rng(seed)
+    if kind == "continuous":
+        return h * rng.uniform(-1.0, 1.0, (n_real, L * L))
+    s = int(kind.replace("discrete", ""))
+    levels = np.linspace(-1.0, 1.0, s)
+    return h * levels[rng.integers(0, s, (n_real, L * L))]
