@@ -1,0 +1,58 @@
+/* Free-fermion Néel dynamics on one gfx950 GPU: the non-interacting
+ * comparison workload of arXiv:1910.11359 (section "Set up for
+ * non-interacting fermions"; results for the non-interacting case, the
+ * free-fermion figure: mean occupation of the two sublattices of a finite
+ * lattice after a Néel start, averaged over disorder realizations).
+ *
+ * Model: L x L square lattice, site i = x*L + y (0 <= x, y < L), one orbital
+ * per site, single-particle Hamiltonian
+ *     h = -tau * sum over nearest-neighbour pairs (|i><j| + |j><i|) + sum_i eps_i |i><i|
+ * with open boundaries (pbc = 0) or periodic ones in both directions
+ * (pbc = 1, L >= 3).  Start: the Néel state, sites with x + y even filled.
+ * Without interactions the state stays a Slater determinant of the orbitals
+ * that start on the filled sites, each evolving as exp(-i h t) e_j; the
+ * library integrates them exactly (Chebyshev expansion of the propagator over
+ * each interval dt, split so that each piece needs at most a few tens of
+ * terms) and never forms h densely.
+ *
+ * Error codes are those of ipeps.h. */
+#ifndef FF_H
+#define FF_H
+
+#include "ipeps.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Runs n_real independent realizations on hip_stream (NULL: the default
+ * stream) and returns after enqueueing; results are valid once the stream
+ * has completed.
+ *   L        1..45 (L*L <= 2048)
+ *   pbc      0 open, 1 periodic (needs L >= 3)
+ *   tau      hopping amplitude (finite; tau = 1/2 is the hopping of the
+ *            spin model's J (SxSx + SySy) at J = 1)
+ *   dt       observation interval (> 0); observations at t = m*dt, m = 1..n_times
+ *   eps      DEVICE, FP64, n_real * L*L on-site fields, realization-major
+ *   n_even   DEVICE, FP64, n_real * n_times outputs: mean occupation of the
+ *            initially filled sublattice (x + y even), [r*n_times + m - 1]
+ *   n_odd    DEVICE, FP64, same layout, the other sublattice (0 when L = 1)
+ * The caller owns all buffers; the library allocates a stream-ordered
+ * workspace of 16 * n_real * n_times * ceil(L*L/2) bytes for the call.
+ * The imbalance of the iPEPS readout corresponds to n_even - n_odd.
+ * Returns IPEPS_OK, IPEPS_EINVAL (argument out of range, a NULL buffer with
+ * work to do, n_real > 65535), IPEPS_ENOMEM, IPEPS_EDEVICE.  NaN fields give
+ * NaN outputs. */
+int ff_neel_dynamics(int L, int pbc, double tau, double dt, int n_times, int n_real,
+                     const double* eps, double* n_even, double* n_odd, void* hip_stream);
+
+/* Host copy of the Bessel-function routine behind the propagator's
+ * coefficients: J_0(x) .. J_kmax(x) into out[0..kmax] (host), x >= 0,
+ * 0 <= kmax <= 200.  Returns IPEPS_OK or IPEPS_EINVAL. */
+int ff_bessel_j(double x, int kmax, double* out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif

@@ -74,4 +74,5 @@ def neel_dynamics(L, pbc, tau, eps, times):
     each time: arrays n_even, n_odd of shape (len(times),)."""
     n = occupations(L, pbc, tau, eps, times)
     ev = sublattice(L)
-    return n[:, ev].mean(axis=1), n[:, ~ev].mean(axis=1)
+    odd = n[:, ~ev].mean(axis=1) if (~ev).any() else np.zeros(len(times))  # L = 1: no odd site
+    return n[:, ev].mean(axis=1), odd

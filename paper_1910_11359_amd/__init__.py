@@ -4,4 +4,4 @@ The compute path is the gfx950 library ``libipeps.so`` (HIP kernels behind the
 C ABI in include/ipeps.h); this package only marshals arguments to it.
 """
 from .native import (FLAG_AUTOTUNE, Config, IpepsError, Obs, Server, State, footprint_bytes, load,  # noqa: F401
-                     make_config)
+                     ff_bessel_j, ff_neel_dynamics, ff_neel_dynamics_device, make_config)

@@ -23,7 +23,7 @@ FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-result", "-Wno-unused-command-line-argument",
 ]
-SOURCES = ["gemm.hip", "linalg.hip", "su.hip", "ctm.hip", "api.cpp", "server.cpp"]
+SOURCES = ["gemm.hip", "linalg.hip", "su.hip", "ctm.hip", "ff.hip", "api.cpp", "server.cpp"]
 
 
 def _compile(src):

@@ -1,0 +1,342 @@
+// Free-fermion Néel dynamics (non-interacting comparison workload).
+//
+// One workgroup per (realization r, filled orbital j): the orbital's L*L
+// complex amplitudes stay in registers (S sites per thread) for the whole
+// run, and the hopping term is applied as a five-point stencil through a
+// double-buffered LDS copy (one barrier per application).  Each observation
+// interval is split into pieces whose Chebyshev argument a*dt is at most
+// kMaxArg, and each piece applies
+//     exp(-i h dt) = exp(-i b dt) sum_k (2 - [k = 0]) (-i)^k J_k(a dt) T_k((h - b) / a)
+// (Chebyshev polynomials of the shifted, scaled Hamiltonian, whose spectrum
+// lies in [-1, 1] by Gershgorin's bound a = (max eps - min eps)/2 + 4|tau|,
+// b = (max eps + min eps)/2), truncated where |J_k| < 1e-18.  After each
+// interval the orbital's weight on the two sublattices is written to a
+// workspace; a second kernel sums the orbitals of each (r, t) in a fixed
+// order, so results are deterministic.
+#include "../../include/ff.h"
+
+#include <algorithm>
+#include <cmath>
+
+#include "common.h"
+
+namespace ipeps {
+namespace {
+
+constexpr int kFfThreads = 256;
+constexpr int kFfMaxTerms = 160;    // coefficients kept per piece
+constexpr double kFfMaxArg = 60.0;  // a * dt per piece
+constexpr double kFfCut = 1e-18;    // |J_k| below which the series stops
+
+// J_0(x) .. J_kmax(x), x >= 0.  x < 0.5: power series; otherwise the
+// backward recurrence J_{k-1} = (2k/x) J_k - J_{k+1} started well above
+// max(kmax, x) (Miller's method), normalised by J_0 + 2 sum_{m>=1} J_{2m} = 1
+// and rescaled whenever it grows beyond 1e200.
+__host__ __device__ inline void bessel_j_seq(double x, int kmax, double* J) {
+    if (x == 0.0) {
+        J[0] = 1.0;
+        for (int k = 1; k <= kmax; ++k) J[k] = 0.0;
+        return;
+    }
+    if (x < 0.5) {
+        const double h = 0.5 * x, h2 = h * h;
+        double lead = 1.0;  // (x/2)^k / k!
+        for (int k = 0; k <= kmax; ++k) {
+            if (k > 0) lead *= h / k;
+            double term = lead, sum = lead;
+            for (int m = 1; m <= 12; ++m) {
+                term *= -h2 / ((double)m * (double)(m + k));
+                sum += term;
+            }
+            J[k] = sum;
+        }
+        return;
+    }
+    const int base = kmax > (int)x ? kmax : (int)x;
+    int top = base + 40 + (int)(4.0 * sqrt((double)base));
+    top += top & 1;
+    double jp = 0.0, jc = 1e-30, norm = 0.0;
+    for (int k = top; k >= 1; --k) {
+        const double jm = (2.0 * k / x) * jc - jp;  // J_{k-1} up to a common factor
+        const int km = k - 1;
+        if (km <= kmax) J[km] = jm;
+        if (km == 0) norm += jm;
+        else if ((km & 1) == 0) norm += 2.0 * jm;
+        jp = jc;
+        jc = jm;
+        if (fabs(jc) > 1e200) {
+            jc *= 1e-200;
+            jp *= 1e-200;
+            norm *= 1e-200;
+            for (int q = km; q <= kmax; ++q) J[q] *= 1e-200;
+        }
+    }
+    const double inv = 1.0 / norm;
+    for (int k = 0; k <= kmax; ++k) J[k] *= inv;
+}
+
+template <int S>
+__global__ __launch_bounds__(kFfThreads) void k_ff_neel(int L, int pbc, double tau, double dt, int n_times,
+                                                        const double* __restrict__ eps_all, int M,
+                                                        double* __restrict__ part_e, double* __restrict__ part_o) {
+    extern __shared__ double lds[];  // [2 buffers][re, im][L*L]
+    __shared__ double cj[kFfMaxTerms];
+    __shared__ double red[kFfThreads / 64];
+    __shared__ int sh_K, sh_site;
+    const int nsite = L * L, tid = threadIdx.x;
+    const int j = blockIdx.x, r = blockIdx.y;
+    const double* eps = eps_all + (long)r * nsite;
+
+    double ep[S];
+    int nb[S][4];
+    double lo = 1e300, hi = -1e300;
+#pragma unroll
+    for (int e = 0; e < S; ++e) {
+        const int i = tid + e * kFfThreads;
+        ep[e] = 0.0;
+        nb[e][0] = nb[e][1] = nb[e][2] = nb[e][3] = -1;
+        if (i < nsite) {
+            ep[e] = eps[i];
+            lo = fmin(lo, ep[e]);
+            hi = fmax(hi, ep[e]);
+            const int x = i / L, y = i - (i / L) * L;
+            if (pbc) {
+                nb[e][0] = ((x + L - 1) % L) * L + y;
+                nb[e][1] = ((x + 1) % L) * L + y;
+                nb[e][2] = x * L + (y + L - 1) % L;
+                nb[e][3] = x * L + (y + 1) % L;
+            } else {
+                if (x > 0) nb[e][0] = i - L;
+                if (x + 1 < L) nb[e][1] = i + L;
+                if (y > 0) nb[e][2] = i - 1;
+                if (y + 1 < L) nb[e][3] = i + 1;
+            }
+        }
+    }
+    hi = block_max(hi, red);
+    lo = -block_max(-lo, red);
+    const double b = 0.5 * (hi + lo);
+    double a = 0.5 * (hi - lo) + 4.0 * fabs(tau);
+    if (!(a > 0.0)) a = 1.0;  // h = b: any positive a is a valid bound
+    const double ia = 1.0 / a;
+    const double xtot = a * dt;
+    if (!(xtot <= kFfMaxArg * 1e5)) {
+        // infinite fields, or more than 1e5 pieces per interval: NaN outputs
+        if (tid == 0)
+            for (int m = 0; m < n_times; ++m) {
+                const long q = ((long)r * n_times + m) * M + j;
+                part_e[q] = part_o[q] = __builtin_nan("");
+            }
+        return;
+    }
+    int nsub = (int)ceil(xtot / kFfMaxArg);
+    nsub = nsub < 1 ? 1 : nsub;
+    const double xs = xtot / nsub, dts = dt / nsub;
+    if (tid == 0) {
+        bessel_j_seq(xs, kFfMaxTerms - 1, cj);
+        int K = kFfMaxTerms;
+        while (K > 1 && fabs(cj[K - 1]) < kFfCut) --K;
+        sh_K = K;
+        // j-th filled site in increasing site order (row x holds (L - (x & 1) + 1) / 2)
+        int rem = j, x = 0;
+        while (rem >= (L - (x & 1) + 1) / 2) {
+            rem -= (L - (x & 1) + 1) / 2;
+            ++x;
+        }
+        sh_site = x * L + (x & 1) + 2 * rem;
+    }
+    __syncthreads();
+    const int K = sh_K, site = sh_site;
+    const double cph = cos(b * dts), sph = -sin(b * dts);  // exp(-i b dts)
+
+    double t0r[S], t0i[S], t1r[S], t1i[S], ar[S], ai[S];
+#pragma unroll
+    for (int e = 0; e < S; ++e) {
+        t0r[e] = (tid + e * kFfThreads == site) ? 1.0 : 0.0;
+        t0i[e] = 0.0;
+    }
+    int par = 0;
+    // out <- (h - b)/a applied to (inr, ini), through LDS buffer par
+    auto apply = [&](const double* inr, const double* ini, double* outr, double* outi) {
+        double* br = lds + (long)par * 2 * nsite;
+        double* bi = br + nsite;
+#pragma unroll
+        for (int e = 0; e < S; ++e) {
+            const int i = tid + e * kFfThreads;
+            if (i < nsite) {
+                br[i] = inr[e];
+                bi[i] = ini[e];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < S; ++e) {
+            double sr = 0.0, si = 0.0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int n = nb[e][q];
+                if (n >= 0) {
+                    sr += br[n];
+                    si += bi[n];
+                }
+            }
+            outr[e] = ((ep[e] - b) * inr[e] - tau * sr) * ia;
+            outi[e] = ((ep[e] - b) * ini[e] - tau * si) * ia;
+        }
+        par ^= 1;
+    };
+    for (int m = 0; m < n_times; ++m) {
+        for (int s = 0; s < nsub; ++s) {
+            const double w0 = cj[0];
+#pragma unroll
+            for (int e = 0; e < S; ++e) {
+                ar[e] = w0 * t0r[e];
+                ai[e] = w0 * t0i[e];
+            }
+            if (K > 1) {
+                apply(t0r, t0i, t1r, t1i);
+                const double w1 = 2.0 * cj[1];  // (-i) 2 J_1
+#pragma unroll
+                for (int e = 0; e < S; ++e) {
+                    ar[e] += w1 * t1i[e];
+                    ai[e] -= w1 * t1r[e];
+                }
+            }
+            for (int k = 2; k < K; ++k) {
+                double t2r[S], t2i[S];
+                apply(t1r, t1i, t2r, t2i);
+                const double w = 2.0 * cj[k];
+                const int ph = k & 3;
+#pragma unroll
+                for (int e = 0; e < S; ++e) {
+                    const double nr = 2.0 * t2r[e] - t0r[e], ni = 2.0 * t2i[e] - t0i[e];
+                    t0r[e] = t1r[e];
+                    t0i[e] = t1i[e];
+                    t1r[e] = nr;
+                    t1i[e] = ni;
+                    // acc += (-i)^k w T_k
+                    if (ph == 0) {
+                        ar[e] += w * nr;
+                        ai[e] += w * ni;
+                    } else if (ph == 1) {
+                        ar[e] += w * ni;
+                        ai[e] -= w * nr;
+                    } else if (ph == 2) {
+                        ar[e] -= w * nr;
+                        ai[e] -= w * ni;
+                    } else {
+                        ar[e] -= w * ni;
+                        ai[e] += w * nr;
+                    }
+                }
+            }
+#pragma unroll
+            for (int e = 0; e < S; ++e) {
+                t0r[e] = cph * ar[e] - sph * ai[e];
+                t0i[e] = cph * ai[e] + sph * ar[e];
+            }
+        }
+        double se = 0.0, so = 0.0;
+#pragma unroll
+        for (int e = 0; e < S; ++e) {
+            const int i = tid + e * kFfThreads;
+            if (i < nsite) {
+                const double p = t0r[e] * t0r[e] + t0i[e] * t0i[e];
+                if ((((i / L) + (i - (i / L) * L)) & 1) == 0) se += p;
+                else so += p;
+            }
+        }
+        se = block_sum(se, red);
+        so = block_sum(so, red);
+        if (tid == 0) {
+            const long q = ((long)r * n_times + m) * M + j;
+            part_e[q] = se;
+            part_o[q] = so;
+        }
+    }
+}
+
+// n[q] = scale * sum_j part[q*M + j], fixed order (block tree over j)
+__global__ __launch_bounds__(256) void k_ff_sum(int M, const double* __restrict__ part_e,
+                                                const double* __restrict__ part_o, double se, double so,
+                                                double* __restrict__ n_even, double* __restrict__ n_odd) {
+    __shared__ double red[4];
+    const long q = blockIdx.x;
+    double ae = 0.0, ao = 0.0;
+    for (int j = threadIdx.x; j < M; j += blockDim.x) {
+        ae += part_e[q * M + j];
+        ao += part_o[q * M + j];
+    }
+    ae = block_sum(ae, red);
+    ao = block_sum(ao, red);
+    if (threadIdx.x == 0) {
+        n_even[q] = ae * se;
+        n_odd[q] = ao * so;
+    }
+}
+
+template <int S>
+hipError_t launch_ff(hipStream_t s, int L, int pbc, double tau, double dt, int n_times, int n_real,
+                     const double* eps, int M, double* pe, double* po) {
+    const size_t lds = (size_t)4 * L * L * sizeof(double);
+    static bool attr_set = false;  // L*L <= 2048: up to 64 KB of dynamic LDS
+    if (!attr_set) {
+        const hipError_t e = hipFuncSetAttribute((const void*)k_ff_neel<S>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                 4 * 2048 * (int)sizeof(double));
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
+    hipLaunchKernelGGL(k_ff_neel<S>, dim3(M, n_real), dim3(kFfThreads), lds, s, L, pbc, tau, dt, n_times, eps, M,
+                       pe, po);
+    return hipGetLastError();
+}
+
+}  // namespace
+}  // namespace ipeps
+
+extern "C" {
+
+int ff_bessel_j(double x, int kmax, double* out) {
+    if (!out || !(x >= 0.0) || !std::isfinite(x) || kmax < 0 || kmax > 200) return IPEPS_EINVAL;
+    ipeps::bessel_j_seq(x, kmax, out);
+    return IPEPS_OK;
+}
+
+int ff_neel_dynamics(int L, int pbc, double tau, double dt, int n_times, int n_real, const double* eps,
+                     double* n_even, double* n_odd, void* hip_stream) {
+    using namespace ipeps;
+    if (L < 1 || L * L > 2048 || (pbc != 0 && pbc != 1) || (pbc && L < 3)) return IPEPS_EINVAL;
+    if (!std::isfinite(tau) || !(dt > 0.0) || !std::isfinite(dt)) return IPEPS_EINVAL;
+    if (n_times < 0 || n_real < 0 || n_real > 65535) return IPEPS_EINVAL;
+    if (n_times == 0 || n_real == 0) return IPEPS_OK;
+    if (!eps || !n_even || !n_odd) return IPEPS_EINVAL;
+    hipStream_t s = (hipStream_t)hip_stream;
+    const int nsite = L * L, M = (nsite + 1) / 2, Mo = nsite - M;
+    const long nq = (long)n_real * n_times;
+    double* ws = nullptr;
+    if (hipMallocAsync((void**)&ws, (size_t)2 * nq * M * sizeof(double), s) != hipSuccess) {
+        (void)hipGetLastError();
+        return IPEPS_ENOMEM;
+    }
+    double* pe = ws;
+    double* po = ws + nq * M;
+    const int S = (nsite + kFfThreads - 1) / kFfThreads;
+    hipError_t e;
+    if (S <= 1) e = launch_ff<1>(s, L, pbc, tau, dt, n_times, n_real, eps, M, pe, po);
+    else if (S <= 2) e = launch_ff<2>(s, L, pbc, tau, dt, n_times, n_real, eps, M, pe, po);
+    else if (S <= 4) e = launch_ff<4>(s, L, pbc, tau, dt, n_times, n_real, eps, M, pe, po);
+    else e = launch_ff<8>(s, L, pbc, tau, dt, n_times, n_real, eps, M, pe, po);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_ff_sum, dim3((unsigned)nq), dim3(256), 0, s, M, pe, po, 1.0 / M,
+                           Mo > 0 ? 1.0 / Mo : 0.0, n_even, n_odd);
+        e = hipGetLastError();
+    }
+    const hipError_t f = hipFreeAsync(ws, s);
+    if (e != hipSuccess || f != hipSuccess) {
+        fprintf(stderr, "ff_neel_dynamics: %s\n", hipGetErrorString(e != hipSuccess ? e : f));
+        return IPEPS_EDEVICE;
+    }
+    return IPEPS_OK;
+}
+
+}  // extern "C"

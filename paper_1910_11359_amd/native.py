@@ -60,7 +60,7 @@ EXPORTS = [
     "ipeps_get_state", "ipeps_trotter_step", "ctmrg_converge", "ipeps_observe",
     "ipeps_corner_spectra", "ipeps_bond_spectra", "ipeps_destroy", "solve_server_create",
     "solve_submit", "solve_poll", "solve_job_times", "solve_server_destroy", "ipeps_strerror",
-    "ipeps_profile", "ipeps_profile_read",
+    "ipeps_profile", "ipeps_profile_read", "ff_neel_dynamics", "ff_bessel_j",
 ]
 
 _lib = None
@@ -102,6 +102,9 @@ def load():
     lib.solve_server_destroy.restype = None
     lib.ipeps_profile.argtypes = [C.c_void_p, C.c_int]
     lib.ipeps_profile_read.argtypes = [C.c_void_p, P(C.c_double), P(C.c_int), P(C.c_double)]
+    lib.ff_neel_dynamics.argtypes = [C.c_int, C.c_int, C.c_double, C.c_double, C.c_int, C.c_int,
+                                     C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+    lib.ff_bessel_j.argtypes = [C.c_double, C.c_int, P(C.c_double)]
     lib.ipeps_strerror.argtypes = [C.c_int]
     lib.ipeps_strerror.restype = C.c_char_p
     _lib = lib
@@ -268,3 +271,37 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+# ------------------------------------------------------- free-fermion dynamics
+def ff_bessel_j(x, kmax):
+    """J_0(x)..J_kmax(x) from the library's host copy of its coefficient routine."""
+    out = np.zeros(kmax + 1)
+    _check(load().ff_bessel_j(float(x), int(kmax), _dptr(out)), "ff_bessel_j")
+    return out
+
+
+def ff_neel_dynamics_device(L, eps_ptr, n_real, n_even_ptr, n_odd_ptr, n_times, dt, tau=0.5, pbc=False,
+                            stream=None):
+    """Enqueue on device buffers (raw pointers); see include/ff.h."""
+    sptr = getattr(stream, "cuda_stream", stream) if stream is not None else None
+    _check(load().ff_neel_dynamics(int(L), int(bool(pbc)), float(tau), float(dt), int(n_times), int(n_real),
+                                   C.c_void_p(eps_ptr), C.c_void_p(n_even_ptr), C.c_void_p(n_odd_ptr),
+                                   C.c_void_p(sptr)), "ff_neel_dynamics")
+
+
+def ff_neel_dynamics(L, eps, n_times, dt, tau=0.5, pbc=False):
+    """Host convenience: eps (n_real, L*L) -> (n_even, n_odd), each (n_real, n_times).
+    Device memory and the stream come from torch; the work is the library's."""
+    import torch
+    eps = np.ascontiguousarray(eps, dtype=np.float64).reshape(-1, L * L)
+    n_real = eps.shape[0]
+    d_eps = torch.from_numpy(eps).to("cuda")
+    ne = torch.empty(max(1, n_real * n_times), dtype=torch.float64, device="cuda")
+    no = torch.empty_like(ne)
+    stream = torch.cuda.current_stream()
+    ff_neel_dynamics_device(L, d_eps.data_ptr(), n_real, ne.data_ptr(), no.data_ptr(), n_times, dt, tau, pbc,
+                            stream)
+    stream.synchronize()
+    k = n_real * n_times
+    return (ne[:k].cpu().numpy().reshape(n_real, n_times), no[:k].cpu().numpy().reshape(n_real, n_times))

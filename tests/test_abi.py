@@ -10,6 +10,7 @@ import ctypes
 import os
 import re
 
+import numpy as np
 import pytest
 
 import paper_1910_11359_amd as P
@@ -28,7 +29,7 @@ def _declared_functions():
         text = re.sub(r"typedef[^;]*;", "", text)
         for m in re.finditer(r"\b([A-Za-z_]\w*)\s*\(", text):
             name = m.group(1)
-            if name.startswith(("ipeps_", "solve_", "ctmrg_")) and name not in ("ipeps_alloc_fn", "ipeps_free_fn"):
+            if name.startswith(("ipeps_", "solve_", "ctmrg_", "ff_")) and name not in ("ipeps_alloc_fn", "ipeps_free_fn"):
                 names.add(name)
     return names
 
@@ -76,3 +77,26 @@ def test_init_rejects_bad_config_before_touching_the_device():
     with pytest.raises(P.IpepsError) as e:
         P.State(P.make_config(D=3, chi=4))
     assert e.value.code == native.IPEPS_EINVAL
+
+
+def test_ff_bessel_coefficients_match_scipy():
+    # host copy of the routine behind the free-fermion propagator
+    from scipy.special import jv
+    k = np.arange(161)
+    for x in (0.0, 1e-3, 0.3, 0.499, 0.5, 1.0, 7.5, 30.0, 60.0):
+        got = P.ff_bessel_j(x, 160)
+        ref = jv(k, x)
+        assert np.max(np.abs(got - ref)) < 2e-15, x
+
+
+def test_ff_rejects_bad_arguments_without_device():
+    lib = native.load()
+    bad = [(0, 0, 0.5, 0.1, 1, 1), (46, 0, 0.5, 0.1, 1, 1), (2, 1, 0.5, 0.1, 1, 1), (4, 2, 0.5, 0.1, 1, 1),
+           (4, 0, 0.5, 0.0, 1, 1), (4, 0, float("nan"), 0.1, 1, 1), (4, 0, 0.5, 0.1, -1, 1),
+           (4, 0, 0.5, 0.1, 1, 70000), (4, 0, 0.5, 0.1, 1, 1)]
+    for i, (L, pbc, tau, dt, nt, nr) in enumerate(bad):
+        # the last case has valid sizes but NULL buffers
+        assert lib.ff_neel_dynamics(L, pbc, tau, dt, nt, nr, None, None, None, None) == native.IPEPS_EINVAL, i
+    # nothing to do: OK without touching the device
+    assert lib.ff_neel_dynamics(4, 0, 0.5, 0.1, 0, 3, None, None, None, None) == native.IPEPS_OK
+    assert lib.ff_neel_dynamics(4, 0, 0.5, 0.1, 5, 0, None, None, None, None) == native.IPEPS_OK
