@@ -1,9 +1,10 @@
 // Free-fermion Néel dynamics (non-interacting comparison workload).
 //
 // One workgroup per (realization r, filled orbital j): the orbital's L*L
-// complex amplitudes stay in registers (S sites per thread) for the whole
-// run, and the hopping term is applied as a five-point stencil through a
-// double-buffered LDS copy (one barrier per application).  Each observation
+// complex amplitudes stay in registers (a run of S consecutive sites per
+// thread) for the whole run, and the hopping term is applied as a five-point
+// stencil, neighbours inside a thread's run from registers and the others
+// through a double-buffered LDS copy (one barrier per application).  Each observation
 // interval is split into pieces whose Chebyshev argument a*dt is at most
 // kMaxArg, and each piece applies
 //     exp(-i h dt) = exp(-i b dt) sum_k (2 - [k = 0]) (-i)^k J_k(a dt) T_k((h - b) / a)
@@ -75,6 +76,9 @@ __host__ __device__ inline void bessel_j_seq(double x, int kmax, double* J) {
     for (int k = 0; k <= kmax; ++k) J[k] *= inv;
 }
 
+// Thread t owns the contiguous run of sites t*S .. t*S + S - 1, so the
+// neighbours along y (i +- 1) are mostly its own registers; the other
+// neighbours are read from the LDS copy.
 template <int S>
 __global__ __launch_bounds__(kFfThreads) void k_ff_neel(int L, int pbc, double tau, double dt, int n_times,
                                                         const double* __restrict__ eps_all, int M,
@@ -85,32 +89,18 @@ __global__ __launch_bounds__(kFfThreads) void k_ff_neel(int L, int pbc, double t
     __shared__ int sh_K, sh_site;
     const int nsite = L * L, tid = threadIdx.x;
     const int j = blockIdx.x, r = blockIdx.y;
+    const int i0 = tid * S;
     const double* eps = eps_all + (long)r * nsite;
 
     double ep[S];
-    int nb[S][4];
     double lo = 1e300, hi = -1e300;
 #pragma unroll
     for (int e = 0; e < S; ++e) {
-        const int i = tid + e * kFfThreads;
         ep[e] = 0.0;
-        nb[e][0] = nb[e][1] = nb[e][2] = nb[e][3] = -1;
-        if (i < nsite) {
-            ep[e] = eps[i];
+        if (i0 + e < nsite) {
+            ep[e] = eps[i0 + e];
             lo = fmin(lo, ep[e]);
             hi = fmax(hi, ep[e]);
-            const int x = i / L, y = i - (i / L) * L;
-            if (pbc) {
-                nb[e][0] = ((x + L - 1) % L) * L + y;
-                nb[e][1] = ((x + 1) % L) * L + y;
-                nb[e][2] = x * L + (y + L - 1) % L;
-                nb[e][3] = x * L + (y + 1) % L;
-            } else {
-                if (x > 0) nb[e][0] = i - L;
-                if (x + 1 < L) nb[e][1] = i + L;
-                if (y > 0) nb[e][2] = i - 1;
-                if (y + 1 < L) nb[e][3] = i + 1;
-            }
         }
     }
     hi = block_max(hi, red);
@@ -118,7 +108,7 @@ __global__ __launch_bounds__(kFfThreads) void k_ff_neel(int L, int pbc, double t
     const double b = 0.5 * (hi + lo);
     double a = 0.5 * (hi - lo) + 4.0 * fabs(tau);
     if (!(a > 0.0)) a = 1.0;  // h = b: any positive a is a valid bound
-    const double ia = 1.0 / a;
+    const double ia = 1.0 / a, tia = tau * ia;
     const double xtot = a * dt;
     if (!(xtot <= kFfMaxArg * 1e5)) {
         // infinite fields, or more than 1e5 pieces per interval: NaN outputs
@@ -148,42 +138,107 @@ __global__ __launch_bounds__(kFfThreads) void k_ff_neel(int L, int pbc, double t
     __syncthreads();
     const int K = sh_K, site = sh_site;
     const double cph = cos(b * dts), sph = -sin(b * dts);  // exp(-i b dts)
+    // diagonal of (h - b)/a, zero beyond the lattice
+    double dg[S];
+#pragma unroll
+    for (int e = 0; e < S; ++e) dg[e] = (i0 + e < nsite) ? (ep[e] - b) * ia : 0.0;
+    const int y0 = i0 % L;
 
     double t0r[S], t0i[S], t1r[S], t1i[S], ar[S], ai[S];
 #pragma unroll
     for (int e = 0; e < S; ++e) {
-        t0r[e] = (tid + e * kFfThreads == site) ? 1.0 : 0.0;
+        t0r[e] = (i0 + e == site) ? 1.0 : 0.0;
         t0i[e] = 0.0;
+        t1r[e] = t1i[e] = ar[e] = ai[e] = 0.0;
     }
     int par = 0;
-    // out <- (h - b)/a applied to (inr, ini), through LDS buffer par
-    auto apply = [&](const double* inr, const double* ini, double* outr, double* outi) {
+    // out <- H~ in (rec = false) or out <- 2 H~ in - out (rec = true), with
+    // H~ = (h - b)/a, through LDS buffer par
+    auto apply = [&](const double* inr, const double* ini, double* outr, double* outi, bool rec) {
         double* br = lds + (long)par * 2 * nsite;
         double* bi = br + nsite;
 #pragma unroll
-        for (int e = 0; e < S; ++e) {
-            const int i = tid + e * kFfThreads;
-            if (i < nsite) {
-                br[i] = inr[e];
-                bi[i] = ini[e];
+        for (int e = 0; e < S; ++e)
+            if (i0 + e < nsite) {
+                br[i0 + e] = inr[e];
+                bi[i0 + e] = ini[e];
             }
-        }
         __syncthreads();
 #pragma unroll
         for (int e = 0; e < S; ++e) {
+            const int i = i0 + e;
             double sr = 0.0, si = 0.0;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int n = nb[e][q];
-                if (n >= 0) {
-                    sr += br[n];
-                    si += bi[n];
+            if (i < nsite) {
+                int y = y0 + e;  // y of site i (run may cross rows)
+                while (y >= L) y -= L;
+                const int x = i / L;
+                // along y
+                if (y > 0) {
+                    if (e > 0) {
+                        sr += inr[e - 1];
+                        si += ini[e - 1];
+                    } else {
+                        sr += br[i - 1];
+                        si += bi[i - 1];
+                    }
+                } else if (pbc) {
+                    sr += br[i + L - 1];
+                    si += bi[i + L - 1];
+                }
+                if (y + 1 < L) {
+                    if (e + 1 < S) {
+                        sr += inr[e + 1];
+                        si += ini[e + 1];
+                    } else {
+                        sr += br[i + 1];
+                        si += bi[i + 1];
+                    }
+                } else if (pbc) {
+                    sr += br[i - L + 1];
+                    si += bi[i - L + 1];
+                }
+                // along x
+                if (x > 0) {
+                    sr += br[i - L];
+                    si += bi[i - L];
+                } else if (pbc) {
+                    sr += br[i + nsite - L];
+                    si += bi[i + nsite - L];
+                }
+                if (x + 1 < L) {
+                    sr += br[i + L];
+                    si += bi[i + L];
+                } else if (pbc) {
+                    sr += br[i - nsite + L];
+                    si += bi[i - nsite + L];
                 }
             }
-            outr[e] = ((ep[e] - b) * inr[e] - tau * sr) * ia;
-            outi[e] = ((ep[e] - b) * ini[e] - tau * si) * ia;
+            const double hr = dg[e] * inr[e] - tia * sr, hi2 = dg[e] * ini[e] - tia * si;
+            outr[e] = rec ? 2.0 * hr - outr[e] : hr;
+            outi[e] = rec ? 2.0 * hi2 - outi[e] : hi2;
         }
         par ^= 1;
+    };
+    // acc += (-i)^k w T_k
+    auto accum = [&](int k, const double* tr, const double* ti) {
+        const double w = 2.0 * cj[k];
+        const int ph = k & 3;
+#pragma unroll
+        for (int e = 0; e < S; ++e) {
+            if (ph == 0) {
+                ar[e] += w * tr[e];
+                ai[e] += w * ti[e];
+            } else if (ph == 1) {
+                ar[e] += w * ti[e];
+                ai[e] -= w * tr[e];
+            } else if (ph == 2) {
+                ar[e] -= w * tr[e];
+                ai[e] -= w * ti[e];
+            } else {
+                ar[e] -= w * ti[e];
+                ai[e] += w * tr[e];
+            }
+        }
     };
     for (int m = 0; m < n_times; ++m) {
         for (int s = 0; s < nsub; ++s) {
@@ -194,40 +249,16 @@ __global__ __launch_bounds__(kFfThreads) void k_ff_neel(int L, int pbc, double t
                 ai[e] = w0 * t0i[e];
             }
             if (K > 1) {
-                apply(t0r, t0i, t1r, t1i);
-                const double w1 = 2.0 * cj[1];  // (-i) 2 J_1
-#pragma unroll
-                for (int e = 0; e < S; ++e) {
-                    ar[e] += w1 * t1i[e];
-                    ai[e] -= w1 * t1r[e];
-                }
+                apply(t0r, t0i, t1r, t1i, false);  // T_1
+                accum(1, t1r, t1i);
             }
-            for (int k = 2; k < K; ++k) {
-                double t2r[S], t2i[S];
-                apply(t1r, t1i, t2r, t2i);
-                const double w = 2.0 * cj[k];
-                const int ph = k & 3;
-#pragma unroll
-                for (int e = 0; e < S; ++e) {
-                    const double nr = 2.0 * t2r[e] - t0r[e], ni = 2.0 * t2i[e] - t0i[e];
-                    t0r[e] = t1r[e];
-                    t0i[e] = t1i[e];
-                    t1r[e] = nr;
-                    t1i[e] = ni;
-                    // acc += (-i)^k w T_k
-                    if (ph == 0) {
-                        ar[e] += w * nr;
-                        ai[e] += w * ni;
-                    } else if (ph == 1) {
-                        ar[e] += w * ni;
-                        ai[e] -= w * nr;
-                    } else if (ph == 2) {
-                        ar[e] -= w * nr;
-                        ai[e] -= w * ni;
-                    } else {
-                        ar[e] -= w * ni;
-                        ai[e] += w * nr;
-                    }
+            // T_{k+1} = 2 H~ T_k - T_{k-1} overwrites T_{k-1}: t0 and t1 swap roles
+            for (int k = 2; k < K; k += 2) {
+                apply(t1r, t1i, t0r, t0i, true);  // T_k into t0
+                accum(k, t0r, t0i);
+                if (k + 1 < K) {
+                    apply(t0r, t0i, t1r, t1i, true);  // T_{k+1} into t1
+                    accum(k + 1, t1r, t1i);
                 }
             }
 #pragma unroll
@@ -239,7 +270,7 @@ __global__ __launch_bounds__(kFfThreads) void k_ff_neel(int L, int pbc, double t
         double se = 0.0, so = 0.0;
 #pragma unroll
         for (int e = 0; e < S; ++e) {
-            const int i = tid + e * kFfThreads;
+            const int i = i0 + e;
             if (i < nsite) {
                 const double p = t0r[e] * t0r[e] + t0i[e] * t0i[e];
                 if ((((i / L) + (i - (i / L) * L)) & 1) == 0) se += p;
@@ -325,6 +356,7 @@ int ff_neel_dynamics(int L, int pbc, double tau, double dt, int n_times, int n_r
     if (S <= 1) e = launch_ff<1>(s, L, pbc, tau, dt, n_times, n_real, eps, M, pe, po);
     else if (S <= 2) e = launch_ff<2>(s, L, pbc, tau, dt, n_times, n_real, eps, M, pe, po);
     else if (S <= 4) e = launch_ff<4>(s, L, pbc, tau, dt, n_times, n_real, eps, M, pe, po);
+    else if (S <= 7) e = launch_ff<7>(s, L, pbc, tau, dt, n_times, n_real, eps, M, pe, po);
     else e = launch_ff<8>(s, L, pbc, tau, dt, n_times, n_real, eps, M, pe, po);
     if (e == hipSuccess) {
         hipLaunchKernelGGL(k_ff_sum, dim3((unsigned)nq), dim3(256), 0, s, M, pe, po, 1.0 / M,
