@@ -104,6 +104,67 @@ def cpu_baseline(D, chi, W, V):
                        f"= {t_step:.1f}s")}
 
 
+FF_FLOP_PER_SITE = 28  # per application of (h - b)/a to a complex orbital: 5-point stencil
+                       # (2 x 5 MACs) + Chebyshev recurrence (4) + series accumulation (4)
+
+
+def free_fermion(P, torch, synthetic, reps=3, with_cpu=True):
+    """The free-fermion Néel workload (L = 40, 100 realizations, t = 5 in 50
+    intervals), inputs resident on the device; roofline against the FP64
+    vector peak (the kernel is FP64 VALU + LDS, no MFMA)."""
+    import numpy as np
+    cfg = synthetic.ff_headline()
+    L, nr, nt, dt, tau = cfg["L"], cfg["n_real"], cfg["n_times"], cfg["dt"], cfg["tau"]
+    eps_h = synthetic.ff_fields(L, nr, cfg["h"], cfg["kind"], 20191025)
+    eps = torch.from_numpy(eps_h).cuda()
+    ne = torch.empty(nr * nt, dtype=torch.float64, device="cuda")
+    no = torch.empty_like(ne)
+    stream = torch.cuda.Stream()
+    run = lambda: P.ff_neel_dynamics_device(L, eps.data_ptr(), nr, ne.data_ptr(), no.data_ptr(), nt, dt, tau,
+                                            cfg["pbc"], stream)
+    run()
+    stream.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        run()
+    e1.record(stream)
+    stream.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    # algorithmic work: per realization, pieces x (K - 1) stencil applications
+    # on each of the ceil(L^2/2) orbitals, K from the library's own coefficient routine
+    M = (L * L + 1) // 2
+    apps = 0
+    for r in range(nr):
+        a = 0.5 * (eps_h[r].max() - eps_h[r].min()) + 4 * abs(tau)
+        nsub = max(1, int(np.ceil(a * dt / 60.0)))
+        J = P.ff_bessel_j(a * dt / nsub, 159)
+        K = 160
+        while K > 1 and abs(J[K - 1]) < 1e-18:
+            K -= 1
+        apps += nsub * (K - 1)
+    flops = float(apps) * nt * M * L * L * FF_FLOP_PER_SITE
+    ach = flops / (ms * 1e-3) / 1e12
+    imb = (ne - no).view(nr, nt).mean(dim=0).cpu().numpy()
+    out = {"workload": f"free-fermion Néel dynamics: L={L}, open, continuous fields h={cfg['h']}, tau={tau}, "
+                       f"{nr} realizations, {nt} intervals of {dt} (t = {nt * dt:g})",
+           "value": nr / (ms * 1e-3), "unit": "realizations/s", "ms_per_run": ms,
+           "imbalance_t_end_mean": float(imb[-1]),
+           "roofline": {"bound": "alu", "achieved": ach, "peak": PEAK_TFLOPS["fp64"], "unit": "TFLOP/s",
+                        "frac": ach / PEAK_TFLOPS["fp64"], "traffic": None, "kernel": "k_ff_neel<7>",
+                        "flops_per_launch": flops}}
+    if with_cpu:
+        from oracle import freefermion as off
+        t0 = time.perf_counter()
+        off.neel_dynamics(L, cfg["pbc"], tau, eps_h[0], dt * np.arange(1, 6))
+        t5 = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": 1.0 / (t5 * nt / 5), "unit": "realizations/s", "kind": "oracle",
+                               "cores": os.cpu_count(),
+                               "sample": f"1 realization, 5 of {nt} observation times ({t5:.2f} s incl. the "
+                                         f"dense eigh), scaled x{nt // 5}"}
+    return out
+
+
 def serving_sample(P, synthetic, dtype, n_req=16, rate=8.0, d_max=4, steps_max=40):
     """Request loop on a bounded sample of the serving stream: the first n_req
     requests of default_rng(20191025) (D capped at d_max, steps at steps_max,
@@ -221,6 +282,8 @@ def main():
     ap.add_argument("--prelude", type=int, default=20, help="untimed Trotter steps first")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-free-fermion", action="store_true",
+                    help="skip the free-fermion Néel workload (L=40, 100 realizations)")
     ap.add_argument("--sweep", action="store_true",
                     help="also run the 64-job batched sweep through the request loop")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -280,6 +343,8 @@ def main():
             err = max(abs(a - b) for x, y in zip(ser, ser64) for a, b in zip(x, y))
             out["serving"]["fp64_jobs_per_s"] = srv64["jobs_per_s"]
             out["serving"]["max_imbalance_err_vs_fp64"] = err
+    if not args.no_free_fermion:
+        out["free_fermion"] = free_fermion(P, torch, synthetic, with_cpu=not args.no_cpu_baseline)
     if args.sweep:
         out["sweep"] = sweep(P, synthetic, args.dtype)
         if args.dtype != "fp64" and not args.no_fp64_ref:
