@@ -290,18 +290,62 @@ def ff_neel_dynamics_device(L, eps_ptr, n_real, n_even_ptr, n_odd_ptr, n_times, 
                                    C.c_void_p(sptr)), "ff_neel_dynamics")
 
 
+_hip = None
+
+
+def _hip_runtime():
+    """The HIP runtime libipeps.so itself links (not torch's bundled copy), for
+    plain device buffers in the host convenience wrappers."""
+    global _hip
+    if _hip is None:
+        load()
+        h = C.CDLL("libamdhip64.so.7")
+        h.hipMalloc.argtypes = [C.POINTER(C.c_void_p), C.c_size_t]
+        h.hipFree.argtypes = [C.c_void_p]
+        h.hipMemcpy.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t, C.c_int]
+        h.hipDeviceSynchronize.argtypes = []
+        _hip = h
+    return _hip
+
+
+class _DeviceArray:
+    """FP64 device buffer (hipMalloc / hipMemcpy of the library's runtime)."""
+
+    H2D, D2H = 1, 2
+
+    def __init__(self, n):
+        self.n = int(n)
+        self.p = C.c_void_p()
+        if _hip_runtime().hipMalloc(C.byref(self.p), max(8, 8 * self.n)) != 0:
+            raise IpepsError(IPEPS_ENOMEM, "hipMalloc")
+
+    def put(self, a):
+        a = np.ascontiguousarray(a, dtype=np.float64)
+        assert a.size == self.n
+        if _hip_runtime().hipMemcpy(self.p, a.ctypes.data, 8 * self.n, self.H2D) != 0:
+            raise IpepsError(IPEPS_EDEVICE, "hipMemcpy")
+
+    def get(self):
+        out = np.empty(self.n)
+        if self.n and _hip_runtime().hipMemcpy(out.ctypes.data, self.p, 8 * self.n, self.D2H) != 0:
+            raise IpepsError(IPEPS_EDEVICE, "hipMemcpy")
+        return out
+
+    def __del__(self):
+        if getattr(self, "p", None) and self.p.value:
+            _hip_runtime().hipFree(self.p)
+            self.p = C.c_void_p()
+
+
 def ff_neel_dynamics(L, eps, n_times, dt, tau=0.5, pbc=False):
     """Host convenience: eps (n_real, L*L) -> (n_even, n_odd), each (n_real, n_times).
-    Device memory and the stream come from torch; the work is the library's."""
-    import torch
+    Copies the fields to the device, runs on the default stream, copies back."""
     eps = np.ascontiguousarray(eps, dtype=np.float64).reshape(-1, L * L)
     n_real = eps.shape[0]
-    d_eps = torch.from_numpy(eps).to("cuda")
-    ne = torch.empty(max(1, n_real * n_times), dtype=torch.float64, device="cuda")
-    no = torch.empty_like(ne)
-    stream = torch.cuda.current_stream()
-    ff_neel_dynamics_device(L, d_eps.data_ptr(), n_real, ne.data_ptr(), no.data_ptr(), n_times, dt, tau, pbc,
-                            stream)
-    stream.synchronize()
     k = n_real * n_times
-    return (ne[:k].cpu().numpy().reshape(n_real, n_times), no[:k].cpu().numpy().reshape(n_real, n_times))
+    d_eps, ne, no = _DeviceArray(eps.size), _DeviceArray(k), _DeviceArray(k)
+    d_eps.put(eps)
+    ff_neel_dynamics_device(L, d_eps.p.value, n_real, ne.p.value, no.p.value, n_times, dt, tau, pbc, None)
+    if _hip_runtime().hipDeviceSynchronize() != 0:
+        raise IpepsError(IPEPS_EDEVICE, "hipDeviceSynchronize")
+    return ne.get().reshape(n_real, n_times), no.get().reshape(n_real, n_times)
