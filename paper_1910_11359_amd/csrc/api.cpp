@@ -329,12 +329,12 @@ void build_plan(ipeps_state* st) {
                 half.push_back(gemm_nn(E0, n, E1, n, F, n, n, n, n));
                 half.push_back(gemm_nn(E2, n, E3, n, G, n, n, n, n));
                 np.push_back(gemm_nn(G, n, F, n, off(st->Nd, Y * n2, e), n, n, n, n));
-                // projectors: P_low = F Vs (n x chi), P_up = Us^T G (chi x n)
+                // projectors: P_low = F Vs (n x chi), P_up = Us^T G (chi x n; Us is
+                // stored transposed, chi x n)
                 char* us = off(st->Us, Y * (long)n * chi, e);
                 char* vs = off(st->Vs, Y * (long)n * chi, e);
                 pr.push_back(gemm_nn(F, n, vs, chi, off(st->Plow, Y * (long)n * chi, e), chi, n, chi, n));
-                pr.push_back(gemm_general(us, true, chi, G, false, n, off(st->Pup, Y * (long)n * chi, e),
-                                          n, chi, n, n));
+                pr.push_back(gemm_nn(us, n, G, n, off(st->Pup, Y * (long)n * chi, e), n, chi, n, n));
                 // renormalisation inputs of column X
                 const int sxy = frame_site(f, X, Y);
                 cs.site_x[Y] = sxy;

@@ -52,9 +52,10 @@ void from_fp64(hipStream_t s, int dtype, const double* in, void* out, long count
 
 // Projector factors from an SVD of the cut matrix: the truncation rule on
 // sigma (k values, descending; values <= tau * s_1 count as zero, multiplets
-// within 100 tau are kept whole) picks g <= chi; Us[i][c] = U[i][c]/sqrt(s_c),
-// Vs[i][c] = V[i][c]/sqrt(s_c) for c < g, zero for g <= c < chi (n x chi,
-// dtype).  U and V are n x k row-major (ld k).  g_out[b] receives g.
+// within 1e-10 of the larger plus tau s_1 are kept whole) picks g <= chi;
+// Vs[i][c] = V[i][c]/sqrt(s_c) (n x chi) and, transposed, Us[c][i] =
+// U[i][c]/sqrt(s_c) (chi x n) for c < g, zero for g <= c < chi (dtype).
+// U and V are n x k row-major (ld k).  g_out[b] receives g.
 void projector_factors(hipStream_t s, int dtype, int batch, int n, int k, int chi, double tau,
                        const double* U, const double* V, const double* sigma, long strideUV,
                        void* Us, void* Vs, long strideP, int* g_out);

@@ -410,8 +410,15 @@ __global__ __launch_bounds__(256) void k_proj_factors(int n, int k, int chi, dou
          e += (long)gridDim.x * blockDim.x) {
         const int i = e / chi, c = e % chi;
         const double wc = w[c];
-        us[e] = (T)(wc != 0.0 ? Ub[(long)i * k + c] * wc : 0.0);
         vs[e] = (T)(wc != 0.0 ? Vb[(long)i * k + c] * wc : 0.0);
+    }
+    // Us transposed (chi x n): P_up = Us^T G is then a plain product with a
+    // k-contiguous left operand
+    for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < (long)n * chi;
+         e += (long)gridDim.x * blockDim.x) {
+        const int c = e / n, i = e % n;
+        const double wc = w[c];
+        us[e] = (T)(wc != 0.0 ? Ub[(long)i * k + c] * wc : 0.0);
     }
 }
 
