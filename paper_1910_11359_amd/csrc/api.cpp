@@ -221,6 +221,8 @@ void allocate(ipeps_state* st) {
     st->Cenv = M.get(16L * chi * chi * e);
     st->Tenv = M.get(16L * cqc * e);
     st->X1 = M.get(8 * cqc * e);
+    st->X1p = M.get(8 * cqc * e);
+    st->T4p = M.get(2 * cqc * e);
     st->X2 = M.get(8 * n2 * e);
     st->X2p = M.get(8 * n2 * e);
     st->E = M.get(8 * n2 * e);
@@ -235,7 +237,6 @@ void allocate(ipeps_state* st) {
     st->Pup = M.get(2L * n * chi * e);
     st->PlowP = M.get(2L * n * chi * e);
     st->PupP = M.get(2L * n * chi * e);
-    st->W1 = M.get(2 * n2 * e);
     st->W1p = M.get(2 * n2 * e);
     st->W2 = M.get(2 * n2 * e);
     st->g_dev = (int*)M.get(2 * sizeof(int));
@@ -279,6 +280,20 @@ void allocate(ipeps_state* st) {
 }
 
 // ---------------------------------------------------------------- plan
+// Output of a (chi q) x (chi q) product with rows (t, u) and columns (c, v)
+// (t, c < chi; u, v < q) stored as [t][c][u][v]: runs of q contiguous
+// elements, and directly the chi^2 x q^2 operand of the next product.
+GemmProb permuted_rows_cols(GemmProb p, int chi, int q) {
+    const long q2 = (long)q * q;
+    p.c_rows0 = q;  // i = t q + u -> t chi q^2 + u q
+    p.c_rs1 = chi * q2;
+    p.c_rs0 = q;
+    p.c_cols0 = q;  // j = c q + v -> c q^2 + v
+    p.c_cs1 = q2;
+    p.c_cs0 = 1;
+    return p;
+}
+
 void build_plan(ipeps_state* st) {
     const int q = st->q, chi = st->chi, n = st->n, k = st->k, dt = st->dtype;
     const size_t e = st->esz;
@@ -299,15 +314,24 @@ void build_plan(ipeps_state* st) {
                     const int g = (f + j) % 4;
                     const int blk = Y * 4 + j;
                     char* x1 = off(st->X1, blk * cqc, e);
-                    char* x2 = off(st->X2, blk * n2, e);
+                    char* x1p = off(st->X1p, blk * cqc, e);
                     char* x2p = off(st->X2p, blk * n2, e);
                     char* E = off(st->E, blk * n2, e);
-                    // S1: C (chi x chi) . Tnext (chi x q chi)
+                    // S1: C (chi x chi) . Tnext (chi x q chi), columns (v, c); and
+                    // again with the columns written in (c, v) order (X1p)
                     s1.push_back(gemm_nn(Cp(s, g), chi, Tp(s, g), (long)q * chi, x1, (long)q * chi,
                                          chi, q * chi, chi));
-                    // S2: Tprev (chi q x chi) . X1 (chi x q chi)
-                    s2.push_back(gemm_nn(Tp(s, (g + 3) % 4), chi, x1, (long)q * chi, x2,
-                                         (long)q * chi, chi * q, q * chi, chi));
+                    GemmProb p1 = gemm_nn(Cp(s, g), chi, Tp(s, g), (long)q * chi, x1p, (long)q * chi,
+                                          chi, q * chi, chi);
+                    p1.c_cols0 = chi;  // column j = v chi + c -> c q + v
+                    p1.c_cs1 = 1;
+                    p1.c_cs0 = q;
+                    s1.push_back(p1);
+                    // S2: Tprev (chi q x chi) . X1p (chi x chi q): row (t, u), column
+                    // (c, v), written as X2p[t][c][u][v] (the chi^2 x q^2 layout S3 reads)
+                    s2.push_back(permuted_rows_cols(gemm_nn(Tp(s, (g + 3) % 4), chi, x1p, (long)q * chi,
+                                                            x2p, 0, chi * q, q * chi, chi),
+                                                    chi, q));
                     // S3: X2p (chi^2 x q^2) . a[L U][D R]; result as the n x n
                     // matrix [prev = (t, D)][next = (c, R)]
                     GemmProb p3 = gemm_nn(x2p, (long)q * q, st->a_lu[s * 4 + g], (long)q * q, E, n,
@@ -342,10 +366,13 @@ void build_plan(ipeps_state* st) {
                 // Z = T3(X,Y) (chi q x chi) . C4(X,Y)  -> [t3p][q3][c4n]
                 s1.push_back(gemm_nn(Tp(sxy, (2 + f) % 4), chi, Cp(sxy, (3 + f) % 4), chi,
                                      off(st->Z, Y * cqc, e), chi, chi * q, chi, chi));
-                // W1 = PupP (chi q x chi) . T4(X,Y) (chi x q chi)
-                w1.push_back(gemm_nn(off(st->PupP, Y * (long)n * chi, e), chi, Tp(sxy, (3 + f) % 4),
-                                     (long)q * chi, off(st->W1, Y * n2, e), (long)q * chi, chi * q,
-                                     q * chi, chi));
+                // W1 = PupP (chi q x chi) . T4p(X,Y) (chi x chi q, columns (c, v)),
+                // written as W1p[t][c][u][v] (the chi^2 x q^2 layout w2 reads)
+                cs.t4[Y] = Tp(sxy, (3 + f) % 4);
+                w1.push_back(permuted_rows_cols(gemm_nn(off(st->PupP, Y * (long)n * chi, e), chi,
+                                                        off(st->T4p, Y * cqc, e), (long)q * chi,
+                                                        off(st->W1p, Y * n2, e), 0, chi * q, q * chi, chi),
+                                                chi, q));
                 // W2 = W1p (chi^2 x q^2) . a[D L][U R] in frame f
                 w2.push_back(gemm_nn(off(st->W1p, Y * n2, e), (long)q * q, st->a_dl[sxy * 4 + f],
                                      (long)q * q, off(st->W2, Y * n2, e), (long)q * q, chi * chi,
@@ -701,7 +728,6 @@ void column_step(ipeps_state* st, int si) {
     hipStream_t s = st->stream;
     run(st, cs.s1);
     run(st, cs.s2);
-    batched_transpose(s, st->dtype, 8 * chi, q * q, chi, st->X2, st->X2p);
     run(st, cs.s3);
     run(st, cs.half);
     run(st, cs.nprod);
@@ -716,8 +742,9 @@ void column_step(ipeps_state* st, int si) {
         permute3(s, st->dtype, 0, chi, q, chi, off(st->Plow, Y * (long)n * chi, e),
                  off(st->PlowP, Y * (long)n * chi, e));
     }
+    for (int Y = 0; Y < 2; ++Y)  // T4p[Y][t][c][v] <- T4[t][v][c]
+        permute3(s, st->dtype, 1, chi, q, chi, cs.t4[Y], off(st->T4p, Y * (long)chi * q * chi, st->esz));
     run(st, cs.w1);
-    batched_transpose(s, st->dtype, 2 * chi, q * q, chi, st->W1, st->W1p);
     run(st, cs.w2);
     run(st, cs.fin);
     normalize_tensors(s, st->dtype, st->d_norms + cs.norm_first, 6, st->norm_ws);

@@ -38,6 +38,7 @@ struct ColumnStep {
     GemmGroup s1, s2, s3, half, nprod, proj, w1, w2, fin;
     // buffers the step touches
     int site_x[2], site_x1[2];  // physical site of frame (X, Y) and (X+1, Y)
+    void* t4[2];                 // T4(X, Y), [chi][q][chi], permuted into T4p[Y] before w1
     int slot;                    // warm-subspace slot (frame * 2 + X)
     long norm_first;             // index of the 6 NormItems in the table
 };
@@ -94,6 +95,8 @@ struct ipeps_state {
 
     // column-step workspace
     void* X1;   // 8 blocks of chi * q * chi
+    void* X1p;  // the same with columns (c, v) for v in q: [chi][chi][q]
+    void* T4p;  // 2 blocks of chi * chi * q
     void* X2;   // 8 blocks of n^2
     void* X2p;  // 8 blocks of n^2
     void* E;    // 8 blocks of n^2
@@ -108,7 +111,6 @@ struct ipeps_state {
     void* Pup;
     void* PlowP;
     void* PupP;
-    void* W1;   // 2 blocks of n^2
     void* W1p;
     void* W2;
     int* g_dev;
