@@ -373,10 +373,18 @@ void build_plan(ipeps_state* st) {
                                                         off(st->T4p, Y * cqc, e), (long)q * chi,
                                                         off(st->W1p, Y * n2, e), 0, chi * q, q * chi, chi),
                                                 chi, q));
-                // W2 = W1p (chi^2 x q^2) . a[D L][U R] in frame f
-                w2.push_back(gemm_nn(off(st->W1p, Y * n2, e), (long)q * q, st->a_dl[sxy * 4 + f],
-                                     (long)q * q, off(st->W2, Y * n2, e), (long)q * q, chi * chi,
-                                     q * q, q * q));
+                // W2 = W1p (chi^2 x q^2) . a[D L][R U] in frame f: row (c', t4n),
+                // column (R, U), written as W2[c'][R][t4n][U], i.e. the
+                // (chi q) x n matrix [(c', R)][(t4n, U)] the T4 update reads
+                GemmProb pw2 = gemm_nn(off(st->W1p, Y * n2, e), (long)q * q, st->a_dl[sxy * 4 + f],
+                                       (long)q * q, off(st->W2, Y * n2, e), 0, chi * chi, q * q, q * q);
+                pw2.c_rows0 = chi;  // i = c' chi + t4n -> c' q n + t4n q
+                pw2.c_rs1 = (long)q * n;
+                pw2.c_rs0 = q;
+                pw2.c_cols0 = q;  // j = R q + U -> R n + U
+                pw2.c_cs1 = n;
+                pw2.c_cs0 = 1;
+                w2.push_back(pw2);
             }
             for (int Y = 0; Y < 2; ++Y) {
                 const int Yn = (Y + 1) % 2, Yp = (Y + 1) % 2;  // Y+1 and Y-1 coincide mod 2
@@ -392,14 +400,9 @@ void build_plan(ipeps_state* st) {
                                             Cp(frame_site(f, X + 1, Y), (3 + f) % 4), chi, chi, chi, n),
                                     ksc, off(st->ws_c, (2 * Y + 1) * (long)ksc * chi * chi, e)));
                 // T4(X+1, Y) = W2(Y) [rows (c', R), k = (t4n, U)] . P_low(Y-1)
-                GemmProb pt = gemm_nn(off(st->W2, Y * n2, e), 0, off(st->Plow, Yp * (long)n * chi, e),
+                fin.push_back(gemm_nn(off(st->W2, Y * n2, e), n, off(st->Plow, Yp * (long)n * chi, e),
                                       chi, Tp(frame_site(f, X + 1, Y), (3 + f) % 4), chi, chi * q,
-                                      chi, n);
-                pt.a_rows0 = q;
-                pt.a_rs1 = (long)n * q;
-                pt.a_rs0 = 1;
-                pt.a_ks = q;
-                fin.push_back(pt);
+                                      chi, n));
             }
             cs.s1 = add_group(st, s1, dt);
             cs.s2 = add_group(st, s2, dt);

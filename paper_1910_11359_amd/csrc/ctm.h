@@ -17,7 +17,7 @@ void absorb_sqrt_lambda(hipStream_t s, int D, int d, const cplx* gam, const doub
 void double_layer_real(hipStream_t s, int D, int d, const cplx* A, double* a_base);
 
 // Frame copies: for site s and rotation g, out_lu[s][g] = rot^g(a) stored as
-// [L][U][D][R] and out_dl[s][g] stored as [D][L][U][R] (frame legs), in the
+// [L][U][D][R] and out_dl[s][g] stored as [D][L][R][U] (frame legs), in the
 // CTMRG dtype.  rot^g maps frame leg F to physical leg (F - g) mod 4.
 void frame_layouts(hipStream_t s, int q, int dtype, const double* a_base, void* const* out_lu,
                    void* const* out_dl);

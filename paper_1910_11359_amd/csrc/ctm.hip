@@ -152,8 +152,8 @@ __global__ void k_frame_layouts(int q, const double* __restrict__ a_base, T* con
         int f[4];  // frame legs U, L, D, R
         if (kind == 0) {  // [L][U][D][R]
             f[1] = i0; f[0] = i1; f[2] = i2; f[3] = i3;
-        } else {          // [D][L][U][R]
-            f[2] = i0; f[1] = i1; f[0] = i2; f[3] = i3;
+        } else {          // [D][L][R][U]
+            f[2] = i0; f[1] = i1; f[3] = i2; f[0] = i3;
         }
         int p[4];
         for (int F = 0; F < 4; ++F) p[(F - g + 4) % 4] = f[F];
