@@ -639,7 +639,8 @@ void orth(ipeps_state* st, double* X, double* Q, const GemmGroup& gram1, const G
     const bool refill = proj1 && proj2;
     const int n = st->n, k = st->k;
     hipStream_t s = st->stream;
-    normalize_columns(s, 2, n, k, X);
+    // chol_inverse scales the Gram to unit diagonal itself (equivalent to
+    // normalising the columns first)
     run(st, gram1);
     chol_inverse(s, 2, k, st->Gm, st->Ri, kCholDrop, refill ? st->dead_dev : nullptr);
     run(st, mul1);
@@ -653,7 +654,6 @@ void orth(ipeps_state* st, double* X, double* Q, const GemmGroup& gram1, const G
         add_gated(s, 2, (long)n * k, st->dead_dev + 2 * k, st->Rb, Q);
     }
     if (!two_pass) return;
-    normalize_columns(s, 2, n, k, Q);
     run(st, gram2);
     chol_inverse(s, 2, k, st->Gm, st->Ri, kCholDrop);
     run(st, mul2);

@@ -22,7 +22,11 @@ size_t jacobi_svd_real_work(int batch, int m, int n);
 // Batched Cholesky of k x k SPD Gram matrices G (row-major, stride k*k, k <= 256) with
 // dependency dropping, followed by the inverse of the factor: on exit
 // Rinv[b] holds R^{-1} (upper triangular, G = R^T R) with the rows/columns of
-// dropped pivots (pivot <= tol * G_ii) set to zero.  If dead is not null
+// dropped pivots set to zero.  The factorisation runs on G scaled to unit
+// diagonal, G' = D^{-1} G D^{-1} = R'^T R' with D = diag(sqrt(G_ii)) (rows
+// with G_ii <= 0 are zero), so a pivot is dropped when the Schur diagonal of
+// G' is <= tol; R^{-1} = D^{-1} R'^{-1}.  X Rinv thus equals normalising the
+// columns of X before taking the Gram.  If dead is not null
 // (batch*k + batch ints), dead[b*k + j] is set to 1 for a dropped column j
 // and 0 otherwise, and dead[batch*k + b] to the number of dropped columns.
 void chol_inverse(hipStream_t s, int batch, int k, const double* G, double* Rinv, double tol,

@@ -266,13 +266,19 @@ __global__ __launch_bounds__(256) void k_chol_inverse(int k, const double* __res
                                                       int* __restrict__ dead) {
     extern __shared__ double smem[];
     __shared__ int dead_s[256];
+    __shared__ double dsc[256];  // 1/sqrt(G_ii): G is factored scaled to unit diagonal
     const int tid = threadIdx.x, lane = tid & 63;
     const int b = blockIdx.x;
     const double* Gb = G + (long)b * k * k;
     double* out = Rinv + (long)b * k * k;
     double* R = IN_LDS ? smem : out;
     double* Tb = IN_LDS ? smem + (long)k * k : smem;  // k x NB
-    for (int e = tid; e < k * k; e += 256) R[e] = Gb[e];
+    for (int i = tid; i < k; i += 256) {
+        const double gii = Gb[(long)i * k + i];
+        dsc[i] = gii > 0.0 ? 1.0 / sqrt(gii) : 0.0;
+    }
+    __syncthreads();
+    for (int e = tid; e < k * k; e += 256) R[e] = Gb[e] * dsc[e / k] * dsc[e % k];
     __syncthreads();
 
     for (int J0 = 0; J0 < k; J0 += kNb) {
@@ -406,9 +412,10 @@ __global__ __launch_bounds__(256) void k_chol_inverse(int k, const double* __res
         }
         __syncthreads();
     }
+    // X = D^{-1} R'^{-1}: G = D R'^T R' D with D = diag(sqrt(G_ii))
     for (int e = tid; e < k * k; e += 256) {
         const int i = e / k, c = e - (e / k) * k;
-        out[e] = (c >= i && !dead_s[i]) ? R[e] : 0.0;
+        out[e] = (c >= i && !dead_s[i]) ? R[e] * dsc[i] : 0.0;
     }
     if (dead) {
         for (int j = tid; j < k; j += 256) dead[(long)b * k + j] = dead_s[j];
