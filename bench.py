@@ -165,13 +165,13 @@ def free_fermion(P, torch, synthetic, reps=3, with_cpu=True):
     return out
 
 
-def serving_sample(P, synthetic, dtype, n_req=16, rate=8.0, d_max=4, steps_max=40):
+def serving_sample(P, synthetic, dtype, n_req=16, rate=8.0, d_max=4, steps_max=40, slots=4):
     """Request loop on a bounded sample of the serving stream: the first n_req
     requests of default_rng(20191025) (D capped at d_max, steps at steps_max,
     chi = min(128, c D^2)), submitted at their Poisson arrival times (rate per
     second) into a 4-slot server; latency = completion - arrival."""
     reqs = synthetic.serving_stream(n=n_req, rate=rate)
-    srv = P.Server(hbm_budget=0, max_slots=4)
+    srv = P.Server(hbm_budget=0, max_slots=slots)
     t0 = time.perf_counter()
     ids = []
     for r in reqs:
@@ -199,7 +199,7 @@ def serving_sample(P, synthetic, dtype, n_req=16, rate=8.0, d_max=4, steps_max=4
     lat = sorted(lat)
     pct = lambda q: lat[min(len(lat) - 1, int(q * len(lat)))]
     return {"jobs_per_s": len(ids) / (t_last - t_first), "p50_s": pct(0.5), "p99_s": pct(0.99),
-            "requests": len(ids), "rate_per_s": rate, "slots": 4, "dtype": dtype,
+            "requests": len(ids), "rate_per_s": rate, "slots": slots, "dtype": dtype,
             "sample": f"first {n_req} requests of the serving stream, D capped at {d_max}, "
                       f"steps at {steps_max}, observe every 10 with 10 warm CTMRG iterations"}, series
 
