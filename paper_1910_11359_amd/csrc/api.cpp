@@ -214,10 +214,13 @@ void allocate(ipeps_state* st) {
     st->lam = (double*)M.get(8 * D * sizeof(double));
     st->eps = (double*)M.get(4 * sizeof(double));
     st->eps_snap = (double*)M.get(4 * sizeof(double));
+    st->eps_snap_pre = (double*)M.get(4 * sizeof(double));
     st->gates = (cplx*)M.get(8 * (long)d * d * d * d * sizeof(cplx));
     st->su_scratch = M.get(su_scratch_bytes(D, d));
     st->A = (cplx*)M.get(4 * d * D4 * sizeof(cplx));
     st->a_base = (double*)M.get(4 * q4 * sizeof(double));
+    st->A_pre = (cplx*)M.get(4 * d * D4 * sizeof(cplx));
+    st->a_base_pre = (double*)M.get(4 * q4 * sizeof(double));
     for (int i = 0; i < 16; ++i) {
         st->a_lu[i] = M.get(q4 * e);
         st->a_dl[i] = M.get(q4 * e);
@@ -263,6 +266,7 @@ void allocate(ipeps_state* st) {
     st->Rb = (double*)M.get(2 * nk * sizeof(double));
     st->dead_dev = (int*)M.get((2L * k + 2) * sizeof(int));
     st->norm_ws = (double*)M.get(normalize_ws_doubles(32) * sizeof(double));
+    st->norm_ws_su = (double*)M.get(normalize_ws_doubles(4) * sizeof(double));
     st->Cs = (double*)M.get(2L * k * k * sizeof(double));
     st->Uc = (double*)M.get(2L * k * k * sizeof(double));
     st->Vc = (double*)M.get(2L * k * k * sizeof(double));
@@ -511,6 +515,8 @@ void build_plan(ipeps_state* st) {
     st->norm_a_first = (long)st->norms.size();
     const long qa = (long)q * q * q * q;
     for (int i = 0; i < 4; ++i) st->norms.push_back({st->a_base + i * qa, qa});
+    st->norm_a_pre_first = (long)st->norms.size();
+    for (int i = 0; i < 4; ++i) st->norms.push_back({st->a_base_pre + i * qa, qa});
     st->norm_env_first = (long)st->norms.size();
     for (int i = 0; i < 16; ++i) st->norms.push_back({off(st->Cenv, i * cc, e), cc});
     for (int i = 0; i < 16; ++i) st->norms.push_back({off(st->Tenv, i * cqc, e), cqc});
@@ -615,16 +621,36 @@ void set_neel(ipeps_state* st) {
 }
 
 // ---------------------------------------------------------------- CTMRG pieces
+// A = Gamma sqrt(lambda), the truncation-error snapshot and the normalised
+// double layer of the current state into (A, a_base, eps) on stream s; a
+// scale per site changes no projector, spectrum or expectation value, and
+// unit norm keeps the cut products far from the FP32 underflow range.
+void build_double_layers(ipeps_state* st, hipStream_t s, cplx* A, double* a_base, double* eps_snap,
+                         long norm_first, double* ws) {
+    absorb_sqrt_lambda(s, st->D, st->d, st->gam, st->lam, A);
+    HIP_CHECK(hipMemcpyAsync(eps_snap, st->eps, 4 * sizeof(double), hipMemcpyDeviceToDevice, s));
+    double_layer_real(s, st->D, st->d, A, a_base);
+    normalize_tensors(s, IPEPS_DTYPE_FP64, st->d_norms + norm_first, 4, ws);
+}
+
 void prepare_double_layers(ipeps_state* st) {
     HIP_CHECK(hipStreamWaitEvent(st->stream, st->ev_su_done, 0));
-    absorb_sqrt_lambda(st->stream, st->D, st->d, st->gam, st->lam, st->A);
-    HIP_CHECK(hipMemcpyAsync(st->eps_snap, st->eps, 4 * sizeof(double), hipMemcpyDeviceToDevice,
-                             st->stream));
-    HIP_CHECK(hipEventRecord(st->ev_gamma_free, st->stream));
-    double_layer_real(st->stream, st->D, st->d, st->A, st->a_base);
-    // a scale per site changes no projector, spectrum or expectation value;
-    // unit norm keeps the cut products far from the FP32 underflow range
-    normalize_tensors(st->stream, IPEPS_DTYPE_FP64, st->d_norms + st->norm_a_first, 4, st->norm_ws);
+    if (st->pre_valid && st->pre_step == st->step_count) {
+        // built at the tail of the simple update (ordered by ev_su_done)
+        std::swap(st->A, st->A_pre);
+        std::swap(st->a_base, st->a_base_pre);
+        std::swap(st->eps_snap, st->eps_snap_pre);
+        std::swap(st->norm_a_first, st->norm_a_pre_first);
+        st->pre_valid = false;
+        HIP_CHECK(hipEventRecord(st->ev_gamma_free, st->stream));
+    } else {
+        absorb_sqrt_lambda(st->stream, st->D, st->d, st->gam, st->lam, st->A);
+        HIP_CHECK(hipMemcpyAsync(st->eps_snap, st->eps, 4 * sizeof(double), hipMemcpyDeviceToDevice,
+                                 st->stream));
+        HIP_CHECK(hipEventRecord(st->ev_gamma_free, st->stream));
+        double_layer_real(st->stream, st->D, st->d, st->A, st->a_base);
+        normalize_tensors(st->stream, IPEPS_DTYPE_FP64, st->d_norms + st->norm_a_first, 4, st->norm_ws);
+    }
     frame_layouts(st->stream, st->q, st->dtype, st->a_base, st->d_a_lu, st->d_a_dl);
     st->ctm_step = st->step_count;
 }
@@ -938,6 +964,7 @@ int ipeps_set_state(ipeps_state* st, const double* gamma, const double* lambda) 
         st->have_env = false;
         st->poisoned = false;
         st->spectra_valid = false;
+        st->pre_valid = false;
         for (bool& w : st->warm_valid) w = false;
     });
 }
@@ -964,6 +991,15 @@ int ipeps_trotter_step(ipeps_state* st, int n_steps, double* trunc_err_out) {
                 su_layer(ss, st->D, st->d, st->layers[l], st->gam, st->lam, st->eps, st->gates,
                          st->su_scratch);
             st->step_count++;
+        }
+        if (n_steps > 0) {
+            // build the next CTMRG's double layers here, hidden behind the
+            // current CTMRG; the *_pre buffers were last read by main-stream
+            // work that precedes ev_gamma_free
+            build_double_layers(st, ss, st->A_pre, st->a_base_pre, st->eps_snap_pre, st->norm_a_pre_first,
+                                st->norm_ws_su);
+            st->pre_valid = true;
+            st->pre_step = st->step_count;
         }
         HIP_CHECK(hipEventRecord(st->ev_su_done, ss));
         if (trunc_err_out) {

@@ -70,6 +70,7 @@ struct ipeps_state {
     hipEvent_t ev_c64_ready, ev_spec_done;
     double* jwork_c;
     double* eps_snap;  // truncation errors as of the last double-layer build
+    double* eps_snap_pre;  // the same for the layers built ahead on the SU stream
     long ctm_step;     // Trotter steps contained in the current environment
     ipeps::DevMem mem;
 
@@ -84,6 +85,13 @@ struct ipeps_state {
     // double layers
     ipeps::cplx* A;
     double* a_base;
+    // A and a_base of the state after the last Trotter step, built at the tail
+    // of the simple update (SU stream); swapped with A, a_base by the next
+    // CTMRG when pre_step == step_count
+    ipeps::cplx* A_pre;
+    double* a_base_pre;
+    bool pre_valid;
+    long pre_step;
     void* a_lu[16];
     void* a_dl[16];
     void** d_a_lu;
@@ -124,6 +132,7 @@ struct ipeps_state {
     uint64_t orth_calls; // counter feeding the refill hash
     int extra_warm_iters; // added warm subspace iterations (converging to a tolerance)
     double* norm_ws;     // partial sums of the tensor normalisation (32 tensors)
+    double* norm_ws_su;  // the same for normalisations on the SU stream
     double *Nfull_U, *Nfull_V;  // direct path (n <= 96)
     int ks_gram, ks_nv, ks_c;   // split-K factors
     double *ws_gram, *ws_nv;    // split-K partials (FP64)
@@ -152,6 +161,7 @@ struct ipeps_state {
     int tune_cap;
     hipEvent_t tune_ev[2];
     long norm_a_first;    // 4 FP64 items: the double-layer tensors
+    long norm_a_pre_first;  // 4 FP64 items: a_base_pre
     long norm_env_first;  // 32 dtype items: the 16 corners and 16 edges
     ipeps::ColumnStep steps[8];  // frame f (in move order) * 2 + X
     ipeps::SvdPlan svd;
