@@ -13,9 +13,11 @@ projector SVDs and normalisations in FP64 (--dtype fp64 runs everything in
 FP64; with FP32 the FP64 path is also timed and reported as fp64_path).
 
 Prints one JSON line.  The roofline entry is for the dominant kernel (the
-GEMM of the four n^3 half-system products of a column step, n = chi D^2):
-algorithmic flops per launch / mean launch time from HIP events on the
-library's stream during the timed steps.  serving runs a bounded sample of
+GEMM launch of the 8 enlarged corners of a column step, each chi^2 x q^2 by
+q^2 x q^2 with q = D^2): algorithmic flops per launch / mean launch time from
+HIP events on the library's stream during the timed steps.  step_mfma_frac
+is the time the step's algorithmic flops need at the MFMA peaks of their
+precisions over the measured step time.  serving runs a bounded sample of
 the request stream in the chosen precision and in FP64 and reports jobs/s,
 p50/p99 latency and the largest imbalance difference between the two.
 cpu_baseline is the oracle (complex128 NumPy) timed on a bounded sample of
@@ -31,11 +33,14 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}
-# HBM bytes per launch of the cut-product GEMM (FETCH_SIZE + WRITE_SIZE, scaled
-# by a 256 MiB copy), profiles/traffic_cut_products_D6_chi72_fp32.md; valid
-# only for the tile planning, kernels and launches they were measured on (the
-# part of gemm.hip from tile_dims on, see gemm_kernel_digest).
-TRAFFIC = {"fp32": {"gemm_kernel_sha256_16": "2d410b19bcb236aa", "bytes_per_launch": 1.777e9}}
+# The roofline kernel: the launch of the 8 enlarged-corner products of a
+# column step (chi^2 x q^2 by q^2 x q^2 each), the largest GEMM launch.
+ROOF_KERNEL = "k_gemm_direct<...,TAG=1> (8 enlarged-corner products)"
+# HBM bytes per launch of that GEMM (FETCH_SIZE + WRITE_SIZE, scaled by a
+# 256 MiB copy), from the traffic profile in profiles/; valid only for the
+# tile planning, kernels and launches they were measured on (the part of
+# gemm.hip from tile_dims on, see gemm_kernel_digest) and for ROOF_KERNEL.
+TRAFFIC = {"fp32": {"kernel": None, "gemm_kernel_sha256_16": None, "bytes_per_launch": None}}
 
 
 def gemm_kernel_digest():
@@ -49,14 +54,34 @@ DTYPE_NAME = {"fp64": "f64", "fp32": "f32", "bf16": "bf16"}
 METRIC = "Trotter+CTMRG steps/s at D=6,χ=72 (MFMA % peak); batched jobs/s, p50/p99 latency"
 
 
-def step_flops(D, chi):
-    """Algorithmic real flops of one CTMRG iteration in the real basis."""
+def step_flops(D, chi, dtype):
+    """Algorithmic real flops of one CTMRG iteration in the real basis:
+    (flops in the contraction precision, FP64 flops).  16 cuts per iteration
+    (4 moves x 2 columns x 2 cuts); the cut matrix N = E2 E3 E0 E1 is applied
+    to blocks of k = chi + p columns through its four n x n factors
+    (n = chi D^2), 2 w + 1 times (w warm subspace iterations: 1 with FP32
+    contractions, 2 with FP64; p = 8 resp. max(16, chi/3)), in FP64."""
     q = D * D
     n = chi * q
-    return 2.0 * (64 * (chi ** 3 * q + chi ** 3 * q ** 2 + chi ** 2 * q ** 4)
-                  + 16 * (3 * n ** 3 + 2 * n ** 2 * chi)
-                  + 16 * (chi ** 2 * q ** 4 + 2 * chi ** 3 * q ** 2)
-                  + 32 * 2 * chi ** 3 * q)
+    contr = 2.0 * (64 * (chi ** 3 * q + chi ** 3 * q ** 2 + chi ** 2 * q ** 4)
+                   + 16 * 4 * n ** 2 * chi
+                   + 16 * (chi ** 2 * q ** 4 + 2 * chi ** 3 * q ** 2)
+                   + 32 * 2 * chi ** 3 * q)
+    if dtype == "fp64":
+        k, w = chi + max(16, chi // 3), 2
+    else:
+        k, w = chi + (8 if chi >= 64 else 16), 1
+    k = min(k, n)
+    fp64 = 2.0 * 16 * (2 * w + 1) * 4 * n ** 2 * k
+    return contr, fp64
+
+
+def step_mfma_frac(D, chi, dtype, ms_per_step):
+    """Time the step's algorithmic flops need at the MFMA peaks of their
+    precisions, as a fraction of the measured step time."""
+    contr, fp64 = step_flops(D, chi, dtype)
+    need = contr / (PEAK_TFLOPS[dtype] * 1e12) + fp64 / (PEAK_TFLOPS["fp64"] * 1e12)
+    return need / (ms_per_step * 1e-3)
 
 
 def cpu_baseline(D, chi, W, V):
@@ -307,7 +332,8 @@ def main():
     peak = PEAK_TFLOPS[args.dtype]
     traffic = None
     tr = TRAFFIC.get(args.dtype)
-    if tr and tr["bytes_per_launch"] and gemm_kernel_digest() == tr["gemm_kernel_sha256_16"]:
+    if (tr and tr["bytes_per_launch"] and tr["kernel"] == ROOF_KERNEL
+            and gemm_kernel_digest() == tr["gemm_kernel_sha256_16"]):
         traffic = tr["bytes_per_launch"]
     out = {
         "metric": METRIC, "value": rec["value"], "unit": "steps/s", "n_gpus": 1, "steps": args.steps,
@@ -321,9 +347,9 @@ def main():
                    "gemm_tiles": "autotuned" if args.autotune else "heuristic"},
         "roofline": {"bound": "mfma", "achieved": rec["achieved"], "peak": peak, "unit": "TFLOP/s",
                      "frac": rec["achieved"] / peak, "traffic": traffic,
-                     "kernel": "k_gemm_direct<...,TAG=1> (4 half-system n^3 products)",
+                     "kernel": ROOF_KERNEL,
                      "launch_ms": rec["launch_ms"], "flops_per_launch": rec["flops"]},
-        "step_mfma_frac": step_flops(D, chi) / (rec["ms_per_step"] * 1e-3) / (peak * 1e12),
+        "step_mfma_frac": step_mfma_frac(D, chi, args.dtype, rec["ms_per_step"]),
     }
     if args.dtype != "fp64" and not args.no_fp64_ref:
         r64 = headline(P, torch, wl, "fp64", args.steps, args.warmup, args.prelude, flags)

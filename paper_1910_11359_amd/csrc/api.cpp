@@ -235,10 +235,18 @@ void allocate(ipeps_state* st) {
     st->X2 = M.get(8 * n2 * e);
     st->X2p = M.get(8 * n2 * e);
     st->E = M.get(8 * n2 * e);
-    st->Fh = M.get(2 * n2 * e);
-    st->Gh = M.get(2 * n2 * e);
-    st->N64 = (double*)M.get(2 * n2 * sizeof(double));
-    st->Nd = (st->dtype == IPEPS_DTYPE_FP64) ? (void*)st->N64 : M.get(2 * n2 * e);
+    if (n <= kDirectMax) {  // the cut matrix is formed for the direct SVD
+        st->Fh = M.get(2 * n2 * e);
+        st->Gh = M.get(2 * n2 * e);
+        st->N64 = (double*)M.get(2 * n2 * sizeof(double));
+        st->Nd = (st->dtype == IPEPS_DTYPE_FP64) ? (void*)st->N64 : M.get(2 * n2 * e);
+        st->Ecut64 = nullptr;
+    } else {  // ... else applied through its factors, in FP64
+        st->Fh = st->Gh = st->Nd = nullptr;
+        st->N64 = nullptr;
+        st->Ecut64 = (st->dtype == IPEPS_DTYPE_FP64) ? (double*)st->E
+                                                     : (double*)M.get(8 * n2 * sizeof(double));
+    }
     st->Z = M.get(2 * cqc * e);
     st->Us = M.get(2L * n * chi * e);
     st->Vs = M.get(2L * n * chi * e);
@@ -316,7 +324,7 @@ void build_plan(ipeps_state* st) {
         for (int X = 0; X < 2; ++X) {
             ColumnStep& cs = st->steps[mi * 2 + X];
             cs.slot = mi * 2 + X;
-            std::vector<GemmProb> s1, s2, s3, half, np, pr, w1, w2, fin;
+            std::vector<GemmProb> s1, s2, s3, half, np, pr, pr2, w1, w2, fin;
             for (int Y = 0; Y < 2; ++Y) {
                 const int fx[4] = {X, X + 1, X + 1, X}, fy[4] = {Y, Y, Y + 1, Y + 1};
                 for (int j = 0; j < 4; ++j) {
@@ -358,17 +366,32 @@ void build_plan(ipeps_state* st) {
                 char* E1 = off(st->E, (Y * 4 + 1) * n2, e);
                 char* E2 = off(st->E, (Y * 4 + 2) * n2, e);
                 char* E3 = off(st->E, (Y * 4 + 3) * n2, e);
-                char* F = off(st->Fh, Y * n2, e);
-                char* G = off(st->Gh, Y * n2, e);
-                half.push_back(gemm_nn(E0, n, E1, n, F, n, n, n, n));
-                half.push_back(gemm_nn(E2, n, E3, n, G, n, n, n, n));
-                np.push_back(gemm_nn(G, n, F, n, off(st->Nd, Y * n2, e), n, n, n, n));
                 // projectors: P_low = F Vs (n x chi), P_up = Us^T G (chi x n; Us is
-                // stored transposed, chi x n)
+                // stored transposed, chi x n), with the half systems F = E0 E1,
+                // G = E2 E3
                 char* us = off(st->Us, Y * (long)n * chi, e);
                 char* vs = off(st->Vs, Y * (long)n * chi, e);
-                pr.push_back(gemm_nn(F, n, vs, chi, off(st->Plow, Y * (long)n * chi, e), chi, n, chi, n));
-                pr.push_back(gemm_nn(us, n, G, n, off(st->Pup, Y * (long)n * chi, e), n, chi, n, n));
+                char* plow = off(st->Plow, Y * (long)n * chi, e);
+                char* pup = off(st->Pup, Y * (long)n * chi, e);
+                if (n <= kDirectMax) {
+                    char* F = off(st->Fh, Y * n2, e);
+                    char* G = off(st->Gh, Y * n2, e);
+                    half.push_back(gemm_nn(E0, n, E1, n, F, n, n, n, n));
+                    half.push_back(gemm_nn(E2, n, E3, n, G, n, n, n, n));
+                    np.push_back(gemm_nn(G, n, F, n, off(st->Nd, Y * n2, e), n, n, n, n));
+                    pr.push_back(gemm_nn(F, n, vs, chi, plow, chi, n, chi, n));
+                    pr.push_back(gemm_nn(us, n, G, n, pup, n, chi, n, n));
+                } else {
+                    // F and G are never formed: E1 Vs and Us^T E2 first (into the
+                    // PlowP / PupP buffers, rewritten by the permutes after), then
+                    // E0 (E1 Vs) and (Us^T E2) E3
+                    char* pl1 = off(st->PlowP, Y * (long)n * chi, e);
+                    char* pu1 = off(st->PupP, Y * (long)n * chi, e);
+                    pr.push_back(gemm_nn(E1, n, vs, chi, pl1, chi, n, chi, n));
+                    pr.push_back(gemm_nn(us, n, E2, n, pu1, n, chi, n, n));
+                    pr2.push_back(gemm_nn(E0, n, pl1, chi, plow, chi, n, chi, n));
+                    pr2.push_back(gemm_nn(pu1, n, E3, n, pup, n, chi, n, n));
+                }
                 // renormalisation inputs of column X
                 const int sxy = frame_site(f, X, Y);
                 cs.site_x[Y] = sxy;
@@ -417,10 +440,11 @@ void build_plan(ipeps_state* st) {
             cs.s1 = add_group(st, s1, dt);
             cs.s2 = add_group(st, s2, dt);
             cs.s3 = add_group(st, s3, dt);
+            cs.s3.tag = 1;
             cs.half = add_group(st, half, dt);
-            cs.half.tag = 1;
             cs.nprod = add_group(st, np, dt);
             cs.proj = add_group(st, pr, dt);
+            cs.proj2 = add_group(st, pr2, dt);
             cs.w1 = add_group(st, w1, dt);
             cs.w2 = add_group(st, w2, dt);
             cs.fin = add_group(st, fin, dt);
@@ -446,15 +470,40 @@ void build_plan(ipeps_state* st) {
         const int kg = st->ks_gram, kv = st->ks_nv;
         double* wg = st->ws_gram;
         double* wv = st->ws_nv;
-        P.NV = batch2([&](int b) {
-            return split(gemm_nn(st->N64 + b * n2, n, st->Qz + b * nk, k, st->Yw + b * nk, k, n, k, n),
-                         kv, wv + b * kv * nk);
-        });
-        P.NtQ = batch2([&](int b) {
-            return split(gemm_general(st->N64 + b * n2, true, n, st->Qw + b * nk, false, k,
-                                      st->Zw + b * nk, k, n, k, n),
-                         kv, wv + b * kv * nk);
-        });
+        // The cut matrix of cut b is N = G F = E2 E3 E0 E1 (n x n each, FP64),
+        // applied factor by factor (4 n^2 k products instead of 3 n^3 to
+        // form it).  Y = N V with column blocks: V (in Qz) -> E1 V (Zw) ->
+        // E0 . (Qw) -> E3 . (Zw) -> E2 . (Yw).  Z = N^T Q as Z^T = Q^T E2 E3
+        // E0 E1 with row blocks (k x n): Q^T E2 (Yw) -> . E3 (Qz) -> . E0
+        // (Yw) -> . E1, written transposed into Zw.  The scratch blocks are
+        // those the subspace iteration overwrites next.
+        auto Ec = [&](int b, int j) { return st->Ecut64 + (b * 4 + j) * n2; };
+        const int fwd_j[4] = {1, 0, 3, 2};
+        double* const fwd_buf[5] = {st->Qz, st->Zw, st->Qw, st->Zw, st->Yw};
+        for (int t = 0; t < 4; ++t)
+            P.NV[t] = batch2([&](int b) {
+                return split(gemm_nn(Ec(b, fwd_j[t]), n, fwd_buf[t] + b * nk, k, fwd_buf[t + 1] + b * nk,
+                                     k, n, k, n),
+                             kv, wv + b * kv * nk);
+            });
+        const int bwd_j[4] = {2, 3, 0, 1};
+        double* const bwd_buf[5] = {st->Qw, st->Yw, st->Qz, st->Yw, st->Zw};
+        for (int t = 0; t < 4; ++t)
+            P.NtQ[t] = batch2([&](int b) {
+                GemmProb p = t == 0 ? gemm_general(st->Qw + b * nk, true, k, Ec(b, 2), false, n,
+                                                   st->Yw + b * nk, n, k, n, n)
+                                    : gemm_nn(bwd_buf[t] + b * nk, n, Ec(b, bwd_j[t]), n,
+                                              bwd_buf[t + 1] + b * nk, n, k, n, n);
+                if (t == 3) {  // C(i, j) -> Zw[j][i]
+                    p.c_rows0 = k;
+                    p.c_rs1 = 0;
+                    p.c_rs0 = 1;
+                    p.c_cols0 = n;
+                    p.c_cs1 = 0;
+                    p.c_cs0 = k;
+                }
+                return split(p, kv, wv + b * kv * nk);
+            });
         auto gram = [&](double* X) {
             return batch2([&](int b) {
                 return split(gemm_general(X + b * nk, true, k, X + b * nk, false, k, st->Gm + b * kk,
@@ -698,7 +747,9 @@ void orth(ipeps_state* st, double* X, double* Q, const GemmGroup& gram1, const G
 // at 1e-9 or 1e-12 by ~5e-6; 1e-9 is used.
 double proj_cutoff(const ipeps_state* st) { return st->dtype == IPEPS_DTYPE_FP64 ? 1e-12 : 1e-9; }
 
-// Truncated SVD of the two cut matrices N64[0..1]; fills Us, Vs and g_dev.
+// Truncated SVD of the two cut matrices (N64[0..1] when formed, n <= 96;
+// otherwise applied through the enlarged corners in Ecut64); fills Us, Vs and
+// g_dev.
 void projector_svd(ipeps_state* st, int slot) {
     const int n = st->n, k = st->k, chi = st->chi;
     hipStream_t s = st->stream;
@@ -729,14 +780,14 @@ void projector_svd(ipeps_state* st, int slot) {
         // dropped here is zero in V, hence dead in the next left block and
         // restarted there.  Zero columns of the final V only add zero Ritz
         // values.
-        run(st, P.NV);  // Yw = N V
+        for (const GemmGroup& g : P.NV) run(st, g);  // Yw = N V
         orth(st, st->Yw, st->Qw, P.gramY, P.QfromY, P.gramQ, P.YfromQ, false, &P.projQw1,
              &P.projQw2);
-        run(st, P.NtQ);  // Zw = N^T Qw
+        for (const GemmGroup& g : P.NtQ) run(st, g);  // Zw = N^T Qw
         orth(st, st->Zw, st->Qz, P.gramZ, P.QfromZ, P.gramQz, P.ZfromQz, false);
     }
     // Rayleigh-Ritz on span(N V) x span(V)
-    run(st, P.NV);
+    for (const GemmGroup& g : P.NV) run(st, g);
     HIP_CHECK(hipMemcpyAsync(st->Zw, st->Yw, 2 * nk * sizeof(double), hipMemcpyDeviceToDevice, s));
     orth(st, st->Yw, st->Qw, P.gramY, P.QfromY, P.gramQ, P.YfromQ, true);
     run(st, P.Cs);  // Cs = Q^T N V
@@ -764,11 +815,16 @@ void column_step(ipeps_state* st, int si) {
     run(st, cs.s1);
     run(st, cs.s2);
     run(st, cs.s3);
-    run(st, cs.half);
-    run(st, cs.nprod);
-    if (st->dtype != IPEPS_DTYPE_FP64) to_fp64(s, st->dtype, st->Nd, st->N64, 2 * n2);
+    if (n <= kDirectMax) {
+        run(st, cs.half);
+        run(st, cs.nprod);
+        if (st->dtype != IPEPS_DTYPE_FP64) to_fp64(s, st->dtype, st->Nd, st->N64, 2 * n2);
+    } else if (st->dtype != IPEPS_DTYPE_FP64) {
+        to_fp64(s, st->dtype, st->E, st->Ecut64, 8 * n2);
+    }
     projector_svd(st, si);
     run(st, cs.proj);
+    run(st, cs.proj2);
     for (int Y = 0; Y < 2; ++Y) {
         const size_t e = st->esz;
         // PupP[c'][D][t4p] <- Pup[c'][t4p][D];  PlowP[q3][c4n][c'] <- Plow[c4n][q3][c']

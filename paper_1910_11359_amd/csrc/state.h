@@ -35,7 +35,10 @@ struct GemmGroup {
 };
 
 struct ColumnStep {
-    GemmGroup s1, s2, s3, half, nprod, proj, w1, w2, fin;
+    // half, nprod: the cut matrix formed explicitly (direct SVD, n <= 96);
+    // otherwise it is applied in factored form and proj2 finishes the
+    // projectors (P_low = E0 (E1 Vs), P_up = (Us^T E2) E3)
+    GemmGroup s1, s2, s3, half, nprod, proj, proj2, w1, w2, fin;
     // buffers the step touches
     int site_x[2], site_x1[2];  // physical site of frame (X, Y) and (X+1, Y)
     void* t4[2];                 // T4(X, Y), [chi][q][chi], permuted into T4p[Y] before w1
@@ -44,8 +47,11 @@ struct ColumnStep {
 };
 
 struct SvdPlan {
-    // orth passes on Y and Z and the Rayleigh-Ritz products, batch 2 (FP64)
-    GemmGroup NV, NtQ, gramY, gramZ, gramQ, gramQz, QfromY, QfromZ, YfromQ, ZfromQz, Cs, Uo,
+    // N V and N^T Q through the four enlarged corners of each cut
+    // (N = E2 E3 E0 E1), one product per group; orth passes on Y and Z and
+    // the Rayleigh-Ritz products, batch 2 (FP64)
+    GemmGroup NV[4], NtQ[4];
+    GemmGroup gramY, gramZ, gramQ, gramQz, QfromY, QfromZ, YfromQ, ZfromQz, Cs, Uo,
         Vo;
     // restart of dropped left columns: Gm = Qw^T Rb, Rb -= Qw Gm
     GemmGroup projQw1, projQw2;
@@ -107,7 +113,9 @@ struct ipeps_state {
     void* T4p;  // 2 blocks of chi * chi * q
     void* X2;   // 8 blocks of n^2
     void* X2p;  // 8 blocks of n^2
-    void* E;    // 8 blocks of n^2
+    void* E;    // 8 blocks of n^2 (enlarged corners E0..E3 of the two cuts)
+    double* Ecut64;  // the same in FP64 (aliases E in FP64 mode; n > 96 only)
+    // n <= 96 only (cut matrix formed for the direct SVD):
     void* Fh;   // 2 blocks of n^2
     void* Gh;   // 2 blocks of n^2
     void* Nd;   // 2 blocks of n^2 (dtype; aliases N64 in FP64 mode)
