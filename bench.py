@@ -16,8 +16,8 @@ Prints one JSON line.  The roofline entry is for the dominant kernel (the
 GEMM launch of the 8 enlarged corners of a column step, each chi^2 x q^2 by
 q^2 x q^2 with q = D^2): algorithmic flops per launch / mean launch time from
 HIP events on the library's stream during the timed steps.  step_mfma_frac
-is the time the step's algorithmic flops need at the MFMA peaks of their
-precisions over the measured step time.  serving runs a bounded sample of
+is the time the step's algorithmic flops need at the MFMA peak of the
+contraction precision over the measured step time.  serving runs a bounded sample of
 the request stream in the chosen precision and in FP64 and reports jobs/s,
 p50/p99 latency and the largest imbalance difference between the two.
 cpu_baseline is the oracle (complex128 NumPy) timed on a bounded sample of
@@ -55,33 +55,30 @@ METRIC = "Trotter+CTMRG steps/s at D=6,χ=72 (MFMA % peak); batched jobs/s, p50/
 
 
 def step_flops(D, chi, dtype):
-    """Algorithmic real flops of one CTMRG iteration in the real basis:
-    (flops in the contraction precision, FP64 flops).  16 cuts per iteration
-    (4 moves x 2 columns x 2 cuts); the cut matrix N = E2 E3 E0 E1 is applied
-    to blocks of k = chi + p columns through its four n x n factors
-    (n = chi D^2), 2 w + 1 times (w warm subspace iterations: 1 with FP32
-    contractions, 2 with FP64; p = 8 resp. max(16, chi/3)), in FP64."""
+    """Algorithmic real flops of one CTMRG iteration in the real basis, all in
+    the contraction precision.  16 cuts per iteration (4 moves x 2 columns x 2
+    cuts); the cut matrix N = E2 E3 E0 E1 is applied to blocks of k = chi + p
+    columns through its four n x n factors (n = chi D^2), 2 w + 1 times (w
+    warm subspace iterations: 1 with FP32 contractions, 2 with FP64; p = 8
+    resp. max(16, chi/3)).  The FP64 orthogonalisations (O(n k^2)) are not
+    counted."""
     q = D * D
     n = chi * q
-    contr = 2.0 * (64 * (chi ** 3 * q + chi ** 3 * q ** 2 + chi ** 2 * q ** 4)
-                   + 16 * 4 * n ** 2 * chi
-                   + 16 * (chi ** 2 * q ** 4 + 2 * chi ** 3 * q ** 2)
-                   + 32 * 2 * chi ** 3 * q)
     if dtype == "fp64":
         k, w = chi + max(16, chi // 3), 2
     else:
         k, w = chi + (8 if chi >= 64 else 16), 1
     k = min(k, n)
-    fp64 = 2.0 * 16 * (2 * w + 1) * 4 * n ** 2 * k
-    return contr, fp64
+    return 2.0 * (64 * (chi ** 3 * q + chi ** 3 * q ** 2 + chi ** 2 * q ** 4)
+                  + 16 * ((2 * w + 1) * 4 * n ** 2 * k + 4 * n ** 2 * chi)
+                  + 16 * (chi ** 2 * q ** 4 + 2 * chi ** 3 * q ** 2)
+                  + 32 * 2 * chi ** 3 * q)
 
 
 def step_mfma_frac(D, chi, dtype, ms_per_step):
-    """Time the step's algorithmic flops need at the MFMA peaks of their
-    precisions, as a fraction of the measured step time."""
-    contr, fp64 = step_flops(D, chi, dtype)
-    need = contr / (PEAK_TFLOPS[dtype] * 1e12) + fp64 / (PEAK_TFLOPS["fp64"] * 1e12)
-    return need / (ms_per_step * 1e-3)
+    """Time the step's algorithmic flops need at the MFMA peak of the
+    contraction precision, as a fraction of the measured step time."""
+    return step_flops(D, chi, dtype) / (PEAK_TFLOPS[dtype] * 1e12) / (ms_per_step * 1e-3)
 
 
 def cpu_baseline(D, chi, W, V):

@@ -240,12 +240,9 @@ void allocate(ipeps_state* st) {
         st->Gh = M.get(2 * n2 * e);
         st->N64 = (double*)M.get(2 * n2 * sizeof(double));
         st->Nd = (st->dtype == IPEPS_DTYPE_FP64) ? (void*)st->N64 : M.get(2 * n2 * e);
-        st->Ecut64 = nullptr;
-    } else {  // ... else applied through its factors, in FP64
+    } else {  // ... else applied through its factors
         st->Fh = st->Gh = st->Nd = nullptr;
         st->N64 = nullptr;
-        st->Ecut64 = (st->dtype == IPEPS_DTYPE_FP64) ? (double*)st->E
-                                                     : (double*)M.get(8 * n2 * sizeof(double));
     }
     st->Z = M.get(2 * cqc * e);
     st->Us = M.get(2L * n * chi * e);
@@ -272,6 +269,12 @@ void allocate(ipeps_state* st) {
     st->Gm = (double*)M.get(2L * k * k * sizeof(double));
     st->Ri = (double*)M.get(2L * k * k * sizeof(double));
     st->Rb = (double*)M.get(2 * nk * sizeof(double));
+    st->Qt = st->Ch[0] = st->Ch[1] = st->Ch[2] = nullptr;
+    if (n > kDirectMax) {
+        st->Qt = M.get(2 * nk * e);
+        if (st->dtype != IPEPS_DTYPE_FP64)
+            for (int i = 0; i < 3; ++i) st->Ch[i] = M.get(2 * nk * e);
+    }
     st->dead_dev = (int*)M.get((2L * k + 2) * sizeof(int));
     st->norm_ws = (double*)M.get(normalize_ws_doubles(32) * sizeof(double));
     st->norm_ws_su = (double*)M.get(normalize_ws_doubles(4) * sizeof(double));
@@ -470,40 +473,52 @@ void build_plan(ipeps_state* st) {
         const int kg = st->ks_gram, kv = st->ks_nv;
         double* wg = st->ws_gram;
         double* wv = st->ws_nv;
-        // The cut matrix of cut b is N = G F = E2 E3 E0 E1 (n x n each, FP64),
-        // applied factor by factor (4 n^2 k products instead of 3 n^3 to
-        // form it).  Y = N V with column blocks: V (in Qz) -> E1 V (Zw) ->
-        // E0 . (Qw) -> E3 . (Zw) -> E2 . (Yw).  Z = N^T Q as Z^T = Q^T E2 E3
-        // E0 E1 with row blocks (k x n): Q^T E2 (Yw) -> . E3 (Qz) -> . E0
-        // (Yw) -> . E1, written transposed into Zw.  The scratch blocks are
-        // those the subspace iteration overwrites next.
-        auto Ec = [&](int b, int j) { return st->Ecut64 + (b * 4 + j) * n2; };
-        const int fwd_j[4] = {1, 0, 3, 2};
-        double* const fwd_buf[5] = {st->Qz, st->Zw, st->Qw, st->Zw, st->Yw};
-        for (int t = 0; t < 4; ++t)
-            P.NV[t] = batch2([&](int b) {
-                return split(gemm_nn(Ec(b, fwd_j[t]), n, fwd_buf[t] + b * nk, k, fwd_buf[t + 1] + b * nk,
-                                     k, n, k, n),
-                             kv, wv + b * kv * nk);
-            });
-        const int bwd_j[4] = {2, 3, 0, 1};
-        double* const bwd_buf[5] = {st->Qw, st->Yw, st->Qz, st->Yw, st->Zw};
-        for (int t = 0; t < 4; ++t)
-            P.NtQ[t] = batch2([&](int b) {
-                GemmProb p = t == 0 ? gemm_general(st->Qw + b * nk, true, k, Ec(b, 2), false, n,
-                                                   st->Yw + b * nk, n, k, n, n)
-                                    : gemm_nn(bwd_buf[t] + b * nk, n, Ec(b, bwd_j[t]), n,
-                                              bwd_buf[t + 1] + b * nk, n, k, n, n);
-                if (t == 3) {  // C(i, j) -> Zw[j][i]
-                    p.c_rows0 = k;
-                    p.c_rs1 = 0;
-                    p.c_rs0 = 1;
-                    p.c_cols0 = n;
-                    p.c_cs1 = 0;
-                    p.c_cs0 = k;
-                }
-                return split(p, kv, wv + b * kv * nk);
-            });
+        // The cut matrix of cut b is N = G F = E2 E3 E0 E1 (n x n each),
+        // applied factor by factor in dtype (4 n^2 k products instead of 3
+        // n^3 to form it).  Y = N V with column blocks: V -> E1 V -> E0 . ->
+        // E3 . -> E2 . (n x k each).  Z = N^T Q as Z^T = Q^T E2 E3 E0 E1 with
+        // row blocks from Qt = Q^T (k x n), the last product written
+        // transposed (n x k).  FP64 mode reads V from Qz, writes Y to Yw and Z
+        // to Zw and uses as scratch the blocks the subspace iteration
+        // overwrites next; FP32 mode goes through Ch[0..2] (converted at
+        // both ends).
+        {
+            const bool f64 = dt == IPEPS_DTYPE_FP64;
+            auto Ec = [&](int b, int j) { return off(st->E, (b * 4 + j) * n2, e); };
+            auto batch2d = [&](auto make) {
+                std::vector<GemmProb> out;
+                for (int b = 0; b < 2; ++b) out.push_back(make(b));
+                return add_group(st, out, dt);
+            };
+            void* fwd_buf[5] = {st->Qz, st->Zw, st->Qw, st->Zw, st->Yw};
+            void* bwd_buf[5] = {st->Qt, st->Yw, st->Qz, st->Yw, st->Zw};
+            if (!f64) {
+                void* const f[5] = {st->Ch[2], st->Ch[0], st->Ch[1], st->Ch[0], st->Ch[1]};
+                void* const g[5] = {st->Qt, st->Ch[0], st->Ch[1], st->Ch[0], st->Ch[2]};
+                for (int t = 0; t < 5; ++t) fwd_buf[t] = f[t], bwd_buf[t] = g[t];
+            }
+            const int fwd_j[4] = {1, 0, 3, 2}, bwd_j[4] = {2, 3, 0, 1};
+            for (int t = 0; t < 4; ++t) {
+                P.NV[t] = batch2d([&](int b) {
+                    return split(gemm_nn(Ec(b, fwd_j[t]), n, off(fwd_buf[t], b * nk, e), k,
+                                         off(fwd_buf[t + 1], b * nk, e), k, n, k, n),
+                                 kv, wv + b * kv * nk);
+                });
+                P.NtQ[t] = batch2d([&](int b) {
+                    GemmProb p = gemm_nn(off(bwd_buf[t], b * nk, e), n, Ec(b, bwd_j[t]), n,
+                                         off(bwd_buf[t + 1], b * nk, e), n, k, n, n);
+                    if (t == 3) {  // C(i, j) -> [j][i]
+                        p.c_rows0 = k;
+                        p.c_rs1 = 0;
+                        p.c_rs0 = 1;
+                        p.c_cols0 = n;
+                        p.c_cs1 = 0;
+                        p.c_cs0 = k;
+                    }
+                    return split(p, kv, wv + b * kv * nk);
+                });
+            }
+        }
         auto gram = [&](double* X) {
             return batch2([&](int b) {
                 return split(gemm_general(X + b * nk, true, k, X + b * nk, false, k, st->Gm + b * kk,
@@ -747,8 +762,25 @@ void orth(ipeps_state* st, double* X, double* Q, const GemmGroup& gram1, const G
 // at 1e-9 or 1e-12 by ~5e-6; 1e-9 is used.
 double proj_cutoff(const ipeps_state* st) { return st->dtype == IPEPS_DTYPE_FP64 ? 1e-12 : 1e-9; }
 
+// Yw = N Qz and Zw = N^T Qw for the two cuts, through the enlarged corners
+// (products in dtype; FP64 blocks converted at both ends in FP32 mode).
+void apply_n(ipeps_state* st) {
+    const long nk = (long)st->n * st->k;
+    const bool f64 = st->dtype == IPEPS_DTYPE_FP64;
+    if (!f64) from_fp64_blocks(st->stream, st->dtype, st->Qz, st->Ch[2], 2, st->n, st->k, false);
+    for (const GemmGroup& g : st->svd.NV) run(st, g);
+    if (!f64) to_fp64(st->stream, st->dtype, st->Ch[1], st->Yw, 2 * nk);
+}
+
+void apply_nt(ipeps_state* st) {
+    const long nk = (long)st->n * st->k;
+    from_fp64_blocks(st->stream, st->dtype, st->Qw, st->Qt, 2, st->n, st->k, true);
+    for (const GemmGroup& g : st->svd.NtQ) run(st, g);
+    if (st->dtype != IPEPS_DTYPE_FP64) to_fp64(st->stream, st->dtype, st->Ch[2], st->Zw, 2 * nk);
+}
+
 // Truncated SVD of the two cut matrices (N64[0..1] when formed, n <= 96;
-// otherwise applied through the enlarged corners in Ecut64); fills Us, Vs and
+// otherwise applied through the enlarged corners in E); fills Us, Vs and
 // g_dev.
 void projector_svd(ipeps_state* st, int slot) {
     const int n = st->n, k = st->k, chi = st->chi;
@@ -780,14 +812,14 @@ void projector_svd(ipeps_state* st, int slot) {
         // dropped here is zero in V, hence dead in the next left block and
         // restarted there.  Zero columns of the final V only add zero Ritz
         // values.
-        for (const GemmGroup& g : P.NV) run(st, g);  // Yw = N V
+        apply_n(st);  // Yw = N V
         orth(st, st->Yw, st->Qw, P.gramY, P.QfromY, P.gramQ, P.YfromQ, false, &P.projQw1,
              &P.projQw2);
-        for (const GemmGroup& g : P.NtQ) run(st, g);  // Zw = N^T Qw
+        apply_nt(st);  // Zw = N^T Qw
         orth(st, st->Zw, st->Qz, P.gramZ, P.QfromZ, P.gramQz, P.ZfromQz, false);
     }
     // Rayleigh-Ritz on span(N V) x span(V)
-    for (const GemmGroup& g : P.NV) run(st, g);
+    apply_n(st);
     HIP_CHECK(hipMemcpyAsync(st->Zw, st->Yw, 2 * nk * sizeof(double), hipMemcpyDeviceToDevice, s));
     orth(st, st->Yw, st->Qw, P.gramY, P.QfromY, P.gramQ, P.YfromQ, true);
     run(st, P.Cs);  // Cs = Q^T N V
@@ -819,8 +851,6 @@ void column_step(ipeps_state* st, int si) {
         run(st, cs.half);
         run(st, cs.nprod);
         if (st->dtype != IPEPS_DTYPE_FP64) to_fp64(s, st->dtype, st->Nd, st->N64, 2 * n2);
-    } else if (st->dtype != IPEPS_DTYPE_FP64) {
-        to_fp64(s, st->dtype, st->E, st->Ecut64, 8 * n2);
     }
     projector_svd(st, si);
     run(st, cs.proj);

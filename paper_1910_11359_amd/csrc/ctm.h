@@ -49,6 +49,10 @@ void normalize_tensors(hipStream_t s, int dtype, const NormItem* d_items, int n,
 // Convert between dtype and FP64.
 void to_fp64(hipStream_t s, int dtype, const void* in, double* out, long count);
 void from_fp64(hipStream_t s, int dtype, const double* in, void* out, long count);
+// FP64 rows x cols blocks (row-major, batch of them back to back) into dtype,
+// as they are (rows x cols) or transposed (cols x rows); LDS-tiled.
+void from_fp64_blocks(hipStream_t s, int dtype, const double* in, void* out, int batch, int rows,
+                      int cols, bool transpose);
 
 // Projector factors from an SVD of the cut matrix: the truncation rule on
 // sigma (k values, descending; values <= tau * s_1 count as zero, multiplets

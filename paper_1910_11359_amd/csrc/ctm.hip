@@ -371,6 +371,55 @@ void from_fp64(hipStream_t s, int dtype, const double* in, void* out, long count
     HIP_CHECK(hipGetLastError());
 }
 
+// 32 x 32 tiles through LDS: reads along the rows of the input, writes along
+// the rows of the output in both orientations.
+template <typename T, bool TRANS>
+__global__ __launch_bounds__(256) void k_from64_blocks(const double* __restrict__ in,
+                                                       T* __restrict__ out, int rows, int cols) {
+    __shared__ double tile[32][33];
+    const long bs = (long)rows * cols;
+    in += blockIdx.z * bs;
+    out += blockIdx.z * bs;
+    const int r0 = blockIdx.y * 32, c0 = blockIdx.x * 32;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    for (int i = ty; i < 32; i += 8) {
+        const int r = r0 + i, c = c0 + tx;
+        if (r < rows && c < cols) tile[i][tx] = in[(long)r * cols + c];
+    }
+    __syncthreads();
+    for (int i = ty; i < 32; i += 8) {
+        if (TRANS) {
+            const int c = c0 + i, r = r0 + tx;
+            if (c < cols && r < rows) out[(long)c * rows + r] = (T)tile[tx][i];
+        } else {
+            const int r = r0 + i, c = c0 + tx;
+            if (r < rows && c < cols) out[(long)r * cols + c] = (T)tile[i][tx];
+        }
+    }
+}
+
+void from_fp64_blocks(hipStream_t s, int dtype, const double* in, void* out, int batch, int rows,
+                      int cols, bool transpose) {
+    if (batch <= 0 || rows <= 0 || cols <= 0) return;
+    const dim3 grid(ceil_div(cols, 32), ceil_div(rows, 32), batch);
+    if (dtype == IPEPS_DTYPE_FP64) {
+        if (transpose)
+            hipLaunchKernelGGL((k_from64_blocks<double, true>), grid, dim3(256), 0, s, in, (double*)out,
+                               rows, cols);
+        else
+            hipLaunchKernelGGL((k_from64_blocks<double, false>), grid, dim3(256), 0, s, in,
+                               (double*)out, rows, cols);
+    } else {
+        if (transpose)
+            hipLaunchKernelGGL((k_from64_blocks<float, true>), grid, dim3(256), 0, s, in, (float*)out,
+                               rows, cols);
+        else
+            hipLaunchKernelGGL((k_from64_blocks<float, false>), grid, dim3(256), 0, s, in, (float*)out,
+                               rows, cols);
+    }
+    HIP_CHECK(hipGetLastError());
+}
+
 // ------------------------------------------------------------ projector factors
 // Keep g <= K values: zeros (<= tau s_1) are dropped, and a multiplet
 // (neighbours whose gap is <= 1e-10 of the larger plus tau s_1) is never cut.

@@ -48,8 +48,8 @@ struct ColumnStep {
 
 struct SvdPlan {
     // N V and N^T Q through the four enlarged corners of each cut
-    // (N = E2 E3 E0 E1), one product per group; orth passes on Y and Z and
-    // the Rayleigh-Ritz products, batch 2 (FP64)
+    // (N = E2 E3 E0 E1), one product per group, in dtype; orth passes on Y
+    // and Z and the Rayleigh-Ritz products, batch 2 (FP64)
     GemmGroup NV[4], NtQ[4];
     GemmGroup gramY, gramZ, gramQ, gramQz, QfromY, QfromZ, YfromQ, ZfromQz, Cs, Uo,
         Vo;
@@ -114,7 +114,6 @@ struct ipeps_state {
     void* X2;   // 8 blocks of n^2
     void* X2p;  // 8 blocks of n^2
     void* E;    // 8 blocks of n^2 (enlarged corners E0..E3 of the two cuts)
-    double* Ecut64;  // the same in FP64 (aliases E in FP64 mode; n > 96 only)
     // n <= 96 only (cut matrix formed for the direct SVD):
     void* Fh;   // 2 blocks of n^2
     void* Gh;   // 2 blocks of n^2
@@ -136,6 +135,10 @@ struct ipeps_state {
     bool warm_valid[16];
     double *Yw, *Zw, *Qw, *Qz, *Gm, *Ri, *Cs, *Uc, *Vc, *sig, *Uo, *Vo, *jwork;
     double* Rb;          // 2 blocks of n*k: refill directions for dropped columns
+    // the cut matrix applied through its factors (n > 96), in dtype: Qt holds
+    // Q^T (k x n); Ch[0..2] the blocks of the product chains (FP32 mode)
+    void* Qt;
+    void* Ch[3];
     int* dead_dev;       // 2*k flags of dropped columns, then 2 counts
     uint64_t orth_calls; // counter feeding the refill hash
     int extra_warm_iters; // added warm subspace iterations (converging to a tolerance)
