@@ -67,8 +67,15 @@ enum { IPEPS_DTYPE_FP64 = 0, IPEPS_DTYPE_FP32 = 1, IPEPS_DTYPE_BF16 = 2 };
  * ipeps_config_default() sets 1, 1, 1/4.  flags: IPEPS_FLAG_AUTOTUNE picks
  * every GEMM group's tile kind by timing the candidates once at ipeps_init
  * (cached per process by shape; results may then differ from the default
- * heuristic choice at rounding level); default 0. */
+ * heuristic choice at rounding level).  The projector SVD of a cut matrix
+ * N = G F (n x n, n = chi D^2) runs by subspace iteration when n > 96; by
+ * default N is formed (two n^3 products) when n <= 1024 and applied through
+ * its four enlarged-corner factors above (no n^3 product; more, narrower
+ * launches).  IPEPS_FLAG_FACTORED_CUTS / IPEPS_FLAG_FORMED_CUTS force one of
+ * the two for every n > 96 (both set: IPEPS_EINVAL).  Default 0. */
 #define IPEPS_FLAG_AUTOTUNE 1u
+#define IPEPS_FLAG_FACTORED_CUTS 2u
+#define IPEPS_FLAG_FORMED_CUTS 4u
 
 typedef struct {
     int D, chi, d_A;

@@ -47,6 +47,9 @@ void ipeps::DevMem::release() {
 namespace {
 
 constexpr int kDirectMax = 96;  // projector SVD by direct Jacobi when n <= this
+// cut matrices applied through their factors (no n^3 product) when n > this
+// (below, forming them takes fewer launches and less time)
+constexpr int kFactoredMin = 1024;
 constexpr int kColdIters = 8;   // subspace iterations for a fresh random block
 constexpr int kWarmIters = 2;   // ... when warm-started from the last iteration (FP64)
 // With FP32 cut products the matrix itself carries ~1e-7 relative rounding;
@@ -93,6 +96,10 @@ void validate(const ipeps_config* c) {
                   "dtype must be FP64 or FP32");
     IPEPS_REQUIRE(std::isfinite(c->J) && std::isfinite(c->V) && std::isfinite(c->W), IPEPS_EINVAL,
                   "non-finite model parameter");
+    const uint32_t known = IPEPS_FLAG_AUTOTUNE | IPEPS_FLAG_FACTORED_CUTS | IPEPS_FLAG_FORMED_CUTS;
+    IPEPS_REQUIRE((c->flags & ~known) == 0, IPEPS_EINVAL, "unknown flag");
+    IPEPS_REQUIRE((c->flags & IPEPS_FLAG_FACTORED_CUTS) == 0 || (c->flags & IPEPS_FLAG_FORMED_CUTS) == 0,
+                  IPEPS_EINVAL, "FACTORED_CUTS and FORMED_CUTS exclude each other");
 }
 
 // Opt-in autotuner (IPEPS_FLAG_AUTOTUNE): every candidate tile kind of a group
@@ -235,7 +242,7 @@ void allocate(ipeps_state* st) {
     st->X2 = M.get(8 * n2 * e);
     st->X2p = M.get(8 * n2 * e);
     st->E = M.get(8 * n2 * e);
-    if (n <= kDirectMax) {  // the cut matrix is formed for the direct SVD
+    if (!st->factored) {  // the cut matrix is formed
         st->Fh = M.get(2 * n2 * e);
         st->Gh = M.get(2 * n2 * e);
         st->N64 = (double*)M.get(2 * n2 * sizeof(double));
@@ -270,7 +277,7 @@ void allocate(ipeps_state* st) {
     st->Ri = (double*)M.get(2L * k * k * sizeof(double));
     st->Rb = (double*)M.get(2 * nk * sizeof(double));
     st->Qt = st->Ch[0] = st->Ch[1] = st->Ch[2] = nullptr;
-    if (n > kDirectMax) {
+    if (st->factored) {
         st->Qt = M.get(2 * nk * e);
         if (st->dtype != IPEPS_DTYPE_FP64)
             for (int i = 0; i < 3; ++i) st->Ch[i] = M.get(2 * nk * e);
@@ -376,7 +383,7 @@ void build_plan(ipeps_state* st) {
                 char* vs = off(st->Vs, Y * (long)n * chi, e);
                 char* plow = off(st->Plow, Y * (long)n * chi, e);
                 char* pup = off(st->Pup, Y * (long)n * chi, e);
-                if (n <= kDirectMax) {
+                if (!st->factored) {
                     char* F = off(st->Fh, Y * n2, e);
                     char* G = off(st->Gh, Y * n2, e);
                     half.push_back(gemm_nn(E0, n, E1, n, F, n, n, n, n));
@@ -482,7 +489,18 @@ void build_plan(ipeps_state* st) {
         // to Zw and uses as scratch the blocks the subspace iteration
         // overwrites next; FP32 mode goes through Ch[0..2] (converted at
         // both ends).
-        {
+        if (!st->factored) {
+            P.NVf = batch2([&](int b) {
+                return split(gemm_nn(st->N64 + b * n2, n, st->Qz + b * nk, k, st->Yw + b * nk, k, n,
+                                     k, n),
+                             kv, wv + b * kv * nk);
+            });
+            P.NtQf = batch2([&](int b) {
+                return split(gemm_general(st->N64 + b * n2, true, n, st->Qw + b * nk, false, k,
+                                          st->Zw + b * nk, k, n, k, n),
+                             kv, wv + b * kv * nk);
+            });
+        } else {
             const bool f64 = dt == IPEPS_DTYPE_FP64;
             auto Ec = [&](int b, int j) { return off(st->E, (b * 4 + j) * n2, e); };
             auto batch2d = [&](auto make) {
@@ -541,16 +559,24 @@ void build_plan(ipeps_state* st) {
         P.ZfromQz = mulR(st->Qz, st->Zw);
         // final: Zw = N V (a copy of Yw before its orthonormalisation, V in
         // Qz), Cs = Yw^T Zw, Uo = Yw Uc, Vo = Qz Vc
+        // Cs = Yw^T Zw = Q^T N V is the upper-triangular R of the two-pass
+        // Cholesky QR of N V, its rows graded like the singular values.  It
+        // is stored transposed: the one-sided Jacobi then rotates the rows of
+        // R, whose cosines start at R_pq / R_pp instead of R_pq / R_qq
+        // (QR-preconditioned Jacobi), and needs fewer sweeps.  The Jacobi
+        // returns Cs^T = Uc S Vc^T, so N ~ (Yw Vc) S (Qz Uc)^T.
         P.Cs = batch2([&](int b) {
-            return split(gemm_general(st->Yw + b * nk, true, k, st->Zw + b * nk, false, k,
-                                      st->Cs + b * kk, k, k, k, n),
-                         kg, wg + b * kg * kk);
+            GemmProb p = gemm_general(st->Yw + b * nk, true, k, st->Zw + b * nk, false, k,
+                                      st->Cs + b * kk, k, k, k, n);
+            p.c_rs0 = 1;  // C(i, j) -> Cs[j][i]
+            p.c_cs0 = k;
+            return split(p, kg, wg + b * kg * kk);
         });
         P.Uo = batch2([&](int b) {
-            return gemm_nn(st->Yw + b * nk, k, st->Uc + b * kk, k, st->Uo + b * nk, k, n, k, k);
+            return gemm_nn(st->Yw + b * nk, k, st->Vc + b * kk, k, st->Uo + b * nk, k, n, k, k);
         });
         P.Vo = batch2([&](int b) {
-            return gemm_nn(st->Qz + b * nk, k, st->Vc + b * kk, k, st->Vo + b * nk, k, n, k, k);
+            return gemm_nn(st->Qz + b * nk, k, st->Uc + b * kk, k, st->Vo + b * nk, k, n, k, k);
         });
 
         // gated on the number of dropped columns of matrix b
@@ -762,9 +788,11 @@ void orth(ipeps_state* st, double* X, double* Q, const GemmGroup& gram1, const G
 // at 1e-9 or 1e-12 by ~5e-6; 1e-9 is used.
 double proj_cutoff(const ipeps_state* st) { return st->dtype == IPEPS_DTYPE_FP64 ? 1e-12 : 1e-9; }
 
-// Yw = N Qz and Zw = N^T Qw for the two cuts, through the enlarged corners
-// (products in dtype; FP64 blocks converted at both ends in FP32 mode).
+// Yw = N Qz and Zw = N^T Qw for the two cuts: with the formed N64 (FP64), or
+// through the enlarged corners (products in dtype; FP64 blocks converted at
+// both ends in FP32 mode).
 void apply_n(ipeps_state* st) {
+    if (!st->factored) return run(st, st->svd.NVf);
     const long nk = (long)st->n * st->k;
     const bool f64 = st->dtype == IPEPS_DTYPE_FP64;
     if (!f64) from_fp64_blocks(st->stream, st->dtype, st->Qz, st->Ch[2], 2, st->n, st->k, false);
@@ -773,15 +801,15 @@ void apply_n(ipeps_state* st) {
 }
 
 void apply_nt(ipeps_state* st) {
+    if (!st->factored) return run(st, st->svd.NtQf);
     const long nk = (long)st->n * st->k;
     from_fp64_blocks(st->stream, st->dtype, st->Qw, st->Qt, 2, st->n, st->k, true);
     for (const GemmGroup& g : st->svd.NtQ) run(st, g);
     if (st->dtype != IPEPS_DTYPE_FP64) to_fp64(st->stream, st->dtype, st->Ch[2], st->Zw, 2 * nk);
 }
 
-// Truncated SVD of the two cut matrices (N64[0..1] when formed, n <= 96;
-// otherwise applied through the enlarged corners in E); fills Us, Vs and
-// g_dev.
+// Truncated SVD of the two cut matrices (formed in N64, or applied through
+// the enlarged corners in E); fills Us, Vs and g_dev.
 void projector_svd(ipeps_state* st, int slot) {
     const int n = st->n, k = st->k, chi = st->chi;
     hipStream_t s = st->stream;
@@ -822,7 +850,7 @@ void projector_svd(ipeps_state* st, int slot) {
     apply_n(st);
     HIP_CHECK(hipMemcpyAsync(st->Zw, st->Yw, 2 * nk * sizeof(double), hipMemcpyDeviceToDevice, s));
     orth(st, st->Yw, st->Qw, P.gramY, P.QfromY, P.gramQ, P.YfromQ, true);
-    run(st, P.Cs);  // Cs = Q^T N V
+    run(st, P.Cs);  // Cs = (Q^T N V)^T
     // Rayleigh-Ritz SVD.  Columns are left unrotated only below 1e-14 |Cs|_F,
     // far under the projector cutoff: a kept direction that was never rotated
     // against the dominant ones would break P_up P_low = 1.  (Taking the right
@@ -847,7 +875,7 @@ void column_step(ipeps_state* st, int si) {
     run(st, cs.s1);
     run(st, cs.s2);
     run(st, cs.s3);
-    if (n <= kDirectMax) {
+    if (!st->factored) {
         run(st, cs.half);
         run(st, cs.nprod);
         if (st->dtype != IPEPS_DTYPE_FP64) to_fp64(s, st->dtype, st->Nd, st->N64, 2 * n2);
@@ -953,6 +981,9 @@ static void fill_dims(ipeps_state* st, const ipeps_config* cfg) {
     st->k = choose_k(st->n, cfg->chi, cfg->dtype);
     st->dtype = cfg->dtype;
     st->esz = cfg->dtype == IPEPS_DTYPE_FP64 ? sizeof(double) : sizeof(float);
+    const bool force_f = (cfg->flags & IPEPS_FLAG_FACTORED_CUTS) != 0;
+    const bool force_n = (cfg->flags & IPEPS_FLAG_FORMED_CUTS) != 0;
+    st->factored = st->n > kDirectMax && (force_f || (!force_n && st->n > kFactoredMin));
 }
 
 size_t ipeps_footprint_bytes(const ipeps_config* cfg) {

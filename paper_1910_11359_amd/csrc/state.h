@@ -35,9 +35,9 @@ struct GemmGroup {
 };
 
 struct ColumnStep {
-    // half, nprod: the cut matrix formed explicitly (direct SVD, n <= 96);
-    // otherwise it is applied in factored form and proj2 finishes the
-    // projectors (P_low = E0 (E1 Vs), P_up = (Us^T E2) E3)
+    // half, nprod: the cut matrix formed explicitly (ipeps_state::factored
+    // false); otherwise it is applied in factored form and proj2 finishes
+    // the projectors (P_low = E0 (E1 Vs), P_up = (Us^T E2) E3)
     GemmGroup s1, s2, s3, half, nprod, proj, proj2, w1, w2, fin;
     // buffers the step touches
     int site_x[2], site_x1[2];  // physical site of frame (X, Y) and (X+1, Y)
@@ -51,6 +51,7 @@ struct SvdPlan {
     // (N = E2 E3 E0 E1), one product per group, in dtype; orth passes on Y
     // and Z and the Rayleigh-Ritz products, batch 2 (FP64)
     GemmGroup NV[4], NtQ[4];
+    GemmGroup NVf, NtQf;  // the same with the formed N64
     GemmGroup gramY, gramZ, gramQ, gramQz, QfromY, QfromZ, YfromQ, ZfromQz, Cs, Uo,
         Vo;
     // restart of dropped left columns: Gm = Qw^T Rb, Rb -= Qw Gm
@@ -63,6 +64,7 @@ struct SvdPlan {
 struct ipeps_state {
     ipeps_config cfg;
     int D, d, q, chi, n, k, dtype;
+    bool factored;  // cut matrices applied through their factors (else formed)
     size_t esz;
     hipStream_t stream;
     // The simple update runs on its own stream so that the Trotter step t+1
@@ -114,7 +116,7 @@ struct ipeps_state {
     void* X2;   // 8 blocks of n^2
     void* X2p;  // 8 blocks of n^2
     void* E;    // 8 blocks of n^2 (enlarged corners E0..E3 of the two cuts)
-    // n <= 96 only (cut matrix formed for the direct SVD):
+    // cut matrices formed (not factored) only:
     void* Fh;   // 2 blocks of n^2
     void* Gh;   // 2 blocks of n^2
     void* Nd;   // 2 blocks of n^2 (dtype; aliases N64 in FP64 mode)

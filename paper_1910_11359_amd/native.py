@@ -22,6 +22,8 @@ IPEPS_EAGAIN = -6
 IPEPS_ENOTFOUND = -7
 DTYPES = {"fp64": 0, "fp32": 1, "bf16": 2}
 FLAG_AUTOTUNE = 1
+FLAG_FACTORED_CUTS = 2
+FLAG_FORMED_CUTS = 4
 JOB_QUEUED, JOB_RUNNING, JOB_DONE = 0, 1, 2
 
 

@@ -64,6 +64,14 @@ def test_footprint_monotone_and_validation():
     assert fp(D=2, chi=8, d_A=6) == 0   # d = 2 d_A <= 10
     assert fp(D=5, chi=25, d_A=5) > 0   # simple update d min(D^3, dD) = 500 <= 512
     assert fp(D=6, chi=36, d_A=5) == 0  # 600 > 512
+    # cut matrices: formed (n = chi D^2 <= 1024 by default) or factored; the
+    # formed path holds F, G and N, the factored one only k-column blocks
+    assert fp(D=4, chi=32, flags=P.FLAG_FACTORED_CUTS) < a
+    assert fp(D=6, chi=72, flags=P.FLAG_FORMED_CUTS) > c
+    assert fp(D=4, chi=32, flags=P.FLAG_FORMED_CUTS) == a
+    assert fp(D=6, chi=72, flags=P.FLAG_FACTORED_CUTS) == c
+    assert fp(D=4, chi=32, flags=P.FLAG_FACTORED_CUTS | P.FLAG_FORMED_CUTS) == 0
+    assert fp(D=4, chi=32, flags=8) == 0  # unknown flag
 
 
 def test_strerror():

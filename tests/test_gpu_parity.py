@@ -49,12 +49,14 @@ def test_small_workload_vs_oracle():
 
 
 @pytest.mark.parametrize("D,chi,seed,flags", [(2, 8, 3, 0), (3, 9, 4, 0), (3, 12, 5, 0), (4, 16, 6, 0),
-                                              (4, 16, 7, 1)])
+                                              (4, 16, 7, 1), (3, 12, 5, 2), (4, 16, 6, 2),
+                                              (4, 16, 7, 3)])
 def test_random_state_vs_oracle(D, chi, seed, flags):
     """Seeded random site tensors and bond weights (full rank at every
     bond): CTMRG from the state, one Trotter step, CTMRG again.  Covers the
-    direct projector SVD (n <= 96) and the subspace-iteration one; flags=1
-    runs with autotuned GEMM tiles."""
+    direct projector SVD (n <= 96) and the subspace-iteration one with the
+    cut matrices formed (the default at these n) and, with flag 2, applied
+    through their enlarged-corner factors; flag 1 autotunes the GEMM tiles."""
     gam, lam = synthetic.random_state(seed, D)
     kw = dict(J=1.0, V=1.0, W=3.0, dt=0.05)
     st = _gpu_state(D, chi, flags=flags, **kw)
@@ -82,30 +84,34 @@ def test_product_start_low_rank_cuts():
     values and a tail spanning ten decades above the cutoff: the tail
     directions sit below the rounding level of the dominant ones in a mixed
     block, so the device must recover them by restarting dropped columns.
-    The FP32 path (products in FP32, cutoff 1e-6) runs beside it and must
-    stay finite with the imbalance within 1e-3."""
+    The same with the cut matrices applied through their factors (FP64,
+    same bars), and the FP32 path with factored cuts (products in FP32)
+    must stay finite with the imbalance within 1e-3."""
     kw = dict(J=1.0, V=1.6759187457576177, W=1.3506622087662332, dt=0.05)
     st = _gpu_state(3, 18, **kw)
-    st32 = P.State(P.make_config(3, 18, dtype="fp32", **kw))
+    stf = _gpu_state(3, 18, flags=P.FLAG_FACTORED_CUTS, **kw)
+    st32 = P.State(P.make_config(3, 18, dtype="fp32", flags=P.FLAG_FACTORED_CUTS, **kw))
     p = par.oracle_params(3, 18, **kw)
     ost = opeps.new_state(p)
     for step in range(1, 6):
-        st.trotter_step(1)
-        st32.trotter_step(1)
+        for s in (st, stf, st32):
+            s.trotter_step(1)
         opeps.trotter_step(ost, p)
         if step not in (1, 2, 5):
             continue
-        st.ctmrg(0.0, 10, True)
-        st32.ctmrg(0.0, 10, True)
-        g, g32 = st.observe(), st32.observe()
+        for s in (st, stf, st32):
+            s.ctmrg(0.0, 10, True)
+        g32 = st32.observe()
         o, _ = orun.observe_state(ost, p, ctm_iters=10)
-        assert abs(g["imbalance"] - o["imbalance"]) < 1e-6, step
-        assert np.max(np.abs(g["n"] - o["n"])) < 1e-6, step
         spread = par.oracle_spread(ost, p, 10, o["corner_spectra"])
-        par.assert_spectra(st.corner_spectra(), o["corner_spectra"], spread, step)
+        for s in (st, stf):
+            g = s.observe()
+            assert abs(g["imbalance"] - o["imbalance"]) < 1e-6, step
+            assert np.max(np.abs(g["n"] - o["n"])) < 1e-6, step
+            par.assert_spectra(s.corner_spectra(), o["corner_spectra"], spread, step)
         assert abs(g32["imbalance"] - o["imbalance"]) < 1e-3, step
-    st.close()
-    st32.close()
+    for s in (st, stf, st32):
+        s.close()
 
 
 @pytest.mark.parametrize("d_A,D,chi", [(1, 2, 8), (3, 2, 8), (4, 2, 8), (5, 2, 4), (3, 3, 9)])
