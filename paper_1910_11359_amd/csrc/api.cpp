@@ -200,6 +200,12 @@ void run(ipeps_state* st, const GemmGroup& g) {
 
 char* off(void* base, long elems, size_t esz) { return (char*)base + elems * (long)esz; }
 
+void run_on(ipeps_state* st, hipStream_t stream, const GemmGroup& g) {
+    if (g.count == 0) return;
+    gemm_launch(stream, g.dtype, g.tile, st->d_probs + g.first, g.count, g.tiles, g.tag,
+                g.reduce_elems);
+}
+
 GemmProb split(GemmProb p, int ks, void* ws) {
     if (ks > 1) {
         p.ksplit = ks;
@@ -242,6 +248,9 @@ void allocate(ipeps_state* st) {
     st->X2 = M.get(8 * n2 * e);
     st->X2p = M.get(8 * n2 * e);
     st->E = M.get(8 * n2 * e);
+    st->X1p_aux = M.get(4 * cqc * e);
+    st->X2p_aux = M.get(4 * n2 * e);
+    st->E_aux = M.get(4 * n2 * e);
     if (!st->factored) {  // the cut matrix is formed
         st->Fh = M.get(2 * n2 * e);
         st->Gh = M.get(2 * n2 * e);
@@ -322,6 +331,14 @@ GemmProb permuted_rows_cols(GemmProb p, int chi, int q) {
     return p;
 }
 
+// Enlarged corner j (0 UL, 1 UR, 2 DR, 3 DL) of cut Y in a column step of
+// column parity X: the UR and DR corners of the second column live in E_aux.
+char* cut_corner(const ipeps_state* st, int X, int Y, int j) {
+    const long n2 = (long)st->n * st->n;
+    if (X == 1 && (j == 1 || j == 2)) return off(st->E_aux, (Y * 2 + (j - 1)) * n2, st->esz);
+    return off(st->E, (Y * 4 + j) * n2, st->esz);
+}
+
 void build_plan(ipeps_state* st) {
     const int q = st->q, chi = st->chi, n = st->n, k = st->k, dt = st->dtype;
     const size_t e = st->esz;
@@ -334,32 +351,38 @@ void build_plan(ipeps_state* st) {
         for (int X = 0; X < 2; ++X) {
             ColumnStep& cs = st->steps[mi * 2 + X];
             cs.slot = mi * 2 + X;
-            std::vector<GemmProb> s1, s2, s3, half, np, pr, pr2, w1, w2, fin;
+            std::vector<GemmProb> s1, s2, s3, half, np, pr, pr2, w1, w2, fin, a1, a2, a3;
             for (int Y = 0; Y < 2; ++Y) {
                 const int fx[4] = {X, X + 1, X + 1, X}, fy[4] = {Y, Y, Y + 1, Y + 1};
                 for (int j = 0; j < 4; ++j) {
                     const int s = frame_site(f, fx[j], fy[j]);
                     const int g = (f + j) % 4;
                     const int blk = Y * 4 + j;
+                    // UR and DR of the second column: computed ahead (aux stream)
+                    const bool ahead = X == 1 && (j == 1 || j == 2);
+                    const int ab = Y * 2 + (j - 1);
                     char* x1 = off(st->X1, blk * cqc, e);
-                    char* x1p = off(st->X1p, blk * cqc, e);
-                    char* x2p = off(st->X2p, blk * n2, e);
-                    char* E = off(st->E, blk * n2, e);
+                    char* x1p = ahead ? off(st->X1p_aux, ab * cqc, e) : off(st->X1p, blk * cqc, e);
+                    char* x2p = ahead ? off(st->X2p_aux, ab * n2, e) : off(st->X2p, blk * n2, e);
+                    char* E = cut_corner(st, X, Y, j);
                     // S1: C (chi x chi) . Tnext (chi x q chi), columns (v, c); and
-                    // again with the columns written in (c, v) order (X1p)
-                    s1.push_back(gemm_nn(Cp(s, g), chi, Tp(s, g), (long)q * chi, x1, (long)q * chi,
-                                         chi, q * chi, chi));
+                    // again with the columns written in (c, v) order (X1p); the
+                    // first copy only where the C renormalisation reads it (UL)
+                    if (!ahead)
+                        s1.push_back(gemm_nn(Cp(s, g), chi, Tp(s, g), (long)q * chi, x1, (long)q * chi,
+                                             chi, q * chi, chi));
                     GemmProb p1 = gemm_nn(Cp(s, g), chi, Tp(s, g), (long)q * chi, x1p, (long)q * chi,
                                           chi, q * chi, chi);
                     p1.c_cols0 = chi;  // column j = v chi + c -> c q + v
                     p1.c_cs1 = 1;
                     p1.c_cs0 = q;
-                    s1.push_back(p1);
+                    (ahead ? a1 : s1).push_back(p1);
                     // S2: Tprev (chi q x chi) . X1p (chi x chi q): row (t, u), column
                     // (c, v), written as X2p[t][c][u][v] (the chi^2 x q^2 layout S3 reads)
-                    s2.push_back(permuted_rows_cols(gemm_nn(Tp(s, (g + 3) % 4), chi, x1p, (long)q * chi,
-                                                            x2p, 0, chi * q, q * chi, chi),
-                                                    chi, q));
+                    (ahead ? a2 : s2)
+                        .push_back(permuted_rows_cols(gemm_nn(Tp(s, (g + 3) % 4), chi, x1p, (long)q * chi,
+                                                              x2p, 0, chi * q, q * chi, chi),
+                                                      chi, q));
                     // S3: X2p (chi^2 x q^2) . a[L U][D R]; result as the n x n
                     // matrix [prev = (t, D)][next = (c, R)]
                     GemmProb p3 = gemm_nn(x2p, (long)q * q, st->a_lu[s * 4 + g], (long)q * q, E, n,
@@ -370,12 +393,12 @@ void build_plan(ipeps_state* st) {
                     p3.c_cols0 = q;
                     p3.c_cs1 = n;
                     p3.c_cs0 = 1;
-                    s3.push_back(p3);
+                    (ahead ? a3 : s3).push_back(p3);
                 }
-                char* E0 = off(st->E, (Y * 4 + 0) * n2, e);
-                char* E1 = off(st->E, (Y * 4 + 1) * n2, e);
-                char* E2 = off(st->E, (Y * 4 + 2) * n2, e);
-                char* E3 = off(st->E, (Y * 4 + 3) * n2, e);
+                char* E0 = cut_corner(st, X, Y, 0);
+                char* E1 = cut_corner(st, X, Y, 1);
+                char* E2 = cut_corner(st, X, Y, 2);
+                char* E3 = cut_corner(st, X, Y, 3);
                 // projectors: P_low = F Vs (n x chi), P_up = Us^T G (chi x n; Us is
                 // stored transposed, chi x n), with the half systems F = E0 E1,
                 // G = E2 E3
@@ -450,7 +473,10 @@ void build_plan(ipeps_state* st) {
             cs.s1 = add_group(st, s1, dt);
             cs.s2 = add_group(st, s2, dt);
             cs.s3 = add_group(st, s3, dt);
-            cs.s3.tag = 1;
+            if (X == 0) cs.s3.tag = 1;  // all 8 corners: the roofline launch
+            cs.aux_s1 = add_group(st, a1, dt);
+            cs.aux_s2 = add_group(st, a2, dt);
+            cs.aux_s3 = add_group(st, a3, dt);
             cs.half = add_group(st, half, dt);
             cs.nprod = add_group(st, np, dt);
             cs.proj = add_group(st, pr, dt);
@@ -502,7 +528,6 @@ void build_plan(ipeps_state* st) {
             });
         } else {
             const bool f64 = dt == IPEPS_DTYPE_FP64;
-            auto Ec = [&](int b, int j) { return off(st->E, (b * 4 + j) * n2, e); };
             auto batch2d = [&](auto make) {
                 std::vector<GemmProb> out;
                 for (int b = 0; b < 2; ++b) out.push_back(make(b));
@@ -516,15 +541,16 @@ void build_plan(ipeps_state* st) {
                 for (int t = 0; t < 5; ++t) fwd_buf[t] = f[t], bwd_buf[t] = g[t];
             }
             const int fwd_j[4] = {1, 0, 3, 2}, bwd_j[4] = {2, 3, 0, 1};
+            for (int xs = 0; xs < 2; ++xs)  // the corners' buffers depend on the column
             for (int t = 0; t < 4; ++t) {
-                P.NV[t] = batch2d([&](int b) {
-                    return split(gemm_nn(Ec(b, fwd_j[t]), n, off(fwd_buf[t], b * nk, e), k,
-                                         off(fwd_buf[t + 1], b * nk, e), k, n, k, n),
+                P.NV[xs][t] = batch2d([&](int b) {
+                    return split(gemm_nn(cut_corner(st, xs, b, fwd_j[t]), n, off(fwd_buf[t], b * nk, e),
+                                         k, off(fwd_buf[t + 1], b * nk, e), k, n, k, n),
                                  kv, wv + b * kv * nk);
                 });
-                P.NtQ[t] = batch2d([&](int b) {
-                    GemmProb p = gemm_nn(off(bwd_buf[t], b * nk, e), n, Ec(b, bwd_j[t]), n,
-                                         off(bwd_buf[t + 1], b * nk, e), n, k, n, n);
+                P.NtQ[xs][t] = batch2d([&](int b) {
+                    GemmProb p = gemm_nn(off(bwd_buf[t], b * nk, e), n, cut_corner(st, xs, b, bwd_j[t]),
+                                         n, off(bwd_buf[t + 1], b * nk, e), n, k, n, n);
                     if (t == 3) {  // C(i, j) -> [j][i]
                         p.c_rows0 = k;
                         p.c_rs1 = 0;
@@ -791,20 +817,20 @@ double proj_cutoff(const ipeps_state* st) { return st->dtype == IPEPS_DTYPE_FP64
 // Yw = N Qz and Zw = N^T Qw for the two cuts: with the formed N64 (FP64), or
 // through the enlarged corners (products in dtype; FP64 blocks converted at
 // both ends in FP32 mode).
-void apply_n(ipeps_state* st) {
+void apply_n(ipeps_state* st, int X) {
     if (!st->factored) return run(st, st->svd.NVf);
     const long nk = (long)st->n * st->k;
     const bool f64 = st->dtype == IPEPS_DTYPE_FP64;
     if (!f64) from_fp64_blocks(st->stream, st->dtype, st->Qz, st->Ch[2], 2, st->n, st->k, false);
-    for (const GemmGroup& g : st->svd.NV) run(st, g);
+    for (const GemmGroup& g : st->svd.NV[X]) run(st, g);
     if (!f64) to_fp64(st->stream, st->dtype, st->Ch[1], st->Yw, 2 * nk);
 }
 
-void apply_nt(ipeps_state* st) {
+void apply_nt(ipeps_state* st, int X) {
     if (!st->factored) return run(st, st->svd.NtQf);
     const long nk = (long)st->n * st->k;
     from_fp64_blocks(st->stream, st->dtype, st->Qw, st->Qt, 2, st->n, st->k, true);
-    for (const GemmGroup& g : st->svd.NtQ) run(st, g);
+    for (const GemmGroup& g : st->svd.NtQ[X]) run(st, g);
     if (st->dtype != IPEPS_DTYPE_FP64) to_fp64(st->stream, st->dtype, st->Ch[2], st->Zw, 2 * nk);
 }
 
@@ -840,14 +866,14 @@ void projector_svd(ipeps_state* st, int slot) {
         // dropped here is zero in V, hence dead in the next left block and
         // restarted there.  Zero columns of the final V only add zero Ritz
         // values.
-        apply_n(st);  // Yw = N V
+        apply_n(st, slot % 2);  // Yw = N V
         orth(st, st->Yw, st->Qw, P.gramY, P.QfromY, P.gramQ, P.YfromQ, false, &P.projQw1,
              &P.projQw2);
-        apply_nt(st);  // Zw = N^T Qw
+        apply_nt(st, slot % 2);  // Zw = N^T Qw
         orth(st, st->Zw, st->Qz, P.gramZ, P.QfromZ, P.gramQz, P.ZfromQz, false);
     }
     // Rayleigh-Ritz on span(N V) x span(V)
-    apply_n(st);
+    apply_n(st, slot % 2);
     HIP_CHECK(hipMemcpyAsync(st->Zw, st->Yw, 2 * nk * sizeof(double), hipMemcpyDeviceToDevice, s));
     orth(st, st->Yw, st->Qw, P.gramY, P.QfromY, P.gramQ, P.YfromQ, true);
     run(st, P.Cs);  // Cs = (Q^T N V)^T
@@ -875,6 +901,19 @@ void column_step(ipeps_state* st, int si) {
     run(st, cs.s1);
     run(st, cs.s2);
     run(st, cs.s3);
+    if (si % 2 == 0) {
+        // the next column step's UR / DR corners, on the aux stream once the
+        // earlier steps (which wrote the tensors they read) are done
+        const ColumnStep& nx = st->steps[si + 1];
+        HIP_CHECK(hipEventRecord(st->ev_aux_go, s));
+        HIP_CHECK(hipStreamWaitEvent(st->aux_stream, st->ev_aux_go, 0));
+        run_on(st, st->aux_stream, nx.aux_s1);
+        run_on(st, st->aux_stream, nx.aux_s2);
+        run_on(st, st->aux_stream, nx.aux_s3);
+        HIP_CHECK(hipEventRecord(st->ev_aux_done, st->aux_stream));
+    } else {
+        HIP_CHECK(hipStreamWaitEvent(s, st->ev_aux_done, 0));
+    }
     if (!st->factored) {
         run(st, cs.half);
         run(st, cs.nprod);
@@ -1025,6 +1064,9 @@ int ipeps_init(const ipeps_config* cfg, void* hip_stream, ipeps_alloc_fn alloc, 
         HIP_CHECK(hipStreamCreateWithFlags(&st->spec_stream, hipStreamNonBlocking));
         HIP_CHECK(hipEventCreateWithFlags(&st->ev_c64_ready, hipEventDisableTiming));
         HIP_CHECK(hipEventCreateWithFlags(&st->ev_spec_done, hipEventDisableTiming));
+        HIP_CHECK(hipStreamCreateWithFlags(&st->aux_stream, hipStreamNonBlocking));
+        HIP_CHECK(hipEventCreateWithFlags(&st->ev_aux_go, hipEventDisableTiming));
+        HIP_CHECK(hipEventCreateWithFlags(&st->ev_aux_done, hipEventDisableTiming));
         HIP_CHECK(hipHostMalloc((void**)&st->host_buf, 65536 * sizeof(double), hipHostMallocDefault));
         st->autotune = (cfg->flags & IPEPS_FLAG_AUTOTUNE) != 0;
         if (st->autotune) {
@@ -1049,9 +1091,13 @@ void ipeps_destroy(ipeps_state* st) {
     (void)hipStreamSynchronize(st->stream);
     if (st->su_stream) (void)hipStreamSynchronize(st->su_stream);
     if (st->spec_stream) (void)hipStreamSynchronize(st->spec_stream);
+    if (st->aux_stream) (void)hipStreamSynchronize(st->aux_stream);
     st->mem.release();
     if (st->su_stream) (void)hipStreamDestroy(st->su_stream);
     if (st->spec_stream) (void)hipStreamDestroy(st->spec_stream);
+    if (st->aux_stream) (void)hipStreamDestroy(st->aux_stream);
+    if (st->ev_aux_go) (void)hipEventDestroy(st->ev_aux_go);
+    if (st->ev_aux_done) (void)hipEventDestroy(st->ev_aux_done);
     if (st->ev_c64_ready) (void)hipEventDestroy(st->ev_c64_ready);
     if (st->ev_spec_done) (void)hipEventDestroy(st->ev_spec_done);
     if (st->ev_gamma_free) (void)hipEventDestroy(st->ev_gamma_free);

@@ -39,6 +39,11 @@ struct ColumnStep {
     // false); otherwise it is applied in factored form and proj2 finishes
     // the projectors (P_low = E0 (E1 Vs), P_up = (Us^T E2) E3)
     GemmGroup s1, s2, s3, half, nprod, proj, proj2, w1, w2, fin;
+    // second column of a move (X = 1): its UR and DR enlarged corners read
+    // only tensors the move leaves alone; the first column step enqueues
+    // them on the aux stream (into X1p_aux, X2p_aux, E_aux) to fill the idle
+    // phases of its projector SVD
+    GemmGroup aux_s1, aux_s2, aux_s3;
     // buffers the step touches
     int site_x[2], site_x1[2];  // physical site of frame (X, Y) and (X+1, Y)
     void* t4[2];                 // T4(X, Y), [chi][q][chi], permuted into T4p[Y] before w1
@@ -50,7 +55,7 @@ struct SvdPlan {
     // N V and N^T Q through the four enlarged corners of each cut
     // (N = E2 E3 E0 E1), one product per group, in dtype; orth passes on Y
     // and Z and the Rayleigh-Ritz products, batch 2 (FP64)
-    GemmGroup NV[4], NtQ[4];
+    GemmGroup NV[2][4], NtQ[2][4];  // [column parity X][factor]
     GemmGroup NVf, NtQf;  // the same with the formed N64
     GemmGroup gramY, gramZ, gramQ, gramQz, QfromY, QfromZ, YfromQ, ZfromQz, Cs, Uo,
         Vo;
@@ -76,6 +81,9 @@ struct ipeps_state {
     // corner spectra run on their own stream, overlapping the next iteration
     hipStream_t spec_stream;
     hipEvent_t ev_c64_ready, ev_spec_done;
+    // enlarged corners of the second column step of a move, computed ahead
+    hipStream_t aux_stream;
+    hipEvent_t ev_aux_go, ev_aux_done;
     double* jwork_c;
     double* eps_snap;  // truncation errors as of the last double-layer build
     double* eps_snap_pre;  // the same for the layers built ahead on the SU stream
@@ -116,6 +124,10 @@ struct ipeps_state {
     void* X2;   // 8 blocks of n^2
     void* X2p;  // 8 blocks of n^2
     void* E;    // 8 blocks of n^2 (enlarged corners E0..E3 of the two cuts)
+    // UR, DR corners of the second column step: 4 blocks each ([Y][j - 1])
+    void* X1p_aux;
+    void* X2p_aux;
+    void* E_aux;
     // cut matrices formed (not factored) only:
     void* Fh;   // 2 blocks of n^2
     void* Gh;   // 2 blocks of n^2
