@@ -5,7 +5,8 @@
 //   M_X = Q_X R_X                         Householder QR, R_X is r x dD
 //   Theta'[(k_i, s_i'), (s_j', k_j)] = sum_b lambda_b sum_{s_i s_j}
 //        G[(s_i' s_j'), (s_i s_j)] R_i[k_i, (s_i, b)] R_j[k_j, (s_j, b)]
-//   Theta' = U S V^H                      one-sided (Hestenes) Jacobi, FP64
+//   Theta' = U S V^H                      one-sided (Hestenes) Jacobi, FP64, on
+//                                         R^H of a column-pivoted QR of Theta'
 //   keep g <= D values (zeros <= 1e-12 s_1 dropped, multiplets -- gaps <=
 //   1e-10 s_g + 1e-12 s_1 -- kept whole)
 //   Gamma_i' = Q_i U_g / outer lambdas,  Gamma_j' = Q_j conj(V_g) / outer lambdas
@@ -223,7 +224,14 @@ __device__ void householder_apply_q(int Dc, int r, int ncols, const cplx* M, con
 __device__ void complex_jacobi(int m, int n, cplx* A, int* flag, double* red) {
     const int g16 = threadIdx.x & 15, group = threadIdx.x >> 4, ngroups = blockDim.x >> 4;
     const int ne = n + (n & 1), npair = ne / 2;
-    const double tol = 4.0 * m * 1.11e-16;
+    // A pair is rotated unless orthogonal to 1e-15 relative; the sweeps end
+    // once no rotation angle exceeds 1e-14.  The angle, not the inner
+    // product, decides convergence: for two columns whose norms differ by a
+    // relative gap delta, an inner product left at tol |a_p| |a_q| mixes
+    // their directions by ~tol / delta, which enters the truncated state
+    // when the pair straddles the cut; well separated pairs still rotate by
+    // rounding-level angles, which do not count.
+    const double tol = 1e-15, tmin = 1e-14;
     // columns below 1e-14 |A|_F are rounding noise and are left alone
     double fro = 0.0;
     for (long e = threadIdx.x; e < (long)m * n; e += blockDim.x) fro += cabs2(A[e]);
@@ -277,7 +285,7 @@ __device__ void complex_jacobi(int m, int n, cplx* A, int* flag, double* red) {
                     ap[i] = csub(cscale(x, c), cscale(y, s));
                     aq[i] = cadd(cscale(x, s), cscale(y, c));
                 }
-                if (g16 == 0) *flag = 1;
+                if (g16 == 0 && fabs(t) > tmin) *flag = 1;
             }
             __syncthreads();
         }
@@ -285,6 +293,121 @@ __device__ void complex_jacobi(int m, int n, cplx* A, int* flag, double* red) {
         __syncthreads();
         if (!any) break;
     }
+}
+
+// Householder QR with column pivoting of the m x m column-major A in place,
+// A P = Q R, leaving R^H (lower triangular) in A and the pivot order in perm
+// (column j of A P is column perm[j] of A).  Q is never formed.  One group
+// of 16 lanes per column (DPP sums inside the group): each group rebuilds
+// the reflector of step j from column j (all groups compute the same bits),
+// applies it to its trailing columns and recomputes their trailing norms
+// exactly (cn, m doubles) for the next pivot search; two barriers per step.
+__device__ void qrcp_to_rh(int m, cplx* A, int* perm, double* cn) {
+    const int g16 = threadIdx.x & 15, group = threadIdx.x >> 4, ngroups = blockDim.x >> 4;
+    for (int c = group; c < m; c += ngroups) {
+        double sq = 0.0;
+        for (int i = g16; i < m; i += 16) sq += cabs2(A[(long)c * m + i]);
+        sq = group16_sum(sq);
+        if (g16 == 0) cn[c] = sq;
+    }
+    for (int c = threadIdx.x; c < m; c += blockDim.x) perm[c] = c;
+    __syncthreads();
+    double beta_prev = 0.0;
+    for (int j = 0; j < m; ++j) {
+        // R(j-1, j-1): column j-1 is no longer read
+        if (j > 0 && threadIdx.x == 0) A[(long)(j - 1) * m + (j - 1)] = cmake(beta_prev, 0.0);
+        // pivot: the largest remaining trailing norm (ties: lowest index)
+        double bv = -1.0;
+        int bi = j;
+        for (int c = j + g16; c < m; c += 16) {
+            const double v = cn[c];
+            if (v > bv) {
+                bv = v;
+                bi = c;
+            }
+        }
+#pragma unroll
+        for (int o = 8; o > 0; o >>= 1) {
+            const double ov = __shfl_xor(bv, o, 16);
+            const int oi = __shfl_xor(bi, o, 16);
+            if (ov > bv || (ov == bv && oi < bi)) {
+                bv = ov;
+                bi = oi;
+            }
+        }
+        const int pj = bi;
+        if (pj != j) {
+            for (int i = threadIdx.x; i < m; i += blockDim.x) {
+                const cplx a = A[(long)j * m + i];
+                A[(long)j * m + i] = A[(long)pj * m + i];
+                A[(long)pj * m + i] = a;
+            }
+            if (threadIdx.x == 0) {
+                const int t = perm[j];
+                perm[j] = perm[pj];
+                perm[pj] = t;
+            }
+        }
+        __syncthreads();
+        // reflector H = I - tau v v^H with v_j = 1, v_i = sc * A(i, j) (i > j)
+        const cplx* col = A + (long)j * m;
+        double s2 = 0.0;
+        for (int i = j + 1 + g16; i < m; i += 16) s2 += cabs2(col[i]);
+        s2 = group16_sum(s2);
+        const cplx alpha = col[j];
+        cplx tau = cmake(0, 0), sc = cmake(0, 0);
+        double beta = alpha.re;
+        if (!(s2 == 0.0 && alpha.im == 0.0)) {
+            const double nrm = sqrt(cabs2(alpha) + s2);
+            beta = alpha.re >= 0 ? -nrm : nrm;
+            tau = cmake((beta - alpha.re) / beta, -alpha.im / beta);
+            const cplx den = cmake(alpha.re - beta, alpha.im);
+            const double dn = cabs2(den);
+            sc = cmake(den.re / dn, -den.im / dn);
+        }
+        beta_prev = beta;
+        const bool reflect = tau.re != 0.0 || tau.im != 0.0;
+        const cplx ct = cconj(tau);
+        for (int c = j + 1 + group; c < m; c += ngroups) {
+            cplx* ac = A + (long)c * m;
+            if (reflect) {
+                double wr = 0.0, wi = 0.0;
+                for (int i = j + g16; i < m; i += 16) {
+                    const cplx v = (i == j) ? cmake(1, 0) : cmul(sc, col[i]);
+                    const cplx t = cdotc(v, ac[i]);
+                    wr += t.re;
+                    wi += t.im;
+                }
+                wr = group16_sum(wr);
+                wi = group16_sum(wi);
+                const cplx f = cmul(ct, cmake(wr, wi));
+                double sq = 0.0;
+                for (int i = j + g16; i < m; i += 16) {
+                    const cplx v = (i == j) ? cmake(1, 0) : cmul(sc, col[i]);
+                    const cplx x = csub(ac[i], cmul(f, v));
+                    ac[i] = x;
+                    if (i > j) sq += cabs2(x);
+                }
+                sq = group16_sum(sq);
+                if (g16 == 0) cn[c] = sq;
+            } else if (g16 == 0) {
+                cn[c] -= cabs2(ac[j]);  // only orders the pivots
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) A[(long)(m - 1) * m + (m - 1)] = cmake(beta_prev, 0.0);
+    __syncthreads();
+    // R (upper triangle) -> R^H (lower triangle), zeros above the diagonal
+    for (long e = threadIdx.x; e < (long)m * m; e += blockDim.x) {
+        const int c = (int)(e / m), r = (int)(e % m);
+        if (r > c) {  // pair (c, r): R(c, r) sits at A[r][c]
+            const cplx x = A[(long)r * m + c];
+            A[(long)c * m + r] = cconj(x);
+            A[(long)r * m + c] = cmake(0, 0);
+        }
+    }
+    __syncthreads();
 }
 
 template <bool THETA_LDS>
@@ -297,8 +420,9 @@ __global__ __launch_bounds__(1024) void k_su_bond(SuDims dm, LayerDesc L, cplx* 
     __shared__ int flag;
     __shared__ int g_s;
     __shared__ double lam_inv_i[3][8], lam_inv_j[3][8], lam_i[3][8], lam_j[3][8];
-    __shared__ double sig_sorted[512];
+    __shared__ double sig_sorted[512];  // also the pivoting norms of the QR
     __shared__ int col_of_rank[512];
+    __shared__ int col_perm[512];
 
     const BondDesc bd = L.bond[blockIdx.x];
     const int D = dm.D, d = dm.d, Dc = dm.Dc, nb = dm.nb, r = dm.r, m = dm.m;
@@ -364,6 +488,10 @@ __global__ __launch_bounds__(1024) void k_su_bond(SuDims dm, LayerDesc L, cplx* 
         S.Th[e] = acc;
     }
     __syncthreads();
+    // QR-preconditioned Jacobi: Theta' P = Q R, then one-sided Jacobi on the
+    // columns of R^H (the rows of R, graded by the pivoting), which converge
+    // in a few sweeps: R^H W = U~ S gives Theta' = (Q W) S (P U~)^H
+    qrcp_to_rh(m, Ac, col_perm, sig_sorted);
     complex_jacobi(m, m, Ac, &flag, red);
     __syncthreads();
 
@@ -419,17 +547,18 @@ __global__ __launch_bounds__(1024) void k_su_bond(SuDims dm, LayerDesc L, cplx* 
     __syncthreads();
     const int g = g_s;
 
-    // ---- U_k = column / s_k ; B_k = U_k^H Theta' / s_k  (k < g)
+    // ---- right vectors V_k = P (column / s_k), stored as B_k = V_k^H; left
+    // vectors U_k = Theta' V_k / s_k  (k < g)
     for (long e = threadIdx.x; e < (long)m * g; e += blockDim.x) {
-        const int k = (int)(e / m), x = (int)(e % m);
-        S.U[(long)k * m + x] = cscale(Ac[(long)col_of_rank[k] * m + x], 1.0 / sig_sorted[k]);
+        const int k = (int)(e / m), i = (int)(e % m);
+        S.B[(long)k * m + col_perm[i]] = cconj(cscale(Ac[(long)col_of_rank[k] * m + i], 1.0 / sig_sorted[k]));
     }
     __syncthreads();
     for (long e = threadIdx.x; e < (long)m * g; e += blockDim.x) {
-        const int k = (int)(e / m), y = (int)(e % m);
+        const int k = (int)(e / m), x = (int)(e % m);
         cplx acc = cmake(0, 0);
-        for (int x = 0; x < m; ++x) acc = cadd(acc, cdotc(S.U[(long)k * m + x], S.Th[(long)y * m + x]));
-        S.B[(long)k * m + y] = cscale(acc, 1.0 / sig_sorted[k]);
+        for (int y = 0; y < m; ++y) acc = cadd(acc, cmul(S.Th[(long)y * m + x], cconj(S.B[(long)k * m + y])));
+        S.U[(long)k * m + x] = cscale(acc, 1.0 / sig_sorted[k]);
     }
     __syncthreads();
 
