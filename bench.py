@@ -1,7 +1,8 @@
 """Throughput of the iPEPS hot path on one MI355X.
 
 One step = one second-order Trotter step (14 simple-update bond updates) +
-one CTMRG iteration (left, right, up and down moves: 64 enlarged corners, 16
+one CTMRG iteration (left, right, up and down moves: 64 enlarged corners, 52
+of them computed, 16
 half-system projector pairs, 16 T and 32 C renormalisations, 16 corner
 spectra) continuing from the previous environment + one readout of the four
 site occupations and the imbalance.  Workload: D=6, chi=72, d=4 (binary
@@ -56,8 +57,10 @@ METRIC = "Trotter+CTMRG steps/s at D=6,χ=72 (MFMA % peak); batched jobs/s, p50/
 
 def step_flops(D, chi, dtype):
     """Algorithmic real flops of one CTMRG iteration in the real basis, all in
-    the contraction precision.  16 cuts per iteration (4 moves x 2 columns x 2
-    cuts); the cut matrix N = E2 E3 E0 E1 is applied to blocks of k = chi + p
+    the contraction precision.  52 enlarged corners per iteration (64 used;
+    the first column step of the right, up and down moves reuses 4 that the
+    previous move computed and left valid).  16 cuts per iteration (4 moves x
+    2 columns x 2 cuts); the cut matrix N = E2 E3 E0 E1 is applied to blocks of k = chi + p
     columns through its four n x n factors (n = chi D^2), 2 w + 1 times (w
     warm subspace iterations: 1 with FP32 contractions, 2 with FP64; p = 8
     resp. max(16, chi/3)).  The FP64 orthogonalisations (O(n k^2)) are not
@@ -69,7 +72,7 @@ def step_flops(D, chi, dtype):
     else:
         k, w = chi + (8 if chi >= 64 else 16), 1
     k = min(k, n)
-    return 2.0 * (64 * (chi ** 3 * q + chi ** 3 * q ** 2 + chi ** 2 * q ** 4)
+    return 2.0 * (52 * (chi ** 3 * q + chi ** 3 * q ** 2 + chi ** 2 * q ** 4)
                   + 16 * ((2 * w + 1) * 4 * n ** 2 * k + 4 * n ** 2 * chi)
                   + 16 * (chi ** 2 * q ** 4 + 2 * chi ** 3 * q ** 2)
                   + 32 * 2 * chi ** 3 * q)

@@ -247,10 +247,9 @@ void allocate(ipeps_state* st) {
     st->T4p = M.get(2 * cqc * e);
     st->X2 = M.get(8 * n2 * e);
     st->X2p = M.get(8 * n2 * e);
-    st->E = M.get(8 * n2 * e);
+    st->E = M.get(16 * n2 * e);
     st->X1p_aux = M.get(4 * cqc * e);
     st->X2p_aux = M.get(4 * n2 * e);
-    st->E_aux = M.get(4 * n2 * e);
     if (!st->factored) {  // the cut matrix is formed
         st->Fh = M.get(2 * n2 * e);
         st->Gh = M.get(2 * n2 * e);
@@ -331,12 +330,16 @@ GemmProb permuted_rows_cols(GemmProb p, int chi, int q) {
     return p;
 }
 
-// Enlarged corner j (0 UL, 1 UR, 2 DR, 3 DL) of cut Y in a column step of
-// column parity X: the UR and DR corners of the second column live in E_aux.
-char* cut_corner(const ipeps_state* st, int X, int Y, int j) {
-    const long n2 = (long)st->n * st->n;
-    if (X == 1 && (j == 1 || j == 2)) return off(st->E_aux, (Y * 2 + (j - 1)) * n2, st->esz);
-    return off(st->E, (Y * 4 + j) * n2, st->esz);
+// Enlarged corner j (0 UL, 1 UR, 2 DR, 3 DL in the move's frame) of cut Y in
+// column step si.  The matrix of an enlarged corner depends only on its site
+// s and corner index g (it contracts C_g, T_g, T_{g-1} and the double layer
+// of s, rows on the T_{g-1} side, columns on the T_g side), not on the frame,
+// so each (s, g) has one slot in E and a slot stays valid while its inputs do.
+char* cut_corner(const ipeps_state* st, int si, int Y, int j) {
+    const int f = kMoveFrames[si / 2], X = si % 2;
+    const int fx[4] = {X, X + 1, X + 1, X}, fy[4] = {Y, Y, Y + 1, Y + 1};
+    const int site = frame_site(f, fx[j], fy[j]), g = (f + j) % 4;
+    return off(st->E, (site * 4 + g) * (long)st->n * st->n, st->esz);
 }
 
 void build_plan(ipeps_state* st) {
@@ -352,25 +355,34 @@ void build_plan(ipeps_state* st) {
             ColumnStep& cs = st->steps[mi * 2 + X];
             cs.slot = mi * 2 + X;
             std::vector<GemmProb> s1, s2, s3, half, np, pr, pr2, w1, w2, fin, a1, a2, a3;
+            const int si = mi * 2 + X;
+            // A move with frame f' rewrites C_f', C_{f'+3} and T_{f'+3}, i.e. the
+            // enlarged corners with g = f' and g = f' + 3; those with g = f' + 1
+            // and f' + 2 it computed for every site and left valid.  The first
+            // column step of the next move reuses them (within one iteration:
+            // each iteration starts on new double layers).
+            const int fprev = mi > 0 ? kMoveFrames[mi - 1] : -1;
             for (int Y = 0; Y < 2; ++Y) {
                 const int fx[4] = {X, X + 1, X + 1, X}, fy[4] = {Y, Y, Y + 1, Y + 1};
                 for (int j = 0; j < 4; ++j) {
                     const int s = frame_site(f, fx[j], fy[j]);
                     const int g = (f + j) % 4;
                     const int blk = Y * 4 + j;
+                    const bool reuse = X == 0 && mi > 0 && (g == (fprev + 1) % 4 || g == (fprev + 2) % 4);
                     // UR and DR of the second column: computed ahead (aux stream)
                     const bool ahead = X == 1 && (j == 1 || j == 2);
                     const int ab = Y * 2 + (j - 1);
                     char* x1 = off(st->X1, blk * cqc, e);
                     char* x1p = ahead ? off(st->X1p_aux, ab * cqc, e) : off(st->X1p, blk * cqc, e);
                     char* x2p = ahead ? off(st->X2p_aux, ab * n2, e) : off(st->X2p, blk * n2, e);
-                    char* E = cut_corner(st, X, Y, j);
-                    // S1: C (chi x chi) . Tnext (chi x q chi), columns (v, c); and
-                    // again with the columns written in (c, v) order (X1p); the
-                    // first copy only where the C renormalisation reads it (UL)
-                    if (!ahead)
+                    char* E = cut_corner(st, si, Y, j);
+                    // S1: C (chi x chi) . Tnext (chi x q chi), columns (v, c), where
+                    // the C renormalisation reads it (UL); and with the columns
+                    // written in (c, v) order (X1p) for the corner itself
+                    if (j == 0)
                         s1.push_back(gemm_nn(Cp(s, g), chi, Tp(s, g), (long)q * chi, x1, (long)q * chi,
                                              chi, q * chi, chi));
+                    if (reuse) continue;
                     GemmProb p1 = gemm_nn(Cp(s, g), chi, Tp(s, g), (long)q * chi, x1p, (long)q * chi,
                                           chi, q * chi, chi);
                     p1.c_cols0 = chi;  // column j = v chi + c -> c q + v
@@ -395,10 +407,10 @@ void build_plan(ipeps_state* st) {
                     p3.c_cs0 = 1;
                     (ahead ? a3 : s3).push_back(p3);
                 }
-                char* E0 = cut_corner(st, X, Y, 0);
-                char* E1 = cut_corner(st, X, Y, 1);
-                char* E2 = cut_corner(st, X, Y, 2);
-                char* E3 = cut_corner(st, X, Y, 3);
+                char* E0 = cut_corner(st, si, Y, 0);
+                char* E1 = cut_corner(st, si, Y, 1);
+                char* E2 = cut_corner(st, si, Y, 2);
+                char* E3 = cut_corner(st, si, Y, 3);
                 // projectors: P_low = F Vs (n x chi), P_up = Us^T G (chi x n; Us is
                 // stored transposed, chi x n), with the half systems F = E0 E1,
                 // G = E2 E3
@@ -473,7 +485,7 @@ void build_plan(ipeps_state* st) {
             cs.s1 = add_group(st, s1, dt);
             cs.s2 = add_group(st, s2, dt);
             cs.s3 = add_group(st, s3, dt);
-            if (X == 0) cs.s3.tag = 1;  // all 8 corners: the roofline launch
+            if (mi == 0 && X == 0) cs.s3.tag = 1;  // all 8 corners: the roofline launch
             cs.aux_s1 = add_group(st, a1, dt);
             cs.aux_s2 = add_group(st, a2, dt);
             cs.aux_s3 = add_group(st, a3, dt);
@@ -541,15 +553,15 @@ void build_plan(ipeps_state* st) {
                 for (int t = 0; t < 5; ++t) fwd_buf[t] = f[t], bwd_buf[t] = g[t];
             }
             const int fwd_j[4] = {1, 0, 3, 2}, bwd_j[4] = {2, 3, 0, 1};
-            for (int xs = 0; xs < 2; ++xs)  // the corners' buffers depend on the column
+            for (int si = 0; si < 8; ++si)  // the corners' slots depend on the column step
             for (int t = 0; t < 4; ++t) {
-                P.NV[xs][t] = batch2d([&](int b) {
-                    return split(gemm_nn(cut_corner(st, xs, b, fwd_j[t]), n, off(fwd_buf[t], b * nk, e),
+                P.NV[si][t] = batch2d([&](int b) {
+                    return split(gemm_nn(cut_corner(st, si, b, fwd_j[t]), n, off(fwd_buf[t], b * nk, e),
                                          k, off(fwd_buf[t + 1], b * nk, e), k, n, k, n),
                                  kv, wv + b * kv * nk);
                 });
-                P.NtQ[xs][t] = batch2d([&](int b) {
-                    GemmProb p = gemm_nn(off(bwd_buf[t], b * nk, e), n, cut_corner(st, xs, b, bwd_j[t]),
+                P.NtQ[si][t] = batch2d([&](int b) {
+                    GemmProb p = gemm_nn(off(bwd_buf[t], b * nk, e), n, cut_corner(st, si, b, bwd_j[t]),
                                          n, off(bwd_buf[t + 1], b * nk, e), n, k, n, n);
                     if (t == 3) {  // C(i, j) -> [j][i]
                         p.c_rows0 = k;
@@ -817,20 +829,20 @@ double proj_cutoff(const ipeps_state* st) { return st->dtype == IPEPS_DTYPE_FP64
 // Yw = N Qz and Zw = N^T Qw for the two cuts: with the formed N64 (FP64), or
 // through the enlarged corners (products in dtype; FP64 blocks converted at
 // both ends in FP32 mode).
-void apply_n(ipeps_state* st, int X) {
+void apply_n(ipeps_state* st, int si) {
     if (!st->factored) return run(st, st->svd.NVf);
     const long nk = (long)st->n * st->k;
     const bool f64 = st->dtype == IPEPS_DTYPE_FP64;
     if (!f64) from_fp64_blocks(st->stream, st->dtype, st->Qz, st->Ch[2], 2, st->n, st->k, false);
-    for (const GemmGroup& g : st->svd.NV[X]) run(st, g);
+    for (const GemmGroup& g : st->svd.NV[si]) run(st, g);
     if (!f64) to_fp64(st->stream, st->dtype, st->Ch[1], st->Yw, 2 * nk);
 }
 
-void apply_nt(ipeps_state* st, int X) {
+void apply_nt(ipeps_state* st, int si) {
     if (!st->factored) return run(st, st->svd.NtQf);
     const long nk = (long)st->n * st->k;
     from_fp64_blocks(st->stream, st->dtype, st->Qw, st->Qt, 2, st->n, st->k, true);
-    for (const GemmGroup& g : st->svd.NtQ[X]) run(st, g);
+    for (const GemmGroup& g : st->svd.NtQ[si]) run(st, g);
     if (st->dtype != IPEPS_DTYPE_FP64) to_fp64(st->stream, st->dtype, st->Ch[2], st->Zw, 2 * nk);
 }
 
@@ -866,14 +878,14 @@ void projector_svd(ipeps_state* st, int slot) {
         // dropped here is zero in V, hence dead in the next left block and
         // restarted there.  Zero columns of the final V only add zero Ritz
         // values.
-        apply_n(st, slot % 2);  // Yw = N V
+        apply_n(st, slot);  // Yw = N V
         orth(st, st->Yw, st->Qw, P.gramY, P.QfromY, P.gramQ, P.YfromQ, false, &P.projQw1,
              &P.projQw2);
-        apply_nt(st, slot % 2);  // Zw = N^T Qw
+        apply_nt(st, slot);  // Zw = N^T Qw
         orth(st, st->Zw, st->Qz, P.gramZ, P.QfromZ, P.gramQz, P.ZfromQz, false);
     }
     // Rayleigh-Ritz on span(N V) x span(V)
-    apply_n(st, slot % 2);
+    apply_n(st, slot);
     HIP_CHECK(hipMemcpyAsync(st->Zw, st->Yw, 2 * nk * sizeof(double), hipMemcpyDeviceToDevice, s));
     orth(st, st->Yw, st->Qw, P.gramY, P.QfromY, P.gramQ, P.YfromQ, true);
     run(st, P.Cs);  // Cs = (Q^T N V)^T

@@ -41,7 +41,7 @@ struct ColumnStep {
     GemmGroup s1, s2, s3, half, nprod, proj, proj2, w1, w2, fin;
     // second column of a move (X = 1): its UR and DR enlarged corners read
     // only tensors the move leaves alone; the first column step enqueues
-    // them on the aux stream (into X1p_aux, X2p_aux, E_aux) to fill the idle
+    // them on the aux stream (into X1p_aux, X2p_aux, their E slots) to fill the idle
     // phases of its projector SVD
     GemmGroup aux_s1, aux_s2, aux_s3;
     // buffers the step touches
@@ -55,7 +55,7 @@ struct SvdPlan {
     // N V and N^T Q through the four enlarged corners of each cut
     // (N = E2 E3 E0 E1), one product per group, in dtype; orth passes on Y
     // and Z and the Rayleigh-Ritz products, batch 2 (FP64)
-    GemmGroup NV[2][4], NtQ[2][4];  // [column parity X][factor]
+    GemmGroup NV[8][4], NtQ[8][4];  // [column step][factor]
     GemmGroup NVf, NtQf;  // the same with the formed N64
     GemmGroup gramY, gramZ, gramQ, gramQz, QfromY, QfromZ, YfromQ, ZfromQz, Cs, Uo,
         Vo;
@@ -123,11 +123,12 @@ struct ipeps_state {
     void* T4p;  // 2 blocks of chi * chi * q
     void* X2;   // 8 blocks of n^2
     void* X2p;  // 8 blocks of n^2
-    void* E;    // 8 blocks of n^2 (enlarged corners E0..E3 of the two cuts)
+    // enlarged corners, one n^2 slot per (site, corner index g), kept across
+    // the moves of an iteration (blocks 0..7 are readout scratch)
+    void* E;
     // UR, DR corners of the second column step: 4 blocks each ([Y][j - 1])
     void* X1p_aux;
     void* X2p_aux;
-    void* E_aux;
     // cut matrices formed (not factored) only:
     void* Fh;   // 2 blocks of n^2
     void* Gh;   // 2 blocks of n^2
