@@ -2,10 +2,10 @@
 
 One step = one second-order Trotter step (14 simple-update bond updates) +
 one CTMRG iteration (left, right, up and down moves: 64 enlarged corners, 52
-of them computed, 16
-half-system projector pairs, 16 T and 32 C renormalisations, 16 corner
-spectra) continuing from the previous environment + one readout of the four
-site occupations and the imbalance.  Workload: D=6, chi=72, d=4 (binary
+of them computed, 16 half-system projector pairs, 16 T and 32 C
+renormalisations, 16 corner spectra) continuing from the previous
+environment + one readout of the four site occupations and the imbalance.
+Workload: D=6, chi=72, d=4 (binary
 disorder), J=1, V=1, W=8, dt=0.05, synthetic Néel ⊗ |+> start; the state is
 first evolved (untimed) to t = 1 so that every bond carries D singular values.
 
@@ -41,7 +41,8 @@ ROOF_KERNEL = "k_gemm_direct<...,TAG=1> (8 enlarged-corner products)"
 # 256 MiB copy), from the traffic profile in profiles/; valid only for the
 # tile planning, kernels and launches they were measured on (the part of
 # gemm.hip from tile_dims on, see gemm_kernel_digest) and for ROOF_KERNEL.
-TRAFFIC = {"fp32": {"kernel": None, "gemm_kernel_sha256_16": None, "bytes_per_launch": None}}
+TRAFFIC = {"fp32": {"kernel": ROOF_KERNEL, "gemm_kernel_sha256_16": "2d410b19bcb236aa",
+                    "bytes_per_launch": 1.397e9}}
 
 
 def gemm_kernel_digest():
