@@ -276,6 +276,8 @@ void allocate(ipeps_state* st) {
     st->ws_gram = (double*)M.get(2L * st->ks_gram * k * k * sizeof(double));
     st->ws_nv = (double*)M.get(2L * st->ks_nv * nk * sizeof(double));
     st->ws_c = M.get(4L * st->ks_c * chi * chi * e);
+    st->ks_p = clampi(n / 512, 1, 8);
+    st->ws_p = M.get(4L * st->ks_p * n * chi * e);
     st->warm = (double*)M.get(16 * nk * sizeof(double));
     st->Yw = (double*)M.get(2 * nk * sizeof(double));
     st->Zw = (double*)M.get(2 * nk * sizeof(double));
@@ -284,9 +286,11 @@ void allocate(ipeps_state* st) {
     st->Gm = (double*)M.get(2L * k * k * sizeof(double));
     st->Ri = (double*)M.get(2L * k * k * sizeof(double));
     st->Rb = (double*)M.get(2 * nk * sizeof(double));
-    st->Qt = st->Ch[0] = st->Ch[1] = st->Ch[2] = nullptr;
+    st->Qt = st->Ch[0] = st->Ch[1] = st->Ch[2] = st->T2 = st->VsK = nullptr;
     if (st->factored) {
         st->Qt = M.get(2 * nk * e);
+        st->T2 = M.get(2 * nk * e);
+        st->VsK = M.get(2L * k * chi * e);
         if (st->dtype != IPEPS_DTYPE_FP64)
             for (int i = 0; i < 3; ++i) st->Ch[i] = M.get(2 * nk * e);
     }
@@ -418,24 +422,27 @@ void build_plan(ipeps_state* st) {
                 char* vs = off(st->Vs, Y * (long)n * chi, e);
                 char* plow = off(st->Plow, Y * (long)n * chi, e);
                 char* pup = off(st->Pup, Y * (long)n * chi, e);
+                // the n x n by n x chi products are split over K (a launch of a
+                // few hundred workgroups would otherwise walk K = n serially)
+                const int ksp = st->ks_p;
+                auto wsp = [&](int r) { return off(st->ws_p, r * (long)ksp * n * chi, e); };
                 if (!st->factored) {
                     char* F = off(st->Fh, Y * n2, e);
                     char* G = off(st->Gh, Y * n2, e);
                     half.push_back(gemm_nn(E0, n, E1, n, F, n, n, n, n));
                     half.push_back(gemm_nn(E2, n, E3, n, G, n, n, n, n));
                     np.push_back(gemm_nn(G, n, F, n, off(st->Nd, Y * n2, e), n, n, n, n));
-                    pr.push_back(gemm_nn(F, n, vs, chi, plow, chi, n, chi, n));
-                    pr.push_back(gemm_nn(us, n, G, n, pup, n, chi, n, n));
+                    pr.push_back(split(gemm_nn(F, n, vs, chi, plow, chi, n, chi, n), ksp, wsp(Y * 2)));
+                    pr.push_back(split(gemm_nn(us, n, G, n, pup, n, chi, n, n), ksp, wsp(Y * 2 + 1)));
                 } else {
-                    // F and G are never formed: E1 Vs and Us^T E2 first (into the
-                    // PlowP / PupP buffers, rewritten by the permutes after), then
-                    // E0 (E1 Vs) and (Us^T E2) E3
-                    char* pl1 = off(st->PlowP, Y * (long)n * chi, e);
+                    // F and G are never formed: Us^T E2 first (into the PupP
+                    // buffer, rewritten by the permute after), then (Us^T E2) E3;
+                    // P_low comes from the last forward chain (SvdPlan::PlowT2)
+                    (void)vs;
+                    (void)plow;
                     char* pu1 = off(st->PupP, Y * (long)n * chi, e);
-                    pr.push_back(gemm_nn(E1, n, vs, chi, pl1, chi, n, chi, n));
-                    pr.push_back(gemm_nn(us, n, E2, n, pu1, n, chi, n, n));
-                    pr2.push_back(gemm_nn(E0, n, pl1, chi, plow, chi, n, chi, n));
-                    pr2.push_back(gemm_nn(pu1, n, E3, n, pup, n, chi, n, n));
+                    pr.push_back(split(gemm_nn(us, n, E2, n, pu1, n, chi, n, n), ksp, wsp(Y)));
+                    pr2.push_back(split(gemm_nn(pu1, n, E3, n, pup, n, chi, n, n), ksp, wsp(Y)));
                 }
                 // renormalisation inputs of column X
                 const int sxy = frame_site(f, X, Y);
@@ -478,9 +485,10 @@ void build_plan(ipeps_state* st) {
                                             Cp(frame_site(f, X + 1, Y), (3 + f) % 4), chi, chi, chi, n),
                                     ksc, off(st->ws_c, (2 * Y + 1) * (long)ksc * chi * chi, e)));
                 // T4(X+1, Y) = W2(Y) [rows (c', R), k = (t4n, U)] . P_low(Y-1)
-                fin.push_back(gemm_nn(off(st->W2, Y * n2, e), n, off(st->Plow, Yp * (long)n * chi, e),
-                                      chi, Tp(frame_site(f, X + 1, Y), (3 + f) % 4), chi, chi * q,
-                                      chi, n));
+                fin.push_back(split(gemm_nn(off(st->W2, Y * n2, e), n, off(st->Plow, Yp * (long)n * chi, e),
+                                            chi, Tp(frame_site(f, X + 1, Y), (3 + f) % 4), chi, chi * q,
+                                            chi, n),
+                                    st->ks_p, off(st->ws_p, Y * (long)st->ks_p * n * chi, e)));
             }
             cs.s1 = add_group(st, s1, dt);
             cs.s2 = add_group(st, s2, dt);
@@ -545,10 +553,12 @@ void build_plan(ipeps_state* st) {
                 for (int b = 0; b < 2; ++b) out.push_back(make(b));
                 return add_group(st, out, dt);
             };
-            void* fwd_buf[5] = {st->Qz, st->Zw, st->Qw, st->Zw, st->Yw};
+            // the forward chain keeps E0 E1 V in T2: after the Rayleigh-Ritz
+            // step (V = Qz, Vo = Qz Uc) P_low = F Vo S^-1/2 = T2 (Uc S^-1/2)
+            void* fwd_buf[5] = {st->Qz, st->Zw, st->T2, st->Zw, st->Yw};
             void* bwd_buf[5] = {st->Qt, st->Yw, st->Qz, st->Yw, st->Zw};
             if (!f64) {
-                void* const f[5] = {st->Ch[2], st->Ch[0], st->Ch[1], st->Ch[0], st->Ch[1]};
+                void* const f[5] = {st->Ch[2], st->Ch[0], st->T2, st->Ch[0], st->Ch[1]};
                 void* const g[5] = {st->Qt, st->Ch[0], st->Ch[1], st->Ch[0], st->Ch[2]};
                 for (int t = 0; t < 5; ++t) fwd_buf[t] = f[t], bwd_buf[t] = g[t];
             }
@@ -574,6 +584,10 @@ void build_plan(ipeps_state* st) {
                     return split(p, kv, wv + b * kv * nk);
                 });
             }
+            P.PlowT2 = batch2d([&](int b) {
+                return gemm_nn(off(st->T2, b * nk, e), k, off(st->VsK, b * (long)k * chi, e), chi,
+                               off(st->Plow, b * (long)n * chi, e), chi, n, chi, k);
+            });
         }
         auto gram = [&](double* X) {
             return batch2([&](int b) {
@@ -900,6 +914,13 @@ void projector_svd(ipeps_state* st, int slot) {
     HIP_CHECK(hipMemcpyAsync(st->warm + 2 * slot * nk, st->Vo, 2 * nk * sizeof(double),
                              hipMemcpyDeviceToDevice, s));
     st->warm_valid[2 * slot] = st->warm_valid[2 * slot + 1] = true;
+    if (st->factored) {
+        // Uc S^-1/2 truncated (k x chi; its Us output is overwritten below),
+        // then P_low = T2 (Uc S^-1/2)
+        projector_factors(s, st->dtype, 2, k, k, chi, proj_cutoff(st), st->Uc, st->Uc, st->sig,
+                          (long)k * k, st->Us, st->VsK, (long)k * chi, st->g_dev);
+        run(st, P.PlowT2);
+    }
     projector_factors(s, st->dtype, 2, n, k, chi, proj_cutoff(st), st->Uo, st->Vo, st->sig, nk,
                       st->Us, st->Vs,
                       (long)n * chi, st->g_dev);

@@ -57,6 +57,7 @@ struct SvdPlan {
     // and Z and the Rayleigh-Ritz products, batch 2 (FP64)
     GemmGroup NV[8][4], NtQ[8][4];  // [column step][factor]
     GemmGroup NVf, NtQf;  // the same with the formed N64
+    GemmGroup PlowT2;     // factored path: P_low = (E0 E1 Qz) (Uc S^-1/2)
     GemmGroup gramY, gramZ, gramQ, gramQz, QfromY, QfromZ, YfromQ, ZfromQz, Cs, Uo,
         Vo;
     // restart of dropped left columns: Gm = Qw^T Rb, Rb -= Qw Gm
@@ -154,13 +155,18 @@ struct ipeps_state {
     // Q^T (k x n); Ch[0..2] the blocks of the product chains (FP32 mode)
     void* Qt;
     void* Ch[3];
+    // E0 E1 V of the last forward chain (n x k, dtype) and the k x chi factor
+    // that turns it into P_low (factored path)
+    void* T2;
+    void* VsK;
     int* dead_dev;       // 2*k flags of dropped columns, then 2 counts
     uint64_t orth_calls; // counter feeding the refill hash
     int extra_warm_iters; // added warm subspace iterations (converging to a tolerance)
     double* norm_ws;     // partial sums of the tensor normalisation (32 tensors)
     double* norm_ws_su;  // the same for normalisations on the SU stream
     double *Nfull_U, *Nfull_V;  // direct path (n <= 96)
-    int ks_gram, ks_nv, ks_c;   // split-K factors
+    int ks_gram, ks_nv, ks_c, ks_p;  // split-K factors
+    void* ws_p;                      // split-K partials of the n x chi products (dtype)
     double *ws_gram, *ws_nv;    // split-K partials (FP64)
     void* ws_c;                 // split-K partials of the corner renormalisations (dtype)
 
