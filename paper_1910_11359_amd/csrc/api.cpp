@@ -50,6 +50,7 @@ constexpr int kDirectMax = 96;  // projector SVD by direct Jacobi when n <= this
 // cut matrices applied through their factors (no n^3 product) when n > this
 // (below, forming them takes fewer launches and less time)
 constexpr int kFactoredMin = 1024;
+constexpr int kChainTile = TILE_DIRECT_SMALL;  // tile kind of the factored chain products
 constexpr int kColdIters = 8;   // subspace iterations for a fresh random block
 constexpr int kWarmIters = 2;   // ... when warm-started from the last iteration (FP64)
 // With FP32 cut products the matrix itself carries ~1e-7 relative rounding;
@@ -163,7 +164,9 @@ GemmTile autotune_tile(ipeps_state* st, std::vector<GemmProb> probs, int dtype, 
     return best;
 }
 
-GemmGroup add_group(ipeps_state* st, std::vector<GemmProb> probs, int dtype) {
+// force >= 0: that tile kind (if the operands allow it) instead of the
+// heuristic or the autotuner
+GemmGroup add_group(ipeps_state* st, std::vector<GemmProb> probs, int dtype, int force = -1) {
     GemmGroup g;
     g.first = (int)st->probs.size();
     g.count = (int)probs.size();
@@ -171,7 +174,18 @@ GemmGroup add_group(ipeps_state* st, std::vector<GemmProb> probs, int dtype) {
     g.tiles = gemm_plan_tiles(probs.data(), g.count, dtype, &g.tile);
     for (const auto& p : probs)
         if (p.ksplit > 1) g.reduce_elems = std::max(g.reduce_elems, (long)p.M * p.N);
-    if (st->autotune && g.count > 0) {
+    bool forced = false;
+    if (force >= 0 && g.count > 0) {
+        GemmTile cand[4];
+        const int nc = gemm_tile_candidates(probs.data(), g.count, dtype, cand);
+        for (int i = 0; i < nc; ++i)
+            if (cand[i] == (GemmTile)force) {
+                g.tile = (GemmTile)force;
+                g.tiles = gemm_plan_with(probs.data(), g.count, dtype, g.tile);
+                forced = true;
+            }
+    }
+    if (st->autotune && g.count > 0 && !forced) {
         const GemmTile t = autotune_tile(st, probs, dtype, g.reduce_elems, g.tile);
         if (t != g.tile) {
             g.tile = t;
@@ -274,7 +288,8 @@ void allocate(ipeps_state* st) {
     st->ks_nv = clampi(n / 512, 1, 8);
     st->ks_c = clampi(n / 256, 1, 32);
     st->ws_gram = (double*)M.get(2L * st->ks_gram * k * k * sizeof(double));
-    st->ws_nv = (double*)M.get(2L * st->ks_nv * nk * sizeof(double));
+    st->ks_chain = clampi(n / 512, 1, 16);
+    st->ws_nv = (double*)M.get(2L * std::max((size_t)st->ks_nv * sizeof(double), (size_t)st->ks_chain * e) * nk);
     st->ws_c = M.get(4L * st->ks_c * chi * chi * e);
     st->ks_p = clampi(n / 512, 1, 8);
     st->ws_p = M.get(4L * st->ks_p * n * chi * e);
@@ -548,11 +563,17 @@ void build_plan(ipeps_state* st) {
             });
         } else {
             const bool f64 = dt == IPEPS_DTYPE_FP64;
+            // the chain products (n x n corner against a k-column block): 64 x 64
+            // tiles, K split in 5 at n = 2592 (measured at D=6, chi=72, k=80:
+            // 128 x 128 tiles, which stream each corner once instead of twice,
+            // are slower, 36.8 vs 36.4 ms per step; splits of 3 to 10 within
+            // 0.1 ms)
             auto batch2d = [&](auto make) {
                 std::vector<GemmProb> out;
                 for (int b = 0; b < 2; ++b) out.push_back(make(b));
-                return add_group(st, out, dt);
+                return add_group(st, out, dt, k <= 128 ? kChainTile : -1);
             };
+            const int kv = st->ks_chain;
             // the forward chain keeps E0 E1 V in T2: after the Rayleigh-Ritz
             // step (V = Qz, Vo = Qz Uc) P_low = F Vo S^-1/2 = T2 (Uc S^-1/2)
             void* fwd_buf[5] = {st->Qz, st->Zw, st->T2, st->Zw, st->Yw};
@@ -568,7 +589,7 @@ void build_plan(ipeps_state* st) {
                 P.NV[si][t] = batch2d([&](int b) {
                     return split(gemm_nn(cut_corner(st, si, b, fwd_j[t]), n, off(fwd_buf[t], b * nk, e),
                                          k, off(fwd_buf[t + 1], b * nk, e), k, n, k, n),
-                                 kv, wv + b * kv * nk);
+                                 kv, off(wv, b * kv * nk, e));
                 });
                 P.NtQ[si][t] = batch2d([&](int b) {
                     GemmProb p = gemm_nn(off(bwd_buf[t], b * nk, e), n, cut_corner(st, si, b, bwd_j[t]),
@@ -581,7 +602,7 @@ void build_plan(ipeps_state* st) {
                         p.c_cs1 = 0;
                         p.c_cs0 = k;
                     }
-                    return split(p, kv, wv + b * kv * nk);
+                    return split(p, kv, off(wv, b * kv * nk, e));
                 });
             }
             P.PlowT2 = batch2d([&](int b) {

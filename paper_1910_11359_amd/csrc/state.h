@@ -165,7 +165,7 @@ struct ipeps_state {
     double* norm_ws;     // partial sums of the tensor normalisation (32 tensors)
     double* norm_ws_su;  // the same for normalisations on the SU stream
     double *Nfull_U, *Nfull_V;  // direct path (n <= 96)
-    int ks_gram, ks_nv, ks_c, ks_p;  // split-K factors
+    int ks_gram, ks_nv, ks_c, ks_p, ks_chain;  // split-K factors
     void* ws_p;                      // split-K partials of the n x chi products (dtype)
     double *ws_gram, *ws_nv;    // split-K partials (FP64)
     void* ws_c;                 // split-K partials of the corner renormalisations (dtype)
