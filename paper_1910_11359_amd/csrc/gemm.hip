@@ -318,14 +318,21 @@ struct Vec16<double> { typedef double v_t __attribute__((ext_vector_type(2))); }
 // by the row, read as 16-byte vectors (k order inside a tile permuted alike
 // for A and B); B (n contiguous) is stored [k][n] with chunks swizzled by the
 // lane group that reads the row, read as scalars.
-__device__ inline void wait_vm(int n) {
-    // s_waitcnt vmcnt(n) (gfx9 encoding: vmcnt[3:0] and [15:14]; expcnt and
-    // lgkmcnt left at their maxima so they impose no wait)
-    switch (n) {
-        case 0: __builtin_amdgcn_s_waitcnt(0 | (7 << 4) | (15 << 8)); break;
-        case 8: __builtin_amdgcn_s_waitcnt(8 | (7 << 4) | (15 << 8)); break;
-        case 16: __builtin_amdgcn_s_waitcnt(0 | (1 << 14) | (7 << 4) | (15 << 8)); break;
-        default: __builtin_amdgcn_s_waitcnt(8 | (1 << 14) | (7 << 4) | (15 << 8)); break;
+// s_waitcnt vmcnt(N) (gfx9 encoding: vmcnt[3:0] and [15:14]; expcnt and
+// lgkmcnt left at their maxima so they impose no wait)
+template <int N>
+__device__ inline void wait_vm_n() {
+    static_assert(N >= 0 && N <= 63, "vmcnt is 6 bits");
+    __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
+}
+// vmcnt(s * STEP) for s in 0..3 (the immediate must be a constant)
+template <int STEP>
+__device__ inline void wait_vm(int s) {
+    switch (s) {
+        case 0: wait_vm_n<0>(); break;
+        case 1: wait_vm_n<STEP>(); break;
+        case 2: wait_vm_n<2 * STEP>(); break;
+        default: wait_vm_n<3 * STEP>(); break;
     }
 }
 
@@ -344,6 +351,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
     constexpr int ASZ = BM * BK, BSZ = BK * BN;
     constexpr int NLD = (BM * ACH) / 256;     // A loads per lane per tile (= B loads)
     static_assert(BM * ACH == BK * BCH, "A and B tiles must need the same number of loads");
+    static_assert(NS >= 2 && NS <= 5, "wait_vm covers up to 3 tiles in flight behind the current one");
     typedef typename Vec16<T>::v_t v_t;
     __shared__ __attribute__((aligned(16))) T Sm[NS * (ASZ + BSZ)];
 
@@ -428,7 +436,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
         if (s < nk) issue(s, s);
     for (int kt = 0; kt < nk; ++kt) {
         const int ahead = nk - 1 - kt;  // tiles issued after this one
-        wait_vm(NLD * 2 * (ahead < NS - 2 ? ahead : NS - 2));
+        wait_vm<NLD * 2>(ahead < NS - 2 ? ahead : NS - 2);
         const int stg = kt % NS;
         T* as = Sm + stg * (ASZ + BSZ);
         const T* bs = as + ASZ;
