@@ -850,7 +850,9 @@ void orth(ipeps_state* st, double* X, double* Q, const GemmGroup& gram1, const G
     }
     if (!two_pass) return;
     run(st, gram2);
-    chol_inverse(s, 2, k, st->Gm, st->Ri, kCholDrop);
+    // second pass: when the first left the columns orthonormal to 1e-13 the
+    // factorisation would change them by no more than that; it is skipped
+    chol_inverse(s, 2, k, st->Gm, st->Ri, kCholDrop, nullptr, 1e-13);
     run(st, mul2);
 }
 

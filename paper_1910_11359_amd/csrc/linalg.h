@@ -29,8 +29,12 @@ size_t jacobi_svd_real_work(int batch, int m, int n);
 // columns of X before taking the Gram.  If dead is not null
 // (batch*k + batch ints), dead[b*k + j] is set to 1 for a dropped column j
 // and 0 otherwise, and dead[batch*k + b] to the number of dropped columns.
+// near_identity > 0: a matrix whose scaled Gram G' has every off-diagonal
+// |G'_ij| <= near_identity and no zero diagonal skips the factorisation and
+// gets R^{-1} = D^{-1} (the second pass of a Cholesky QR, whose first pass
+// already left the columns orthonormal to that level).
 void chol_inverse(hipStream_t s, int batch, int k, const double* G, double* Rinv, double tol,
-                  int* dead = nullptr);
+                  int* dead = nullptr, double near_identity = 0.0);
 
 // Scale the columns of batched n x k row-major matrices (stride n*k) to unit
 // 2-norm; zero columns stay zero.

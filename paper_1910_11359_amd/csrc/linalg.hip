@@ -263,10 +263,11 @@ __device__ inline double readlane_d(double v, int lane) {
 template <bool IN_LDS>
 __global__ __launch_bounds__(256) void k_chol_inverse(int k, const double* __restrict__ G,
                                                       double* __restrict__ Rinv, double tol,
-                                                      int* __restrict__ dead) {
+                                                      int* __restrict__ dead, double near_identity) {
     extern __shared__ double smem[];
     __shared__ int dead_s[256];
     __shared__ double dsc[256];  // 1/sqrt(G_ii): G is factored scaled to unit diagonal
+    __shared__ double red[4];
     const int tid = threadIdx.x, lane = tid & 63;
     const int b = blockIdx.x;
     const double* Gb = G + (long)b * k * k;
@@ -278,7 +279,28 @@ __global__ __launch_bounds__(256) void k_chol_inverse(int k, const double* __res
         dsc[i] = gii > 0.0 ? 1.0 / sqrt(gii) : 0.0;
     }
     __syncthreads();
-    for (int e = tid; e < k * k; e += 256) R[e] = Gb[e] * dsc[e / k] * dsc[e % k];
+    double off_max = 0.0;  // largest |G'_ij| off the diagonal; 1 if a diagonal is zero
+    for (int e = tid; e < k * k; e += 256) {
+        const int i = e / k, c = e - (e / k) * k;
+        const double v = Gb[e] * dsc[i] * dsc[c];
+        R[e] = v;
+        if (i != c) off_max = fmax(off_max, fabs(v));
+        else if (!(dsc[i] > 0.0)) off_max = 1.0;
+    }
+    if (near_identity > 0.0) {
+        off_max = block_max(off_max, red);
+        if (off_max <= near_identity) {  // R' = I: R^{-1} = D^{-1}, nothing dropped
+            for (int e = tid; e < k * k; e += 256) {
+                const int i = e / k, c = e - (e / k) * k;
+                out[e] = (i == c) ? dsc[i] : 0.0;
+            }
+            if (dead) {
+                for (int j = tid; j < k; j += 256) dead[(long)b * k + j] = 0;
+                if (tid == 0) dead[(long)gridDim.x * k + b] = 0;
+            }
+            return;
+        }
+    }
     __syncthreads();
 
     for (int J0 = 0; J0 < k; J0 += kNb) {
@@ -432,7 +454,7 @@ static size_t chol_lds_bytes(int k, bool in_lds) {
 }
 
 void chol_inverse(hipStream_t s, int batch, int k, const double* G, double* Rinv, double tol,
-                  int* dead) {
+                  int* dead, double near_identity) {
     if (batch <= 0) return;
     IPEPS_REQUIRE(k >= 1 && k <= 256, IPEPS_EINVAL, "chol_inverse: k must be in 1..256");
     const bool in_lds = k <= 128;
@@ -448,9 +470,11 @@ void chol_inverse(hipStream_t s, int batch, int k, const double* G, double* Rinv
         attr_set = true;
     }
     if (in_lds)
-        hipLaunchKernelGGL(k_chol_inverse<true>, dim3(batch), dim3(256), lds, s, k, G, Rinv, tol, dead);
+        hipLaunchKernelGGL(k_chol_inverse<true>, dim3(batch), dim3(256), lds, s, k, G, Rinv, tol, dead,
+                           near_identity);
     else
-        hipLaunchKernelGGL(k_chol_inverse<false>, dim3(batch), dim3(256), lds, s, k, G, Rinv, tol, dead);
+        hipLaunchKernelGGL(k_chol_inverse<false>, dim3(batch), dim3(256), lds, s, k, G, Rinv, tol, dead,
+                           near_identity);
     HIP_CHECK(hipGetLastError());
 }
 
