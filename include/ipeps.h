@@ -180,6 +180,21 @@ int ctmrg_converge(ipeps_state* st, double tol, int max_iter, int cold_start, in
  * yet), ENUMERIC. */
 int ipeps_observe(ipeps_state* st, ipeps_obs* out);
 
+/* The same readout, asynchronous (Readout; Results): copies the current
+ * environment, site tensors and truncation errors on the state's stream
+ * (about 12 MB at D=6, chi=72 FP32) and reads the copy out on a stream of its
+ * own, so the caller can enqueue the next Trotter step and CTMRG before the
+ * result is needed.  One readout may be pending per state: a second call
+ * before ipeps_observe_result returns EINVAL.  The result equals what
+ * ipeps_observe returns for the same environment (same kernels, same
+ * inputs).  Errors: EINVAL (no environment yet, or a readout pending). */
+int ipeps_observe_async(ipeps_state* st);
+
+/* Waits for the pending asynchronous readout and fills out (fields as for
+ * ipeps_observe, of the environment at the time of ipeps_observe_async).
+ * Errors: EINVAL (nothing pending), ENUMERIC. */
+int ipeps_observe_result(ipeps_state* st, ipeps_obs* out);
+
 /* Singular values of the 16 corners (sites in order, C1..C4 each),
  * normalised to unit 2-norm, zero-padded: out holds 16 * chi doubles.
  * Synchronises the stream. */

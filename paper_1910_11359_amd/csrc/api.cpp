@@ -327,6 +327,20 @@ void allocate(ipeps_state* st) {
     st->spectra = (double*)M.get(16L * chi * sizeof(double));
     st->spec_prev = (double*)M.get(16L * chi * sizeof(double));
     st->dev_scalars = (double*)M.get(8 * sizeof(double));
+    // asynchronous readout: snapshot of C, T, A, eps and its own scratch
+    st->Csnap = M.get(16L * chi * chi * e);
+    st->Tsnap = M.get(16L * cqc * e);
+    st->Asnap = (cplx*)M.get(4 * d * D4 * sizeof(cplx));
+    st->eps_r = (double*)M.get(8 * sizeof(double));
+    st->X1r = M.get(8 * cqc * e);
+    st->X2r = M.get(8 * n2 * e);
+    st->X2pr = M.get(8 * n2 * e);
+    st->Er = M.get(8 * n2 * e);
+    st->Eout_r = M.get(4 * q4 * e);
+    st->E64_r = (double*)M.get(4 * q4 * sizeof(double));
+    st->rho_r = (cplx*)M.get(4 * (long)d * d * sizeof(cplx));
+    st->rho_T_r = (cplx*)M.get(4 * D4 * d * sizeof(cplx));
+    st->obs_r = (double*)M.get(16 * sizeof(double));
     st->Eout = M.get(4 * q4 * e);
     st->E64 = (double*)M.get(4 * q4 * sizeof(double));
     st->rho = (cplx*)M.get(4 * (long)d * d * sizeof(cplx));
@@ -684,33 +698,45 @@ void build_plan(ipeps_state* st) {
     for (int i = 0; i < 16; ++i) st->norms.push_back({off(st->Cenv, i * cc, e), cc});
     for (int i = 0; i < 16; ++i) st->norms.push_back({off(st->Tenv, i * cqc, e), cqc});
 
-    // readout: per site, L' = (T4 (C1 T1)) C2 and R' = (T2 (C3 T3)) C4
-    {
+    // readout: per site, L' = (T4 (C1 T1)) C2 and R' = (T2 (C3 T3)) C4; once
+    // on the live tensors and scratch, once on the snapshot of the
+    // asynchronous readout
+    auto build_read = [&](void* Cb, void* Tb, void* X1b, void* X2b, void* X2pb, void* Eb, void* Eoutb,
+                          GemmGroup* g) {
+        auto Cq = [&](int site, int kk) { return off(Cb, (site * 4 + kk) * cc, e); };
+        auto Tq = [&](int site, int kk) { return off(Tb, (site * 4 + kk) * cqc, e); };
         std::vector<GemmProb> r1, r2, r3, r4;
         const long q4 = (long)q * q * q * q;
         for (int s = 0; s < 4; ++s) {
             for (int side = 0; side < 2; ++side) {
-                const int g = side ? 2 : 0;
+                const int g0 = side ? 2 : 0;
                 const int blk = side * 4 + s;
-                char* x1 = off(st->X1, blk * cqc, e);
-                char* x2 = off(st->X2, blk * n2, e);
-                r1.push_back(gemm_nn(Cp(s, g), chi, Tp(s, g), (long)q * chi, x1, (long)q * chi, chi,
+                char* x1 = off(X1b, blk * cqc, e);
+                char* x2 = off(X2b, blk * n2, e);
+                r1.push_back(gemm_nn(Cq(s, g0), chi, Tq(s, g0), (long)q * chi, x1, (long)q * chi, chi,
                                      q * chi, chi));
-                r2.push_back(gemm_nn(Tp(s, (g + 3) % 4), chi, x1, (long)q * chi, x2, (long)q * chi,
+                r2.push_back(gemm_nn(Tq(s, (g0 + 3) % 4), chi, x1, (long)q * chi, x2, (long)q * chi,
                                      chi * q, q * chi, chi));
                 // contract the open chi leg with the next corner (C2 resp. C4)
-                r3.push_back(gemm_nn(x2, chi, Cp(s, g + 1), chi, off(st->X2p, blk * n2, e), chi,
+                r3.push_back(gemm_nn(x2, chi, Cq(s, g0 + 1), chi, off(X2pb, blk * n2, e), chi,
                                      chi * q * q, chi, chi));
             }
             // E[s] = Lp (q^2 x chi^2) . Rp (chi^2 x q^2)
-            r4.push_back(gemm_nn(off(st->E, s * n2, e), (long)chi * chi, off(st->E, (4 + s) * n2, e),
-                                 (long)q * q, off(st->Eout, s * q4, e), (long)q * q, q * q, q * q,
+            r4.push_back(gemm_nn(off(Eb, s * n2, e), (long)chi * chi, off(Eb, (4 + s) * n2, e),
+                                 (long)q * q, off(Eoutb, s * q4, e), (long)q * q, q * q, q * q,
                                  chi * chi));
         }
-        st->read1 = add_group(st, r1, dt);
-        st->read2 = add_group(st, r2, dt);
-        st->read3 = add_group(st, r3, dt);
-        st->read4 = add_group(st, r4, dt);
+        g[0] = add_group(st, r1, dt);
+        g[1] = add_group(st, r2, dt);
+        g[2] = add_group(st, r3, dt);
+        g[3] = add_group(st, r4, dt);
+    };
+    {
+        GemmGroup g[4];
+        build_read(st->Cenv, st->Tenv, st->X1, st->X2, st->X2p, st->E, st->Eout, g);
+        st->read1 = g[0], st->read2 = g[1], st->read3 = g[2], st->read4 = g[3];
+        build_read(st->Csnap, st->Tsnap, st->X1r, st->X2r, st->X2pr, st->Er, st->Eout_r, g);
+        st->read1r = g[0], st->read2r = g[1], st->read3r = g[2], st->read4r = g[3];
     }
 
     // upload
@@ -949,6 +975,31 @@ void projector_svd(ipeps_state* st, int slot) {
                       (long)n * chi, st->g_dev);
 }
 
+void readout_enqueue(ipeps_state* st, hipStream_t s, bool snap);
+
+// pinned host slots of the asynchronous readout (host_buf holds 65536)
+constexpr int kAsyncHost = 1024;
+
+// Enqueue a deferred asynchronous readout on ro_stream, after the snapshot
+// and, if given, after event `after` of the main stream.
+void launch_deferred_readout(ipeps_state* st, hipEvent_t after) {
+    if (!st->ro_deferred) return;
+    hipStream_t rs = st->ro_stream;
+    HIP_CHECK(hipStreamWaitEvent(rs, st->ev_ro_snap, 0));
+    if (after) HIP_CHECK(hipStreamWaitEvent(rs, after, 0));
+    readout_enqueue(st, rs, true);
+    double* h = st->host_buf + kAsyncHost;
+    HIP_CHECK(hipMemcpyAsync(h, st->obs_r, 16 * sizeof(double), hipMemcpyDeviceToHost, rs));
+    HIP_CHECK(hipMemcpyAsync(h + 16, st->eps_r, 4 * sizeof(double), hipMemcpyDeviceToHost, rs));
+    // Delta of the snapshot's environment (its CTMRG recorded ev_spec_done last:
+    // a later CTMRG records it only after its spectra, which wait for
+    // ev_ro_done before they overwrite Delta)
+    HIP_CHECK(hipStreamWaitEvent(rs, st->ev_spec_done, 0));
+    HIP_CHECK(hipMemcpyAsync(h + 20, st->dev_scalars, sizeof(double), hipMemcpyDeviceToHost, rs));
+    HIP_CHECK(hipEventRecord(st->ev_ro_done, rs));
+    st->ro_deferred = false;
+}
+
 void column_step(ipeps_state* st, int si) {
     const ColumnStep& cs = st->steps[si];
     const int q = st->q, chi = st->chi, n = st->n;
@@ -967,6 +1018,9 @@ void column_step(ipeps_state* st, int si) {
         run_on(st, st->aux_stream, nx.aux_s2);
         run_on(st, st->aux_stream, nx.aux_s3);
         HIP_CHECK(hipEventRecord(st->ev_aux_done, st->aux_stream));
+        // a readout started after the previous CTMRG runs beside this step's
+        // projector SVD
+        if (si == 0) launch_deferred_readout(st, st->ev_aux_go);
     } else {
         HIP_CHECK(hipStreamWaitEvent(s, st->ev_aux_done, 0));
     }
@@ -1010,6 +1064,8 @@ void corner_spectra_update(ipeps_state* st, bool first) {
     // (FP32) of |C|_F need no rotation
     jacobi_svd_real(ss, 16, chi, chi, st->C64, chi, (long)chi * chi, st->csig, nullptr, nullptr,
                     st->jwork_c, st->dtype == IPEPS_DTYPE_FP64 ? 1e-10 : 1e-8);
+    // an asynchronous readout may still have to copy the previous Delta
+    HIP_CHECK(hipStreamWaitEvent(ss, st->ev_ro_done, 0));
     spectra_delta(ss, 16, chi, st->csig, st->spectra, st->spec_prev, st->dev_scalars, first ? 1 : 0);
     HIP_CHECK(hipEventRecord(st->ev_spec_done, ss));
     st->spectra_valid = true;
@@ -1121,6 +1177,10 @@ int ipeps_init(const ipeps_config* cfg, void* hip_stream, ipeps_alloc_fn alloc, 
         HIP_CHECK(hipEventCreateWithFlags(&st->ev_c64_ready, hipEventDisableTiming));
         HIP_CHECK(hipEventCreateWithFlags(&st->ev_spec_done, hipEventDisableTiming));
         HIP_CHECK(hipStreamCreateWithFlags(&st->aux_stream, hipStreamNonBlocking));
+        HIP_CHECK(hipStreamCreateWithFlags(&st->ro_stream, hipStreamNonBlocking));
+        HIP_CHECK(hipEventCreateWithFlags(&st->ev_ro_snap, hipEventDisableTiming));
+        HIP_CHECK(hipEventCreateWithFlags(&st->ev_ro_done, hipEventDisableTiming));
+        HIP_CHECK(hipEventRecord(st->ev_ro_done, st->ro_stream));  // complete: nothing pending
         HIP_CHECK(hipEventCreateWithFlags(&st->ev_aux_go, hipEventDisableTiming));
         HIP_CHECK(hipEventCreateWithFlags(&st->ev_aux_done, hipEventDisableTiming));
         HIP_CHECK(hipHostMalloc((void**)&st->host_buf, 65536 * sizeof(double), hipHostMallocDefault));
@@ -1148,12 +1208,16 @@ void ipeps_destroy(ipeps_state* st) {
     if (st->su_stream) (void)hipStreamSynchronize(st->su_stream);
     if (st->spec_stream) (void)hipStreamSynchronize(st->spec_stream);
     if (st->aux_stream) (void)hipStreamSynchronize(st->aux_stream);
+    if (st->ro_stream) (void)hipStreamSynchronize(st->ro_stream);
     st->mem.release();
     if (st->su_stream) (void)hipStreamDestroy(st->su_stream);
     if (st->spec_stream) (void)hipStreamDestroy(st->spec_stream);
     if (st->aux_stream) (void)hipStreamDestroy(st->aux_stream);
     if (st->ev_aux_go) (void)hipEventDestroy(st->ev_aux_go);
     if (st->ev_aux_done) (void)hipEventDestroy(st->ev_aux_done);
+    if (st->ro_stream) (void)hipStreamDestroy(st->ro_stream);
+    if (st->ev_ro_snap) (void)hipEventDestroy(st->ev_ro_snap);
+    if (st->ev_ro_done) (void)hipEventDestroy(st->ev_ro_done);
     if (st->ev_c64_ready) (void)hipEventDestroy(st->ev_c64_ready);
     if (st->ev_spec_done) (void)hipEventDestroy(st->ev_spec_done);
     if (st->ev_gamma_free) (void)hipEventDestroy(st->ev_gamma_free);
@@ -1281,46 +1345,103 @@ int ctmrg_converge(ipeps_state* st, double tol, int max_iter, int cold_start, in
     return rc;
 }
 
+}  // extern "C"
+
+namespace {
+// The readout of one environment on stream s: the live tensors and scratch,
+// or (snap) the snapshot taken by ipeps_observe_async and its own scratch.
+void readout_enqueue(ipeps_state* st, hipStream_t s, bool snap) {
+    const int q = st->q, chi = st->chi, n = st->n;
+    const long n2 = (long)n * n, q4 = (long)q * q * q * q;
+    const size_t e = st->esz;
+    void* X2p = snap ? st->X2pr : st->X2p;
+    void* E = snap ? st->Er : st->E;
+    run_on(st, s, snap ? st->read1r : st->read1);
+    run_on(st, s, snap ? st->read2r : st->read2);
+    run_on(st, s, snap ? st->read3r : st->read3);
+    for (int site = 0; site < 4; ++site) {
+        // Lp[q^2][t4p][t2p] <- L'[t4p][q^2][t2p];  Rp[t4p][t2p][q^2] <- R'[t2p][q^2][t4p]
+        permute3(s, st->dtype, 0, chi, q * q, chi, off(X2p, site * n2, e), off(E, site * n2, e));
+        permute3(s, st->dtype, 2, chi, q * q, chi, off(X2p, (4 + site) * n2, e), off(E, (4 + site) * n2, e));
+    }
+    run_on(st, s, snap ? st->read4r : st->read4);
+    double* E64 = snap ? st->E64_r : st->E64;
+    to_fp64(s, st->dtype, snap ? st->Eout_r : st->Eout, E64, 4 * q4);
+    readout(s, st->D, st->d, st->cfg.d_A, E64, snap ? st->Asnap : st->A, snap ? st->rho_T_r : st->rho_T,
+            snap ? st->rho_r : st->rho, snap ? st->obs_r : st->obs_dev);
+}
+
+// h: 16 readout values, 4 truncation errors, Delta (host layout of both paths)
+void decode_obs(const double* h, double t, int iters, ipeps_obs* out) {
+    for (int i = 0; i < 16; ++i) IPEPS_REQUIRE(std::isfinite(h[i]), IPEPS_ENUMERIC, "NaN in readout");
+    out->t = t;
+    for (int i = 0; i < 4; ++i) out->n[i] = h[i];
+    out->imbalance = h[4];
+    out->sum_n = h[5];
+    out->max_offdiag = h[6];
+    for (int i = 0; i < 4; ++i) out->trunc_err[i] = h[16 + i];
+    out->ctm_iters = iters;
+    out->ctm_delta = h[20];
+    for (int i = 0; i < 4; ++i) {
+        out->renyi1[i] = h[8 + i];
+        out->renyi_half[i] = h[12 + i];
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
 int ipeps_observe(ipeps_state* st, ipeps_obs* out) {
     if (!st || !out) return IPEPS_EINVAL;
     return wrap(st, [&] {
         check_poison(st);
         IPEPS_REQUIRE(st->have_env, IPEPS_EINVAL, "no environment: call ctmrg_converge first");
-        const int q = st->q, chi = st->chi, n = st->n;
-        const long n2 = (long)n * n, q4 = (long)q * q * q * q;
-        const size_t e = st->esz;
         hipStream_t s = st->stream;
-        run(st, st->read1);
-        run(st, st->read2);
-        run(st, st->read3);
-        for (int site = 0; site < 4; ++site) {
-            // Lp[q^2][t4p][t2p] <- L'[t4p][q^2][t2p];  Rp[t4p][t2p][q^2] <- R'[t2p][q^2][t4p]
-            permute3(s, st->dtype, 0, chi, q * q, chi, off(st->X2p, site * n2, e), off(st->E, site * n2, e));
-            permute3(s, st->dtype, 2, chi, q * q, chi, off(st->X2p, (4 + site) * n2, e),
-                     off(st->E, (4 + site) * n2, e));
-        }
-        run(st, st->read4);
-        to_fp64(s, st->dtype, st->Eout, st->E64, 4 * q4);
-        readout(s, st->D, st->d, st->cfg.d_A, st->E64, st->A, st->rho_T, st->rho, st->obs_dev);
+        readout_enqueue(st, s, false);
         HIP_CHECK(hipMemcpyAsync(st->host_buf, st->obs_dev, 16 * sizeof(double), hipMemcpyDeviceToHost, s));
         HIP_CHECK(hipMemcpyAsync(st->host_buf + 16, st->eps_snap, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
         wait_spectra(st);
         HIP_CHECK(hipMemcpyAsync(st->host_buf + 20, st->dev_scalars, sizeof(double), hipMemcpyDeviceToHost, s));
         HIP_CHECK(hipStreamSynchronize(s));
-        const double* h = st->host_buf;
-        for (int i = 0; i < 16; ++i) IPEPS_REQUIRE(std::isfinite(h[i]), IPEPS_ENUMERIC, "NaN in readout");
-        out->t = st->ctm_step * st->cfg.dt;
-        for (int i = 0; i < 4; ++i) out->n[i] = h[i];
-        out->imbalance = h[4];
-        out->sum_n = h[5];
-        out->max_offdiag = h[6];
-        for (int i = 0; i < 4; ++i) out->trunc_err[i] = h[16 + i];
-        out->ctm_iters = st->last_iters;
-        out->ctm_delta = h[20];
-        for (int i = 0; i < 4; ++i) {
-            out->renyi1[i] = h[8 + i];
-            out->renyi_half[i] = h[12 + i];
-        }
+        decode_obs(st->host_buf, st->ctm_step * st->cfg.dt, st->last_iters, out);
+    });
+}
+
+int ipeps_observe_async(ipeps_state* st) {
+    if (!st) return IPEPS_EINVAL;
+    return wrap(st, [&] {
+        check_poison(st);
+        IPEPS_REQUIRE(st->have_env, IPEPS_EINVAL, "no environment: call ctmrg_converge first");
+        IPEPS_REQUIRE(!st->ro_pending, IPEPS_EINVAL, "an asynchronous readout is pending: call ipeps_observe_result");
+        hipStream_t s = st->stream, rs = st->ro_stream;
+        const int chi = st->chi, q = st->q;
+        const long cc = (long)chi * chi, cqc = (long)chi * q * chi;
+        const long D4 = (long)st->D * st->D * st->D * st->D;
+        // snapshot on the main stream (after the CTMRG that made the environment)
+        HIP_CHECK(hipMemcpyAsync(st->Csnap, st->Cenv, 16 * cc * st->esz, hipMemcpyDeviceToDevice, s));
+        HIP_CHECK(hipMemcpyAsync(st->Tsnap, st->Tenv, 16 * cqc * st->esz, hipMemcpyDeviceToDevice, s));
+        HIP_CHECK(hipMemcpyAsync(st->Asnap, st->A, 4 * st->d * D4 * sizeof(cplx), hipMemcpyDeviceToDevice, s));
+        HIP_CHECK(hipMemcpyAsync(st->eps_r, st->eps_snap, 4 * sizeof(double), hipMemcpyDeviceToDevice, s));
+        HIP_CHECK(hipEventRecord(st->ev_ro_snap, s));
+        // the readout kernels are enqueued by the next CTMRG once its first
+        // enlarged corners are launched (they then fill the idle phases of its
+        // first projector SVD), or by ipeps_observe_result
+        st->ro_deferred = true;
+        st->ro_pending = true;
+        st->ro_t = st->ctm_step * st->cfg.dt;
+        st->ro_iters = st->last_iters;
+    });
+}
+
+int ipeps_observe_result(ipeps_state* st, ipeps_obs* out) {
+    if (!st || !out) return IPEPS_EINVAL;
+    return wrap(st, [&] {
+        IPEPS_REQUIRE(st->ro_pending, IPEPS_EINVAL, "no asynchronous readout pending");
+        launch_deferred_readout(st, nullptr);
+        HIP_CHECK(hipEventSynchronize(st->ev_ro_done));
+        st->ro_pending = false;
+        decode_obs(st->host_buf + kAsyncHost, st->ro_t, st->ro_iters, out);
     });
 }
 

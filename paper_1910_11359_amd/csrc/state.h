@@ -85,6 +85,15 @@ struct ipeps_state {
     // enlarged corners of the second column step of a move, computed ahead
     hipStream_t aux_stream;
     hipEvent_t ev_aux_go, ev_aux_done;
+    // asynchronous readout (ipeps_observe_async): C, T, A and the truncation
+    // errors are copied on the main stream, then read out on ro_stream with
+    // scratch of its own while the main stream goes on
+    hipStream_t ro_stream;
+    hipEvent_t ev_ro_snap, ev_ro_done;
+    bool ro_pending;
+    bool ro_deferred;  // snapshot taken, readout kernels not yet enqueued
+    double ro_t;
+    int ro_iters;
     double* jwork_c;
     double* eps_snap;  // truncation errors as of the last double-layer build
     double* eps_snap_pre;  // the same for the layers built ahead on the SU stream
@@ -117,6 +126,12 @@ struct ipeps_state {
     // environment: C[(site*4 + k)], T[(site*4 + k)] contiguous
     void* Cenv;
     void* Tenv;
+
+    // snapshot and scratch of the asynchronous readout
+    void *Csnap, *Tsnap, *X1r, *X2r, *X2pr, *Er, *Eout_r;
+    ipeps::cplx *Asnap, *rho_T_r, *rho_r;
+    double *eps_r, *E64_r, *obs_r;
+    ipeps::GemmGroup read1r, read2r, read3r, read4r;
 
     // column-step workspace
     void* X1;   // 8 blocks of chi * q * chi

@@ -63,6 +63,7 @@ EXPORTS = [
     "ipeps_corner_spectra", "ipeps_bond_spectra", "ipeps_destroy", "solve_server_create",
     "solve_submit", "solve_poll", "solve_job_times", "solve_server_destroy", "ipeps_strerror",
     "ipeps_profile", "ipeps_profile_read", "ff_neel_dynamics", "ff_bessel_j",
+    "ipeps_observe_async", "ipeps_observe_result",
 ]
 
 _lib = None
@@ -91,6 +92,8 @@ def load():
     lib.ctmrg_converge.argtypes = [C.c_void_p, C.c_double, C.c_int, C.c_int, P(C.c_int),
                                    P(C.c_double)]
     lib.ipeps_observe.argtypes = [C.c_void_p, P(Obs)]
+    lib.ipeps_observe_async.argtypes = [C.c_void_p]
+    lib.ipeps_observe_result.argtypes = [C.c_void_p, P(Obs)]
     lib.ipeps_corner_spectra.argtypes = [C.c_void_p, P(C.c_double)]
     lib.ipeps_bond_spectra.argtypes = [C.c_void_p, P(C.c_double)]
     lib.ipeps_destroy.argtypes = [C.c_void_p]
@@ -208,6 +211,15 @@ class State:
     def observe(self):
         o = Obs()
         _check(self._lib.ipeps_observe(self.h, C.byref(o)), "ipeps_observe")
+        return o.as_dict()
+
+    def observe_async(self):
+        """Start a readout of the current environment (result via observe_result)."""
+        _check(self._lib.ipeps_observe_async(self.h), "ipeps_observe_async")
+
+    def observe_result(self):
+        o = Obs()
+        _check(self._lib.ipeps_observe_result(self.h, C.byref(o)), "ipeps_observe_result")
         return o.as_dict()
 
     def corner_spectra(self):
