@@ -285,6 +285,8 @@ def headline(P, torch, wl, dtype, steps, warmup, prelude, flags=0):
         return prev
 
     def drain():
+        if not pending[0]:
+            return None
         obs = st.observe_result()
         pending[0] = False
         return obs
