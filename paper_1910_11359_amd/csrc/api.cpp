@@ -980,10 +980,34 @@ void readout_enqueue(ipeps_state* st, hipStream_t s, bool snap);
 // pinned host slots of the asynchronous readout (host_buf holds 65536)
 constexpr int kAsyncHost = 1024;
 
+// Enqueue the deferred corner spectra on the spectra stream, after the FP64
+// snapshot of the corners and, if given, after event `after` of the main
+// stream.
+void launch_deferred_spectra(ipeps_state* st, hipEvent_t after) {
+    if (!st->spec_deferred) return;
+    const int chi = st->chi;
+    hipStream_t ss = st->spec_stream;
+    HIP_CHECK(hipStreamWaitEvent(ss, st->ev_c64_ready, 0));
+    if (after) HIP_CHECK(hipStreamWaitEvent(ss, after, 0));
+    // spectra are reported to 1e-8 sigma_1 (FP64 corners) and carry the
+    // ~1e-7 rounding of FP32 corners: columns below 1e-10 (FP64) or 1e-8
+    // (FP32) of |C|_F need no rotation
+    jacobi_svd_real(ss, 16, chi, chi, st->C64, chi, (long)chi * chi, st->csig, nullptr, nullptr,
+                    st->jwork_c, st->dtype == IPEPS_DTYPE_FP64 ? 1e-10 : 1e-8);
+    // an asynchronous readout may still have to copy the previous Delta
+    HIP_CHECK(hipStreamWaitEvent(ss, st->ev_ro_done, 0));
+    spectra_delta(ss, 16, chi, st->csig, st->spectra, st->spec_prev, st->dev_scalars,
+                  st->spec_first ? 1 : 0);
+    HIP_CHECK(hipEventRecord(st->ev_spec_done, ss));
+    st->spec_deferred = false;
+}
+
 // Enqueue a deferred asynchronous readout on ro_stream, after the snapshot
-// and, if given, after event `after` of the main stream.
+// and, if given, after event `after` of the main stream (the spectra of its
+// environment first: the readout reports their Delta).
 void launch_deferred_readout(ipeps_state* st, hipEvent_t after) {
     if (!st->ro_deferred) return;
+    launch_deferred_spectra(st, after);
     hipStream_t rs = st->ro_stream;
     HIP_CHECK(hipStreamWaitEvent(rs, st->ev_ro_snap, 0));
     if (after) HIP_CHECK(hipStreamWaitEvent(rs, after, 0));
@@ -1018,9 +1042,12 @@ void column_step(ipeps_state* st, int si) {
         run_on(st, st->aux_stream, nx.aux_s2);
         run_on(st, st->aux_stream, nx.aux_s3);
         HIP_CHECK(hipEventRecord(st->ev_aux_done, st->aux_stream));
-        // a readout started after the previous CTMRG runs beside this step's
-        // projector SVD
-        if (si == 0) launch_deferred_readout(st, st->ev_aux_go);
+        // the spectra of the previous environment and a readout started
+        // after the previous CTMRG run beside this step's projector SVD
+        if (si == 0) {
+            launch_deferred_spectra(st, st->ev_aux_go);
+            launch_deferred_readout(st, st->ev_aux_go);
+        }
     } else {
         HIP_CHECK(hipStreamWaitEvent(s, st->ev_aux_done, 0));
     }
@@ -1048,30 +1075,27 @@ void column_step(ipeps_state* st, int si) {
     normalize_tensors(s, st->dtype, st->d_norms + cs.norm_first, 6, st->norm_ws);
 }
 
-// Snapshot the 16 corners (FP64) on the main stream, then take their spectra
-// and the change Delta on the spectra stream, overlapping the next iteration.
-// Readers of spectra / Delta wait for ev_spec_done (wait_spectra).
+// Snapshot the 16 corners (FP64) on the main stream; their spectra and the
+// change Delta follow on the spectra stream, deferred like an asynchronous
+// readout: the next CTMRG enqueues them after its first enlarged corners (so
+// they do not share the GPU with that launch), or any reader of spectra /
+// Delta does (wait_spectra).
 void corner_spectra_update(ipeps_state* st, bool first) {
     const int chi = st->chi;
     hipStream_t s = st->stream;
+    launch_deferred_spectra(st, nullptr);  // an earlier update nobody launched yet
     HIP_CHECK(hipStreamWaitEvent(s, st->ev_spec_done, 0));  // C64 free again
     to_fp64(s, st->dtype, st->Cenv, st->C64, 16L * chi * chi);
     HIP_CHECK(hipEventRecord(st->ev_c64_ready, s));
-    hipStream_t ss = st->spec_stream;
-    HIP_CHECK(hipStreamWaitEvent(ss, st->ev_c64_ready, 0));
-    // spectra are reported to 1e-8 sigma_1 (FP64 corners) and carry the
-    // ~1e-7 rounding of FP32 corners: columns below 1e-10 (FP64) or 1e-8
-    // (FP32) of |C|_F need no rotation
-    jacobi_svd_real(ss, 16, chi, chi, st->C64, chi, (long)chi * chi, st->csig, nullptr, nullptr,
-                    st->jwork_c, st->dtype == IPEPS_DTYPE_FP64 ? 1e-10 : 1e-8);
-    // an asynchronous readout may still have to copy the previous Delta
-    HIP_CHECK(hipStreamWaitEvent(ss, st->ev_ro_done, 0));
-    spectra_delta(ss, 16, chi, st->csig, st->spectra, st->spec_prev, st->dev_scalars, first ? 1 : 0);
-    HIP_CHECK(hipEventRecord(st->ev_spec_done, ss));
+    st->spec_deferred = true;
+    st->spec_first = first;
     st->spectra_valid = true;
 }
 
-void wait_spectra(ipeps_state* st) { HIP_CHECK(hipStreamWaitEvent(st->stream, st->ev_spec_done, 0)); }
+void wait_spectra(ipeps_state* st) {
+    launch_deferred_spectra(st, nullptr);
+    HIP_CHECK(hipStreamWaitEvent(st->stream, st->ev_spec_done, 0));
+}
 
 void check_poison(ipeps_state* st) {
     IPEPS_REQUIRE(!st->poisoned, IPEPS_ENUMERIC, "state poisoned by an earlier NaN/Inf");

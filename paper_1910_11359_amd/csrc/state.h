@@ -92,6 +92,7 @@ struct ipeps_state {
     hipEvent_t ev_ro_snap, ev_ro_done;
     bool ro_pending;
     bool ro_deferred;  // snapshot taken, readout kernels not yet enqueued
+    bool spec_deferred, spec_first;  // corner spectra waiting to be enqueued
     double ro_t;
     int ro_iters;
     double* jwork_c;
