@@ -22,11 +22,20 @@ n_i(t) = sum over filled j of |U_ij(t)|^2.  This module forms h densely,
 diagonalises it (numpy.linalg.eigh) and builds U(t) = V diag(exp(-i E t)) V^T
 exactly for every requested time: no time stepping.
 
+The single-particle spectrum and the inverse participation ratios (the
+IPR equation and the rescaled energy epsilon(E) of the same section):
+spectrum_ipr diagonalises h (numpy.linalg.eigh) and returns the energies in
+ascending order with I_k = sum_i |<i|E_k>|^4; cumulative_ipr rescales each
+realization's spectrum to [0, 1] with its own E_min, E_max and sums the IPR
+of the states in bins of width 0.05 (epsilon = 1 counted in the last bin).
+
 Parity status: pinned (tests/test_oracle_freefermion.py) by the clean-torus
 closed form J_0(4 tau t)^2 for the imbalance, the 2 x 2 plaquette closed
 form cos^2(2 tau t), the analytic single-particle spectra of the clean open
 and periodic lattices, particle-number conservation, invariance under a
-uniform field shift, and frozen occupations without hopping.
+uniform field shift, and frozen occupations without hopping; the IPR by
+its exact value 1 without hopping, the clean plaquette's non-degenerate
+states (1/4), and the second-order perturbative IPR at weak hopping.
 """
 import numpy as np
 
@@ -76,3 +85,35 @@ def neel_dynamics(L, pbc, tau, eps, times):
     ev = sublattice(L)
     odd = n[:, ~ev].mean(axis=1) if (~ev).any() else np.zeros(len(times))  # L = 1: no odd site
     return n[:, ev].mean(axis=1), odd
+
+
+def spectrum_ipr(L, pbc, tau, eps):
+    """Energies E_k (ascending) of h and the IPR I_k = sum_i |<i|E_k>|^4 of
+    each eigenvector, both of shape (L^2,)."""
+    E, V = np.linalg.eigh(hamiltonian(L, pbc, tau, eps))
+    return E, np.sum(V ** 4, axis=0)
+
+
+N_IPR_BINS = 20  # rescaled-energy intervals of width 0.05
+
+
+def ipr_bin(E):
+    """Bin index of every energy after the rescaling epsilon = (E - E_min) /
+    (E_max - E_min) of one realization (all 0 when the spectrum is flat)."""
+    E = np.asarray(E, dtype=np.float64)
+    lo, hi = E.min(), E.max()
+    if not hi > lo:
+        return np.zeros(E.shape, dtype=int)
+    b = np.floor((E - lo) / (hi - lo) / 0.05).astype(int)
+    return np.minimum(b, N_IPR_BINS - 1)
+
+
+def cumulative_ipr(E, ipr):
+    """Summed IPR and number of states per rescaled-energy bin of one
+    realization: arrays of shape (20,)."""
+    b = ipr_bin(E)
+    sums = np.zeros(N_IPR_BINS)
+    counts = np.zeros(N_IPR_BINS, dtype=int)
+    np.add.at(sums, b, ipr)
+    np.add.at(counts, b, 1)
+    return sums, counts
