@@ -1,4 +1,4 @@
-/* Free-fermion Néel dynamics on one gfx950 GPU: the non-interacting
+/* Free-fermion Néel dynamics and single-particle spectra on one gfx950 GPU: the non-interacting
  * comparison workload of arXiv:1910.11359 (section "Set up for
  * non-interacting fermions"; results for the non-interacting case, the
  * free-fermion figure: mean occupation of the two sublattices of a finite
@@ -45,6 +45,36 @@ extern "C" {
  * NaN outputs. */
 int ff_neel_dynamics(int L, int pbc, double tau, double dt, int n_times, int n_real,
                      const double* eps, double* n_even, double* n_odd, void* hip_stream);
+
+/* Single-particle spectrum and inverse participation ratios (the spectrum
+ * and cumulative-IPR figures of the non-interacting section: the IPR
+ * equation I_k = sum_i |<i|E_k>|^4 and the rescaled energy
+ * epsilon(E) = (E - E_min) / (E_max - E_min)) of n_real realizations of h
+ * (model as above), on hip_stream; returns after enqueueing.
+ *   L          1..16 (the L^2 x L^2 eigenproblem is solved in one workgroup
+ *              per realization: a one-sided Jacobi SVD of h + c I, with c
+ *              twice a Gershgorin bound, whose singular vectors are the
+ *              eigenvectors of h)
+ *   pbc, tau   as above
+ *   eps        DEVICE, FP64, n_real * L*L fields, realization-major
+ *   energies   DEVICE, FP64, n_real * L*L: the energies of each realization
+ *              in ascending order
+ *   ipr        DEVICE, FP64, n_real * L*L: IPR of the eigenvector of the same
+ *              energy (1 on one site, 1/L^2 spread evenly)
+ *   bin_ipr    DEVICE, FP64, n_real * 20: per realization the summed IPR of
+ *              the states with epsilon in [0.05 b, 0.05 (b + 1)), b = 0..19
+ *              (epsilon = 1 in b = 19; all states in b = 0 for a flat
+ *              spectrum)
+ *   bin_count  DEVICE, int32, n_real * 20: the number of those states (0:
+ *              the interval is not populated)
+ * Eigenvectors of degenerate energies are any orthonormal basis of their
+ * space (their IPRs are not unique).  The caller owns all buffers; the
+ * library allocates a stream-ordered workspace of about
+ * 16 * n_real * L^4 bytes for the call.  Returns IPEPS_OK, IPEPS_EINVAL
+ * (argument out of range, a NULL buffer with work to do, n_real > 65535),
+ * IPEPS_ENOMEM, IPEPS_EDEVICE.  NaN fields give NaN outputs. */
+int ff_spectrum_ipr(int L, int pbc, double tau, int n_real, const double* eps, double* energies,
+                    double* ipr, double* bin_ipr, int* bin_count, void* hip_stream);
 
 /* Host copy of the Bessel-function routine behind the propagator's
  * coefficients: J_0(x) .. J_kmax(x) into out[0..kmax] (host), x >= 0,

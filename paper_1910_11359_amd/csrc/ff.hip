@@ -20,6 +20,7 @@
 #include <cmath>
 
 #include "common.h"
+#include "linalg.h"
 
 namespace ipeps {
 namespace {
@@ -323,6 +324,92 @@ hipError_t launch_ff(hipStream_t s, int L, int pbc, double tau, double dt, int n
 }
 
 }  // namespace
+// ------------------------------------------------------------ spectrum, IPR
+// h + c I per realization (row-major n x n, n = L^2) with c = 2 G, G =
+// max_i |eps_i| + 4 |tau| (a Gershgorin bound on |E|; c = 1 when G = 0): its
+// spectrum lies in [G, 3G], so its singular vectors are eigenvectors of h
+// and sigma - c are the energies.
+__global__ __launch_bounds__(256) void k_ff_shifted_h(int L, int pbc, double tau, const double* eps,
+                                                     double* H, double* shift) {
+    __shared__ double red[4];
+    const int b = blockIdx.x, n = L * L;
+    const double* e = eps + (long)b * n;
+    double g = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) g = fmax(g, fabs(e[i]));
+    g = block_max(g, red) + 4.0 * fabs(tau);
+    const double c = g > 0.0 ? 2.0 * g : 1.0;
+    if (threadIdx.x == 0) shift[b] = c;
+    double* Hb = H + (long)b * n * n;
+    for (long idx = threadIdx.x; idx < (long)n * n; idx += blockDim.x) {
+        const int i = (int)(idx / n), j = (int)(idx % n);
+        double v = 0.0;
+        if (i == j) {
+            v = e[i] + c;
+        } else {
+            int dx = j / L - i / L, dy = j % L - i % L;
+            bool adj;
+            if (pbc) {  // L >= 3: +-1 modulo L are distinct neighbours
+                dx = (dx + L) % L;
+                dy = (dy + L) % L;
+                adj = ((dx == 1 || dx == L - 1) && dy == 0) || (dx == 0 && (dy == 1 || dy == L - 1));
+            } else {
+                adj = (abs(dx) == 1 && dy == 0) || (dx == 0 && abs(dy) == 1);
+            }
+            if (adj) v = -tau;
+        }
+        Hb[idx] = v;
+    }
+}
+
+// Energies ascending, IPR of every eigenvector (sum_i u_i^4), and per
+// rescaled-energy bin (width 0.05, epsilon = 1 in the last one) the summed
+// IPR and the number of states, one realization per workgroup; the bin sums
+// run over the states in ascending order (deterministic).
+constexpr int kIprBins = 20;
+__global__ __launch_bounds__(256) void k_ff_ipr(int n, const double* sig, const double* U,
+                                               const double* shift, double* E, double* ipr,
+                                               double* bin_ipr, int* bin_cnt) {
+    __shared__ double Es[256], Is[256];
+    __shared__ int Bs[256];
+    const int b = blockIdx.x;
+    const double c = shift[b];
+    const double* sb = sig + (long)b * n;
+    const double* Ub = U + (long)b * n * n;
+    for (int k = threadIdx.x; k < n; k += blockDim.x) {  // k: descending singular value
+        double s4 = 0.0;
+        for (int i = 0; i < n; ++i) {
+            const double u = Ub[(long)i * n + k];
+            s4 += (u * u) * (u * u);
+        }
+        Es[n - 1 - k] = sb[k] - c;
+        Is[n - 1 - k] = s4;
+    }
+    __syncthreads();
+    const double lo = Es[0], hi = Es[n - 1];
+    for (int a = threadIdx.x; a < n; a += blockDim.x) {
+        int bin = 0;
+        if (hi > lo) {
+            bin = (int)floor((Es[a] - lo) / (hi - lo) / 0.05);
+            bin = bin < kIprBins - 1 ? bin : kIprBins - 1;
+        }
+        Bs[a] = bin;
+        E[(long)b * n + a] = Es[a];
+        ipr[(long)b * n + a] = Is[a];
+    }
+    __syncthreads();
+    if (threadIdx.x < kIprBins) {
+        double sum = 0.0;
+        int cnt = 0;
+        for (int a = 0; a < n; ++a)
+            if (Bs[a] == (int)threadIdx.x) {
+                sum += Is[a];
+                ++cnt;
+            }
+        bin_ipr[(long)b * kIprBins + threadIdx.x] = sum;
+        bin_cnt[(long)b * kIprBins + threadIdx.x] = cnt;
+    }
+}
+
 }  // namespace ipeps
 
 extern "C" {
@@ -366,6 +453,50 @@ int ff_neel_dynamics(int L, int pbc, double tau, double dt, int n_times, int n_r
     const hipError_t f = hipFreeAsync(ws, s);
     if (e != hipSuccess || f != hipSuccess) {
         fprintf(stderr, "ff_neel_dynamics: %s\n", hipGetErrorString(e != hipSuccess ? e : f));
+        return IPEPS_EDEVICE;
+    }
+    return IPEPS_OK;
+}
+
+int ff_spectrum_ipr(int L, int pbc, double tau, int n_real, const double* eps, double* energies,
+                    double* ipr, double* bin_ipr, int* bin_count, void* hip_stream) {
+    using namespace ipeps;
+    if (L < 1 || L > 16 || (pbc != 0 && pbc != 1) || (pbc && L < 3)) return IPEPS_EINVAL;
+    if (!std::isfinite(tau) || n_real < 0 || n_real > 65535) return IPEPS_EINVAL;
+    if (n_real == 0) return IPEPS_OK;
+    if (!eps || !energies || !ipr || !bin_ipr || !bin_count) return IPEPS_EINVAL;
+    hipStream_t s = (hipStream_t)hip_stream;
+    const int n = L * L;
+    const long nn = (long)n_real * n * n;
+    const size_t jw = jacobi_svd_real_work(n_real, n, n);
+    const size_t doubles = 2 * (size_t)nn + (size_t)n_real * n + (size_t)n_real + (jw > 0 ? jw : 1);
+    double* ws = nullptr;
+    if (hipMallocAsync((void**)&ws, doubles * sizeof(double), s) != hipSuccess) {
+        (void)hipGetLastError();
+        return IPEPS_ENOMEM;
+    }
+    double* H = ws;
+    double* Uv = H + nn;
+    double* sig = Uv + nn;
+    double* shift = sig + (long)n_real * n;
+    double* work = shift + n_real;
+    hipError_t e = hipSuccess;
+    try {
+        hipLaunchKernelGGL(k_ff_shifted_h, dim3(n_real), dim3(256), 0, s, L, pbc, tau, eps, H, shift);
+        e = hipGetLastError();
+        if (e == hipSuccess) {
+            // left singular vectors only (normalised columns): eigenvectors
+            jacobi_svd_real(s, n_real, n, n, H, n, (long)n * n, sig, Uv, nullptr, work, 0.0);
+            hipLaunchKernelGGL(k_ff_ipr, dim3(n_real), dim3(256), 0, s, n, sig, Uv, shift, energies, ipr,
+                               bin_ipr, bin_count);
+            e = hipGetLastError();
+        }
+    } catch (...) {
+        e = hipErrorUnknown;
+    }
+    const hipError_t f = hipFreeAsync(ws, s);
+    if (e != hipSuccess || f != hipSuccess) {
+        fprintf(stderr, "ff_spectrum_ipr: %s\n", hipGetErrorString(e != hipSuccess ? e : f));
         return IPEPS_EDEVICE;
     }
     return IPEPS_OK;

@@ -63,7 +63,7 @@ EXPORTS = [
     "ipeps_corner_spectra", "ipeps_bond_spectra", "ipeps_destroy", "solve_server_create",
     "solve_submit", "solve_poll", "solve_job_times", "solve_server_destroy", "ipeps_strerror",
     "ipeps_profile", "ipeps_profile_read", "ff_neel_dynamics", "ff_bessel_j",
-    "ipeps_observe_async", "ipeps_observe_result",
+    "ipeps_observe_async", "ipeps_observe_result", "ff_spectrum_ipr",
 ]
 
 _lib = None
@@ -110,6 +110,8 @@ def load():
     lib.ff_neel_dynamics.argtypes = [C.c_int, C.c_int, C.c_double, C.c_double, C.c_int, C.c_int,
                                      C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
     lib.ff_bessel_j.argtypes = [C.c_double, C.c_int, P(C.c_double)]
+    lib.ff_spectrum_ipr.argtypes = [C.c_int, C.c_int, C.c_double, C.c_int, C.c_void_p, C.c_void_p,
+                                    C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
     lib.ipeps_strerror.argtypes = [C.c_int]
     lib.ipeps_strerror.restype = C.c_char_p
     _lib = lib
@@ -345,6 +347,13 @@ class _DeviceArray:
             raise IpepsError(IPEPS_EDEVICE, "hipMemcpy")
         return out
 
+    def get_int32(self):
+        """The buffer's first 4 n bytes as int32 (the buffer holds 8 n)."""
+        out = np.empty(self.n, dtype=np.int32)
+        if self.n and _hip_runtime().hipMemcpy(out.ctypes.data, self.p, 4 * self.n, self.D2H) != 0:
+            raise IpepsError(IPEPS_EDEVICE, "hipMemcpy")
+        return out
+
     def __del__(self):
         if getattr(self, "p", None) and self.p.value:
             _hip_runtime().hipFree(self.p)
@@ -363,3 +372,28 @@ def ff_neel_dynamics(L, eps, n_times, dt, tau=0.5, pbc=False):
     if _hip_runtime().hipDeviceSynchronize() != 0:
         raise IpepsError(IPEPS_EDEVICE, "hipDeviceSynchronize")
     return ne.get().reshape(n_real, n_times), no.get().reshape(n_real, n_times)
+
+
+def ff_spectrum_ipr_device(L, eps_ptr, n_real, e_ptr, ipr_ptr, bin_ptr, cnt_ptr, tau=0.5, pbc=False,
+                           stream=None):
+    """Enqueue on device buffers (raw pointers); see include/ff.h."""
+    sptr = getattr(stream, "cuda_stream", stream) if stream is not None else None
+    _check(load().ff_spectrum_ipr(int(L), int(bool(pbc)), float(tau), int(n_real), C.c_void_p(eps_ptr),
+                                  C.c_void_p(e_ptr), C.c_void_p(ipr_ptr), C.c_void_p(bin_ptr),
+                                  C.c_void_p(cnt_ptr), C.c_void_p(sptr)), "ff_spectrum_ipr")
+
+
+def ff_spectrum_ipr(L, eps, tau=0.5, pbc=False):
+    """Host convenience: eps (n_real, L*L) -> energies, ipr (n_real, L*L) and the
+    per-bin IPR sums (n_real, 20) and state counts (n_real, 20, int32)."""
+    eps = np.ascontiguousarray(eps, dtype=np.float64).reshape(-1, L * L)
+    n_real, n = eps.shape
+    d_eps, E, I = _DeviceArray(eps.size), _DeviceArray(n_real * n), _DeviceArray(n_real * n)
+    B, K = _DeviceArray(n_real * 20), _DeviceArray(n_real * 20)
+    d_eps.put(eps)
+    ff_spectrum_ipr_device(L, d_eps.p.value, n_real, E.p.value, I.p.value, B.p.value, K.p.value, tau, pbc,
+                           None)
+    if _hip_runtime().hipDeviceSynchronize() != 0:
+        raise IpepsError(IPEPS_EDEVICE, "hipDeviceSynchronize")
+    return (E.get().reshape(n_real, n), I.get().reshape(n_real, n), B.get().reshape(n_real, 20),
+            K.get_int32().reshape(n_real, 20))

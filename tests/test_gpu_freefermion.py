@@ -77,3 +77,67 @@ def test_invalid_arguments_raise():
     assert e.value.code == -1
     with pytest.raises(P.IpepsError):
         P.ff_neel_dynamics(4, np.zeros((1, 16)), 3, -0.1)
+
+
+# ------------------------------------------------------------ spectrum, IPR
+def _check_spectrum(L, pbc, eps, tau=0.5):
+    """Device energies, IPRs and bins against the oracle for every realization.
+    Energies to 1e-10 of the Gershgorin scale G (Jacobi SVD of h + 2G I).
+    IPRs where the level spacing d exceeds 1e-6 G (degenerate levels have no
+    unique eigenvectors), to 1e-10 + 4 (4 m eps)(3G)/d: the Jacobi stops when
+    every pair of columns (norms up to 3G) is orthogonal to 4 m eps relative,
+    which leaves two levels d apart mixed by up to that over d, and the IPR
+    moves by at most 4 times the mixing.  The bins exactly as the oracle bins
+    the device's own energies."""
+    E, I, B, K = P.ff_spectrum_ipr(L, eps, tau, pbc)
+    n = L * L
+    for r in range(eps.shape[0]):
+        G = np.max(np.abs(eps[r])) + 4 * abs(tau)
+        Eo, Io = off.spectrum_ipr(L, pbc, tau, eps[r])
+        assert np.all(np.diff(E[r]) >= 0)
+        np.testing.assert_allclose(E[r], Eo, atol=1e-10 * max(G, 1.0), rtol=0)
+        gap = np.full(n, np.inf)
+        if n > 1:
+            d = np.diff(Eo)
+            gap[:-1] = np.minimum(gap[:-1], d)
+            gap[1:] = np.minimum(gap[1:], d)
+        ok = gap > 1e-6 * max(G, 1.0)
+        tol = 1e-10 + 4 * (4 * n * 1.11e-16) * 3 * max(G, 1.0) / gap[ok]
+        assert np.all(np.abs(I[r][ok] - Io[ok]) <= tol), np.max(np.abs(I[r][ok] - Io[ok]) / tol)
+        assert np.all(I[r] <= 1 + 1e-12) and np.all(I[r] >= 1.0 / n - 1e-12)
+        sums, counts = off.cumulative_ipr(E[r], I[r])
+        np.testing.assert_array_equal(K[r], counts)
+        np.testing.assert_allclose(B[r], sums, atol=1e-13, rtol=0)
+        assert K[r].sum() == n
+
+
+@pytest.mark.parametrize("L,pbc,kind,h,n_real,seed", [
+    (1, False, "continuous", 3.0, 2, 11),
+    (2, False, "continuous", 1.0, 2, 12),
+    (3, True, "continuous", 4.0, 3, 13),
+    (5, False, "discrete3", 10.0, 3, 14),
+    (8, True, "continuous", 4.0, 2, 15),
+    (10, False, "discrete3", 100.0, 3, 16),
+    (10, False, "continuous", 100.0, 3, 17),
+    (12, False, "discrete2", 10.0, 2, 18),
+])
+def test_spectrum_ipr_vs_oracle(L, pbc, kind, h, n_real, seed):
+    _check_spectrum(L, pbc, synthetic.ff_fields(L, n_real, h, kind, seed))
+
+
+def test_spectrum_ipr_limits():
+    """No hopping: the energies are the sorted fields and every IPR is 1; the
+    clean plaquette's outer states have IPR 1/4 (one per site each)."""
+    eps = synthetic.ff_fields(6, 2, 5.0, "continuous", 21)
+    E, I, B, K = P.ff_spectrum_ipr(6, eps, 0.0)
+    np.testing.assert_allclose(E, np.sort(eps, axis=1), atol=1e-13, rtol=0)
+    np.testing.assert_allclose(I, 1.0, atol=1e-13)
+    E, I, B, K = P.ff_spectrum_ipr(2, np.zeros((1, 4)), 0.7)
+    np.testing.assert_allclose(E[0], [-1.4, 0.0, 0.0, 1.4], atol=1e-13)
+    np.testing.assert_allclose(I[0, [0, 3]], 0.25, atol=1e-13)
+
+
+def test_spectrum_ipr_full_size():
+    """The largest supported lattice, L = 16 (256 x 256), 100 realizations of
+    continuous disorder h = 10, every realization against the oracle."""
+    _check_spectrum(16, False, synthetic.ff_fields(16, 100, 10.0, "continuous", 20191025))
