@@ -136,6 +136,48 @@ FF_FLOP_PER_SITE = 28  # per application of (h - b)/a to a complex orbital: 5-po
                        # (2 x 5 MACs) + Chebyshev recurrence (4) + series accumulation (4)
 
 
+def spectrum_ipr_record(P, torch, synthetic, tau, with_cpu, n_real=100, h=100.0, reps=3):
+    """Single-particle spectra and IPRs (the spectrum figure's h = 100, 100
+    realizations) at L = 10 and at the device's largest lattice L = 16, inputs
+    resident on the device; the oracle (numpy eigh per realization) timed on
+    the host for the same batch."""
+    import numpy as np
+    rec = {}
+    for L in (10, 16):
+        n = L * L
+        eps_h = synthetic.ff_fields(L, n_real, h, "continuous", 20191025)
+        eps = torch.from_numpy(eps_h).cuda()
+        E = torch.empty(n_real * n, dtype=torch.float64, device="cuda")
+        I = torch.empty_like(E)
+        B = torch.empty(n_real * 20, dtype=torch.float64, device="cuda")
+        K = torch.empty(n_real * 20, dtype=torch.int32, device="cuda")
+        stream = torch.cuda.Stream()
+        run = lambda: P.ff_spectrum_ipr_device(L, eps.data_ptr(), n_real, E.data_ptr(), I.data_ptr(),
+                                               B.data_ptr(), K.data_ptr(), tau, False, stream)
+        run()
+        stream.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            run()
+        e1.record(stream)
+        stream.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        r = {"workload": f"spectrum + IPR + cumulative IPR: L={L}, open, continuous h={h:g}, tau={tau}, "
+                         f"{n_real} realizations (one-sided Jacobi SVD of h + 2G I per realization)",
+             "value": n_real / (ms * 1e-3), "unit": "realizations/s", "ms_per_batch": ms,
+             "mean_ipr": float(I.mean().item())}
+        if with_cpu:
+            from oracle import freefermion as off
+            t0 = time.perf_counter()
+            for k in range(n_real):
+                off.spectrum_ipr(L, False, tau, eps_h[k])
+            r["cpu_baseline"] = {"value": n_real / (time.perf_counter() - t0), "unit": "realizations/s",
+                                 "kind": "oracle", "sample": f"the same {n_real} realizations"}
+        rec[f"L{L}"] = r
+    return rec
+
+
 def free_fermion(P, torch, synthetic, reps=3, with_cpu=True):
     """The free-fermion Néel workload (L = 40, 100 realizations, t = 5 in 50
     intervals), inputs resident on the device; roofline against the FP64
@@ -181,6 +223,7 @@ def free_fermion(P, torch, synthetic, reps=3, with_cpu=True):
            "roofline": {"bound": "alu", "achieved": ach, "peak": PEAK_TFLOPS["fp64"], "unit": "TFLOP/s",
                         "frac": ach / PEAK_TFLOPS["fp64"], "traffic": None, "kernel": "k_ff_neel<7>",
                         "flops_per_launch": flops}}
+    out["spectrum_ipr"] = spectrum_ipr_record(P, torch, synthetic, tau, with_cpu)
     if with_cpu:
         from oracle import freefermion as off
         t0 = time.perf_counter()
