@@ -248,12 +248,20 @@ void allocate(ipeps_state* st) {
     st->a_base = (double*)M.get(4 * q4 * sizeof(double));
     st->A_pre = (cplx*)M.get(4 * d * D4 * sizeof(cplx));
     st->a_base_pre = (double*)M.get(4 * q4 * sizeof(double));
+    // the 32 frame copies in one block (copied whole when the next step's
+    // were built ahead), and the block the simple update builds them into
+    st->frames = M.get(32 * q4 * e);
+    st->frames_pre = M.get(32 * q4 * e);
     for (int i = 0; i < 16; ++i) {
-        st->a_lu[i] = M.get(q4 * e);
-        st->a_dl[i] = M.get(q4 * e);
+        st->a_lu[i] = off(st->frames, i * q4, e);
+        st->a_dl[i] = off(st->frames, (16 + i) * q4, e);
+        st->a_lu_pre[i] = off(st->frames_pre, i * q4, e);
+        st->a_dl_pre[i] = off(st->frames_pre, (16 + i) * q4, e);
     }
     st->d_a_lu = (void**)M.get(16 * sizeof(void*));
     st->d_a_dl = (void**)M.get(16 * sizeof(void*));
+    st->d_a_lu_pre = (void**)M.get(16 * sizeof(void*));
+    st->d_a_dl_pre = (void**)M.get(16 * sizeof(void*));
     st->Cenv = M.get(16L * chi * chi * e);
     st->Tenv = M.get(16L * cqc * e);
     st->X1 = M.get(8 * cqc * e);
@@ -748,6 +756,8 @@ void build_plan(ipeps_state* st) {
                         hipMemcpyHostToDevice));
     HIP_CHECK(hipMemcpy(st->d_a_lu, st->a_lu, 16 * sizeof(void*), hipMemcpyHostToDevice));
     HIP_CHECK(hipMemcpy(st->d_a_dl, st->a_dl, 16 * sizeof(void*), hipMemcpyHostToDevice));
+    HIP_CHECK(hipMemcpy(st->d_a_lu_pre, st->a_lu_pre, 16 * sizeof(void*), hipMemcpyHostToDevice));
+    HIP_CHECK(hipMemcpy(st->d_a_dl_pre, st->a_dl_pre, 16 * sizeof(void*), hipMemcpyHostToDevice));
 }
 
 void build_layers(ipeps_state* st) {
@@ -825,13 +835,21 @@ void build_double_layers(ipeps_state* st, hipStream_t s, cplx* A, double* a_base
 void prepare_double_layers(ipeps_state* st) {
     HIP_CHECK(hipStreamWaitEvent(st->stream, st->ev_su_done, 0));
     if (st->pre_valid && st->pre_step == st->step_count) {
-        // built at the tail of the simple update (ordered by ev_su_done)
+        // built at the tail of the simple update (ordered by ev_su_done),
+        // frame copies included: one device copy into the plan's buffers
         std::swap(st->A, st->A_pre);
         std::swap(st->a_base, st->a_base_pre);
         std::swap(st->eps_snap, st->eps_snap_pre);
         std::swap(st->norm_a_first, st->norm_a_pre_first);
         st->pre_valid = false;
+        const long q4 = (long)st->q * st->q * st->q * st->q;
+        HIP_CHECK(hipMemcpyAsync(st->frames, st->frames_pre, 32 * q4 * st->esz, hipMemcpyDeviceToDevice,
+                                 st->stream));
+        // the next simple update may rebuild the *_pre buffers (frames_pre
+        // included) once this point is passed
         HIP_CHECK(hipEventRecord(st->ev_gamma_free, st->stream));
+        st->ctm_step = st->step_count;
+        return;
     } else {
         absorb_sqrt_lambda(st->stream, st->D, st->d, st->gam, st->lam, st->A);
         HIP_CHECK(hipMemcpyAsync(st->eps_snap, st->eps, 4 * sizeof(double), hipMemcpyDeviceToDevice,
@@ -1305,6 +1323,7 @@ int ipeps_trotter_step(ipeps_state* st, int n_steps, double* trunc_err_out) {
             // work that precedes ev_gamma_free
             build_double_layers(st, ss, st->A_pre, st->a_base_pre, st->eps_snap_pre, st->norm_a_pre_first,
                                 st->norm_ws_su);
+            frame_layouts(ss, st->q, st->dtype, st->a_base_pre, st->d_a_lu_pre, st->d_a_dl_pre);
             st->pre_valid = true;
             st->pre_step = st->step_count;
         }

@@ -123,6 +123,14 @@ struct ipeps_state {
     void* a_dl[16];
     void** d_a_lu;
     void** d_a_dl;
+    // the same 32 frame copies as two contiguous blocks: the live one the
+    // plan reads and the one the simple update fills for the next CTMRG
+    void* frames;
+    void* frames_pre;
+    void* a_lu_pre[16];
+    void* a_dl_pre[16];
+    void** d_a_lu_pre;
+    void** d_a_dl_pre;
 
     // environment: C[(site*4 + k)], T[(site*4 + k)] contiguous
     void* Cenv;
