@@ -395,7 +395,7 @@ void build_plan(ipeps_state* st) {
         for (int X = 0; X < 2; ++X) {
             ColumnStep& cs = st->steps[mi * 2 + X];
             cs.slot = mi * 2 + X;
-            std::vector<GemmProb> s1, s2, s3, half, np, pr, pr2, w1, w2, fin, a1, a2, a3;
+            std::vector<GemmProb> s1, s2, s3, half, np, pr, pr2, w1, w2, fin, a1, a2, a3, s1w, s2w, s3w;
             const int si = mi * 2 + X;
             // A move with frame f' rewrites C_f', C_{f'+3} and T_{f'+3}, i.e. the
             // enlarged corners with g = f' and g = f' + 3; those with g = f' + 1
@@ -410,6 +410,11 @@ void build_plan(ipeps_state* st) {
                     const int g = (f + j) % 4;
                     const int blk = Y * 4 + j;
                     const bool reuse = X == 0 && mi > 0 && (g == (fprev + 1) % 4 || g == (fprev + 2) % 4);
+                    // warm variant of the left move's first column step (later
+                    // iterations of one call, double layers unchanged): the
+                    // last move (down) left the types f_down + 1, + 2 valid
+                    const bool warmv = mi == 0 && X == 0;
+                    const bool reuse_w = warmv && (g == (kMoveFrames[3] + 1) % 4 || g == (kMoveFrames[3] + 2) % 4);
                     // UR and DR of the second column: computed ahead (aux stream)
                     const bool ahead = X == 1 && (j == 1 || j == 2);
                     const int ab = Y * 2 + (j - 1);
@@ -420,9 +425,11 @@ void build_plan(ipeps_state* st) {
                     // S1: C (chi x chi) . Tnext (chi x q chi), columns (v, c), where
                     // the C renormalisation reads it (UL); and with the columns
                     // written in (c, v) order (X1p) for the corner itself
-                    if (j == 0)
+                    if (j == 0) {
                         s1.push_back(gemm_nn(Cp(s, g), chi, Tp(s, g), (long)q * chi, x1, (long)q * chi,
                                              chi, q * chi, chi));
+                        if (warmv) s1w.push_back(s1.back());
+                    }
                     if (reuse) continue;
                     GemmProb p1 = gemm_nn(Cp(s, g), chi, Tp(s, g), (long)q * chi, x1p, (long)q * chi,
                                           chi, q * chi, chi);
@@ -430,12 +437,14 @@ void build_plan(ipeps_state* st) {
                     p1.c_cs1 = 1;
                     p1.c_cs0 = q;
                     (ahead ? a1 : s1).push_back(p1);
+                    if (warmv && !reuse_w) s1w.push_back(p1);
                     // S2: Tprev (chi q x chi) . X1p (chi x chi q): row (t, u), column
                     // (c, v), written as X2p[t][c][u][v] (the chi^2 x q^2 layout S3 reads)
                     (ahead ? a2 : s2)
                         .push_back(permuted_rows_cols(gemm_nn(Tp(s, (g + 3) % 4), chi, x1p, (long)q * chi,
                                                               x2p, 0, chi * q, q * chi, chi),
                                                       chi, q));
+                    if (warmv && !reuse_w) s2w.push_back((ahead ? a2 : s2).back());
                     // S3: X2p (chi^2 x q^2) . a[L U][D R]; result as the n x n
                     // matrix [prev = (t, D)][next = (c, R)]
                     GemmProb p3 = gemm_nn(x2p, (long)q * q, st->a_lu[s * 4 + g], (long)q * q, E, n,
@@ -447,6 +456,7 @@ void build_plan(ipeps_state* st) {
                     p3.c_cs1 = n;
                     p3.c_cs0 = 1;
                     (ahead ? a3 : s3).push_back(p3);
+                    if (warmv && !reuse_w) s3w.push_back(p3);
                 }
                 char* E0 = cut_corner(st, si, Y, 0);
                 char* E1 = cut_corner(st, si, Y, 1);
@@ -488,6 +498,7 @@ void build_plan(ipeps_state* st) {
                 // Z = T3(X,Y) (chi q x chi) . C4(X,Y)  -> [t3p][q3][c4n]
                 s1.push_back(gemm_nn(Tp(sxy, (2 + f) % 4), chi, Cp(sxy, (3 + f) % 4), chi,
                                      off(st->Z, Y * cqc, e), chi, chi * q, chi, chi));
+                if (mi == 0 && X == 0) s1w.push_back(s1.back());
                 // W1 = PupP (chi q x chi) . T4p(X,Y) (chi x chi q, columns (c, v)),
                 // written as W1p[t][c][u][v] (the chi^2 x q^2 layout w2 reads)
                 cs.t4[Y] = Tp(sxy, (3 + f) % 4);
@@ -531,6 +542,9 @@ void build_plan(ipeps_state* st) {
             cs.s2 = add_group(st, s2, dt);
             cs.s3 = add_group(st, s3, dt);
             if (mi == 0 && X == 0) cs.s3.tag = 1;  // all 8 corners: the roofline launch
+            cs.s1w = add_group(st, s1w, dt);
+            cs.s2w = add_group(st, s2w, dt);
+            cs.s3w = add_group(st, s3w, dt);
             cs.aux_s1 = add_group(st, a1, dt);
             cs.aux_s2 = add_group(st, a2, dt);
             cs.aux_s3 = add_group(st, a3, dt);
@@ -1047,9 +1061,10 @@ void column_step(ipeps_state* st, int si) {
     const int q = st->q, chi = st->chi, n = st->n;
     const long n2 = (long)n * n;
     hipStream_t s = st->stream;
-    run(st, cs.s1);
-    run(st, cs.s2);
-    run(st, cs.s3);
+    const bool warm = si == 0 && st->corners_warm;
+    run(st, warm ? cs.s1w : cs.s1);
+    run(st, warm ? cs.s2w : cs.s2);
+    run(st, warm ? cs.s3w : cs.s3);
     if (si % 2 == 0) {
         // the next column step's UR / DR corners, on the aux stream once the
         // earlier steps (which wrote the tensors they read) are done
@@ -1364,8 +1379,10 @@ int ctmrg_converge(ipeps_state* st, double tol, int max_iter, int cold_start, in
         // (s_{k+1}/s_chi)^(2q) per iteration) stays below the change being
         // resolved; a fixed iteration count (tol <= 0) keeps the plain schedule.
         st->extra_warm_iters = 0;
+        st->corners_warm = false;
         for (int it = 0; it < max_iter; ++it) {
             for (int si = 0; si < 8; ++si) column_step(st, si);
+            st->corners_warm = true;  // the next left move may reuse the down move's corners
             corner_spectra_update(st, false);
             it_done = it + 1;
             if (tol > 0 || (delta && it + 1 == max_iter)) {
@@ -1379,6 +1396,7 @@ int ctmrg_converge(ipeps_state* st, double tol, int max_iter, int cold_start, in
             }
         }
         st->extra_warm_iters = 0;
+        st->corners_warm = false;
         st->last_iters = it_done;
         st->last_delta = dl;
         if (tol > 0 && !(dl < tol)) throw status_error(IPEPS_ENOTCONV, "CTMRG not converged");

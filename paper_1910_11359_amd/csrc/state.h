@@ -44,6 +44,9 @@ struct ColumnStep {
     // them on the aux stream (into X1p_aux, X2p_aux, their E slots) to fill the idle
     // phases of its projector SVD
     GemmGroup aux_s1, aux_s2, aux_s3;
+    // left move, first column: the variant for later iterations of one call,
+    // which reuses the corners of types 0 and 1 the down move left valid
+    GemmGroup s1w, s2w, s3w;
     // buffers the step touches
     int site_x[2], site_x1[2];  // physical site of frame (X, Y) and (X+1, Y)
     void* t4[2];                 // T4(X, Y), [chi][q][chi], permuted into T4p[Y] before w1
@@ -92,6 +95,7 @@ struct ipeps_state {
     hipEvent_t ev_ro_snap, ev_ro_done;
     bool ro_pending;
     bool ro_deferred;  // snapshot taken, readout kernels not yet enqueued
+    bool corners_warm;  // corner slots valid from the previous iteration of this call
     bool spec_deferred, spec_first;  // corner spectra waiting to be enqueued
     double ro_t;
     int ro_iters;

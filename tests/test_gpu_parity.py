@@ -219,6 +219,33 @@ def test_warm_start_continues():
     assert dl < 1e-6
 
 
+@pytest.mark.parametrize("D,chi,flags,dtype,tol", [(3, 12, 0, "fp64", 1e-11), (4, 32, 0, "fp64", 1e-11),
+                                                     (4, 32, 2, "fp64", 1e-11), (4, 32, 2, "fp32", 1e-4)])
+def test_corner_reuse_across_iterations(D, chi, flags, dtype, tol):
+    """Within one CTMRG call the left move of the second and later
+    iterations reuses the enlarged corners the down move left valid; a
+    sequence of one-iteration calls recomputes them.  The two schedules are
+    otherwise the same (warm projector subspaces persist across calls), so
+    they agree to rounding."""
+    kw = dict(J=1.0, V=1.0, W=4.0, dt=0.05, dtype=dtype, flags=flags)
+    out = []
+    for split in (False, True):
+        st = _gpu_state(D, chi, **kw)
+        st.trotter_step(5)
+        if split:
+            st.ctmrg(0.0, 1, True)
+            for _ in range(4):
+                st.ctmrg(0.0, 1, False)
+        else:
+            st.ctmrg(0.0, 5, True)
+        out.append((st.observe(), st.corner_spectra()))
+        st.close()
+    (a, ca), (b, cb) = out
+    assert np.max(np.abs(a["n"] - b["n"])) < tol
+    assert abs(a["imbalance"] - b["imbalance"]) < tol
+    assert np.max(np.abs(ca - cb)) < 100 * tol
+
+
 def test_nan_state_is_reported_and_poisons():
     gam, lam = synthetic.random_state(9, 2)
     gam[0, 0, 0, 0, 0, 0] = np.nan
