@@ -14,9 +14,10 @@ __device__ inline void circle_pair(int r, int k, int ne, int* p, int* q) {
         *p = r;
         *q = ne - 1;
     } else {
+        // 0 <= r < m and 1 <= k < m: one conditional correction each
         const int m = ne - 1;
-        *p = (r + k) % m;
-        *q = (r - k + m) % m;
+        *p = r + k >= m ? r + k - m : r + k;
+        *q = r - k < 0 ? r - k + m : r - k;
     }
     if (*p > *q) {
         int t = *p;
@@ -31,6 +32,12 @@ __device__ inline void circle_pair(int r, int k, int ne, int* p, int* q) {
 // product).  Each pair of a round is handled by a group of 16 lanes (4 groups
 // per wave) holding its two columns in registers (EPL elements per lane);
 // the inner product is summed with DPP moves inside the group.
+// A sweep asks for another only if one of its rotations turned by more than
+// kSweepAngle: rotations of angle <= theta leave inner products of order
+// theta^2 |a_p||a_q|, far below the convergence test, so the sweep after
+// would rotate nothing that matters (it only confirmed convergence).
+constexpr double kSweepAngle = 1e-9;
+
 template <int EPL>
 __device__ void jacobi_sweeps(int m, int n, double* Ac, double* Vc, double* nrm, int* flag,
                               double* red, double skip_rel) {
@@ -112,7 +119,7 @@ __device__ void jacobi_sweeps(int m, int n, double* Ac, double* Vc, double* nrm,
                 if (g16 == 0) {
                     nrm[p] = al - t * ga;
                     nrm[q] = be + t * ga;
-                    *flag = 1;
+                    if (fabs(t) > kSweepAngle) *flag = 1;
                 }
             }
             __syncthreads();
