@@ -44,7 +44,7 @@ ROOF_KERNEL = "k_gemm_direct<...,TAG=1> (8 enlarged-corner products)"
 # tile planning, kernels and launches they were measured on (the part of
 # gemm.hip from tile_dims on, see gemm_kernel_digest) and for ROOF_KERNEL.
 TRAFFIC = {"fp32": {"kernel": ROOF_KERNEL, "gemm_kernel_sha256_16": "3408463f91b88de2",
-                    "bytes_per_launch": 1.400e9}}
+                    "bytes_per_launch": 1.394e9}}
 
 
 def gemm_kernel_digest():
