@@ -62,7 +62,9 @@ def step_flops(D, chi, dtype):
     """Algorithmic real flops of one CTMRG iteration in the real basis, all in
     the contraction precision.  52 enlarged corners per iteration (64 used;
     the first column step of the right, up and down moves reuses 4 that the
-    previous move computed and left valid).  16 cuts per iteration (4 moves x
+    previous move computed and left valid; later iterations of one CTMRG
+    call compute 48, the left move reusing 4 of the down move's, but the
+    headline step runs one iteration per call).  16 cuts per iteration (4 moves x
     2 columns x 2 cuts); the cut matrix N = E2 E3 E0 E1 is applied to blocks of k = chi + p
     columns through its four n x n factors (n = chi D^2), 2 w + 1 times (w
     warm subspace iterations: 1 with FP32 contractions, 2 with FP64; p = 8
