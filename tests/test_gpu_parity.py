@@ -146,14 +146,24 @@ def _dimer_exact(t, J, W):
     return 1 - np.sin(J * t / 2) ** 2 - J ** 2 / w ** 2 * np.sin(w * t / 2) ** 2
 
 
-def test_dimer_limit_closed_form():
-    st = _gpu_state(4, 16, J=1.0, V=1.0, W=5.0, dt=0.5, layer_J=(1, 0, 0, 0),
-                    layer_V=(1, 0, 0, 0), layer_w=(1, 0, 0, 0))
+@pytest.mark.parametrize("layer", [0, 1, 2, 3])
+def test_dimer_limit_closed_form(layer):
+    """Only one layer of bonds carries the Hamiltonian, with the whole field:
+    independent dimers, no Trotter error, exact readout.  Layers H_A, H_B
+    (horizontal dimers with the occupied site left or right) and V_A, V_B
+    (vertical dimers with the occupied site above or below), so both bond
+    directions of the simple update and of the CTMRG are pinned."""
+    one = [0, 0, 0, 0]
+    one[layer] = 1
+    st = _gpu_state(4, 16, J=1.0, V=1.0, W=5.0, dt=0.5, layer_J=one, layer_V=one, layer_w=one)
     for steps in (1, 1, 2):
         st.trotter_step(steps)
         st.ctmrg(0.0, 2, True)
         g = st.observe()
-        assert abs(g["imbalance"] - _dimer_exact(g["t"], 1.0, 5.0)) < 1e-10
+        imb = _dimer_exact(g["t"], 1.0, 5.0)
+        assert abs(g["imbalance"] - imb) < 1e-12, (layer, g["t"])
+        assert np.max(np.abs(g["n"] - 0.5 * (1.0 + imb * np.array([1, -1, -1, 1])))) < 1e-12
+    st.close()
 
 
 @pytest.mark.parametrize("dtype,tol", [("fp64", 1e-9), ("fp32", 1e-4)])

@@ -1,0 +1,114 @@
+"""Device paths that only run at large n, against oracle goldens
+(tests/golden/path_*.json, written by tests/golden/make_path_golden.py,
+which calls only oracle/).
+
+Cases and the device paths they reach (FP64 unless stated):
+  D5_chi25    n = 625: formed cut matrices, subspace block k = 41
+  D6_chi36    n = 1296: cut matrices applied through their enlarged-corner
+              factors (the default above n = 1024), 128 x 128 tiles for the
+              enlarged corners, K split over workgroups
+  D3_chi108   n = 972, k = 144 (> 128): the Cholesky with R in global memory
+              and the wide Jacobi variants
+  D6_chi72    the headline sizes n = 2592: 128 x 128 tiles for the enlarged
+              corners and the T update, split-K 5, k = 96 (FP64) / 80 (FP32)
+  D6_chi72_neel10
+              the headline model from Néel ⊗ |+>, 10 Trotter steps, 10 cold
+              CTMRG iterations (the throughput schedule's observation)
+
+Random-state cases: CTMRG from a cold start to a corner-spectrum change
+< 1e-10 (capped as in the golden), readout, one Trotter step, the same again.
+Bars (FP64): imbalance and occupations 1e-6 absolute, Rényi entropies 1e-6,
+bond spectra and truncation errors 1e-10, corner spectra of converged
+environments (both sides below 1e-10) entry by entry to 1e-8 sigma_1.  FP32
+contractions (projector SVDs, simple update and norms in FP64), the same
+number of CTMRG iterations as the oracle needed: imbalance within 1e-3.  The
+largest deviations are printed (pytest -s).
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import synthetic
+
+P = pytest.importorskip("paper_1910_11359_amd")
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CASES = ["D5_chi25", "D6_chi36", "D3_chi108", "D6_chi72", "D6_chi72_neel10"]
+
+
+def _golden(name):
+    path = os.path.join(HERE, "golden", f"path_{name}.json")
+    if not os.path.exists(path):
+        pytest.skip(f"{path} not written yet")
+    return json.load(open(path))
+
+
+def _state(g, dtype):
+    c, m = g["case"], g["model"]
+    st = P.State(P.make_config(c["D"], c["chi"], J=m["J"], V=m["V"], W=m["W"], dt=m["dt"],
+                               dtype=dtype))
+    if c["kind"] == "random":
+        gam, lam = synthetic.random_state(c["seed"], c["D"])
+        st.set_state(gam, lam)
+    return st
+
+
+def _schedule(g, dtype):
+    """Yields (golden observation, device observation, device delta, state)."""
+    c = g["case"]
+    st = _state(g, dtype)
+    if c["kind"] == "random":
+        for o in g["obs"]:
+            if o["step"]:
+                st.trotter_step(1)
+            if dtype == "fp64":
+                it, dl = st.ctmrg(c["tol"], c["max_iter"], True, allow_notconv=True)
+            else:
+                it, dl = st.ctmrg(0.0, o["ctm_iters"], True)
+            yield o, st.observe(), dl, st
+    else:
+        st.trotter_step(c["n_steps"])
+        it, dl = st.ctmrg(0.0, c["ctm_iters"], True)
+        yield g["obs"][0], st.observe(), dl, st
+    st.close()
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_fp64_path_against_oracle(name):
+    g = _golden(name)
+    tol = g["case"].get("tol", 0.0)
+    for o, got, dl, st in _schedule(g, "fp64"):
+        dI = abs(got["imbalance"] - o["imbalance"])
+        dn = float(np.max(np.abs(got["n"] - np.array(o["n"]))))
+        dr = float(max(np.max(np.abs(got["renyi1"] - np.array(o["renyi1"]))),
+                       np.max(np.abs(got["renyi_half"] - np.array(o["renyi_half"])))))
+        de = float(np.max(np.abs(got["eps"] - np.array(o["eps"]))))
+        db = float(np.max(np.abs(st.bond_spectra() - np.array(o["bond_spectra"]))))
+        msg = (f"{name} step {o['step']}: |dI| {dI:.2e} |dn| {dn:.2e} |dS| {dr:.2e} "
+               f"|d eps| {de:.2e} |d bond| {db:.2e} delta dev {dl:.1e} oracle {o['ctm_delta']:.1e}")
+        conv = tol > 0 and dl < tol and o["ctm_delta"] < tol
+        if conv:
+            ref = np.array(o["corner_spectra"])
+            got_s = st.corner_spectra()
+            rel = np.max(np.abs(got_s - ref) / ref[:, :1])
+            msg += f" corner spectra max |d|/s1 {rel:.2e}"
+        print(msg, flush=True)
+        assert dI < 1e-6 and dn < 1e-6 and dr < 1e-6, msg
+        assert de < 1e-10 and db < 1e-10, msg
+        if tol > 0:
+            assert conv, msg  # random states converge on both sides
+            assert rel < 1e-8, msg
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_fp32_path_against_oracle(name):
+    g = _golden(name)
+    for o, got, dl, st in _schedule(g, "fp32"):
+        dI = abs(got["imbalance"] - o["imbalance"])
+        dn = float(np.max(np.abs(got["n"] - np.array(o["n"]))))
+        print(f"{name} fp32 step {o['step']}: |dI| {dI:.2e} |dn| {dn:.2e}", flush=True)
+        assert dI <= 1e-3 and dn <= 1e-3, (name, o["step"], dI, dn)

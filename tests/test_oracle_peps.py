@@ -37,6 +37,15 @@ def test_trunc_rule_cases():
     assert tr([1.0, 0.3, 0.3 * (1 - 1e-9), 0.1], 2) == 2
     assert tr([0.0, 0.0], 2) == 0
     assert tr([2.0, 2.0, 2.0, 1.0], 2) == 1          # stops at one value
+    # the absolute part of the multiplet gap (1e-12 s_1) decides here: the
+    # pair 1e-3, 1e-3 - 5e-13 is 5e-13 apart, above the relative gap
+    # 1e-10 * 1e-3 = 1e-13 but below 1e-13 + 1e-12 * s_1, so it counts as one
+    # multiplet and the cut moves below it; 2e-12 apart it is two values
+    assert tr([1.0, 1e-3, 1e-3 - 5e-13, 1e-4], 2) == 1
+    assert tr([1.0, 1e-3, 1e-3 - 2e-12, 1e-4], 2) == 2
+    # the absolute part scales with s_1: the same relative pattern scaled by 1e6
+    assert tr([1e6, 1e3, 1e3 - 5e-7, 1e2], 2) == 1
+    assert tr([1e6, 1e3, 1e3 - 2e-6, 1e2], 2) == 2
 
 
 def _imb(obs):
@@ -62,14 +71,27 @@ def _dimer_exact(t, J, W):
     return 1 - np.sin(J * t / 2) ** 2 - J ** 2 / w ** 2 * np.sin(w * t / 2) ** 2
 
 
-@pytest.mark.parametrize("W,steps", [(5.0, [1, 2, 4]), (0.0, [2])])
-def test_dimer_limit(W, steps):
-    p = Params(D=4, chi=16, J=1.0, V=1.0, W=W, dt=0.5,
-               layer_J=(1, 0, 0, 0), layer_V=(1, 0, 0, 0), layer_w=(1, 0, 0, 0))
+def _one_layer(layer):
+    v = [0, 0, 0, 0]
+    v[layer] = 1
+    return tuple(v)
+
+
+# layer 0 = H_A, 1 = H_B, 2 = V_A, 3 = V_B: horizontal dimers whose left site
+# is on sublattice A (occupied) or B (empty), vertical dimers whose upper site
+# is on A or B; V_B is applied once per step with dt, the others twice with dt/2
+@pytest.mark.parametrize("W,steps,layer", [(5.0, [1, 2, 4], 0), (0.0, [2], 0),
+                                           (5.0, [1, 2, 4], 1), (5.0, [1, 2, 4], 2),
+                                           (0.0, [2], 2), (5.0, [1, 2, 4], 3)])
+def test_dimer_limit(W, steps, layer):
+    one = _one_layer(layer)
+    p = Params(D=4, chi=16, J=1.0, V=1.0, W=W, dt=0.5, layer_J=one, layer_V=one, layer_w=one)
     obs, _ = run.run_job(p, max(steps), steps, ctm_iters=2)
     for o in obs:
         imb = _dimer_exact(o["t"], 1.0, W)
         assert abs(o["imbalance"] - imb) < 1e-12
+        # sites (0,0), (1,1) are A, (1,0), (0,1) are B
+        assert np.max(np.abs(o["n"] - 0.5 * (1.0 + imb * np.array([1, -1, -1, 1])))) < 1e-12
         # every site is one end of an isolated dimer: rho_p = diag(n, 1 - n)
         # with n = (1 + I)/2 on A sites, so both entropies are binary-entropy
         # closed forms of the exact imbalance
