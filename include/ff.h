@@ -46,6 +46,23 @@ extern "C" {
 int ff_neel_dynamics(int L, int pbc, double tau, double dt, int n_times, int n_real,
                      const double* eps, double* n_even, double* n_odd, void* hip_stream);
 
+/* ff_neel_dynamics for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same kernels and results, with the per-orbital partial
+ * weights in a fixed scratch array of FF_NOALLOC_SCRATCH_DOUBLES doubles
+ * (64 MiB) that the library holds on every device it runs on until the
+ * process ends.  Allocates nothing (no hipMalloc / hipFree / stream-ordered
+ * allocation).  Needs 2 * n_real * n_times * ceil(L*L/2) <=
+ * FF_NOALLOC_SCRATCH_DOUBLES (the L = 40, 100-realization, 50-time workload
+ * fits), else returns IPEPS_ETOOBIG with a message on stderr.  Every call on
+ * one device shares that device's scratch: calls whose work overlaps on one
+ * device (two streams, or two host threads) race and must be ordered by the
+ * caller.  The scratch needs no clearing (each entry is written before it is
+ * read).  Other arguments, results and errors as for ff_neel_dynamics. */
+#define FF_NOALLOC_SCRATCH_DOUBLES (8L * 1024 * 1024)
+int ff_neel_dynamics_noalloc(int L, int pbc, double tau, double dt, int n_times, int n_real,
+                             const double* eps, double* n_even, double* n_odd, void* hip_stream);
+
 /* Single-particle spectrum and inverse participation ratios (the spectrum
  * and cumulative-IPR figures of the non-interacting section: the IPR
  * equation I_k = sum_i |<i|E_k>|^4 and the rescaled energy

@@ -50,6 +50,7 @@ extern "C" {
 #define IPEPS_ENOTCONV (-5)  /* CTMRG reached max_iter above tol (result still written) */
 #define IPEPS_EAGAIN (-6)    /* job not finished yet */
 #define IPEPS_ENOTFOUND (-7) /* unknown job id */
+#define IPEPS_ETOOBIG (-8)   /* request larger than a no-allocation entry point's fixed scratch */
 
 /* arithmetic of the CTMRG contractions; simple-update SVDs, projector
  * SVDs and environment norms are FP64 in every mode */

@@ -1565,6 +1565,7 @@ const char* ipeps_strerror(int code) {
         case IPEPS_ENOTCONV: return "CTMRG did not converge";
         case IPEPS_EAGAIN: return "not finished";
         case IPEPS_ENOTFOUND: return "unknown job";
+        case IPEPS_ETOOBIG: return "request exceeds the fixed scratch of a no-allocation entry point";
         default: return "unknown error";
     }
 }

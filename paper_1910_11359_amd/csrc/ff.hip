@@ -18,6 +18,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <mutex>
 
 #include "common.h"
 #include "linalg.h"
@@ -420,22 +422,25 @@ int ff_bessel_j(double x, int kmax, double* out) {
     return IPEPS_OK;
 }
 
-int ff_neel_dynamics(int L, int pbc, double tau, double dt, int n_times, int n_real, const double* eps,
-                     double* n_even, double* n_odd, void* hip_stream) {
-    using namespace ipeps;
+}  // extern "C"
+
+namespace ipeps {
+namespace {
+
+int neel_check(int L, int pbc, double tau, double dt, int n_times, int n_real) {
     if (L < 1 || L * L > 2048 || (pbc != 0 && pbc != 1) || (pbc && L < 3)) return IPEPS_EINVAL;
     if (!std::isfinite(tau) || !(dt > 0.0) || !std::isfinite(dt)) return IPEPS_EINVAL;
     if (n_times < 0 || n_real < 0 || n_real > 65535) return IPEPS_EINVAL;
-    if (n_times == 0 || n_real == 0) return IPEPS_OK;
-    if (!eps || !n_even || !n_odd) return IPEPS_EINVAL;
-    hipStream_t s = (hipStream_t)hip_stream;
+    return IPEPS_OK;
+}
+
+// The dynamics kernel and the fixed-order sum into n_even / n_odd, with the
+// per-orbital partial weights in ws (2 * n_real * n_times * ceil(L^2/2)
+// doubles, each written once before it is read: nothing needs clearing).
+hipError_t neel_enqueue(hipStream_t s, int L, int pbc, double tau, double dt, int n_times, int n_real,
+                        const double* eps, double* n_even, double* n_odd, double* ws) {
     const int nsite = L * L, M = (nsite + 1) / 2, Mo = nsite - M;
     const long nq = (long)n_real * n_times;
-    double* ws = nullptr;
-    if (hipMallocAsync((void**)&ws, (size_t)2 * nq * M * sizeof(double), s) != hipSuccess) {
-        (void)hipGetLastError();
-        return IPEPS_ENOMEM;
-    }
     double* pe = ws;
     double* po = ws + nq * M;
     const int S = (nsite + kFfThreads - 1) / kFfThreads;
@@ -450,9 +455,87 @@ int ff_neel_dynamics(int L, int pbc, double tau, double dt, int n_times, int n_r
                            Mo > 0 ? 1.0 / Mo : 0.0, n_even, n_odd);
         e = hipGetLastError();
     }
+    return e;
+}
+
+// Scratch of ff_neel_dynamics_noalloc: one copy per device, held until the
+// process ends.  Host code never passes the array's name to a kernel (on the
+// host it is only a stand-in for the symbol): the device address comes from
+// hipGetSymbolAddress, once per device with that device current.
+constexpr long kNeelScratchDoubles = FF_NOALLOC_SCRATCH_DOUBLES;
+__device__ __align__(256) double scratch[kNeelScratchDoubles];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of this device's scratch (nullptr and a message on failure).
+double* scratch_for_current_device() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            fprintf(stderr, "ff_neel_dynamics_noalloc: hipGetSymbolAddress failed on device %d: %s\n", dev,
+                    hipGetErrorString(e));
+            return nullptr;
+        }
+        g_scratch_ptr[dev] = (double*)p;
+    }
+    return g_scratch_ptr[dev];
+}
+
+}  // namespace
+}  // namespace ipeps
+
+extern "C" {
+
+int ff_neel_dynamics(int L, int pbc, double tau, double dt, int n_times, int n_real, const double* eps,
+                     double* n_even, double* n_odd, void* hip_stream) {
+    using namespace ipeps;
+    const int rc = neel_check(L, pbc, tau, dt, n_times, n_real);
+    if (rc != IPEPS_OK) return rc;
+    if (n_times == 0 || n_real == 0) return IPEPS_OK;
+    if (!eps || !n_even || !n_odd) return IPEPS_EINVAL;
+    hipStream_t s = (hipStream_t)hip_stream;
+    const long nq = (long)n_real * n_times, M = (L * L + 1) / 2;
+    double* ws = nullptr;
+    if (hipMallocAsync((void**)&ws, (size_t)2 * nq * M * sizeof(double), s) != hipSuccess) {
+        (void)hipGetLastError();
+        return IPEPS_ENOMEM;
+    }
+    const hipError_t e = neel_enqueue(s, L, pbc, tau, dt, n_times, n_real, eps, n_even, n_odd, ws);
     const hipError_t f = hipFreeAsync(ws, s);
     if (e != hipSuccess || f != hipSuccess) {
         fprintf(stderr, "ff_neel_dynamics: %s\n", hipGetErrorString(e != hipSuccess ? e : f));
+        return IPEPS_EDEVICE;
+    }
+    return IPEPS_OK;
+}
+
+int ff_neel_dynamics_noalloc(int L, int pbc, double tau, double dt, int n_times, int n_real,
+                             const double* eps, double* n_even, double* n_odd, void* hip_stream) {
+    using namespace ipeps;
+    const int rc = neel_check(L, pbc, tau, dt, n_times, n_real);
+    if (rc != IPEPS_OK) return rc;
+    if (n_times == 0 || n_real == 0) return IPEPS_OK;
+    if (!eps || !n_even || !n_odd) return IPEPS_EINVAL;
+    const long need = 2L * n_real * n_times * ((L * L + 1) / 2);
+    if (need > kNeelScratchDoubles) {
+        fprintf(stderr,
+                "ff_neel_dynamics_noalloc: 2 * n_real * n_times * ceil(L^2/2) = %ld doubles exceeds the "
+                "fixed scratch of %ld doubles\n",
+                need, kNeelScratchDoubles);
+        return IPEPS_ETOOBIG;
+    }
+    double* ws = scratch_for_current_device();
+    if (!ws) return IPEPS_EDEVICE;
+    const hipError_t e =
+        neel_enqueue((hipStream_t)hip_stream, L, pbc, tau, dt, n_times, n_real, eps, n_even, n_odd, ws);
+    if (e != hipSuccess) {
+        fprintf(stderr, "ff_neel_dynamics_noalloc: %s\n", hipGetErrorString(e));
         return IPEPS_EDEVICE;
     }
     return IPEPS_OK;

@@ -20,6 +20,7 @@ IPEPS_ENUMERIC = -4
 IPEPS_ENOTCONV = -5
 IPEPS_EAGAIN = -6
 IPEPS_ENOTFOUND = -7
+IPEPS_ETOOBIG = -8
 DTYPES = {"fp64": 0, "fp32": 1, "bf16": 2}
 FLAG_AUTOTUNE = 1
 FLAG_FACTORED_CUTS = 2
@@ -63,7 +64,7 @@ EXPORTS = [
     "ipeps_corner_spectra", "ipeps_bond_spectra", "ipeps_destroy", "solve_server_create",
     "solve_submit", "solve_poll", "solve_job_times", "solve_server_destroy", "ipeps_strerror",
     "ipeps_profile", "ipeps_profile_read", "ff_neel_dynamics", "ff_bessel_j",
-    "ipeps_observe_async", "ipeps_observe_result", "ff_spectrum_ipr",
+    "ipeps_observe_async", "ipeps_observe_result", "ff_spectrum_ipr", "ff_neel_dynamics_noalloc",
 ]
 
 _lib = None
@@ -109,6 +110,7 @@ def load():
     lib.ipeps_profile_read.argtypes = [C.c_void_p, P(C.c_double), P(C.c_int), P(C.c_double)]
     lib.ff_neel_dynamics.argtypes = [C.c_int, C.c_int, C.c_double, C.c_double, C.c_int, C.c_int,
                                      C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+    lib.ff_neel_dynamics_noalloc.argtypes = lib.ff_neel_dynamics.argtypes
     lib.ff_bessel_j.argtypes = [C.c_double, C.c_int, P(C.c_double)]
     lib.ff_spectrum_ipr.argtypes = [C.c_int, C.c_int, C.c_double, C.c_int, C.c_void_p, C.c_void_p,
                                     C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
@@ -304,6 +306,16 @@ def ff_neel_dynamics_device(L, eps_ptr, n_real, n_even_ptr, n_odd_ptr, n_times, 
     _check(load().ff_neel_dynamics(int(L), int(bool(pbc)), float(tau), float(dt), int(n_times), int(n_real),
                                    C.c_void_p(eps_ptr), C.c_void_p(n_even_ptr), C.c_void_p(n_odd_ptr),
                                    C.c_void_p(sptr)), "ff_neel_dynamics")
+
+
+def ff_neel_dynamics_noalloc_device(L, eps_ptr, n_real, n_even_ptr, n_odd_ptr, n_times, dt, tau=0.5,
+                                    pbc=False, stream=None):
+    """The no-allocation variant (fixed device scratch; see include/ff.h)."""
+    sptr = getattr(stream, "cuda_stream", stream) if stream is not None else None
+    _check(load().ff_neel_dynamics_noalloc(int(L), int(bool(pbc)), float(tau), float(dt), int(n_times),
+                                           int(n_real), C.c_void_p(eps_ptr), C.c_void_p(n_even_ptr),
+                                           C.c_void_p(n_odd_ptr), C.c_void_p(sptr)),
+           "ff_neel_dynamics_noalloc")
 
 
 _hip = None
