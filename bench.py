@@ -35,7 +35,7 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0, "bf16x3": 2500.0}
 # The roofline kernel: the launch of the 8 enlarged-corner products of a
 # column step (chi^2 x q^2 by q^2 x q^2 each), the largest GEMM launch.
 ROOF_KERNEL = "k_gemm_direct<...,TAG=1> (8 enlarged-corner products)"
@@ -54,7 +54,7 @@ def gemm_kernel_digest():
     with open(os.path.join(ROOT, "paper_1910_11359_amd", "csrc", "gemm.hip"), "rb") as f:
         src = f.read()
     return hashlib.sha256(src[src.index(b"static void tile_dims("):]).hexdigest()[:16]
-DTYPE_NAME = {"fp64": "f64", "fp32": "f32", "bf16": "bf16"}
+DTYPE_NAME = {"fp64": "f64", "fp32": "f32", "bf16": "bf16", "bf16x3": "bf16x3"}
 METRIC = "Trotter+CTMRG steps/s at D=6,χ=72 (MFMA % peak); batched jobs/s, p50/p99 latency"
 
 
@@ -363,7 +363,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--dtype", default="fp32", choices=["fp64", "fp32"],
+    ap.add_argument("--dtype", default="fp32", choices=["fp64", "fp32", "bf16", "bf16x3"],
                     help="CTMRG contraction precision (SVDs, simple update and norms stay FP64)")
     ap.add_argument("--no-fp64-ref", action="store_true",
                     help="skip the FP64 comparison run (headline and serving)")

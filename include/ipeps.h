@@ -53,8 +53,16 @@ extern "C" {
 #define IPEPS_ETOOBIG (-8)   /* request larger than a no-allocation entry point's fixed scratch */
 
 /* arithmetic of the CTMRG contractions; simple-update SVDs, projector
- * SVDs and environment norms are FP64 in every mode */
-enum { IPEPS_DTYPE_FP64 = 0, IPEPS_DTYPE_FP32 = 1, IPEPS_DTYPE_BF16 = 2 };
+ * SVDs and environment norms are FP64 in every mode.  FP64 and FP32 store
+ * the environment tensors in that precision and multiply on FP64 / FP32
+ * MFMA.  BF16 stores them in FP32 and rounds every operand of the
+ * environment contractions (enlarged corners, cut-matrix products,
+ * projectors, renormalisation) to BF16 (nearest even) at the MFMA, with FP32
+ * accumulation and FP32 results; the readout contraction stays in FP32.
+ * BF16X3 (split BF16) is BF16 with each operand carried as two BF16 terms
+ * x = h + l, l = bf16(x - h), and each product as h h' + h l' + l h' (three
+ * BF16 MFMAs, about 16 bits of operand precision). */
+enum { IPEPS_DTYPE_FP64 = 0, IPEPS_DTYPE_FP32 = 1, IPEPS_DTYPE_BF16 = 2, IPEPS_DTYPE_BF16X3 = 3 };
 
 /* Job parameters (Eq. Hanc with S = sigma/2):
  *   h_bond = J (Sx Sx + Sy Sy) + V Sz Sz + w W (Sz Za (x) 1 + 1 (x) Sz Za)

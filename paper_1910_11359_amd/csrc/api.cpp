@@ -93,8 +93,9 @@ void validate(const ipeps_config* c) {
     IPEPS_REQUIRE(c->chi >= c->D * c->D && c->chi <= 160, IPEPS_EINVAL, "chi must be in D^2..160");
     IPEPS_REQUIRE(c->dt > 0 && std::isfinite(c->dt), IPEPS_EINVAL, "dt must be > 0");
     IPEPS_REQUIRE(c->trotter_order == 2, IPEPS_EINVAL, "trotter_order must be 2");
-    IPEPS_REQUIRE(c->dtype == IPEPS_DTYPE_FP64 || c->dtype == IPEPS_DTYPE_FP32, IPEPS_EINVAL,
-                  "dtype must be FP64 or FP32");
+    IPEPS_REQUIRE(c->dtype == IPEPS_DTYPE_FP64 || c->dtype == IPEPS_DTYPE_FP32 || c->dtype == IPEPS_DTYPE_BF16 ||
+                      c->dtype == IPEPS_DTYPE_BF16X3,
+                  IPEPS_EINVAL, "dtype must be FP64, FP32, BF16 or BF16X3");
     IPEPS_REQUIRE(std::isfinite(c->J) && std::isfinite(c->V) && std::isfinite(c->W), IPEPS_EINVAL,
                   "non-finite model parameter");
     const uint32_t known = IPEPS_FLAG_AUTOTUNE | IPEPS_FLAG_FACTORED_CUTS | IPEPS_FLAG_FORMED_CUTS;
@@ -384,7 +385,9 @@ char* cut_corner(const ipeps_state* st, int si, int Y, int j) {
 }
 
 void build_plan(ipeps_state* st) {
-    const int q = st->q, chi = st->chi, n = st->n, k = st->k, dt = st->dtype;
+    // dt: arithmetic of the environment contractions (BF16 mode: FP32 tensors,
+    // BF16 MFMA operands); the readout products run in the storage precision
+    const int q = st->q, chi = st->chi, n = st->n, k = st->k, dt = st->mma, dst = st->dtype;
     const size_t e = st->esz;
     const long n2 = (long)n * n, cqc = (long)chi * q * chi, cc = (long)chi * chi;
     auto Cp = [&](int site, int kk) { return off(st->Cenv, (site * 4 + kk) * cc, e); };
@@ -748,10 +751,10 @@ void build_plan(ipeps_state* st) {
                                  (long)q * q, off(Eoutb, s * q4, e), (long)q * q, q * q, q * q,
                                  chi * chi));
         }
-        g[0] = add_group(st, r1, dt);
-        g[1] = add_group(st, r2, dt);
-        g[2] = add_group(st, r3, dt);
-        g[3] = add_group(st, r4, dt);
+        g[0] = add_group(st, r1, dst);
+        g[1] = add_group(st, r2, dst);
+        g[2] = add_group(st, r3, dst);
+        g[3] = add_group(st, r4, dst);
     };
     {
         GemmGroup g[4];
@@ -1187,8 +1190,10 @@ static void fill_dims(ipeps_state* st, const ipeps_config* cfg) {
     st->chi = cfg->chi;
     st->n = cfg->chi * st->q;
     st->k = choose_k(st->n, cfg->chi, cfg->dtype);
-    st->dtype = cfg->dtype;
-    st->esz = cfg->dtype == IPEPS_DTYPE_FP64 ? sizeof(double) : sizeof(float);
+    // the BF16 modes keep the tensors in FP32 and round the MFMA operands
+    st->dtype = cfg->dtype == IPEPS_DTYPE_FP64 ? IPEPS_DTYPE_FP64 : IPEPS_DTYPE_FP32;
+    st->mma = cfg->dtype;
+    st->esz = st->dtype == IPEPS_DTYPE_FP64 ? sizeof(double) : sizeof(float);
     const bool force_f = (cfg->flags & IPEPS_FLAG_FACTORED_CUTS) != 0;
     const bool force_n = (cfg->flags & IPEPS_FLAG_FORMED_CUTS) != 0;
     st->factored = st->n > kDirectMax && (force_f || (!force_n && st->n > kFactoredMin));

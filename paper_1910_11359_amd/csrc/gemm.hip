@@ -1,4 +1,7 @@
-// Grouped MFMA GEMM for gfx950 (CDNA4), FP64 and FP32.
+// Grouped MFMA GEMM for gfx950 (CDNA4), FP64, FP32 and BF16 with FP32
+// accumulation (BF16 modes: FP32 operands in memory and LDS, rounded to BF16
+// (nearest even) as the MFMA fragment is built, v_mfma_f32_16x16x32_bf16,
+// FP32 results; split BF16 carries each operand as two BF16 terms).
 //
 // One workgroup computes a BM x BN tile of one problem; 4 waves in a 2x2
 // arrangement each own a (BM/2) x (BN/2) block made of 16x16 MFMA blocks
@@ -10,7 +13,12 @@
 // MFMA lane layouts (checked on the device): operand A element (i, k) is held
 // by lane i + 16 k, operand B element (k, j) by lane j + 16 k; the FP32
 // result register r of lane l is row 4 (l / 16) + r, column l % 16; the FP64
-// result register r of lane l is row l / 16 + 4 r, column l % 16.
+// result register r of lane l is row l / 16 + 4 r, column l % 16.  The BF16
+// 16x16x32 MFMA takes 8 values per lane: lane l holds row (A) / column (B)
+// l % 16, and element e of lane group g = l / 16 is paired with element e of
+// the same lane group of the other operand; the k order (g, e) -> k is a
+// free choice as long as A and B use the same one (here k = 8 g + e inside a
+// 32-wide k tile); the result layout is that of the FP32 16x16x4 MFMA.
 #include "gemm.h"
 
 #include <cstdint>
@@ -19,6 +27,29 @@ namespace ipeps {
 
 typedef double d4_t __attribute__((ext_vector_type(4)));
 typedef float f4_t __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8_t __attribute__((ext_vector_type(8)));
+
+// BF = 1: each operand value x is rounded to h = bf16(x) (nearest even);
+// BF = 3 (split BF16): x is carried as h + l with l = bf16(x - h), and the
+// product as h_a h_b + h_a l_b + l_a h_b (three MFMAs; the dropped l_a l_b
+// is ~2^-16 of the product), about 16 bits of operand precision.
+template <int BF>
+struct BfOperand {
+    bf8_t h, l;
+    __device__ inline void set(int e, float x) {
+        const __bf16 hx = (__bf16)x;
+        h[e] = hx;
+        if constexpr (BF == 3) l[e] = (__bf16)(x - (float)hx);
+    }
+};
+template <int BF>
+__device__ inline f4_t mfma_bf16(const BfOperand<BF>& a, const BfOperand<BF>& b, f4_t c) {
+    if constexpr (BF == 3) {
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.l, b.h, c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.h, b.l, c, 0, 0, 0);
+    }
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.h, b.h, c, 0, 0, 0);
+}
 
 template <typename T>
 struct Mfma;
@@ -41,9 +72,11 @@ struct Mfma<float> {
 
 // TAG only gives launches of one role (the n^3 cut products) their own kernel
 // symbol, so profilers report them separately; the code is identical.
-template <typename T, int BM, int BN, int BK, int TAG>
+template <typename T, int BM, int BN, int BK, int TAG, int BF = 0>
 __global__ __launch_bounds__(256) void k_gemm_grouped(const GemmProb* __restrict__ probs,
                                                       int nprob) {
+    static_assert(BF == 0 || BF == 1 || BF == 3, "BF: 0, 1 or 3 BF16 products");
+    static_assert(!BF || (sizeof(T) == 4 && BK % 32 == 0), "BF16 modes: FP32 storage, k tiles of 32");
     constexpr int NT = 256;
     constexpr int WM = BM / 2, WN = BN / 2;
     constexpr int FM = WM / 16, FN = WN / 16;
@@ -143,18 +176,37 @@ __global__ __launch_bounds__(256) void k_gemm_grouped(const GemmProb* __restrict
     __syncthreads();
     for (int kt = 0; kt < nk; ++kt) {
         if (kt + 1 < nk) load(kbeg + (kt + 1) * BK);
+        if constexpr (BF) {
 #pragma unroll
-        for (int kk = 0; kk < BK; kk += 4) {
-            T fa[FM], fb[FN];
-            const int kr = kk + (lane >> 4);
+            for (int kk = 0; kk < BK; kk += 32) {
+                BfOperand<BF> fa[FM], fb[FN];
+                const int kr = kk + 8 * (lane >> 4);
 #pragma unroll
-            for (int a = 0; a < FM; ++a) fa[a] = As[kr * PA + wm0 + a * 16 + (lane & 15)];
+                for (int e = 0; e < 8; ++e) {
 #pragma unroll
-            for (int b = 0; b < FN; ++b) fb[b] = Bs[kr * PB + wn0 + b * 16 + (lane & 15)];
+                    for (int a = 0; a < FM; ++a) fa[a].set(e, As[(kr + e) * PA + wm0 + a * 16 + (lane & 15)]);
 #pragma unroll
-            for (int a = 0; a < FM; ++a)
+                    for (int b = 0; b < FN; ++b) fb[b].set(e, Bs[(kr + e) * PB + wn0 + b * 16 + (lane & 15)]);
+                }
 #pragma unroll
-                for (int b = 0; b < FN; ++b) acc[a][b] = Mfma<T>::step(fa[a], fb[b], acc[a][b]);
+                for (int a = 0; a < FM; ++a)
+#pragma unroll
+                    for (int b = 0; b < FN; ++b) acc[a][b] = mfma_bf16(fa[a], fb[b], acc[a][b]);
+            }
+        } else {
+#pragma unroll
+            for (int kk = 0; kk < BK; kk += 4) {
+                T fa[FM], fb[FN];
+                const int kr = kk + (lane >> 4);
+#pragma unroll
+                for (int a = 0; a < FM; ++a) fa[a] = As[kr * PA + wm0 + a * 16 + (lane & 15)];
+#pragma unroll
+                for (int b = 0; b < FN; ++b) fb[b] = Bs[kr * PB + wn0 + b * 16 + (lane & 15)];
+#pragma unroll
+                for (int a = 0; a < FM; ++a)
+#pragma unroll
+                    for (int b = 0; b < FN; ++b) acc[a][b] = Mfma<T>::step(fa[a], fb[b], acc[a][b]);
+            }
         }
         __syncthreads();
         if (kt + 1 < nk) {
@@ -338,8 +390,10 @@ __device__ inline void wait_vm(int s) {
 
 // At least two waves per SIMD: without the bound the FP64 128 x 128 variant
 // takes 194 VGPRs + 128 AGPRs (one wave per SIMD) and ran 27 % slower.
-template <typename T, int BM, int BN, int BK, int NS, int TAG>
+template <typename T, int BM, int BN, int BK, int NS, int TAG, int BF = 0>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) void k_gemm_direct(const GemmProb* __restrict__ probs, int nprob) {
+    static_assert(BF == 0 || BF == 1 || BF == 3, "BF: 0, 1 or 3 BF16 products");
+    static_assert(!BF || (sizeof(T) == 4 && BK == 32), "BF16 modes: FP32 storage, k tiles of 32");
     constexpr int VW = 16 / (int)sizeof(T);
     constexpr int WM = BM / 2, WN = BN / 2;
     constexpr int FM = WM / 16, FN = WN / 16;
@@ -456,6 +510,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
         __builtin_amdgcn_s_waitcnt((15 & 15) | (3 << 14) | (7 << 4) | (0 << 8));  // lgkmcnt(0)
         __builtin_amdgcn_s_barrier();
         if (kt + NS - 1 < nk) issue(kt + NS - 1, (kt + NS - 1) % NS);
+        BfOperand<BF> ha[FM], hb[FN];  // BF16 modes: the lane's 8 k values of this tile
 #pragma unroll
         for (int ch = 0; ch < NCH; ++ch) {
             v_t fa[FM];
@@ -476,13 +531,30 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
                     fb[b][tq] = bs[k * BN + (((n / VW) ^ sw) * VW) + (n % VW)];
                 }
             }
+            if constexpr (BF) {
+                // k = lg KPL + ch VW + tq for both operands (element ch VW + tq)
 #pragma unroll
-            for (int tq = 0; tq < VW; ++tq)
+                for (int tq = 0; tq < VW; ++tq) {
 #pragma unroll
-                for (int a = 0; a < FM; ++a)
+                    for (int a = 0; a < FM; ++a) ha[a].set(ch * VW + tq, fa[a][tq]);
 #pragma unroll
-                    for (int b = 0; b < FN; ++b)
-                        acc[a][b] = Mfma<T>::step(fa[a][tq], fb[b][tq], acc[a][b]);
+                    for (int b = 0; b < FN; ++b) hb[b].set(ch * VW + tq, fb[b][tq]);
+                }
+            } else {
+#pragma unroll
+                for (int tq = 0; tq < VW; ++tq)
+#pragma unroll
+                    for (int a = 0; a < FM; ++a)
+#pragma unroll
+                        for (int b = 0; b < FN; ++b)
+                            acc[a][b] = Mfma<T>::step(fa[a][tq], fb[b][tq], acc[a][b]);
+            }
+        }
+        if constexpr (BF) {
+#pragma unroll
+            for (int a = 0; a < FM; ++a)
+#pragma unroll
+                for (int b = 0; b < FN; ++b) acc[a][b] = mfma_bf16(ha[a], hb[b], acc[a][b]);
         }
     }
 
@@ -547,43 +619,42 @@ __global__ __launch_bounds__(256) void k_splitk_reduce(const GemmProb* __restric
     }
 }
 
+template <int TAG, int BF>
+static void launch_f32(hipStream_t stream, GemmTile tile, const GemmProb* d_probs, int nprob, dim3 grid) {
+    dim3 block(256);
+    if (tile == TILE_DIRECT)
+        hipLaunchKernelGGL((k_gemm_direct<float, 128, 128, 32, 2, TAG, BF>), grid, block, 0, stream, d_probs,
+                           nprob);
+    else if (tile == TILE_DIRECT_SMALL)
+        hipLaunchKernelGGL((k_gemm_direct<float, 64, 64, 32, 2, TAG, BF>), grid, block, 0, stream, d_probs,
+                           nprob);
+    else if (tile == TILE_LARGE)
+        hipLaunchKernelGGL((k_gemm_grouped<float, 128, 128, 32, TAG, BF>), grid, block, 0, stream, d_probs,
+                           nprob);
+    else
+        hipLaunchKernelGGL((k_gemm_grouped<float, 64, 64, 32, TAG, BF>), grid, block, 0, stream, d_probs,
+                           nprob);
+}
+
 template <int TAG>
 static void launch_tagged(hipStream_t stream, int dtype, GemmTile tile, const GemmProb* d_probs,
                           int nprob, dim3 grid) {
     dim3 block(256);
-    if (tile == TILE_DIRECT) {
-        if (dtype == IPEPS_DTYPE_FP64)
-            hipLaunchKernelGGL((k_gemm_direct<double, 128, 128, 16, 2, TAG>), grid, block, 0, stream,
-                               d_probs, nprob);
-        else
-            hipLaunchKernelGGL((k_gemm_direct<float, 128, 128, 32, 2, TAG>), grid, block, 0, stream,
-                               d_probs, nprob);
-        return;
-    }
-    if (tile == TILE_DIRECT_SMALL) {
-        if (dtype == IPEPS_DTYPE_FP64)
-            hipLaunchKernelGGL((k_gemm_direct<double, 64, 64, 16, 2, TAG>), grid, block, 0, stream,
-                               d_probs, nprob);
-        else
-            hipLaunchKernelGGL((k_gemm_direct<float, 64, 64, 32, 2, TAG>), grid, block, 0, stream,
-                               d_probs, nprob);
-        return;
-    }
-    if (dtype == IPEPS_DTYPE_FP64) {
-        if (tile == TILE_LARGE)
-            hipLaunchKernelGGL((k_gemm_grouped<double, 128, 128, 16, TAG>), grid, block, 0, stream,
-                               d_probs, nprob);
-        else
-            hipLaunchKernelGGL((k_gemm_grouped<double, 64, 64, 16, TAG>), grid, block, 0, stream,
-                               d_probs, nprob);
-    } else {
-        if (tile == TILE_LARGE)
-            hipLaunchKernelGGL((k_gemm_grouped<float, 128, 128, 32, TAG>), grid, block, 0, stream,
-                               d_probs, nprob);
-        else
-            hipLaunchKernelGGL((k_gemm_grouped<float, 64, 64, 32, TAG>), grid, block, 0, stream,
-                               d_probs, nprob);
-    }
+    if (dtype == IPEPS_DTYPE_BF16) return launch_f32<TAG, 1>(stream, tile, d_probs, nprob, grid);
+    if (dtype == IPEPS_DTYPE_BF16X3) return launch_f32<TAG, 3>(stream, tile, d_probs, nprob, grid);
+    if (dtype != IPEPS_DTYPE_FP64) return launch_f32<TAG, 0>(stream, tile, d_probs, nprob, grid);
+    if (tile == TILE_DIRECT)
+        hipLaunchKernelGGL((k_gemm_direct<double, 128, 128, 16, 2, TAG>), grid, block, 0, stream, d_probs,
+                           nprob);
+    else if (tile == TILE_DIRECT_SMALL)
+        hipLaunchKernelGGL((k_gemm_direct<double, 64, 64, 16, 2, TAG>), grid, block, 0, stream, d_probs,
+                           nprob);
+    else if (tile == TILE_LARGE)
+        hipLaunchKernelGGL((k_gemm_grouped<double, 128, 128, 16, TAG>), grid, block, 0, stream, d_probs,
+                           nprob);
+    else
+        hipLaunchKernelGGL((k_gemm_grouped<double, 64, 64, 16, TAG>), grid, block, 0, stream, d_probs,
+                           nprob);
 }
 
 void gemm_launch(hipStream_t stream, int dtype, GemmTile tile, const GemmProb* d_probs,

@@ -73,6 +73,7 @@ struct SvdPlan {
 struct ipeps_state {
     ipeps_config cfg;
     int D, d, q, chi, n, k, dtype;
+    int mma;  // arithmetic of the environment contractions (dtype, or BF16 on FP32 tensors)
     bool factored;  // cut matrices applied through their factors (else formed)
     size_t esz;
     hipStream_t stream;

@@ -21,7 +21,7 @@ IPEPS_ENOTCONV = -5
 IPEPS_EAGAIN = -6
 IPEPS_ENOTFOUND = -7
 IPEPS_ETOOBIG = -8
-DTYPES = {"fp64": 0, "fp32": 1, "bf16": 2}
+DTYPES = {"fp64": 0, "fp32": 1, "bf16": 2, "bf16x3": 3}
 FLAG_AUTOTUNE = 1
 FLAG_FACTORED_CUTS = 2
 FLAG_FORMED_CUTS = 4

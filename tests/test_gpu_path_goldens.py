@@ -20,8 +20,10 @@ Random-state cases: CTMRG from a cold start to a corner-spectrum change
 Bars (FP64): imbalance and occupations 1e-6 absolute, Rényi entropies 1e-6,
 bond spectra and truncation errors 1e-10, corner spectra of converged
 environments (both sides below 1e-10) entry by entry to 1e-8 sigma_1.  FP32
-contractions (projector SVDs, simple update and norms in FP64), the same
-number of CTMRG iterations as the oracle needed: imbalance within 1e-3.  The
+contractions and split-BF16 contractions with FP32 accumulation (projector
+SVDs, simple update and norms in FP64), the same number of CTMRG
+iterations as the oracle needed: imbalance and occupations within 1e-3;
+plain BF16 operands within their measured 3e-2.  The
 largest deviations are printed (pytest -s).
 """
 import json
@@ -104,11 +106,12 @@ def test_fp64_path_against_oracle(name):
             assert rel < 1e-8, msg
 
 
+@pytest.mark.parametrize("dtype,bar", [("fp32", 1e-3), ("bf16x3", 1e-3), ("bf16", 3e-2)])
 @pytest.mark.parametrize("name", CASES)
-def test_fp32_path_against_oracle(name):
+def test_low_precision_path_against_oracle(name, dtype, bar):
     g = _golden(name)
-    for o, got, dl, st in _schedule(g, "fp32"):
+    for o, got, dl, st in _schedule(g, dtype):
         dI = abs(got["imbalance"] - o["imbalance"])
         dn = float(np.max(np.abs(got["n"] - np.array(o["n"]))))
-        print(f"{name} fp32 step {o['step']}: |dI| {dI:.2e} |dn| {dn:.2e}", flush=True)
-        assert dI <= 1e-3 and dn <= 1e-3, (name, o["step"], dI, dn)
+        print(f"{name} {dtype} step {o['step']}: |dI| {dI:.2e} |dn| {dn:.2e}", flush=True)
+        assert dI <= bar and dn <= bar, (name, dtype, o["step"], dI, dn)
