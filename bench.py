@@ -15,12 +15,18 @@ Default precision: CTMRG contractions in FP32 on MFMA, the simple update,
 projector SVDs and normalisations in FP64 (--dtype fp64 runs everything in
 FP64; with FP32 the FP64 path is also timed and reported as fp64_path).
 
-Prints one JSON line.  The roofline entry is for the dominant kernel (the
-GEMM launch of the 8 enlarged corners of a column step, each chi^2 x q^2 by
-q^2 x q^2 with q = D^2): algorithmic flops per launch / mean launch time from
-HIP events on the library's stream during the timed steps.  step_mfma_frac
-is the time the step's algorithmic flops need at the MFMA peak of the
-contraction precision over the measured step time.  serving runs a bounded sample of
+Prints one JSON line.  The roofline entry is for the dominant kernel family,
+the environment-contraction GEMMs (k_gemm_direct / k_gemm_grouped in the
+contraction precision: enlarged corners, cut-matrix chains, projectors, C
+and T renormalisation), every launch of the timed steps on the library's
+stream: their algorithmic flops / their summed HIP-event time.  corner_launch
+is the single largest launch (8 enlarged corners).  step_mfma_frac is the
+time the step's algorithmic flops need at the MFMA peak of the contraction
+precision over the measured step time; fp64_gemms covers the FP64 products
+of the projector SVDs.  With a precision other than FP64 the same schedule
+also runs in FP64 and in the other contraction precisions (fp32, bf16x3 =
+split BF16, bf16); precision_vs_fp64 compares their imbalance with FP64 at
+t = 1 after 10 cold CTMRG iterations.  serving runs a bounded sample of
 the request stream in the chosen precision and in FP64 and reports jobs/s,
 p50/p99 latency and the largest imbalance difference between the two.
 cpu_baseline is the oracle (complex128 NumPy) timed on a bounded sample of
@@ -36,15 +42,17 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0, "bf16x3": 2500.0}
-# The roofline kernel: the launch of the 8 enlarged-corner products of a
-# column step (chi^2 x q^2 by q^2 x q^2 each), the largest GEMM launch.
+# The largest single GEMM launch, reported beside the roofline: the 8
+# enlarged-corner products of the left move's first column step (chi^2 x q^2
+# by q^2 x q^2 each), a kernel symbol of its own (TAG=1).
 ROOF_KERNEL = "k_gemm_direct<...,TAG=1> (8 enlarged-corner products)"
-# HBM bytes per launch of that GEMM (FETCH_SIZE + WRITE_SIZE, scaled by a
-# 256 MiB copy), from the traffic profile in profiles/; valid only for the
-# tile planning, kernels and launches they were measured on (the part of
-# gemm.hip from tile_dims on, see gemm_kernel_digest) and for ROOF_KERNEL.
-TRAFFIC = {"fp32": {"kernel": ROOF_KERNEL, "gemm_kernel_sha256_16": "3408463f91b88de2",
-                    "bytes_per_launch": 1.394e9}}
+# HBM bytes per launch of the roofline kernel family (every environment-
+# contraction GEMM launch of a step: FETCH_SIZE + WRITE_SIZE summed over its
+# dispatches, scaled by a 256 MiB copy, divided by the launches), from the
+# traffic profile in profiles/; valid only for the tile planning, kernels
+# and launches they were measured on (the part of gemm.hip from tile_dims
+# on, see gemm_kernel_digest).  Keyed by contraction precision.
+TRAFFIC = {}
 
 
 def gemm_kernel_digest():
@@ -304,9 +312,13 @@ def sweep(P, synthetic, dtype, slots=8):
                         "in [1,20]; 50 steps, 10 CTMRG iterations every 10 steps"}
 
 
-def headline(P, torch, wl, dtype, steps, warmup, prelude, flags=0):
+def headline(P, torch, wl, dtype, steps, warmup, prelude, flags=0, prof_steps=3):
     """Time `steps` steps (after `warmup`) of the headline workload; the state
-    is first evolved for `prelude` Trotter steps and 10 cold CTMRG iterations."""
+    is first evolved for `prelude` Trotter steps and 10 cold CTMRG iterations.
+    The 8-corner launch is timed with HIP events during the timed steps;
+    every GEMM launch on the library's stream is timed during prof_steps
+    further steps of the same schedule.  Returns the step rate and the
+    launch statistics."""
     stream = torch.cuda.Stream()
     cfg = P.make_config(wl["D"], wl["chi"], J=wl["J"], V=wl["V"], W=wl["W"], dt=wl["dt"], dtype=dtype,
                         flags=flags)
@@ -324,17 +336,15 @@ def headline(P, torch, wl, dtype, steps, warmup, prelude, flags=0):
         # collected one step later.
         st.ctmrg(0.0, 1, False, want_delta=False)
         st.trotter_step(1)
-        prev = st.observe_result() if pending[0] else None
+        if pending[0]:
+            st.observe_result()
         st.observe_async()
         pending[0] = True
-        return prev
 
     def drain():
-        if not pending[0]:
-            return None
-        obs = st.observe_result()
-        pending[0] = False
-        return obs
+        if pending[0]:
+            st.observe_result()
+            pending[0] = False
 
     for _ in range(warmup):
         one_step()
@@ -345,17 +355,54 @@ def headline(P, torch, wl, dtype, steps, warmup, prelude, flags=0):
     t0 = time.perf_counter()
     for _ in range(steps):
         one_step()
-    obs = drain()  # the last step's readout, inside the timed region
+    drain()  # the last step's readout, inside the timed region
     stream.synchronize()
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     ms_tot, launches, fl = st.profile_read()
+    # every GEMM launch timed on its own (two events each add ~3 ms per step,
+    # so this runs on prof_steps further steps of the same schedule, after
+    # the timed ones)
+    st.profile(True, every_gemm=True)
+    for _ in range(prof_steps):
+        one_step()
+    drain()
+    gemm = {k: st.profile_read_gemms(k) for k in ("fp64", dtype)}
     st.profile(False)
     st.close()
     launch_ms = ms_tot / max(1, launches)
-    return {"value": steps / dt, "ms_per_step": 1e3 * dt / steps, "t_end": obs["t"],
-            "achieved": fl / (launch_ms * 1e-3) / 1e12 if launches else 0.0,
-            "launch_ms": launch_ms, "flops": fl}
+    return {"value": steps / dt, "ms_per_step": 1e3 * dt / steps,
+            "corner_achieved": fl / (launch_ms * 1e-3) / 1e12 if launches else 0.0,
+            "corner_launch_ms": launch_ms, "corner_flops": fl, "gemm": gemm, "prof_steps": prof_steps}
+
+
+def precision_point(P, wl, dtype, n_steps=20, iters=10):
+    """Imbalance after n_steps Trotter steps from Néel and `iters` cold CTMRG
+    iterations (the precision test's t = 1 observation)."""
+    st = P.State(P.make_config(wl["D"], wl["chi"], J=wl["J"], V=wl["V"], W=wl["W"], dt=wl["dt"],
+                               dtype=dtype))
+    st.trotter_step(n_steps)
+    st.ctmrg(0.0, iters, True)
+    o = st.observe()
+    st.close()
+    return o["imbalance"], o["n"]
+
+
+def gemm_roofline(rec, dtype):
+    """Every environment-contraction GEMM launch of the timed steps (the
+    enlarged corners, the cut-matrix chains, the projectors and the C / T
+    renormalisation; main stream), as one kernel family: algorithmic flops
+    per launch over the mean HIP-event launch time."""
+    ms, fl, n = rec["gemm"][dtype]
+    ach = fl / (ms * 1e-3) / 1e12 if ms > 0 else 0.0
+    return {"bound": "mfma", "achieved": ach, "peak": PEAK_TFLOPS[dtype], "unit": "TFLOP/s",
+            "frac": ach / PEAK_TFLOPS[dtype], "traffic": None,
+            "kernel": f"k_gemm_direct / k_gemm_grouped in {dtype}: every environment-contraction GEMM "
+                      f"launch of the timed steps (main stream)",
+            "launches_per_step": n / rec["prof_steps"], "launch_ms": ms / max(1, n),
+            "flops_per_launch": fl / max(1, n), "ms_per_step": ms / rec["prof_steps"],
+            "timing": f"HIP events around every such launch during {rec['prof_steps']} profiled steps "
+                      f"after the timed ones"}
 
 
 def main():
@@ -367,6 +414,8 @@ def main():
                     help="CTMRG contraction precision (SVDs, simple update and norms stay FP64)")
     ap.add_argument("--no-fp64-ref", action="store_true",
                     help="skip the FP64 comparison run (headline and serving)")
+    ap.add_argument("--no-other-dtypes", action="store_true",
+                    help="skip the headline runs in the other contraction precisions")
     ap.add_argument("--autotune", action="store_true",
                     help="time every GEMM group's candidate tile kinds at init and keep the fastest")
     ap.add_argument("--prelude", type=int, default=20, help="untimed Trotter steps first")
@@ -395,11 +444,12 @@ def main():
     flags = P.FLAG_AUTOTUNE if args.autotune else 0
     rec = headline(P, torch, wl, args.dtype, args.steps, args.warmup, args.prelude, flags)
     peak = PEAK_TFLOPS[args.dtype]
-    traffic = None
+    roof = gemm_roofline(rec, args.dtype)
     tr = TRAFFIC.get(args.dtype)
-    if (tr and tr["bytes_per_launch"] and tr["kernel"] == ROOF_KERNEL
+    if (tr and tr["bytes_per_launch"] and tr["kernel"] == "gemm_family"
             and gemm_kernel_digest() == tr["gemm_kernel_sha256_16"]):
-        traffic = tr["bytes_per_launch"]
+        roof["traffic"] = tr["bytes_per_launch"]
+    ms64, fl64, n64 = rec["gemm"]["fp64"]
     out = {
         "metric": METRIC, "value": rec["value"], "unit": "steps/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": rec["ms_per_step"], "higher_is_better": True,
@@ -407,19 +457,37 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"headline iPEPS step: D={D}, chi={chi}, d=4, J=1, V={wl['V']}, "
                                f"W={wl['W']}, dt={wl['dt']}, after {args.prelude} prelude steps",
-                   "D": D, "chi": chi, "d": 4, "t_end": rec["t_end"],
-                   "contractions": args.dtype, "svd_su_norms": "fp64",
+                   "D": D, "chi": chi, "d": 4, "contractions": args.dtype, "svd_su_norms": "fp64",
                    "gemm_tiles": "autotuned" if args.autotune else "heuristic"},
-        "roofline": {"bound": "mfma", "achieved": rec["achieved"], "peak": peak, "unit": "TFLOP/s",
-                     "frac": rec["achieved"] / peak, "traffic": traffic,
-                     "kernel": ROOF_KERNEL,
-                     "launch_ms": rec["launch_ms"], "flops_per_launch": rec["flops"]},
+        "roofline": roof,
         "step_mfma_frac": step_mfma_frac(D, chi, args.dtype, rec["ms_per_step"]),
+        "corner_launch": {"kernel": ROOF_KERNEL, "achieved": rec["corner_achieved"],
+                          "frac": rec["corner_achieved"] / peak, "launch_ms": rec["corner_launch_ms"],
+                          "flops_per_launch": rec["corner_flops"]},
+        "fp64_gemms": {"achieved": fl64 / (ms64 * 1e-3) / 1e12 if ms64 > 0 else 0.0,
+                       "frac": (fl64 / (ms64 * 1e-3) / 1e12 if ms64 > 0 else 0.0) / PEAK_TFLOPS["fp64"],
+                       "ms_per_step": ms64 / rec["prof_steps"], "launches_per_step": n64 / rec["prof_steps"],
+                       "what": "FP64 products of the projector SVDs (Grams, orthogonalisation)"},
     }
     if args.dtype != "fp64" and not args.no_fp64_ref:
         r64 = headline(P, torch, wl, "fp64", args.steps, args.warmup, args.prelude, flags)
         out["fp64_path"] = {"value": r64["value"], "ms_per_step": r64["ms_per_step"],
-                            "roofline_frac": r64["achieved"] / PEAK_TFLOPS["fp64"]}
+                            "roofline_frac": gemm_roofline(r64, "fp64")["frac"],
+                            "step_mfma_frac": step_mfma_frac(D, chi, "fp64", r64["ms_per_step"])}
+        i64, n64_ = precision_point(P, wl, "fp64")
+        prec = {}
+        compared = [args.dtype] + ([] if args.no_other_dtypes else
+                                   [d for d in ("fp32", "bf16x3", "bf16") if d != args.dtype])
+        for other in compared:
+            io, no = precision_point(P, wl, other)
+            prec[other] = {"imbalance_err": abs(io - i64), "max_n_err": float(max(abs(a - b) for a, b in zip(no, n64_)))}
+        out["precision_vs_fp64"] = dict(prec, schedule="Néel, 20 Trotter steps (t = 1), 10 cold CTMRG "
+                                                        "iterations, readout; the same in FP64")
+        for other in [d for d in ("fp32", "bf16x3", "bf16") if d != args.dtype and not args.no_other_dtypes]:
+            ro = headline(P, torch, wl, other, args.steps, args.warmup, args.prelude, flags)
+            out[f"{other}_path"] = {"value": ro["value"], "ms_per_step": ro["ms_per_step"],
+                                    "gemm_frac": gemm_roofline(ro, other)["frac"],
+                                    "imbalance_err_vs_fp64": prec[other]["imbalance_err"]}
     if args.copy_probe > 0:
         src = torch.empty(args.copy_probe << 18, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)

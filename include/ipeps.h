@@ -264,15 +264,25 @@ int solve_job_times(ipeps_server* srv, uint64_t job_id, double* t_submit, double
 void solve_server_destroy(ipeps_server* srv);
 
 /* ------------------------------------------------------------ instrumentation
- * Time the launches of the n^3 half-system products (the largest MFMA GEMM
- * launch of a CTMRG column step, four (chi D^2)^3 products) with HIP events on
- * the state's stream.  ipeps_profile(st, 1) starts (and clears) recording of
- * up to 4096 launches; ipeps_profile_read synchronises the stream and returns
- * the summed launch time in ms, the number of launches and the algorithmic
- * flops of one launch (2 M N K summed over its products), then clears. */
+ * HIP-event timing of the GEMM launches on the state's stream.
+ * ipeps_profile(st, 1) starts (and clears) recording of the launches of the
+ * largest enlarged-corner GEMM launch of an iteration (the 8 corner products
+ * of the left move's first column step, a kernel symbol of its own);
+ * ipeps_profile(st, 2) records every GEMM launch on the state's stream (the
+ * environment contractions, and the FP64 products of the projector SVDs);
+ * ipeps_profile(st, 0) stops.  At most 16384 launches are recorded.
+ * ipeps_profile_read synchronises the stream and returns the summed time in
+ * ms of the recorded enlarged-corner launches, their number and the
+ * algorithmic flops of one of them (2 M N K summed over its products), then
+ * clears the record.  ipeps_profile_read_gemms synchronises and returns, for
+ * the recorded launches whose arithmetic is `dtype` (IPEPS_DTYPE_*), their
+ * summed time, summed algorithmic flops and number, without clearing.
+ * Errors: EINVAL. */
 int ipeps_profile(ipeps_state* st, int enable);
 int ipeps_profile_read(ipeps_state* st, double* total_ms, int* launches,
                        double* flops_per_launch);
+int ipeps_profile_read_gemms(ipeps_state* st, int dtype, double* total_ms, double* flops,
+                             int* launches);
 
 const char* ipeps_strerror(int code);
 

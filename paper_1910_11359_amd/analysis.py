@@ -11,12 +11,17 @@ Host post-processing of imbalance series I(t) that the device path returns
   extrapolation first reaches I = 0.
 * `classify` labels a series "localized" or "ergodic".  The paper's
   criterion is qualitative (whether the simulated imbalance, or its
-  polynomial continuation, localizes in time).  The reading taken: a series
-  is localized when the imbalance over the last third of the simulated
-  window stays at or above `plateau` (0.3 of the initial imbalance by
-  default) and the degree-1 fit over that third falls by less than `drift`
-  (0.1 of the initial imbalance) per unit of simulated time, i.e. slow
-  dynamics far from zero; ergodic otherwise.
+  polynomial continuation, localizes in time) and names no threshold.  The
+  reading taken: a series is localized when the imbalance over the last
+  third of the simulated window stays at or above `plateau` (0.3 of the
+  initial imbalance by default) and the degree-1 fit over that third falls
+  by less than `drift` (0.1 of the initial imbalance) per unit of simulated
+  time, i.e. slow dynamics far from zero; ergodic otherwise.  Both
+  thresholds are free parameters of this reading, reported as such with
+  each label (details=True), next to the zero crossings of the paper's own
+  polynomial continuations.  Those continuations alone do not decide: on a
+  pure exponential decay the degree-2 and degree-4 fits curve upwards and
+  never reach zero, so a vote over the degrees calls it localized.
 * `phase_diagram` applies `classify` to a set of parameter points.
 """
 import numpy as np
@@ -83,23 +88,42 @@ def zero_crossing(fit, t_from, t_to, n_grid=4001):
     return float(0.5 * (a + b))
 
 
-def classify(t, imbalance, plateau=0.3, drift=0.1):
+def classify(t, imbalance, plateau=0.3, drift=0.1, horizon=2.0, details=False):
     """'localized' or 'ergodic' for one series (reading in the module notes).
-    The imbalance is taken relative to its value at the first time."""
+    The imbalance is taken relative to its value at the first time.
+
+    plateau and drift are free parameters of this reading: the paper states
+    its criterion only qualitatively and fixes no threshold.  details=True
+    returns a dict with the label, the two thresholds (marked as free
+    parameters), the quantities they are compared with (the smallest
+    relative imbalance over the last third of the window and the fall per
+    unit time of its degree-1 fit), and, for the paper's fits of degree 1, 2,
+    4 and 5 over the whole window, the first time their extrapolation
+    reaches zero before horizon * t_max (None: not before), the continuation
+    the imbalance figure draws."""
     t = np.asarray(t, dtype=np.float64)
     y = np.asarray(imbalance, dtype=np.float64)
     if len(t) < 3:
         raise ValueError("need at least 3 observations")
     y0 = y[0] if y[0] != 0 else 1.0
-    y = y / y0
+    yr = y / y0
     tail = t >= t[0] + (2.0 / 3.0) * (t[-1] - t[0])
     if tail.sum() < 2:
         tail[-2:] = True
-    slope = np.polyfit(t[tail], y[tail], 1)[0] if tail.sum() >= 2 else 0.0
-    localized = np.min(y[tail]) >= plateau and -slope < drift
-    return "localized" if localized else "ergodic"
+    slope = np.polyfit(t[tail], yr[tail], 1)[0] if tail.sum() >= 2 else 0.0
+    tail_min = float(np.min(yr[tail]))
+    localized = tail_min >= plateau and -slope < drift
+    label = "localized" if localized else "ergodic"
+    if not details:
+        return label
+    fits = imbalance_fits(t, y)
+    return {"label": label, "tail_min_relative": tail_min, "tail_fall_per_time": float(-slope),
+            "free_parameters": {"plateau": plateau, "drift": drift, "horizon": horizon,
+                                "note": "thresholds of this reading; the paper fixes none"},
+            "fit_zero_crossing": {d: zero_crossing(f, t[0], horizon * t[-1]) for d, f in fits.items()}}
 
 
-def phase_diagram(series, **kw):
-    """series: {(d_A, h): (t, imbalance)} -> {(d_A, h): 'localized' | 'ergodic'}."""
-    return {key: classify(t, y, **kw) for key, (t, y) in series.items()}
+def phase_diagram(series, details=False, **kw):
+    """series: {(d_A, h): (t, imbalance)} -> {(d_A, h): 'localized' | 'ergodic'}
+    (details=True: the per-point dicts of classify, free parameters included)."""
+    return {key: classify(t, y, details=details, **kw) for key, (t, y) in series.items()}

@@ -202,14 +202,16 @@ GemmGroup add_group(ipeps_state* st, std::vector<GemmProb> probs, int dtype, int
 
 void run(ipeps_state* st, const GemmGroup& g) {
     if (g.count == 0) return;
-    const bool timed = st->prof_on && g.tag == 1 && st->prof_used + 2 <= (int)st->prof_ev.size();
+    const bool timed = st->prof_on && (g.tag == 1 || st->prof_mode == 2) &&
+                       st->prof_used + 2 <= (int)st->prof_ev.size();
     if (timed) HIP_CHECK(hipEventRecord(st->prof_ev[st->prof_used], st->stream));
     gemm_launch(st->stream, g.dtype, g.tile, st->d_probs + g.first, g.count, g.tiles, g.tag,
                 g.reduce_elems);
     if (timed) {
         HIP_CHECK(hipEventRecord(st->prof_ev[st->prof_used + 1], st->stream));
         st->prof_used += 2;
-        st->prof_flops = g.flops;
+        st->prof_meta.push_back({g.flops, g.dtype, g.tag});
+        if (g.tag == 1) st->prof_flops = g.flops;
     }
 }
 
@@ -1532,14 +1534,16 @@ int ipeps_bond_spectra(ipeps_state* st, double* out) {
 }
 
 int ipeps_profile(ipeps_state* st, int enable) {
-    if (!st) return IPEPS_EINVAL;
+    if (!st || enable < 0 || enable > 2) return IPEPS_EINVAL;
     return wrap(st, [&] {
         if (enable && st->prof_ev.empty()) {
-            st->prof_ev.resize(2 * 4096);
+            st->prof_ev.resize(2 * 16384);
             for (auto& e : st->prof_ev) HIP_CHECK(hipEventCreate(&e));
         }
         st->prof_on = enable != 0;
+        st->prof_mode = enable;
         st->prof_used = 0;
+        st->prof_meta.clear();
     });
 }
 
@@ -1548,15 +1552,40 @@ int ipeps_profile_read(ipeps_state* st, double* total_ms, int* launches, double*
     return wrap(st, [&] {
         HIP_CHECK(hipStreamSynchronize(st->stream));
         double tot = 0;
+        int cnt = 0;
         for (int i = 0; i + 1 < st->prof_used; i += 2) {
+            if (st->prof_meta[i / 2].tag != 1) continue;
             float ms = 0;
             HIP_CHECK(hipEventElapsedTime(&ms, st->prof_ev[i], st->prof_ev[i + 1]));
             tot += ms;
+            ++cnt;
         }
         if (total_ms) *total_ms = tot;
-        if (launches) *launches = st->prof_used / 2;
+        if (launches) *launches = cnt;
         if (flops_per_launch) *flops_per_launch = st->prof_flops;
         st->prof_used = 0;
+        st->prof_meta.clear();
+    });
+}
+
+int ipeps_profile_read_gemms(ipeps_state* st, int dtype, double* total_ms, double* flops, int* launches) {
+    if (!st) return IPEPS_EINVAL;
+    return wrap(st, [&] {
+        HIP_CHECK(hipStreamSynchronize(st->stream));
+        double tot = 0, fl = 0;
+        int cnt = 0;
+        for (int i = 0; i + 1 < st->prof_used; i += 2) {
+            const auto& m = st->prof_meta[i / 2];
+            if (m.dtype != dtype) continue;
+            float ms = 0;
+            HIP_CHECK(hipEventElapsedTime(&ms, st->prof_ev[i], st->prof_ev[i + 1]));
+            tot += ms;
+            fl += m.flops;
+            ++cnt;
+        }
+        if (total_ms) *total_ms = tot;
+        if (flops) *flops = fl;
+        if (launches) *launches = cnt;
     });
 }
 

@@ -230,9 +230,15 @@ struct ipeps_state {
 
     // timing of the half-system product launches (HIP events on the stream)
     bool prof_on;
+    int prof_mode;  // 1: the TAG 1 launches only; 2: every GEMM launch on the main stream
     std::vector<hipEvent_t> prof_ev;
     int prof_used;
     double prof_flops;
+    struct ProfLaunch {
+        double flops;
+        int dtype, tag;
+    };
+    std::vector<ProfLaunch> prof_meta;  // one per recorded event pair
 
     long step_count;
     bool have_env;

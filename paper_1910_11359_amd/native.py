@@ -65,6 +65,7 @@ EXPORTS = [
     "solve_submit", "solve_poll", "solve_job_times", "solve_server_destroy", "ipeps_strerror",
     "ipeps_profile", "ipeps_profile_read", "ff_neel_dynamics", "ff_bessel_j",
     "ipeps_observe_async", "ipeps_observe_result", "ff_spectrum_ipr", "ff_neel_dynamics_noalloc",
+    "ipeps_profile_read_gemms",
 ]
 
 _lib = None
@@ -108,6 +109,7 @@ def load():
     lib.solve_server_destroy.restype = None
     lib.ipeps_profile.argtypes = [C.c_void_p, C.c_int]
     lib.ipeps_profile_read.argtypes = [C.c_void_p, P(C.c_double), P(C.c_int), P(C.c_double)]
+    lib.ipeps_profile_read_gemms.argtypes = [C.c_void_p, C.c_int, P(C.c_double), P(C.c_double), P(C.c_int)]
     lib.ff_neel_dynamics.argtypes = [C.c_int, C.c_int, C.c_double, C.c_double, C.c_int, C.c_int,
                                      C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
     lib.ff_neel_dynamics_noalloc.argtypes = lib.ff_neel_dynamics.argtypes
@@ -231,8 +233,17 @@ class State:
         _check(self._lib.ipeps_corner_spectra(self.h, _dptr(out)), "ipeps_corner_spectra")
         return out
 
-    def profile(self, enable=True):
-        _check(self._lib.ipeps_profile(self.h, int(bool(enable))), "ipeps_profile")
+    def profile(self, enable=True, every_gemm=False):
+        mode = (2 if every_gemm else 1) if enable else 0
+        _check(self._lib.ipeps_profile(self.h, mode), "ipeps_profile")
+
+    def profile_read_gemms(self, dtype):
+        """(summed ms, summed algorithmic flops, launches) of the recorded GEMM
+        launches whose arithmetic is dtype ('fp64', 'fp32', 'bf16', 'bf16x3')."""
+        ms, fl, n = C.c_double(), C.c_double(), C.c_int()
+        _check(self._lib.ipeps_profile_read_gemms(self.h, DTYPES[dtype], C.byref(ms), C.byref(fl),
+                                                  C.byref(n)), "ipeps_profile_read_gemms")
+        return ms.value, fl.value, n.value
 
     def profile_read(self):
         ms, n, fl = C.c_double(), C.c_int(), C.c_double()

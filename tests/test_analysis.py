@@ -76,3 +76,17 @@ def test_classification_and_phase_diagram():
     assert an.classify(t, drift) == "ergodic"
     pd = an.phase_diagram({(5, 6.0): (t, plateau), (2, 6.0): (t, decay)})
     assert pd == {(5, 6.0): "localized", (2, 6.0): "ergodic"}
+
+
+def test_classification_details_report_free_parameters_and_fit_crossings():
+    t = _series(31, 3.0)
+    drift = 0.9 - 0.2 * t
+    d = an.classify(t, drift, details=True)
+    assert d["label"] == "ergodic"
+    assert d["free_parameters"]["plateau"] == 0.3 and d["free_parameters"]["drift"] == 0.1
+    # a line is its own fit of every degree: each continuation reaches zero at 4.5
+    for deg in (1, 2, 4, 5):
+        assert abs(d["fit_zero_crossing"][deg] - 4.5) < 1e-9
+    assert abs(d["tail_fall_per_time"] - 0.2 / 0.9) < 1e-12
+    pd = an.phase_diagram({(2, 6.0): (t, drift)}, details=True)
+    assert pd[(2, 6.0)]["label"] == "ergodic"
