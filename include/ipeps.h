@@ -263,6 +263,57 @@ int solve_job_times(ipeps_server* srv, uint64_t job_id, double* t_submit, double
 /* Wait for all jobs, stop the loop and release everything. */
 void solve_server_destroy(ipeps_server* srv);
 
+/* ------------------------------------------------------------ batches
+ * Many jobs of one layout advanced in lockstep, every launch carrying all of
+ * them (the simple-update layers, the enlarged-corner, cut-matrix, projector
+ * and renormalisation GEMMs, the Cholesky, Jacobi and projector kernels of
+ * the projector SVDs, the spectra): the parameter points of a sweep, or the
+ * resident requests of one shape in the request loop.  Each job keeps its own
+ * state and its results are those it gets alone (every GEMM problem keeps the
+ * tile kind and summation order of the job's own plan; FP64 results are
+ * bitwise the same).
+ *
+ * Layout: D, chi, d_A, dtype and flags; jobs of one layout may differ in J, V,
+ * W, dt, the layer hooks and the seed.  A slab is one device allocation with
+ * `slots` regions of ipeps_slab_region_bytes(cfg) each; ipeps_slab_init
+ * creates a state (as ipeps_init, Néel ⊗ |+>) inside region `slot`, and
+ * ipeps_destroy of that state frees the region again.  Batches need their
+ * states to come from one slab (their buffers then sit at one fixed offset
+ * from each other). */
+typedef struct ipeps_slab ipeps_slab;
+typedef struct ipeps_batch ipeps_batch;
+
+/* Bytes of one slab region for this layout; 0 for an invalid config. */
+size_t ipeps_slab_region_bytes(const ipeps_config* cfg);
+/* Errors: EINVAL (bad config, slots < 1), ENOMEM. */
+int ipeps_slab_create(const ipeps_config* layout, int slots, ipeps_slab** out);
+/* cfg must have the slab's layout; the slot must be free.  The state's own
+ * stream is hip_stream.  Errors: EINVAL, ENOMEM, EDEVICE. */
+int ipeps_slab_init(ipeps_slab* slab, int slot, const ipeps_config* cfg, void* hip_stream,
+                    ipeps_state** out);
+/* Synchronises the device and releases the slab (its states must have been
+ * destroyed). */
+void ipeps_slab_destroy(ipeps_slab* slab);
+
+/* A lockstep batch of n >= 1 states of one slab, at the same phase of their
+ * schedules (all with or all without an environment, the same warm projector
+ * subspaces, no pending asynchronous readout); states[0] leads: its streams
+ * carry all the work, ordered after everything already enqueued on any
+ * job's streams.  While the batch exists its states must not be used
+ * otherwise.  Errors: EINVAL (NULL, repeated or poisoned states, different
+ * layouts, not one slab, different phases), EDEVICE. */
+int ipeps_batch_create(ipeps_state* const* states, int n, ipeps_batch** out);
+/* ipeps_trotter_step for every job (no truncation errors returned). */
+int ipeps_batch_trotter_step(ipeps_batch* b, int n_steps);
+/* ctmrg_converge with tol <= 0 for every job: exactly iters iterations,
+ * cold (cold_start != 0) or warm. */
+int ipeps_batch_ctmrg(ipeps_batch* b, int iters, int cold_start);
+/* ipeps_observe for every job: out[i] for states[i].  Synchronises. */
+int ipeps_batch_observe(ipeps_batch* b, ipeps_obs* out);
+/* Orders every job's streams after the batch's work, waits for it and
+ * releases the batch (not the states). */
+void ipeps_batch_destroy(ipeps_batch* b);
+
 /* ------------------------------------------------------------ instrumentation
  * HIP-event timing of the GEMM launches on the state's stream.
  * ipeps_profile(st, 1) starts (and clears) recording of the launches of the

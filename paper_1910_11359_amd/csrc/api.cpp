@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <unordered_map>
 #include <mutex>
 #include <new>
 #include <string>
@@ -197,16 +198,62 @@ GemmGroup add_group(ipeps_state* st, std::vector<GemmProb> probs, int dtype, int
         g.flops += 2.0 * p.M * (double)p.N * p.K;
         st->probs.push_back(p);
     }
+    if (g.count > 0) st->groups.push_back(g);
     return g;
 }
 
-void run(ipeps_state* st, const GemmGroup& g) {
+// ---------------------------------------------------------------- execution
+// The CTMRG and the simple update run on one state, or on several states of
+// one buffer layout in lockstep (a batch; every state then holds the same
+// buffers at the same offsets from its first allocation, and its buffers sit
+// jm.delta[j] bytes from the lead's): every launch carries all the jobs.
+// GEMM groups are replayed from a merged problem table (each problem of the
+// lead's group once per job, its pointers moved by the job's offset, with the
+// lead's tile kind, so every job's arithmetic is the one it has alone); the
+// other kernels take the JobMap.  All work goes to the lead's streams.
+struct Ex {
+    ipeps_state* st = nullptr;       // lead: dimensions, plan, streams, control flags
+    std::vector<ipeps_state*> jobs;  // every job, jobs[0] == st
+    JobMap jm;                       // delta == nullptr: one job
+    GemmProb* d_probs = nullptr;     // merged problem table (batch)
+    std::unordered_map<int, GemmGroup> merged;  // lead group .first -> merged group
+    NormItem* d_norms = nullptr;     // merged normalisation items (batch)
+    std::unordered_map<long, long> norm_first;  // lead item range .first -> merged first
+    double* norm_ws = nullptr;       // workspace of the merged normalisations
+    std::vector<long> hdelta;        // host copy of jm.delta
+    bool batched() const { return jm.delta != nullptr; }
+    int nj() const { return (int)jobs.size(); }
+    // a buffer pointer of the lead moved to job j's copy
+    template <typename T>
+    T* at(T* p, int j) const {
+        return batched() ? (T*)((char*)p + hdelta[j]) : p;
+    }
+};
+
+Ex solo(ipeps_state* st) {
+    Ex x;
+    x.st = st;
+    x.jobs.push_back(st);
+    return x;
+}
+
+void launch_group(const Ex& x, hipStream_t stream, const GemmGroup& g) {
+    if (!x.batched()) {
+        gemm_launch(stream, g.dtype, g.tile, x.st->d_probs + g.first, g.count, g.tiles, g.tag,
+                    g.reduce_elems);
+        return;
+    }
+    const GemmGroup& m = x.merged.at(g.first);
+    gemm_launch(stream, m.dtype, m.tile, x.d_probs + m.first, m.count, m.tiles, g.tag, m.reduce_elems);
+}
+
+void run(const Ex& x, const GemmGroup& g) {
     if (g.count == 0) return;
-    const bool timed = st->prof_on && (g.tag == 1 || st->prof_mode == 2) &&
+    ipeps_state* st = x.st;
+    const bool timed = !x.batched() && st->prof_on && (g.tag == 1 || st->prof_mode == 2) &&
                        st->prof_used + 2 <= (int)st->prof_ev.size();
     if (timed) HIP_CHECK(hipEventRecord(st->prof_ev[st->prof_used], st->stream));
-    gemm_launch(st->stream, g.dtype, g.tile, st->d_probs + g.first, g.count, g.tiles, g.tag,
-                g.reduce_elems);
+    launch_group(x, st->stream, g);
     if (timed) {
         HIP_CHECK(hipEventRecord(st->prof_ev[st->prof_used + 1], st->stream));
         st->prof_used += 2;
@@ -217,10 +264,16 @@ void run(ipeps_state* st, const GemmGroup& g) {
 
 char* off(void* base, long elems, size_t esz) { return (char*)base + elems * (long)esz; }
 
-void run_on(ipeps_state* st, hipStream_t stream, const GemmGroup& g) {
+void run_on(const Ex& x, hipStream_t stream, const GemmGroup& g) {
     if (g.count == 0) return;
-    gemm_launch(stream, g.dtype, g.tile, st->d_probs + g.first, g.count, g.tiles, g.tag,
-                g.reduce_elems);
+    launch_group(x, stream, g);
+}
+
+// Frobenius normalisation of `count` items of the lead's table from `first`
+// (all jobs in a batch)
+void normalize_items(const Ex& x, hipStream_t s, int dtype, long first, int count, double* ws) {
+    if (!x.batched()) return normalize_tensors(s, dtype, x.st->d_norms + first, count, ws);
+    normalize_tensors(s, dtype, x.d_norms + x.norm_first.at(first), count * x.nj(), x.norm_ws);
 }
 
 GemmProb split(GemmProb p, int ks, void* ws) {
@@ -851,34 +904,45 @@ void build_double_layers(ipeps_state* st, hipStream_t s, cplx* A, double* a_base
     normalize_tensors(s, IPEPS_DTYPE_FP64, st->d_norms + norm_first, 4, ws);
 }
 
-void prepare_double_layers(ipeps_state* st) {
-    HIP_CHECK(hipStreamWaitEvent(st->stream, st->ev_su_done, 0));
-    if (st->pre_valid && st->pre_step == st->step_count) {
+// Double layers of every job for the CTMRG about to run on the lead's main
+// stream: the ones the simple update built ahead (swapped in, frame copies
+// copied whole), or built here.
+void prepare_double_layers(const Ex& x) {
+    ipeps_state* L = x.st;
+    hipStream_t s = L->stream;
+    HIP_CHECK(hipStreamWaitEvent(s, L->ev_su_done, 0));
+    const long q4 = (long)L->q * L->q * L->q * L->q;
+    bool all_pre = true;
+    for (ipeps_state* st : x.jobs) all_pre = all_pre && st->pre_valid && st->pre_step == st->step_count;
+    if (all_pre) {
         // built at the tail of the simple update (ordered by ev_su_done),
         // frame copies included: one device copy into the plan's buffers
-        std::swap(st->A, st->A_pre);
-        std::swap(st->a_base, st->a_base_pre);
-        std::swap(st->eps_snap, st->eps_snap_pre);
-        std::swap(st->norm_a_first, st->norm_a_pre_first);
-        st->pre_valid = false;
-        const long q4 = (long)st->q * st->q * st->q * st->q;
-        HIP_CHECK(hipMemcpyAsync(st->frames, st->frames_pre, 32 * q4 * st->esz, hipMemcpyDeviceToDevice,
-                                 st->stream));
+        for (ipeps_state* st : x.jobs) {
+            std::swap(st->A, st->A_pre);
+            std::swap(st->a_base, st->a_base_pre);
+            std::swap(st->eps_snap, st->eps_snap_pre);
+            std::swap(st->norm_a_first, st->norm_a_pre_first);
+            st->pre_valid = false;
+            st->ctm_step = st->step_count;
+        }
+        copy_jobs(s, L->frames, L->frames_pre, 32 * q4 * L->esz, x.jm);
         // the next simple update may rebuild the *_pre buffers (frames_pre
         // included) once this point is passed
-        HIP_CHECK(hipEventRecord(st->ev_gamma_free, st->stream));
-        st->ctm_step = st->step_count;
+        HIP_CHECK(hipEventRecord(L->ev_gamma_free, s));
         return;
-    } else {
-        absorb_sqrt_lambda(st->stream, st->D, st->d, st->gam, st->lam, st->A);
-        HIP_CHECK(hipMemcpyAsync(st->eps_snap, st->eps, 4 * sizeof(double), hipMemcpyDeviceToDevice,
-                                 st->stream));
-        HIP_CHECK(hipEventRecord(st->ev_gamma_free, st->stream));
-        double_layer_real(st->stream, st->D, st->d, st->A, st->a_base);
-        normalize_tensors(st->stream, IPEPS_DTYPE_FP64, st->d_norms + st->norm_a_first, 4, st->norm_ws);
     }
-    frame_layouts(st->stream, st->q, st->dtype, st->a_base, st->d_a_lu, st->d_a_dl);
-    st->ctm_step = st->step_count;
+    for (ipeps_state* st : x.jobs) {
+        absorb_sqrt_lambda(s, st->D, st->d, st->gam, st->lam, st->A);
+        HIP_CHECK(hipMemcpyAsync(st->eps_snap, st->eps, 4 * sizeof(double), hipMemcpyDeviceToDevice, s));
+    }
+    HIP_CHECK(hipEventRecord(L->ev_gamma_free, s));
+    for (ipeps_state* st : x.jobs) {
+        double_layer_real(s, st->D, st->d, st->A, st->a_base);
+        normalize_tensors(s, IPEPS_DTYPE_FP64, st->d_norms + st->norm_a_first, 4, st->norm_ws);
+        frame_layouts(s, st->q, st->dtype, st->a_base, st->d_a_lu, st->d_a_dl);
+        st->pre_valid = false;
+        st->ctm_step = st->step_count;
+    }
 }
 
 // Order the main stream after all enqueued simple-update work.
@@ -891,32 +955,38 @@ void join_su(ipeps_state* st) { HIP_CHECK(hipStreamWaitEvent(st->stream, st->ev_
 // independent directions, and the next power step with N pulls out the
 // directions the dominant ones were hiding.  two_pass re-orthonormalises Q
 // back into X (CholQR2).
-void orth(ipeps_state* st, double* X, double* Q, const GemmGroup& gram1, const GemmGroup& mul1,
+void orth(const Ex& x, double* X, double* Q, const GemmGroup& gram1, const GemmGroup& mul1,
           const GemmGroup& gram2, const GemmGroup& mul2, bool two_pass,
           const GemmGroup* proj1 = nullptr, const GemmGroup* proj2 = nullptr) {
+    ipeps_state* st = x.st;
     const bool refill = proj1 && proj2;
     const int n = st->n, k = st->k;
     hipStream_t s = st->stream;
     // chol_inverse scales the Gram to unit diagonal itself (equivalent to
     // normalising the columns first)
-    run(st, gram1);
-    chol_inverse(s, 2, k, st->Gm, st->Ri, kCholDrop, refill ? st->dead_dev : nullptr);
-    run(st, mul1);
+    run(x, gram1);
+    chol_inverse(s, 2, k, st->Gm, st->Ri, kCholDrop, refill ? st->dead_dev : nullptr, 0.0, x.jm);
+    run(x, mul1);
     if (refill) {
-        const uint64_t seed = st->cfg.seed * 0x9E3779B97F4A7C15ull + 0x632BE59BD9B4E019ull * ++st->orth_calls;
-        dead_fill(s, 2, n, k, st->dead_dev, seed, st->Rb);
-        for (int pass = 0; pass < 2; ++pass) {
-            run(st, *proj1);  // Gm = Q^T Rb
-            run(st, *proj2);  // Rb -= Q Gm
+        // each job's own random stream (its seed, its call counter); the
+        // launches return at once for a job that dropped nothing
+        for (ipeps_state* j : x.jobs) {
+            const uint64_t seed = j->cfg.seed * 0x9E3779B97F4A7C15ull + 0x632BE59BD9B4E019ull * ++j->orth_calls;
+            dead_fill(s, 2, n, k, j->dead_dev, seed, j->Rb);
         }
-        add_gated(s, 2, (long)n * k, st->dead_dev + 2 * k, st->Rb, Q);
+        for (int pass = 0; pass < 2; ++pass) {
+            run(x, *proj1);  // Gm = Q^T Rb
+            run(x, *proj2);  // Rb -= Q Gm
+        }
+        for (int j = 0; j < x.nj(); ++j)
+            add_gated(s, 2, (long)n * k, x.jobs[j]->dead_dev + 2 * k, x.jobs[j]->Rb, x.at(Q, j));
     }
     if (!two_pass) return;
-    run(st, gram2);
+    run(x, gram2);
     // second pass: when the first left the columns orthonormal to 1e-13 the
     // factorisation would change them by no more than that; it is skipped
-    chol_inverse(s, 2, k, st->Gm, st->Ri, kCholDrop, nullptr, 1e-13);
-    run(st, mul2);
+    chol_inverse(s, 2, k, st->Gm, st->Ri, kCholDrop, nullptr, 1e-13, x.jm);
+    run(x, mul2);
 }
 
 // Relative cutoff below which singular values of a cut matrix count as zero:
@@ -929,33 +999,36 @@ double proj_cutoff(const ipeps_state* st) { return st->dtype == IPEPS_DTYPE_FP64
 // Yw = N Qz and Zw = N^T Qw for the two cuts: with the formed N64 (FP64), or
 // through the enlarged corners (products in dtype; FP64 blocks converted at
 // both ends in FP32 mode).
-void apply_n(ipeps_state* st, int si) {
-    if (!st->factored) return run(st, st->svd.NVf);
+void apply_n(const Ex& x, int si) {
+    ipeps_state* st = x.st;
+    if (!st->factored) return run(x, st->svd.NVf);
     const long nk = (long)st->n * st->k;
     const bool f64 = st->dtype == IPEPS_DTYPE_FP64;
-    if (!f64) from_fp64_blocks(st->stream, st->dtype, st->Qz, st->Ch[2], 2, st->n, st->k, false);
-    for (const GemmGroup& g : st->svd.NV[si]) run(st, g);
-    if (!f64) to_fp64(st->stream, st->dtype, st->Ch[1], st->Yw, 2 * nk);
+    if (!f64) from_fp64_blocks(st->stream, st->dtype, st->Qz, st->Ch[2], 2, st->n, st->k, false, x.jm);
+    for (const GemmGroup& g : st->svd.NV[si]) run(x, g);
+    if (!f64) to_fp64(st->stream, st->dtype, st->Ch[1], st->Yw, 2 * nk, x.jm);
 }
 
-void apply_nt(ipeps_state* st, int si) {
-    if (!st->factored) return run(st, st->svd.NtQf);
+void apply_nt(const Ex& x, int si) {
+    ipeps_state* st = x.st;
+    if (!st->factored) return run(x, st->svd.NtQf);
     const long nk = (long)st->n * st->k;
-    from_fp64_blocks(st->stream, st->dtype, st->Qw, st->Qt, 2, st->n, st->k, true);
-    for (const GemmGroup& g : st->svd.NtQ[si]) run(st, g);
-    if (st->dtype != IPEPS_DTYPE_FP64) to_fp64(st->stream, st->dtype, st->Ch[2], st->Zw, 2 * nk);
+    from_fp64_blocks(st->stream, st->dtype, st->Qw, st->Qt, 2, st->n, st->k, true, x.jm);
+    for (const GemmGroup& g : st->svd.NtQ[si]) run(x, g);
+    if (st->dtype != IPEPS_DTYPE_FP64) to_fp64(st->stream, st->dtype, st->Ch[2], st->Zw, 2 * nk, x.jm);
 }
 
 // Truncated SVD of the two cut matrices (formed in N64, or applied through
 // the enlarged corners in E); fills Us, Vs and g_dev.
-void projector_svd(ipeps_state* st, int slot) {
+void projector_svd(const Ex& x, int slot) {
+    ipeps_state* st = x.st;
     const int n = st->n, k = st->k, chi = st->chi;
     hipStream_t s = st->stream;
+    const JobMap& jm = x.jm;
     if (n <= kDirectMax) {
-        jacobi_svd_real(s, 2, n, n, st->N64, n, (long)n * n, st->sig, st->Uo, st->Vo, st->jwork);
+        jacobi_svd_real(s, 2, n, n, st->N64, n, (long)n * n, st->sig, st->Uo, st->Vo, st->jwork, 1e-14, jm);
         projector_factors(s, st->dtype, 2, n, n, chi, proj_cutoff(st), st->Uo, st->Vo, st->sig,
-                          (long)n * n, st->Us,
-                          st->Vs, (long)n * chi, st->g_dev);
+                          (long)n * n, st->Us, st->Vs, (long)n * chi, st->g_dev, jm);
         return;
     }
     const long nk = (long)n * k;
@@ -963,12 +1036,12 @@ void projector_svd(ipeps_state* st, int slot) {
     const bool warm = st->warm_valid[2 * slot];
     // the current right block V lives in Qz (orthonormal after orth)
     if (warm) {
-        HIP_CHECK(hipMemcpyAsync(st->Qz, st->warm + 2 * slot * nk, 2 * nk * sizeof(double),
-                                 hipMemcpyDeviceToDevice, s));
+        copy_jobs(s, st->Qz, st->warm + 2 * slot * nk, 2 * nk * sizeof(double), jm);
     } else {
-        random_block(s, 2, n, k, st->cfg.seed * 1315423911ull + (uint64_t)slot + 1, st->Zw);
-        orth(st, st->Zw, st->Qz, P.gramZ, P.QfromZ, P.gramQz, P.ZfromQz, true);
-        HIP_CHECK(hipMemcpyAsync(st->Qz, st->Zw, 2 * nk * sizeof(double), hipMemcpyDeviceToDevice, s));
+        for (ipeps_state* j : x.jobs)
+            random_block(s, 2, n, k, j->cfg.seed * 1315423911ull + (uint64_t)slot + 1, j->Zw);
+        orth(x, st->Zw, st->Qz, P.gramZ, P.QfromZ, P.gramQz, P.ZfromQz, true);
+        copy_jobs(s, st->Qz, st->Zw, 2 * nk * sizeof(double), jm);
     }
     int iters = warm ? (st->dtype == IPEPS_DTYPE_FP64 ? kWarmIters : kWarmItersLow) : kColdIters;
     if (warm) iters += st->extra_warm_iters;
@@ -978,38 +1051,35 @@ void projector_svd(ipeps_state* st, int slot) {
         // dropped here is zero in V, hence dead in the next left block and
         // restarted there.  Zero columns of the final V only add zero Ritz
         // values.
-        apply_n(st, slot);  // Yw = N V
-        orth(st, st->Yw, st->Qw, P.gramY, P.QfromY, P.gramQ, P.YfromQ, false, &P.projQw1,
-             &P.projQw2);
-        apply_nt(st, slot);  // Zw = N^T Qw
-        orth(st, st->Zw, st->Qz, P.gramZ, P.QfromZ, P.gramQz, P.ZfromQz, false);
+        apply_n(x, slot);  // Yw = N V
+        orth(x, st->Yw, st->Qw, P.gramY, P.QfromY, P.gramQ, P.YfromQ, false, &P.projQw1, &P.projQw2);
+        apply_nt(x, slot);  // Zw = N^T Qw
+        orth(x, st->Zw, st->Qz, P.gramZ, P.QfromZ, P.gramQz, P.ZfromQz, false);
     }
     // Rayleigh-Ritz on span(N V) x span(V)
-    apply_n(st, slot);
-    HIP_CHECK(hipMemcpyAsync(st->Zw, st->Yw, 2 * nk * sizeof(double), hipMemcpyDeviceToDevice, s));
-    orth(st, st->Yw, st->Qw, P.gramY, P.QfromY, P.gramQ, P.YfromQ, true);
-    run(st, P.Cs);  // Cs = (Q^T N V)^T
+    apply_n(x, slot);
+    copy_jobs(s, st->Zw, st->Yw, 2 * nk * sizeof(double), jm);
+    orth(x, st->Yw, st->Qw, P.gramY, P.QfromY, P.gramQ, P.YfromQ, true);
+    run(x, P.Cs);  // Cs = (Q^T N V)^T
     // Rayleigh-Ritz SVD.  Columns are left unrotated only below 1e-14 |Cs|_F,
     // far under the projector cutoff: a kept direction that was never rotated
     // against the dominant ones would break P_up P_low = 1.  (Taking the right
     // vectors as Cs^T U S^-1 instead of accumulating them halves the Jacobi
     // traffic but moved the FP32 imbalance by 2e-4 at D=6, chi=72; not used.)
-    jacobi_svd_real(s, 2, k, k, st->Cs, k, (long)k * k, st->sig, st->Uc, st->Vc, st->jwork, 1e-14);
-    run(st, P.Uo);
-    run(st, P.Vo);
-    HIP_CHECK(hipMemcpyAsync(st->warm + 2 * slot * nk, st->Vo, 2 * nk * sizeof(double),
-                             hipMemcpyDeviceToDevice, s));
-    st->warm_valid[2 * slot] = st->warm_valid[2 * slot + 1] = true;
+    jacobi_svd_real(s, 2, k, k, st->Cs, k, (long)k * k, st->sig, st->Uc, st->Vc, st->jwork, 1e-14, jm);
+    run(x, P.Uo);
+    run(x, P.Vo);
+    copy_jobs(s, st->warm + 2 * slot * nk, st->Vo, 2 * nk * sizeof(double), jm);
+    for (ipeps_state* j : x.jobs) j->warm_valid[2 * slot] = j->warm_valid[2 * slot + 1] = true;
     if (st->factored) {
         // Uc S^-1/2 truncated (k x chi; its Us output is overwritten below),
         // then P_low = T2 (Uc S^-1/2)
         projector_factors(s, st->dtype, 2, k, k, chi, proj_cutoff(st), st->Uc, st->Uc, st->sig,
-                          (long)k * k, st->Us, st->VsK, (long)k * chi, st->g_dev);
-        run(st, P.PlowT2);
+                          (long)k * k, st->Us, st->VsK, (long)k * chi, st->g_dev, jm);
+        run(x, P.PlowT2);
     }
-    projector_factors(s, st->dtype, 2, n, k, chi, proj_cutoff(st), st->Uo, st->Vo, st->sig, nk,
-                      st->Us, st->Vs,
-                      (long)n * chi, st->g_dev);
+    projector_factors(s, st->dtype, 2, n, k, chi, proj_cutoff(st), st->Uo, st->Vo, st->sig, nk, st->Us,
+                      st->Vs, (long)n * chi, st->g_dev, jm);
 }
 
 void readout_enqueue(ipeps_state* st, hipStream_t s, bool snap);
@@ -1017,10 +1087,11 @@ void readout_enqueue(ipeps_state* st, hipStream_t s, bool snap);
 // pinned host slots of the asynchronous readout (host_buf holds 65536)
 constexpr int kAsyncHost = 1024;
 
-// Enqueue the deferred corner spectra on the spectra stream, after the FP64
-// snapshot of the corners and, if given, after event `after` of the main
-// stream.
-void launch_deferred_spectra(ipeps_state* st, hipEvent_t after) {
+// Enqueue the deferred corner spectra (of every job) on the lead's spectra
+// stream, after the FP64 snapshot of the corners and, if given, after event
+// `after` of the main stream.
+void launch_deferred_spectra(const Ex& x, hipEvent_t after) {
+    ipeps_state* st = x.st;
     if (!st->spec_deferred) return;
     const int chi = st->chi;
     hipStream_t ss = st->spec_stream;
@@ -1030,21 +1101,21 @@ void launch_deferred_spectra(ipeps_state* st, hipEvent_t after) {
     // ~1e-7 rounding of FP32 corners: columns below 1e-10 (FP64) or 1e-8
     // (FP32) of |C|_F need no rotation
     jacobi_svd_real(ss, 16, chi, chi, st->C64, chi, (long)chi * chi, st->csig, nullptr, nullptr,
-                    st->jwork_c, st->dtype == IPEPS_DTYPE_FP64 ? 1e-10 : 1e-8);
+                    st->jwork_c, st->dtype == IPEPS_DTYPE_FP64 ? 1e-10 : 1e-8, x.jm);
     // an asynchronous readout may still have to copy the previous Delta
     HIP_CHECK(hipStreamWaitEvent(ss, st->ev_ro_done, 0));
     spectra_delta(ss, 16, chi, st->csig, st->spectra, st->spec_prev, st->dev_scalars,
-                  st->spec_first ? 1 : 0);
+                  st->spec_first ? 1 : 0, x.jm);
     HIP_CHECK(hipEventRecord(st->ev_spec_done, ss));
-    st->spec_deferred = false;
+    for (ipeps_state* j : x.jobs) j->spec_deferred = false;
 }
 
 // Enqueue a deferred asynchronous readout on ro_stream, after the snapshot
 // and, if given, after event `after` of the main stream (the spectra of its
-// environment first: the readout reports their Delta).
+// environment first: the readout reports their Delta).  One job only.
 void launch_deferred_readout(ipeps_state* st, hipEvent_t after) {
     if (!st->ro_deferred) return;
-    launch_deferred_spectra(st, after);
+    launch_deferred_spectra(solo(st), after);
     hipStream_t rs = st->ro_stream;
     HIP_CHECK(hipStreamWaitEvent(rs, st->ev_ro_snap, 0));
     if (after) HIP_CHECK(hipStreamWaitEvent(rs, after, 0));
@@ -1061,56 +1132,57 @@ void launch_deferred_readout(ipeps_state* st, hipEvent_t after) {
     st->ro_deferred = false;
 }
 
-void column_step(ipeps_state* st, int si) {
+void column_step(const Ex& x, int si) {
+    ipeps_state* st = x.st;
     const ColumnStep& cs = st->steps[si];
     const int q = st->q, chi = st->chi, n = st->n;
     const long n2 = (long)n * n;
     hipStream_t s = st->stream;
     const bool warm = si == 0 && st->corners_warm;
-    run(st, warm ? cs.s1w : cs.s1);
-    run(st, warm ? cs.s2w : cs.s2);
-    run(st, warm ? cs.s3w : cs.s3);
+    run(x, warm ? cs.s1w : cs.s1);
+    run(x, warm ? cs.s2w : cs.s2);
+    run(x, warm ? cs.s3w : cs.s3);
     if (si % 2 == 0) {
         // the next column step's UR / DR corners, on the aux stream once the
         // earlier steps (which wrote the tensors they read) are done
         const ColumnStep& nx = st->steps[si + 1];
         HIP_CHECK(hipEventRecord(st->ev_aux_go, s));
         HIP_CHECK(hipStreamWaitEvent(st->aux_stream, st->ev_aux_go, 0));
-        run_on(st, st->aux_stream, nx.aux_s1);
-        run_on(st, st->aux_stream, nx.aux_s2);
-        run_on(st, st->aux_stream, nx.aux_s3);
+        run_on(x, st->aux_stream, nx.aux_s1);
+        run_on(x, st->aux_stream, nx.aux_s2);
+        run_on(x, st->aux_stream, nx.aux_s3);
         HIP_CHECK(hipEventRecord(st->ev_aux_done, st->aux_stream));
         // the spectra of the previous environment and a readout started
         // after the previous CTMRG run beside this step's projector SVD
         if (si == 0) {
-            launch_deferred_spectra(st, st->ev_aux_go);
-            launch_deferred_readout(st, st->ev_aux_go);
+            launch_deferred_spectra(x, st->ev_aux_go);
+            if (!x.batched()) launch_deferred_readout(st, st->ev_aux_go);
         }
     } else {
         HIP_CHECK(hipStreamWaitEvent(s, st->ev_aux_done, 0));
     }
     if (!st->factored) {
-        run(st, cs.half);
-        run(st, cs.nprod);
-        if (st->dtype != IPEPS_DTYPE_FP64) to_fp64(s, st->dtype, st->Nd, st->N64, 2 * n2);
+        run(x, cs.half);
+        run(x, cs.nprod);
+        if (st->dtype != IPEPS_DTYPE_FP64) to_fp64(s, st->dtype, st->Nd, st->N64, 2 * n2, x.jm);
     }
-    projector_svd(st, si);
-    run(st, cs.proj);
-    run(st, cs.proj2);
+    projector_svd(x, si);
+    run(x, cs.proj);
+    run(x, cs.proj2);
+    const size_t e = st->esz;
     for (int Y = 0; Y < 2; ++Y) {
-        const size_t e = st->esz;
         // PupP[c'][D][t4p] <- Pup[c'][t4p][D];  PlowP[q3][c4n][c'] <- Plow[c4n][q3][c']
         permute3(s, st->dtype, 1, chi, chi, q, off(st->Pup, Y * (long)n * chi, e),
-                 off(st->PupP, Y * (long)n * chi, e));
+                 off(st->PupP, Y * (long)n * chi, e), x.jm);
         permute3(s, st->dtype, 0, chi, q, chi, off(st->Plow, Y * (long)n * chi, e),
-                 off(st->PlowP, Y * (long)n * chi, e));
+                 off(st->PlowP, Y * (long)n * chi, e), x.jm);
     }
     for (int Y = 0; Y < 2; ++Y)  // T4p[Y][t][c][v] <- T4[t][v][c]
-        permute3(s, st->dtype, 1, chi, q, chi, cs.t4[Y], off(st->T4p, Y * (long)chi * q * chi, st->esz));
-    run(st, cs.w1);
-    run(st, cs.w2);
-    run(st, cs.fin);
-    normalize_tensors(s, st->dtype, st->d_norms + cs.norm_first, 6, st->norm_ws);
+        permute3(s, st->dtype, 1, chi, q, chi, cs.t4[Y], off(st->T4p, Y * (long)chi * q * chi, e), x.jm);
+    run(x, cs.w1);
+    run(x, cs.w2);
+    run(x, cs.fin);
+    normalize_items(x, s, st->dtype, cs.norm_first, 6, st->norm_ws);
 }
 
 // Snapshot the 16 corners (FP64) on the main stream; their spectra and the
@@ -1118,21 +1190,100 @@ void column_step(ipeps_state* st, int si) {
 // readout: the next CTMRG enqueues them after its first enlarged corners (so
 // they do not share the GPU with that launch), or any reader of spectra /
 // Delta does (wait_spectra).
-void corner_spectra_update(ipeps_state* st, bool first) {
+void corner_spectra_update(const Ex& x, bool first) {
+    ipeps_state* st = x.st;
     const int chi = st->chi;
     hipStream_t s = st->stream;
-    launch_deferred_spectra(st, nullptr);  // an earlier update nobody launched yet
+    launch_deferred_spectra(x, nullptr);  // an earlier update nobody launched yet
     HIP_CHECK(hipStreamWaitEvent(s, st->ev_spec_done, 0));  // C64 free again
-    to_fp64(s, st->dtype, st->Cenv, st->C64, 16L * chi * chi);
+    to_fp64(s, st->dtype, st->Cenv, st->C64, 16L * chi * chi, x.jm);
     HIP_CHECK(hipEventRecord(st->ev_c64_ready, s));
-    st->spec_deferred = true;
-    st->spec_first = first;
-    st->spectra_valid = true;
+    for (ipeps_state* j : x.jobs) {
+        j->spec_deferred = true;
+        j->spec_first = first;
+        j->spectra_valid = true;
+    }
 }
 
-void wait_spectra(ipeps_state* st) {
-    launch_deferred_spectra(st, nullptr);
-    HIP_CHECK(hipStreamWaitEvent(st->stream, st->ev_spec_done, 0));
+void wait_spectra(const Ex& x) {
+    launch_deferred_spectra(x, nullptr);
+    HIP_CHECK(hipStreamWaitEvent(x.st->stream, x.st->ev_spec_done, 0));
+}
+
+// n_steps Trotter steps of every job on the lead's simple-update stream (one
+// launch per layer for all jobs), then each job's double layers for the next
+// CTMRG, built there ahead of it.
+void trotter_steps(const Ex& x, int n_steps) {
+    ipeps_state* L = x.st;
+    hipStream_t ss = L->su_stream;
+    HIP_CHECK(hipStreamWaitEvent(ss, L->ev_gamma_free, 0));
+    for (int t = 0; t < n_steps; ++t) {
+        for (int l = 0; l < 7; ++l)
+            su_layer(ss, L->D, L->d, L->layers[l], L->gam, L->lam, L->eps, L->gates, L->su_scratch, x.jm);
+        for (ipeps_state* j : x.jobs) j->step_count++;
+    }
+    if (n_steps > 0) {
+        // build the next CTMRG's double layers here, hidden behind the
+        // current CTMRG; the *_pre buffers were last read by main-stream
+        // work that precedes ev_gamma_free
+        for (ipeps_state* j : x.jobs) {
+            build_double_layers(j, ss, j->A_pre, j->a_base_pre, j->eps_snap_pre, j->norm_a_pre_first,
+                                j->norm_ws_su);
+            frame_layouts(ss, j->q, j->dtype, j->a_base_pre, j->d_a_lu_pre, j->d_a_dl_pre);
+            j->pre_valid = true;
+            j->pre_step = j->step_count;
+        }
+    }
+    HIP_CHECK(hipEventRecord(L->ev_su_done, ss));
+}
+
+// CTMRG iterations of every job (section Readout; appendix).  tol <= 0:
+// exactly max_iter; else until the lead's Delta < tol (one job only).
+// want_delta: the lead's last Delta is read back.
+void ctmrg_iterations(const Ex& x, double tol, int max_iter, bool cold_start, bool want_delta, int* it_done,
+                      double* dl) {
+    ipeps_state* L = x.st;
+    prepare_double_layers(x);
+    if (cold_start || !L->have_env) {
+        for (ipeps_state* j : x.jobs)
+            init_environment(L->stream, j->D, j->chi, j->dtype, j->a_base, j->Cenv, j->Tenv);
+        normalize_items(x, L->stream, L->dtype, L->norm_env_first, 32, L->norm_ws);
+        for (ipeps_state* j : x.jobs) {
+            for (bool& w : j->warm_valid) w = false;
+            j->have_env = true;
+        }
+        corner_spectra_update(x, true);
+    } else if (!L->spectra_valid) {
+        corner_spectra_update(x, true);
+    }
+    // Converging to tol: once the spectra move by less than 1e-5 (1e-7) per
+    // iteration, the warm-started projector subspaces get two (four) more
+    // power iterations, so that their error (which decays like
+    // (s_{k+1}/s_chi)^(2q) per iteration) stays below the change being
+    // resolved; a fixed iteration count (tol <= 0) keeps the plain schedule.
+    L->extra_warm_iters = 0;
+    L->corners_warm = false;
+    for (int it = 0; it < max_iter; ++it) {
+        for (int si = 0; si < 8; ++si) column_step(x, si);
+        L->corners_warm = true;  // the next left move may reuse the down move's corners
+        corner_spectra_update(x, false);
+        *it_done = it + 1;
+        if (tol > 0 || (want_delta && it + 1 == max_iter)) {
+            wait_spectra(x);
+            HIP_CHECK(hipMemcpyAsync(L->host_buf, L->dev_scalars, sizeof(double), hipMemcpyDeviceToHost, L->stream));
+            HIP_CHECK(hipStreamSynchronize(L->stream));
+            *dl = L->host_buf[0];
+            IPEPS_REQUIRE(!std::isnan(*dl), IPEPS_ENUMERIC, "NaN in the environment");
+            if (tol > 0 && *dl < tol) break;
+            if (tol > 0) L->extra_warm_iters = *dl < 1e-7 ? 4 : (*dl < 1e-5 ? 2 : 0);
+        }
+    }
+    for (ipeps_state* j : x.jobs) {
+        j->extra_warm_iters = 0;
+        j->corners_warm = false;
+        j->last_iters = *it_done;
+        j->last_delta = *dl;
+    }
 }
 
 void check_poison(ipeps_state* st) {
@@ -1184,7 +1335,7 @@ void ipeps_config_default(ipeps_config* c) {
     c->seed = 1;
 }
 
-static void fill_dims(ipeps_state* st, const ipeps_config* cfg) {
+static void fill_dims_internal(ipeps_state* st, const ipeps_config* cfg) {
     st->cfg = *cfg;
     st->D = cfg->D;
     st->d = 2 * cfg->d_A;
@@ -1205,7 +1356,7 @@ size_t ipeps_footprint_bytes(const ipeps_config* cfg) {
     try {
         validate(cfg);
         ipeps_state* st = new ipeps_state();
-        fill_dims(st, cfg);
+        fill_dims_internal(st, cfg);
         st->mem.dry = true;
         allocate(st);
         size_t tot = st->mem.total;
@@ -1227,7 +1378,7 @@ int ipeps_init(const ipeps_config* cfg, void* hip_stream, ipeps_alloc_fn alloc, 
         if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1)
             throw status_error(IPEPS_EDEVICE, "no HIP device");
         st = new ipeps_state();
-        fill_dims(st, cfg);
+        fill_dims_internal(st, cfg);
         st->stream = (hipStream_t)hip_stream;
         st->mem.alloc = alloc;
         st->mem.free_fn = free_fn;
@@ -1331,26 +1482,9 @@ int ipeps_trotter_step(ipeps_state* st, int n_steps, double* trunc_err_out) {
     if (!st || n_steps < 0) return IPEPS_EINVAL;
     return wrap(st, [&] {
         check_poison(st);
-        hipStream_t ss = st->su_stream;
-        HIP_CHECK(hipStreamWaitEvent(ss, st->ev_gamma_free, 0));
-        for (int t = 0; t < n_steps; ++t) {
-            for (int l = 0; l < 7; ++l)
-                su_layer(ss, st->D, st->d, st->layers[l], st->gam, st->lam, st->eps, st->gates,
-                         st->su_scratch);
-            st->step_count++;
-        }
-        if (n_steps > 0) {
-            // build the next CTMRG's double layers here, hidden behind the
-            // current CTMRG; the *_pre buffers were last read by main-stream
-            // work that precedes ev_gamma_free
-            build_double_layers(st, ss, st->A_pre, st->a_base_pre, st->eps_snap_pre, st->norm_a_pre_first,
-                                st->norm_ws_su);
-            frame_layouts(ss, st->q, st->dtype, st->a_base_pre, st->d_a_lu_pre, st->d_a_dl_pre);
-            st->pre_valid = true;
-            st->pre_step = st->step_count;
-        }
-        HIP_CHECK(hipEventRecord(st->ev_su_done, ss));
+        trotter_steps(solo(st), n_steps);
         if (trunc_err_out) {
+            hipStream_t ss = st->su_stream;
             HIP_CHECK(hipMemcpyAsync(st->host_buf, st->eps, 4 * sizeof(double), hipMemcpyDeviceToHost, ss));
             HIP_CHECK(hipMemcpyAsync(st->host_buf + 4, st->lam, 8 * st->D * sizeof(double), hipMemcpyDeviceToHost, ss));
             HIP_CHECK(hipStreamSynchronize(ss));
@@ -1367,45 +1501,7 @@ int ctmrg_converge(ipeps_state* st, double tol, int max_iter, int cold_start, in
     double dl = INFINITY;
     int rc = wrap(st, [&] {
         check_poison(st);
-        prepare_double_layers(st);
-        bool first = false;
-        if (cold_start || !st->have_env) {
-            init_environment(st->stream, st->D, st->chi, st->dtype, st->a_base, st->Cenv, st->Tenv);
-            normalize_tensors(st->stream, st->dtype, st->d_norms + st->norm_env_first, 32, st->norm_ws);
-            for (bool& w : st->warm_valid) w = false;
-            st->have_env = true;
-            corner_spectra_update(st, true);
-            first = true;
-        } else if (!st->spectra_valid) {
-            corner_spectra_update(st, true);
-        }
-        (void)first;
-        // Converging to tol: once the spectra move by less than 1e-5 (1e-7) per
-        // iteration, the warm-started projector subspaces get two (four) more
-        // power iterations, so that their error (which decays like
-        // (s_{k+1}/s_chi)^(2q) per iteration) stays below the change being
-        // resolved; a fixed iteration count (tol <= 0) keeps the plain schedule.
-        st->extra_warm_iters = 0;
-        st->corners_warm = false;
-        for (int it = 0; it < max_iter; ++it) {
-            for (int si = 0; si < 8; ++si) column_step(st, si);
-            st->corners_warm = true;  // the next left move may reuse the down move's corners
-            corner_spectra_update(st, false);
-            it_done = it + 1;
-            if (tol > 0 || (delta && it + 1 == max_iter)) {
-                wait_spectra(st);
-                HIP_CHECK(hipMemcpyAsync(st->host_buf, st->dev_scalars, sizeof(double), hipMemcpyDeviceToHost, st->stream));
-                HIP_CHECK(hipStreamSynchronize(st->stream));
-                dl = st->host_buf[0];
-                IPEPS_REQUIRE(!std::isnan(dl), IPEPS_ENUMERIC, "NaN in the environment");
-                if (tol > 0 && dl < tol) break;
-                if (tol > 0) st->extra_warm_iters = dl < 1e-7 ? 4 : (dl < 1e-5 ? 2 : 0);
-            }
-        }
-        st->extra_warm_iters = 0;
-        st->corners_warm = false;
-        st->last_iters = it_done;
-        st->last_delta = dl;
+        ctmrg_iterations(solo(st), tol, max_iter, cold_start != 0, delta != nullptr, &it_done, &dl);
         if (tol > 0 && !(dl < tol)) throw status_error(IPEPS_ENOTCONV, "CTMRG not converged");
     });
     if (iters) *iters = it_done;
@@ -1424,15 +1520,16 @@ void readout_enqueue(ipeps_state* st, hipStream_t s, bool snap) {
     const size_t e = st->esz;
     void* X2p = snap ? st->X2pr : st->X2p;
     void* E = snap ? st->Er : st->E;
-    run_on(st, s, snap ? st->read1r : st->read1);
-    run_on(st, s, snap ? st->read2r : st->read2);
-    run_on(st, s, snap ? st->read3r : st->read3);
+    const Ex x = solo(st);
+    run_on(x, s, snap ? st->read1r : st->read1);
+    run_on(x, s, snap ? st->read2r : st->read2);
+    run_on(x, s, snap ? st->read3r : st->read3);
     for (int site = 0; site < 4; ++site) {
         // Lp[q^2][t4p][t2p] <- L'[t4p][q^2][t2p];  Rp[t4p][t2p][q^2] <- R'[t2p][q^2][t4p]
         permute3(s, st->dtype, 0, chi, q * q, chi, off(X2p, site * n2, e), off(E, site * n2, e));
         permute3(s, st->dtype, 2, chi, q * q, chi, off(X2p, (4 + site) * n2, e), off(E, (4 + site) * n2, e));
     }
-    run_on(st, s, snap ? st->read4r : st->read4);
+    run_on(x, s, snap ? st->read4r : st->read4);
     double* E64 = snap ? st->E64_r : st->E64;
     to_fp64(s, st->dtype, snap ? st->Eout_r : st->Eout, E64, 4 * q4);
     readout(s, st->D, st->d, st->cfg.d_A, E64, snap ? st->Asnap : st->A, snap ? st->rho_T_r : st->rho_T,
@@ -1469,7 +1566,7 @@ int ipeps_observe(ipeps_state* st, ipeps_obs* out) {
         readout_enqueue(st, s, false);
         HIP_CHECK(hipMemcpyAsync(st->host_buf, st->obs_dev, 16 * sizeof(double), hipMemcpyDeviceToHost, s));
         HIP_CHECK(hipMemcpyAsync(st->host_buf + 16, st->eps_snap, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
-        wait_spectra(st);
+        wait_spectra(solo(st));
         HIP_CHECK(hipMemcpyAsync(st->host_buf + 20, st->dev_scalars, sizeof(double), hipMemcpyDeviceToHost, s));
         HIP_CHECK(hipStreamSynchronize(s));
         decode_obs(st->host_buf, st->ctm_step * st->cfg.dt, st->last_iters, out);
@@ -1517,8 +1614,8 @@ int ipeps_corner_spectra(ipeps_state* st, double* out) {
     if (!st || !out) return IPEPS_EINVAL;
     return wrap(st, [&] {
         IPEPS_REQUIRE(st->have_env, IPEPS_EINVAL, "no environment");
-        if (!st->spectra_valid) corner_spectra_update(st, true);
-        wait_spectra(st);
+        if (!st->spectra_valid) corner_spectra_update(solo(st), true);
+        wait_spectra(solo(st));
         HIP_CHECK(hipMemcpyAsync(out, st->spectra, 16L * st->chi * sizeof(double), hipMemcpyDeviceToHost, st->stream));
         HIP_CHECK(hipStreamSynchronize(st->stream));
     });
@@ -1602,6 +1699,311 @@ const char* ipeps_strerror(int code) {
         case IPEPS_ETOOBIG: return "request exceeds the fixed scratch of a no-allocation entry point";
         default: return "unknown error";
     }
+}
+
+}  // extern "C"
+
+// ==================================================================== slabs and batches
+namespace {
+
+bool same_layout(const ipeps_config& a, const ipeps_config& b) {
+    return a.D == b.D && a.chi == b.chi && a.d_A == b.d_A && a.dtype == b.dtype && a.flags == b.flags;
+}
+
+// Bytes one state of this layout draws from its allocator (every request
+// rounded to 256 bytes, as DevMem::get does).
+size_t layout_bytes(const ipeps_config* cfg) {
+    ipeps_state* st = new ipeps_state();
+    fill_dims_internal(st, cfg);
+    st->mem.dry = true;
+    allocate(st);
+    const size_t tot = st->mem.total;
+    delete st;
+    return tot;
+}
+
+}  // namespace
+
+struct ipeps_slab {
+    std::mutex mu;
+    ipeps_config layout;
+    char* base = nullptr;
+    size_t region = 0;
+    int slots = 0;
+    struct Cursor {
+        ipeps_slab* slab;
+        int slot;
+        size_t used;
+    };
+    std::vector<Cursor> cur;
+    std::vector<char> busy;
+};
+
+namespace {
+void* slab_alloc(size_t bytes, void* stream, void* ctx) {
+    (void)stream;
+    auto* c = (ipeps_slab::Cursor*)ctx;
+    ipeps_slab* sl = c->slab;
+    if (c->used + bytes > sl->region) return nullptr;
+    void* p = sl->base + (size_t)c->slot * sl->region + c->used;
+    c->used += bytes;
+    return p;
+}
+void slab_free(void* p, void* stream, void* ctx) {
+    (void)stream;
+    auto* c = (ipeps_slab::Cursor*)ctx;
+    ipeps_slab* sl = c->slab;
+    if (p == sl->base + (size_t)c->slot * sl->region) {  // the state's first allocation
+        std::lock_guard<std::mutex> lk(sl->mu);
+        sl->busy[c->slot] = 0;
+        c->used = 0;
+    }
+}
+}  // namespace
+
+struct ipeps_batch {
+    Ex x;
+    std::vector<hipEvent_t> ev;  // cross-stream ordering with the jobs' own streams
+};
+
+namespace {
+// jobs' own streams -> lead's streams (at batch creation), or back (at destruction)
+void order_streams(ipeps_batch* b, bool into_lead) {
+    ipeps_state* L = b->x.st;
+    hipStream_t lead[3] = {L->stream, L->su_stream, L->spec_stream};
+    int e = 0;
+    for (ipeps_state* j : b->x.jobs) {
+        if (j == L) continue;
+        hipStream_t own[3] = {j->stream, j->su_stream, j->spec_stream};
+        for (int a = 0; a < 3; ++a) {
+            hipEvent_t ev = b->ev[e++];
+            if (into_lead) {
+                HIP_CHECK(hipEventRecord(ev, own[a]));
+                for (hipStream_t t : lead) HIP_CHECK(hipStreamWaitEvent(t, ev, 0));
+            } else {
+                HIP_CHECK(hipEventRecord(ev, lead[a]));
+                for (hipStream_t t : own) HIP_CHECK(hipStreamWaitEvent(t, ev, 0));
+            }
+        }
+    }
+}
+}  // namespace
+
+extern "C" {
+
+int ipeps_slab_create(const ipeps_config* cfg, int slots, ipeps_slab** out) {
+    if (!out || slots < 1) return IPEPS_EINVAL;
+    *out = nullptr;
+    ipeps_slab* sl = nullptr;
+    int rc = wrap(nullptr, [&] {
+        validate(cfg);
+        sl = new ipeps_slab();
+        sl->layout = *cfg;
+        sl->region = (layout_bytes(cfg) + 4095) & ~(size_t)4095;
+        sl->slots = slots;
+        if (hipMalloc((void**)&sl->base, sl->region * slots) != hipSuccess) {
+            (void)hipGetLastError();
+            sl->base = nullptr;
+            throw status_error(IPEPS_ENOMEM, "slab allocation failed");
+        }
+        sl->cur.resize(slots);
+        sl->busy.assign(slots, 0);
+        for (int i = 0; i < slots; ++i) sl->cur[i] = {sl, i, 0};
+    });
+    if (rc != IPEPS_OK) {
+        delete sl;
+        return rc;
+    }
+    *out = sl;
+    return IPEPS_OK;
+}
+
+size_t ipeps_slab_region_bytes(const ipeps_config* cfg) {
+    try {
+        validate(cfg);
+        return (layout_bytes(cfg) + 4095) & ~(size_t)4095;
+    } catch (...) {
+        return 0;
+    }
+}
+
+int ipeps_slab_init(ipeps_slab* sl, int slot, const ipeps_config* cfg, void* hip_stream, ipeps_state** out) {
+    if (!sl || !cfg || !out || slot < 0 || slot >= sl->slots) return IPEPS_EINVAL;
+    if (!same_layout(*cfg, sl->layout)) return IPEPS_EINVAL;
+    {
+        std::lock_guard<std::mutex> lk(sl->mu);
+        if (sl->busy[slot]) return IPEPS_EINVAL;
+        sl->busy[slot] = 1;
+        sl->cur[slot].used = 0;
+    }
+    const int rc = ipeps_init(cfg, hip_stream, slab_alloc, slab_free, &sl->cur[slot], out);
+    if (rc != IPEPS_OK) {
+        std::lock_guard<std::mutex> lk(sl->mu);
+        sl->busy[slot] = 0;
+    }
+    return rc;
+}
+
+void ipeps_slab_destroy(ipeps_slab* sl) {
+    if (!sl) return;
+    (void)hipDeviceSynchronize();
+    if (sl->base) (void)hipFree(sl->base);
+    delete sl;
+}
+
+int ipeps_batch_create(ipeps_state* const* states, int n, ipeps_batch** out) {
+    if (!states || !out || n < 1) return IPEPS_EINVAL;
+    *out = nullptr;
+    ipeps_batch* b = nullptr;
+    int rc = wrap(nullptr, [&] {
+        ipeps_state* L = states[0];
+        IPEPS_REQUIRE(L != nullptr, IPEPS_EINVAL, "NULL state");
+        for (int j = 0; j < n; ++j) {
+            ipeps_state* s = states[j];
+            IPEPS_REQUIRE(s != nullptr && !s->poisoned, IPEPS_EINVAL, "NULL or poisoned state");
+            IPEPS_REQUIRE(same_layout(s->cfg, L->cfg), IPEPS_EINVAL, "batch: states of different layouts");
+            IPEPS_REQUIRE(s->mem.ptrs.size() == L->mem.ptrs.size(), IPEPS_EINVAL, "batch: allocation mismatch");
+            const char* b0 = (const char*)s->mem.ptrs[0];
+            const char* l0 = (const char*)L->mem.ptrs[0];
+            for (size_t i = 0; i < s->mem.ptrs.size(); ++i)
+                IPEPS_REQUIRE((const char*)s->mem.ptrs[i] - b0 == (const char*)L->mem.ptrs[i] - l0, IPEPS_EINVAL,
+                              "batch: states not allocated in one layout (use one slab)");
+            IPEPS_REQUIRE(s->have_env == L->have_env && s->spectra_valid == L->spectra_valid &&
+                              !s->ro_pending && !s->spec_deferred == !L->spec_deferred &&
+                              std::equal(s->warm_valid, s->warm_valid + 16, L->warm_valid),
+                          IPEPS_EINVAL, "batch: states at different phases of their schedule");
+            for (int k = 0; k < j; ++k) IPEPS_REQUIRE(states[k] != s, IPEPS_EINVAL, "batch: repeated state");
+        }
+        b = new ipeps_batch();
+        Ex& x = b->x;
+        x.st = L;
+        for (int j = 0; j < n; ++j) {
+            x.jobs.push_back(states[j]);
+            x.hdelta.push_back((long)((const char*)states[j]->mem.ptrs[0] - (const char*)L->mem.ptrs[0]));
+        }
+        if (n > 1) {
+            auto shift = [](const void* p, long d) -> void* { return p ? (void*)((const char*)p + d) : nullptr; };
+            // merged GEMM table: every group of the lead's plan, once per job
+            std::vector<GemmProb> mp;
+            for (const GemmGroup& g : L->groups) {
+                GemmGroup m = g;
+                m.first = (int)mp.size();
+                m.count = g.count * n;
+                m.flops = g.flops * n;
+                for (int j = 0; j < n; ++j)
+                    for (int i = g.first; i < g.first + g.count; ++i) {
+                        GemmProb p = L->probs[i];
+                        p.A = shift(p.A, x.hdelta[j]);
+                        p.B = shift(p.B, x.hdelta[j]);
+                        p.C = shift(p.C, x.hdelta[j]);
+                        p.ws = shift(p.ws, x.hdelta[j]);
+                        p.gate = (const int*)shift(p.gate, x.hdelta[j]);
+                        mp.push_back(p);
+                    }
+                m.tiles = gemm_plan_with(mp.data() + m.first, m.count, g.dtype, g.tile);
+                x.merged[g.first] = m;
+            }
+            // merged normalisations: the environment and every column step
+            std::vector<NormItem> mn;
+            std::vector<std::pair<long, int>> ranges = {{L->norm_env_first, 32}};
+            for (const ColumnStep& cs : L->steps) ranges.push_back({cs.norm_first, 6});
+            for (auto& r : ranges) {
+                x.norm_first[r.first] = (long)mn.size();
+                for (int j = 0; j < n; ++j)
+                    for (int i = 0; i < r.second; ++i) {
+                        NormItem it = L->norms[r.first + i];
+                        it.ptr = shift(it.ptr, x.hdelta[j]);
+                        mn.push_back(it);
+                    }
+            }
+            HIP_CHECK(hipMalloc(&x.d_probs, mp.size() * sizeof(GemmProb)));
+            HIP_CHECK(hipMemcpy(x.d_probs, mp.data(), mp.size() * sizeof(GemmProb), hipMemcpyHostToDevice));
+            HIP_CHECK(hipMalloc(&x.d_norms, mn.size() * sizeof(NormItem)));
+            HIP_CHECK(hipMemcpy(x.d_norms, mn.data(), mn.size() * sizeof(NormItem), hipMemcpyHostToDevice));
+            long* dd = nullptr;
+            HIP_CHECK(hipMalloc(&dd, n * sizeof(long)));
+            HIP_CHECK(hipMemcpy(dd, x.hdelta.data(), n * sizeof(long), hipMemcpyHostToDevice));
+            x.jm.delta = dd;
+            x.jm.njobs = n;
+            HIP_CHECK(hipMalloc(&x.norm_ws, normalize_ws_doubles(32 * n) * sizeof(double)));
+        }
+        b->ev.resize(3 * (n - 1));
+        for (auto& e : b->ev) HIP_CHECK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        order_streams(b, true);
+    });
+    if (rc != IPEPS_OK) {
+        ipeps_batch_destroy(b);
+        return rc;
+    }
+    *out = b;
+    return IPEPS_OK;
+}
+
+void ipeps_batch_destroy(ipeps_batch* b) {
+    if (!b) return;
+    try {
+        if (b->x.st && b->ev.size() == 3 * (b->x.jobs.size() - 1)) order_streams(b, false);
+    } catch (...) {
+    }
+    if (b->x.st) {
+        (void)hipStreamSynchronize(b->x.st->stream);
+        (void)hipStreamSynchronize(b->x.st->su_stream);
+        (void)hipStreamSynchronize(b->x.st->spec_stream);
+    }
+    if (b->x.d_probs) (void)hipFree(b->x.d_probs);
+    if (b->x.d_norms) (void)hipFree(b->x.d_norms);
+    if (b->x.jm.delta) (void)hipFree((void*)b->x.jm.delta);
+    if (b->x.norm_ws) (void)hipFree(b->x.norm_ws);
+    for (auto& e : b->ev)
+        if (e) (void)hipEventDestroy(e);
+    delete b;
+}
+
+int ipeps_batch_trotter_step(ipeps_batch* b, int n_steps) {
+    if (!b || n_steps < 0) return IPEPS_EINVAL;
+    return wrap(b->x.st, [&] {
+        for (ipeps_state* j : b->x.jobs) check_poison(j);
+        trotter_steps(b->x, n_steps);
+    });
+}
+
+int ipeps_batch_ctmrg(ipeps_batch* b, int iters, int cold_start) {
+    if (!b || iters < 1) return IPEPS_EINVAL;
+    return wrap(b->x.st, [&] {
+        for (ipeps_state* j : b->x.jobs) check_poison(j);
+        int it = 0;
+        double dl = INFINITY;
+        ctmrg_iterations(b->x, 0.0, iters, cold_start != 0, false, &it, &dl);
+    });
+}
+
+int ipeps_batch_observe(ipeps_batch* b, ipeps_obs* out) {
+    if (!b || !out) return IPEPS_EINVAL;
+    ipeps_state* L = b->x.st;
+    return wrap(L, [&] {
+        for (ipeps_state* j : b->x.jobs) {
+            check_poison(j);
+            IPEPS_REQUIRE(j->have_env, IPEPS_EINVAL, "no environment: run the CTMRG first");
+        }
+        hipStream_t s = L->stream;
+        wait_spectra(b->x);
+        for (ipeps_state* j : b->x.jobs) {
+            readout_enqueue(j, s, false);
+            HIP_CHECK(hipMemcpyAsync(j->host_buf, j->obs_dev, 16 * sizeof(double), hipMemcpyDeviceToHost, s));
+            HIP_CHECK(hipMemcpyAsync(j->host_buf + 16, j->eps_snap, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
+            HIP_CHECK(hipMemcpyAsync(j->host_buf + 20, j->dev_scalars, sizeof(double), hipMemcpyDeviceToHost, s));
+        }
+        HIP_CHECK(hipStreamSynchronize(s));
+        for (size_t i = 0; i < b->x.jobs.size(); ++i) {
+            ipeps_state* j = b->x.jobs[i];
+            try {
+                decode_obs(j->host_buf, j->ctm_step * j->cfg.dt, j->last_iters, &out[i]);
+            } catch (const status_error& e) {
+                j->poisoned = true;
+                throw;
+            }
+        }
+    });
 }
 
 }  // extern "C"

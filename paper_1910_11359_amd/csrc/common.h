@@ -37,6 +37,23 @@ struct status_error : std::runtime_error {
 
 inline int ceil_div(long a, long b) { return (int)((a + b - 1) / b); }
 
+// Several jobs of one layout in one launch: the jobs' device buffers were
+// allocated in the same order and sizes, so every buffer of job j sits
+// delta[j] bytes from the same buffer of the lead job.  A kernel of `batch`
+// matrices per job then runs per_job * njobs blocks (or block rows): block b
+// works on matrix b % per_job of job b / per_job.  delta == NULL: one job,
+// the plain batch.
+struct JobMap {
+    const long* delta = nullptr;
+    int per_job = 1;
+    int njobs = 1;
+};
+template <typename T>
+__device__ inline T* jptr(T* p, const JobMap& jm, int b) {
+    return jm.delta && p ? (T*)((char*)p + jm.delta[b / jm.per_job]) : p;
+}
+__device__ inline int jlocal(const JobMap& jm, int b) { return jm.delta ? b % jm.per_job : b; }
+
 // ------------------------------------------------------------- complex FP64
 struct cplx {
     double re, im;

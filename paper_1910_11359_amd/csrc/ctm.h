@@ -35,7 +35,9 @@ void batched_transpose(hipStream_t s, int dtype, int batch, int R, int Cc, const
 // Rank-3 permutations of small tensors (dtype elements):
 //   mode 0: out[b][a][c] = in[a][b][c];  mode 1: out[a][c][b] = in[a][b][c];
 //   mode 2: out[c][a][b] = in[a][b][c]
-void permute3(hipStream_t s, int dtype, int mode, int A, int B, int C, const void* in, void* out);
+// With a JobMap (njobs > 1): the same permutation for every job (grid rows).
+void permute3(hipStream_t s, int dtype, int mode, int A, int B, int C, const void* in, void* out,
+              JobMap jm = JobMap());
 
 // Divide each of the n tensors of d_items by its Frobenius norm (accumulated
 // in FP64, deterministic order); ws holds normalize_ws_doubles(n) doubles.
@@ -46,13 +48,16 @@ struct NormItem {
 size_t normalize_ws_doubles(int max_items);
 void normalize_tensors(hipStream_t s, int dtype, const NormItem* d_items, int n, double* ws);
 
-// Convert between dtype and FP64.
-void to_fp64(hipStream_t s, int dtype, const void* in, double* out, long count);
+// Convert between dtype and FP64 (to_fp64: for every job of jm).
+void to_fp64(hipStream_t s, int dtype, const void* in, double* out, long count, JobMap jm = JobMap());
 void from_fp64(hipStream_t s, int dtype, const double* in, void* out, long count);
 // FP64 rows x cols blocks (row-major, batch of them back to back) into dtype,
 // as they are (rows x cols) or transposed (cols x rows); LDS-tiled.
 void from_fp64_blocks(hipStream_t s, int dtype, const double* in, void* out, int batch, int rows,
-                      int cols, bool transpose);
+                      int cols, bool transpose, JobMap jm = JobMap());
+
+// Device-to-device copy of `bytes` for every job of jm (one launch).
+void copy_jobs(hipStream_t s, void* dst, const void* src, size_t bytes, JobMap jm);
 
 // Projector factors from an SVD of the cut matrix: the truncation rule on
 // sigma (k values, descending; values <= tau * s_1 count as zero, multiplets
@@ -62,12 +67,12 @@ void from_fp64_blocks(hipStream_t s, int dtype, const double* in, void* out, int
 // U and V are n x k row-major (ld k).  g_out[b] receives g.
 void projector_factors(hipStream_t s, int dtype, int batch, int n, int k, int chi, double tau,
                        const double* U, const double* V, const double* sigma, long strideUV,
-                       void* Us, void* Vs, long strideP, int* g_out);
+                       void* Us, void* Vs, long strideP, int* g_out, JobMap jm = JobMap());
 
 // Normalised corner spectra (16 x chi) from raw singular values; delta_out =
 // max over corners of |s - s_prev|_2; prev <- current.
 void spectra_delta(hipStream_t s, int nspec, int chi, const double* sig, double* spectra,
-                   double* prev, double* delta_out, int first);
+                   double* prev, double* delta_out, int first, JobMap jm = JobMap());
 
 // Random n x k starting block (seeded counter-based uniforms in [-1, 1)).
 void random_block(hipStream_t s, int batch, int n, int k, uint64_t seed, double* X);

@@ -270,7 +270,10 @@ void batched_transpose(hipStream_t s, int dtype, int batch, int R, int Cc, const
 }
 
 template <typename T>
-__global__ void k_permute3(int mode, int A, int B, int C, const T* __restrict__ in, T* __restrict__ out) {
+__global__ void k_permute3(int mode, int A, int B, int C, const T* __restrict__ in, T* __restrict__ out,
+                           JobMap jm) {
+    in = jptr(in, jm, blockIdx.y);
+    out = jptr(out, jm, blockIdx.y);
     const long tot = (long)A * B * C;
     for (long e = blockIdx.x * blockDim.x + threadIdx.x; e < tot; e += (long)gridDim.x * blockDim.x) {
         const int c = e % C, b = (e / C) % B, a = e / ((long)B * C);
@@ -282,15 +285,18 @@ __global__ void k_permute3(int mode, int A, int B, int C, const T* __restrict__ 
     }
 }
 
-void permute3(hipStream_t s, int dtype, int mode, int A, int B, int C, const void* in, void* out) {
+void permute3(hipStream_t s, int dtype, int mode, int A, int B, int C, const void* in, void* out,
+              JobMap jm) {
     const long tot = (long)A * B * C;
     const int grid = ceil_div(tot, 256) < 4096 ? ceil_div(tot, 256) : 4096;
+    jm.per_job = 1;
+    const dim3 g(grid, jm.delta ? jm.njobs : 1);
     if (dtype == IPEPS_DTYPE_FP64)
-        hipLaunchKernelGGL(k_permute3<double>, dim3(grid), dim3(256), 0, s, mode, A, B, C,
-                           (const double*)in, (double*)out);
+        hipLaunchKernelGGL(k_permute3<double>, g, dim3(256), 0, s, mode, A, B, C,
+                           (const double*)in, (double*)out, jm);
     else
-        hipLaunchKernelGGL(k_permute3<float>, dim3(grid), dim3(256), 0, s, mode, A, B, C,
-                           (const float*)in, (float*)out);
+        hipLaunchKernelGGL(k_permute3<float>, g, dim3(256), 0, s, mode, A, B, C,
+                           (const float*)in, (float*)out, jm);
     HIP_CHECK(hipGetLastError());
 }
 
@@ -341,7 +347,9 @@ void normalize_tensors(hipStream_t s, int dtype, const NormItem* d_items, int n,
 }
 
 template <typename T>
-__global__ void k_to64(const T* in, double* out, long n) {
+__global__ void k_to64(const T* in, double* out, long n, JobMap jm) {
+    in = jptr(in, jm, blockIdx.y);
+    out = jptr(out, jm, blockIdx.y);
     for (long e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x)
         out[e] = (double)in[e];
 }
@@ -351,13 +359,15 @@ __global__ void k_from64(const double* in, T* out, long n) {
         out[e] = (T)in[e];
 }
 
-void to_fp64(hipStream_t s, int dtype, const void* in, double* out, long count) {
+void to_fp64(hipStream_t s, int dtype, const void* in, double* out, long count, JobMap jm) {
     const int grid = ceil_div(count, 256) < 8192 ? ceil_div(count, 256) : 8192;
     if (count <= 0) return;
+    jm.per_job = 1;
+    const dim3 g(grid, jm.delta ? jm.njobs : 1);
     if (dtype == IPEPS_DTYPE_FP64)
-        hipLaunchKernelGGL(k_to64<double>, dim3(grid), dim3(256), 0, s, (const double*)in, out, count);
+        hipLaunchKernelGGL(k_to64<double>, g, dim3(256), 0, s, (const double*)in, out, count, jm);
     else
-        hipLaunchKernelGGL(k_to64<float>, dim3(grid), dim3(256), 0, s, (const float*)in, out, count);
+        hipLaunchKernelGGL(k_to64<float>, g, dim3(256), 0, s, (const float*)in, out, count, jm);
     HIP_CHECK(hipGetLastError());
 }
 
@@ -375,11 +385,12 @@ void from_fp64(hipStream_t s, int dtype, const double* in, void* out, long count
 // the rows of the output in both orientations.
 template <typename T, bool TRANS>
 __global__ __launch_bounds__(256) void k_from64_blocks(const double* __restrict__ in,
-                                                       T* __restrict__ out, int rows, int cols) {
+                                                       T* __restrict__ out, int rows, int cols,
+                                                       JobMap jm) {
     __shared__ double tile[32][33];
     const long bs = (long)rows * cols;
-    in += blockIdx.z * bs;
-    out += blockIdx.z * bs;
+    in = jptr(in, jm, blockIdx.z) + jlocal(jm, blockIdx.z) * bs;
+    out = jptr(out, jm, blockIdx.z) + jlocal(jm, blockIdx.z) * bs;
     const int r0 = blockIdx.y * 32, c0 = blockIdx.x * 32;
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
     for (int i = ty; i < 32; i += 8) {
@@ -399,24 +410,52 @@ __global__ __launch_bounds__(256) void k_from64_blocks(const double* __restrict_
 }
 
 void from_fp64_blocks(hipStream_t s, int dtype, const double* in, void* out, int batch, int rows,
-                      int cols, bool transpose) {
+                      int cols, bool transpose, JobMap jm) {
     if (batch <= 0 || rows <= 0 || cols <= 0) return;
-    const dim3 grid(ceil_div(cols, 32), ceil_div(rows, 32), batch);
+    jm.per_job = batch;
+    const dim3 grid(ceil_div(cols, 32), ceil_div(rows, 32), batch * (jm.delta ? jm.njobs : 1));
     if (dtype == IPEPS_DTYPE_FP64) {
         if (transpose)
             hipLaunchKernelGGL((k_from64_blocks<double, true>), grid, dim3(256), 0, s, in, (double*)out,
-                               rows, cols);
+                               rows, cols, jm);
         else
             hipLaunchKernelGGL((k_from64_blocks<double, false>), grid, dim3(256), 0, s, in,
-                               (double*)out, rows, cols);
+                               (double*)out, rows, cols, jm);
     } else {
         if (transpose)
             hipLaunchKernelGGL((k_from64_blocks<float, true>), grid, dim3(256), 0, s, in, (float*)out,
-                               rows, cols);
+                               rows, cols, jm);
         else
             hipLaunchKernelGGL((k_from64_blocks<float, false>), grid, dim3(256), 0, s, in, (float*)out,
-                               rows, cols);
+                               rows, cols, jm);
     }
+    HIP_CHECK(hipGetLastError());
+}
+
+// 16-byte words when both ends and the size allow it, else bytes
+__global__ __launch_bounds__(256) void k_copy_jobs(char* dst, const char* src, size_t bytes, JobMap jm) {
+    dst = jptr(dst, jm, blockIdx.y);
+    src = jptr(src, jm, blockIdx.y);
+    const bool wide = ((((uintptr_t)dst) | ((uintptr_t)src) | bytes) & 15) == 0;
+    if (wide) {
+        const size_t nw = bytes / 16;
+        for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < nw; e += (size_t)gridDim.x * blockDim.x)
+            ((uint4*)dst)[e] = ((const uint4*)src)[e];
+    } else {
+        for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < bytes; e += (size_t)gridDim.x * blockDim.x)
+            dst[e] = src[e];
+    }
+}
+
+void copy_jobs(hipStream_t s, void* dst, const void* src, size_t bytes, JobMap jm) {
+    if (bytes == 0) return;
+    if (!jm.delta) {
+        HIP_CHECK(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, s));
+        return;
+    }
+    jm.per_job = 1;
+    const int grid = ceil_div((long)(bytes / 16 + 1), 256) < 1024 ? ceil_div((long)(bytes / 16 + 1), 256) : 1024;
+    hipLaunchKernelGGL(k_copy_jobs, dim3(grid, jm.njobs), dim3(256), 0, s, (char*)dst, (const char*)src, bytes, jm);
     HIP_CHECK(hipGetLastError());
 }
 
@@ -437,11 +476,17 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_proj_factors(int n, int k, int chi, double tau,
                                                       const double* U, const double* V,
                                                       const double* sigma, long strideUV, T* Us,
-                                                      T* Vs, long strideP, int* g_out) {
+                                                      T* Vs, long strideP, int* g_out, JobMap jm) {
     // every block of matrix b re-derives g (k <= 256 values) and the weights
     __shared__ int g_s;
     __shared__ double w[256];
-    const int b = blockIdx.y;
+    const int b = jlocal(jm, blockIdx.y);
+    U = jptr(U, jm, blockIdx.y);
+    V = jptr(V, jm, blockIdx.y);
+    sigma = jptr(sigma, jm, blockIdx.y);
+    Us = jptr(Us, jm, blockIdx.y);
+    Vs = jptr(Vs, jm, blockIdx.y);
+    g_out = jptr(g_out, jm, blockIdx.y);
     const double* sg = sigma + (long)b * k;
     if (threadIdx.x == 0) {
         g_s = trunc_rule_dev(sg, k, chi, tau);
@@ -473,23 +518,28 @@ __global__ __launch_bounds__(256) void k_proj_factors(int n, int k, int chi, dou
 
 void projector_factors(hipStream_t s, int dtype, int batch, int n, int k, int chi, double tau,
                        const double* U, const double* V, const double* sigma, long strideUV,
-                       void* Us, void* Vs, long strideP, int* g_out) {
+                       void* Us, void* Vs, long strideP, int* g_out, JobMap jm) {
     IPEPS_REQUIRE(chi <= 256 && k <= 256, IPEPS_EINVAL, "projector_factors: chi, k > 256");
     const long tot = (long)n * chi;
-    const dim3 grid(ceil_div(tot, 256) < 512 ? ceil_div(tot, 256) : 512, batch);
+    jm.per_job = batch;
+    const dim3 grid(ceil_div(tot, 256) < 512 ? ceil_div(tot, 256) : 512, batch * (jm.delta ? jm.njobs : 1));
     if (dtype == IPEPS_DTYPE_FP64)
         hipLaunchKernelGGL(k_proj_factors<double>, grid, dim3(256), 0, s, n, k, chi, tau, U, V,
-                           sigma, strideUV, (double*)Us, (double*)Vs, strideP, g_out);
+                           sigma, strideUV, (double*)Us, (double*)Vs, strideP, g_out, jm);
     else
         hipLaunchKernelGGL(k_proj_factors<float>, grid, dim3(256), 0, s, n, k, chi, tau, U, V,
-                           sigma, strideUV, (float*)Us, (float*)Vs, strideP, g_out);
+                           sigma, strideUV, (float*)Us, (float*)Vs, strideP, g_out, jm);
     HIP_CHECK(hipGetLastError());
 }
 
 // ------------------------------------------------------------ spectra
 __global__ void k_spectra_delta(int nspec, int chi, const double* sig, double* spectra, double* prev,
-                                double* delta_out, int first) {
+                                double* delta_out, int first, JobMap jm) {
     __shared__ double dmax[64];
+    sig = jptr(sig, jm, blockIdx.x);
+    spectra = jptr(spectra, jm, blockIdx.x);
+    prev = jptr(prev, jm, blockIdx.x);
+    delta_out = jptr(delta_out, jm, blockIdx.x);
     const int c = threadIdx.x;
     double dl = 0.0;
     if (c < nspec) {
@@ -517,9 +567,10 @@ __global__ void k_spectra_delta(int nspec, int chi, const double* sig, double* s
 }
 
 void spectra_delta(hipStream_t s, int nspec, int chi, const double* sig, double* spectra,
-                   double* prev, double* delta_out, int first) {
-    hipLaunchKernelGGL(k_spectra_delta, dim3(1), dim3(64), 0, s, nspec, chi, sig, spectra, prev,
-                       delta_out, first);
+                   double* prev, double* delta_out, int first, JobMap jm) {
+    jm.per_job = 1;
+    hipLaunchKernelGGL(k_spectra_delta, dim3(jm.delta ? jm.njobs : 1), dim3(64), 0, s, nspec, chi, sig,
+                       spectra, prev, delta_out, first, jm);
     HIP_CHECK(hipGetLastError());
 }
 

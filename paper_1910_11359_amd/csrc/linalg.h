@@ -1,4 +1,6 @@
 // Small dense FP64 linear algebra on the device: one workgroup per matrix.
+// The batched routines also take a JobMap: `batch` matrices for each of
+// jm.njobs jobs of one buffer layout (common.h), in one launch.
 #pragma once
 
 #include "common.h"
@@ -16,7 +18,7 @@ namespace ipeps {
 // (device scratch of jacobi_svd_real_work doubles).
 void jacobi_svd_real(hipStream_t s, int batch, int m, int n, const double* A, long lda,
                      long strideA, double* sigma, double* U, double* V, double* work,
-                     double skip_rel = 1e-14);
+                     double skip_rel = 1e-14, JobMap jm = JobMap());
 size_t jacobi_svd_real_work(int batch, int m, int n);
 
 // Batched Cholesky of k x k SPD Gram matrices G (row-major, stride k*k, k <= 256) with
@@ -34,7 +36,7 @@ size_t jacobi_svd_real_work(int batch, int m, int n);
 // gets R^{-1} = D^{-1} (the second pass of a Cholesky QR, whose first pass
 // already left the columns orthonormal to that level).
 void chol_inverse(hipStream_t s, int batch, int k, const double* G, double* Rinv, double tol,
-                  int* dead = nullptr, double near_identity = 0.0);
+                  int* dead = nullptr, double near_identity = 0.0, JobMap jm = JobMap());
 
 // Scale the columns of batched n x k row-major matrices (stride n*k) to unit
 // 2-norm; zero columns stay zero.

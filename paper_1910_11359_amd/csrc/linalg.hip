@@ -165,11 +165,16 @@ template <bool IN_LDS, int EPL>
 __global__ __launch_bounds__(jacobi_threads<EPL>()) void k_jacobi_svd(int m, int n, const double* __restrict__ A,
                                                      long lda, long strideA, double* sigma,
                                                      double* U, double* V, double* work,
-                                                     double skip_rel) {
+                                                     double skip_rel, JobMap jm) {
     extern __shared__ double smem[];
     __shared__ int flag;
     __shared__ double red[16];
-    const int b = blockIdx.x;
+    const int b = jlocal(jm, blockIdx.x);
+    A = jptr(A, jm, blockIdx.x);
+    sigma = jptr(sigma, jm, blockIdx.x);
+    U = jptr(U, jm, blockIdx.x);
+    V = jptr(V, jm, blockIdx.x);
+    work = jptr(work, jm, blockIdx.x);
     const bool wantV = (V != nullptr);
     const long nv = wantV ? (long)n * n : 0;
     double *Ac, *Vc, *sig_s, *nrm;
@@ -207,7 +212,9 @@ size_t jacobi_svd_real_work(int batch, int m, int n) {
 template <int EPL>
 static void launch_jacobi(hipStream_t s, int batch, int m, int n, const double* A, long lda,
                           long strideA, double* sigma, double* U, double* V, double* work,
-                          double skip_rel) {
+                          double skip_rel, JobMap jm) {
+    const int blocks = batch * (jm.delta ? jm.njobs : 1);
+    if (jm.delta) jm.per_job = batch;
     const size_t lds = jacobi_lds_bytes(m, n, V != nullptr);
     if (lds <= kMaxLds) {
         static bool attr_set = false;
@@ -217,31 +224,31 @@ static void launch_jacobi(hipStream_t s, int batch, int m, int n, const double* 
                                           (int)kMaxLds));
             attr_set = true;
         }
-        hipLaunchKernelGGL((k_jacobi_svd<true, EPL>), dim3(batch), dim3(jacobi_threads<EPL>()), lds, s, m, n, A, lda,
-                           strideA, sigma, U, V, work, skip_rel);
+        hipLaunchKernelGGL((k_jacobi_svd<true, EPL>), dim3(blocks), dim3(jacobi_threads<EPL>()), lds, s, m, n, A, lda,
+                           strideA, sigma, U, V, work, skip_rel, jm);
     } else {
         IPEPS_REQUIRE(work != nullptr, IPEPS_EINVAL, "jacobi_svd_real: work buffer needed");
-        hipLaunchKernelGGL((k_jacobi_svd<false, EPL>), dim3(batch), dim3(jacobi_threads<EPL>()), 0, s, m, n, A, lda,
-                           strideA, sigma, U, V, work, skip_rel);
+        hipLaunchKernelGGL((k_jacobi_svd<false, EPL>), dim3(blocks), dim3(jacobi_threads<EPL>()), 0, s, m, n, A, lda,
+                           strideA, sigma, U, V, work, skip_rel, jm);
     }
     HIP_CHECK(hipGetLastError());
 }
 
 void jacobi_svd_real(hipStream_t s, int batch, int m, int n, const double* A, long lda,
                      long strideA, double* sigma, double* U, double* V, double* work,
-                     double skip_rel) {
+                     double skip_rel, JobMap jm) {
     if (batch <= 0 || n <= 0) return;
     IPEPS_REQUIRE(m >= n && m <= 256, IPEPS_EINVAL, "jacobi_svd_real: need n <= m <= 256");
     if (m <= 64)
-        launch_jacobi<4>(s, batch, m, n, A, lda, strideA, sigma, U, V, work, skip_rel);
+        launch_jacobi<4>(s, batch, m, n, A, lda, strideA, sigma, U, V, work, skip_rel, jm);
     else if (m <= 96)
-        launch_jacobi<6>(s, batch, m, n, A, lda, strideA, sigma, U, V, work, skip_rel);
+        launch_jacobi<6>(s, batch, m, n, A, lda, strideA, sigma, U, V, work, skip_rel, jm);
     else if (m <= 128)
-        launch_jacobi<8>(s, batch, m, n, A, lda, strideA, sigma, U, V, work, skip_rel);
+        launch_jacobi<8>(s, batch, m, n, A, lda, strideA, sigma, U, V, work, skip_rel, jm);
     else if (m <= 176)
-        launch_jacobi<11>(s, batch, m, n, A, lda, strideA, sigma, U, V, work, skip_rel);
+        launch_jacobi<11>(s, batch, m, n, A, lda, strideA, sigma, U, V, work, skip_rel, jm);
     else
-        launch_jacobi<16>(s, batch, m, n, A, lda, strideA, sigma, U, V, work, skip_rel);
+        launch_jacobi<16>(s, batch, m, n, A, lda, strideA, sigma, U, V, work, skip_rel, jm);
 }
 
 // ----------------------------------------------------------------- Cholesky
@@ -270,13 +277,17 @@ __device__ inline double readlane_d(double v, int lane) {
 template <bool IN_LDS>
 __global__ __launch_bounds__(256) void k_chol_inverse(int k, const double* __restrict__ G,
                                                       double* __restrict__ Rinv, double tol,
-                                                      int* __restrict__ dead, double near_identity) {
+                                                      int* __restrict__ dead, double near_identity,
+                                                      JobMap jm, int nbatch) {
     extern __shared__ double smem[];
     __shared__ int dead_s[256];
     __shared__ double dsc[256];  // 1/sqrt(G_ii): G is factored scaled to unit diagonal
     __shared__ double red[4];
     const int tid = threadIdx.x, lane = tid & 63;
-    const int b = blockIdx.x;
+    const int b = jlocal(jm, blockIdx.x);
+    G = jptr(G, jm, blockIdx.x);
+    Rinv = jptr(Rinv, jm, blockIdx.x);
+    dead = jptr(dead, jm, blockIdx.x);
     const double* Gb = G + (long)b * k * k;
     double* out = Rinv + (long)b * k * k;
     double* R = IN_LDS ? smem : out;
@@ -303,7 +314,7 @@ __global__ __launch_bounds__(256) void k_chol_inverse(int k, const double* __res
             }
             if (dead) {
                 for (int j = tid; j < k; j += 256) dead[(long)b * k + j] = 0;
-                if (tid == 0) dead[(long)gridDim.x * k + b] = 0;
+                if (tid == 0) dead[(long)nbatch * k + b] = 0;
             }
             return;
         }
@@ -451,7 +462,7 @@ __global__ __launch_bounds__(256) void k_chol_inverse(int k, const double* __res
         if (tid == 0) {
             int cnt = 0;
             for (int j = 0; j < k; ++j) cnt += dead_s[j];
-            dead[(long)gridDim.x * k + b] = cnt;
+            dead[(long)nbatch * k + b] = cnt;
         }
     }
 }
@@ -461,8 +472,10 @@ static size_t chol_lds_bytes(int k, bool in_lds) {
 }
 
 void chol_inverse(hipStream_t s, int batch, int k, const double* G, double* Rinv, double tol,
-                  int* dead, double near_identity) {
+                  int* dead, double near_identity, JobMap jm) {
     if (batch <= 0) return;
+    const int blocks = batch * (jm.delta ? jm.njobs : 1);
+    if (jm.delta) jm.per_job = batch;
     IPEPS_REQUIRE(k >= 1 && k <= 256, IPEPS_EINVAL, "chol_inverse: k must be in 1..256");
     const bool in_lds = k <= 128;
     const size_t lds = chol_lds_bytes(k, in_lds);
@@ -477,11 +490,11 @@ void chol_inverse(hipStream_t s, int batch, int k, const double* G, double* Rinv
         attr_set = true;
     }
     if (in_lds)
-        hipLaunchKernelGGL(k_chol_inverse<true>, dim3(batch), dim3(256), lds, s, k, G, Rinv, tol, dead,
-                           near_identity);
+        hipLaunchKernelGGL(k_chol_inverse<true>, dim3(blocks), dim3(256), lds, s, k, G, Rinv, tol, dead,
+                           near_identity, jm, batch);
     else
-        hipLaunchKernelGGL(k_chol_inverse<false>, dim3(batch), dim3(256), lds, s, k, G, Rinv, tol, dead,
-                           near_identity);
+        hipLaunchKernelGGL(k_chol_inverse<false>, dim3(blocks), dim3(256), lds, s, k, G, Rinv, tol, dead,
+                           near_identity, jm, batch);
     HIP_CHECK(hipGetLastError());
 }
 

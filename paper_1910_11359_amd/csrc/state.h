@@ -214,6 +214,7 @@ struct ipeps_state {
 
     // plan
     std::vector<ipeps::GemmProb> probs;
+    std::vector<ipeps::GemmGroup> groups;  // every non-empty group, in plan order
     ipeps::GemmProb* d_probs;
     std::vector<ipeps::NormItem> norms;
     ipeps::NormItem* d_norms;

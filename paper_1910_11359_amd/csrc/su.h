@@ -28,9 +28,10 @@ void build_gates(hipStream_t s, const ipeps_config& cfg, cplx* gates);
 // Scratch (bytes) one bond update needs.
 size_t su_scratch_bytes(int D, int d);
 
-// Apply one layer: both bonds in parallel (one workgroup each).
+// Apply one layer: both bonds in parallel (one workgroup each), for every
+// job of jm (a row of workgroups per job).
 //   gam: 4 * d * D^4 complex; lam: 8 * D; eps: 4.
 void su_layer(hipStream_t s, int D, int d, const LayerDesc& L, cplx* gam, double* lam,
-              double* eps, const cplx* gates, void* scratch);
+              double* eps, const cplx* gates, void* scratch, JobMap jm = JobMap());
 
 }  // namespace ipeps

@@ -413,7 +413,13 @@ __device__ void qrcp_to_rh(int m, cplx* A, int* perm, double* cn) {
 template <bool THETA_LDS>
 __global__ __launch_bounds__(1024) void k_su_bond(SuDims dm, LayerDesc L, cplx* gam,
                                                   double* lam, double* eps, const cplx* gates,
-                                                  char* scratch, size_t scratch_per_bond) {
+                                                  char* scratch, size_t scratch_per_bond, JobMap jm) {
+    // block row y: job y of jm (its tensors, weights, gates and scratch)
+    gam = jptr(gam, jm, blockIdx.y);
+    lam = jptr(lam, jm, blockIdx.y);
+    eps = jptr(eps, jm, blockIdx.y);
+    gates = jptr(gates, jm, blockIdx.y);
+    scratch = jptr(scratch, jm, blockIdx.y);
     extern __shared__ char smem_raw[];
     __shared__ double red[16];
     __shared__ cplx bcast[2];
@@ -604,7 +610,9 @@ __global__ __launch_bounds__(1024) void k_su_bond(SuDims dm, LayerDesc L, cplx* 
 }
 
 void su_layer(hipStream_t s, int D, int d, const LayerDesc& L, cplx* gam, double* lam,
-              double* eps, const cplx* gates, void* scratch) {
+              double* eps, const cplx* gates, void* scratch, JobMap jm) {
+    jm.per_job = 1;
+    const dim3 grid(2, jm.delta ? jm.njobs : 1);
     const SuDims dm = su_dims(D, d);
     IPEPS_REQUIRE(dm.m <= 512 && D <= 8, IPEPS_EINVAL, "simple update: d*min(D^3,dD) > 512");
     const size_t per_bond = su_layout(dm, nullptr, nullptr);
@@ -617,11 +625,11 @@ void su_layer(hipStream_t s, int D, int d, const LayerDesc& L, cplx* gam, double
                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMax));
             attr = true;
         }
-        hipLaunchKernelGGL(k_su_bond<true>, dim3(2), dim3(1024), lds, s, dm, L, gam, lam, eps,
-                           gates, (char*)scratch, per_bond);
+        hipLaunchKernelGGL(k_su_bond<true>, grid, dim3(1024), lds, s, dm, L, gam, lam, eps,
+                           gates, (char*)scratch, per_bond, jm);
     } else {
-        hipLaunchKernelGGL(k_su_bond<false>, dim3(2), dim3(1024), 0, s, dm, L, gam, lam, eps,
-                           gates, (char*)scratch, per_bond);
+        hipLaunchKernelGGL(k_su_bond<false>, grid, dim3(1024), 0, s, dm, L, gam, lam, eps,
+                           gates, (char*)scratch, per_bond, jm);
     }
     HIP_CHECK(hipGetLastError());
 }

@@ -65,7 +65,9 @@ EXPORTS = [
     "solve_submit", "solve_poll", "solve_job_times", "solve_server_destroy", "ipeps_strerror",
     "ipeps_profile", "ipeps_profile_read", "ff_neel_dynamics", "ff_bessel_j",
     "ipeps_observe_async", "ipeps_observe_result", "ff_spectrum_ipr", "ff_neel_dynamics_noalloc",
-    "ipeps_profile_read_gemms",
+    "ipeps_profile_read_gemms", "ipeps_slab_region_bytes", "ipeps_slab_create", "ipeps_slab_init",
+    "ipeps_slab_destroy", "ipeps_batch_create", "ipeps_batch_trotter_step", "ipeps_batch_ctmrg",
+    "ipeps_batch_observe", "ipeps_batch_destroy",
 ]
 
 _lib = None
@@ -116,6 +118,18 @@ def load():
     lib.ff_bessel_j.argtypes = [C.c_double, C.c_int, P(C.c_double)]
     lib.ff_spectrum_ipr.argtypes = [C.c_int, C.c_int, C.c_double, C.c_int, C.c_void_p, C.c_void_p,
                                     C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+    lib.ipeps_slab_region_bytes.argtypes = [P(Config)]
+    lib.ipeps_slab_region_bytes.restype = C.c_size_t
+    lib.ipeps_slab_create.argtypes = [P(Config), C.c_int, P(C.c_void_p)]
+    lib.ipeps_slab_init.argtypes = [C.c_void_p, C.c_int, P(Config), C.c_void_p, P(C.c_void_p)]
+    lib.ipeps_slab_destroy.argtypes = [C.c_void_p]
+    lib.ipeps_slab_destroy.restype = None
+    lib.ipeps_batch_create.argtypes = [P(C.c_void_p), C.c_int, P(C.c_void_p)]
+    lib.ipeps_batch_trotter_step.argtypes = [C.c_void_p, C.c_int]
+    lib.ipeps_batch_ctmrg.argtypes = [C.c_void_p, C.c_int, C.c_int]
+    lib.ipeps_batch_observe.argtypes = [C.c_void_p, P(Obs)]
+    lib.ipeps_batch_destroy.argtypes = [C.c_void_p]
+    lib.ipeps_batch_destroy.restype = None
     lib.ipeps_strerror.argtypes = [C.c_int]
     lib.ipeps_strerror.restype = C.c_char_p
     _lib = lib
@@ -255,6 +269,72 @@ class State:
         out = np.zeros((8, self.cfg.D))
         _check(self._lib.ipeps_bond_spectra(self.h, _dptr(out)), "ipeps_bond_spectra")
         return out
+
+
+class Slab:
+    """One device allocation holding `slots` states of one layout
+    (ipeps_slab_*; include/ipeps.h)."""
+
+    def __init__(self, layout_cfg, slots):
+        self._lib = load()
+        h = C.c_void_p()
+        _check(self._lib.ipeps_slab_create(C.byref(layout_cfg), int(slots), C.byref(h)), "ipeps_slab_create")
+        self.h = h
+
+    def state(self, slot, cfg, stream=None):
+        st = State.__new__(State)
+        st.cfg, st._lib = cfg, self._lib
+        handle = C.c_void_p()
+        sptr = getattr(stream, "cuda_stream", stream) if stream is not None else None
+        _check(self._lib.ipeps_slab_init(self.h, int(slot), C.byref(cfg), C.c_void_p(sptr), C.byref(handle)),
+               "ipeps_slab_init")
+        st.h = handle
+        return st
+
+    def close(self):
+        if getattr(self, "h", None):
+            self._lib.ipeps_slab_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Lockstep batch of states of one slab (ipeps_batch_*); states[0] leads."""
+
+    def __init__(self, states):
+        self._lib = load()
+        self.states = list(states)
+        arr = (C.c_void_p * len(self.states))(*[s.h.value for s in self.states])
+        h = C.c_void_p()
+        _check(self._lib.ipeps_batch_create(arr, len(self.states), C.byref(h)), "ipeps_batch_create")
+        self.h = h
+
+    def trotter_step(self, n_steps=1):
+        _check(self._lib.ipeps_batch_trotter_step(self.h, int(n_steps)), "ipeps_batch_trotter_step")
+
+    def ctmrg(self, iters, cold=True):
+        _check(self._lib.ipeps_batch_ctmrg(self.h, int(iters), int(bool(cold))), "ipeps_batch_ctmrg")
+
+    def observe(self):
+        buf = (Obs * len(self.states))()
+        _check(self._lib.ipeps_batch_observe(self.h, buf), "ipeps_batch_observe")
+        return [buf[i].as_dict() for i in range(len(self.states))]
+
+    def close(self):
+        if getattr(self, "h", None):
+            self._lib.ipeps_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Server:
