@@ -285,7 +285,7 @@ def serving_sample(P, synthetic, dtype, n_req=16, rate=8.0, d_max=4, steps_max=4
                       f"steps at {steps_max}, observe every 10 with 10 warm CTMRG iterations"}, series
 
 
-def sweep(P, synthetic, dtype, slots=8):
+def sweep(P, synthetic, dtype, slots=64):
     """The batched parameter sweep: 64 jobs (D in 3..6 with chi = 2 D^2, V in
     {0, 1}, 8 seeded W in [1, 20]), 50 Trotter steps each, 10 CTMRG
     iterations every 10 steps, all submitted at once to a request loop with

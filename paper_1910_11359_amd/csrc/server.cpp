@@ -1,17 +1,26 @@
-// Request loop: admits time-evolution jobs by HBM footprint into a fixed
-// number of slots; each slot is a worker thread with its own HIP stream, so
-// admitted jobs keep their tensors on the device and run concurrently.  A
-// job that finishes frees its slot and memory at once and the next queued
-// job that fits is admitted (queue order, skipping jobs that do not fit yet).
+// Request loop with continuous batching.  Jobs are admitted by HBM footprint
+// into slabs (one device allocation per layout: D, chi, d_A, precision,
+// flags), where each keeps its state resident.  One executor thread advances
+// every resident job in rounds: the jobs of one slab that are at the same
+// point of their schedule (first observation or later, the same number of
+// Trotter steps to the next observation, the same CTMRG iteration count) run
+// as one lockstep batch, every kernel launch carrying all of them; the
+// batches of different slabs go to different streams and overlap.  A job
+// that finishes frees its slot at once, a slab with no job left returns its
+// memory, and jobs that arrived meanwhile are admitted at the start of the
+// next round (queue order, skipping jobs that do not fit yet).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
 #include <deque>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <thread>
+#include <tuple>
 #include <vector>
 
 #include "../../include/ipeps.h"
@@ -23,106 +32,235 @@ double now_s() {
     return duration<double>(steady_clock::now().time_since_epoch()).count();
 }
 
+struct Bucket;
+
 struct Job {
     ipeps_job spec;
-    size_t footprint = 0;
+    size_t footprint = 0;  // one slab region of its layout
     int status = IPEPS_JOB_QUEUED;
     std::vector<ipeps_obs> series;
     double t_submit = 0, t_admit = 0, t_done = 0;
+    // resident part (executor thread only)
+    ipeps_state* st = nullptr;
+    Bucket* bucket = nullptr;
+    int slot = -1;
+    int done = 0;  // Trotter steps taken
+    int nobs = 0;  // observations made
+};
+
+bool same_layout(const ipeps_config& a, const ipeps_config& b) {
+    return a.D == b.D && a.chi == b.chi && a.d_A == b.d_A && a.dtype == b.dtype && a.flags == b.flags;
+}
+
+struct Bucket {
+    ipeps_config layout;
+    ipeps_slab* slab = nullptr;
+    size_t bytes = 0;  // cap regions
+    std::vector<uint64_t> slot_job;  // 0: free
+    hipStream_t stream = nullptr;    // the stream of its states
+    int used() const {
+        int u = 0;
+        for (uint64_t j : slot_job) u += j != 0;
+        return u;
+    }
 };
 
 }  // namespace
 
 struct ipeps_server {
     std::mutex mu;
-    std::condition_variable cv_work, cv_done;
+    std::condition_variable cv_work;
     std::map<uint64_t, Job> jobs;
     std::deque<uint64_t> pending;
     uint64_t next_id = 1;
     size_t budget = 0, used = 0;
+    int max_slots = 1;
     int running = 0;
     bool stopping = false;
     int device = 0;
-    std::vector<std::thread> workers;
+    std::vector<std::unique_ptr<Bucket>> buckets;  // executor thread only
+    std::thread executor;
 };
 
 namespace {
 
-int run_job(ipeps_server* srv, Job& job, hipStream_t stream, std::vector<ipeps_obs>* series) {
-    (void)srv;
-    ipeps_state* st = nullptr;
-    int rc = ipeps_init(&job.spec.cfg, stream, nullptr, nullptr, nullptr, &st);
-    if (rc != IPEPS_OK) return rc;
-    const int every = job.spec.observe_every > 0 ? job.spec.observe_every : job.spec.n_steps;
-    int done = 0, nobs = 0;
-    while (rc == IPEPS_OK && done < job.spec.n_steps) {
-        int chunk = every;
-        if (done + chunk > job.spec.n_steps) chunk = job.spec.n_steps - done;
-        rc = ipeps_trotter_step(st, chunk, nullptr);
-        if (rc != IPEPS_OK) break;
-        done += chunk;
-        int it = 0;
-        double dl = 0;
-        rc = ctmrg_converge(st, 0.0, job.spec.ctm_iters > 0 ? job.spec.ctm_iters : 10, nobs == 0, &it, &dl);
-        if (rc != IPEPS_OK) break;
-        ipeps_obs o;
-        rc = ipeps_observe(st, &o);
-        if (rc != IPEPS_OK) break;
-        series->push_back(o);
-        ++nobs;
+// Admission (executor thread, server lock held): queued jobs in order, each
+// into a free slot of a slab of its layout, or into a new slab sized for the
+// queued jobs of that layout, as far as the budget and max_slots allow.
+void admit(ipeps_server* srv, std::vector<uint64_t>& admitted) {
+    for (auto it = srv->pending.begin(); it != srv->pending.end();) {
+        if (srv->running >= srv->max_slots) break;
+        Job& j = srv->jobs[*it];
+        Bucket* bk = nullptr;
+        int slot = -1;
+        for (auto& b : srv->buckets) {
+            if (!same_layout(b->layout, j.spec.cfg)) continue;
+            for (size_t s = 0; s < b->slot_job.size(); ++s)
+                if (!b->slot_job[s]) {
+                    bk = b.get();
+                    slot = (int)s;
+                    break;
+                }
+            if (bk) break;
+        }
+        if (!bk) {
+            const size_t region = j.footprint;
+            int want = 0;
+            for (uint64_t id : srv->pending) want += same_layout(srv->jobs[id].spec.cfg, j.spec.cfg);
+            want = std::min(want, srv->max_slots - srv->running);
+            const int fit = (int)((srv->budget - srv->used) / region);
+            const int cap = std::min(want, fit);
+            if (cap >= 1) {
+                ipeps_slab* slab = nullptr;
+                if (ipeps_slab_create(&j.spec.cfg, cap, &slab) == IPEPS_OK) {
+                    auto b = std::make_unique<Bucket>();
+                    b->layout = j.spec.cfg;
+                    b->slab = slab;
+                    b->bytes = region * cap;
+                    b->slot_job.assign(cap, 0);
+                    if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess) b->stream = nullptr;
+                    srv->used += b->bytes;
+                    bk = b.get();
+                    slot = 0;
+                    srv->buckets.push_back(std::move(b));
+                }
+            }
+        }
+        if (!bk) {  // does not fit yet: later jobs may
+            ++it;
+            continue;
+        }
+        bk->slot_job[slot] = *it;
+        j.bucket = bk;
+        j.slot = slot;
+        j.status = IPEPS_JOB_RUNNING;
+        j.t_admit = now_s();
+        srv->running++;
+        admitted.push_back(*it);
+        it = srv->pending.erase(it);
     }
-    ipeps_destroy(st);
-    return rc;
 }
 
-void worker_main(ipeps_server* srv) {
+void finish(ipeps_server* srv, Job& j, uint64_t id, int rc) {
+    if (j.st) ipeps_destroy(j.st);  // frees the slab region
+    j.st = nullptr;
+    std::lock_guard<std::mutex> lk(srv->mu);
+    j.bucket->slot_job[j.slot] = 0;
+    j.status = rc == IPEPS_OK ? IPEPS_JOB_DONE : rc;
+    j.t_done = now_s();
+    srv->running--;
+    (void)id;
+}
+
+// One group of a round: the jobs of one slab at the same point of their
+// schedules, as one batch.
+struct Group {
+    Bucket* bucket;
+    bool cold;
+    int chunk, iters;
+    std::vector<uint64_t> ids;
+    ipeps_batch* batch = nullptr;
+    int rc = IPEPS_OK;
+};
+
+void executor_main(ipeps_server* srv) {
     (void)hipSetDevice(srv->device);
-    hipStream_t stream = nullptr;
-    if (hipStreamCreateWithFlags(&stream, hipStreamNonBlocking) != hipSuccess) stream = nullptr;
     for (;;) {
-        uint64_t id = 0;
+        std::vector<uint64_t> admitted, resident;
         {
             std::unique_lock<std::mutex> lk(srv->mu);
             for (;;) {
-                for (auto it = srv->pending.begin(); it != srv->pending.end(); ++it) {
-                    Job& j = srv->jobs[*it];
-                    if (srv->used + j.footprint <= srv->budget) {
-                        id = *it;
-                        srv->pending.erase(it);
-                        break;
+                // slabs with no job left return their memory first (no work
+                // is in flight between rounds)
+                for (auto it = srv->buckets.begin(); it != srv->buckets.end();) {
+                    if ((*it)->used() == 0) {
+                        srv->used -= (*it)->bytes;
+                        ipeps_slab_destroy((*it)->slab);
+                        if ((*it)->stream) (void)hipStreamDestroy((*it)->stream);
+                        it = srv->buckets.erase(it);
+                    } else {
+                        ++it;
                     }
                 }
-                if (id) break;
-                if (srv->stopping && srv->pending.empty()) {
-                    if (stream) (void)hipStreamDestroy(stream);
-                    return;
+                admit(srv, admitted);
+                if (srv->running > 0) break;
+                if (srv->stopping && srv->pending.empty()) return;
+                if (!srv->pending.empty() && srv->buckets.empty() && srv->running == 0) {
+                    // the first queued job does not fit even alone: fail it
+                    Job& j = srv->jobs[srv->pending.front()];
+                    j.status = IPEPS_ENOMEM;
+                    j.t_done = now_s();
+                    srv->pending.pop_front();
+                    continue;
                 }
                 srv->cv_work.wait(lk);
             }
+            for (auto& kv : srv->jobs)
+                if (kv.second.status == IPEPS_JOB_RUNNING) resident.push_back(kv.first);
+        }
+        // states of the newly admitted jobs
+        for (uint64_t id : admitted) {
             Job& j = srv->jobs[id];
-            srv->used += j.footprint;
-            srv->running++;
-            j.status = IPEPS_JOB_RUNNING;
-            j.t_admit = now_s();
+            const int rc = ipeps_slab_init(j.bucket->slab, j.slot, &j.spec.cfg, j.bucket->stream, &j.st);
+            if (rc != IPEPS_OK) {
+                j.st = nullptr;
+                finish(srv, j, id, rc);
+            }
         }
-        std::vector<ipeps_obs> series;
-        Job copy;
-        {
-            std::lock_guard<std::mutex> lk(srv->mu);
-            copy = srv->jobs[id];
-        }
-        const int rc = run_job(srv, copy, stream, &series);
-        {
-            std::lock_guard<std::mutex> lk(srv->mu);
+        // group the resident jobs
+        std::vector<Group> groups;
+        for (uint64_t id : resident) {
             Job& j = srv->jobs[id];
-            j.series = std::move(series);
-            j.status = (rc == IPEPS_OK) ? IPEPS_JOB_DONE : rc;
-            j.t_done = now_s();
-            srv->used -= j.footprint;
-            srv->running--;
+            if (!j.st || j.status != IPEPS_JOB_RUNNING) continue;
+            const int every = j.spec.observe_every > 0 ? j.spec.observe_every : j.spec.n_steps;
+            const int chunk = std::min(every, j.spec.n_steps - j.done);
+            const int iters = j.spec.ctm_iters > 0 ? j.spec.ctm_iters : 10;
+            const bool cold = j.nobs == 0;
+            Group* g = nullptr;
+            for (auto& gg : groups)
+                if (gg.bucket == j.bucket && gg.cold == cold && gg.chunk == chunk && gg.iters == iters) g = &gg;
+            if (!g) {
+                groups.push_back(Group{j.bucket, cold, chunk, iters, {}, nullptr, IPEPS_OK});
+                g = &groups.back();
+            }
+            g->ids.push_back(id);
         }
-        srv->cv_work.notify_all();
-        srv->cv_done.notify_all();
+        // enqueue every group's Trotter steps and CTMRG (slabs on their own streams) ...
+        for (auto& g : groups) {
+            std::vector<ipeps_state*> sts;
+            for (uint64_t id : g.ids) sts.push_back(srv->jobs[id].st);
+            g.rc = ipeps_batch_create(sts.data(), (int)sts.size(), &g.batch);
+            if (g.rc == IPEPS_OK) g.rc = ipeps_batch_trotter_step(g.batch, g.chunk);
+            if (g.rc == IPEPS_OK) g.rc = ipeps_batch_ctmrg(g.batch, g.iters, g.cold ? 1 : 0);
+        }
+        // ... then read every group out
+        for (auto& g : groups) {
+            std::vector<ipeps_obs> obs(g.ids.size());
+            if (g.rc == IPEPS_OK) g.rc = ipeps_batch_observe(g.batch, obs.data());
+            if (g.batch) ipeps_batch_destroy(g.batch);
+            for (size_t i = 0; i < g.ids.size(); ++i) {
+                const uint64_t id = g.ids[i];
+                Job& j = srv->jobs[id];
+                int rc = g.rc;
+                ipeps_obs o = obs[i];
+                if (rc != IPEPS_OK && rc != IPEPS_ENUMERIC && rc != IPEPS_EINVAL) {
+                    finish(srv, j, id, rc);
+                    continue;
+                }
+                if (rc != IPEPS_OK) rc = ipeps_observe(j.st, &o);  // which job of the batch failed
+                if (rc != IPEPS_OK) {
+                    finish(srv, j, id, rc);
+                    continue;
+                }
+                j.done += g.chunk;
+                j.nobs++;
+                {
+                    std::lock_guard<std::mutex> lk(srv->mu);
+                    j.series.push_back(o);
+                }
+                if (j.done >= j.spec.n_steps) finish(srv, j, id, IPEPS_OK);
+            }
+        }
     }
 }
 
@@ -131,7 +269,7 @@ void worker_main(ipeps_server* srv) {
 extern "C" {
 
 int solve_server_create(size_t hbm_budget, int max_slots, ipeps_server** out) {
-    if (!out || max_slots < 1 || max_slots > 64) return IPEPS_EINVAL;
+    if (!out || max_slots < 1 || max_slots > 256) return IPEPS_EINVAL;
     *out = nullptr;
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return IPEPS_EDEVICE;
@@ -143,7 +281,8 @@ int solve_server_create(size_t hbm_budget, int max_slots, ipeps_server** out) {
     ipeps_server* srv = new ipeps_server();
     srv->budget = hbm_budget;
     srv->device = dev;
-    for (int i = 0; i < max_slots; ++i) srv->workers.emplace_back(worker_main, srv);
+    srv->max_slots = max_slots;
+    srv->executor = std::thread(executor_main, srv);
     *out = srv;
     return IPEPS_OK;
 }
@@ -151,7 +290,8 @@ int solve_server_create(size_t hbm_budget, int max_slots, ipeps_server** out) {
 int solve_submit(ipeps_server* srv, const ipeps_job* job, uint64_t* job_id) {
     if (!srv || !job || !job_id) return IPEPS_EINVAL;
     if (job->n_steps < 1 || job->observe_every < 0 || job->ctm_iters < 0) return IPEPS_EINVAL;
-    const size_t fp = ipeps_footprint_bytes(&job->cfg);
+    if (ipeps_footprint_bytes(&job->cfg) == 0) return IPEPS_EINVAL;
+    const size_t fp = ipeps_slab_region_bytes(&job->cfg);
     if (fp == 0) return IPEPS_EINVAL;
     std::lock_guard<std::mutex> lk(srv->mu);
     if (fp > srv->budget || srv->stopping) return IPEPS_EINVAL;
@@ -201,7 +341,7 @@ void solve_server_destroy(ipeps_server* srv) {
         srv->stopping = true;
     }
     srv->cv_work.notify_all();
-    for (auto& t : srv->workers) t.join();
+    if (srv->executor.joinable()) srv->executor.join();
     delete srv;
 }
 
