@@ -291,8 +291,8 @@ int ipeps_slab_create(const ipeps_config* layout, int slots, ipeps_slab** out);
  * stream is hip_stream.  Errors: EINVAL, ENOMEM, EDEVICE. */
 int ipeps_slab_init(ipeps_slab* slab, int slot, const ipeps_config* cfg, void* hip_stream,
                     ipeps_state** out);
-/* Synchronises the device and releases the slab (its states must have been
- * destroyed). */
+/* Releases the slab; its states must have been destroyed (ipeps_destroy
+ * waits for each state's work) and no batch of them may exist. */
 void ipeps_slab_destroy(ipeps_slab* slab);
 
 /* A lockstep batch of n >= 1 states of one slab, at the same phase of their
@@ -308,8 +308,17 @@ int ipeps_batch_trotter_step(ipeps_batch* b, int n_steps);
 /* ctmrg_converge with tol <= 0 for every job: exactly iters iterations,
  * cold (cold_start != 0) or warm. */
 int ipeps_batch_ctmrg(ipeps_batch* b, int iters, int cold_start);
-/* ipeps_observe for every job: out[i] for states[i].  Synchronises. */
+/* ipeps_observe for every job: out[i] for states[i].  Synchronises.
+ * Errors: EINVAL, ENUMERIC (a job's readout is not finite: that job is
+ * poisoned and its out[i] zeroed, the other jobs' results are valid). */
 int ipeps_batch_observe(ipeps_batch* b, ipeps_obs* out);
+/* The same in two halves: _async enqueues the readouts (one may be pending
+ * per batch), _query returns 1 once they are complete (0 before; no
+ * synchronisation), _result waits for them and fills out as above, and
+ * status[i] (nullable) with job i's own code. */
+int ipeps_batch_observe_async(ipeps_batch* b);
+int ipeps_batch_query(ipeps_batch* b);
+int ipeps_batch_observe_result(ipeps_batch* b, ipeps_obs* out, int* status);
 /* Orders every job's streams after the batch's work, waits for it and
  * releases the batch (not the states). */
 void ipeps_batch_destroy(ipeps_batch* b);

@@ -1764,6 +1764,8 @@ void slab_free(void* p, void* stream, void* ctx) {
 struct ipeps_batch {
     Ex x;
     std::vector<hipEvent_t> ev;  // cross-stream ordering with the jobs' own streams
+    hipEvent_t ev_obs = nullptr;  // the pending readout's completion
+    bool obs_pending = false;
 };
 
 namespace {
@@ -1846,7 +1848,6 @@ int ipeps_slab_init(ipeps_slab* sl, int slot, const ipeps_config* cfg, void* hip
 
 void ipeps_slab_destroy(ipeps_slab* sl) {
     if (!sl) return;
-    (void)hipDeviceSynchronize();
     if (sl->base) (void)hipFree(sl->base);
     delete sl;
 }
@@ -1956,6 +1957,7 @@ void ipeps_batch_destroy(ipeps_batch* b) {
     if (b->x.norm_ws) (void)hipFree(b->x.norm_ws);
     for (auto& e : b->ev)
         if (e) (void)hipEventDestroy(e);
+    if (b->ev_obs) (void)hipEventDestroy(b->ev_obs);
     delete b;
 }
 
@@ -1977,10 +1979,11 @@ int ipeps_batch_ctmrg(ipeps_batch* b, int iters, int cold_start) {
     });
 }
 
-int ipeps_batch_observe(ipeps_batch* b, ipeps_obs* out) {
-    if (!b || !out) return IPEPS_EINVAL;
+int ipeps_batch_observe_async(ipeps_batch* b) {
+    if (!b) return IPEPS_EINVAL;
     ipeps_state* L = b->x.st;
     return wrap(L, [&] {
+        IPEPS_REQUIRE(!b->obs_pending, IPEPS_EINVAL, "batch: a readout is pending");
         for (ipeps_state* j : b->x.jobs) {
             check_poison(j);
             IPEPS_REQUIRE(j->have_env, IPEPS_EINVAL, "no environment: run the CTMRG first");
@@ -1993,17 +1996,50 @@ int ipeps_batch_observe(ipeps_batch* b, ipeps_obs* out) {
             HIP_CHECK(hipMemcpyAsync(j->host_buf + 16, j->eps_snap, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
             HIP_CHECK(hipMemcpyAsync(j->host_buf + 20, j->dev_scalars, sizeof(double), hipMemcpyDeviceToHost, s));
         }
-        HIP_CHECK(hipStreamSynchronize(s));
+        if (!b->ev_obs) HIP_CHECK(hipEventCreateWithFlags(&b->ev_obs, hipEventDisableTiming));
+        HIP_CHECK(hipEventRecord(b->ev_obs, s));
+        b->obs_pending = true;
+    });
+}
+
+int ipeps_batch_query(ipeps_batch* b) {
+    if (!b) return IPEPS_EINVAL;
+    if (!b->obs_pending) return IPEPS_EINVAL;
+    const hipError_t e = hipEventQuery(b->ev_obs);
+    if (e == hipSuccess) return 1;
+    if (e == hipErrorNotReady) return 0;
+    (void)hipGetLastError();
+    return IPEPS_EDEVICE;
+}
+
+int ipeps_batch_observe_result(ipeps_batch* b, ipeps_obs* out, int* status) {
+    if (!b || !out) return IPEPS_EINVAL;
+    ipeps_state* L = b->x.st;
+    return wrap(L, [&] {
+        IPEPS_REQUIRE(b->obs_pending, IPEPS_EINVAL, "batch: no readout pending");
+        HIP_CHECK(hipEventSynchronize(b->ev_obs));
+        b->obs_pending = false;
+        int bad = IPEPS_OK;
         for (size_t i = 0; i < b->x.jobs.size(); ++i) {
             ipeps_state* j = b->x.jobs[i];
+            if (status) status[i] = IPEPS_OK;
             try {
                 decode_obs(j->host_buf, j->ctm_step * j->cfg.dt, j->last_iters, &out[i]);
             } catch (const status_error& e) {
-                j->poisoned = true;
-                throw;
+                j->poisoned = true;  // the others' results stand
+                std::memset(&out[i], 0, sizeof(ipeps_obs));
+                if (status) status[i] = e.code;
+                bad = e.code;
             }
         }
+        if (bad != IPEPS_OK) throw status_error(bad, "NaN in the readout of a job of the batch");
     });
+}
+
+int ipeps_batch_observe(ipeps_batch* b, ipeps_obs* out) {
+    const int rc = ipeps_batch_observe_async(b);
+    if (rc != IPEPS_OK) return rc;
+    return ipeps_batch_observe_result(b, out, nullptr);
 }
 
 }  // extern "C"

@@ -1,14 +1,16 @@
 // Request loop with continuous batching.  Jobs are admitted by HBM footprint
 // into slabs (one device allocation per layout: D, chi, d_A, precision,
 // flags), where each keeps its state resident.  One executor thread advances
-// every resident job in rounds: the jobs of one slab that are at the same
-// point of their schedule (first observation or later, the same number of
-// Trotter steps to the next observation, the same CTMRG iteration count) run
-// as one lockstep batch, every kernel launch carrying all of them; the
-// batches of different slabs go to different streams and overlap.  A job
-// that finishes frees its slot at once, a slab with no job left returns its
-// memory, and jobs that arrived meanwhile are admitted at the start of the
-// next round (queue order, skipping jobs that do not fit yet).
+// the resident jobs from observation to observation: the idle jobs of one
+// slab that are at the same point of their schedule (first observation or
+// later, the same number of Trotter steps to the next observation, the same
+// CTMRG iteration count) go as one lockstep batch, every kernel launch
+// carrying all of them, and batches run side by side on the GPU (each slab
+// its own streams) without waiting for each other: a batch that completes
+// hands its jobs back at once, a job that finishes frees its slot, a slab
+// with no job left returns its memory, and jobs that arrived meanwhile are
+// admitted (queue order, skipping jobs that do not fit yet) and batched with
+// the idle jobs of their slab.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -46,6 +48,7 @@ struct Job {
     int slot = -1;
     int done = 0;  // Trotter steps taken
     int nobs = 0;  // observations made
+    bool busy = false;  // in a batch that has not completed yet
 };
 
 bool same_layout(const ipeps_config& a, const ipeps_config& b) {
@@ -152,8 +155,10 @@ void finish(ipeps_server* srv, Job& j, uint64_t id, int rc) {
     (void)id;
 }
 
-// One group of a round: the jobs of one slab at the same point of their
-// schedules, as one batch.
+// A group: idle resident jobs of one slab at the same point of their
+// schedules (first observation or later, the same number of Trotter steps
+// to the next observation, the same CTMRG iteration count), advanced to
+// their next observation as one lockstep batch.
 struct Group {
     Bucket* bucket;
     bool cold;
@@ -163,15 +168,59 @@ struct Group {
     int rc = IPEPS_OK;
 };
 
+// Collect a finished group's readouts into its jobs' series.
+void complete(ipeps_server* srv, Group& g) {
+    std::vector<ipeps_obs> obs(g.ids.size());
+    std::vector<int> status(g.ids.size(), g.rc);
+    if (g.rc == IPEPS_OK) {
+        const int rc = ipeps_batch_observe_result(g.batch, obs.data(), status.data());
+        // a NaN in one job poisons only that job; other failures hit all
+        if (rc != IPEPS_OK && rc != IPEPS_ENUMERIC) status.assign(g.ids.size(), rc);
+    }
+    if (g.batch) ipeps_batch_destroy(g.batch);
+    g.batch = nullptr;
+    for (size_t i = 0; i < g.ids.size(); ++i) {
+        const uint64_t id = g.ids[i];
+        Job& j = srv->jobs[id];
+        j.busy = false;
+        const int rc = status[i];
+        if (rc != IPEPS_OK) {
+            finish(srv, j, id, rc);
+            continue;
+        }
+        j.done += g.chunk;
+        j.nobs++;
+        {
+            std::lock_guard<std::mutex> lk(srv->mu);
+            j.series.push_back(obs[i]);
+        }
+        if (j.done >= j.spec.n_steps) finish(srv, j, id, IPEPS_OK);
+    }
+}
+
 void executor_main(ipeps_server* srv) {
     (void)hipSetDevice(srv->device);
+    std::vector<Group> active;
     for (;;) {
-        std::vector<uint64_t> admitted, resident;
+        bool progress = false;
+        // groups whose readout has completed
+        for (auto it = active.begin(); it != active.end();) {
+            const int q = it->rc == IPEPS_OK ? ipeps_batch_query(it->batch) : 1;
+            if (q == 0) {
+                ++it;
+                continue;
+            }
+            if (q < 0) it->rc = q;
+            complete(srv, *it);
+            it = active.erase(it);
+            progress = true;
+        }
+        std::vector<uint64_t> admitted, idle;
         {
             std::unique_lock<std::mutex> lk(srv->mu);
             for (;;) {
-                // slabs with no job left return their memory first (no work
-                // is in flight between rounds)
+                // a slab with no job left returns its memory (its jobs' work
+                // has completed: each job's batches were waited for)
                 for (auto it = srv->buckets.begin(); it != srv->buckets.end();) {
                     if ((*it)->used() == 0) {
                         srv->used -= (*it)->bytes;
@@ -183,9 +232,9 @@ void executor_main(ipeps_server* srv) {
                     }
                 }
                 admit(srv, admitted);
-                if (srv->running > 0) break;
+                if (srv->running > 0 || !active.empty()) break;
                 if (srv->stopping && srv->pending.empty()) return;
-                if (!srv->pending.empty() && srv->buckets.empty() && srv->running == 0) {
+                if (!srv->pending.empty() && srv->buckets.empty()) {
                     // the first queued job does not fit even alone: fail it
                     Job& j = srv->jobs[srv->pending.front()];
                     j.status = IPEPS_ENOMEM;
@@ -196,7 +245,7 @@ void executor_main(ipeps_server* srv) {
                 srv->cv_work.wait(lk);
             }
             for (auto& kv : srv->jobs)
-                if (kv.second.status == IPEPS_JOB_RUNNING) resident.push_back(kv.first);
+                if (kv.second.status == IPEPS_JOB_RUNNING && !kv.second.busy) idle.push_back(kv.first);
         }
         // states of the newly admitted jobs
         for (uint64_t id : admitted) {
@@ -207,9 +256,9 @@ void executor_main(ipeps_server* srv) {
                 finish(srv, j, id, rc);
             }
         }
-        // group the resident jobs
-        std::vector<Group> groups;
-        for (uint64_t id : resident) {
+        // idle jobs into groups, each launched as a batch (slabs on their own streams)
+        std::vector<Group> fresh;
+        for (uint64_t id : idle) {
             Job& j = srv->jobs[id];
             if (!j.st || j.status != IPEPS_JOB_RUNNING) continue;
             const int every = j.spec.observe_every > 0 ? j.spec.observe_every : j.spec.n_steps;
@@ -217,50 +266,28 @@ void executor_main(ipeps_server* srv) {
             const int iters = j.spec.ctm_iters > 0 ? j.spec.ctm_iters : 10;
             const bool cold = j.nobs == 0;
             Group* g = nullptr;
-            for (auto& gg : groups)
+            for (auto& gg : fresh)
                 if (gg.bucket == j.bucket && gg.cold == cold && gg.chunk == chunk && gg.iters == iters) g = &gg;
             if (!g) {
-                groups.push_back(Group{j.bucket, cold, chunk, iters, {}, nullptr, IPEPS_OK});
-                g = &groups.back();
+                fresh.push_back(Group{j.bucket, cold, chunk, iters, {}, nullptr, IPEPS_OK});
+                g = &fresh.back();
             }
             g->ids.push_back(id);
         }
-        // enqueue every group's Trotter steps and CTMRG (slabs on their own streams) ...
-        for (auto& g : groups) {
+        for (auto& g : fresh) {
             std::vector<ipeps_state*> sts;
-            for (uint64_t id : g.ids) sts.push_back(srv->jobs[id].st);
+            for (uint64_t id : g.ids) {
+                sts.push_back(srv->jobs[id].st);
+                srv->jobs[id].busy = true;
+            }
             g.rc = ipeps_batch_create(sts.data(), (int)sts.size(), &g.batch);
             if (g.rc == IPEPS_OK) g.rc = ipeps_batch_trotter_step(g.batch, g.chunk);
             if (g.rc == IPEPS_OK) g.rc = ipeps_batch_ctmrg(g.batch, g.iters, g.cold ? 1 : 0);
+            if (g.rc == IPEPS_OK) g.rc = ipeps_batch_observe_async(g.batch);
+            active.push_back(std::move(g));
+            progress = true;
         }
-        // ... then read every group out
-        for (auto& g : groups) {
-            std::vector<ipeps_obs> obs(g.ids.size());
-            if (g.rc == IPEPS_OK) g.rc = ipeps_batch_observe(g.batch, obs.data());
-            if (g.batch) ipeps_batch_destroy(g.batch);
-            for (size_t i = 0; i < g.ids.size(); ++i) {
-                const uint64_t id = g.ids[i];
-                Job& j = srv->jobs[id];
-                int rc = g.rc;
-                ipeps_obs o = obs[i];
-                if (rc != IPEPS_OK && rc != IPEPS_ENUMERIC && rc != IPEPS_EINVAL) {
-                    finish(srv, j, id, rc);
-                    continue;
-                }
-                if (rc != IPEPS_OK) rc = ipeps_observe(j.st, &o);  // which job of the batch failed
-                if (rc != IPEPS_OK) {
-                    finish(srv, j, id, rc);
-                    continue;
-                }
-                j.done += g.chunk;
-                j.nobs++;
-                {
-                    std::lock_guard<std::mutex> lk(srv->mu);
-                    j.series.push_back(o);
-                }
-                if (j.done >= j.spec.n_steps) finish(srv, j, id, IPEPS_OK);
-            }
-        }
+        if (!progress) std::this_thread::sleep_for(std::chrono::microseconds(200));
     }
 }
 

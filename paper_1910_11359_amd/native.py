@@ -67,7 +67,8 @@ EXPORTS = [
     "ipeps_observe_async", "ipeps_observe_result", "ff_spectrum_ipr", "ff_neel_dynamics_noalloc",
     "ipeps_profile_read_gemms", "ipeps_slab_region_bytes", "ipeps_slab_create", "ipeps_slab_init",
     "ipeps_slab_destroy", "ipeps_batch_create", "ipeps_batch_trotter_step", "ipeps_batch_ctmrg",
-    "ipeps_batch_observe", "ipeps_batch_destroy",
+    "ipeps_batch_observe", "ipeps_batch_destroy", "ipeps_batch_observe_async", "ipeps_batch_query",
+    "ipeps_batch_observe_result",
 ]
 
 _lib = None
@@ -128,6 +129,9 @@ def load():
     lib.ipeps_batch_trotter_step.argtypes = [C.c_void_p, C.c_int]
     lib.ipeps_batch_ctmrg.argtypes = [C.c_void_p, C.c_int, C.c_int]
     lib.ipeps_batch_observe.argtypes = [C.c_void_p, P(Obs)]
+    lib.ipeps_batch_observe_async.argtypes = [C.c_void_p]
+    lib.ipeps_batch_query.argtypes = [C.c_void_p]
+    lib.ipeps_batch_observe_result.argtypes = [C.c_void_p, P(Obs), P(C.c_int)]
     lib.ipeps_batch_destroy.argtypes = [C.c_void_p]
     lib.ipeps_batch_destroy.restype = None
     lib.ipeps_strerror.argtypes = [C.c_int]
@@ -324,6 +328,17 @@ class Batch:
         buf = (Obs * len(self.states))()
         _check(self._lib.ipeps_batch_observe(self.h, buf), "ipeps_batch_observe")
         return [buf[i].as_dict() for i in range(len(self.states))]
+
+    def observe_status(self):
+        """Readouts and per-job codes (a job whose readout is not finite gets
+        IPEPS_ENUMERIC; the others' results stand)."""
+        _check(self._lib.ipeps_batch_observe_async(self.h), "ipeps_batch_observe_async")
+        buf = (Obs * len(self.states))()
+        st = (C.c_int * len(self.states))()
+        rc = self._lib.ipeps_batch_observe_result(self.h, buf, st)
+        if rc not in (IPEPS_OK, IPEPS_ENUMERIC):
+            _check(rc, "ipeps_batch_observe_result")
+        return [buf[i].as_dict() for i in range(len(self.states))], list(st)
 
     def close(self):
         if getattr(self, "h", None):

@@ -96,3 +96,40 @@ def test_batch_rejects_mixed_layouts_and_foreign_states():
     for s in (a, b, s1):
         s.close()
     slab.close()
+
+
+def test_nan_in_one_job_leaves_the_others():
+    """Job 1 of a batch of three starts from a state with a NaN: its readout
+    reports IPEPS_ENUMERIC and it is poisoned; jobs 0 and 2 give what they
+    give alone."""
+    import synthetic
+    cfgs = [_cfg(3, 12, "fp64", 0, p) for p in PARAMS]
+    gam, lam = synthetic.random_state(11, 3)
+    bad = gam.copy()
+    bad[0, 0, 0, 0, 0, 0] = np.nan
+    ref = []
+    for i in (0, 2):
+        st = P.State(cfgs[i])
+        st.set_state(gam, lam)
+        st.trotter_step(1)
+        st.ctmrg(0.0, 3, True)
+        ref.append(st.observe())
+        st.close()
+    slab = P.Slab(cfgs[0], 3)
+    sts = [slab.state(i, cfgs[i]) for i in range(3)]
+    for i, st in enumerate(sts):
+        st.set_state(bad if i == 1 else gam, lam)
+    b = P.Batch(sts)
+    b.trotter_step(1)
+    b.ctmrg(3, True)
+    obs, status = b.observe_status()
+    b.close()
+    assert status == [0, -4, 0], status
+    for o, r in zip((obs[0], obs[2]), ref):
+        assert o["imbalance"] == r["imbalance"] and np.array_equal(o["n"], r["n"])
+    with pytest.raises(P.IpepsError) as e:
+        sts[1].ctmrg(0.0, 1, True)
+    assert e.value.code == -4
+    for st in sts:
+        st.close()
+    slab.close()
