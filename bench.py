@@ -26,9 +26,15 @@ precision over the measured step time; fp64_gemms covers the FP64 products
 of the projector SVDs.  With a precision other than FP64 the same schedule
 also runs in FP64 and in the other contraction precisions (fp32, bf16x3 =
 split BF16, bf16); precision_vs_fp64 compares their imbalance with FP64 at
-t = 1 after 10 cold CTMRG iterations.  serving runs a bounded sample of
-the request stream in the chosen precision and in FP64 and reports jobs/s,
-p50/p99 latency and the largest imbalance difference between the two.
+t = 1 after 10 cold CTMRG iterations.
+
+sweep: batched jobs/s of the 64-job parameter sweep through the request loop
+(jobs of one D advance as one lockstep batch) in the contraction precision,
+split BF16 and FP64, with the largest imbalance difference from FP64 over
+all observations.  serving: the first requests of the serving stream at
+their own shapes (D up to 8, chi up to 128), Poisson arrivals at 0.8 x the
+sweep's capacity, p50/p99 latency and jobs/s in the contraction precision
+and in FP64.
 cpu_baseline is the oracle (complex128 NumPy) timed on a bounded sample of
 the same step and scaled to steps/s.
 """
@@ -246,26 +252,24 @@ def free_fermion(P, torch, synthetic, reps=3, with_cpu=True):
     return out
 
 
-def serving_sample(P, synthetic, dtype, n_req=16, rate=8.0, d_max=4, steps_max=40, slots=4):
+def serving_sample(P, synthetic, dtype, rate, n_req=12, steps_max=10, slots=64):
     """Request loop on a bounded sample of the serving stream: the first n_req
-    requests of default_rng(20191025) (D capped at d_max, steps at steps_max,
-    chi = min(128, c D^2)), submitted at their Poisson arrival times (rate per
-    second) into a 4-slot server; latency = completion - arrival."""
+    requests of default_rng(20191025) at their own shapes (D in 3..8, chi =
+    min(128, c D^2), W, V), Trotter steps capped at steps_max, observed every
+    10 steps with 10 CTMRG iterations, submitted at their Poisson arrival
+    times (rate per second); latency = completion - arrival."""
     reqs = synthetic.serving_stream(n=n_req, rate=rate)
     srv = P.Server(hbm_budget=0, max_slots=slots)
     t0 = time.perf_counter()
     ids = []
     for r in reqs:
-        D = min(r["D"], d_max)
-        chi = min(128, max(D * D, (r["chi"] // (r["D"] ** 2)) * D * D))
-        cfg = P.make_config(D, chi, J=r["J"], V=r["V"], W=r["W"], dt=r["dt"], dtype=dtype)
+        cfg = P.make_config(r["D"], r["chi"], J=r["J"], V=r["V"], W=r["W"], dt=r["dt"], dtype=dtype)
         while time.perf_counter() - t0 < r["arrival"]:
             time.sleep(0.001)
-        ids.append((srv.submit(cfg, n_steps=min(r["n_steps"], steps_max),
-                               observe_every=r["observe_every"], ctm_iters=r["ctm_iters"]),
-                    r["arrival"]))
+        ids.append(srv.submit(cfg, n_steps=min(r["n_steps"], steps_max), observe_every=r["observe_every"],
+                              ctm_iters=r["ctm_iters"]))
     lat, t_last, series = [], 0.0, []
-    for jid, arr in ids:
+    for jid in ids:
         while True:
             res = srv.poll(jid)[1]
             if res is not None:
@@ -275,21 +279,23 @@ def serving_sample(P, synthetic, dtype, n_req=16, rate=8.0, d_max=4, steps_max=4
         rc, (ts, ta, td) = srv.times(jid)
         lat.append(td - ts)
         t_last = max(t_last, td)
-    t_first = min(srv.times(j)[1][0] for j, _ in ids)
+    t_first = min(srv.times(j)[1][0] for j in ids)
     srv.close()
     lat = sorted(lat)
     pct = lambda q: lat[min(len(lat) - 1, int(q * len(lat)))]
+    shapes = sorted({(r["D"], r["chi"]) for r in reqs})
     return {"jobs_per_s": len(ids) / (t_last - t_first), "p50_s": pct(0.5), "p99_s": pct(0.99),
-            "requests": len(ids), "rate_per_s": rate, "slots": slots, "dtype": dtype,
-            "sample": f"first {n_req} requests of the serving stream, D capped at {d_max}, "
-                      f"steps at {steps_max}, observe every 10 with 10 warm CTMRG iterations"}, series
+            "requests": len(ids), "rate_per_s": rate, "dtype": dtype,
+            "sample": f"first {n_req} requests of the serving stream at their shapes (D, chi) = {shapes}, "
+                      f"Trotter steps capped at {steps_max}, observe every 10 with 10 CTMRG iterations"}, series
 
 
 def sweep(P, synthetic, dtype, slots=64):
     """The batched parameter sweep: 64 jobs (D in 3..6 with chi = 2 D^2, V in
     {0, 1}, 8 seeded W in [1, 20]), 50 Trotter steps each, 10 CTMRG
-    iterations every 10 steps, all submitted at once to a request loop with
-    `slots` concurrent jobs.  Returns jobs/s and the whole duration."""
+    iterations every 10 steps, all submitted at once to the request loop
+    (jobs of one D run as one lockstep batch).  Returns jobs/s, the duration
+    and the imbalance series."""
     jobs = synthetic.sweep_jobs()
     srv = P.Server(hbm_budget=0, max_slots=slots)
     t0 = time.perf_counter()
@@ -297,19 +303,24 @@ def sweep(P, synthetic, dtype, slots=64):
                                     dtype=dtype),
                       n_steps=j["n_steps"], observe_every=j["observe_every"],
                       ctm_iters=j["ctm_iters"]) for j in jobs]
-    done = 0
+    series = []
     for jid in ids:
-        while srv.poll(jid)[1] is None:
+        while True:
+            res = srv.poll(jid)[1]
+            if res is not None:
+                break
             time.sleep(0.005)
-        done += 1
-        print(f"sweep {dtype}: {done}/{len(ids)} jobs done after {time.perf_counter() - t0:.1f} s",
-              file=sys.stderr, flush=True)
+        series.append([o["imbalance"] for o in res])
     dt = time.perf_counter() - t0
+    print(f"sweep {dtype}: {len(ids)} jobs in {dt:.1f} s", file=sys.stderr, flush=True)
     srv.close()
-    return {"jobs": len(ids), "seconds": dt, "jobs_per_s": len(ids) / dt, "slots": slots,
-            "dtype": dtype,
+    return {"jobs": len(ids), "seconds": dt, "jobs_per_s": len(ids) / dt, "dtype": dtype,
             "workload": "64 jobs: D in {3,4,5,6}, chi = 2D^2, V in {0,1}, W = 8 seeded values "
-                        "in [1,20]; 50 steps, 10 CTMRG iterations every 10 steps"}
+                        "in [1,20]; 50 steps, 10 CTMRG iterations every 10 steps"}, series
+
+
+def max_err(a, b):
+    return max(abs(x - y) for sa, sb in zip(a, b) for x, y in zip(sa, sb))
 
 
 def headline(P, torch, wl, dtype, steps, warmup, prelude, flags=0, prof_steps=3):
@@ -423,8 +434,8 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-free-fermion", action="store_true",
                     help="skip the free-fermion Néel workload (L=40, 100 realizations)")
-    ap.add_argument("--sweep", action="store_true",
-                    help="also run the 64-job batched sweep through the request loop")
+    ap.add_argument("--no-sweep", action="store_true",
+                    help="skip the 64-job batched sweep through the request loop")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="also copy MIB MiB device to device once (reference kernel for HBM counters)")
     args = ap.parse_args()
@@ -494,20 +505,30 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         out["copy_probe_bytes"] = 2 * src.numel() * 4
+    if not args.no_sweep:
+        # batched jobs/s: the 64-job sweep in the contraction precision, split
+        # BF16 and FP64, each with its largest imbalance difference from FP64
+        sw, ser = sweep(P, synthetic, args.dtype)
+        sw64, ser64 = sweep(P, synthetic, "fp64")
+        sw["fp64_jobs_per_s"] = sw64["jobs_per_s"]
+        sw["max_imbalance_err_vs_fp64"] = max_err(ser, ser64)
+        if args.dtype != "bf16x3":
+            swb, serb = sweep(P, synthetic, "bf16x3")
+            sw["bf16x3_jobs_per_s"] = swb["jobs_per_s"]
+            sw["bf16x3_max_imbalance_err_vs_fp64"] = max_err(serb, ser64)
+        out["sweep"] = sw
     if not args.no_serving:
-        srv, ser = serving_sample(P, synthetic, args.dtype)
+        # requests arrive at 0.8 x the measured capacity of the sweep mix
+        cap = out["sweep"]["jobs_per_s"] if "sweep" in out else 1.0
+        srv, ser = serving_sample(P, synthetic, args.dtype, rate=0.8 * cap)
+        srv64, ser64 = serving_sample(P, synthetic, "fp64", rate=0.8 * cap)
+        srv["fp64_jobs_per_s"] = srv64["jobs_per_s"]
+        srv["fp64_p50_s"], srv["fp64_p99_s"] = srv64["p50_s"], srv64["p99_s"]
+        srv["max_imbalance_err_vs_fp64"] = max_err(ser, ser64)
+        srv["rate_note"] = "0.8 x the sweep's jobs/s in the contraction precision"
         out["serving"] = srv
-        if args.dtype != "fp64":
-            srv64, ser64 = serving_sample(P, synthetic, "fp64")
-            err = max(abs(a - b) for x, y in zip(ser, ser64) for a, b in zip(x, y))
-            out["serving"]["fp64_jobs_per_s"] = srv64["jobs_per_s"]
-            out["serving"]["max_imbalance_err_vs_fp64"] = err
     if not args.no_free_fermion:
         out["free_fermion"] = free_fermion(P, torch, synthetic, with_cpu=not args.no_cpu_baseline)
-    if args.sweep:
-        out["sweep"] = sweep(P, synthetic, args.dtype)
-        if args.dtype != "fp64" and not args.no_fp64_ref:
-            out["sweep"]["fp64_jobs_per_s"] = sweep(P, synthetic, "fp64")["jobs_per_s"]
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(D, chi, wl["W"], wl["V"])
     print(json.dumps(out), flush=True)
