@@ -3,23 +3,27 @@ t=5) on the device against oracle values stored in tests/golden/ (written by
 tests/golden/make_plain_golden.py, which calls only oracle/).
 
 Every 10 steps CTMRG runs from a cold start until the corner spectra move by
-less than 1e-10 in one iteration (capped at the golden's max_iter, the same
-cap the oracle used).
+less than 1e-10 in one iteration, capped at the iteration count the golden
+records for that observation (the oracle's own cap).
 
 The simple-update trajectory can be ill-conditioned: near-degenerate bond
 weights make it amplify a rounding difference by ~3x per step (W=2, V=0
 after t=3).  Each golden observation therefore carries "su_spread", the
 oracle's own bond-spectrum change when its start is perturbed by 1e-15
-relative.  Tolerances at an observation, with a = 1e3 * su_spread (device and
-oracle differ by many roundings per step, not one):
+relative.  The device differs from the oracle by roundings of the same size
+at every step; the measured largest bond-spectrum difference over su_spread
+is 1.5 (W=2, V=0), 1.9 (W=10, V=0), 2.1 (W=10, V=1) and 14 (W=2, V=1, where
+both are ~1e-14, far below the 1e-10 floor), so the tolerances are
+a = SPREAD_FACTOR = 10 times su_spread, with floors:
 * imbalance and occupations: max(1e-6, a); truncation errors and bond
   spectra: max(1e-10, a);
 * corner spectra, where both the device and the oracle converged and
-  a < 1e-10: 2-norms of near-degenerate clusters to 1e-8 and single entries
-  to 1e-6 (an unconverged iterate's spectra are rounding-sensitive);
+  a < 1e-10: entry by entry to 1e-8 sigma_1, clusters of values within
+  1e-6 relative of each other through their 2-norm (tests/_parity.py);
 * observations with a > 1e-3 lie past the trajectory's predictability
   horizon and are not compared; at least the first half of the
   observations must be inside it.
+The achieved maxima are printed (pytest -s).
 """
 import json
 import os
@@ -48,6 +52,9 @@ def _golden(W, V):
     return g
 
 
+SPREAD_FACTOR = 10.0
+
+
 @pytest.mark.parametrize("W,V", CASES)
 def test_plain_fp64_against_oracle_goldens(W, V):
     g = _golden(W, V)
@@ -56,25 +63,34 @@ def test_plain_fp64_against_oracle_goldens(W, V):
                                dt=cfg["dt"]))
     obs = {o["step"]: o for o in g["obs"]}
     compared = 0
+    worst = {"dI": 0.0, "bond/spread": 0.0, "entry": 0.0, "cluster": 0.0}
     for step in range(0, cfg["n_steps"] + 1):
         if step > 0:
             st.trotter_step(1)
         if step not in obs:
             continue
         o = obs[step]
-        a = 1e3 * o["su_spread"]
+        a = SPREAD_FACTOR * o["su_spread"]
         if a > 1e-3:
             continue
         compared += 1
-        it, dl = st.ctmrg(g["tol"], g["max_iter"], True, allow_notconv=True)
+        cap = o.get("max_iter", g["max_iter"])
+        it, dl = st.ctmrg(g["tol"], cap, True, allow_notconv=True)
         got = st.observe()
         tol_obs, tol_su = max(1e-6, a), max(1e-10, a)
-        assert abs(got["imbalance"] - o["imbalance"]) < tol_obs, (step, got["imbalance"], o["imbalance"])
+        dI = abs(got["imbalance"] - o["imbalance"])
+        db = float(np.max(np.abs(st.bond_spectra() - np.array(o["bond_spectra"]))))
+        worst["dI"] = max(worst["dI"], dI)
+        if o["su_spread"] > 0:
+            worst["bond/spread"] = max(worst["bond/spread"], db / o["su_spread"])
+        assert dI < tol_obs, (step, got["imbalance"], o["imbalance"])
         assert np.max(np.abs(got["n"] - np.array(o["n"]))) < tol_obs, step
         assert np.max(np.abs(got["eps"] - np.array(o["eps"]))) < tol_su, step
-        assert np.max(np.abs(st.bond_spectra() - np.array(o["bond_spectra"]))) < tol_su, step
+        assert db < tol_su, (step, db, tol_su)
         if o["ctm_delta"] < g["tol"] and dl < g["tol"] and a < 1e-10:
-            cl, en = par.spectra_errors(st.corner_spectra(), np.array(o["corner_spectra"]))
-            assert cl < 1e-8 and en < par.ENTRY_TOL, (step, cl, en)
+            en, cl = par.converged_spectra_errors(st.corner_spectra(), np.array(o["corner_spectra"]))
+            worst["entry"], worst["cluster"] = max(worst["entry"], en), max(worst["cluster"], cl)
+            assert en < par.CONVERGED_TOL and cl < par.CONVERGED_TOL, (step, en, cl)
+    print(f"W={W} V={V}: {compared} observations compared, worst {worst}", flush=True)
     assert compared >= (len(obs) + 1) // 2, compared
     st.close()
