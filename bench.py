@@ -58,7 +58,10 @@ ROOF_KERNEL = "k_gemm_direct<...,TAG=1> (8 enlarged-corner products)"
 # traffic profile in profiles/; valid only for the tile planning, kernels
 # and launches they were measured on (the part of gemm.hip from tile_dims
 # on, see gemm_kernel_digest).  Keyed by contraction precision.
-TRAFFIC = {}
+TRAFFIC = {"fp32": {"kernel": "gemm_family", "gemm_kernel_sha256_16": "38718641a46a7d03",
+                    "bytes_per_launch": 1.4166e8,
+                    "note": "FETCH_SIZE + WRITE_SIZE per GEMM launch (with its split-K sum), steady "
+                            "steps, profiles/traffic_contraction_gemms_D6_chi72_fp32.md"}}
 
 
 def gemm_kernel_digest():
@@ -404,14 +407,15 @@ def gemm_roofline(rec, dtype):
     enlarged corners, the cut-matrix chains, the projectors and the C / T
     renormalisation; main stream), as one kernel family: algorithmic flops
     per launch over the mean HIP-event launch time."""
-    ms, fl, n = rec["gemm"][dtype]
+    ms, fl, by, n = rec["gemm"][dtype]
     ach = fl / (ms * 1e-3) / 1e12 if ms > 0 else 0.0
     return {"bound": "mfma", "achieved": ach, "peak": PEAK_TFLOPS[dtype], "unit": "TFLOP/s",
             "frac": ach / PEAK_TFLOPS[dtype], "traffic": None,
             "kernel": f"k_gemm_direct / k_gemm_grouped in {dtype}: every environment-contraction GEMM "
                       f"launch of the timed steps (main stream)",
             "launches_per_step": n / rec["prof_steps"], "launch_ms": ms / max(1, n),
-            "flops_per_launch": fl / max(1, n), "ms_per_step": ms / rec["prof_steps"],
+            "flops_per_launch": fl / max(1, n), "algorithmic_bytes_per_launch": by / max(1, n),
+            "ms_per_step": ms / rec["prof_steps"],
             "timing": f"HIP events around every such launch during {rec['prof_steps']} profiled steps "
                       f"after the timed ones"}
 
@@ -460,7 +464,8 @@ def main():
     if (tr and tr["bytes_per_launch"] and tr["kernel"] == "gemm_family"
             and gemm_kernel_digest() == tr["gemm_kernel_sha256_16"]):
         roof["traffic"] = tr["bytes_per_launch"]
-    ms64, fl64, n64 = rec["gemm"]["fp64"]
+        roof["traffic_note"] = tr["note"]
+    ms64, fl64, _, n64 = rec["gemm"]["fp64"]
     out = {
         "metric": METRIC, "value": rec["value"], "unit": "steps/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": rec["ms_per_step"], "higher_is_better": True,

@@ -336,13 +336,15 @@ void ipeps_batch_destroy(ipeps_batch* b);
  * algorithmic flops of one of them (2 M N K summed over its products), then
  * clears the record.  ipeps_profile_read_gemms synchronises and returns, for
  * the recorded launches whose arithmetic is `dtype` (IPEPS_DTYPE_*), their
- * summed time, summed algorithmic flops and number, without clearing.
+ * summed time, summed algorithmic flops, summed algorithmic bytes (each
+ * operand read once and each result written once, in the storage
+ * precision) and number, without clearing.
  * Errors: EINVAL. */
 int ipeps_profile(ipeps_state* st, int enable);
 int ipeps_profile_read(ipeps_state* st, double* total_ms, int* launches,
                        double* flops_per_launch);
 int ipeps_profile_read_gemms(ipeps_state* st, int dtype, double* total_ms, double* flops,
-                             int* launches);
+                             double* bytes, int* launches);
 
 const char* ipeps_strerror(int code);
 

@@ -194,8 +194,10 @@ GemmGroup add_group(ipeps_state* st, std::vector<GemmProb> probs, int dtype, int
             g.tiles = gemm_plan_with(probs.data(), g.count, dtype, t);
         }
     }
+    const double esz = dtype == IPEPS_DTYPE_FP64 ? 8.0 : 4.0;  // BF16 modes keep FP32 operands
     for (auto& p : probs) {
         g.flops += 2.0 * p.M * (double)p.N * p.K;
+        g.bytes += esz * ((double)p.M * p.K + (double)p.K * p.N + (double)p.M * p.N);
         st->probs.push_back(p);
     }
     if (g.count > 0) st->groups.push_back(g);
@@ -257,7 +259,7 @@ void run(const Ex& x, const GemmGroup& g) {
     if (timed) {
         HIP_CHECK(hipEventRecord(st->prof_ev[st->prof_used + 1], st->stream));
         st->prof_used += 2;
-        st->prof_meta.push_back({g.flops, g.dtype, g.tag});
+        st->prof_meta.push_back({g.flops, g.bytes, g.dtype, g.tag});
         if (g.tag == 1) st->prof_flops = g.flops;
     }
 }
@@ -1665,11 +1667,12 @@ int ipeps_profile_read(ipeps_state* st, double* total_ms, int* launches, double*
     });
 }
 
-int ipeps_profile_read_gemms(ipeps_state* st, int dtype, double* total_ms, double* flops, int* launches) {
+int ipeps_profile_read_gemms(ipeps_state* st, int dtype, double* total_ms, double* flops, double* bytes,
+                             int* launches) {
     if (!st) return IPEPS_EINVAL;
     return wrap(st, [&] {
         HIP_CHECK(hipStreamSynchronize(st->stream));
-        double tot = 0, fl = 0;
+        double tot = 0, fl = 0, by = 0;
         int cnt = 0;
         for (int i = 0; i + 1 < st->prof_used; i += 2) {
             const auto& m = st->prof_meta[i / 2];
@@ -1678,10 +1681,12 @@ int ipeps_profile_read_gemms(ipeps_state* st, int dtype, double* total_ms, doubl
             HIP_CHECK(hipEventElapsedTime(&ms, st->prof_ev[i], st->prof_ev[i + 1]));
             tot += ms;
             fl += m.flops;
+            by += m.bytes;
             ++cnt;
         }
         if (total_ms) *total_ms = tot;
         if (flops) *flops = fl;
+        if (bytes) *bytes = by;
         if (launches) *launches = cnt;
     });
 }

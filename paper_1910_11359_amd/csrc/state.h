@@ -32,6 +32,7 @@ struct GemmGroup {
     int tag = 0;       // 1: the n^3 half-system products (own kernel symbol)
     long reduce_elems = 0;  // largest M*N of a split-K problem (0: none)
     double flops = 0;  // algorithmic flops of the whole launch
+    double bytes = 0;  // algorithmic bytes: every operand read once, the result written once
 };
 
 struct ColumnStep {
@@ -236,7 +237,7 @@ struct ipeps_state {
     int prof_used;
     double prof_flops;
     struct ProfLaunch {
-        double flops;
+        double flops, bytes;
         int dtype, tag;
     };
     std::vector<ProfLaunch> prof_meta;  // one per recorded event pair

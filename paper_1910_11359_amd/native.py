@@ -112,7 +112,8 @@ def load():
     lib.solve_server_destroy.restype = None
     lib.ipeps_profile.argtypes = [C.c_void_p, C.c_int]
     lib.ipeps_profile_read.argtypes = [C.c_void_p, P(C.c_double), P(C.c_int), P(C.c_double)]
-    lib.ipeps_profile_read_gemms.argtypes = [C.c_void_p, C.c_int, P(C.c_double), P(C.c_double), P(C.c_int)]
+    lib.ipeps_profile_read_gemms.argtypes = [C.c_void_p, C.c_int, P(C.c_double), P(C.c_double), P(C.c_double),
+                                             P(C.c_int)]
     lib.ff_neel_dynamics.argtypes = [C.c_int, C.c_int, C.c_double, C.c_double, C.c_int, C.c_int,
                                      C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
     lib.ff_neel_dynamics_noalloc.argtypes = lib.ff_neel_dynamics.argtypes
@@ -256,12 +257,13 @@ class State:
         _check(self._lib.ipeps_profile(self.h, mode), "ipeps_profile")
 
     def profile_read_gemms(self, dtype):
-        """(summed ms, summed algorithmic flops, launches) of the recorded GEMM
-        launches whose arithmetic is dtype ('fp64', 'fp32', 'bf16', 'bf16x3')."""
-        ms, fl, n = C.c_double(), C.c_double(), C.c_int()
+        """(summed ms, summed algorithmic flops, summed algorithmic bytes,
+        launches) of the recorded GEMM launches whose arithmetic is dtype
+        ('fp64', 'fp32', 'bf16', 'bf16x3')."""
+        ms, fl, by, n = C.c_double(), C.c_double(), C.c_double(), C.c_int()
         _check(self._lib.ipeps_profile_read_gemms(self.h, DTYPES[dtype], C.byref(ms), C.byref(fl),
-                                                  C.byref(n)), "ipeps_profile_read_gemms")
-        return ms.value, fl.value, n.value
+                                                  C.byref(by), C.byref(n)), "ipeps_profile_read_gemms")
+        return ms.value, fl.value, by.value, n.value
 
     def profile_read(self):
         ms, n, fl = C.c_double(), C.c_int(), C.c_double()
