@@ -260,6 +260,12 @@ int solve_poll(ipeps_server* srv, uint64_t job_id, int* status, ipeps_obs* serie
 int solve_job_times(ipeps_server* srv, uint64_t job_id, double* t_submit, double* t_admit,
                     double* t_done);
 
+/* enable != 0: the batches the loop launches replay their warm CTMRG
+ * iterations from captured graphs (ipeps_batch_set_graph); a group whose
+ * jobs all go on keeps its batch, and its graph, for its next chunk.
+ * Applies to batches created afterwards.  Errors: EINVAL (NULL). */
+int solve_server_set_graphs(ipeps_server* srv, int enable);
+
 /* Wait for all jobs, stop the loop and release everything. */
 void solve_server_destroy(ipeps_server* srv);
 
@@ -308,6 +314,19 @@ int ipeps_batch_trotter_step(ipeps_batch* b, int n_steps);
 /* ctmrg_converge with tol <= 0 for every job: exactly iters iterations,
  * cold (cold_start != 0) or warm. */
 int ipeps_batch_ctmrg(ipeps_batch* b, int iters, int cold_start);
+/* enable != 0: from the second iteration of each ipeps_batch_ctmrg call on,
+ * replay one warm iteration (the eight column steps of section Readout, the
+ * corner snapshot and the previous iteration's spectra) from a HIP graph
+ * captured from the lead's main stream on first use and kept until
+ * ipeps_batch_destroy; results equal the eager launches bit for bit (the
+ * random restarts of dropped subspace columns draw from counters kept on
+ * the device).  Capture and instantiation happen on the calling thread and
+ * cost about one iteration's launch time; the replays save the per-launch
+ * host work, which dominates at small D and chi.  The capture runs on a
+ * stream of the batch's own (the lead's stream may be the null stream), the
+ * replays on the lead's stream.  Default: off.  Errors: EINVAL (NULL),
+ * EDEVICE. */
+int ipeps_batch_set_graph(ipeps_batch* b, int enable);
 /* ipeps_observe for every job: out[i] for states[i].  Synchronises.
  * Errors: EINVAL, ENUMERIC (a job's readout is not finite: that job is
  * poisoned and its out[i] zeroed, the other jobs' results are valid). */

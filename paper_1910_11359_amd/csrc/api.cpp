@@ -376,6 +376,7 @@ void allocate(ipeps_state* st) {
             for (int i = 0; i < 3; ++i) st->Ch[i] = M.get(2 * nk * e);
     }
     st->dead_dev = (int*)M.get((2L * k + 2) * sizeof(int));
+    st->refill_ctr = (uint64_t*)M.get(2 * sizeof(uint64_t));
     st->norm_ws = (double*)M.get(normalize_ws_doubles(32) * sizeof(double));
     st->norm_ws_su = (double*)M.get(normalize_ws_doubles(4) * sizeof(double));
     st->Cs = (double*)M.get(2L * k * k * sizeof(double));
@@ -889,6 +890,8 @@ void set_neel(ipeps_state* st) {
     HIP_CHECK(hipMemcpyAsync(st->gam, g.data(), g.size() * sizeof(cplx), hipMemcpyHostToDevice, st->stream));
     HIP_CHECK(hipMemcpyAsync(st->lam, lam.data(), lam.size() * sizeof(double), hipMemcpyHostToDevice, st->stream));
     HIP_CHECK(hipMemsetAsync(st->eps, 0, 4 * sizeof(double), st->stream));
+    const uint64_t ctr[2] = {st->cfg.seed, 0};  // refill seed and call count
+    HIP_CHECK(hipMemcpyAsync(st->refill_ctr, ctr, sizeof(ctr), hipMemcpyHostToDevice, st->stream));
     HIP_CHECK(hipEventRecord(st->ev_gamma_free, st->stream));
     HIP_CHECK(hipStreamSynchronize(st->stream));
 }
@@ -970,18 +973,14 @@ void orth(const Ex& x, double* X, double* Q, const GemmGroup& gram1, const GemmG
     chol_inverse(s, 2, k, st->Gm, st->Ri, kCholDrop, refill ? st->dead_dev : nullptr, 0.0, x.jm);
     run(x, mul1);
     if (refill) {
-        // each job's own random stream (its seed, its call counter); the
-        // launches return at once for a job that dropped nothing
-        for (ipeps_state* j : x.jobs) {
-            const uint64_t seed = j->cfg.seed * 0x9E3779B97F4A7C15ull + 0x632BE59BD9B4E019ull * ++j->orth_calls;
-            dead_fill(s, 2, n, k, j->dead_dev, seed, j->Rb);
-        }
+        // each job's own random stream (its seed, its device-side call
+        // counter); the blocks of a job that dropped nothing return at once
+        dead_fill(s, 2, n, k, st->dead_dev, st->refill_ctr, st->Rb, x.jm);
         for (int pass = 0; pass < 2; ++pass) {
             run(x, *proj1);  // Gm = Q^T Rb
             run(x, *proj2);  // Rb -= Q Gm
         }
-        for (int j = 0; j < x.nj(); ++j)
-            add_gated(s, 2, (long)n * k, x.jobs[j]->dead_dev + 2 * k, x.jobs[j]->Rb, x.at(Q, j));
+        add_gated(s, 2, (long)n * k, st->dead_dev + 2 * k, st->Rb, Q, x.jm);
     }
     if (!two_pass) return;
     run(x, gram2);
@@ -1097,7 +1096,9 @@ void launch_deferred_spectra(const Ex& x, hipEvent_t after) {
     if (!st->spec_deferred) return;
     const int chi = st->chi;
     hipStream_t ss = st->spec_stream;
-    HIP_CHECK(hipStreamWaitEvent(ss, st->ev_c64_ready, 0));
+    // under capture the spectra stream forks from the main stream at `after`,
+    // which the snapshot precedes
+    if (!st->capturing) HIP_CHECK(hipStreamWaitEvent(ss, st->ev_c64_ready, 0));
     if (after) HIP_CHECK(hipStreamWaitEvent(ss, after, 0));
     // spectra are reported to 1e-8 sigma_1 (FP64 corners) and carry the
     // ~1e-7 rounding of FP32 corners: columns below 1e-10 (FP64) or 1e-8
@@ -1105,7 +1106,8 @@ void launch_deferred_spectra(const Ex& x, hipEvent_t after) {
     jacobi_svd_real(ss, 16, chi, chi, st->C64, chi, (long)chi * chi, st->csig, nullptr, nullptr,
                     st->jwork_c, st->dtype == IPEPS_DTYPE_FP64 ? 1e-10 : 1e-8, x.jm);
     // an asynchronous readout may still have to copy the previous Delta
-    HIP_CHECK(hipStreamWaitEvent(ss, st->ev_ro_done, 0));
+    // (under capture the main stream waits for it before the graph's launch)
+    if (!st->capturing) HIP_CHECK(hipStreamWaitEvent(ss, st->ev_ro_done, 0));
     spectra_delta(ss, 16, chi, st->csig, st->spectra, st->spec_prev, st->dev_scalars,
                   st->spec_first ? 1 : 0, x.jm);
     HIP_CHECK(hipEventRecord(st->ev_spec_done, ss));
@@ -1239,11 +1241,51 @@ void trotter_steps(const Ex& x, int n_steps) {
     HIP_CHECK(hipEventRecord(L->ev_su_done, ss));
 }
 
+// One warm CTMRG iteration captured from the lead's main stream into an
+// executable graph (nothing runs).  Valid for the iterations after the first
+// of a call with a fixed count: every projector subspace warm, the left move
+// reusing the down move's corners, the previous iteration's spectra deferred,
+// no added warm iterations.  The plan's buffers and tables are fixed for the
+// life of the jobs (a batch's merged tables for the life of the batch), and
+// the refill seeds count up on the device, so a replay does exactly what
+// the same iteration enqueued eagerly does.
+// The capture runs on `cap`, a stream of the caller's that stands in for the
+// lead's main stream (which may be the null stream, where no capture is
+// possible); the graph is launched on the main stream.
+hipGraphExec_t capture_warm_iteration(const Ex& x, hipStream_t cap) {
+    ipeps_state* L = x.st;
+    hipGraph_t g = nullptr;
+    hipStream_t main_stream = L->stream;
+    HIP_CHECK(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+    L->stream = cap;
+    L->capturing = true;
+    try {
+        for (int si = 0; si < 8; ++si) column_step(x, si);
+        corner_spectra_update(x, false);
+    } catch (...) {
+        L->capturing = false;
+        L->stream = main_stream;
+        (void)hipStreamEndCapture(cap, &g);
+        if (g) (void)hipGraphDestroy(g);
+        throw;
+    }
+    L->capturing = false;
+    L->stream = main_stream;
+    HIP_CHECK(hipStreamEndCapture(cap, &g));
+    hipGraphExec_t ge = nullptr;
+    const hipError_t e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    HIP_CHECK(e);
+    return ge;
+}
+
 // CTMRG iterations of every job (section Readout; appendix).  tol <= 0:
 // exactly max_iter; else until the lead's Delta < tol (one job only).
-// want_delta: the lead's last Delta is read back.
+// want_delta: the lead's last Delta is read back.  graph (tol <= 0 only):
+// the iterations after the first replay the warm-iteration graph held
+// there, captured on stream cap on first use.
 void ctmrg_iterations(const Ex& x, double tol, int max_iter, bool cold_start, bool want_delta, int* it_done,
-                      double* dl) {
+                      double* dl, hipGraphExec_t* graph = nullptr, hipStream_t cap = nullptr) {
     ipeps_state* L = x.st;
     prepare_double_layers(x);
     if (cold_start || !L->have_env) {
@@ -1265,10 +1307,26 @@ void ctmrg_iterations(const Ex& x, double tol, int max_iter, bool cold_start, bo
     // resolved; a fixed iteration count (tol <= 0) keeps the plain schedule.
     L->extra_warm_iters = 0;
     L->corners_warm = false;
+    const bool replay = graph && tol <= 0 && L->extra_warm_iters == 0 && !L->prof_on;
     for (int it = 0; it < max_iter; ++it) {
-        for (int si = 0; si < 8; ++si) column_step(x, si);
-        L->corners_warm = true;  // the next left move may reuse the down move's corners
-        corner_spectra_update(x, false);
+        if (replay && it > 0) {
+            if (!*graph) *graph = capture_warm_iteration(x, cap);
+            HIP_CHECK(hipStreamWaitEvent(L->stream, L->ev_ro_done, 0));
+            HIP_CHECK(hipGraphLaunch(*graph, L->stream));
+            // the graph ends with this iteration's corner snapshot, its
+            // spectra (of the previous one) already joined
+            HIP_CHECK(hipEventRecord(L->ev_spec_done, L->stream));
+            HIP_CHECK(hipEventRecord(L->ev_c64_ready, L->stream));
+            for (ipeps_state* j : x.jobs) {
+                j->spec_deferred = true;
+                j->spec_first = false;
+                j->spectra_valid = true;
+            }
+        } else {
+            for (int si = 0; si < 8; ++si) column_step(x, si);
+            L->corners_warm = true;  // the next left move may reuse the down move's corners
+            corner_spectra_update(x, false);
+        }
         *it_done = it + 1;
         if (tol > 0 || (want_delta && it + 1 == max_iter)) {
             wait_spectra(x);
@@ -1771,6 +1829,9 @@ struct ipeps_batch {
     std::vector<hipEvent_t> ev;  // cross-stream ordering with the jobs' own streams
     hipEvent_t ev_obs = nullptr;  // the pending readout's completion
     bool obs_pending = false;
+    bool use_graph = false;         // replay warm iterations from a captured graph
+    hipGraphExec_t graph = nullptr;  // captured on first use, kept for the batch's life
+    hipStream_t cap = nullptr;       // the stream the capture runs on
 };
 
 namespace {
@@ -1956,6 +2017,8 @@ void ipeps_batch_destroy(ipeps_batch* b) {
         (void)hipStreamSynchronize(b->x.st->su_stream);
         (void)hipStreamSynchronize(b->x.st->spec_stream);
     }
+    if (b->graph) (void)hipGraphExecDestroy(b->graph);
+    if (b->cap) (void)hipStreamDestroy(b->cap);
     if (b->x.d_probs) (void)hipFree(b->x.d_probs);
     if (b->x.d_norms) (void)hipFree(b->x.d_norms);
     if (b->x.jm.delta) (void)hipFree((void*)b->x.jm.delta);
@@ -1980,7 +2043,16 @@ int ipeps_batch_ctmrg(ipeps_batch* b, int iters, int cold_start) {
         for (ipeps_state* j : b->x.jobs) check_poison(j);
         int it = 0;
         double dl = INFINITY;
-        ctmrg_iterations(b->x, 0.0, iters, cold_start != 0, false, &it, &dl);
+        ctmrg_iterations(b->x, 0.0, iters, cold_start != 0, false, &it, &dl,
+                         b->use_graph ? &b->graph : nullptr, b->cap);
+    });
+}
+
+int ipeps_batch_set_graph(ipeps_batch* b, int enable) {
+    if (!b) return IPEPS_EINVAL;
+    return wrap(b->x.st, [&] {
+        if (enable && !b->cap) HIP_CHECK(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
+        b->use_graph = enable != 0;
     });
 }
 

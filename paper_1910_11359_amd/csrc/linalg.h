@@ -45,11 +45,15 @@ void normalize_columns(hipStream_t s, int batch, int n, int k, double* X);
 // R (batched n x k row-major, flags as written by chol_inverse): column j
 // uniform in [-1, 1) from a counter hash of (seed, element) where
 // dead[b*k + j] != 0, zero elsewhere; matrices with no dropped column are
-// left untouched.
-void dead_fill(hipStream_t s, int batch, int n, int k, const int* dead, uint64_t seed, double* R);
+// left untouched.  The seed comes from ctr = {config seed, calls} on the
+// device (seed * C1 + C2 * (calls + 1)), and the call count is advanced
+// afterwards (once per call, for every job of jm).
+void dead_fill(hipStream_t s, int batch, int n, int k, const int* dead, uint64_t* ctr, double* R,
+               JobMap jm = JobMap());
 
 // X_b[e] += Y_b[e] for e < count, for the batches b with gate[b] != 0
-// (matrix b at offset b*count).
-void add_gated(hipStream_t s, int batch, long count, const int* gate, const double* Y, double* X);
+// (matrix b at offset b*count), for every job of jm.
+void add_gated(hipStream_t s, int batch, long count, const int* gate, const double* Y, double* X,
+               JobMap jm = JobMap());
 
 }  // namespace ipeps

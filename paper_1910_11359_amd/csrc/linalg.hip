@@ -467,6 +467,156 @@ __global__ __launch_bounds__(256) void k_chol_inverse(int k, const double* __res
     }
 }
 
+// k <= 128: right-looking in registers, one barrier per pivot.  Thread
+// (rb, cb) holds the 4 x 8 block at rows 4 rb.., columns 8 cb.. of the k x k
+// working matrix W (column-block-major, so the waves whose columns are all
+// factored drop out).  Row r of W holds the Schur complement S of the scaled
+// Gram until pivot r is taken (both triangles, kept symmetric), then row r of
+// the matrix V that becomes R'^{-1}: X R' = I is solved left to right, so at
+// pivot j column j of X is final (X[i][j] = V[i][j] / R'[j][j], V[j][j] = 1)
+// and its contribution V[i][c] -= X[i][j] R'[j][c] (i <= j < c) goes out at
+// once from the row R'[j][.] = S[j][.] / R'[j][j] the trailing update uses.
+// Every element (r, c > j) then takes one fused multiply-add with the
+// coefficient W[r][j] (V[r][j] above the pivot, S[j][r] = S[r][j] below it;
+// 1 + S[j][j] on the pivot row, which turns S[j][c] into V[j][c] =
+// -S[j][c] / S[j][j]).  Pivot j's row (zero at and left of j) and column go
+// through LDS, double-buffered; the pivot loop is unrolled by 8 so that the
+// register holding them is known at compile time.  A dropped pivot has
+// 1/R'[j][j] = 0: its row of R' and its row and column of X are zero.
+constexpr int kCholThreads = 512, kCholRB = 4, kCholCB = 8;
+
+template <int U>
+struct CholStep {
+    static constexpr int value = U;
+};
+
+__global__ __launch_bounds__(kCholThreads) void k_chol_inverse_reg(int k, const double* __restrict__ G,
+                                                                 double* __restrict__ Rinv, double tol,
+                                                                 int* __restrict__ dead, double near_identity,
+                                                                 JobMap jm, int nbatch) {
+    __shared__ double rowbuf[2][128];
+    __shared__ double colbuf[2][128];
+    __shared__ double dbuf[2];
+    __shared__ int dead_s[128];
+    __shared__ double dsc[128];  // 1/sqrt(G_ii)
+    __shared__ double ipv[128];  // 1/R'[j][j], 0 for a dropped pivot
+    __shared__ double red[kCholThreads / 64];
+    const int tid = threadIdx.x;
+    const int b = jlocal(jm, blockIdx.x);
+    G = jptr(G, jm, blockIdx.x);
+    Rinv = jptr(Rinv, jm, blockIdx.x);
+    dead = jptr(dead, jm, blockIdx.x);
+    const double* Gb = G + (long)b * k * k;
+    double* out = Rinv + (long)b * k * k;
+    const int RB = (k + kCholRB - 1) / kCholRB, CB = (k + kCholCB - 1) / kCholCB;
+    const int cb = tid / RB, rb = tid - (tid / RB) * RB;
+    const bool act = cb < CB;
+    const int r0 = kCholRB * rb, c0 = kCholCB * cb;
+    for (int i = tid; i < 128; i += kCholThreads) {
+        const double gii = i < k ? Gb[(long)i * k + i] : 0.0;
+        dsc[i] = gii > 0.0 ? 1.0 / sqrt(gii) : 0.0;
+        colbuf[0][i] = colbuf[1][i] = 0.0;
+        rowbuf[0][i] = rowbuf[1][i] = 0.0;
+    }
+    __syncthreads();
+    double w[kCholRB][kCholCB];
+    double off_max = 0.0;  // largest |G'_ij| off the diagonal; 1 if a diagonal is zero
+#pragma unroll
+    for (int p = 0; p < kCholRB; ++p)
+#pragma unroll
+        for (int q = 0; q < kCholCB; ++q) {
+            const int r = r0 + p, c = c0 + q;
+            const bool in = act && r < k && c < k;
+            const double v = in ? Gb[(long)r * k + c] * dsc[r] * dsc[c] : 0.0;
+            w[p][q] = v;
+            if (in && r != c) off_max = fmax(off_max, fabs(v));
+            else if (in && !(dsc[r] > 0.0)) off_max = 1.0;
+        }
+    if (near_identity > 0.0) {
+        off_max = block_max(off_max, red);
+        if (off_max <= near_identity) {  // R' = I: R^{-1} = D^{-1}, nothing dropped
+            for (int e = tid; e < k * k; e += kCholThreads) {
+                const int i = e / k, c = e - (e / k) * k;
+                out[e] = (i == c) ? dsc[i] : 0.0;
+            }
+            if (dead) {
+                for (int j = tid; j < k; j += kCholThreads) dead[(long)b * k + j] = 0;
+                if (tid == 0) dead[(long)nbatch * k + b] = 0;
+            }
+            return;
+        }
+    }
+    // pivot jn's row and column (jn % 8 == QN, so its row is w[QN % 4] of the
+    // threads with r0 == jn - QN % 4 and its column w[.][QN] of those with
+    // c0 == jn - QN) into buffer bf
+    auto publish = [&](auto qn, int jn, int bf) {
+        constexpr int QN = decltype(qn)::value, PN = QN % kCholRB;
+        if (act && r0 + PN == jn) {
+#pragma unroll
+            for (int q = 0; q < kCholCB; ++q) rowbuf[bf][c0 + q] = c0 + q > jn ? w[PN][q] : 0.0;
+            if (c0 + QN == jn) dbuf[bf] = w[PN][QN];
+        }
+        if (act && c0 + QN == jn)
+#pragma unroll
+            for (int p = 0; p < kCholRB; ++p) colbuf[bf][r0 + p] = r0 + p == jn ? 1.0 + w[p][QN] : w[p][QN];
+    };
+    // pivot j (j % 8 == U; bf = j & 1 = U & 1 since the blocks of 8 start even)
+    auto step = [&](auto u, int j) {
+        constexpr int U = decltype(u)::value, bf = U & 1;
+        const double d = dbuf[bf];
+        const bool dj = !(d > tol);
+        const double ip = dj ? 0.0 : fast_rsq(d);
+        const double ip2 = ip * ip;
+        if (act && c0 + kCholCB - 1 > j) {
+            double rc[kCholCB], cr[kCholRB];
+#pragma unroll
+            for (int q = 0; q < kCholCB; ++q) rc[q] = rowbuf[bf][c0 + q] * ip2;
+#pragma unroll
+            for (int p = 0; p < kCholRB; ++p) cr[p] = colbuf[bf][r0 + p];
+#pragma unroll
+            for (int p = 0; p < kCholRB; ++p)
+#pragma unroll
+                for (int q = 0; q < kCholCB; ++q) w[p][q] = fma(-cr[p], rc[q], w[p][q]);
+        }
+        if (j + 1 < k) publish(CholStep<(U + 1) % kCholCB>{}, j + 1, bf ^ 1);
+        if (tid == 0) {
+            ipv[j] = ip;
+            dead_s[j] = dj ? 1 : 0;
+        }
+        __syncthreads();
+    };
+    publish(CholStep<0>{}, 0, 0);
+    __syncthreads();
+    for (int J = 0; J < k; J += kCholCB) {
+        step(CholStep<0>{}, J);
+        if (J + 1 < k) step(CholStep<1>{}, J + 1);
+        if (J + 2 < k) step(CholStep<2>{}, J + 2);
+        if (J + 3 < k) step(CholStep<3>{}, J + 3);
+        if (J + 4 < k) step(CholStep<4>{}, J + 4);
+        if (J + 5 < k) step(CholStep<5>{}, J + 5);
+        if (J + 6 < k) step(CholStep<6>{}, J + 6);
+        if (J + 7 < k) step(CholStep<7>{}, J + 7);
+    }
+    // R^{-1} = D^{-1} R'^{-1}, X[i][c] = V[i][c] / R'[c][c]
+    if (act)
+#pragma unroll
+        for (int p = 0; p < kCholRB; ++p)
+#pragma unroll
+            for (int q = 0; q < kCholCB; ++q) {
+                const int i = r0 + p, c = c0 + q;
+                const double v = c == i ? 1.0 : w[p][q];  // V[i][i] = 1
+                if (i < k && c < k) out[(long)i * k + c] = (c >= i && !dead_s[i]) ? v * ipv[c] * dsc[i] : 0.0;
+            }
+    if (dead) {
+        for (int j = tid; j < k; j += kCholThreads) dead[(long)b * k + j] = dead_s[j];
+        if (tid == 0) {
+            int cnt = 0;
+            for (int j = 0; j < k; ++j) cnt += dead_s[j];
+            dead[(long)nbatch * k + b] = cnt;
+        }
+    }
+}
+
 static size_t chol_lds_bytes(int k, bool in_lds) {
     return ((in_lds ? (size_t)k * k : 0) + (size_t)k * kNb) * sizeof(double);
 }
@@ -490,7 +640,7 @@ void chol_inverse(hipStream_t s, int batch, int k, const double* G, double* Rinv
         attr_set = true;
     }
     if (in_lds)
-        hipLaunchKernelGGL(k_chol_inverse<true>, dim3(blocks), dim3(256), lds, s, k, G, Rinv, tol, dead,
+        hipLaunchKernelGGL(k_chol_inverse_reg, dim3(blocks), dim3(kCholThreads), 0, s, k, G, Rinv, tol, dead,
                            near_identity, jm, batch);
     else
         hipLaunchKernelGGL(k_chol_inverse<false>, dim3(blocks), dim3(256), lds, s, k, G, Rinv, tol, dead,
@@ -516,11 +666,23 @@ void normalize_columns(hipStream_t s, int batch, int n, int k, double* X) {
     HIP_CHECK(hipGetLastError());
 }
 
+// The refill seed of a job: ctr = {config seed, calls so far}; every call
+// hashes seed * C1 + C2 * (calls + 1), then k_count_up advances the count
+// (device-resident, so a replayed graph draws new numbers each time).
+__device__ inline uint64_t refill_seed(const uint64_t* ctr) {
+    return ctr[0] * 0x9E3779B97F4A7C15ull + 0x632BE59BD9B4E019ull * (ctr[1] + 1);
+}
+
 __global__ __launch_bounds__(256) void k_dead_fill(int n, int k, const int* __restrict__ dead,
-                                                   uint64_t seed, double* __restrict__ R) {
+                                                   const uint64_t* __restrict__ ctr, double* __restrict__ R,
+                                                   JobMap jm, int batch) {
     const long tot = (long)n * k;
-    const int b = blockIdx.y;
-    if (dead[(long)gridDim.y * k + b] == 0) return;
+    dead = jptr(dead, jm, blockIdx.y);
+    ctr = jptr(ctr, jm, blockIdx.y);
+    R = jptr(R, jm, blockIdx.y);
+    const int b = jlocal(jm, blockIdx.y);
+    if (dead[(long)batch * k + b] == 0) return;
+    const uint64_t seed = refill_seed(ctr);
     for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < tot;
          e += (long)gridDim.x * blockDim.x) {
         const int j = (int)(e % k);
@@ -529,18 +691,29 @@ __global__ __launch_bounds__(256) void k_dead_fill(int n, int k, const int* __re
     }
 }
 
-void dead_fill(hipStream_t s, int batch, int n, int k, const int* dead, uint64_t seed, double* R) {
+__global__ void k_count_up(uint64_t* ctr, JobMap jm) {
+    if (threadIdx.x == 0) jptr(ctr, jm, blockIdx.x)[1] += 1;
+}
+
+void dead_fill(hipStream_t s, int batch, int n, int k, const int* dead, uint64_t* ctr, double* R, JobMap jm) {
     if (batch <= 0 || k <= 0) return;
     const long tot = (long)n * k;
     const int grid = ceil_div(tot, 256) < 1024 ? (int)ceil_div(tot, 256) : 1024;
-    hipLaunchKernelGGL(k_dead_fill, dim3(grid, batch), dim3(256), 0, s, n, k, dead, seed, R);
+    const int nj = jm.delta ? jm.njobs : 1;
+    jm.per_job = batch;
+    hipLaunchKernelGGL(k_dead_fill, dim3(grid, batch * nj), dim3(256), 0, s, n, k, dead, ctr, R, jm, batch);
+    jm.per_job = 1;
+    hipLaunchKernelGGL(k_count_up, dim3(nj), dim3(64), 0, s, ctr, jm);
     HIP_CHECK(hipGetLastError());
 }
 
 __global__ __launch_bounds__(256) void k_add_gated(long count, const int* __restrict__ gate,
                                                    const double* __restrict__ Y,
-                                                   double* __restrict__ X) {
-    const int b = blockIdx.y;
+                                                   double* __restrict__ X, JobMap jm) {
+    gate = jptr(gate, jm, blockIdx.y);
+    Y = jptr(Y, jm, blockIdx.y);
+    X = jptr(X, jm, blockIdx.y);
+    const int b = jlocal(jm, blockIdx.y);
     if (gate[b] == 0) return;
     const double* Yb = Y + b * count;
     double* Xb = X + b * count;
@@ -549,10 +722,12 @@ __global__ __launch_bounds__(256) void k_add_gated(long count, const int* __rest
         Xb[e] += Yb[e];
 }
 
-void add_gated(hipStream_t s, int batch, long count, const int* gate, const double* Y, double* X) {
+void add_gated(hipStream_t s, int batch, long count, const int* gate, const double* Y, double* X, JobMap jm) {
     if (batch <= 0 || count <= 0) return;
     const int grid = ceil_div(count, 256) < 1024 ? (int)ceil_div(count, 256) : 1024;
-    hipLaunchKernelGGL(k_add_gated, dim3(grid, batch), dim3(256), 0, s, count, gate, Y, X);
+    const int nj = jm.delta ? jm.njobs : 1;
+    jm.per_job = batch;
+    hipLaunchKernelGGL(k_add_gated, dim3(grid, batch * nj), dim3(256), 0, s, count, gate, Y, X, jm);
     HIP_CHECK(hipGetLastError());
 }
 

@@ -14,6 +14,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
@@ -61,6 +62,15 @@ struct Bucket {
     size_t bytes = 0;  // cap regions
     std::vector<uint64_t> slot_job;  // 0: free
     hipStream_t stream = nullptr;    // the stream of its states
+    // the batch of the group that last completed with every job still
+    // running, kept (with its captured graph) for the same group's next chunk
+    ipeps_batch* kept = nullptr;
+    std::vector<uint64_t> kept_ids;
+    void drop_kept() {
+        if (kept) ipeps_batch_destroy(kept);
+        kept = nullptr;
+        kept_ids.clear();
+    }
     int used() const {
         int u = 0;
         for (uint64_t j : slot_job) u += j != 0;
@@ -80,6 +90,7 @@ struct ipeps_server {
     int max_slots = 1;
     int running = 0;
     bool stopping = false;
+    std::atomic<bool> graphs{false};  // batches replay captured warm iterations
     int device = 0;
     std::vector<std::unique_ptr<Bucket>> buckets;  // executor thread only
     std::thread executor;
@@ -168,7 +179,9 @@ struct Group {
     int rc = IPEPS_OK;
 };
 
-// Collect a finished group's readouts into its jobs' series.
+// Collect a finished group's readouts into its jobs' series.  The batch is
+// kept in its bucket when every job goes on (the next chunk of the same
+// group reuses it), else destroyed before any of its states is.
 void complete(ipeps_server* srv, Group& g) {
     std::vector<ipeps_obs> obs(g.ids.size());
     std::vector<int> status(g.ids.size(), g.rc);
@@ -177,7 +190,18 @@ void complete(ipeps_server* srv, Group& g) {
         // a NaN in one job poisons only that job; other failures hit all
         if (rc != IPEPS_OK && rc != IPEPS_ENUMERIC) status.assign(g.ids.size(), rc);
     }
-    if (g.batch) ipeps_batch_destroy(g.batch);
+    bool keep = g.batch != nullptr;
+    for (size_t i = 0; i < g.ids.size(); ++i) {
+        const Job& j = srv->jobs[g.ids[i]];
+        keep = keep && status[i] == IPEPS_OK && j.done + g.chunk < j.spec.n_steps;
+    }
+    if (keep) {
+        g.bucket->drop_kept();
+        g.bucket->kept = g.batch;
+        g.bucket->kept_ids = g.ids;
+    } else if (g.batch) {
+        ipeps_batch_destroy(g.batch);
+    }
     g.batch = nullptr;
     for (size_t i = 0; i < g.ids.size(); ++i) {
         const uint64_t id = g.ids[i];
@@ -223,6 +247,7 @@ void executor_main(ipeps_server* srv) {
                 // has completed: each job's batches were waited for)
                 for (auto it = srv->buckets.begin(); it != srv->buckets.end();) {
                     if ((*it)->used() == 0) {
+                        (*it)->drop_kept();
                         srv->used -= (*it)->bytes;
                         ipeps_slab_destroy((*it)->slab);
                         if ((*it)->stream) (void)hipStreamDestroy((*it)->stream);
@@ -280,7 +305,17 @@ void executor_main(ipeps_server* srv) {
                 sts.push_back(srv->jobs[id].st);
                 srv->jobs[id].busy = true;
             }
-            g.rc = ipeps_batch_create(sts.data(), (int)sts.size(), &g.batch);
+            Bucket* bk = g.bucket;
+            if (bk->kept && bk->kept_ids == g.ids) {  // the same jobs as last time
+                g.batch = bk->kept;
+                bk->kept = nullptr;
+                bk->kept_ids.clear();
+            } else {
+                // its jobs are idle; some may be in this group
+                bk->drop_kept();
+                g.rc = ipeps_batch_create(sts.data(), (int)sts.size(), &g.batch);
+                if (g.rc == IPEPS_OK && srv->graphs.load()) g.rc = ipeps_batch_set_graph(g.batch, 1);
+            }
             if (g.rc == IPEPS_OK) g.rc = ipeps_batch_trotter_step(g.batch, g.chunk);
             if (g.rc == IPEPS_OK) g.rc = ipeps_batch_ctmrg(g.batch, g.iters, g.cold ? 1 : 0);
             if (g.rc == IPEPS_OK) g.rc = ipeps_batch_observe_async(g.batch);
@@ -359,6 +394,12 @@ int solve_job_times(ipeps_server* srv, uint64_t job_id, double* t_submit, double
     if (t_done) *t_done = j.t_done;
     if (j.status == IPEPS_JOB_QUEUED || j.status == IPEPS_JOB_RUNNING) return IPEPS_EAGAIN;
     return j.status < 0 ? j.status : IPEPS_OK;
+}
+
+int solve_server_set_graphs(ipeps_server* srv, int enable) {
+    if (!srv) return IPEPS_EINVAL;
+    srv->graphs.store(enable != 0);
+    return IPEPS_OK;
 }
 
 void solve_server_destroy(ipeps_server* srv) {

@@ -99,6 +99,9 @@ struct ipeps_state {
     bool ro_deferred;  // snapshot taken, readout kernels not yet enqueued
     bool corners_warm;  // corner slots valid from the previous iteration of this call
     bool spec_deferred, spec_first;  // corner spectra waiting to be enqueued
+    // the main stream is being captured into a graph: waits on events
+    // recorded before the capture are made before the graph's launch instead
+    bool capturing;
     double ro_t;
     int ro_iters;
     double* jwork_c;
@@ -190,7 +193,7 @@ struct ipeps_state {
     void* T2;
     void* VsK;
     int* dead_dev;       // 2*k flags of dropped columns, then 2 counts
-    uint64_t orth_calls; // counter feeding the refill hash
+    uint64_t* refill_ctr; // device: {config seed, refill calls}, feeding the refill hash
     int extra_warm_iters; // added warm subspace iterations (converging to a tolerance)
     double* norm_ws;     // partial sums of the tensor normalisation (32 tensors)
     double* norm_ws_su;  // the same for normalisations on the SU stream

@@ -5,6 +5,7 @@ of the method runs in Python.  Loading fails loudly when the gfx950 library
 has not been built (``python -m paper_1910_11359_amd.build``).
 """
 import ctypes as C
+import weakref
 import os
 
 import numpy as np
@@ -68,7 +69,7 @@ EXPORTS = [
     "ipeps_profile_read_gemms", "ipeps_slab_region_bytes", "ipeps_slab_create", "ipeps_slab_init",
     "ipeps_slab_destroy", "ipeps_batch_create", "ipeps_batch_trotter_step", "ipeps_batch_ctmrg",
     "ipeps_batch_observe", "ipeps_batch_destroy", "ipeps_batch_observe_async", "ipeps_batch_query",
-    "ipeps_batch_observe_result",
+    "ipeps_batch_observe_result", "ipeps_batch_set_graph", "solve_server_set_graphs",
 ]
 
 _lib = None
@@ -108,6 +109,7 @@ def load():
     lib.solve_poll.argtypes = [C.c_void_p, C.c_uint64, P(C.c_int), P(Obs), C.c_int, P(C.c_int)]
     lib.solve_job_times.argtypes = [C.c_void_p, C.c_uint64, P(C.c_double), P(C.c_double),
                                     P(C.c_double)]
+    lib.solve_server_set_graphs.argtypes = [C.c_void_p, C.c_int]
     lib.solve_server_destroy.argtypes = [C.c_void_p]
     lib.solve_server_destroy.restype = None
     lib.ipeps_profile.argtypes = [C.c_void_p, C.c_int]
@@ -129,6 +131,7 @@ def load():
     lib.ipeps_batch_create.argtypes = [P(C.c_void_p), C.c_int, P(C.c_void_p)]
     lib.ipeps_batch_trotter_step.argtypes = [C.c_void_p, C.c_int]
     lib.ipeps_batch_ctmrg.argtypes = [C.c_void_p, C.c_int, C.c_int]
+    lib.ipeps_batch_set_graph.argtypes = [C.c_void_p, C.c_int]
     lib.ipeps_batch_observe.argtypes = [C.c_void_p, P(Obs)]
     lib.ipeps_batch_observe_async.argtypes = [C.c_void_p]
     lib.ipeps_batch_query.argtypes = [C.c_void_p]
@@ -286,6 +289,7 @@ class Slab:
         h = C.c_void_p()
         _check(self._lib.ipeps_slab_create(C.byref(layout_cfg), int(slots), C.byref(h)), "ipeps_slab_create")
         self.h = h
+        self._states = weakref.WeakSet()
 
     def state(self, slot, cfg, stream=None):
         st = State.__new__(State)
@@ -295,10 +299,15 @@ class Slab:
         _check(self._lib.ipeps_slab_init(self.h, int(slot), C.byref(cfg), C.c_void_p(sptr), C.byref(handle)),
                "ipeps_slab_init")
         st.h = handle
+        st._slab = self  # the slab's memory outlives the state
+        self._states.add(st)
         return st
 
     def close(self):
+        """Destroys the states still open in the slab, then the slab."""
         if getattr(self, "h", None):
+            for st in list(self._states):
+                st.close()
             self._lib.ipeps_slab_destroy(self.h)
             self.h = None
 
@@ -312,13 +321,19 @@ class Slab:
 class Batch:
     """Lockstep batch of states of one slab (ipeps_batch_*); states[0] leads."""
 
-    def __init__(self, states):
+    def __init__(self, states, graph=False):
         self._lib = load()
         self.states = list(states)
         arr = (C.c_void_p * len(self.states))(*[s.h.value for s in self.states])
         h = C.c_void_p()
         _check(self._lib.ipeps_batch_create(arr, len(self.states), C.byref(h)), "ipeps_batch_create")
         self.h = h
+        if graph:
+            self.set_graph(True)
+
+    def set_graph(self, enable=True):
+        """Replay the warm CTMRG iterations from a captured HIP graph."""
+        _check(self._lib.ipeps_batch_set_graph(self.h, int(bool(enable))), "ipeps_batch_set_graph")
 
     def trotter_step(self, n_steps=1):
         _check(self._lib.ipeps_batch_trotter_step(self.h, int(n_steps)), "ipeps_batch_trotter_step")
@@ -357,12 +372,14 @@ class Batch:
 class Server:
     """The request loop (wraps ipeps_server*)."""
 
-    def __init__(self, hbm_budget=0, max_slots=4):
+    def __init__(self, hbm_budget=0, max_slots=4, graphs=False):
         self._lib = load()
         h = C.c_void_p()
         _check(self._lib.solve_server_create(C.c_size_t(int(hbm_budget)), int(max_slots),
                                              C.byref(h)), "solve_server_create")
         self.h = h
+        if graphs:
+            _check(self._lib.solve_server_set_graphs(self.h, 1), "solve_server_set_graphs")
 
     def submit(self, cfg, n_steps, observe_every=10, ctm_iters=10, tag=0):
         j = Job()

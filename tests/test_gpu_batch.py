@@ -74,6 +74,57 @@ def test_batch_equals_alone(D, chi, dtype, flags):
     slab.close()
 
 
+@pytest.mark.parametrize("D,chi,dtype,flags,njobs", [(2, 8, "fp64", 0, 3), (3, 18, "fp64", 2, 3),
+                                                      (4, 16, "fp32", 0, 3), (4, 32, "bf16x3", 2, 3),
+                                                      (3, 12, "fp64", 0, 1)])
+def test_graph_replays_equal_eager(D, chi, dtype, flags, njobs):
+    """Warm iterations replayed from the batch's captured graph: every
+    observation of three chunks (the graph captured in the first, replayed in
+    all) equals the jobs' solo eager runs bit for bit, with eager work of
+    another state and host synchronisations between the chunks."""
+    print(f"graph batch D={D} chi={chi} {dtype} flags={flags} jobs={njobs}", flush=True)
+    params = PARAMS[:njobs]
+    sched = [(3, 4, True), (2, 5, False), (1, 3, False)]  # (Trotter steps, iterations, cold)
+
+    def solo_run(p):
+        st = P.State(_cfg(D, chi, dtype, flags, p))
+        out = []
+        for n, it, cold in sched:
+            st.trotter_step(n)
+            st.ctmrg(0.0, it, cold)
+            out.append((st.observe(), st.corner_spectra()))
+        st.close()
+        return out
+
+    solo = [solo_run(p) for p in params]
+    other = P.State(_cfg(D, chi, dtype, flags, PARAMS[-1]))
+    slab = P.Slab(_cfg(D, chi, dtype, flags, params[0]), 4)
+    sts = [slab.state(sl, _cfg(D, chi, dtype, flags, p)) for sl, p in zip((1, 3, 0), params)]
+    b = P.Batch(sts, graph=True)
+    got = []
+    for n, it, cold in sched:
+        b.trotter_step(n)
+        b.ctmrg(it, cold)
+        got.append(b.observe())
+        # eager work on another state between the replays
+        other.trotter_step(1)
+        other.ctmrg(0.0, 2, True)
+        other.observe()
+    b.close()
+    spectra = [st.corner_spectra() for st in sts]  # after the last chunk
+    for i in range(njobs):
+        for c, (ref, ref_spec) in enumerate(solo[i]):
+            g = got[c][i]
+            assert g["imbalance"] == ref["imbalance"], (i, c, g["imbalance"], ref["imbalance"])
+            assert np.array_equal(g["n"], ref["n"]) and np.array_equal(g["eps"], ref["eps"])
+            assert g["t"] == ref["t"] and g["ctm_delta"] == ref["ctm_delta"], (i, c)
+        assert np.array_equal(spectra[i], solo[i][-1][1])
+    other.close()
+    for st in sts:
+        st.close()
+    slab.close()
+
+
 def test_batch_rejects_mixed_layouts_and_foreign_states():
     a = P.State(P.make_config(2, 8))
     b = P.State(P.make_config(2, 8, W=2.0))

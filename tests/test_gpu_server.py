@@ -50,20 +50,24 @@ JOBS = [dict(D=2, chi=8, W=5.0, V=1.0), dict(D=3, chi=18, W=3.0, V=0.0),
         dict(D=4, chi=16, W=2.0, V=1.0), dict(D=2, chi=12, W=1.5, V=0.5)]
 
 
-def test_mix_equals_alone():
-    srv = P.Server(hbm_budget=0, max_slots=4)
+@pytest.mark.parametrize("graphs", [False, True])
+def test_mix_equals_alone(graphs):
+    """graphs: the loop's batches replay captured warm iterations and a group
+    whose jobs all go on keeps its batch (and graph) for the next chunk."""
+    print(f"server mix graphs={graphs}", flush=True)
+    srv = P.Server(hbm_budget=0, max_slots=4, graphs=graphs)
     ids, cfgs = [], []
     for j in JOBS:
         cfg = P.make_config(j["D"], j["chi"], W=j["W"], V=j["V"], dt=0.05)
         cfgs.append(cfg)
-        ids.append(srv.submit(cfg, n_steps=6, observe_every=3, ctm_iters=4))
+        ids.append(srv.submit(cfg, n_steps=9, observe_every=3, ctm_iters=4))
     res = _wait(srv, ids)
     times = [srv.times(j)[1] for j in ids]
     srv.close()
     for jid, cfg in zip(ids, cfgs):
-        ref = _alone(cfg, 6, 3, 4)
+        ref = _alone(cfg, 9, 3, 4)
         got = res[jid]
-        assert len(got) == len(ref) == 2
+        assert len(got) == len(ref) == 3
         for g, r in zip(got, ref):
             assert g["t"] == r["t"]
             assert g["imbalance"] == r["imbalance"]
