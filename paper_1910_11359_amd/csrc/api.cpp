@@ -51,7 +51,9 @@ constexpr int kDirectMax = 96;  // projector SVD by direct Jacobi when n <= this
 // cut matrices applied through their factors (no n^3 product) when n > this
 // (below, forming them takes fewer launches and less time)
 constexpr int kFactoredMin = 1024;
-constexpr int kChainTile = TILE_DIRECT_SMALL;  // tile kind of the factored chain products
+// tile kind of the factored chain products: a panel tile holding the k
+// columns whole when k is in 65..128 (see chain_splits), else 64 x 64 tiles
+constexpr int kChainTile = -2;
 constexpr int kColdIters = 8;   // subspace iterations for a fresh random block
 constexpr int kWarmIters = 2;   // ... when warm-started from the last iteration (FP64)
 // With FP32 cut products the matrix itself carries ~1e-7 relative rounding;
@@ -140,7 +142,7 @@ GemmTile autotune_tile(ipeps_state* st, std::vector<GemmProb> probs, int dtype, 
         HIP_CHECK(hipMalloc(&st->tune_dev, n * sizeof(GemmProb)));
         st->tune_cap = n;
     }
-    GemmTile cand[4];
+    GemmTile cand[5];
     const int nc = gemm_tile_candidates(probs.data(), n, dtype, cand);
     GemmTile best = fallback;
     float best_ms = 1e30f;
@@ -177,8 +179,12 @@ GemmGroup add_group(ipeps_state* st, std::vector<GemmProb> probs, int dtype, int
     for (const auto& p : probs)
         if (p.ksplit > 1) g.reduce_elems = std::max(g.reduce_elems, (long)p.M * p.N);
     bool forced = false;
+    if (force == kChainTile) {
+        const int pt = gemm_panel_for(probs.data(), g.count, dtype);
+        force = pt >= 0 ? pt : (int)TILE_DIRECT_SMALL;
+    }
     if (force >= 0 && g.count > 0) {
-        GemmTile cand[4];
+        GemmTile cand[5];
         const int nc = gemm_tile_candidates(probs.data(), g.count, dtype, cand);
         for (int i = 0; i < nc; ++i)
             if (cand[i] == (GemmTile)force) {
@@ -288,6 +294,16 @@ GemmProb split(GemmProb p, int ks, void* ws) {
 
 int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
+// K splits of the chain products (two n x n corners against n x k blocks per
+// launch): with panel tiles (k in 65..128; 2 ceil(n / 64) tiles) enough for
+// about two workgroups per CU (measured at n = 2592: 6 splits, FP32 k = 80
+// 36 us and FP64 k = 96 66 us per launch, against 46 and 84 us with 64 x 64
+// tiles); with 64 x 64 tiles one per 512 rows of K.
+int chain_splits(int n, int k) {
+    if (k > 64 && k <= 128) return clampi((512 + n / 64) / (2 * ceil_div(n, 64)), 1, 16);
+    return clampi(n / 512, 1, 16);
+}
+
 // ---------------------------------------------------------------- allocation
 void allocate(ipeps_state* st) {
     DevMem& M = st->mem;
@@ -354,7 +370,7 @@ void allocate(ipeps_state* st) {
     st->ks_nv = clampi(n / 512, 1, 8);
     st->ks_c = clampi(n / 256, 1, 32);
     st->ws_gram = (double*)M.get(2L * st->ks_gram * k * k * sizeof(double));
-    st->ks_chain = clampi(n / 512, 1, 16);
+    st->ks_chain = chain_splits(n, k);
     st->ws_nv = (double*)M.get(2L * std::max((size_t)st->ks_nv * sizeof(double), (size_t)st->ks_chain * e) * nk);
     st->ws_c = M.get(4L * st->ks_c * chi * chi * e);
     st->ks_p = clampi(n / 512, 1, 8);
@@ -660,11 +676,10 @@ void build_plan(ipeps_state* st) {
             });
         } else {
             const bool f64 = dt == IPEPS_DTYPE_FP64;
-            // the chain products (n x n corner against a k-column block): 64 x 64
-            // tiles, K split in 5 at n = 2592 (measured at D=6, chi=72, k=80:
-            // 128 x 128 tiles, which stream each corner once instead of twice,
-            // are slower, 36.8 vs 36.4 ms per step; splits of 3 to 10 within
-            // 0.1 ms)
+            // the chain products (n x n corner against a k-column block): panel
+            // tiles that hold the k columns whole, so each corner is streamed
+            // once (64 x 64 tiles streamed it twice at k = 80 and computed 128
+            // columns), K split per chain_splits
             auto batch2d = [&](auto make) {
                 std::vector<GemmProb> out;
                 for (int b = 0; b < 2; ++b) out.push_back(make(b));

@@ -43,14 +43,34 @@ GemmProb gemm_general(const void* A, bool transA, long lda, const void* B, bool 
 // every problem of the group has A with k contiguous and B with n contiguous,
 // 16-byte aligned, with K and N (and the A row strides, B k stride) multiples
 // of the 16-byte vector.
-enum GemmTile { TILE_LARGE = 0, TILE_SMALL = 1, TILE_DIRECT = 2, TILE_DIRECT_SMALL = 3 };
+//
+// Panel tiles (TILE_PANEL + 16 m + np / 16): every problem of the group has
+// one side of at most 128 (the columns of a subspace block), padded to
+// np = 80, 96, 112 or 128 and held whole in one tile: m = 0, N <= np, tiles
+// of 64 x np (4 waves stacked along M); m = 1, M <= np, tiles of np x 64
+// (4 waves side by side along N).  Same operand layouts as the direct tiles.
+enum GemmTile {
+    TILE_LARGE = 0,
+    TILE_SMALL = 1,
+    TILE_DIRECT = 2,
+    TILE_DIRECT_SMALL = 3,
+    TILE_PANEL = 64,
+    TILE_PANEL_LAST = TILE_PANEL + 16 + 8
+};
+inline GemmTile panel_tile(bool skinny_m, int np) { return (GemmTile)(TILE_PANEL + (skinny_m ? 16 : 0) + np / 16); }
+inline bool is_panel(GemmTile t) { return t >= TILE_PANEL; }
+
+// The panel tile for a group (all problems thin on the same side, with the
+// same padded width in 80..128, operands as the direct tiles need them), or
+// -1.
+int gemm_panel_for(const GemmProb* probs, int n, int dtype);
 
 // Chooses the tile shape for a group by a size heuristic and fills tiles_n /
 // tile_begin; returns the total number of tiles (the grid size).
 int gemm_plan_tiles(GemmProb* probs, int n, int dtype, GemmTile* tile);
 
-// Tile kinds that can run the group (at most 4; the direct ones only where
-// the operand layout allows them); returns their number.
+// Tile kinds that can run the group (at most 5; the direct and panel ones
+// only where the operand layout allows them); returns their number.
 int gemm_tile_candidates(const GemmProb* probs, int n, int dtype, GemmTile* out);
 
 // Fills tiles_n / tile_begin for a given tile kind; returns the total tiles.

@@ -291,7 +291,12 @@ GemmProb gemm_nn(const void* A, long lda, const void* B, long ldb, void* C, long
 
 static void tile_dims(int dtype, GemmTile tile, int* bm, int* bn) {
     (void)dtype;
-    if (tile == TILE_LARGE || tile == TILE_DIRECT) {
+    if (is_panel(tile)) {
+        const int np = 16 * ((tile - TILE_PANEL) % 16);
+        const bool sm = (tile - TILE_PANEL) >= 16;
+        *bm = sm ? np : 64;
+        *bn = sm ? 64 : np;
+    } else if (tile == TILE_LARGE || tile == TILE_DIRECT) {
         *bm = 128;
         *bn = 128;
     } else {
@@ -343,8 +348,25 @@ int gemm_plan_tiles(GemmProb* probs, int n, int dtype, GemmTile* tile) {
     return gemm_plan_with(probs, n, dtype, *tile);
 }
 
+int gemm_panel_for(const GemmProb* probs, int n, int dtype) {
+    if (n < 1 || !direct_ok(probs, n, dtype)) return -1;
+    auto pad = [](int v) { return v <= 80 ? 80 : (v + 15) / 16 * 16; };
+    for (int sm = 0; sm < 2; ++sm) {
+        const int w0 = sm ? probs[0].M : probs[0].N;
+        bool ok = w0 > 64 && w0 <= 128;
+        for (int i = 0; i < n && ok; ++i) {
+            const int w = sm ? probs[i].M : probs[i].N, other = sm ? probs[i].N : probs[i].M;
+            ok = w > 64 && pad(w) == pad(w0) && other > 128;
+        }
+        if (ok) return (int)panel_tile(sm != 0, pad(w0));
+    }
+    return -1;
+}
+
 int gemm_tile_candidates(const GemmProb* probs, int n, int dtype, GemmTile* out) {
     int c = 0;
+    const int pt = gemm_panel_for(probs, n, dtype);
+    if (pt >= 0) out[c++] = (GemmTile)pt;
     if (direct_ok(probs, n, dtype)) {
         out[c++] = TILE_DIRECT;
         out[c++] = TILE_DIRECT_SMALL;
@@ -599,6 +621,235 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
 }
 
 
+// Panel kernel: the direct kernel's LDS-DMA ring and A layout, for problems
+// with one side held whole in one tile (a k-column block of a subspace
+// iteration against an n x n enlarged corner).  WGM = 4: a 64 x BN tile with
+// the 4 waves stacked along M (16 x BN each); WGM = 1: a BM x 64 tile with
+// the waves side by side along N (BM x 16 each).  BM and BN need not be
+// powers of two: B chunks are rotated by 16 columns per reading lane group
+// (the rows those groups read are KPL apart), and a stage's loads are padded
+// to whole wave loads per wave (the surplus lands in a scratch area of the
+// stage), so every wave issues the same count and vmcnt stays exact.
+template <typename T, int BM, int BN, int BK, int WGM, int NS, int TAG, int BF = 0>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) void k_gemm_panel(const GemmProb* __restrict__ probs, int nprob) {
+    static_assert(BF == 0 || BF == 1 || BF == 3, "BF: 0, 1 or 3 BF16 products");
+    static_assert(!BF || (sizeof(T) == 4 && BK == 32), "BF16 modes: FP32 storage, k tiles of 32");
+    static_assert(WGM == 4 || WGM == 1, "waves stacked along M or along N");
+    constexpr int VW = 16 / (int)sizeof(T);
+    constexpr int WGN = 4 / WGM;
+    constexpr int WM = BM / WGM, WN = BN / WGN;
+    constexpr int FM = WM / 16, FN = WN / 16;
+    static_assert(FM * 16 * WGM == BM && FN * 16 * WGN == BN, "tiles of whole 16 x 16 blocks");
+    constexpr int KPL = BK / 4;
+    constexpr int NCH = KPL / VW;
+    constexpr int ACH = BK / VW;  // 16-byte chunks per A row (8)
+    static_assert(ACH == 8, "the A swizzle takes 8 chunks per row");
+    constexpr int BCH = BN / VW;  // 16-byte chunks per B row
+    constexpr int ROT = 16 / VW;  // B chunk rotation per reading lane group
+    constexpr int ACHK = BM * ACH, BCHK = BK * BCH;  // chunks per stage
+    static_assert(ACHK % 64 == 0 && BCHK % 64 == 0, "whole wave loads");
+    constexpr int NLA = (ACHK + 255) / 256, NLB = (BCHK + 255) / 256;  // loads per lane and stage
+    constexpr int ASZ = NLA * 256 * VW, BSZ = NLB * 256 * VW;             // padded stage areas
+    static_assert(NS >= 2 && NS <= 4, "wait_vm covers up to 3 tiles in flight behind the current one");
+    typedef typename Vec16<T>::v_t v_t;
+    __shared__ __attribute__((aligned(16))) T Sm[NS * (ASZ + BSZ)];
+
+    const int G = gridDim.x;
+    const int xcd = blockIdx.x & 7, idx = blockIdx.x >> 3;
+    const int per = G >> 3, rem = G & 7;
+    const int bid = xcd * per + (xcd < rem ? xcd : rem) + idx;
+    int p = 0;
+    while (p + 1 < nprob && probs[p + 1].tile_begin <= bid) ++p;
+    const GemmProb& P = probs[p];
+    if (P.gate && *P.gate == 0) return;
+    const int ks = P.ksplit > 1 ? P.ksplit : 1;
+    const int tt = bid - P.tile_begin;
+    const int split = tt % ks, t = tt / ks;
+    const int tm = t / P.tiles_n, tn = t - (t / P.tiles_n) * P.tiles_n;
+    const int M = P.M, N = P.N;
+    const int kchunk = ((P.K + ks - 1) / ks + BK - 1) / BK * BK;
+    const int kbeg = split * kchunk;
+    const int K = (kbeg + kchunk < P.K) ? kbeg + kchunk : P.K;
+    const int m0 = tm * BM, n0 = tn * BN;
+    const T* __restrict__ A = (const T*)P.A;
+    const T* __restrict__ B = (const T*)P.B;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+
+    // per-lane sources (fixed across k tiles); surplus chunks re-read chunk 0
+    long a_src[NLA];
+    int a_lk[NLA];
+#pragma unroll
+    for (int r = 0; r < NLA; ++r) {
+        int c = (r * 4 + wave) * 64 + lane;
+        c = c < ACHK ? c : lane;
+        const int row = c / ACH;
+        const int lchunk = (c % ACH) ^ (row & 7);
+        int i = m0 + row;
+        i = i < M ? i : M - 1;
+        a_src[r] = (long)(i / P.a_rows0) * P.a_rs1 + (long)(i % P.a_rows0) * P.a_rs0;
+        a_lk[r] = lchunk * VW;
+    }
+    int b_k[NLB], b_n[NLB];
+#pragma unroll
+    for (int r = 0; r < NLB; ++r) {
+        int c = (r * 4 + wave) * 64 + lane;
+        c = c < BCHK ? c : lane;
+        const int k = c / BCH, slot = c % BCH;
+        int gch = slot - ROT * ((k / KPL) & 3);
+        gch = gch < 0 ? gch + BCH : gch;
+        gch = gch < 0 ? gch + BCH : gch;
+        int n = n0 + gch * VW;
+        n = n < N ? n : N - VW;
+        b_k[r] = k;
+        b_n[r] = n;
+    }
+    auto issue = [&](int kt, int stg) {
+        const int k0 = kbeg + kt * BK;
+        T* as = Sm + stg * (ASZ + BSZ);
+        T* bs = as + ASZ;
+#pragma unroll
+        for (int r = 0; r < NLA; ++r) {
+            int k = k0 + a_lk[r];
+            k = k < K ? k : K - VW;
+            __builtin_amdgcn_global_load_lds((const void*)(A + a_src[r] + k),
+                                             (__attribute__((address_space(3))) void*)(as + (r * 4 + wave) * 64 * VW),
+                                             16, 0, 0);
+        }
+#pragma unroll
+        for (int r = 0; r < NLB; ++r) {
+            int k = k0 + b_k[r];
+            k = k < K ? k : K - 1;
+            __builtin_amdgcn_global_load_lds((const void*)(B + (long)k * P.b_ks + b_n[r]),
+                                             (__attribute__((address_space(3))) void*)(bs + (r * 4 + wave) * 64 * VW),
+                                             16, 0, 0);
+        }
+    };
+
+    const int wm0 = WGM == 4 ? wave * WM : 0, wn0 = WGM == 4 ? 0 : wave * WN;
+    const int lg = lane >> 4, l16 = lane & 15;
+    // B read offsets of this lane's columns (the rotation depends on lg only)
+    int b_off[FN];
+#pragma unroll
+    for (int b = 0; b < FN; ++b) {
+        const int n = wn0 + b * 16 + l16;
+        int slot = n / VW + ROT * lg;
+        slot = slot < BCH ? slot : slot - BCH;
+        slot = slot < BCH ? slot : slot - BCH;
+        b_off[b] = slot * VW + n % VW;
+    }
+    typedef typename Mfma<T>::acc_t acc_t;
+    acc_t acc[FM][FN];
+#pragma unroll
+    for (int a = 0; a < FM; ++a)
+#pragma unroll
+        for (int b = 0; b < FN; ++b) acc[a][b] = acc_t{0, 0, 0, 0};
+
+    const int nk = K > kbeg ? (K - kbeg + BK - 1) / BK : 0;
+#pragma unroll
+    for (int s = 0; s < NS - 1; ++s)
+        if (s < nk) issue(s, s);
+    for (int kt = 0; kt < nk; ++kt) {
+        const int ahead = nk - 1 - kt;  // tiles issued after this one
+        wait_vm<NLA + NLB>(ahead < NS - 2 ? ahead : NS - 2);
+        const int stg = kt % NS;
+        T* as = Sm + stg * (ASZ + BSZ);
+        const T* bs = as + ASZ;
+        const int k0 = kbeg + kt * BK;
+        if (k0 + BK > K) {
+            // tail tile: zero the A chunks of this lane that lie beyond K
+#pragma unroll
+            for (int r = 0; r < NLA; ++r)
+                if (k0 + a_lk[r] >= K) {
+                    v_t z = {};
+                    *(v_t*)(as + (r * 4 + wave) * 64 * VW + lane * VW) = z;
+                }
+        }
+        __builtin_amdgcn_s_waitcnt((15 & 15) | (3 << 14) | (7 << 4) | (0 << 8));  // lgkmcnt(0)
+        __builtin_amdgcn_s_barrier();
+        if (kt + NS - 1 < nk) issue(kt + NS - 1, (kt + NS - 1) % NS);
+        BfOperand<BF> ha[FM], hb[FN];
+#pragma unroll
+        for (int ch = 0; ch < NCH; ++ch) {
+            v_t fa[FM];
+            T fb[FN][VW];
+#pragma unroll
+            for (int a = 0; a < FM; ++a) {
+                const int row = wm0 + a * 16 + l16;
+                const int pc = (lg * NCH + ch) ^ (row & 7);
+                fa[a] = *(const v_t*)(as + row * BK + pc * VW);
+            }
+#pragma unroll
+            for (int tq = 0; tq < VW; ++tq) {
+                const int k = lg * KPL + ch * VW + tq;
+#pragma unroll
+                for (int b = 0; b < FN; ++b) fb[b][tq] = bs[k * BN + b_off[b]];
+            }
+            if constexpr (BF) {
+#pragma unroll
+                for (int tq = 0; tq < VW; ++tq) {
+#pragma unroll
+                    for (int a = 0; a < FM; ++a) ha[a].set(ch * VW + tq, fa[a][tq]);
+#pragma unroll
+                    for (int b = 0; b < FN; ++b) hb[b].set(ch * VW + tq, fb[b][tq]);
+                }
+            } else {
+#pragma unroll
+                for (int tq = 0; tq < VW; ++tq)
+#pragma unroll
+                    for (int a = 0; a < FM; ++a)
+#pragma unroll
+                        for (int b = 0; b < FN; ++b)
+                            acc[a][b] = Mfma<T>::step(fa[a][tq], fb[b][tq], acc[a][b]);
+            }
+        }
+        if constexpr (BF) {
+#pragma unroll
+            for (int a = 0; a < FM; ++a)
+#pragma unroll
+                for (int b = 0; b < FN; ++b) acc[a][b] = mfma_bf16(ha[a], hb[b], acc[a][b]);
+        }
+    }
+
+    // ---- epilogue (as the direct kernel)
+    const T alpha = (T)P.alpha, beta = (T)P.beta;
+    if (ks > 1) {
+        T* __restrict__ W = (T*)P.ws + (long)split * M * N;
+#pragma unroll
+        for (int b = 0; b < FN; ++b) {
+            const int j = n0 + wn0 + b * 16 + l16;
+            if (j >= N) continue;
+#pragma unroll
+            for (int a = 0; a < FM; ++a)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int i = m0 + wm0 + a * 16 + Mfma<T>::row(lane, r);
+                    if (i < M) W[(long)i * N + j] = alpha * acc[a][b][r];
+                }
+        }
+        return;
+    }
+    T* __restrict__ C = (T*)P.C;
+#pragma unroll
+    for (int b = 0; b < FN; ++b) {
+        const int j = n0 + wn0 + b * 16 + l16;
+        if (j >= N) continue;
+        const long cj = (long)(j / P.c_cols0) * P.c_cs1 + (long)(j % P.c_cols0) * P.c_cs0;
+#pragma unroll
+        for (int a = 0; a < FM; ++a) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = m0 + wm0 + a * 16 + Mfma<T>::row(lane, r);
+                if (i >= M) continue;
+                const long off =
+                    (long)(i / P.c_rows0) * P.c_rs1 + (long)(i % P.c_rows0) * P.c_rs0 + cj;
+                T v = alpha * acc[a][b][r];
+                if (beta != T(0)) v += beta * C[off];
+                C[off] = v;
+            }
+        }
+    }
+}
+
 // C = sum over splits (fixed order) + beta C, with C's two-level indexing.
 template <typename T>
 __global__ __launch_bounds__(256) void k_splitk_reduce(const GemmProb* __restrict__ probs) {
@@ -619,9 +870,35 @@ __global__ __launch_bounds__(256) void k_splitk_reduce(const GemmProb* __restric
     }
 }
 
+// panel tiles: np in 80..128, skinny M or N
+template <typename T, int BK, int TAG, int BF>
+static void launch_panel(hipStream_t stream, GemmTile tile, const GemmProb* d_probs, int nprob, dim3 grid) {
+    dim3 block(256);
+    const int np = 16 * ((tile - TILE_PANEL) % 16);
+    const bool sm = (tile - TILE_PANEL) >= 16;
+#define IPEPS_PANEL(NP)                                                                                   \
+    if (np == NP) {                                                                                       \
+        if (sm)                                                                                           \
+            hipLaunchKernelGGL((k_gemm_panel<T, NP, 64, BK, 1, 2, TAG, BF>), grid, block, 0, stream, d_probs, \
+                               nprob);                                                                    \
+        else                                                                                              \
+            hipLaunchKernelGGL((k_gemm_panel<T, 64, NP, BK, 4, 2, TAG, BF>), grid, block, 0, stream, d_probs, \
+                               nprob);                                                                    \
+        return;                                                                                           \
+    }
+    IPEPS_PANEL(80)
+    IPEPS_PANEL(96)
+    IPEPS_PANEL(112)
+    IPEPS_PANEL(128)
+#undef IPEPS_PANEL
+    IPEPS_REQUIRE(false, IPEPS_EINVAL, "gemm: no panel kernel of this width");
+}
+
 template <int TAG, int BF>
 static void launch_f32(hipStream_t stream, GemmTile tile, const GemmProb* d_probs, int nprob, dim3 grid) {
     dim3 block(256);
+    if constexpr (TAG == 0)  // (panel tiles never carry the cut products)
+        if (is_panel(tile)) return launch_panel<float, 32, TAG, BF>(stream, tile, d_probs, nprob, grid);
     if (tile == TILE_DIRECT)
         hipLaunchKernelGGL((k_gemm_direct<float, 128, 128, 32, 2, TAG, BF>), grid, block, 0, stream, d_probs,
                            nprob);
@@ -643,6 +920,8 @@ static void launch_tagged(hipStream_t stream, int dtype, GemmTile tile, const Ge
     if (dtype == IPEPS_DTYPE_BF16) return launch_f32<TAG, 1>(stream, tile, d_probs, nprob, grid);
     if (dtype == IPEPS_DTYPE_BF16X3) return launch_f32<TAG, 3>(stream, tile, d_probs, nprob, grid);
     if (dtype != IPEPS_DTYPE_FP64) return launch_f32<TAG, 0>(stream, tile, d_probs, nprob, grid);
+    if constexpr (TAG == 0)
+        if (is_panel(tile)) return launch_panel<double, 16, TAG, 0>(stream, tile, d_probs, nprob, grid);
     if (tile == TILE_DIRECT)
         hipLaunchKernelGGL((k_gemm_direct<double, 128, 128, 16, 2, TAG>), grid, block, 0, stream, d_probs,
                            nprob);
