@@ -16,8 +16,8 @@ projector SVDs and normalisations in FP64 (--dtype fp64 runs everything in
 FP64; with FP32 the FP64 path is also timed and reported as fp64_path).
 
 Prints one JSON line.  The roofline entry is for the dominant kernel family,
-the environment-contraction GEMMs (k_gemm_direct / k_gemm_grouped in the
-contraction precision: enlarged corners, cut-matrix chains, projectors, C
+the environment-contraction GEMMs (k_gemm_direct / k_gemm_panel /
+k_gemm_grouped in the contraction precision: enlarged corners, cut-matrix chains, projectors, C
 and T renormalisation), every launch of the timed steps on the library's
 stream: their algorithmic flops / their summed HIP-event time.  corner_launch
 is the single largest launch (8 enlarged corners).  step_mfma_frac is the
@@ -58,8 +58,8 @@ ROOF_KERNEL = "k_gemm_direct<...,TAG=1> (8 enlarged-corner products)"
 # traffic profile in profiles/; valid only for the tile planning, kernels
 # and launches they were measured on (the part of gemm.hip from tile_dims
 # on, see gemm_kernel_digest).  Keyed by contraction precision.
-TRAFFIC = {"fp32": {"kernel": "gemm_family", "gemm_kernel_sha256_16": "38718641a46a7d03",
-                    "bytes_per_launch": 1.4166e8,
+TRAFFIC = {"fp32": {"kernel": "gemm_family", "gemm_kernel_sha256_16": "419e68446ac75529",
+                    "bytes_per_launch": 1.3286e8,
                     "note": "FETCH_SIZE + WRITE_SIZE per GEMM launch (with its split-K sum), steady "
                             "steps, profiles/traffic_contraction_gemms_D6_chi72_fp32.md"}}
 
@@ -411,7 +411,7 @@ def gemm_roofline(rec, dtype):
     ach = fl / (ms * 1e-3) / 1e12 if ms > 0 else 0.0
     return {"bound": "mfma", "achieved": ach, "peak": PEAK_TFLOPS[dtype], "unit": "TFLOP/s",
             "frac": ach / PEAK_TFLOPS[dtype], "traffic": None,
-            "kernel": f"k_gemm_direct / k_gemm_grouped in {dtype}: every environment-contraction GEMM "
+            "kernel": f"k_gemm_direct / k_gemm_panel / k_gemm_grouped in {dtype}: every environment-contraction GEMM "
                       f"launch of the timed steps (main stream)",
             "launches_per_step": n / rec["prof_steps"], "launch_ms": ms / max(1, n),
             "flops_per_launch": fl / max(1, n), "algorithmic_bytes_per_launch": by / max(1, n),

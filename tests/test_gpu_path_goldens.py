@@ -10,7 +10,9 @@ Cases and the device paths they reach (FP64 unless stated):
   D3_chi108   n = 972, k = 144 (> 128): the Cholesky with R in global memory
               and the wide Jacobi variants
   D6_chi72    the headline sizes n = 2592: 128 x 128 tiles for the enlarged
-              corners and the T update, split-K 5, k = 96 (FP64) / 80 (FP32)
+              corners and the T update, panel tiles for the subspace chains,
+              k = 96 (FP64) / 80 (FP32); a fixed 8 cold CTMRG iterations per
+              observation (environment not converged: spectra not compared)
   D6_chi72_neel10
               the headline model from Néel ⊗ |+>, 10 Trotter steps, 10 cold
               CTMRG iterations (the throughput schedule's observation)
