@@ -627,8 +627,10 @@ void build_plan(ipeps_state* st) {
             cs.aux_s3 = add_group(st, a3, dt);
             cs.half = add_group(st, half, dt);
             cs.nprod = add_group(st, np, dt);
-            cs.proj = add_group(st, pr, dt);
-            cs.proj2 = add_group(st, pr2, dt);
+            // P_up's chi rows against n x n factors: panel tiles when chi is in
+            // 65..128 (64 x 64 tiles otherwise)
+            cs.proj = add_group(st, pr, dt, st->factored ? kChainTile : -1);
+            cs.proj2 = add_group(st, pr2, dt, st->factored ? kChainTile : -1);
             cs.w1 = add_group(st, w1, dt);
             cs.w2 = add_group(st, w2, dt);
             cs.fin = add_group(st, fin, dt);
@@ -1034,6 +1036,15 @@ void apply_nt(const Ex& x, int si) {
     if (st->dtype != IPEPS_DTYPE_FP64) to_fp64(st->stream, st->dtype, st->Ch[2], st->Zw, 2 * nk, x.jm);
 }
 
+// Columns of a projector SVD's matrix A left unrotated by the Jacobi: below
+// skip |A|_F, i.e. below skip sqrt(k) sigma_1, far under the projector
+// cutoff (a kept direction never rotated against the dominant ones would
+// break P_up P_low = 1): 1e-14 with FP64 products (cutoff 1e-12), 5e-11 with
+// FP32 or BF16 products (cutoff 1e-9; 5e-11 sqrt(k) < 1e-9 up to k = 400).
+// The rotations among the columns between 1e-14 and 5e-11 of |A|_F cost the
+// Rayleigh-Ritz Jacobi about one of its seven sweeps at D=6, chi=72, k=80.
+double svd_skip(const ipeps_state* st) { return st->dtype == IPEPS_DTYPE_FP64 ? 1e-14 : 5e-11; }
+
 // Truncated SVD of the two cut matrices (formed in N64, or applied through
 // the enlarged corners in E); fills Us, Vs and g_dev.
 void projector_svd(const Ex& x, int slot) {
@@ -1042,7 +1053,8 @@ void projector_svd(const Ex& x, int slot) {
     hipStream_t s = st->stream;
     const JobMap& jm = x.jm;
     if (n <= kDirectMax) {
-        jacobi_svd_real(s, 2, n, n, st->N64, n, (long)n * n, st->sig, st->Uo, st->Vo, st->jwork, 1e-14, jm);
+        jacobi_svd_real(s, 2, n, n, st->N64, n, (long)n * n, st->sig, st->Uo, st->Vo, st->jwork, svd_skip(st),
+                        jm);
         projector_factors(s, st->dtype, 2, n, n, chi, proj_cutoff(st), st->Uo, st->Vo, st->sig,
                           (long)n * n, st->Us, st->Vs, (long)n * chi, st->g_dev, jm);
         return;
@@ -1077,12 +1089,11 @@ void projector_svd(const Ex& x, int slot) {
     copy_jobs(s, st->Zw, st->Yw, 2 * nk * sizeof(double), jm);
     orth(x, st->Yw, st->Qw, P.gramY, P.QfromY, P.gramQ, P.YfromQ, true);
     run(x, P.Cs);  // Cs = (Q^T N V)^T
-    // Rayleigh-Ritz SVD.  Columns are left unrotated only below 1e-14 |Cs|_F,
-    // far under the projector cutoff: a kept direction that was never rotated
-    // against the dominant ones would break P_up P_low = 1.  (Taking the right
-    // vectors as Cs^T U S^-1 instead of accumulating them halves the Jacobi
-    // traffic but moved the FP32 imbalance by 2e-4 at D=6, chi=72; not used.)
-    jacobi_svd_real(s, 2, k, k, st->Cs, k, (long)k * k, st->sig, st->Uc, st->Vc, st->jwork, 1e-14, jm);
+    // Rayleigh-Ritz SVD (columns below svd_skip |Cs|_F left unrotated).
+    // (Taking the right vectors as Cs^T U S^-1 instead of accumulating them
+    // halves the Jacobi traffic but moved the FP32 imbalance by 2e-4 at D=6,
+    // chi=72; not used.)
+    jacobi_svd_real(s, 2, k, k, st->Cs, k, (long)k * k, st->sig, st->Uc, st->Vc, st->jwork, svd_skip(st), jm);
     run(x, P.Uo);
     run(x, P.Vo);
     copy_jobs(s, st->warm + 2 * slot * nk, st->Vo, 2 * nk * sizeof(double), jm);
