@@ -157,12 +157,14 @@ FF_FLOP_PER_SITE = 28  # per application of (h - b)/a to a complex orbital: 5-po
 
 def spectrum_ipr_record(P, torch, synthetic, tau, with_cpu, n_real=100, h=100.0, reps=3):
     """Single-particle spectra and IPRs (the spectrum figure's h = 100, 100
-    realizations) at L = 10 and at the device's largest lattice L = 16, inputs
-    resident on the device; the oracle (numpy eigh per realization) timed on
-    the host for the same batch."""
+    realizations) at L = 10, 16 (one-sided Jacobi, one workgroup per
+    realization) and L = 20, 40 (block Jacobi), inputs resident on the device;
+    the oracle (numpy eigh per realization) timed on the host for the same
+    batch (L = 40: on 3 of the realizations, scaled)."""
     import numpy as np
     rec = {}
-    for L in (10, 16):
+    for L in (10, 16, 20, 40):
+        reps_l = reps if L <= 16 else 1
         n = L * L
         eps_h = synthetic.ff_fields(L, n_real, h, "continuous", 20191025)
         eps = torch.from_numpy(eps_h).cuda()
@@ -177,22 +179,27 @@ def spectrum_ipr_record(P, torch, synthetic, tau, with_cpu, n_real=100, h=100.0,
         stream.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(stream)
-        for _ in range(reps):
+        for _ in range(reps_l):
             run()
         e1.record(stream)
         stream.synchronize()
-        ms = e0.elapsed_time(e1) / reps
+        ms = e0.elapsed_time(e1) / reps_l
+        how = ("one-sided Jacobi SVD of h + 2G I per realization" if L <= 16 else
+               "block Jacobi, 32-index blocks, 64 x 64 MFMA rotations")
         r = {"workload": f"spectrum + IPR + cumulative IPR: L={L}, open, continuous h={h:g}, tau={tau}, "
-                         f"{n_real} realizations (one-sided Jacobi SVD of h + 2G I per realization)",
+                         f"{n_real} realizations ({how})",
              "value": n_real / (ms * 1e-3), "unit": "realizations/s", "ms_per_batch": ms,
              "mean_ipr": float(I.mean().item())}
         if with_cpu:
             from oracle import freefermion as off
+            ns = n_real if L <= 20 else 3
             t0 = time.perf_counter()
-            for k in range(n_real):
+            for k in range(ns):
                 off.spectrum_ipr(L, False, tau, eps_h[k])
-            r["cpu_baseline"] = {"value": n_real / (time.perf_counter() - t0), "unit": "realizations/s",
-                                 "kind": "oracle", "sample": f"the same {n_real} realizations"}
+            r["cpu_baseline"] = {"value": ns / (time.perf_counter() - t0), "unit": "realizations/s",
+                                 "kind": "oracle",
+                                 "sample": f"the same {n_real} realizations" if ns == n_real else
+                                           f"{ns} of the {n_real} realizations"}
         rec[f"L{L}"] = r
     return rec
 

@@ -67,11 +67,18 @@ int ff_neel_dynamics_noalloc(int L, int pbc, double tau, double dt, int n_times,
  * and cumulative-IPR figures of the non-interacting section: the IPR
  * equation I_k = sum_i |<i|E_k>|^4 and the rescaled energy
  * epsilon(E) = (E - E_min) / (E_max - E_min)) of n_real realizations of h
- * (model as above), on hip_stream; returns after enqueueing.
- *   L          1..16 (the L^2 x L^2 eigenproblem is solved in one workgroup
- *              per realization: a one-sided Jacobi SVD of h + c I, with c
- *              twice a Gershgorin bound, whose singular vectors are the
- *              eigenvectors of h)
+ * (model as above), on hip_stream.
+ *   L          1..40.  L <= 16: the L^2 x L^2 eigenproblem is solved in one
+ *              workgroup per realization (a one-sided Jacobi SVD of h + c I,
+ *              with c twice a Gershgorin bound G, whose singular vectors are
+ *              the eigenvectors of h); returns after enqueueing.  L > 16: a
+ *              two-sided block Jacobi over blocks of 32 indices (each pair of
+ *              blocks diagonalised exactly, its rotation applied to h and to
+ *              the eigenvectors as 64 x 64 MFMA products), all realizations
+ *              in every launch; the call waits for the stream once per sweep
+ *              to test convergence (off-diagonal part of h below 1e-12 of its
+ *              Frobenius norm, or at the level the 64 x 64 solves reach) and
+ *              returns after enqueueing the readout
  *   pbc, tau   as above
  *   eps        DEVICE, FP64, n_real * L*L fields, realization-major
  *   energies   DEVICE, FP64, n_real * L*L: the energies of each realization
@@ -87,9 +94,12 @@ int ff_neel_dynamics_noalloc(int L, int pbc, double tau, double dt, int n_times,
  * Eigenvectors of degenerate energies are any orthonormal basis of their
  * space (their IPRs are not unique).  The caller owns all buffers; the
  * library allocates a stream-ordered workspace of about
- * 16 * n_real * L^4 bytes for the call.  Returns IPEPS_OK, IPEPS_EINVAL
+ * 16 * n_real * L^4 bytes for the call (L > 16: 16 * n_real * np^2 with np
+ * = L^2 rounded up to a multiple of 64).  Returns IPEPS_OK, IPEPS_EINVAL
  * (argument out of range, a NULL buffer with work to do, n_real > 65535),
- * IPEPS_ENOMEM, IPEPS_EDEVICE.  NaN fields give NaN outputs. */
+ * IPEPS_ENOMEM, IPEPS_ENOTCONV (L > 16: not converged in 60 sweeps; the
+ * outputs hold the last iterate), IPEPS_EDEVICE.  NaN fields give NaN
+ * outputs (L > 16: IPEPS_ENOTCONV). */
 int ff_spectrum_ipr(int L, int pbc, double tau, int n_real, const double* eps, double* energies,
                     double* ipr, double* bin_ipr, int* bin_count, void* hip_stream);
 

@@ -20,6 +20,7 @@
 #include <cmath>
 #include <cstdio>
 #include <mutex>
+#include <vector>
 
 #include "common.h"
 #include "linalg.h"
@@ -412,6 +413,319 @@ __global__ __launch_bounds__(256) void k_ff_ipr(int n, const double* sig, const 
     }
 }
 
+
+// ------------------------------------------------- block Jacobi (L > 16)
+// The L^2 x L^2 eigenproblems beyond one workgroup's LDS: a two-sided block
+// Jacobi on h (padded to np = 32 nb rows with decoupled diagonal entries 3G
+// above the spectrum), blocks of 32 indices paired by the circle method
+// (nb - 1 rounds a sweep, nb rounded up to even, so padding may fill a
+// whole block).  Per round and pair (I, J): the 64 x 64 block
+// S = h[IJ, IJ] is diagonalised exactly (one-sided Jacobi of S + 2G I, which
+// is positive definite, so its right singular vectors Q are eigenvectors of
+// S), then h <- Q^T h Q on the rows and columns IJ and V <- V Q, as 64 x 64
+// MFMA products per 64-row (or 64-column) chunk.  Sweeps end once the
+// squared off-diagonal part of h is below 1e-24 of its squared Frobenius
+// norm, or below 1e-18 and no longer shrinking by 4x per sweep (the level
+// the 64 x 64 solves can reach).
+constexpr int kBjB = 32, kBjW = 2 * kBjB;
+
+__device__ inline void bj_pair(int r, int kk, int nbp, int* p, int* q) {
+    if (kk == 0) {
+        *p = r;
+        *q = nbp - 1;
+    } else {
+        const int m = nbp - 1;
+        *p = r + kk >= m ? r + kk - m : r + kk;
+        *q = r - kk < 0 ? r - kk + m : r - kk;
+    }
+    if (*p > *q) {
+        const int t = *p;
+        *p = *q;
+        *q = t;
+    }
+}
+
+// h padded to np (decoupled 3G on the padded diagonal), V = I, G per
+// realization (max |eps| + 4 |tau|, 1 when that is 0)
+__global__ __launch_bounds__(256) void k_bj_init(int L, int pbc, double tau, const double* eps, int np,
+                                                 double* H, double* V, double* gmax) {
+    __shared__ double red[4];
+    const int b = blockIdx.y, n = L * L;
+    const double* e = eps + (long)b * n;
+    double g = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) g = fmax(g, fabs(e[i]));
+    g = block_max(g, red) + 4.0 * fabs(tau);
+    if (!(g > 0.0)) g = 1.0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) gmax[b] = g;
+    double* Hb = H + (long)b * np * np;
+    double* Vb = V + (long)b * np * np;
+    for (long idx = blockIdx.x * (long)blockDim.x + threadIdx.x; idx < (long)np * np;
+         idx += (long)gridDim.x * blockDim.x) {
+        const int i = (int)(idx / np), j = (int)(idx % np);
+        double v = 0.0;
+        if (i >= n || j >= n) {
+            v = i == j ? 3.0 * g : 0.0;
+        } else if (i == j) {
+            v = e[i];
+        } else {
+            int dx = j / L - i / L, dy = j % L - i % L;
+            bool adj;
+            if (pbc) {
+                dx = (dx + L) % L;
+                dy = (dy + L) % L;
+                adj = ((dx == 1 || dx == L - 1) && dy == 0) || (dx == 0 && (dy == 1 || dy == L - 1));
+            } else {
+                adj = (abs(dx) == 1 && dy == 0) || (dx == 0 && abs(dy) == 1);
+            }
+            if (adj) v = -tau;
+        }
+        Hb[idx] = v;
+        Vb[idx] = i == j ? 1.0 : 0.0;
+    }
+}
+
+// global index of entry t (< 64) of pair (p, q)
+__device__ inline int bj_index(int t, int p, int q) { return t < kBjB ? p * kBjB + t : q * kBjB + t - kBjB; }
+
+// S = h[IJ, IJ] + 2G I for every pair of the round (pairs kk0 .. of the
+// circle method), 64 x 64 row-major each
+__global__ __launch_bounds__(256) void k_bj_gather(int np, int nbp, int round, int kk0, const double* H,
+                                                   const double* gmax, double* S) {
+    const int pi = blockIdx.x, npe = gridDim.x, b = blockIdx.y;
+    int p, q;
+    bj_pair(round, pi + kk0, nbp, &p, &q);
+    const double* Hb = H + (long)b * np * np;
+    double* Sb = S + ((long)b * npe + pi) * kBjW * kBjW;
+    const double c = 2.0 * gmax[b];
+    for (int e = threadIdx.x; e < kBjW * kBjW; e += blockDim.x) {
+        const int i = e / kBjW, j = e % kBjW;
+        Sb[e] = Hb[(long)bj_index(i, p, q) * np + bj_index(j, p, q)] + (i == j ? c : 0.0);
+    }
+}
+
+// One 64 x 64 x 64 FP64 product per workgroup on v_mfma_f64_16x16x4f64,
+// operands in LDS as unpadded 64 x 64 row-major tiles (64 KB for two):
+// wave w computes rows 16 w .. 16 w + 15 of C = A B; result register r of
+// lane l is row l / 16 + 4 r, column l % 16 of its 16 x 16 block.  An A
+// tile read by rows (lane i of a 16-lane group takes row i, the group takes
+// column k) stores element (i, j) at column j ^ 2 (i % 16); a tile read by
+// columns (B, or A^T: a 16-lane group takes 16 consecutive columns of row
+// k) stores it at column j ^ 16 (i % 2).  Either way the two 16-lane groups
+// of a half-wave read 32 distinct bank pairs.
+typedef double bj_d4 __attribute__((ext_vector_type(4)));
+__device__ inline int bj_rsw(int i, int j) { return i * kBjW + (j ^ (2 * (i & 15))); }
+__device__ inline int bj_csw(int i, int j) { return i * kBjW + (j ^ (16 * (i & 1))); }
+template <bool TRANS_A>
+__device__ inline void bj_mm(const double* As, const double* Bs, bj_d4 acc[4]) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int i = lane & 15, kq = lane >> 4;
+#pragma unroll
+    for (int f = 0; f < 4; ++f) acc[f] = bj_d4{0, 0, 0, 0};
+#pragma unroll 4
+    for (int s = 0; s < kBjW / 4; ++s) {
+        const int k = 4 * s + kq;
+        const double a = TRANS_A ? As[bj_csw(k, 16 * w + i)] : As[bj_rsw(16 * w + i, k)];
+#pragma unroll
+        for (int f = 0; f < 4; ++f)
+            acc[f] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, Bs[bj_csw(k, 16 * f + i)], acc[f], 0, 0, 0);
+    }
+}
+
+// columns IJ of h (z = 0) and of V (z = 1) times Q, one 64-row chunk
+__global__ __launch_bounds__(256) void k_bj_cols(int np, int nbp, int round, int kk0, int npe, double* H,
+                                                 double* V, const double* Q) {
+    __shared__ double As[kBjW * kBjW], Qs[kBjW * kBjW];
+    const int pi = blockIdx.x % npe, b = blockIdx.y;
+    double* M = (blockIdx.z ? V : H) + (long)b * np * np;
+    int p, q;
+    bj_pair(round, pi + kk0, nbp, &p, &q);
+    const double* Qb = Q + ((long)b * npe + pi) * kBjW * kBjW;
+    const int row0 = (blockIdx.x / npe) * kBjW;
+    for (int e = threadIdx.x; e < kBjW * kBjW; e += blockDim.x) {
+        const int i = e / kBjW, j = e % kBjW;
+        As[bj_rsw(i, j)] = M[(long)(row0 + i) * np + bj_index(j, p, q)];
+        Qs[bj_csw(i, j)] = Qb[e];
+    }
+    __syncthreads();
+    bj_d4 acc[4];
+    bj_mm<false>(As, Qs, acc);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int f = 0; f < 4; ++f)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int i = 16 * w + (lane >> 4) + 4 * r, j = 16 * f + (lane & 15);
+            M[(long)(row0 + i) * np + bj_index(j, p, q)] = acc[f][r];
+        }
+}
+
+// rows IJ of h: Q^T times them, one 64-column chunk
+__global__ __launch_bounds__(256) void k_bj_rows(int np, int nbp, int round, int kk0, int npe, double* H,
+                                                 const double* Q) {
+    __shared__ double Bs[kBjW * kBjW], Qs[kBjW * kBjW];
+    const int pi = blockIdx.x % npe, b = blockIdx.y;
+    double* Hb = H + (long)b * np * np;
+    int p, q;
+    bj_pair(round, pi + kk0, nbp, &p, &q);
+    const double* Qb = Q + ((long)b * npe + pi) * kBjW * kBjW;
+    const int col0 = (blockIdx.x / npe) * kBjW;
+    for (int e = threadIdx.x; e < kBjW * kBjW; e += blockDim.x) {
+        const int i = e / kBjW, j = e % kBjW;
+        Bs[bj_csw(i, j)] = Hb[(long)bj_index(i, p, q) * np + col0 + j];
+        Qs[bj_csw(i, j)] = Qb[e];
+    }
+    __syncthreads();
+    bj_d4 acc[4];
+    bj_mm<true>(Qs, Bs, acc);  // (Q^T)(i, k) = Q(k, i)
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int f = 0; f < 4; ++f)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int i = 16 * w + (lane >> 4) + 4 * r, j = 16 * f + (lane & 15);
+            Hb[(long)bj_index(i, p, q) * np + col0 + j] = acc[f][r];
+        }
+}
+
+// off-diagonal over total squared Frobenius norm of h, per realization
+__global__ __launch_bounds__(256) void k_bj_off(int np, const double* H, double* ratio) {
+    __shared__ double red[4];
+    const int b = blockIdx.x;
+    const double* Hb = H + (long)b * np * np;
+    double off = 0.0, tot = 0.0;
+    for (long idx = threadIdx.x; idx < (long)np * np; idx += blockDim.x) {
+        const double v = Hb[idx];
+        tot += v * v;
+        if (idx / np != idx % np) off += v * v;
+    }
+    off = block_sum(off, red);
+    tot = block_sum(tot, red);
+    if (threadIdx.x == 0) ratio[b] = tot > 0.0 ? off / tot : 0.0;
+}
+
+// energies ascending (the diagonal of the converged h, the np - n padded
+// entries 3G last and dropped), IPR of the matching columns of V, bins as
+// k_ff_ipr; one realization per workgroup
+constexpr int kBjMaxN = 1600;
+__global__ __launch_bounds__(1024) void k_bj_ipr(int n, int np, const double* H, const double* V, double* E,
+                                                 double* ipr, double* bin_ipr, int* bin_cnt) {
+    __shared__ double d[kBjMaxN + kBjB], Es[kBjMaxN], Is[kBjMaxN];
+    __shared__ int Bs[kBjMaxN];
+    const int b = blockIdx.x;
+    const double* Hb = H + (long)b * np * np;
+    const double* Vb = V + (long)b * np * np;
+    for (int k = threadIdx.x; k < np; k += blockDim.x) d[k] = Hb[(long)k * np + k];
+    __syncthreads();
+    for (int k = threadIdx.x; k < np; k += blockDim.x) {
+        const double dk = d[k];
+        int rank = 0;
+        for (int l = 0; l < np; ++l) rank += (d[l] < dk) || (d[l] == dk && l < k);
+        if (rank < n) {
+            double s4 = 0.0;
+            for (int i = 0; i < n; ++i) {
+                const double u = Vb[(long)i * np + k];
+                s4 += (u * u) * (u * u);
+            }
+            Es[rank] = dk;
+            Is[rank] = s4;
+        }
+    }
+    __syncthreads();
+    const double lo = Es[0], hi = Es[n - 1];
+    for (int a = threadIdx.x; a < n; a += blockDim.x) {
+        int bin = 0;
+        if (hi > lo) {
+            bin = (int)floor((Es[a] - lo) / (hi - lo) / 0.05);
+            bin = bin < kIprBins - 1 ? bin : kIprBins - 1;
+        }
+        Bs[a] = bin;
+        E[(long)b * n + a] = Es[a];
+        ipr[(long)b * n + a] = Is[a];
+    }
+    __syncthreads();
+    if (threadIdx.x < kIprBins) {
+        double sum = 0.0;
+        int cnt = 0;
+        for (int a = 0; a < n; ++a)
+            if (Bs[a] == (int)threadIdx.x) {
+                sum += Is[a];
+                ++cnt;
+            }
+        bin_ipr[(long)b * kIprBins + threadIdx.x] = sum;
+        bin_cnt[(long)b * kIprBins + threadIdx.x] = cnt;
+    }
+}
+
+// Enqueue the block Jacobi for n_real realizations on s; waits on the host
+// once per sweep for the convergence test.  Returns IPEPS_OK, IPEPS_ENOMEM,
+// IPEPS_ENOTCONV (60 sweeps) or IPEPS_EDEVICE.
+int bj_spectrum_ipr(hipStream_t s, int L, int pbc, double tau, int n_real, const double* eps, double* energies,
+                    double* ipr, double* bin_ipr, int* bin_count) {
+    const int n = L * L;
+    int nb = (n + kBjB - 1) / kBjB;
+    nb += nb & 1;  // even: every block has a partner, and np is a multiple of 64
+    const int np = nb * kBjB, nbp = nb, kk0 = 0, npe = nb / 2, nch = np / kBjW;
+    const long nn = (long)np * np;
+    const size_t doubles = 2 * (size_t)n_real * nn + 2 * (size_t)n_real * npe * kBjW * kBjW +
+                           (size_t)n_real * npe * kBjW + 2 * (size_t)n_real;
+    double* ws = nullptr;
+    if (hipMallocAsync((void**)&ws, doubles * sizeof(double), s) != hipSuccess) {
+        (void)hipGetLastError();
+        return IPEPS_ENOMEM;
+    }
+    double* H = ws;
+    double* V = H + (long)n_real * nn;
+    double* S = V + (long)n_real * nn;
+    double* Q = S + (long)n_real * npe * kBjW * kBjW;
+    double* sig = Q + (long)n_real * npe * kBjW * kBjW;
+    double* gmax = sig + (long)n_real * npe * kBjW;
+    double* ratio = gmax + n_real;
+    int rc = IPEPS_OK;
+    std::vector<double> hr(n_real);
+    try {
+        const int gi = (int)std::min<long>(1024, (nn + 255) / 256);
+        hipLaunchKernelGGL(k_bj_init, dim3(gi, n_real), dim3(256), 0, s, L, pbc, tau, eps, np, H, V, gmax);
+        HIP_CHECK(hipGetLastError());
+        bool conv = false;
+        double prev = 1.0;
+        for (int sweep = 0; sweep < 60 && !conv; ++sweep) {
+            for (int round = 0; round < nbp - 1; ++round) {
+                hipLaunchKernelGGL(k_bj_gather, dim3(npe, n_real), dim3(256), 0, s, np, nbp, round, kk0, H,
+                                   gmax, S);
+                jacobi_svd_real(s, n_real * npe, kBjW, kBjW, S, kBjW, (long)kBjW * kBjW, sig, nullptr, Q,
+                                nullptr, 0.0);
+                hipLaunchKernelGGL(k_bj_cols, dim3(nch * npe, n_real, 2), dim3(256), 0, s, np, nbp, round, kk0,
+                                   npe, H, V, Q);
+                hipLaunchKernelGGL(k_bj_rows, dim3(nch * npe, n_real), dim3(256), 0, s, np, nbp, round, kk0, npe,
+                                   H, Q);
+            }
+            hipLaunchKernelGGL(k_bj_off, dim3(n_real), dim3(256), 0, s, np, H, ratio);
+            HIP_CHECK(hipGetLastError());
+            HIP_CHECK(hipMemcpyAsync(hr.data(), ratio, n_real * sizeof(double), hipMemcpyDeviceToHost, s));
+            HIP_CHECK(hipStreamSynchronize(s));
+            double worst = 0.0;
+            bool nan = false;
+            for (double v : hr) {
+                nan = nan || std::isnan(v);
+                worst = std::max(worst, v);
+            }
+            if (nan) break;  // NaN fields: the outputs carry them, IPEPS_ENOTCONV
+            // converged: below 1e-24, or below 1e-18 and no longer shrinking
+            // (the floor the 64 x 64 solves leave: they diagonalise S + 2G I
+            // to 4 (2b) eps relative, i.e. leave entries ~1e-13 G of S)
+            conv = worst < 1e-24 || (worst < 1e-18 && worst > 0.25 * prev);
+            prev = worst;
+        }
+        if (!conv) rc = IPEPS_ENOTCONV;
+        hipLaunchKernelGGL(k_bj_ipr, dim3(n_real), dim3(1024), 0, s, n, np, H, V, energies, ipr, bin_ipr,
+                           bin_count);
+        HIP_CHECK(hipGetLastError());
+    } catch (...) {
+        rc = IPEPS_EDEVICE;
+    }
+    if (hipFreeAsync(ws, s) != hipSuccess) rc = IPEPS_EDEVICE;
+    return rc;
+}
 }  // namespace ipeps
 
 extern "C" {
@@ -544,11 +858,16 @@ int ff_neel_dynamics_noalloc(int L, int pbc, double tau, double dt, int n_times,
 int ff_spectrum_ipr(int L, int pbc, double tau, int n_real, const double* eps, double* energies,
                     double* ipr, double* bin_ipr, int* bin_count, void* hip_stream) {
     using namespace ipeps;
-    if (L < 1 || L > 16 || (pbc != 0 && pbc != 1) || (pbc && L < 3)) return IPEPS_EINVAL;
+    if (L < 1 || L > 40 || (pbc != 0 && pbc != 1) || (pbc && L < 3)) return IPEPS_EINVAL;
     if (!std::isfinite(tau) || n_real < 0 || n_real > 65535) return IPEPS_EINVAL;
     if (n_real == 0) return IPEPS_OK;
     if (!eps || !energies || !ipr || !bin_ipr || !bin_count) return IPEPS_EINVAL;
     hipStream_t s = (hipStream_t)hip_stream;
+    if (L > 16) {
+        const int rc = bj_spectrum_ipr(s, L, pbc, tau, n_real, eps, energies, ipr, bin_ipr, bin_count);
+        if (rc == IPEPS_EDEVICE) fprintf(stderr, "ff_spectrum_ipr: HIP error in the block Jacobi\n");
+        return rc;
+    }
     const int n = L * L;
     const long nn = (long)n_real * n * n;
     const size_t jw = jacobi_svd_real_work(n_real, n, n);
