@@ -272,20 +272,26 @@ def serving_sample(P, synthetic, dtype, rate, n_req=12, steps_max=10, slots=64):
     srv = P.Server(hbm_budget=0, max_slots=slots)
     t0 = time.perf_counter()
     ids = []
-    for r in reqs:
+    for k, r in enumerate(reqs):
         cfg = P.make_config(r["D"], r["chi"], J=r["J"], V=r["V"], W=r["W"], dt=r["dt"], dtype=dtype)
         while time.perf_counter() - t0 < r["arrival"]:
             time.sleep(0.001)
+        if (k + 1) % 32 == 0:
+            print(f"serving {dtype}: {k + 1}/{len(reqs)} requests submitted ({time.perf_counter() - t0:.0f} s)",
+                  file=sys.stderr, flush=True)
         ids.append(srv.submit(cfg, n_steps=min(r["n_steps"], steps_max), observe_every=r["observe_every"],
                               ctm_iters=r["ctm_iters"]))
     lat, t_last, series = [], 0.0, []
-    for jid in ids:
+    for k, jid in enumerate(ids):
         while True:
             res = srv.poll(jid)[1]
             if res is not None:
                 break
             time.sleep(0.002)
         series.append([o["imbalance"] for o in res])
+        if (k + 1) % 16 == 0:
+            print(f"serving {dtype}: {k + 1}/{len(ids)} requests done ({time.perf_counter() - t0:.0f} s)",
+                  file=sys.stderr, flush=True)
         rc, (ts, ta, td) = srv.times(jid)
         lat.append(td - ts)
         t_last = max(t_last, td)
@@ -443,6 +449,11 @@ def main():
     ap.add_argument("--prelude", type=int, default=20, help="untimed Trotter steps first")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serving-requests", type=int, default=12,
+                    help="requests of the serving stream in the serving sample (the stream has 256)")
+    ap.add_argument("--serving-rate", type=float, default=0.0,
+                    help="arrivals per second for the serving sample, in --dtype only (default: 0.8 x the "
+                         "sweep's jobs/s, in --dtype and FP64)")
     ap.add_argument("--no-free-fermion", action="store_true",
                     help="skip the free-fermion Néel workload (L=40, 100 realizations)")
     ap.add_argument("--no-sweep", action="store_true",
@@ -530,15 +541,21 @@ def main():
             sw["bf16x3_max_imbalance_err_vs_fp64"] = max_err(serb, ser64)
         out["sweep"] = sw
     if not args.no_serving:
-        # requests arrive at 0.8 x the measured capacity of the sweep mix
-        cap = out["sweep"]["jobs_per_s"] if "sweep" in out else 1.0
-        srv, ser = serving_sample(P, synthetic, args.dtype, rate=0.8 * cap)
-        srv64, ser64 = serving_sample(P, synthetic, "fp64", rate=0.8 * cap)
-        srv["fp64_jobs_per_s"] = srv64["jobs_per_s"]
-        srv["fp64_p50_s"], srv["fp64_p99_s"] = srv64["p50_s"], srv64["p99_s"]
-        srv["max_imbalance_err_vs_fp64"] = max_err(ser, ser64)
-        srv["rate_note"] = "0.8 x the sweep's jobs/s in the contraction precision"
-        out["serving"] = srv
+        nreq = args.serving_requests
+        if args.serving_rate > 0:  # a given arrival rate, one precision
+            srv, _ = serving_sample(P, synthetic, args.dtype, rate=args.serving_rate, n_req=nreq)
+            srv["rate_note"] = "--serving-rate"
+            out["serving"] = srv
+        else:
+            # requests arrive at 0.8 x the measured capacity of the sweep mix
+            cap = out["sweep"]["jobs_per_s"] if "sweep" in out else 1.0
+            srv, ser = serving_sample(P, synthetic, args.dtype, rate=0.8 * cap, n_req=nreq)
+            srv64, ser64 = serving_sample(P, synthetic, "fp64", rate=0.8 * cap, n_req=nreq)
+            srv["fp64_jobs_per_s"] = srv64["jobs_per_s"]
+            srv["fp64_p50_s"], srv["fp64_p99_s"] = srv64["p50_s"], srv64["p99_s"]
+            srv["max_imbalance_err_vs_fp64"] = max_err(ser, ser64)
+            srv["rate_note"] = "0.8 x the sweep's jobs/s in the contraction precision"
+            out["serving"] = srv
     if not args.no_free_fermion:
         out["free_fermion"] = free_fermion(P, torch, synthetic, with_cpu=not args.no_cpu_baseline)
     if not args.no_cpu_baseline:
