@@ -8,6 +8,12 @@ until the corner spectra change by less than 1e-10 in one iteration (capped at
 --max-iter), then records the imbalance, occupations, truncation errors,
 corner spectra and bond spectra to tests/golden/plain_W{W}_V{V}.json.
 
+    python tests/golden/make_plain_golden.py W V --extend CAP
+
+reruns, from the same trajectory, the observations of an existing file whose
+CTMRG stopped at the cap above the tolerance, now with cap CAP, and records
+each observation's cap as "max_iter" (converged observations are kept).
+
     python tests/golden/make_plain_golden.py W V --spread
 
 adds to an existing file the oracle's own rounding sensitivity along the
@@ -36,6 +42,7 @@ def main():
     ap.add_argument("V", type=float)
     ap.add_argument("--max-iter", type=int, default=200)
     ap.add_argument("--spread", action="store_true")
+    ap.add_argument("--extend", type=int, default=0)
     args = ap.parse_args()
     cfg = [c for c in synthetic.plain_configs() if c["W"] == args.W and c["V"] == args.V][0]
     p = Params(D=cfg["D"], chi=cfg["chi"], J=cfg["J"], V=cfg["V"], W=cfg["W"], dt=cfg["dt"])
@@ -43,6 +50,9 @@ def main():
     path = os.path.join(ROOT, "tests", "golden", f"plain_W{args.W:g}_V{args.V:g}.json")
     if args.spread:
         add_spread(path, p, cfg)
+        return
+    if args.extend:
+        extend(path, p, cfg, args.extend)
         return
     st = peps.new_state(p)
     for step in range(0, cfg["n_steps"] + 1):
@@ -59,6 +69,31 @@ def main():
                            "bond_spectra": o["bond_spectra"].tolist()})
         print(f"step {step} I={o['imbalance']:.12f} iters={o['ctm_iters']} "
               f"delta={o['ctm_delta']:.2e} ({time.time() - t0:.0f}s)", flush=True)
+        with open(path, "w") as f:
+            json.dump(out, f)
+
+
+def extend(path, p, cfg, cap):
+    with open(path) as f:
+        out = json.load(f)
+    obs = {o["step"]: o for o in out["obs"]}
+    for o in out["obs"]:
+        o.setdefault("max_iter", out["max_iter"])
+    st = peps.new_state(p)
+    for step in range(0, cfg["n_steps"] + 1):
+        if step > 0:
+            peps.trotter_step(st, p)
+        o = obs.get(step)
+        if o is None or o["ctm_delta"] < out["tol"]:
+            continue
+        t0 = time.time()
+        n, _ = run.observe_state(st, p, tol=cfg["ctm_tol"], max_iter=cap)
+        o.update({"imbalance": n["imbalance"], "n": n["n"].tolist(), "eps": n["eps"].tolist(),
+                  "ctm_iters": n["ctm_iters"], "ctm_delta": n["ctm_delta"],
+                  "corner_spectra": n["corner_spectra"].tolist(),
+                  "bond_spectra": n["bond_spectra"].tolist(), "max_iter": cap})
+        print(f"step {step} I={n['imbalance']:.12f} iters={n['ctm_iters']} "
+              f"delta={n['ctm_delta']:.2e} ({time.time() - t0:.0f}s)", flush=True)
         with open(path, "w") as f:
             json.dump(out, f)
 
