@@ -541,10 +541,20 @@ __global__ __launch_bounds__(256) void k_bj_cols(int np, int nbp, int round, int
     bj_pair(round, pi + kk0, nbp, &p, &q);
     const double* Qb = Q + ((long)b * npe + pi) * kBjW * kBjW;
     const int row0 = (blockIdx.x / npe) * kBjW;
-    for (int e = threadIdx.x; e < kBjW * kBjW; e += blockDim.x) {
-        const int i = e / kBjW, j = e % kBjW;
-        As[bj_rsw(i, j)] = M[(long)(row0 + i) * np + bj_index(j, p, q)];
-        Qs[bj_csw(i, j)] = Qb[e];
+    // all loads in flight before the LDS stores (one wait, not one per element)
+    constexpr int PER = kBjW * kBjW / 256;
+    double va[PER], vq[PER];
+#pragma unroll
+    for (int t = 0; t < PER; ++t) {
+        const int e = threadIdx.x + 256 * t, i = e / kBjW, j = e % kBjW;
+        va[t] = M[(long)(row0 + i) * np + bj_index(j, p, q)];
+        vq[t] = Qb[e];
+    }
+#pragma unroll
+    for (int t = 0; t < PER; ++t) {
+        const int e = threadIdx.x + 256 * t, i = e / kBjW, j = e % kBjW;
+        As[bj_rsw(i, j)] = va[t];
+        Qs[bj_csw(i, j)] = vq[t];
     }
     __syncthreads();
     bj_d4 acc[4];
@@ -569,10 +579,19 @@ __global__ __launch_bounds__(256) void k_bj_rows(int np, int nbp, int round, int
     bj_pair(round, pi + kk0, nbp, &p, &q);
     const double* Qb = Q + ((long)b * npe + pi) * kBjW * kBjW;
     const int col0 = (blockIdx.x / npe) * kBjW;
-    for (int e = threadIdx.x; e < kBjW * kBjW; e += blockDim.x) {
-        const int i = e / kBjW, j = e % kBjW;
-        Bs[bj_csw(i, j)] = Hb[(long)bj_index(i, p, q) * np + col0 + j];
-        Qs[bj_csw(i, j)] = Qb[e];
+    constexpr int PER = kBjW * kBjW / 256;
+    double vb[PER], vq[PER];
+#pragma unroll
+    for (int t = 0; t < PER; ++t) {
+        const int e = threadIdx.x + 256 * t, i = e / kBjW, j = e % kBjW;
+        vb[t] = Hb[(long)bj_index(i, p, q) * np + col0 + j];
+        vq[t] = Qb[e];
+    }
+#pragma unroll
+    for (int t = 0; t < PER; ++t) {
+        const int e = threadIdx.x + 256 * t, i = e / kBjW, j = e % kBjW;
+        Bs[bj_csw(i, j)] = vb[t];
+        Qs[bj_csw(i, j)] = vq[t];
     }
     __syncthreads();
     bj_d4 acc[4];
