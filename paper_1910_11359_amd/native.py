@@ -198,7 +198,10 @@ class State:
         self.h = handle
 
     def close(self):
+        """Destroys the state (a batch open over it is closed first)."""
         if getattr(self, "h", None):
+            for b in list(getattr(self, "_batches", ())):
+                b.close()
             self._lib.ipeps_destroy(self.h)
             self.h = None
 
@@ -328,6 +331,10 @@ class Batch:
         h = C.c_void_p()
         _check(self._lib.ipeps_batch_create(arr, len(self.states), C.byref(h)), "ipeps_batch_create")
         self.h = h
+        for st in self.states:  # closing a state closes the batch first
+            if not hasattr(st, "_batches"):
+                st._batches = weakref.WeakSet()
+            st._batches.add(self)
         if graph:
             self.set_graph(True)
 
