@@ -37,13 +37,116 @@ __device__ inline void circle_pair(int r, int k, int ne, int* p, int* q) {
 // theta^2 |a_p||a_q|, far below the convergence test, so the sweep after
 // would rotate nothing that matters (it only confirmed convergence).
 constexpr double kSweepAngle = 1e-9;
+// Tail sweeps: once a sweep rotates no pair that involves a column above
+// kHeadRel |A|_F at all (every such pair passed the relative test), the
+// sweeps that follow pair only the columns below it (the noise-level tail of
+// a Rayleigh-Ritz matrix, whose clustered values converge linearly while the
+// head converges quadratically).  Rotating two tail columns turns their inner
+// products with a head column into combinations of two that already passed
+// the test, the same drift a full last sweep leaves behind its own rotations.
+constexpr double kHeadRel = 1e-6;
+
+// One sweep over the columns list[0..nc) (list == nullptr: columns 0..nc):
+// exact squared norms first, then the ne - 1 rounds of the circle method.
+// Returns whether a rotation turned by more than kSweepAngle; *head is set
+// when any pair with a column above head2 was rotated.
+template <int EPL>
+__device__ __forceinline__ bool jacobi_one_sweep(int m, int n, int nc, const short* list, double* Ac,
+                                                 double* Vc, double* nrm, int* flag, int* head,
+                                                 double tol2, double small2, double head2) {
+    const int g16 = threadIdx.x & 15, group = threadIdx.x >> 4, ngroups = blockDim.x >> 4;
+    const int ne = nc + (nc & 1);
+    const int npair = ne / 2;
+    for (int jj = group; jj < nc; jj += ngroups) {
+        const int j = list ? list[jj] : jj;
+        const double* aj = Ac + (long)j * m;
+        double sq = 0.0;
+#pragma unroll
+        for (int e = 0; e < EPL; ++e) {
+            const int i = g16 + 16 * e;
+            const double v = (i < m) ? aj[i] : 0.0;
+            sq += v * v;
+        }
+        sq = group16_sum(sq);
+        if (g16 == 0) nrm[j] = sq;
+    }
+    if (threadIdx.x == 0) {
+        *flag = 0;
+        *head = 0;
+    }
+    __syncthreads();
+    for (int r = 0; r < ne - 1; ++r) {
+        for (int kk = group; kk < npair; kk += ngroups) {
+            int p, q;
+            circle_pair(r, kk, ne, &p, &q);
+            if (q >= nc) continue;
+            if (list) {
+                p = list[p];
+                q = list[q];
+            }
+            double* ap = Ac + (long)p * m;
+            double* aq = Ac + (long)q * m;
+            double x[EPL], y[EPL];
+            double ga = 0.0;
+#pragma unroll
+            for (int e = 0; e < EPL; ++e) {
+                const int i = g16 + 16 * e;
+                x[e] = (i < m) ? ap[i] : 0.0;
+                y[e] = (i < m) ? aq[i] : 0.0;
+                ga += x[e] * y[e];
+            }
+            ga = group16_sum(ga);
+            const double al = nrm[p], be = nrm[q];
+            if (al <= small2 || be <= small2) continue;
+            // converged pair: relative test, or an inner product below
+            // skip_rel^2 |A|_F^2, which moves no singular value by more
+            // than ~skip_rel |A|_F
+            if (ga * ga <= tol2 * al * be || fabs(ga) <= small2) continue;
+            const double zeta = 0.5 * (be - al) * fast_rcp(ga);
+            const double az = fabs(zeta);
+            const double den = (az > 1e150) ? 2.0 * az : az + (1.0 + az * az) * fast_rsq(1.0 + az * az);
+            const double t = copysign(fast_rcp(den), zeta);
+            const double c = fast_rsq(1.0 + t * t), s = c * t;
+#pragma unroll
+            for (int e = 0; e < EPL; ++e) {
+                const int i = g16 + 16 * e;
+                if (i < m) {
+                    ap[i] = c * x[e] - s * y[e];
+                    aq[i] = s * x[e] + c * y[e];
+                }
+            }
+            if (Vc) {
+                double* vp = Vc + (long)p * n;
+                double* vq = Vc + (long)q * n;
+#pragma unroll
+                for (int e = 0; e < EPL; ++e) {
+                    const int i = g16 + 16 * e;
+                    if (i < n) {
+                        const double xv = vp[i], yv = vq[i];
+                        vp[i] = c * xv - s * yv;
+                        vq[i] = s * xv + c * yv;
+                    }
+                }
+            }
+            if (g16 == 0) {
+                nrm[p] = al - t * ga;
+                nrm[q] = be + t * ga;
+                if (fabs(t) > kSweepAngle) *flag = 1;
+                if (fmax(al, be) > head2) *head = 1;
+            }
+        }
+        __syncthreads();
+    }
+    const bool any = *flag != 0;
+    __syncthreads();
+    return any;
+}
 
 template <int EPL>
-__device__ void jacobi_sweeps(int m, int n, double* Ac, double* Vc, double* nrm, int* flag,
-                              double* red, double skip_rel) {
-    const int g16 = threadIdx.x & 15, group = threadIdx.x >> 4, ngroups = blockDim.x >> 4;
-    const int ne = n + (n & 1);
-    const int npair = ne / 2;
+__device__ __forceinline__ void jacobi_sweeps(int m, int n, double* Ac, double* Vc, double* nrm, int* flag,
+                                              double* red, double skip_rel) {
+    __shared__ int s_head, s_ntail;
+    __shared__ short s_tail[256];
     const double tol = 4.0 * m * 1.11e-16, tol2 = tol * tol;
     // columns below skip_rel |A|_F are left alone: a rotation against a large
     // column re-pollutes them at their own size; pairs whose inner product is
@@ -52,82 +155,29 @@ __device__ void jacobi_sweeps(int m, int n, double* Ac, double* Vc, double* nrm,
     for (long e = threadIdx.x; e < (long)m * n; e += blockDim.x) fro += Ac[e] * Ac[e];
     fro = block_sum(fro, red);
     const double small2 = skip_rel * skip_rel * fro;
-    for (int sweep = 0; sweep < 40; ++sweep) {
-        for (int j = group; j < n; j += ngroups) {
-            const double* aj = Ac + (long)j * m;
-            double sq = 0.0;
-#pragma unroll
-            for (int e = 0; e < EPL; ++e) {
-                const int i = g16 + 16 * e;
-                const double v = (i < m) ? aj[i] : 0.0;
-                sq += v * v;
-            }
-            sq = group16_sum(sq);
-            if (g16 == 0) nrm[j] = sq;
-        }
-        if (threadIdx.x == 0) *flag = 0;
+    const double head2 = kHeadRel * kHeadRel * fro;
+    int sweep = 0;
+    for (; sweep < 40; ++sweep) {
+        if (!jacobi_one_sweep<EPL>(m, n, n, nullptr, Ac, Vc, nrm, flag, &s_head, tol2, small2, head2))
+            return;
+        const int head = s_head;
         __syncthreads();
-        for (int r = 0; r < ne - 1; ++r) {
-            for (int kk = group; kk < npair; kk += ngroups) {
-                int p, q;
-                circle_pair(r, kk, ne, &p, &q);
-                if (q >= n) continue;
-                double* ap = Ac + (long)p * m;
-                double* aq = Ac + (long)q * m;
-                double x[EPL], y[EPL];
-                double ga = 0.0;
-#pragma unroll
-                for (int e = 0; e < EPL; ++e) {
-                    const int i = g16 + 16 * e;
-                    x[e] = (i < m) ? ap[i] : 0.0;
-                    y[e] = (i < m) ? aq[i] : 0.0;
-                    ga += x[e] * y[e];
-                }
-                ga = group16_sum(ga);
-                const double al = nrm[p], be = nrm[q];
-                if (al <= small2 || be <= small2) continue;
-                // converged pair: relative test, or an inner product below
-                // skip_rel^2 |A|_F^2, which moves no singular value by more
-                // than ~skip_rel |A|_F
-                if (ga * ga <= tol2 * al * be || fabs(ga) <= small2) continue;
-                const double zeta = 0.5 * (be - al) * fast_rcp(ga);
-                const double az = fabs(zeta);
-                const double den = (az > 1e150) ? 2.0 * az : az + (1.0 + az * az) * fast_rsq(1.0 + az * az);
-                const double t = copysign(fast_rcp(den), zeta);
-                const double c = fast_rsq(1.0 + t * t), s = c * t;
-#pragma unroll
-                for (int e = 0; e < EPL; ++e) {
-                    const int i = g16 + 16 * e;
-                    if (i < m) {
-                        ap[i] = c * x[e] - s * y[e];
-                        aq[i] = s * x[e] + c * y[e];
-                    }
-                }
-                if (Vc) {
-                    double* vp = Vc + (long)p * n;
-                    double* vq = Vc + (long)q * n;
-#pragma unroll
-                    for (int e = 0; e < EPL; ++e) {
-                        const int i = g16 + 16 * e;
-                        if (i < n) {
-                            const double xv = vp[i], yv = vq[i];
-                            vp[i] = c * xv - s * yv;
-                            vq[i] = s * xv + c * yv;
-                        }
-                    }
-                }
-                if (g16 == 0) {
-                    nrm[p] = al - t * ga;
-                    nrm[q] = be + t * ga;
-                    if (fabs(t) > kSweepAngle) *flag = 1;
-                }
-            }
-            __syncthreads();
-        }
-        const int any = *flag;
-        __syncthreads();
-        if (!any) break;
+        if (!head) break;
     }
+    if (++sweep >= 40) return;
+    // the head has converged: the remaining sweeps pair the tail only
+    if (threadIdx.x == 0) {
+        int c = 0;
+        for (int j = 0; j < n; ++j)
+            if (nrm[j] <= head2) s_tail[c++] = (short)j;
+        s_ntail = c;
+    }
+    __syncthreads();
+    const int ntail = s_ntail;
+    if (ntail < 2) return;
+    for (; sweep < 40; ++sweep)
+        if (!jacobi_one_sweep<EPL>(m, n, ntail, s_tail, Ac, Vc, nrm, flag, &s_head, tol2, small2, head2))
+            return;
 }
 
 // Column norms, ranks (descending, ties by index) and sorted outputs.
