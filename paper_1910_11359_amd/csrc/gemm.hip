@@ -384,6 +384,72 @@ struct Vec16<float> { typedef float v_t __attribute__((ext_vector_type(4))); };
 template <>
 struct Vec16<double> { typedef double v_t __attribute__((ext_vector_type(2))); };
 
+// Epilogue through LDS: the workgroup writes its accumulators into `lds`
+// (RING elements, at least BN rows' worth; 16-byte chunks XOR-swizzled by the
+// row) in passes of RP tile rows, then stores the tile in row order, one
+// 16-byte vector per lane where the output layout keeps VW consecutive
+// columns contiguous (always for the split-K partials, row-major M x N).
+// Every lane of the workgroup must call it (it holds barriers).
+template <typename T, int BM, int BN, int WM, int FM, int FN, int RING, typename Acc>
+__device__ inline void store_tile_staged(const GemmProb& P, T* lds, const Acc (&acc)[FM][FN], int ks,
+                                         int split, int m0, int n0, int wm0, int wn0) {
+    typedef typename Vec16<T>::v_t v_t;
+    constexpr int VW = 16 / (int)sizeof(T);
+    constexpr int RP = (RING / BN) < BM ? (RING / BN) : BM;  // tile rows per pass
+    static_assert(BM % RP == 0 && RP % WM == 0, "whole wave tiles per pass");
+    constexpr int CPR = BN / VW;  // 16-byte chunks per tile row
+    static_assert(CPR % 8 == 0, "the swizzle permutes groups of 8 chunks");
+    const int tid = threadIdx.x, lane = tid & 63, l16 = lane & 15;
+    const int M = P.M, N = P.N;
+    const T alpha = (T)P.alpha, beta = (T)P.beta;
+    const bool partial = ks > 1;
+    T* __restrict__ C = partial ? (T*)P.ws + (long)split * M * N : (T*)P.C;
+    const bool vec = partial || (P.c_cs0 == 1 && P.c_cols0 % VW == 0 && P.c_cs1 % VW == 0 &&
+                                 P.c_rs0 % VW == 0 && P.c_rs1 % VW == 0 && ((uintptr_t)P.C & 15) == 0);
+    __syncthreads();  // every wave is done reading the operand tiles
+#pragma unroll
+    for (int h = 0; h < BM / RP; ++h) {
+        if (wm0 / RP == h) {
+#pragma unroll
+            for (int a = 0; a < FM; ++a)
+#pragma unroll
+                for (int b = 0; b < FN; ++b)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int row = wm0 - h * RP + a * 16 + Mfma<T>::row(lane, r);
+                        const int col = wn0 + b * 16 + l16;
+                        lds[row * BN + ((col / VW) ^ (row & 7)) * VW + col % VW] = alpha * acc[a][b][r];
+                    }
+        }
+        __syncthreads();
+        for (int e = tid; e < RP * CPR; e += blockDim.x) {
+            const int row = e / CPR, ch = e - (e / CPR) * CPR;
+            const int i = m0 + h * RP + row, j0 = n0 + ch * VW;
+            if (i >= M || j0 >= N) continue;  // N is a multiple of VW
+            v_t v = *(const v_t*)(lds + row * BN + (ch ^ (row & 7)) * VW);
+            if (partial) {
+                *(v_t*)(C + (long)i * N + j0) = v;
+            } else if (vec) {
+                const long off = (long)(i / P.c_rows0) * P.c_rs1 + (long)(i % P.c_rows0) * P.c_rs0 +
+                                 (long)(j0 / P.c_cols0) * P.c_cs1 + (long)(j0 % P.c_cols0);
+                if (beta != T(0)) v += beta * *(const v_t*)(C + off);
+                *(v_t*)(C + off) = v;
+            } else {
+#pragma unroll
+                for (int q = 0; q < VW; ++q) {
+                    const int j = j0 + q;
+                    const long off = (long)(i / P.c_rows0) * P.c_rs1 + (long)(i % P.c_rows0) * P.c_rs0 +
+                                     (long)(j / P.c_cols0) * P.c_cs1 + (long)(j % P.c_cols0) * P.c_cs0;
+                    T w = v[q];
+                    if (beta != T(0)) w += beta * C[off];
+                    C[off] = w;
+                }
+            }
+        }
+        if (h + 1 < BM / RP) __syncthreads();
+    }
+}
+
 // Direct kernel: operand tiles copied global -> LDS by 16-byte LDS-DMA loads
 // (no register staging) through an NS-stage ring, one barrier per k tile, and
 // an XCD-aware tile order (workgroup b runs on XCD b % 8; each XCD gets a
@@ -581,6 +647,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
     }
 
     // ---- epilogue
+    if constexpr (sizeof(T) == 4) {
+        // FP32: the tile goes through LDS (the operand ring, free now) and
+        // leaves as 16-byte row-order stores
+        store_tile_staged<T, BM, BN, WM, FM, FN, NS * (ASZ + BSZ)>(P, Sm, acc, ks, split, m0, n0, wm0, wn0);
+        return;
+    }
     const T alpha = (T)P.alpha, beta = (T)P.beta;
     if (ks > 1) {
         T* __restrict__ W = (T*)P.ws + (long)split * M * N;
