@@ -931,9 +931,19 @@ __global__ __launch_bounds__(256) void k_splitk_reduce(const GemmProb* __restric
     const T* W = (const T*)P.ws;
     T* C = (T*)P.C;
     const T beta = (T)P.beta;
+    const int ks = P.ksplit;
     for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < MN; e += (long)gridDim.x * blockDim.x) {
-        T v = W[e];
-        for (int sp = 1; sp < P.ksplit; ++sp) v += W[sp * MN + e];
+        // the partials are loaded eight at a time, then added in split order
+        const T* __restrict__ w = W + e;
+        T v = w[0];
+        for (int sp = 1; sp < ks; sp += 8) {
+            T x[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) x[u] = sp + u < ks ? w[(long)(sp + u) * MN] : T(0);
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (sp + u < ks) v += x[u];
+        }
         const int i = (int)(e / P.N), j = (int)(e % P.N);
         const long off = (long)(i / P.c_rows0) * P.c_rs1 + (long)(i % P.c_rows0) * P.c_rs0 +
                          (long)(j / P.c_cols0) * P.c_cs1 + (long)(j % P.c_cols0) * P.c_cs0;
