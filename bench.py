@@ -58,8 +58,8 @@ ROOF_KERNEL = "k_gemm_direct<...,TAG=1> (8 enlarged-corner products)"
 # traffic profile in profiles/; valid only for the tile planning, kernels
 # and launches they were measured on (the part of gemm.hip from tile_dims
 # on, see gemm_kernel_digest).  Keyed by contraction precision.
-TRAFFIC = {"fp32": {"kernel": "gemm_family", "gemm_kernel_sha256_16": "f973dd07eb148f89",
-                    "bytes_per_launch": 1.1465e8,
+TRAFFIC = {"fp32": {"kernel": "gemm_family", "gemm_kernel_sha256_16": "fb039deec08e37cb",
+                    "bytes_per_launch": 1.1457e8,
                     "note": "FETCH_SIZE + WRITE_SIZE per GEMM launch (with its split-K sum), steady "
                             "steps, profiles/traffic_contraction_gemms_D6_chi72_fp32.md"}}
 

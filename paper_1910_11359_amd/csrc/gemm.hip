@@ -932,6 +932,47 @@ __global__ __launch_bounds__(256) void k_splitk_reduce(const GemmProb* __restric
     T* C = (T*)P.C;
     const T beta = (T)P.beta;
     const int ks = P.ksplit;
+    typedef typename Vec16<T>::v_t v_t;
+    constexpr int VW = 16 / (int)sizeof(T);
+    if (MN >= 65536 && P.N % VW == 0 && ((uintptr_t)W & 15) == 0) {
+        // one 16-byte vector of a row per thread (MN is a multiple of VW, so
+        // every split's partial stays aligned); the same additions per
+        // element.  Small sums (the k x k Grams) keep one element per thread:
+        // more loads in flight
+        const bool vec = P.c_cs0 == 1 && P.c_cols0 % VW == 0 && P.c_cs1 % VW == 0 && P.c_rs0 % VW == 0 &&
+                         P.c_rs1 % VW == 0 && ((uintptr_t)C & 15) == 0;
+        for (long e = ((long)blockIdx.x * blockDim.x + threadIdx.x) * VW; e < MN;
+             e += (long)gridDim.x * blockDim.x * VW) {
+            const T* __restrict__ w = W + e;
+            v_t v = *(const v_t*)w;
+            for (int sp = 1; sp < ks; sp += 8) {
+                v_t x[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) x[u] = sp + u < ks ? *(const v_t*)(w + (long)(sp + u) * MN) : v_t{};
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+                    if (sp + u < ks) v += x[u];
+            }
+            const int i = (int)(e / P.N), j0 = (int)(e % P.N);
+            if (vec) {
+                const long off = (long)(i / P.c_rows0) * P.c_rs1 + (long)(i % P.c_rows0) * P.c_rs0 +
+                                 (long)(j0 / P.c_cols0) * P.c_cs1 + (long)(j0 % P.c_cols0);
+                if (beta != T(0)) v += beta * *(const v_t*)(C + off);
+                *(v_t*)(C + off) = v;
+            } else {
+#pragma unroll
+                for (int q = 0; q < VW; ++q) {
+                    const int j = j0 + q;
+                    const long off = (long)(i / P.c_rows0) * P.c_rs1 + (long)(i % P.c_rows0) * P.c_rs0 +
+                                     (long)(j / P.c_cols0) * P.c_cs1 + (long)(j % P.c_cols0) * P.c_cs0;
+                    T y = v[q];
+                    if (beta != T(0)) y += beta * C[off];
+                    C[off] = y;
+                }
+            }
+        }
+        return;
+    }
     for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < MN; e += (long)gridDim.x * blockDim.x) {
         // the partials are loaded eight at a time, then added in split order
         const T* __restrict__ w = W + e;
