@@ -12,8 +12,8 @@ Paper passages followed
       the imbalance, their difference.
 
 The paper gives no CTMRG details; this module takes the common directional
-CTMRG for a 2x2 unit cell with half-system projectors (the readings are
-listed in DESIGN.md):
+CTMRG for a 2x2 unit cell with half-system projectors (these readings fill
+what the paper leaves open):
     * environment of every site: corners C1..C4 (top-left, top-right,
       bottom-right, bottom-left) and edges T1..T4 (up, right, down, left);
       C_k has legs [prev, next] and T_k legs [prev, q, next], going clockwise

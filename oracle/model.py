@@ -9,7 +9,7 @@ Paper passages followed
     * Eq. (Hanc): the disorder enters as h * S^z_{ip} S^z_{ia}; the auxiliary
       S^z values are equally spaced in [-h, h] (d_A = 2: ±h; d_A = 3: h, 0, -h).
 
-Readings (listed in DESIGN.md)
+Readings (where the paper leaves the choice open)
     * spin operators are S = sigma/2 (paper says "Pauli spin operators");
     * the XY coefficient is J, the S^z S^z coefficient V (the paper's Delta),
       the field strength W (the paper's h);
