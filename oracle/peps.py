@@ -19,10 +19,9 @@ Coordinates are taken mod 2; y grows downwards.  Sites with x+y even are
 the A (initially occupied) sublattice.
 
 Readings (where the paper leaves the choice open): the 2x2 cell with
-checkerboard layers, a symmetric second-order Trotter step H_A/2 H_B/2
-V_A/2 V_B V_A/2 H_B/2 H_A/2 (layers never merged across steps), the
-truncation rule ``trunc_rule``, lambda normalised to unit 2-norm,
-pseudo-inverse cutoff
+checkerboard layers, a symmetric second-order Trotter step H_A/2 H_B/2 V_A/2
+V_B V_A/2 H_B/2 H_A/2 (layers never merged across steps), the truncation
+rule ``trunc_rule``, lambda normalised to unit 2-norm, pseudo-inverse cutoff
 1e-14 relative, site tensors normalised to max |.| = 1 after each update,
 and the per-update error sum_{k>g} s_k^2 / sum_k s_k^2 added to both end
 sites.
