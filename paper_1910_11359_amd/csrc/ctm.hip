@@ -43,6 +43,8 @@ __device__ inline LegTerms fwd_terms(int m, int D, bool transposed) {
     const int k = m / D, kp = m % D;
     const double h = 0.70710678118654752440;
     LegTerms t;
+    t.x[1] = t.y[1] = 0;
+    t.c[1] = cmake(0, 0);
     if (k == kp) {
         t.n = 1;
         t.x[0] = k;
@@ -62,14 +64,20 @@ __device__ inline LegTerms fwd_terms(int m, int D, bool transposed) {
             t.c[1] = cmake(0, -h);
         }
     }
-    if (transposed)
-        for (int i = 0; i < t.n; ++i) {
-            int tmp = t.x[i];
-            t.x[i] = t.y[i];
-            t.y[i] = tmp;
-        }
+    if (transposed) {  // constant indices: the terms stay in registers
+        const int x0 = t.x[0], x1 = t.x[1];
+        t.x[0] = t.y[0];
+        t.x[1] = t.y[1];
+        t.y[0] = x0;
+        t.y[1] = x1;
+    }
     return t;
 }
+// Term i (0 or 1) of a leg, read with constant indices (a run-time index into
+// the term arrays would put them in scratch memory).
+__device__ inline int term_x(const LegTerms& t, int i) { return i ? t.x[1] : t.x[0]; }
+__device__ inline int term_y(const LegTerms& t, int i) { return i ? t.y[1] : t.y[0]; }
+__device__ inline cplx term_c(const LegTerms& t, int i) { return i ? t.c[1] : t.c[0]; }
 
 // Inverse terms: E_c[(k, k')] = sum_t c_t E_H[m_t] (H legs); H^T legs use the
 // pair (k', k).
@@ -86,6 +94,8 @@ __device__ inline InvTerms inv_terms(int k, int kp, int D, bool transposed) {
     }
     const double h = 0.70710678118654752440;
     InvTerms t;
+    t.m[1] = 0;
+    t.c[1] = cmake(0, 0);
     if (k == kp) {
         t.n = 1;
         t.m[0] = k * D + k;
@@ -106,35 +116,79 @@ __device__ inline InvTerms inv_terms(int k, int kp, int D, bool transposed) {
     return t;
 }
 
-__global__ void k_double_layer(int D, int d, const cplx* __restrict__ A, double* __restrict__ a) {
-    const int site = blockIdx.y;
+// Double layer in the real basis: a[mu][ml][md][mr] = Re sum over the leg
+// terms (at most two per leg) of c_u c_l c_d c_r sum_p A_p[x] conj(A_p[y]),
+// x = (xu, xl, xd, xr) the ket and y the bra indices of the terms.  One
+// workgroup per (site, mu, ml): the A_p[xu][xl][.][.] and A_p[yu][yl][.][.]
+// slices of its (at most four) up/left term pairs go to LDS, then
+// W[kx][ky] = sum over those pairs of c_u c_l sum_p A_p[xu xl kx]
+// conj(A_p[yu yl ky]) (kx, ky the down/right index pairs), and each output
+// is Re sum over its down/right terms of c_d c_r W[kx][ky].
+__global__ __launch_bounds__(256) void k_double_layer(int D, int d, const cplx* __restrict__ A,
+                                                      double* __restrict__ a) {
+    extern __shared__ cplx sl[];  // [ket, bra][pair < 4][p < d][D^2], then W[D^2][D^2]
+    const int site = blockIdx.y, mul = blockIdx.x;
     const int q = D * D;
     const long q4 = (long)q * q * q * q;
-    const long D4 = (long)D * D * D * D;
-    const cplx* As = A + site * d * D4;
-    for (long e = blockIdx.x * blockDim.x + threadIdx.x; e < q4; e += (long)gridDim.x * blockDim.x) {
-        const int mr = e % q, md = (e / q) % q, ml = (e / (q * q)) % q, mu = e / ((long)q * q * q);
-        const LegTerms tu = fwd_terms(mu, D, false), tl = fwd_terms(ml, D, false);
+    const long D4 = (long)q * q;
+    const int mu = mul / q, ml = mul - (mul / q) * q;
+    const cplx* As = A + (long)site * d * D4;
+    const LegTerms tu = fwd_terms(mu, D, false), tl = fwd_terms(ml, D, false);
+    const int npair = tu.n * tl.n;
+    const int slab = d * q;  // one slice: d x D^2
+    for (int e = threadIdx.x; e < 2 * npair * slab; e += blockDim.x) {
+        const int side = e / (npair * slab), rem = e - side * (npair * slab);
+        const int pr = rem / slab, rem2 = rem - pr * slab;
+        const int pp = rem2 / q, dr = rem2 - pp * q;
+        const int iu = pr / tl.n, il = pr - (pr / tl.n) * tl.n;
+        const int u = side ? term_y(tu, iu) : term_x(tu, iu), l = side ? term_y(tl, il) : term_x(tl, il);
+        sl[e] = As[(long)pp * D4 + ((long)u * D + l) * q + dr];
+    }
+    __syncthreads();
+    const cplx* kx_s = sl;
+    const cplx* ky_s = sl + npair * slab;
+    cplx* W = sl + 2 * 4 * slab;
+    for (int e = threadIdx.x; e < q * q; e += blockDim.x) {
+        const int kx = e / q, ky = e - (e / q) * q;
+        cplx w = cmake(0, 0);
+        for (int pr = 0; pr < npair; ++pr) {
+            const int iu = pr / tl.n, il = pr - (pr / tl.n) * tl.n;
+            cplx sum = cmake(0, 0);
+            for (int p = 0; p < d; ++p)
+                sum = cadd(sum, cmul(kx_s[(pr * d + p) * q + kx], cconj(ky_s[(pr * d + p) * q + ky])));
+            w = cadd(w, cmul(cmul(term_c(tu, iu), term_c(tl, il)), sum));
+        }
+        W[e] = w;
+    }
+    __syncthreads();
+    double* out = a + (long)site * q4 + (long)mul * q * q;
+    for (int o = threadIdx.x; o < q * q; o += blockDim.x) {
+        const int md = o / q, mr = o - (o / q) * q;
         const LegTerms td = fwd_terms(md, D, true), tr = fwd_terms(mr, D, true);
         double acc = 0.0;
-        for (int iu = 0; iu < tu.n; ++iu)
-            for (int il = 0; il < tl.n; ++il)
-                for (int id = 0; id < td.n; ++id)
-                    for (int ir = 0; ir < tr.n; ++ir) {
-                        const cplx c = cmul(cmul(tu.c[iu], tl.c[il]), cmul(td.c[id], tr.c[ir]));
-                        const long kx = (((long)tu.x[iu] * D + tl.x[il]) * D + td.x[id]) * D + tr.x[ir];
-                        const long ky = (((long)tu.y[iu] * D + tl.y[il]) * D + td.y[id]) * D + tr.y[ir];
-                        cplx s = cmake(0, 0);
-                        for (int p = 0; p < d; ++p) s = cadd(s, cmul(As[p * D4 + kx], cconj(As[p * D4 + ky])));
-                        acc += cmul(c, s).re;
-                    }
-        a[site * q4 + e] = acc;
+#pragma unroll
+        for (int id = 0; id < 2; ++id)
+#pragma unroll
+            for (int ir = 0; ir < 2; ++ir)
+                if (id < td.n && ir < tr.n) {
+                    const int kx = td.x[id] * D + tr.x[ir], ky = td.y[id] * D + tr.y[ir];
+                    acc += cmul(cmul(td.c[id], tr.c[ir]), W[kx * q + ky]).re;
+                }
+        out[o] = acc;
     }
 }
 
 void double_layer_real(hipStream_t s, int D, int d, const cplx* A, double* a_base) {
-    const long q = (long)D * D, q4 = q * q * q * q;
-    hipLaunchKernelGGL(k_double_layer, dim3(ceil_div(q4, 256), 4), dim3(256), 0, s, D, d, A, a_base);
+    const long q = (long)D * D;
+    const size_t lds = (2 * 4 * (size_t)d * q + (size_t)q * q) * sizeof(cplx);
+    static bool attr_set = false;
+    if (!attr_set) {
+        HIP_CHECK(hipFuncSetAttribute((const void*)k_double_layer, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                      160 * 1024 - 1024));
+        attr_set = true;
+    }
+    IPEPS_REQUIRE(lds <= 160 * 1024 - 1024, IPEPS_EINVAL, "double layer: d D^2 too large for LDS");
+    hipLaunchKernelGGL(k_double_layer, dim3(q * q, 4), dim3(256), lds, s, D, d, A, a_base);
     HIP_CHECK(hipGetLastError());
 }
 
@@ -603,32 +657,45 @@ __global__ __launch_bounds__(256) void k_readout_rows(int D, int d, const double
     const double* Es = E + site * q4;
     const cplx* As = A + site * d * D4;
     const int r = x % D, dd = (x / D) % D, l = (x / (D * D)) % D, u = x / (D * D * D);
+    // d <= 10; the loops over sp run to 10 with a guard so that tr, ti stay
+    // in registers
     double tr[10], ti[10];
-    for (int sp = 0; sp < d; ++sp) tr[sp] = ti[sp] = 0.0;
+#pragma unroll
+    for (int sp = 0; sp < 10; ++sp) tr[sp] = ti[sp] = 0.0;
     for (long xp = lane; xp < D4; xp += 64) {
         const int rp = xp % D, dp = (xp / D) % D, lp = (xp / (D * D)) % D, up = xp / (D * D * D);
         const InvTerms tl = inv_terms(l, lp, D, false), tu = inv_terms(u, up, D, false);
         const InvTerms tR = inv_terms(r, rp, D, true), tD = inv_terms(dd, dp, D, true);
         cplx ec = cmake(0, 0);
-        for (int a = 0; a < tl.n; ++a)
-            for (int b = 0; b < tu.n; ++b)
-                for (int c = 0; c < tR.n; ++c)
-                    for (int e = 0; e < tD.n; ++e) {
-                        const double ev = Es[(((long)tl.m[a] * q + tu.m[b]) * q + tR.m[c]) * q + tD.m[e]];
-                        ec = cadd(ec, cscale(cmul(cmul(tl.c[a], tu.c[b]), cmul(tR.c[c], tD.c[e])), ev));
-                    }
-        for (int sp = 0; sp < d; ++sp) {
-            const cplx t = cmul(ec, cconj(As[sp * D4 + xp]));
-            tr[sp] += t.re;
-            ti[sp] += t.im;
-        }
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+#pragma unroll
+                for (int c = 0; c < 2; ++c)
+#pragma unroll
+                    for (int e = 0; e < 2; ++e)
+                        if (a < tl.n && b < tu.n && c < tR.n && e < tD.n) {
+                            const double ev = Es[(((long)tl.m[a] * q + tu.m[b]) * q + tR.m[c]) * q + tD.m[e]];
+                            ec = cadd(ec, cscale(cmul(cmul(tl.c[a], tu.c[b]), cmul(tR.c[c], tD.c[e])), ev));
+                        }
+#pragma unroll
+        for (int sp = 0; sp < 10; ++sp)
+            if (sp < d) {
+                const cplx t = cmul(ec, cconj(As[sp * D4 + xp]));
+                tr[sp] += t.re;
+                ti[sp] += t.im;
+            }
     }
-    for (int sp = 0; sp < d; ++sp) {
+#pragma unroll
+    for (int sp = 0; sp < 10; ++sp) {
         tr[sp] = wave_sum(tr[sp]);
         ti[sp] = wave_sum(ti[sp]);
     }
     if (lane == 0)
-        for (int sp = 0; sp < d; ++sp) T[row * d + sp] = cmake(tr[sp], ti[sp]);
+#pragma unroll
+        for (int sp = 0; sp < 10; ++sp)
+            if (sp < d) T[row * d + sp] = cmake(tr[sp], ti[sp]);
 }
 
 // rho[s][s'] = sum_x A[s][x] T[x][s'], trace-normalised; occupations with the
