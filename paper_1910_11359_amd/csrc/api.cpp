@@ -1047,6 +1047,7 @@ double svd_skip(const ipeps_state* st) { return st->dtype == IPEPS_DTYPE_FP64 ? 
 
 // Truncated SVD of the two cut matrices (formed in N64, or applied through
 // the enlarged corners in E); fills Us, Vs and g_dev.
+void launch_aux_ahead(const Ex& x, int si);
 void projector_svd(const Ex& x, int slot) {
     ipeps_state* st = x.st;
     const int n = st->n, k = st->k, chi = st->chi;
@@ -1089,6 +1090,11 @@ void projector_svd(const Ex& x, int slot) {
     copy_jobs(s, st->Zw, st->Yw, 2 * nk * sizeof(double), jm);
     orth(x, st->Yw, st->Qw, P.gramY, P.QfromY, P.gramQ, P.YfromQ, true);
     run(x, P.Cs);  // Cs = (Q^T N V)^T
+    if (st->aux_defer >= 0) {
+        const int sd = st->aux_defer;
+        st->aux_defer = -1;
+        launch_aux_ahead(x, sd);
+    }
     // Rayleigh-Ritz SVD (columns below svd_skip |Cs|_F left unrotated).
     // (Taking the right vectors as Cs^T U S^-1 instead of accumulating them
     // halves the Jacobi traffic but moved the FP32 imbalance by 2e-4 at D=6,
@@ -1162,6 +1168,25 @@ void launch_deferred_readout(ipeps_state* st, hipEvent_t after) {
     st->ro_deferred = false;
 }
 
+// The UR / DR corners of column step si + 1 on the aux stream, once the
+// main stream has passed everything that wrote the tensors they read (they
+// read only tensors the move leaves alone); with si == 0 also the spectra of
+// the previous environment and a readout started after the previous CTMRG.
+void launch_aux_ahead(const Ex& x, int si) {
+    ipeps_state* st = x.st;
+    const ColumnStep& nx = st->steps[si + 1];
+    HIP_CHECK(hipEventRecord(st->ev_aux_go, st->stream));
+    HIP_CHECK(hipStreamWaitEvent(st->aux_stream, st->ev_aux_go, 0));
+    run_on(x, st->aux_stream, nx.aux_s1);
+    run_on(x, st->aux_stream, nx.aux_s2);
+    run_on(x, st->aux_stream, nx.aux_s3);
+    HIP_CHECK(hipEventRecord(st->ev_aux_done, st->aux_stream));
+    if (si == 0) {
+        launch_deferred_spectra(x, st->ev_aux_go);
+        if (!x.batched()) launch_deferred_readout(st, st->ev_aux_go);
+    }
+}
+
 void column_step(const Ex& x, int si) {
     ipeps_state* st = x.st;
     const ColumnStep& cs = st->steps[si];
@@ -1173,21 +1198,15 @@ void column_step(const Ex& x, int si) {
     run(x, warm ? cs.s2w : cs.s2);
     run(x, warm ? cs.s3w : cs.s3);
     if (si % 2 == 0) {
-        // the next column step's UR / DR corners, on the aux stream once the
-        // earlier steps (which wrote the tensors they read) are done
-        const ColumnStep& nx = st->steps[si + 1];
-        HIP_CHECK(hipEventRecord(st->ev_aux_go, s));
-        HIP_CHECK(hipStreamWaitEvent(st->aux_stream, st->ev_aux_go, 0));
-        run_on(x, st->aux_stream, nx.aux_s1);
-        run_on(x, st->aux_stream, nx.aux_s2);
-        run_on(x, st->aux_stream, nx.aux_s3);
-        HIP_CHECK(hipEventRecord(st->ev_aux_done, st->aux_stream));
-        // the spectra of the previous environment and a readout started
-        // after the previous CTMRG run beside this step's projector SVD
-        if (si == 0) {
-            launch_deferred_spectra(x, st->ev_aux_go);
-            if (!x.batched()) launch_deferred_readout(st, st->ev_aux_go);
-        }
+        // the next column step's UR / DR corners go to the aux stream; with
+        // the subspace-iteration SVD they start with its Rayleigh-Ritz
+        // Jacobi (launch_aux_ahead from projector_svd), whose one workgroup
+        // per cut leaves the GPU to them, instead of sharing it with the
+        // chain products before it
+        if (n > kDirectMax)
+            st->aux_defer = si;
+        else
+            launch_aux_ahead(x, si);
     } else {
         HIP_CHECK(hipStreamWaitEvent(s, st->ev_aux_done, 0));
     }

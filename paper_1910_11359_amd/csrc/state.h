@@ -90,6 +90,7 @@ struct ipeps_state {
     // enlarged corners of the second column step of a move, computed ahead
     hipStream_t aux_stream;
     hipEvent_t ev_aux_go, ev_aux_done;
+    int aux_defer = -1;  // >= 0: column step whose corners-ahead launch waits for its Rayleigh-Ritz SVD
     // asynchronous readout (ipeps_observe_async): C, T, A and the truncation
     // errors are copied on the main stream, then read out on ro_stream with
     // scratch of its own while the main stream goes on
