@@ -1048,6 +1048,7 @@ double svd_skip(const ipeps_state* st) { return st->dtype == IPEPS_DTYPE_FP64 ? 
 // Truncated SVD of the two cut matrices (formed in N64, or applied through
 // the enlarged corners in E); fills Us, Vs and g_dev.
 void launch_aux_ahead(const Ex& x, int si);
+void launch_side_work(const Ex& x);
 void projector_svd(const Ex& x, int slot) {
     ipeps_state* st = x.st;
     const int n = st->n, k = st->k, chi = st->chi;
@@ -1095,6 +1096,7 @@ void projector_svd(const Ex& x, int slot) {
         st->aux_defer = -1;
         launch_aux_ahead(x, sd);
     }
+    if (slot == 1) launch_side_work(x);
     // Rayleigh-Ritz SVD (columns below svd_skip |Cs|_F left unrotated).
     // (Taking the right vectors as Cs^T U S^-1 instead of accumulating them
     // halves the Jacobi traffic but moved the FP32 imbalance by 2e-4 at D=6,
@@ -1170,8 +1172,7 @@ void launch_deferred_readout(ipeps_state* st, hipEvent_t after) {
 
 // The UR / DR corners of column step si + 1 on the aux stream, once the
 // main stream has passed everything that wrote the tensors they read (they
-// read only tensors the move leaves alone); with si == 0 also the spectra of
-// the previous environment and a readout started after the previous CTMRG.
+// read only tensors the move leaves alone).
 void launch_aux_ahead(const Ex& x, int si) {
     ipeps_state* st = x.st;
     const ColumnStep& nx = st->steps[si + 1];
@@ -1181,10 +1182,18 @@ void launch_aux_ahead(const Ex& x, int si) {
     run_on(x, st->aux_stream, nx.aux_s2);
     run_on(x, st->aux_stream, nx.aux_s3);
     HIP_CHECK(hipEventRecord(st->ev_aux_done, st->aux_stream));
-    if (si == 0) {
-        launch_deferred_spectra(x, st->ev_aux_go);
-        if (!x.batched()) launch_deferred_readout(st, st->ev_aux_go);
-    }
+}
+
+// The spectra of the previous environment and a readout started after the
+// previous CTMRG run, on their own streams from this point of the main
+// stream on: with the subspace-iteration SVD, the second column step's
+// Rayleigh-Ritz Jacobi (whose idle CUs nothing else fills; the first column
+// step's go to the corners ahead), else the first column step's SVD.
+void launch_side_work(const Ex& x) {
+    ipeps_state* st = x.st;
+    HIP_CHECK(hipEventRecord(st->ev_side_go, st->stream));
+    launch_deferred_spectra(x, st->ev_side_go);
+    if (!x.batched()) launch_deferred_readout(st, st->ev_side_go);
 }
 
 void column_step(const Ex& x, int si) {
@@ -1203,10 +1212,12 @@ void column_step(const Ex& x, int si) {
         // Jacobi (launch_aux_ahead from projector_svd), whose one workgroup
         // per cut leaves the GPU to them, instead of sharing it with the
         // chain products before it
-        if (n > kDirectMax)
+        if (n > kDirectMax) {
             st->aux_defer = si;
-        else
+        } else {
             launch_aux_ahead(x, si);
+            if (si == 0) launch_side_work(x);
+        }
     } else {
         HIP_CHECK(hipStreamWaitEvent(s, st->ev_aux_done, 0));
     }
@@ -1236,9 +1247,9 @@ void column_step(const Ex& x, int si) {
 
 // Snapshot the 16 corners (FP64) on the main stream; their spectra and the
 // change Delta follow on the spectra stream, deferred like an asynchronous
-// readout: the next CTMRG enqueues them after its first enlarged corners (so
-// they do not share the GPU with that launch), or any reader of spectra /
-// Delta does (wait_spectra).
+// readout: the next CTMRG iteration enqueues them part way through
+// (launch_side_work), where they fill CUs its SVD leaves idle, or any
+// reader of spectra / Delta does (wait_spectra).
 void corner_spectra_update(const Ex& x, bool first) {
     ipeps_state* st = x.st;
     const int chi = st->chi;
@@ -1502,6 +1513,7 @@ int ipeps_init(const ipeps_config* cfg, void* hip_stream, ipeps_alloc_fn alloc, 
         HIP_CHECK(hipEventCreateWithFlags(&st->ev_ro_done, hipEventDisableTiming));
         HIP_CHECK(hipEventRecord(st->ev_ro_done, st->ro_stream));  // complete: nothing pending
         HIP_CHECK(hipEventCreateWithFlags(&st->ev_aux_go, hipEventDisableTiming));
+        HIP_CHECK(hipEventCreateWithFlags(&st->ev_side_go, hipEventDisableTiming));
         HIP_CHECK(hipEventCreateWithFlags(&st->ev_aux_done, hipEventDisableTiming));
         HIP_CHECK(hipHostMalloc((void**)&st->host_buf, 65536 * sizeof(double), hipHostMallocDefault));
         st->autotune = (cfg->flags & IPEPS_FLAG_AUTOTUNE) != 0;
@@ -1534,6 +1546,7 @@ void ipeps_destroy(ipeps_state* st) {
     if (st->spec_stream) (void)hipStreamDestroy(st->spec_stream);
     if (st->aux_stream) (void)hipStreamDestroy(st->aux_stream);
     if (st->ev_aux_go) (void)hipEventDestroy(st->ev_aux_go);
+    if (st->ev_side_go) (void)hipEventDestroy(st->ev_side_go);
     if (st->ev_aux_done) (void)hipEventDestroy(st->ev_aux_done);
     if (st->ro_stream) (void)hipStreamDestroy(st->ro_stream);
     if (st->ev_ro_snap) (void)hipEventDestroy(st->ev_ro_snap);

@@ -91,6 +91,7 @@ struct ipeps_state {
     hipStream_t aux_stream;
     hipEvent_t ev_aux_go, ev_aux_done;
     int aux_defer = -1;  // >= 0: column step whose corners-ahead launch waits for its Rayleigh-Ritz SVD
+    hipEvent_t ev_side_go;  // main stream at the second column step's Rayleigh-Ritz SVD: spectra and readout start
     // asynchronous readout (ipeps_observe_async): C, T, A and the truncation
     // errors are copied on the main stream, then read out on ro_stream with
     // scratch of its own while the main stream goes on
