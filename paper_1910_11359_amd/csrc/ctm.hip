@@ -193,38 +193,70 @@ void double_layer_real(hipStream_t s, int D, int d, const cplx* A, double* a_bas
 }
 
 // ------------------------------------------------------------ frame layouts
+// Each site's double layer a[u][l][d][r] (FP64) in the leg orders the
+// contractions read, for the 4 frame rotations g (frame leg F sits at source
+// position (F - g) mod 4): kind 0 as [L][U][D][R], kind 1 as [D][L][R][U].
+// One workgroup per output and pair of its outer legs: the output's fastest
+// leg and the leg that is fastest in the source form a q x q tile, read along
+// the source's fastest leg and written along the output's through LDS (one
+// pass, no tile, when the two coincide).
 template <typename T>
-__global__ void k_frame_layouts(int q, const double* __restrict__ a_base, T* const* out_lu,
-                                T* const* out_dl) {
-    const int which = blockIdx.y;  // site*8 + g*2 + kind
+__global__ __launch_bounds__(256) void k_frame_layouts(int q, const double* __restrict__ a_base, T* const* out_lu,
+                                                       T* const* out_dl) {
+    extern __shared__ double tile[];  // q x (q + 1)
+    const int which = blockIdx.y;     // site*8 + g*2 + kind
     const int site = which / 8, g = (which / 2) % 4, kind = which % 2;
-    T* out = kind == 0 ? out_lu[site * 4 + g] : out_dl[site * 4 + g];
-    const long q4 = (long)q * q * q * q;
-    const double* a = a_base + site * q4;
-    for (long e = blockIdx.x * blockDim.x + threadIdx.x; e < q4; e += (long)gridDim.x * blockDim.x) {
-        const int i3 = e % q, i2 = (e / q) % q, i1 = (e / ((long)q * q)) % q, i0 = e / ((long)q * q * q);
-        int f[4];  // frame legs U, L, D, R
-        if (kind == 0) {  // [L][U][D][R]
-            f[1] = i0; f[0] = i1; f[2] = i2; f[3] = i3;
-        } else {          // [D][L][R][U]
-            f[2] = i0; f[1] = i1; f[3] = i2; f[0] = i3;
+    T* __restrict__ out = kind == 0 ? out_lu[site * 4 + g] : out_dl[site * 4 + g];
+    const long q2 = (long)q * q, q3 = q2 * q;
+    const double* __restrict__ a = a_base + site * q3 * q;
+    // frame leg (U 0, L 1, D 2, R 3) at output positions 0..3, and the source
+    // stride of each output position
+    const int F0 = kind == 0 ? 1 : 2, F1 = kind == 0 ? 0 : 1, F2 = kind == 0 ? 2 : 3, F3 = kind == 0 ? 3 : 0;
+    auto sstride = [&](int F) {
+        const int pos = (F - g + 4) & 3;
+        return pos == 3 ? 1L : pos == 2 ? (long)q : pos == 1 ? q2 : q3;
+    };
+    const long s0 = sstride(F0), s1 = sstride(F1), s2 = sstride(F2), s3 = sstride(F3);
+    // ob: the output position fastest in the source (3: no transpose)
+    const int ob = s3 == 1 ? 3 : s0 == 1 ? 0 : s1 == 1 ? 1 : 2;
+    // outer output positions x < y: the two not in {3, ob} ({0, 1} when ob = 3)
+    const int x = ob == 0 ? 1 : 0, y = ob == 2 || ob == 3 ? 1 : 2;
+    const long sx = x == 0 ? s0 : s1, sy = y == 1 ? s1 : s2;
+    const long ox = x == 0 ? q3 : q2, oy = y == 1 ? q2 : (long)q;
+    const int ix = blockIdx.x / q, iy = blockIdx.x - (blockIdx.x / q) * q;
+    const double* __restrict__ src = a + ix * sx + iy * sy;
+    T* __restrict__ dst = out + ix * ox + iy * oy;
+    const int n = q * q;
+    if (ob == 3) {
+        // i3 fastest on both sides; the other tile leg is output position 2
+        for (int e = threadIdx.x; e < n; e += blockDim.x) {
+            const int i3 = e % q, i2 = e / q;
+            dst[(long)i2 * q + i3] = (T)src[i2 * s2 + i3];
         }
-        int p[4];
-        for (int F = 0; F < 4; ++F) p[(F - g + 4) % 4] = f[F];
-        const long src = (((long)p[0] * q + p[1]) * q + p[2]) * q + p[3];
-        out[e] = (T)a[src];
+        return;
+    }
+    const long ob_out = ob == 0 ? q3 : ob == 1 ? q2 : (long)q;
+    for (int e = threadIdx.x; e < n; e += blockDim.x) {
+        const int b = e % q, i3 = e / q;  // b: the index of output position ob
+        tile[i3 * (q + 1) + b] = src[i3 * s3 + b];
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < n; e += blockDim.x) {
+        const int i3 = e % q, b = e / q;
+        dst[b * ob_out + i3] = (T)tile[i3 * (q + 1) + b];
     }
 }
 
 void frame_layouts(hipStream_t s, int q, int dtype, const double* a_base, void* const* out_lu,
                    void* const* out_dl) {
-    const long q4 = (long)q * q * q * q;
-    dim3 grid(ceil_div(q4, 256) < 4096 ? ceil_div(q4, 256) : 4096, 32);
+    IPEPS_REQUIRE(q >= 1 && q <= 64, IPEPS_EINVAL, "frame layouts: q must be in 1..64");
+    const dim3 grid(q * q, 32);
+    const size_t lds = (size_t)q * (q + 1) * sizeof(double);
     if (dtype == IPEPS_DTYPE_FP64)
-        hipLaunchKernelGGL(k_frame_layouts<double>, grid, dim3(256), 0, s, q, a_base,
+        hipLaunchKernelGGL(k_frame_layouts<double>, grid, dim3(256), lds, s, q, a_base,
                            (double* const*)out_lu, (double* const*)out_dl);
     else
-        hipLaunchKernelGGL(k_frame_layouts<float>, grid, dim3(256), 0, s, q, a_base,
+        hipLaunchKernelGGL(k_frame_layouts<float>, grid, dim3(256), lds, s, q, a_base,
                            (float* const*)out_lu, (float* const*)out_dl);
     HIP_CHECK(hipGetLastError());
 }
