@@ -759,12 +759,15 @@ void build_plan(ipeps_state* st) {
             p.c_cs0 = k;
             return split(p, kg, wg + b * kg * kk);
         });
-        P.Uo = batch2([&](int b) {
-            return gemm_nn(st->Yw + b * nk, k, st->Vc + b * kk, k, st->Uo + b * nk, k, n, k, k);
-        });
-        P.Vo = batch2([&](int b) {
-            return gemm_nn(st->Qz + b * nk, k, st->Uc + b * kk, k, st->Vo + b * nk, k, n, k, k);
-        });
+        // Uo and Vo of both cuts in one launch (independent products)
+        {
+            std::vector<GemmProb> uv;
+            for (int b = 0; b < 2; ++b)
+                uv.push_back(gemm_nn(st->Yw + b * nk, k, st->Vc + b * kk, k, st->Uo + b * nk, k, n, k, k));
+            for (int b = 0; b < 2; ++b)
+                uv.push_back(gemm_nn(st->Qz + b * nk, k, st->Uc + b * kk, k, st->Vo + b * nk, k, n, k, k));
+            P.UoVo = add_group(st, uv, IPEPS_DTYPE_FP64);
+        }
 
         // gated on the number of dropped columns of matrix b
         auto proj1 = [&](double* Q) {
@@ -1102,8 +1105,7 @@ void projector_svd(const Ex& x, int slot) {
     // halves the Jacobi traffic but moved the FP32 imbalance by 2e-4 at D=6,
     // chi=72; not used.)
     jacobi_svd_real(s, 2, k, k, st->Cs, k, (long)k * k, st->sig, st->Uc, st->Vc, st->jwork, svd_skip(st), jm);
-    run(x, P.Uo);
-    run(x, P.Vo);
+    run(x, P.UoVo);
     copy_jobs(s, st->warm + 2 * slot * nk, st->Vo, 2 * nk * sizeof(double), jm);
     for (ipeps_state* j : x.jobs) j->warm_valid[2 * slot] = j->warm_valid[2 * slot + 1] = true;
     if (st->factored) {
@@ -1230,15 +1232,24 @@ void column_step(const Ex& x, int si) {
     run(x, cs.proj);
     run(x, cs.proj2);
     const size_t e = st->esz;
+    // PupP[c'][D][t4p] <- Pup[c'][t4p][D];  PlowP[q3][c4n][c'] <- Plow[c4n][q3][c'];
+    // T4p[Y][t][c][v] <- T4[t][v][c]: six independent copies, one launch
+    Permute3Batch pb{};
+    auto add = [&](int mode, int A, int B, int C, const void* in, void* out) {
+        const int i = pb.n++;
+        pb.mode[i] = mode;
+        pb.A[i] = A;
+        pb.B[i] = B;
+        pb.C[i] = C;
+        pb.in[i] = in;
+        pb.out[i] = out;
+    };
     for (int Y = 0; Y < 2; ++Y) {
-        // PupP[c'][D][t4p] <- Pup[c'][t4p][D];  PlowP[q3][c4n][c'] <- Plow[c4n][q3][c']
-        permute3(s, st->dtype, 1, chi, chi, q, off(st->Pup, Y * (long)n * chi, e),
-                 off(st->PupP, Y * (long)n * chi, e), x.jm);
-        permute3(s, st->dtype, 0, chi, q, chi, off(st->Plow, Y * (long)n * chi, e),
-                 off(st->PlowP, Y * (long)n * chi, e), x.jm);
+        add(1, chi, chi, q, off(st->Pup, Y * (long)n * chi, e), off(st->PupP, Y * (long)n * chi, e));
+        add(0, chi, q, chi, off(st->Plow, Y * (long)n * chi, e), off(st->PlowP, Y * (long)n * chi, e));
     }
-    for (int Y = 0; Y < 2; ++Y)  // T4p[Y][t][c][v] <- T4[t][v][c]
-        permute3(s, st->dtype, 1, chi, q, chi, cs.t4[Y], off(st->T4p, Y * (long)chi * q * chi, e), x.jm);
+    for (int Y = 0; Y < 2; ++Y) add(1, chi, q, chi, cs.t4[Y], off(st->T4p, Y * (long)chi * q * chi, e));
+    permute3_batch(s, st->dtype, pb, x.jm);
     run(x, cs.w1);
     run(x, cs.w2);
     run(x, cs.fin);

@@ -36,6 +36,15 @@ void batched_transpose(hipStream_t s, int dtype, int batch, int R, int Cc, const
 //   mode 0: out[b][a][c] = in[a][b][c];  mode 1: out[a][c][b] = in[a][b][c];
 //   mode 2: out[c][a][b] = in[a][b][c]
 // With a JobMap (njobs > 1): the same permutation for every job (grid rows).
+// Independent permute3 copies (same modes and index meaning) in one launch.
+constexpr int kPermuteBatch = 6;
+struct Permute3Batch {
+    int n;
+    int mode[kPermuteBatch], A[kPermuteBatch], B[kPermuteBatch], C[kPermuteBatch];
+    const void* in[kPermuteBatch];
+    void* out[kPermuteBatch];
+};
+void permute3_batch(hipStream_t s, int dtype, const Permute3Batch& pb, JobMap jm);
 void permute3(hipStream_t s, int dtype, int mode, int A, int B, int C, const void* in, void* out,
               JobMap jm = JobMap());
 

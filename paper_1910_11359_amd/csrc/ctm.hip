@@ -386,6 +386,39 @@ void permute3(hipStream_t s, int dtype, int mode, int A, int B, int C, const voi
     HIP_CHECK(hipGetLastError());
 }
 
+// Up to kPermuteBatch independent permute3 copies in one launch (blockIdx.z
+// selects the copy; grid x sized for the largest).
+template <typename T>
+__global__ void k_permute3_batch(Permute3Batch pb, JobMap jm) {
+    const int z = blockIdx.z;
+    const int mode = pb.mode[z], A = pb.A[z], B = pb.B[z], C = pb.C[z];
+    const T* __restrict__ in = jptr((const T*)pb.in[z], jm, blockIdx.y);
+    T* __restrict__ out = jptr((T*)pb.out[z], jm, blockIdx.y);
+    const long tot = (long)A * B * C;
+    for (long e = blockIdx.x * blockDim.x + threadIdx.x; e < tot; e += (long)gridDim.x * blockDim.x) {
+        const int c = e % C, b = (e / C) % B, a = e / ((long)B * C);
+        long o;
+        if (mode == 0) o = ((long)b * A + a) * C + c;
+        else if (mode == 1) o = ((long)a * C + c) * B + b;
+        else o = ((long)c * A + a) * B + b;
+        out[o] = in[e];
+    }
+}
+
+void permute3_batch(hipStream_t s, int dtype, const Permute3Batch& pb, JobMap jm) {
+    IPEPS_REQUIRE(pb.n >= 1 && pb.n <= kPermuteBatch, IPEPS_EINVAL, "permute3_batch: 1..6 copies");
+    long tot = 0;
+    for (int i = 0; i < pb.n; ++i) tot = std::max(tot, (long)pb.A[i] * pb.B[i] * pb.C[i]);
+    const int grid = ceil_div(tot, 256) < 4096 ? ceil_div(tot, 256) : 4096;
+    jm.per_job = 1;
+    const dim3 g(grid, jm.delta ? jm.njobs : 1, pb.n);
+    if (dtype == IPEPS_DTYPE_FP64)
+        hipLaunchKernelGGL(k_permute3_batch<double>, g, dim3(256), 0, s, pb, jm);
+    else
+        hipLaunchKernelGGL(k_permute3_batch<float>, g, dim3(256), 0, s, pb, jm);
+    HIP_CHECK(hipGetLastError());
+}
+
 // ------------------------------------------------------------ norms / conversion
 // Deterministic two-pass Frobenius normalisation: kNormBlocks blocks per
 // tensor write partial sums of squares (FP64) in a fixed partition, then every
