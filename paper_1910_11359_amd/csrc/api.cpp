@@ -1051,7 +1051,8 @@ double svd_skip(const ipeps_state* st) { return st->dtype == IPEPS_DTYPE_FP64 ? 
 // Truncated SVD of the two cut matrices (formed in N64, or applied through
 // the enlarged corners in E); fills Us, Vs and g_dev.
 void launch_aux_ahead(const Ex& x, int si);
-void launch_side_work(const Ex& x);
+void launch_side_spectra(const Ex& x);
+void launch_side_readout(const Ex& x);
 void projector_svd(const Ex& x, int slot) {
     ipeps_state* st = x.st;
     const int n = st->n, k = st->k, chi = st->chi;
@@ -1099,7 +1100,8 @@ void projector_svd(const Ex& x, int slot) {
         st->aux_defer = -1;
         launch_aux_ahead(x, sd);
     }
-    if (slot == 1) launch_side_work(x);
+    if (slot == 1) launch_side_spectra(x);
+    if (slot == (st->dtype == IPEPS_DTYPE_FP64 ? 1 : 5)) launch_side_readout(x);
     // Rayleigh-Ritz SVD (columns below svd_skip |Cs|_F left unrotated).
     // (Taking the right vectors as Cs^T U S^-1 instead of accumulating them
     // halves the Jacobi traffic but moved the FP32 imbalance by 2e-4 at D=6,
@@ -1186,16 +1188,25 @@ void launch_aux_ahead(const Ex& x, int si) {
     HIP_CHECK(hipEventRecord(st->ev_aux_done, st->aux_stream));
 }
 
-// The spectra of the previous environment and a readout started after the
-// previous CTMRG run, on their own streams from this point of the main
-// stream on: with the subspace-iteration SVD, the second column step's
-// Rayleigh-Ritz Jacobi (whose idle CUs nothing else fills; the first column
-// step's go to the corners ahead), else the first column step's SVD.
-void launch_side_work(const Ex& x) {
+// The spectra of the previous environment (spectra stream) and a readout
+// started after the previous CTMRG run (readout stream), each from the point
+// of the main stream where it is called on.  With the subspace-iteration SVD
+// the spectra start with the second column step's Rayleigh-Ritz Jacobi (a
+// Jacobi phase whose idle CUs the corners ahead do not fill), and so does
+// the readout in FP64; with FP32 or BF16 contractions the readout starts
+// with the sixth column step's (after the second, its products slowed the
+// T update that follows; FP64 steps lost 5 ms with it there).  With the
+// direct SVD both start with the first column step's SVD.
+void launch_side_spectra(const Ex& x) {
     ipeps_state* st = x.st;
     HIP_CHECK(hipEventRecord(st->ev_side_go, st->stream));
     launch_deferred_spectra(x, st->ev_side_go);
-    if (!x.batched()) launch_deferred_readout(st, st->ev_side_go);
+}
+void launch_side_readout(const Ex& x) {
+    ipeps_state* st = x.st;
+    if (x.batched()) return;
+    HIP_CHECK(hipEventRecord(st->ev_side_go, st->stream));
+    launch_deferred_readout(st, st->ev_side_go);
 }
 
 void column_step(const Ex& x, int si) {
@@ -1218,7 +1229,10 @@ void column_step(const Ex& x, int si) {
             st->aux_defer = si;
         } else {
             launch_aux_ahead(x, si);
-            if (si == 0) launch_side_work(x);
+            if (si == 0) {
+                launch_side_spectra(x);
+                launch_side_readout(x);
+            }
         }
     } else {
         HIP_CHECK(hipStreamWaitEvent(s, st->ev_aux_done, 0));
@@ -1259,7 +1273,7 @@ void column_step(const Ex& x, int si) {
 // Snapshot the 16 corners (FP64) on the main stream; their spectra and the
 // change Delta follow on the spectra stream, deferred like an asynchronous
 // readout: the next CTMRG iteration enqueues them part way through
-// (launch_side_work), where they fill CUs its SVD leaves idle, or any
+// (launch_side_spectra), where they fill CUs its SVD leaves idle, or any
 // reader of spectra / Delta does (wait_spectra).
 void corner_spectra_update(const Ex& x, bool first) {
     ipeps_state* st = x.st;
