@@ -1111,11 +1111,28 @@ void projector_svd(const Ex& x, int slot) {
     copy_jobs(s, st->warm + 2 * slot * nk, st->Vo, 2 * nk * sizeof(double), jm);
     for (ipeps_state* j : x.jobs) j->warm_valid[2 * slot] = j->warm_valid[2 * slot + 1] = true;
     if (st->factored) {
-        // Uc S^-1/2 truncated (k x chi; its Us output is overwritten below),
-        // then P_low = T2 (Uc S^-1/2)
-        projector_factors(s, st->dtype, 2, k, k, chi, proj_cutoff(st), st->Uc, st->Uc, st->sig,
-                          (long)k * k, st->Us, st->VsK, (long)k * chi, st->g_dev, jm);
+        // one launch: Uc S^-1/2 truncated (k x chi, into VsK) and the
+        // projector factors Us, Vs from Uo, Vo; then P_low = T2 (Uc S^-1/2)
+        ProjFactorsPair pp{};
+        pp.n[0] = k;
+        pp.U[0] = st->Uc;
+        pp.V[0] = st->Uc;
+        pp.strideUV[0] = (long)k * k;
+        pp.Us[0] = nullptr;
+        pp.Vs[0] = st->VsK;
+        pp.strideP[0] = (long)k * chi;
+        pp.g_out[0] = nullptr;
+        pp.n[1] = n;
+        pp.U[1] = st->Uo;
+        pp.V[1] = st->Vo;
+        pp.strideUV[1] = nk;
+        pp.Us[1] = st->Us;
+        pp.Vs[1] = st->Vs;
+        pp.strideP[1] = (long)n * chi;
+        pp.g_out[1] = st->g_dev;
+        projector_factors_pair(s, st->dtype, 2, k, chi, proj_cutoff(st), st->sig, pp, jm);
         run(x, P.PlowT2);
+        return;
     }
     projector_factors(s, st->dtype, 2, n, k, chi, proj_cutoff(st), st->Uo, st->Vo, st->sig, nk, st->Us,
                       st->Vs, (long)n * chi, st->g_dev, jm);

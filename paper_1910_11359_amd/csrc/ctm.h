@@ -77,6 +77,20 @@ void copy_jobs(hipStream_t s, void* dst, const void* src, size_t bytes, JobMap j
 void projector_factors(hipStream_t s, int dtype, int batch, int n, int k, int chi, double tau,
                        const double* U, const double* V, const double* sigma, long strideUV,
                        void* Us, void* Vs, long strideP, int* g_out, JobMap jm = JobMap());
+// Two projector_factors calls with the same k, chi, tau and singular values
+// in one launch; Us[i] and g_out[i] may be NULL (not written).
+struct ProjFactorsPair {
+    int n[2];
+    const double* U[2];
+    const double* V[2];
+    long strideUV[2];
+    void* Us[2];
+    void* Vs[2];
+    long strideP[2];
+    int* g_out[2];
+};
+void projector_factors_pair(hipStream_t s, int dtype, int batch, int k, int chi, double tau,
+                            const double* sigma, const ProjFactorsPair& pp, JobMap jm = JobMap());
 
 // Normalised corner spectra (16 x chi) from raw singular values; delta_out =
 // max over corners of |s - s_prev|_2; prev <- current.

@@ -592,10 +592,9 @@ __device__ inline int trunc_rule_dev(const double* s, int n, int K, double tau) 
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_proj_factors(int n, int k, int chi, double tau,
-                                                      const double* U, const double* V,
-                                                      const double* sigma, long strideUV, T* Us,
-                                                      T* Vs, long strideP, int* g_out, JobMap jm) {
+__device__ inline void proj_factors_body(int n, int k, int chi, double tau, const double* U, const double* V,
+                                         const double* sigma, long strideUV, T* Us, T* Vs, long strideP,
+                                         int* g_out, JobMap jm) {
     // every block of matrix b re-derives g (k <= 256 values) and the weights
     __shared__ int g_s;
     __shared__ double w[256];
@@ -603,13 +602,13 @@ __global__ __launch_bounds__(256) void k_proj_factors(int n, int k, int chi, dou
     U = jptr(U, jm, blockIdx.y);
     V = jptr(V, jm, blockIdx.y);
     sigma = jptr(sigma, jm, blockIdx.y);
-    Us = jptr(Us, jm, blockIdx.y);
+    if (Us) Us = jptr(Us, jm, blockIdx.y);
     Vs = jptr(Vs, jm, blockIdx.y);
-    g_out = jptr(g_out, jm, blockIdx.y);
+    if (g_out) g_out = jptr(g_out, jm, blockIdx.y);
     const double* sg = sigma + (long)b * k;
     if (threadIdx.x == 0) {
         g_s = trunc_rule_dev(sg, k, chi, tau);
-        if (blockIdx.x == 0) g_out[b] = g_s;
+        if (blockIdx.x == 0 && g_out) g_out[b] = g_s;
     }
     __syncthreads();
     const int g = g_s;
@@ -617,7 +616,6 @@ __global__ __launch_bounds__(256) void k_proj_factors(int n, int k, int chi, dou
     __syncthreads();
     const double* Ub = U + b * strideUV;
     const double* Vb = V + b * strideUV;
-    T* us = Us + b * strideP;
     T* vs = Vs + b * strideP;
     for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < (long)n * chi;
          e += (long)gridDim.x * blockDim.x) {
@@ -625,14 +623,47 @@ __global__ __launch_bounds__(256) void k_proj_factors(int n, int k, int chi, dou
         const double wc = w[c];
         vs[e] = (T)(wc != 0.0 ? Vb[(long)i * k + c] * wc : 0.0);
     }
+    if (!Us) return;
     // Us transposed (chi x n): P_up = Us^T G is then a plain product with a
     // k-contiguous left operand
+    T* us = Us + b * strideP;
     for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < (long)n * chi;
          e += (long)gridDim.x * blockDim.x) {
         const int c = e / n, i = e % n;
         const double wc = w[c];
         us[e] = (T)(wc != 0.0 ? Ub[(long)i * k + c] * wc : 0.0);
     }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_proj_factors(int n, int k, int chi, double tau,
+                                                      const double* U, const double* V,
+                                                      const double* sigma, long strideUV, T* Us,
+                                                      T* Vs, long strideP, int* g_out, JobMap jm) {
+    proj_factors_body<T>(n, k, chi, tau, U, V, sigma, strideUV, Us, Vs, strideP, g_out, jm);
+}
+
+// Two projector_factors calls on the same singular values in one launch
+// (blockIdx.z selects the call).
+template <typename T>
+__global__ __launch_bounds__(256) void k_proj_factors_pair(ProjFactorsPair pp, int k, int chi, double tau,
+                                                           const double* sigma, JobMap jm) {
+    const int z = blockIdx.z;
+    proj_factors_body<T>(pp.n[z], k, chi, tau, pp.U[z], pp.V[z], sigma, pp.strideUV[z], (T*)pp.Us[z],
+                         (T*)pp.Vs[z], pp.strideP[z], pp.g_out[z], jm);
+}
+
+void projector_factors_pair(hipStream_t s, int dtype, int batch, int k, int chi, double tau,
+                            const double* sigma, const ProjFactorsPair& pp, JobMap jm) {
+    IPEPS_REQUIRE(chi <= 256 && k <= 256, IPEPS_EINVAL, "projector_factors: chi, k > 256");
+    const long tot = (long)std::max(pp.n[0], pp.n[1]) * chi;
+    jm.per_job = batch;
+    const dim3 grid(ceil_div(tot, 256) < 512 ? ceil_div(tot, 256) : 512, batch * (jm.delta ? jm.njobs : 1), 2);
+    if (dtype == IPEPS_DTYPE_FP64)
+        hipLaunchKernelGGL(k_proj_factors_pair<double>, grid, dim3(256), 0, s, pp, k, chi, tau, sigma, jm);
+    else
+        hipLaunchKernelGGL(k_proj_factors_pair<float>, grid, dim3(256), 0, s, pp, k, chi, tau, sigma, jm);
+    HIP_CHECK(hipGetLastError());
 }
 
 void projector_factors(hipStream_t s, int dtype, int batch, int n, int k, int chi, double tau,
