@@ -759,14 +759,17 @@ void build_plan(ipeps_state* st) {
             p.c_cs0 = k;
             return split(p, kg, wg + b * kg * kk);
         });
-        // Uo and Vo of both cuts in one launch (independent products)
-        {
+        // Uo and Vo of both cuts in one launch (independent products); Vo is
+        // written straight into the column step's warm-start slot, the next
+        // iteration's starting block
+        for (int si = 0; si < 8; ++si) {
             std::vector<GemmProb> uv;
+            double* vo = st->warm + 2 * si * nk;
             for (int b = 0; b < 2; ++b)
                 uv.push_back(gemm_nn(st->Yw + b * nk, k, st->Vc + b * kk, k, st->Uo + b * nk, k, n, k, k));
             for (int b = 0; b < 2; ++b)
-                uv.push_back(gemm_nn(st->Qz + b * nk, k, st->Uc + b * kk, k, st->Vo + b * nk, k, n, k, k));
-            P.UoVo = add_group(st, uv, IPEPS_DTYPE_FP64);
+                uv.push_back(gemm_nn(st->Qz + b * nk, k, st->Uc + b * kk, k, vo + b * nk, k, n, k, k));
+            P.UoVo[si] = add_group(st, uv, IPEPS_DTYPE_FP64);
         }
 
         // gated on the number of dropped columns of matrix b
@@ -1020,14 +1023,20 @@ double proj_cutoff(const ipeps_state* st) { return st->dtype == IPEPS_DTYPE_FP64
 // Yw = N Qz and Zw = N^T Qw for the two cuts: with the formed N64 (FP64), or
 // through the enlarged corners (products in dtype; FP64 blocks converted at
 // both ends in FP32 mode).
-void apply_n(const Ex& x, int si) {
+// Yw = N V; with copy, also Zw = Yw (returns whether that copy was made:
+// the FP64 conversion at the end of a chain in FP32 or BF16 writes both).
+bool apply_n(const Ex& x, int si, bool copy = false) {
     ipeps_state* st = x.st;
-    if (!st->factored) return run(x, st->svd.NVf);
+    if (!st->factored) {
+        run(x, st->svd.NVf);
+        return false;
+    }
     const long nk = (long)st->n * st->k;
     const bool f64 = st->dtype == IPEPS_DTYPE_FP64;
     if (!f64) from_fp64_blocks(st->stream, st->dtype, st->Qz, st->Ch[2], 2, st->n, st->k, false, x.jm);
     for (const GemmGroup& g : st->svd.NV[si]) run(x, g);
-    if (!f64) to_fp64(st->stream, st->dtype, st->Ch[1], st->Yw, 2 * nk, x.jm);
+    if (!f64) to_fp64(st->stream, st->dtype, st->Ch[1], st->Yw, 2 * nk, x.jm, copy ? st->Zw : nullptr);
+    return copy && !f64;
 }
 
 void apply_nt(const Ex& x, int si) {
@@ -1091,8 +1100,7 @@ void projector_svd(const Ex& x, int slot) {
         orth(x, st->Zw, st->Qz, P.gramZ, P.QfromZ, P.gramQz, P.ZfromQz, false);
     }
     // Rayleigh-Ritz on span(N V) x span(V)
-    apply_n(x, slot);
-    copy_jobs(s, st->Zw, st->Yw, 2 * nk * sizeof(double), jm);
+    if (!apply_n(x, slot, true)) copy_jobs(s, st->Zw, st->Yw, 2 * nk * sizeof(double), jm);
     orth(x, st->Yw, st->Qw, P.gramY, P.QfromY, P.gramQ, P.YfromQ, true);
     run(x, P.Cs);  // Cs = (Q^T N V)^T
     if (st->aux_defer >= 0) {
@@ -1107,8 +1115,8 @@ void projector_svd(const Ex& x, int slot) {
     // halves the Jacobi traffic but moved the FP32 imbalance by 2e-4 at D=6,
     // chi=72; not used.)
     jacobi_svd_real(s, 2, k, k, st->Cs, k, (long)k * k, st->sig, st->Uc, st->Vc, st->jwork, svd_skip(st), jm);
-    run(x, P.UoVo);
-    copy_jobs(s, st->warm + 2 * slot * nk, st->Vo, 2 * nk * sizeof(double), jm);
+    run(x, P.UoVo[slot]);
+    double* Vo = st->warm + 2 * slot * nk;  // V_o of both cuts (and the next warm start)
     for (ipeps_state* j : x.jobs) j->warm_valid[2 * slot] = j->warm_valid[2 * slot + 1] = true;
     if (st->factored) {
         // one launch: Uc S^-1/2 truncated (k x chi, into VsK) and the
@@ -1124,7 +1132,7 @@ void projector_svd(const Ex& x, int slot) {
         pp.g_out[0] = nullptr;
         pp.n[1] = n;
         pp.U[1] = st->Uo;
-        pp.V[1] = st->Vo;
+        pp.V[1] = Vo;
         pp.strideUV[1] = nk;
         pp.Us[1] = st->Us;
         pp.Vs[1] = st->Vs;
@@ -1134,7 +1142,7 @@ void projector_svd(const Ex& x, int slot) {
         run(x, P.PlowT2);
         return;
     }
-    projector_factors(s, st->dtype, 2, n, k, chi, proj_cutoff(st), st->Uo, st->Vo, st->sig, nk, st->Us,
+    projector_factors(s, st->dtype, 2, n, k, chi, proj_cutoff(st), st->Uo, Vo, st->sig, nk, st->Us,
                       st->Vs, (long)n * chi, st->g_dev, jm);
 }
 

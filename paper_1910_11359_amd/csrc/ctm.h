@@ -57,8 +57,10 @@ struct NormItem {
 size_t normalize_ws_doubles(int max_items);
 void normalize_tensors(hipStream_t s, int dtype, const NormItem* d_items, int n, double* ws);
 
-// Convert between dtype and FP64 (to_fp64: for every job of jm).
-void to_fp64(hipStream_t s, int dtype, const void* in, double* out, long count, JobMap jm = JobMap());
+// Convert between dtype and FP64 (to_fp64: for every job of jm; out2, if
+// not NULL, receives a second copy).
+void to_fp64(hipStream_t s, int dtype, const void* in, double* out, long count, JobMap jm = JobMap(),
+             double* out2 = nullptr);
 void from_fp64(hipStream_t s, int dtype, const double* in, void* out, long count);
 // FP64 rows x cols blocks (row-major, batch of them back to back) into dtype,
 // as they are (rows x cols) or transposed (cols x rows); LDS-tiled.

@@ -466,9 +466,18 @@ void normalize_tensors(hipStream_t s, int dtype, const NormItem* d_items, int n,
 }
 
 template <typename T>
-__global__ void k_to64(const T* in, double* out, long n, JobMap jm) {
+__global__ void k_to64(const T* in, double* out, double* out2, long n, JobMap jm) {
     in = jptr(in, jm, blockIdx.y);
     out = jptr(out, jm, blockIdx.y);
+    if (out2) {
+        out2 = jptr(out2, jm, blockIdx.y);
+        for (long e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x) {
+            const double v = (double)in[e];
+            out[e] = v;
+            out2[e] = v;
+        }
+        return;
+    }
     for (long e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x)
         out[e] = (double)in[e];
 }
@@ -478,15 +487,15 @@ __global__ void k_from64(const double* in, T* out, long n) {
         out[e] = (T)in[e];
 }
 
-void to_fp64(hipStream_t s, int dtype, const void* in, double* out, long count, JobMap jm) {
+void to_fp64(hipStream_t s, int dtype, const void* in, double* out, long count, JobMap jm, double* out2) {
     const int grid = ceil_div(count, 256) < 8192 ? ceil_div(count, 256) : 8192;
     if (count <= 0) return;
     jm.per_job = 1;
     const dim3 g(grid, jm.delta ? jm.njobs : 1);
     if (dtype == IPEPS_DTYPE_FP64)
-        hipLaunchKernelGGL(k_to64<double>, g, dim3(256), 0, s, (const double*)in, out, count, jm);
+        hipLaunchKernelGGL(k_to64<double>, g, dim3(256), 0, s, (const double*)in, out, out2, count, jm);
     else
-        hipLaunchKernelGGL(k_to64<float>, g, dim3(256), 0, s, (const float*)in, out, count, jm);
+        hipLaunchKernelGGL(k_to64<float>, g, dim3(256), 0, s, (const float*)in, out, out2, count, jm);
     HIP_CHECK(hipGetLastError());
 }
 

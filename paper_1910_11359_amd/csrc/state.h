@@ -62,7 +62,8 @@ struct SvdPlan {
     GemmGroup NV[8][4], NtQ[8][4];  // [column step][factor]
     GemmGroup NVf, NtQf;  // the same with the formed N64
     GemmGroup PlowT2;     // factored path: P_low = (E0 E1 Qz) (Uc S^-1/2)
-    GemmGroup gramY, gramZ, gramQ, gramQz, QfromY, QfromZ, YfromQ, ZfromQz, Cs, UoVo;
+    GemmGroup gramY, gramZ, gramQ, gramQz, QfromY, QfromZ, YfromQ, ZfromQz, Cs;
+    GemmGroup UoVo[8];  // [column step]: Vo goes to that step's warm-start slot
     // restart of dropped left columns: Gm = Qw^T Rb, Rb -= Qw Gm
     GemmGroup projQw1, projQw2;
 
